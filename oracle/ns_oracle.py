@@ -1,0 +1,451 @@
+"""Plain float64 oracle of the paper's method (test infrastructure only).
+
+Notation follows the paper: ``A`` is the SPD matrix of ``A theta* = b``
+(eq. ae1), ``X = G_{k-1}`` the current inverse estimate, ``Y = F_{k-1}`` its
+residual, ``Z = G_k`` the next estimate, ``h`` / ``n`` the order of the power
+series, ``p, w`` the unified-factorization parameters (eq. h1).
+
+Orientation.  The paper writes the residual on the left, ``Y = I - X A`` and
+``Z = P(Y) X``.  This oracle uses the mirrored (right) orientation everywhere,
+``Y = I - A X`` and ``Z = X P(Y)``.  For the right pairing
+``A Z = (I - Y) P(Y)`` holds without any commutation, so every identity of
+Sections 3-5 holds verbatim with left and right exchanged (and every iterate is
+a polynomial in ``A`` in exact arithmetic, so the two orientations produce the
+same iterates up to rounding).
+
+Every matrix-matrix product goes through ``_mm``, which counts it: the paper
+measures cost in matrix-matrix multiplications ("mmm", Section 4), and those
+printed counts pin the evaluation orders below.
+
+parity pins: every function here is pinned by a test in ``tests/`` against
+exact integer identities (nilpotent shift operands), printed mmm counts, the
+eigen-decomposition closed forms of eqs. (fk1)/(ermoex1), diagonal closed
+forms, and an independent Cholesky solve.
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+
+import numpy as np
+
+__all__ = [
+    "MMCounter", "alpha_frobenius", "alpha_inf_half", "splitting_condition",
+    "residual", "z_horner", "z_unified", "z_unified_plus1", "z_squaring",
+    "z_table", "TABLE_ORDERS", "z_form", "form_mmm", "ns_step",
+    "dns_init", "dns_step", "richardson_update", "SolveOptions", "SolveReport",
+    "solve", "stop_check", "STOP", "efficiency_index",
+]
+
+
+class MMCounter:
+    """Counts matrix-matrix multiplications (mmm)."""
+
+    def __init__(self) -> None:
+        self.n = 0
+
+    def __call__(self, x: np.ndarray, y: np.ndarray) -> np.ndarray:
+        self.n += 1
+        return x @ y
+
+
+def _mm(ctr: MMCounter | None, x: np.ndarray, y: np.ndarray) -> np.ndarray:
+    if ctr is None:
+        return x @ y
+    return ctr(x, y)
+
+
+def _eye_like(a: np.ndarray) -> np.ndarray:
+    return np.eye(a.shape[0], dtype=np.float64)
+
+
+# ---------------------------------------------------------------------------
+# Section 2: splitting and the scalar preconditioner S^{-1} = I / alpha
+# ---------------------------------------------------------------------------
+
+def alpha_frobenius(a: np.ndarray) -> float:
+    """``alpha = ||A||_F``, summed with correct rounding (math.fsum).
+
+    With ``S = alpha I``, ``2S - A`` is positive definite because
+    ``lambda_max(A) <= ||A||_F``, which is the convergence condition of the
+    splitting (eqs. minus, sp1, spro).
+    """
+    return math.sqrt(math.fsum(np.square(np.asarray(a, dtype=np.float64)).ravel()))
+
+
+def alpha_inf_half(a: np.ndarray, eps: float) -> float:
+    """``alpha = ||A||_inf / 2 + eps`` (maximum row sum; Section 2)."""
+    return float(np.max(np.sum(np.abs(a), axis=1))) / 2.0 + float(eps)
+
+
+def splitting_condition(a: np.ndarray, alpha: float) -> bool:
+    """True iff ``2S - A`` is positive definite for ``S = alpha I`` (Section 2)."""
+    m = 2.0 * alpha * _eye_like(a) - a
+    try:
+        np.linalg.cholesky(0.5 * (m + m.T))
+        return True
+    except np.linalg.LinAlgError:
+        return False
+
+
+# ---------------------------------------------------------------------------
+# Sections 3-4 and the Appendix: Z = X * sum_{j<h} Y^j, Y = I - A X
+# ---------------------------------------------------------------------------
+
+def residual(a: np.ndarray, x: np.ndarray, ctr: MMCounter | None = None) -> np.ndarray:
+    """``Y = I - A X`` (eq. xa1 / xa2, right orientation): one mmm."""
+    return _eye_like(a) - _mm(ctr, a, x)
+
+
+def z_horner(a, x, h, ctr=None, y=None):
+    """Horner's scheme for eq. (z1): ``Z_0 = X``, ``Z_i = X + Z_{i-1} Y``.
+
+    ``h`` mmm including the residual (Section 4).
+    """
+    if y is None:
+        y = residual(a, x, ctr)
+    z = x
+    for _ in range(h - 1):
+        z = x + _mm(ctr, z, y)
+    return z
+
+
+def z_unified(a, x, p, w, ctr=None, y=None):
+    """Unified factorization, eqs. (xa2)-(zi1), order ``h = w (p + 1)``.
+
+    ``U = X sum_{d<=p} Y^d`` (u1, by Horner), ``Y^{p+1} = I - A U`` (ua1),
+    ``Z = U sum_{j<w} (Y^{p+1})^j`` via ``Z_i = Z_{i-1} Y^{p+1} + U`` (zi1).
+    ``p + w + 1`` mmm; ``p + 1`` when ``w = 1`` and ``w`` when ``p = 0``
+    (eq. np1 and the note after it).
+    """
+    if y is None:
+        y = residual(a, x, ctr)
+    u = x
+    for _ in range(p):
+        u = x + _mm(ctr, u, y)
+    if w == 1:
+        return u
+    yp1 = y if p == 0 else residual(a, u, ctr)
+    z = u
+    for _ in range(w - 1):
+        z = _mm(ctr, z, yp1) + u
+    return z
+
+
+def z_unified_plus1(a, x, p, w, ctr=None, y=None):
+    """Eq. (ztab2): ``Z_1 = X (I + Y Q(Y))`` with ``Q`` the (ztab1) product.
+
+    Order ``h_1 = w (p + 1) + 1`` (eq. hape1), evaluated as ``Z_1 = X + Z Y``
+    with ``Z = X Q(Y)`` from :func:`z_unified`: one mmm more than (ztab1).
+    """
+    if y is None:
+        y = residual(a, x, ctr)
+    z = z_unified(a, x, p, w, ctr, y=y)
+    return x + _mm(ctr, z, y)
+
+
+def z_squaring(a, x, n, ctr=None, y=None):
+    """Factorized form ``Z = X (I + Y)(I + Y^2)(I + Y^4)...`` for ``n = 2^s``.
+
+    Tables 1-2, orders 2, 4, 8 (``(I+Y^2)(I+Y)X``, ``(I+Y^4)(I+Y^2)(I+Y)X``):
+    the powers come from repeated squaring, the factors are multiplied out,
+    then applied to ``X``.  ``2 s`` mmm: 2, 4 and 6 for orders 2, 4, 8
+    (the Appendix's remark that two / three second-order steps cost 4 / 6 mmm).
+    """
+    s = int(round(math.log2(n)))
+    if n < 2 or (1 << s) != n:
+        raise ValueError("squaring form needs n = 2^s >= 2")
+    if y is None:
+        y = residual(a, x, ctr)
+    eye = _eye_like(a)
+    p = eye + y
+    ypow = y
+    for _ in range(s - 1):
+        ypow = _mm(ctr, ypow, ypow)
+        p = _mm(ctr, p, eye + ypow)
+    return _mm(ctr, x, p)
+
+
+TABLE_ORDERS = (11, 15, 45)
+
+
+def z_table(a, x, h, ctr=None, y=None):
+    """Nested factorizations printed in the paper, right orientation.
+
+    * ``h = 11``: Table 2, second form, ``(I + Y (I + (Y^2+Y^4)(I+Y^4))(I+Y)) X``;
+      the polynomial is formed first and applied to ``X`` last: 6 mmm.
+    * ``h = 15``: Table 3, nested form
+      ``(I + (I + (Y^3)^2)((Y^3)^2 + Y^3)) (I + Y + Y^2) X`` with ``Y^3`` from
+      the residual of ``U = (I + Y + Y^2) X`` (eq. ua1): 7 mmm.
+    * ``h = 45``: eqs. (ex1)-(ex3): ``U3 = X [3I + (AX)(-3I + AX)]`` with
+      ``AX = I - Y`` taken from the residual,
+      ``Y^3 = I - A U3``, ``U9 = U3 (I + Y^3 + Y^6)``, ``Y^9 = I - A U9``,
+      ``Z = U9 (I + (I + (Y^9)^2)(Y^9 + (Y^9)^2))``: 10 mmm.
+    """
+    eye = _eye_like(a)
+    if h == 11:
+        if y is None:
+            y = residual(a, x, ctr)
+        y2 = _mm(ctr, y, y)
+        y4 = _mm(ctr, y2, y2)
+        v = y2 + y4
+        v = v + _mm(ctr, v, y4)                 # (Y^2+Y^4)(I+Y^4)
+        r = eye + _mm(ctr, y + y2, eye + v)     # I + Y(I+Y)(I + ...)
+        return _mm(ctr, x, r)
+    if h == 15:
+        if y is None:
+            y = residual(a, x, ctr)
+        u = x + _mm(ctr, x + _mm(ctr, x, y), y)  # X (I + Y + Y^2)
+        y3 = residual(a, u, ctr)                  # Y^3 = I - A U
+        y6 = _mm(ctr, y3, y3)
+        s = y6 + y3
+        wpoly = s + _mm(ctr, y6, s)               # (I + Y^6)(Y^6 + Y^3)
+        return u + _mm(ctr, u, wpoly)
+    if h == 45:
+        if y is None:
+            y = residual(a, x, ctr)
+        ax = eye - y                              # A X, from the residual
+        u3 = _mm(ctr, x, 3.0 * eye + _mm(ctr, ax, ax - 3.0 * eye))
+        y3 = residual(a, u3, ctr)
+        y6 = _mm(ctr, y3, y3)
+        u9 = _mm(ctr, u3, eye + y3 + y6)
+        y9 = residual(a, u9, ctr)
+        y18 = _mm(ctr, y9, y9)
+        s = y9 + y18
+        wpoly = s + _mm(ctr, y18, s)              # (I + (Y^9)^2)(Y^9 + (Y^9)^2)
+        return u9 + _mm(ctr, u9, wpoly)
+    raise ValueError(f"no nested table form for order {h}")
+
+
+FORMS = ("horner", "squaring", "unified", "unified_plus1", "table")
+
+
+def z_form(a, x, order, form, p=None, w=None, ctr=None, y=None):
+    """One step ``Z = X sum_{j<order} Y^j`` by the named evaluation form."""
+    if form == "horner":
+        return z_horner(a, x, order, ctr, y)
+    if form == "squaring":
+        return z_squaring(a, x, order, ctr, y)
+    if form == "unified":
+        if p is None or w is None or w * (p + 1) != order:
+            raise ValueError("unified form needs order = w (p + 1)")
+        return z_unified(a, x, p, w, ctr, y)
+    if form == "unified_plus1":
+        if p is None or w is None or w * (p + 1) + 1 != order:
+            raise ValueError("unified_plus1 form needs order = w (p + 1) + 1")
+        return z_unified_plus1(a, x, p, w, ctr, y)
+    if form == "table":
+        return z_table(a, x, order, ctr, y)
+    raise ValueError(f"unknown form {form!r}")
+
+
+def form_mmm(order, form, p=None, w=None) -> int:
+    """mmm of one step, counted by running the form on a 1x1 operand."""
+    ctr = MMCounter()
+    z_form(np.eye(1) * 0.5, np.eye(1), order, form, p, w, ctr)
+    return ctr.n
+
+
+def efficiency_index(order: int, mmm: int) -> float:
+    """Efficiency index ``order^(1/mmm)`` (eq. ei)."""
+    return float(order) ** (1.0 / float(mmm))
+
+
+def ns_step(a, g, order, form="squaring", p=None, w=None, ctr=None, f=None):
+    """Classical high-order Newton-Schulz step, eq. (ns): ``G_k = G_{k-1} P(F_{k-1})``
+    with ``F_{k-1} = I - A G_{k-1}`` (passed in as ``f`` when already known)."""
+    return z_form(a, g, order, form, p, w, ctr, y=f)
+
+
+# ---------------------------------------------------------------------------
+# Section 5.1: double Newton-Schulz (composite expansion with T = L_k)
+# ---------------------------------------------------------------------------
+
+@dataclasses.dataclass
+class DNSState:
+    L: np.ndarray      # L_{k-1}
+    Gam: np.ndarray    # Gamma_k = I - A L_{k-1}
+    G: np.ndarray      # G_{k-1}
+    F: np.ndarray      # F_{k-1} = I - A G_{k-1}
+
+
+def dns_init(a, t0, order, form="squaring", p=None, w=None, ctr=None) -> DNSState:
+    """Precalculation of Section 5.1: ``T_0 = G_0``, ``Gamma_0 = I - A T_0``,
+    ``L_0 = T_0 P(Gamma_0)``, ``Gamma_1 = I - A L_0``; ``F_0 = Gamma_0``."""
+    gam0 = residual(a, t0, ctr)
+    l0 = z_form(a, t0, order, form, p, w, ctr, y=gam0)
+    gam1 = residual(a, l0, ctr)
+    return DNSState(L=l0, Gam=gam1, G=t0, F=gam0)
+
+
+def dns_step(a, st: DNSState, order, form="squaring", p=None, w=None, ctr=None) -> DNSState:
+    """One step of eqs. (gamk11)-(fks1), right orientation.
+
+    ``L_k = L_{k-1} P(Gamma_k)`` (lkk1); ``Gamma_k^n = I - A L_k`` (gamk21),
+    which is also ``Gamma_{k+1}``; the ordinary loop ``H = G_{k-1} P(F_{k-1})``;
+    the merge ``G_k = L_k + H Gamma_k^n`` (gkgen21); ``F_k = I - A G_k``, which
+    equals ``F_{k-1}^n Gamma_k^n`` (fks1).
+    """
+    l_k = z_form(a, st.L, order, form, p, w, ctr, y=st.Gam)
+    gam_n = residual(a, l_k, ctr)
+    hmat = z_form(a, st.G, order, form, p, w, ctr, y=st.F)
+    g_k = l_k + _mm(ctr, hmat, gam_n)
+    f_k = residual(a, g_k, ctr)
+    return DNSState(L=l_k, Gam=gam_n, G=g_k, F=f_k)
+
+
+# ---------------------------------------------------------------------------
+# Section 6: Richardson iteration coupled with the inverse estimate
+# ---------------------------------------------------------------------------
+
+def richardson_update(a, b, theta, g):
+    """``theta_k = theta_{k-1} - G_k (A theta_{k-1} - b)``: eq. (redttk1) with
+    ``omega_k = G_k``.  Returns ``(theta_k, r)`` where ``r = b - A theta_{k-1}``."""
+    r = b - a @ theta
+    return theta + g @ r, r
+
+
+# Stop reasons (shared meaning with the solver's report; values are the
+# oracle's own).
+STOP = {
+    "none": 0, "f_tol": 1, "floor": 2, "k_max": 3, "diverged": 4,
+    "resid_tol": 5, "refine_max": 6, "refine_stall": 7,
+}
+
+
+def stop_check(fhist, f_tol, k, k_max, floor_detect=True):
+    """Stop rule for the Newton-Schulz phase; the paper gives none.
+
+    ``fhist[j] = ||F_j||_F`` for ``j = 0..k``.  Stop when
+    (i) ``||F_k|| <= f_tol``;
+    (ii) the rounding floor is reached: some earlier ratio
+    ``||F_j|| / ||F_{j-1}||`` was below 1/2 (the iteration had entered its
+    fast regime) and now the ratio is above 1/2;
+    (iii) ``k = k_max``;
+    (iv) divergence: a non-finite norm or ``||F_k|| > ||F_0||``.
+    Returns the reason name or ``None``.
+    """
+    fk = fhist[k]
+    if not math.isfinite(fk) or fk > fhist[0]:
+        return "diverged"
+    if fk <= f_tol:
+        return "f_tol"
+    if floor_detect and k >= 2:
+        entered = any(fhist[j] < 0.5 * fhist[j - 1] for j in range(1, k))
+        if entered and fk > 0.5 * fhist[k - 1]:
+            return "floor"
+    if k >= k_max:
+        return "k_max"
+    return None
+
+
+@dataclasses.dataclass
+class SolveOptions:
+    order: int = 8
+    form: str = "squaring"
+    p: int | None = None
+    w: int | None = None
+    composite: bool = False        # double Newton-Schulz (Section 5.1)
+    k_max: int = 64
+    f_tol: float = 0.0
+    floor_detect: bool = True
+    refine_max: int = 64
+    resid_tol: float = 1e-12
+    scale: str = "frobenius"       # or "inf_half"
+    eps: float = 0.0               # for "inf_half"
+    theta0: str = "g0b"            # "g0b": theta_0 = G_0 b;  "zero"
+
+
+@dataclasses.dataclass
+class SolveReport:
+    alpha: float
+    theta: np.ndarray
+    G: np.ndarray
+    fnorm_hist: list        # ||F_k||_F, k = 0..ns_steps
+    resid_hist: list        # ||b - A theta_j|| / ||b|| for every theta_j formed
+    ns_steps: int
+    refine_steps: int
+    ns_stop: str            # why the Newton-Schulz phase ended
+    refine_stop: str        # why the refinement phase ended
+    rel_resid: float        # of the returned theta
+    mmm: int
+
+
+def solve(a, b, opts: SolveOptions = SolveOptions()) -> SolveReport:
+    """Coupled Newton-Schulz / Richardson solve of ``A theta = b``.
+
+    1. ``G_0 = I / alpha`` (Section 2; ``alpha = ||A||_F`` or ``||A||_inf/2+eps``)
+       and ``theta_0 = G_0 b``.
+    2. Step ``k``: ``G_k`` from eq. (ns) (or eqs. (gamk11)-(fks1) for the
+       composite form), then the Richardson update with the new ``G_k``
+       (eq. redttk1 with ``omega_k = G_k``), then ``F_k = I - A G_k`` and the
+       stop rule of :func:`stop_check`.
+    3. Refinement-only Richardson steps with the final ``G`` until
+       ``||b - A theta|| / ||b|| <= resid_tol``, ``refine_max`` steps, or a
+       stall (less than a factor 2 of progress over 3 steps).
+    """
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    ctr = MMCounter()
+    eye = _eye_like(a)
+    if opts.scale == "frobenius":
+        alpha = alpha_frobenius(a)
+    elif opts.scale == "inf_half":
+        alpha = alpha_inf_half(a, opts.eps)
+    else:
+        raise ValueError(opts.scale)
+    bnorm = float(np.linalg.norm(b))
+    if bnorm == 0.0:
+        bnorm = 1.0
+    g0 = eye / alpha
+    theta = g0 @ b if opts.theta0 == "g0b" else np.zeros_like(b)
+
+    if opts.composite:
+        st = dns_init(a, g0, opts.order, opts.form, opts.p, opts.w, ctr)
+        g, f = st.G, st.F
+    else:
+        g = g0
+        f = residual(a, g, ctr)
+    fhist = [float(np.linalg.norm(f))]
+    rhist: list[float] = []
+    ns_stop = "diverged" if not math.isfinite(fhist[0]) else None
+    k = 0
+    while ns_stop is None:
+        k += 1
+        if opts.composite:
+            st = dns_step(a, st, opts.order, opts.form, opts.p, opts.w, ctr)
+            g, f = st.G, st.F
+            theta, r = richardson_update(a, b, theta, g)
+        else:
+            g = ns_step(a, g, opts.order, opts.form, opts.p, opts.w, ctr, f=f)
+            theta, r = richardson_update(a, b, theta, g)
+            f = residual(a, g, ctr)          # also the next step's residual
+        rhist.append(float(np.linalg.norm(r)) / bnorm)
+        fhist.append(float(np.linalg.norm(f)))
+        ns_stop = stop_check(fhist, opts.f_tol, k, opts.k_max, opts.floor_detect)
+
+    refine = 0
+    rel = float("nan")
+    refine_stop = "diverged"
+    if ns_stop != "diverged":
+        while True:
+            r = b - a @ theta
+            rel = float(np.linalg.norm(r)) / bnorm
+            rhist.append(rel)
+            if not math.isfinite(rel):
+                refine_stop = "diverged"
+                break
+            if rel <= opts.resid_tol:
+                refine_stop = "resid_tol"
+                break
+            if refine >= opts.refine_max:
+                refine_stop = "refine_max"
+                break
+            if refine >= 3 and rel > 0.5 * rhist[-4]:
+                refine_stop = "refine_stall"
+                break
+            theta = theta + g @ r
+            refine += 1
+    return SolveReport(alpha=alpha, theta=theta, G=g, fnorm_hist=fhist, resid_hist=rhist,
+                       ns_steps=k, refine_steps=refine, ns_stop=ns_stop,
+                       refine_stop=refine_stop, rel_resid=rel, mmm=ctr.n)

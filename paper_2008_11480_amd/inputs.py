@@ -1,0 +1,183 @@
+"""Seeded synthetic workloads for the SPD solver.
+
+This module only *builds inputs*.  It contains none of the solver's arithmetic
+(no scaling, no Newton-Schulz step, no Richardson update), so both the HIP path
+and the CPU oracle may draw their inputs from it.
+
+The paper's own simulation uses the Gram matrix of a harmonic regressor with
+three frequencies (Section 7); its data set is not published, so the recipes
+below stand in for it:
+
+* ``spd_qlq``: ``A = Q diag(lam) Q^T`` with ``Q`` Haar-orthogonal (QR of a
+  seeded Gaussian, column signs fixed by ``sign(diag R)``) and ``lam``
+  log-uniform in ``[1, kappa]`` with both ends pinned, so that
+  ``cond_2(A) = kappa`` exactly.  ``b ~ N(0, 1)``.  The eigen-decomposition is
+  returned as well; the closed-form error laws of the method are stated in it.
+* ``harmonic_gram``: the Gram matrix of a harmonic regressor
+  ``phi(t) = [cos w_1 t, sin w_1 t, ..., cos w_m t, sin w_m t]`` sampled at
+  ``t = 1..4N`` (``N = 2m``), plus a ``1e-6 I`` ridge, and ``b = sum_t phi y``
+  with ``y = phi^T theta_true + N(0, 0.01)`` (Section 1 names harmonic
+  regressors as the SPD source).
+* ``harmonic_batch``: many such systems with ``m ~ U{8..128}``.
+* ``serving_trace``: Poisson arrivals of SPD requests with log-uniform sizes
+  and condition numbers.
+
+All generators use numpy's PCG64 (``numpy.random.default_rng(seed)``).
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+
+import numpy as np
+
+
+@dataclasses.dataclass
+class SPDSystem:
+    """One SPD system ``A theta = b`` with its spectral data (when known)."""
+
+    A: np.ndarray  # (N, N) float64, C-contiguous, symmetric
+    b: np.ndarray  # (N,) float64
+    lam: np.ndarray | None = None  # eigenvalues (known for spd_qlq)
+    Q: np.ndarray | None = None  # eigenvectors, columns (known for spd_qlq)
+    seed: int = 0
+    kappa: float | None = None
+
+    @property
+    def n(self) -> int:
+        return int(self.A.shape[0])
+
+
+def haar_orthogonal(n: int, rng: np.random.Generator) -> np.ndarray:
+    """Haar-distributed orthogonal matrix: QR of a Gaussian, signs fixed."""
+    z = rng.standard_normal((n, n))
+    q, r = np.linalg.qr(z)
+    d = np.sign(np.diag(r))
+    d[d == 0] = 1.0
+    return np.ascontiguousarray(q * d[None, :])
+
+
+def loguniform_spectrum(n: int, kappa: float, rng: np.random.Generator) -> np.ndarray:
+    """``n`` eigenvalues log-uniform in ``[1, kappa]``, first = 1, last = kappa."""
+    if n == 1:
+        return np.array([1.0])
+    lam = np.exp(rng.uniform(0.0, math.log(kappa), size=n))
+    lam[0] = 1.0
+    lam[-1] = float(kappa)
+    return lam
+
+
+def spd_qlq(n: int, kappa: float, seed: int, with_eig: bool = True) -> SPDSystem:
+    """``A = Q diag(lam) Q^T`` (symmetrised), ``b ~ N(0,1)``; all from ``seed``."""
+    rng = np.random.default_rng(seed)
+    q = haar_orthogonal(n, rng)
+    lam = loguniform_spectrum(n, kappa, rng)
+    a = (q * lam[None, :]) @ q.T
+    a = 0.5 * (a + a.T)
+    b = rng.standard_normal(n)
+    return SPDSystem(A=np.ascontiguousarray(a), b=b,
+                     lam=lam if with_eig else None, Q=q if with_eig else None,
+                     seed=seed, kappa=float(kappa))
+
+
+def spd_diag(lam: np.ndarray, seed: int) -> SPDSystem:
+    """Diagonal SPD system with the given spectrum and ``b ~ N(0,1)``."""
+    rng = np.random.default_rng(seed)
+    lam = np.asarray(lam, dtype=np.float64)
+    n = lam.size
+    return SPDSystem(A=np.diag(lam).copy(), b=rng.standard_normal(n), lam=lam.copy(),
+                     Q=np.eye(n), seed=seed, kappa=float(lam.max() / lam.min()))
+
+
+def harmonic_gram(m: int, seed: int, ridge: float = 1e-6, noise_var: float = 0.01,
+                  samples_per_dim: int = 4) -> SPDSystem:
+    """Gram matrix of a harmonic regressor with ``m`` frequencies (``N = 2m``).
+
+    ``phi(t)`` interleaves ``cos w_i t`` and ``sin w_i t``; ``t = 1..4N``;
+    ``w_i ~ U(0, pi)``; ``theta_true ~ N(0, I)``; ``y = phi^T theta_true + e``
+    with ``e ~ N(0, noise_var)``.
+    """
+    rng = np.random.default_rng(seed)
+    n = 2 * m
+    w = rng.uniform(0.0, math.pi, size=m)
+    t = np.arange(1, samples_per_dim * n + 1, dtype=np.float64)
+    phi = np.empty((t.size, n))
+    phi[:, 0::2] = np.cos(np.outer(t, w))
+    phi[:, 1::2] = np.sin(np.outer(t, w))
+    theta_true = rng.standard_normal(n)
+    y = phi @ theta_true + math.sqrt(noise_var) * rng.standard_normal(t.size)
+    a = phi.T @ phi + ridge * np.eye(n)
+    a = 0.5 * (a + a.T)
+    b = phi.T @ y
+    return SPDSystem(A=np.ascontiguousarray(a), b=b, seed=seed)
+
+
+def harmonic_batch(count: int, seed: int, m_lo: int = 8, m_hi: int = 128) -> list[SPDSystem]:
+    """``count`` harmonic Gram systems, ``m ~ U{m_lo..m_hi}``, per-system seeds
+    spawned from ``seed``."""
+    ss = np.random.SeedSequence(seed)
+    rng = np.random.default_rng(ss)
+    ms = rng.integers(m_lo, m_hi + 1, size=count)
+    children = ss.spawn(count)
+    out = []
+    for m, child in zip(ms, children):
+        sub = int(child.generate_state(1)[0])
+        out.append(harmonic_gram(int(m), sub))
+    return out
+
+
+@dataclasses.dataclass
+class Request:
+    arrival_s: float
+    n: int
+    kappa: float
+    seed: int
+
+
+def serving_trace(rate_per_s: float, duration_s: float, seed: int,
+                  n_lo: int = 32, n_hi: int = 2048,
+                  kappa_lo: float = 10.0, kappa_hi: float = 1e6) -> list[Request]:
+    """Poisson arrivals; ``N = round(exp U(ln n_lo, ln n_hi))``,
+    ``kappa = exp U(ln kappa_lo, ln kappa_hi)``, one seed per request."""
+    rng = np.random.default_rng(seed)
+    out = []
+    t = 0.0
+    while True:
+        t += rng.exponential(1.0 / rate_per_s)
+        if t >= duration_s:
+            break
+        n = int(round(math.exp(rng.uniform(math.log(n_lo), math.log(n_hi)))))
+        kappa = float(math.exp(rng.uniform(math.log(kappa_lo), math.log(kappa_hi))))
+        out.append(Request(arrival_s=t, n=n, kappa=kappa, seed=int(rng.integers(0, 2**62))))
+    return out
+
+
+def random_symmetric_contraction(n: int, radius: float, seed: int) -> np.ndarray:
+    """Random symmetric matrix with spectral radius ``radius`` (test operand)."""
+    rng = np.random.default_rng(seed)
+    q = haar_orthogonal(n, rng)
+    mu = rng.uniform(-radius, radius, size=n)
+    mu[0] = radius
+    f = (q * mu[None, :]) @ q.T
+    return np.ascontiguousarray(0.5 * (f + f.T))
+
+
+def shift_matrix(m: int) -> np.ndarray:
+    """Nilpotent upper shift ``J`` (ones on the first super-diagonal).
+
+    Powers of ``J`` are exact in floating point, so any polynomial in ``J``
+    with small integer coefficients is evaluated exactly: this turns the
+    matrix programs of the method into exact integer identities.
+    """
+    return np.eye(m, k=1)
+
+
+# Workloads used by the tests and the benchmark, named by what they are.
+WORKLOADS = {
+    # N=64, kappa=100, order 4 squaring, 12 steps, target rel. residual 1e-13.
+    "spd64_k1e2_o4": dict(n=64, kappa=1e2, seed=1, order=4, k_max=12, resid_tol=1e-13),
+    # N=4096, kappa=1e4, order 8 squaring, to the ||F|| floor, FP64.
+    "spd4096_k1e4_o8": dict(n=4096, kappa=1e4, seed=2, order=8, k_max=64, resid_tol=1e-12),
+    # N=8192, kappa=1e6, composite (double) Newton-Schulz of order 8, mixed.
+    "spd8192_k1e6_dns8": dict(n=8192, kappa=1e6, seed=3, order=8, k_max=64, resid_tol=1e-10),
+}

@@ -1,0 +1,308 @@
+"""Pins of the CPU oracle against what the paper and the mathematics fix.
+
+None of these tests compares the oracle with itself: the expected values are
+exact integer identities (nilpotent shift operands, for which every power is
+exact in floating point), counts printed in the paper, eigen-decomposition and
+diagonal closed forms, an independent Cholesky solve (LAPACK through scipy),
+and ``numpy.linalg.matrix_power`` for the error law.
+"""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+import scipy.linalg
+
+import oracle
+from paper_2008_11480_amd import inputs
+
+
+def band_ones(m, h):
+    """sum_{j<h} J^j for the m x m upper shift J: ones on diagonals 0..h-1."""
+    out = np.zeros((m, m))
+    for j in range(min(h, m)):
+        out += np.eye(m, k=j)
+    return out
+
+
+def shift_power(m, e):
+    return np.eye(m, k=e) if e < m else np.zeros((m, m))
+
+
+# Evaluation forms and the order each one produces.
+FORM_CASES = (
+    [("horner", h, None, None) for h in range(2, 20)]
+    + [("squaring", n, None, None) for n in (2, 4, 8, 16, 32)]
+    + [("unified", w * (p + 1), p, w) for p in range(0, 8) for w in range(1, 7)]
+    + [("unified_plus1", w * (p + 1) + 1, p, w) for p in range(0, 8) for w in range(1, 7)]
+    + [("table", h, None, None) for h in oracle.TABLE_ORDERS]
+)
+
+
+@pytest.mark.parametrize("form,order,p,w", FORM_CASES)
+def test_forms_are_exact_power_series(form, order, p, w):
+    """Each factorized evaluation equals X sum_{j<order} Y^j exactly (eq. z1).
+
+    With A = c (I - J) and X = I / c (c a power of two), Y = I - A X = J
+    exactly, so Z must be the band of ones of width ``order``.  A dropped term,
+    a wrong power or a sign error changes an integer entry.
+    """
+    if form == "unified" and order < 2:
+        pytest.skip("order 1 is the identity step")
+    m = 64
+    c = 4.0
+    a = c * (np.eye(m) - inputs.shift_matrix(m))
+    x = np.eye(m) / c
+    z = oracle.z_form(a, x, order, form, p, w)
+    np.testing.assert_array_equal(z * c, band_ones(m, order))
+
+
+def test_ns_step_error_law_exact():
+    """eq. (fk1): after k steps F_k = F_0^{n^k}; exact on the shift operand."""
+    m = 80
+    a = np.eye(m) - inputs.shift_matrix(m)
+    for n, form in ((2, "squaring"), (3, "horner"), (4, "squaring")):
+        g = np.eye(m)
+        for k in range(1, 4):
+            g = oracle.ns_step(a, g, n, form)
+            f = oracle.residual(a, g)
+            np.testing.assert_array_equal(f, shift_power(m, n ** k))
+
+
+def test_printed_mmm_counts(golden_dir):
+    with open(os.path.join(golden_dir, "mmm_counts.json")) as fh:
+        gold = json.load(fh)
+    for e in gold["counts"]:
+        got = oracle.form_mmm(e["order"], e["form"], e.get("p"), e.get("w"))
+        assert got == e["mmm"], e
+    for e in gold["efficiency_index"]:
+        ei = oracle.efficiency_index(e["order"], e["mmm"])
+        assert round(ei, e["digits"]) == e["ei"], e
+
+
+@pytest.mark.parametrize("p", range(0, 8))
+@pytest.mark.parametrize("w", range(1, 7))
+def test_unified_mmm_formula(p, w):
+    """eq. (np1): p + w + 1 mmm, p + 1 when w = 1, w when p = 0."""
+    if w * (p + 1) < 2:
+        pytest.skip("order 1")
+    expected = p + w + 1
+    if w == 1:
+        expected = p + 1
+    elif p == 0:
+        expected = w
+    assert oracle.form_mmm(w * (p + 1), "unified", p, w) == expected
+    assert oracle.form_mmm(w * (p + 1), "horner") == w * (p + 1)   # Section 4: h mmm
+
+
+def test_error_law_matrix_identity():
+    """F_{k+1} = F_k^n as matrices (eq. fk1) on a random SPD system, above the
+    rounding floor; the power comes from numpy.linalg.matrix_power."""
+    s = inputs.spd_qlq(48, 50.0, seed=11)
+    a = s.A
+    alpha = oracle.alpha_frobenius(a)
+    for n, form in ((2, "squaring"), (4, "squaring"), (8, "squaring"), (3, "horner"),
+                    (6, "unified"), (7, "unified_plus1"), (11, "table"), (15, "table")):
+        p = w = None
+        if form == "unified":
+            p, w = 2, 2
+        if form == "unified_plus1":
+            p, w = 2, 2
+        g = np.eye(48) / alpha
+        f = oracle.residual(a, g)
+        for _ in range(3):
+            g = oracle.ns_step(a, g, n, form, p, w)
+            f_next = oracle.residual(a, g)
+            fpow = np.linalg.matrix_power(f, n)
+            err = np.linalg.norm(f_next - fpow)
+            assert err <= 1e-13 * max(1.0, np.linalg.norm(f)) * 48, (n, form, err)
+            f = f_next
+            if np.linalg.norm(f) < 1e-6:
+                break
+
+
+def eigen_fnorm(lam, alpha, e):
+    mu = 1.0 - lam / alpha
+    return math.sqrt(float(np.sum(mu ** (2 * e))))
+
+
+@pytest.mark.parametrize("order", [2, 4, 8])
+def test_eigen_closed_form_fnorm_and_theta(order):
+    """On A = Q diag(lam) Q^T: ||F_k||_F = sqrt(sum mu_i^{2 n^k}) with
+    mu = 1 - lam / alpha (eq. fk1 with h = 1, S = alpha I), and the coupled
+    Richardson iterate theta_K = theta* - Q diag(mu^{E_K}) Q^T theta* with
+    E_K = (n^{K+1} - 1)/(n - 1) while above the rounding floor."""
+    s = inputs.spd_qlq(64, 100.0, seed=1)
+    opts = oracle.SolveOptions(order=order, form="squaring", k_max=3, floor_detect=False,
+                               refine_max=0, resid_tol=0.0)
+    rep = oracle.solve(s.A, s.b, opts)
+    alpha = rep.alpha
+    for k, fk in enumerate(rep.fnorm_hist):
+        ref = eigen_fnorm(s.lam, alpha, order ** k)
+        if ref > 1e-9:
+            assert abs(fk - ref) <= 1e-9 * ref + 1e-12, (k, fk, ref)
+    theta_star = s.Q @ ((s.Q.T @ s.b) / s.lam)
+    mu = 1.0 - s.lam / alpha
+    kk = rep.ns_steps
+    e_k = (order ** (kk + 1) - 1) // (order - 1)
+    theta_ref = theta_star - s.Q @ ((mu ** e_k) * (s.Q.T @ theta_star))
+    assert np.linalg.norm(rep.theta - theta_ref) <= 1e-12 * np.linalg.norm(theta_star)
+
+
+def test_diagonal_closed_form():
+    """Diagonal A: G_K = diag((1 - (1 - lam/alpha)^{n^K}) / lam) (eqs. g02, fk1)."""
+    lam = np.array([1.0, 2.0, 3.5, 10.0, 40.0, 100.0])
+    s = inputs.spd_diag(lam, seed=3)
+    alpha = oracle.alpha_frobenius(s.A)
+    assert alpha == pytest.approx(math.sqrt(float(np.sum(lam ** 2))), rel=1e-15)
+    for n in (2, 4, 8):
+        g = np.eye(6) / alpha
+        for k in range(1, 4):
+            g = oracle.ns_step(s.A, g, n, "squaring")
+            ref = (1.0 - (1.0 - lam / alpha) ** (n ** k)) / lam
+            np.testing.assert_allclose(np.diag(g), ref, rtol=2e-15, atol=0)
+            assert np.max(np.abs(g - np.diag(np.diag(g)))) == 0.0
+
+
+@pytest.mark.parametrize("n,kappa,order,composite",
+                         [(64, 1e2, 4, False), (64, 1e2, 8, False), (200, 1e4, 8, False),
+                          (96, 1e3, 8, True), (64, 1e2, 4, True)])
+def test_solution_matches_cholesky(n, kappa, order, composite):
+    """theta agrees with LAPACK's Cholesky solve to ~kappa * u (the limit
+    of theta itself is A^{-1} b, eq. ae1)."""
+    s = inputs.spd_qlq(n, kappa, seed=7)
+    rep = oracle.solve(s.A, s.b, oracle.SolveOptions(order=order, composite=composite,
+                                                     resid_tol=1e-13))
+    chol = scipy.linalg.cho_solve(scipy.linalg.cho_factor(s.A), s.b)
+    rel = np.linalg.norm(rep.theta - chol) / np.linalg.norm(chol)
+    assert rel <= 20 * kappa * np.finfo(float).eps, rel
+    assert rep.rel_resid <= max(1e-12, 4 * np.linalg.norm(s.b - s.A @ chol) / np.linalg.norm(s.b))
+
+
+@pytest.mark.parametrize("n,ks", [(2, (1, 2, 3)), (3, (1, 2)), (4, (1,))])
+def test_double_ns_exponent_exact(n, ks):
+    """eq. (ermoex1) with h = 1: F_k = J^{k n^{k+1} + n^k} and
+    G_k = sum_{j < e_k} J^j exactly on the shift operand."""
+    m = 64 if n != 3 else 72
+    a = np.eye(m) - inputs.shift_matrix(m)
+    st = oracle.dns_init(a, np.eye(m), n, "horner")
+    np.testing.assert_array_equal(st.F, shift_power(m, 1))          # F_0 = Gamma_0
+    np.testing.assert_array_equal(st.Gam, shift_power(m, n))        # Gamma_1 = Gamma_0^n
+    for k in range(1, max(ks) + 1):
+        st = oracle.dns_step(a, st, n, "horner")
+        e_k = k * n ** (k + 1) + n ** k
+        if k in ks:
+            np.testing.assert_array_equal(st.F, shift_power(m, e_k))
+            np.testing.assert_array_equal(st.G, band_ones(m, e_k))
+            np.testing.assert_array_equal(st.Gam, shift_power(m, n ** (k + 1)))
+
+
+def test_double_ns_eigen_closed_form():
+    """||F_k||_F = sqrt(sum mu^{2 e_k}), e_k = k n^{k+1} + n^k (eq. ermoex1)."""
+    s = inputs.spd_qlq(64, 1e3, seed=5)
+    n = 2
+    rep = oracle.solve(s.A, s.b, oracle.SolveOptions(order=n, form="squaring", composite=True,
+                                                     k_max=3, floor_detect=False,
+                                                     refine_max=0, resid_tol=0))
+    for k, fk in enumerate(rep.fnorm_hist):
+        e_k = k * n ** (k + 1) + n ** k
+        ref = eigen_fnorm(s.lam, rep.alpha, e_k)
+        if ref > 1e-9:
+            assert abs(fk - ref) <= 1e-9 * ref, (k, fk, ref)
+
+
+@pytest.mark.parametrize("composite", [False, True])
+def test_richardson_mismatch_exact(composite):
+    """theta_K - theta* = -(prod_k F_k) theta*: with theta_0 = G_0 b the
+    mismatch is -J^{E} theta* on the shift operand, E the summed exponents
+    (E = sum_{k<=K} n^k classically; sum_{k<=K} (k n^{k+1} + n^k) for the
+    composite form, eqs. redttk1 and ermoex1)."""
+    m, n, K = 80, 2, 3
+    a = np.eye(m) - inputs.shift_matrix(m)
+    rng = np.random.default_rng(0)
+    b = rng.integers(-3, 4, size=m).astype(float)
+    theta_star = np.linalg.solve(a, b)          # exact: unit upper triangular
+    assert np.array_equal(a @ theta_star, b)
+    opts = oracle.SolveOptions(order=n, form="squaring", composite=composite, k_max=K,
+                               floor_detect=False, refine_max=0, resid_tol=0, scale="inf_half",
+                               eps=0.0)
+    # ||A||_inf / 2 = 1 here, so G_0 = I and F_0 = J exactly.
+    rep = oracle.solve(a, b, opts)
+    assert rep.alpha == 1.0
+    if composite:
+        e = sum(k * n ** (k + 1) + n ** k for k in range(0, K + 1))
+    else:
+        e = sum(n ** k for k in range(0, K + 1))
+    np.testing.assert_array_equal(rep.theta - theta_star, -(shift_power(m, e) @ theta_star))
+
+
+def test_order2_twice_equals_order4():
+    """Appendix: two second-order steps equal one fourth-order step."""
+    s = inputs.spd_qlq(40, 30.0, seed=9)
+    alpha = oracle.alpha_frobenius(s.A)
+    g0 = np.eye(40) / alpha
+    g2 = oracle.ns_step(s.A, oracle.ns_step(s.A, g0, 2, "squaring"), 2, "squaring")
+    g4 = oracle.ns_step(s.A, g0, 4, "squaring")
+    assert np.linalg.norm(g2 - g4) <= 1e-13 * np.linalg.norm(g4)
+
+
+def test_splitting_condition_and_divergence():
+    """rho(I - A/alpha) < 1 iff 2 alpha I - A is positive definite (Section 2);
+    a violated condition is reported as divergence."""
+    s = inputs.spd_qlq(32, 10.0, seed=4)
+    lmax = float(s.lam.max())
+    for alpha in (0.4 * lmax, 0.6 * lmax, lmax, oracle.alpha_frobenius(s.A)):
+        rho = np.max(np.abs(1.0 - s.lam / alpha))
+        assert (rho < 1.0) == oracle.splitting_condition(s.A, alpha)
+    assert oracle.alpha_frobenius(s.A) >= lmax
+    # alpha = 0.4 lambda_max < lambda_max / 2: diverges.
+    eps = 0.4 * lmax - float(np.max(np.sum(np.abs(s.A), axis=1))) / 2.0
+    rep = oracle.solve(s.A, s.b, oracle.SolveOptions(order=4, scale="inf_half", eps=eps))
+    assert rep.ns_stop == "diverged"
+    # Indefinite matrix: diverges under the Frobenius scaling too.
+    a_bad = s.A - 2.0 * np.eye(32) * s.lam.min() - np.outer(s.Q[:, 0], s.Q[:, 0]) * 5.0
+    rep = oracle.solve(a_bad, s.b, oracle.SolveOptions(order=4))
+    assert rep.ns_stop == "diverged"
+
+
+def test_iterates_symmetric():
+    """Every G_k is a polynomial in A, hence symmetric to rounding."""
+    s = inputs.spd_qlq(128, 1e3, seed=12)
+    alpha = oracle.alpha_frobenius(s.A)
+    g = np.eye(128) / alpha
+    for _ in range(4):
+        g = oracle.ns_step(s.A, g, 8, "squaring")
+        assert np.linalg.norm(g - g.T) <= 1e-13 * np.linalg.norm(g)
+
+
+def test_stop_rule():
+    chk = oracle.stop_check
+    # slow start with ratios near 1 is not a floor
+    h = [64.0, 63.9, 63.7, 60.0]
+    assert chk(h, 0.0, 3, 64) is None
+    # fast regime entered, then stagnation: floor
+    h = [64.0, 50.0, 10.0, 1e-3, 4e-11, 3.9e-11]
+    assert chk(h, 0.0, 4, 64) is None
+    assert chk(h, 0.0, 5, 64) == "floor"
+    assert chk(h, 0.0, 5, 64, floor_detect=False) is None
+    assert chk(h, 1e-10, 4, 64) == "f_tol"
+    assert chk([1.0, 2.0], 0.0, 1, 64) == "diverged"
+    assert chk([1.0, float("nan")], 0.0, 1, 64) == "diverged"
+    assert chk([1.0, 0.9], 0.0, 1, 1) == "k_max"
+
+
+def test_spd64_trace_and_floor():
+    """N=64, kappa=100, order 4, 12 steps: the relative residual reaches the
+    1e-13 target and the ||F|| trace follows the closed form until the floor."""
+    s = inputs.spd_qlq(64, 100.0, seed=1)
+    rep = oracle.solve(s.A, s.b, oracle.SolveOptions(order=4, k_max=12, floor_detect=False,
+                                                     resid_tol=1e-13))
+    assert rep.ns_steps == 12
+    assert rep.rel_resid <= 1e-13
+    assert rep.mmm == 1 + 12 * 4          # F_0, then 4 mmm per step (Table 1, h=4)
+    for k in range(1, 7):
+        ref = eigen_fnorm(s.lam, rep.alpha, 4 ** k)
+        if ref > 1e-9:
+            assert rep.fnorm_hist[k] == pytest.approx(ref, rel=1e-9)
+    assert max(rep.fnorm_hist[8:]) < 1e-12
