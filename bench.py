@@ -1,0 +1,232 @@
+#!/usr/bin/env python3
+"""Benchmark: coupled high-order Newton-Schulz / Richardson SPD solves on one MI355X.
+
+One "step" is one whole solve (richardson_ns_solve through the C ABI) of a
+seeded synthetic system already resident in HBM: N = 4096, kappa = 1e4,
+A = Q diag(lam) Q^T, order-8 factorized Newton-Schulz (I+F)(I+F^2)(I+F^4) in
+float64 until the ||F|| rounding floor, coupled Richardson updates and float64
+refinement to a relative residual of 1e-12.
+
+Prints ONE JSON line (see the keys below).  The float64 GEMM's roofline comes
+from per-launch HIP events recorded by the library on its stream during the
+timed region; the CPU baseline is the oracle timed on a bounded sample.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+from paper_2008_11480_amd import inputs  # noqa: E402
+
+PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3, "bf16": 2500.0}
+HBM_PEAK_GBS = 8000.0
+GEMM_KERNEL_SRC = os.path.join(ROOT, "paper_2008_11480_amd", "csrc", "nsr_gemm_f64.hip")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "gemm_f64_spd4096_traffic.json")
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def kernel_hash(path):
+    with open(path, "rb") as fh:
+        return hashlib.sha256(fh.read()).hexdigest()[:16]
+
+
+def traffic_per_launch():
+    """HBM bytes per GEMM launch from the committed rocprofv3 PMC summary,
+    or None when the kernel source changed since the counters were taken."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            t = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if t.get("kernel_sha256_16") != kernel_hash(GEMM_KERNEL_SRC):
+        return None
+    return t.get("bytes_per_launch")
+
+
+def blas_threads():
+    try:
+        import threadpoolctl
+        info = threadpoolctl.threadpool_info()
+        n = [i.get("num_threads", 0) for i in info if i.get("user_api") == "blas"]
+        return int(max(n)) if n else os.cpu_count()
+    except Exception:
+        return os.cpu_count()
+
+
+def cpu_baseline(sysm, order, steps_per_solve, refine_steps):
+    """Oracle (numpy float64) on a bounded sample: one order-`order` squaring
+    step (its residual included) plus one Richardson update, on the same
+    N = 4096 system; scaled to solves/s with the GPU solve's step count."""
+    import oracle
+    a, b = sysm.A, sysm.b
+    alpha = oracle.alpha_frobenius(a)
+    g = np.eye(a.shape[0]) / alpha
+    theta = g @ b
+    t0 = time.perf_counter()
+    g = oracle.ns_step(a, g, order, "squaring")
+    theta, _ = oracle.richardson_update(a, b, theta, g)
+    f = oracle.residual(a, g)
+    t_step = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    theta, _ = oracle.richardson_update(a, b, theta, g)
+    t_ref = time.perf_counter() - t0
+    del f
+    t_solve = steps_per_solve * t_step + (refine_steps + 1) * t_ref
+    return {
+        "value": 1.0 / t_solve,
+        "unit": "solves/s",
+        "cores": blas_threads(),
+        "kind": "oracle",
+        "sample": (f"one oracle Newton-Schulz step (order {order}, squaring form, "
+                   f"{oracle.form_mmm(order, 'squaring')} mmm with its residual) plus one "
+                   f"Richardson update at N={a.shape[0]} took {t_step:.2f} s; scaled to the "
+                   f"GPU solve's {steps_per_solve} steps + {refine_steps + 1} residual "
+                   f"evaluations"),
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="spd4096_k1e4_o8",
+                    choices=["spd4096_k1e4_o8", "spd64_k1e2_o4"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibrate-copy-mib", type=int, default=0,
+                    help="also run a plain device copy of this many MiB (PMC calibration)")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU: the solver runs on a single MI355X "
+              "(see DESIGN.md for how the path would shard); --gpus must be 1.",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2008_11480_amd import nsr
+
+    assert torch.cuda.is_available(), "no GPU"
+    torch.cuda.set_device(0)
+    w = dict(inputs.WORKLOADS[args.workload])
+    n, kappa, order = w["n"], w["kappa"], w["order"]
+    log(f"generating {args.workload}: N={n} kappa={kappa:g} seed={w['seed']}")
+    sysm = inputs.spd_qlq(n, kappa, w["seed"])
+    A = torch.from_numpy(sysm.A).to("cuda")
+    b = torch.from_numpy(sysm.b).to("cuda")
+    theta = torch.zeros_like(b)
+    solver = nsr.Solver(n, composite=False)
+    solver.bind(A)
+    fixed = args.workload == "spd64_k1e2_o4"
+    kw = dict(order=order, form="squaring", k_max=w["k_max"], floor_detect=not fixed,
+              resid_tol=w["resid_tol"])
+
+    if args.calibrate_copy_mib > 0:
+        nel = args.calibrate_copy_mib * (1 << 20) // 8
+        src = torch.ones(nel, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"calibration copy of {args.calibrate_copy_mib} MiB done")
+        del src, dst
+
+    for i in range(args.warmup):
+        rep = solver.solve(b, theta, **kw)
+        log(f"warmup {i}: ns_steps={rep.ns_steps} refine={rep.refine_steps} "
+            f"rel_resid={rep.rel_resid:.2e}")
+    torch.cuda.synchronize()
+
+    solver.timing(True)
+    solver.timing_reset()
+    lat = []
+    reps = []
+    torch.cuda.synchronize()
+    t_begin = time.perf_counter()
+    for i in range(args.steps):
+        t0 = time.perf_counter()
+        rep = solver.solve(b, theta, **kw)
+        lat.append(time.perf_counter() - t0)     # solve() returns after a stream sync
+        reps.append(rep)
+        log(f"step {i}: {lat[-1] * 1e3:.1f} ms ns_steps={rep.ns_steps} mmm={rep.mmm} "
+            f"rel_resid={rep.rel_resid:.2e}")
+    torch.cuda.synchronize()
+    t_total = time.perf_counter() - t_begin
+    launches, gemm_ms, gemm_flop = solver.timing_read(1)
+    solver.timing(False)
+
+    th = theta.cpu().numpy()
+    theta_star = sysm.Q @ ((sysm.Q.T @ sysm.b) / sysm.lam)
+    fwd = float(np.linalg.norm(th - theta_star) / np.linalg.norm(theta_star))
+    rel = float(np.linalg.norm(sysm.b - sysm.A @ th) / np.linalg.norm(sysm.b))
+    last = reps[-1]
+
+    ms_per_step = t_total / args.steps * 1e3
+    value = args.steps / t_total
+    flop_per_solve = last.gemm_flop + 4.0 * n * n * (last.ns_steps + last.refine_steps + 1)
+    avg_launch_ms = gemm_ms / max(launches, 1)
+    flop_per_launch = gemm_flop / max(launches, 1)
+    achieved = flop_per_launch / (avg_launch_ms * 1e-3) / 1e12 if launches else None
+    traffic = traffic_per_launch()
+
+    out = {
+        "metric": "solves/s at rel. residual <= 1e-10 (plain FP64 path)",
+        "value": value,
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": args.workload, "n": n, "kappa": kappa, "order": order,
+            "form": "squaring (I+F)(I+F^2)(I+F^4)", "precision": "fp64",
+            "stop": "||F||_F floor, then Richardson to rel. residual "
+                    f"{w['resid_tol']:g}", "seed": w["seed"],
+        },
+        "roofline": {
+            "bound": "mfma",
+            "kernel": "gemm_f64_kernel<128,128,16>",
+            "achieved": achieved,
+            "peak": PEAK_TFLOPS["f64"],
+            "unit": "TFLOP/s",
+            "frac": (achieved / PEAK_TFLOPS["f64"]) if achieved else None,
+            "traffic": traffic,
+            "launches": launches,
+            "avg_launch_ms": avg_launch_ms,
+            "flop_per_launch": flop_per_launch,
+        },
+        "solve": {
+            "ns_steps": last.ns_steps, "refine_steps": last.refine_steps, "mmm": last.mmm,
+            "ns_stop": last.ns_stop, "rel_resid": rel, "fwd_err_vs_closed_form": fwd,
+            "alg_tflops_per_solve": flop_per_solve / (ms_per_step * 1e-3) / 1e12,
+            "latency_ms_p50": float(np.percentile(np.array(lat) * 1e3, 50)),
+            "latency_ms_p99": float(np.percentile(np.array(lat) * 1e3, 99)),
+            "fnorm_hist": last.fnorm_hist,
+        },
+    }
+    if not args.no_cpu_baseline:
+        log("timing the CPU oracle on a bounded sample")
+        out["cpu_baseline"] = cpu_baseline(sysm, order, last.ns_steps, last.refine_steps)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

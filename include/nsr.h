@@ -1,0 +1,236 @@
+/*
+ * nsr.h -- C ABI of a high-order Newton-Schulz / Richardson solver for SPD
+ * systems on AMD Instinct MI355X (gfx950).
+ *
+ * Method: Stotsky, "Convergence Rate Improvement of Richardson and
+ * Newton-Schulz Iterations" (arXiv 2008.11480).
+ *   problem            A theta* = b, A symmetric positive definite   (eq. ae1)
+ *   preconditioner     S^{-1} = I / alpha                            (Section 2)
+ *   Newton-Schulz      G_k = G_{k-1} P(F_{k-1}),  F = I - A G,
+ *                      P(F) = I + F + ... + F^{n-1}                  (eqs. ns, fk1)
+ *   factorized forms   (I+F)(I+F^2)(I+F^4)..., Horner, unified (p,w) (Section 4,
+ *                                                                     Appendix)
+ *   composite form     double Newton-Schulz                          (Section 5.1)
+ *   Richardson         theta_k = theta_{k-1} + G_k (b - A theta_{k-1}) (eq. redttk1)
+ *
+ * The residual is kept on the right, F = I - A G and G <- G P(F); every
+ * iterate is a polynomial in A, so this is the paper's left-residual
+ * iteration with the products mirrored, and F_{k+1} = F_k^n holds exactly.
+ *
+ * Conventions
+ *   - Every call returns an int status: NS_OK (0) or a negative ns_status.
+ *     ns_status_string() names a status, ns_last_error() gives the message of
+ *     the calling thread's most recent failure.  No C++ exception and no
+ *     abort() crosses this boundary.
+ *   - Matrices are row-major float64 with a leading dimension (ld >= n).
+ *     All matrix and vector pointers are DEVICE pointers unless stated.
+ *   - The caller owns A, b, theta and the workspace; the library never calls
+ *     hipMalloc on the solve path.  A is borrowed from ns_bind() until the
+ *     next ns_bind() or ns_destroy(); it is never written.
+ *   - All work is enqueued on the stream given to ns_create() (a hipStream_t
+ *     passed as void*; NULL is the default stream).  Calls that return a
+ *     host-visible number (alpha_out, fnorm_out, reports) synchronize that
+ *     stream before returning.
+ *   - A solver handle is not thread-safe: one handle per host thread.
+ */
+#ifndef NSR_H
+#define NSR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  NS_OK = 0,
+  NS_EINVAL = -1,      /* bad argument, unsupported option combination      */
+  NS_ENOTSPD = -2,     /* alpha <= 0 or non-finite: A cannot be SPD          */
+  NS_EDIVERGED = -3,   /* ||F_k||_F grew above ||F_0||_F or became non-finite */
+  NS_ENOCONV = -4,     /* resid_tol not reached within k_max / refine_max    */
+  NS_ENOMEM = -5,      /* workspace too small                                */
+  NS_EHIP = -6,        /* a HIP runtime call failed                          */
+  NS_EBUSY = -7,       /* batch ticket not finished (ns_batch_poll, wait=0)  */
+  NS_EPRECISION = -8,  /* precision mode cannot reach the tolerance          */
+  NS_ESTATE = -9       /* call out of order (e.g. ns_step before ns_init_scale) */
+} ns_status;
+
+typedef enum {
+  NS_PREC_FP64 = 0,       /* every product and vector in float64             */
+  NS_PREC_FP32 = 1,       /* products in float32 MFMA, Richardson in float64 */
+  NS_PREC_MIXED_BF16 = 2  /* powers of F in bf16 MFMA (fp32 accumulate), the
+                             residual and G-side products in float32,
+                             Richardson in float64                           */
+} ns_precision;
+
+typedef enum {
+  NS_SCALE_FROBENIUS = 0, /* alpha = ||A||_F  (lambda_max <= ||A||_F, so the
+                             splitting condition 2S - A > 0 holds)           */
+  NS_SCALE_INF_HALF = 1   /* alpha = ||A||_inf / 2 + eps (Section 2)         */
+} ns_scale;
+
+typedef enum {
+  NS_FACT_HORNER = 0,        /* Horner's scheme, eq. (z1): n mmm per step      */
+  NS_FACT_SQUARING = 1,      /* (I+F)(I+F^2)(I+F^4)..., n = 2^s: 2s mmm
+                                (Tables 1-2, orders 2, 4, 8)                   */
+  NS_FACT_UNIFIED = 3,       /* eqs. (xa2)-(zi1), n = w(p+1): p+w+1 mmm        */
+  NS_FACT_UNIFIED_PLUS1 = 4, /* eq. (ztab2), n = w(p+1)+1                      */
+  NS_FACT_COMPOSITE_DOUBLE = 5 /* double Newton-Schulz, Section 5.1; inner
+                                  sums in the squaring form (n = 2^s)          */
+} ns_factorization;
+
+/* Why a phase of richardson_ns_solve ended (ns_solve_report.*_stop). */
+typedef enum {
+  NS_STOP_NONE = 0,
+  NS_STOP_F_TOL = 1,        /* ||F_k||_F <= f_tol                              */
+  NS_STOP_FLOOR = 2,        /* rounding floor: an earlier ||F|| ratio was < 1/2
+                               and the current one is > 1/2                    */
+  NS_STOP_K_MAX = 3,
+  NS_STOP_DIVERGED = 4,     /* ||F_k|| > ||F_0|| or non-finite                 */
+  NS_STOP_RESID_TOL = 5,    /* ||b - A theta|| / ||b|| <= resid_tol            */
+  NS_STOP_REFINE_MAX = 6,
+  NS_STOP_REFINE_STALL = 7  /* less than a factor 2 over 3 refinement steps    */
+} ns_stop_reason;
+
+typedef struct ns_solver ns_solver;
+
+/* Bytes of device workspace a solver of dimension n needs for the given
+ * precision; composite != 0 adds the buffers of the double Newton-Schulz
+ * loop.  Returns 0 for n < 1 or an unknown precision. */
+size_t ns_workspace_bytes(int64_t n, int precision, int composite);
+
+/* Create a solver for n x n systems on HIP device `device`, enqueuing on
+ * `hip_stream`.  `workspace` is a device buffer of `bytes` bytes (at least
+ * ns_workspace_bytes(n, precision, composite) with composite = 1 if the
+ * composite form will be used, 256-byte aligned), owned by the caller and
+ * used exclusively by this solver until ns_destroy().  Errors: NS_EINVAL (n<1,
+ * unknown precision, NULL out/workspace, misaligned workspace), NS_ENOMEM
+ * (bytes too small), NS_EHIP. */
+int ns_create(int device, void* hip_stream, int64_t n, int precision,
+              void* workspace, size_t bytes, ns_solver** out);
+
+int ns_destroy(ns_solver* s);
+
+/* Borrow A (device, row-major float64, lda >= n, symmetric positive definite;
+ * symmetry is assumed, not checked).  Resets the iteration state.  In the
+ * float32 / mixed modes this also stores a float32 copy of A in the
+ * workspace.  Errors: NS_EINVAL (NULL, lda < n). */
+int ns_bind(ns_solver* s, const double* A, int64_t lda);
+
+/* Section 2 (scalar preconditioner): compute alpha (NS_SCALE_FROBENIUS:
+ * ||A||_F; NS_SCALE_INF_HALF: max row sum / 2 + eps), set G_0 = I / alpha
+ * (kept implicit, never materialised) and F_0 = I - A G_0, and return alpha
+ * and ||F_0||_F (either out pointer may be NULL).  Errors: NS_ESTATE (no A
+ * bound), NS_ENOTSPD (alpha not finite or <= 0). */
+int ns_init_scale(ns_solver* s, int scale, double eps, double* alpha_out,
+                  double* fnorm0_out);
+
+/* One Newton-Schulz step of order `order` evaluated by `factorization`
+ * (p, w used by the unified forms only): G_k = G_{k-1} P(F_{k-1}), then
+ * F_k = I - A G_k, eq. (ns) and (fk1).  For NS_FACT_COMPOSITE_DOUBLE it is
+ * one step of eqs. (gamk11)-(fks1) (the first call also forms L_0).  Writes
+ * ||F_k||_F to fnorm_out when non-NULL (this synchronizes the stream).
+ * Errors: NS_ESTATE (before ns_init_scale), NS_EINVAL (order < 2, order not
+ * matching the factorization, factorization unsupported for the precision). */
+int ns_step(ns_solver* s, int order, int factorization, int p, int w,
+            double* fnorm_out);
+
+/* Copy the current G_k into G_out (device, row-major float64, ldg >= n). */
+int ns_get_G(ns_solver* s, double* G_out, int64_t ldg);
+
+/* Copy the current F_k = I - A G_k into F_out (device, float64, ldf >= n). */
+int ns_get_F(ns_solver* s, double* F_out, int64_t ldf);
+
+/* One Richardson step with the current G: r = b - A theta (float64),
+ * theta += G r (eq. redttk1 with omega = G).  b, theta: device float64 of
+ * length n.  Writes ||r||_2 (of the residual BEFORE the update) to
+ * rnorm_out when non-NULL. */
+int ns_richardson_step(ns_solver* s, const double* b, double* theta, double* rnorm_out);
+
+typedef struct {
+  int order;          /* n >= 2                                              */
+  int factorization;  /* ns_factorization                                    */
+  int p, w;           /* unified-form parameters                             */
+  int k_max;          /* at most this many Newton-Schulz steps (<= 64)       */
+  int refine_max;     /* at most this many refinement-only Richardson steps  */
+  int floor_detect;   /* 1: stop Newton-Schulz at the rounding floor         */
+  int scale;          /* ns_scale                                            */
+  double eps;         /* for NS_SCALE_INF_HALF                               */
+  double f_tol;       /* stop Newton-Schulz when ||F_k||_F <= f_tol          */
+  double resid_tol;   /* target of ||b - A theta||_2 / ||b||_2               */
+  int theta0_mode;    /* 0: theta_0 = G_0 b;  1: theta_0 = 0;  2: caller's   */
+} ns_solve_opts;
+
+#define NS_HIST_F 65
+#define NS_HIST_R 200
+
+typedef struct {
+  int status;            /* NS_OK, NS_EDIVERGED or NS_ENOCONV               */
+  int ns_stop;           /* ns_stop_reason of the Newton-Schulz phase        */
+  int refine_stop;       /* ns_stop_reason of the refinement phase           */
+  int ns_steps;
+  int refine_steps;
+  int precision;         /* ns_precision the solve ran in                    */
+  double alpha;
+  double rel_resid;      /* ||b - A theta||_2 / ||b||_2 of the returned theta */
+  int64_t mmm;           /* matrix-matrix products executed                  */
+  double gemm_flop;      /* 2 n^3 per product                               */
+  int n_fnorm;           /* entries of fnorm_hist: ||F_k||_F, k = 0..ns_steps */
+  double fnorm_hist[NS_HIST_F];
+  int n_resid;           /* entries of resid_hist: relative residual of every
+                            theta formed, in order                           */
+  double resid_hist[NS_HIST_R];
+} ns_solve_report;
+
+/* Coupled solve (eq. redttk1 with omega_k = G_k, Newton-Schulz first in each
+ * step): ns_init_scale, theta_0 per theta0_mode, then per step k ns_step and
+ * one Richardson update with G_k, then the stop rule on ||F_k||_F; then
+ * refinement-only Richardson steps until resid_tol, refine_max or a stall.
+ * theta (device, length n) receives the solution.  report may be NULL.
+ * Returns NS_OK if resid_tol was reached, NS_ENOCONV if not, NS_EDIVERGED if
+ * the iteration diverged (theta is then undefined). */
+int richardson_ns_solve(ns_solver* s, const double* b, double* theta,
+                        const ns_solve_opts* opts, ns_solve_report* report);
+
+/* Per-kernel timing with HIP events on the solver's stream.  While enabled,
+ * every GEMM launch is bracketed by an event pair.  ns_timing_read returns
+ * the number of timed GEMM launches, their summed duration (ms) and their
+ * summed algorithmic flop (2 m n k each) since the last reset, synchronizing
+ * the stream.  kind: 0 = all GEMMs, 1 = float64 GEMMs, 2 = float32,
+ * 3 = bf16. */
+int ns_timing_enable(ns_solver* s, int enable);
+int ns_timing_read(ns_solver* s, int kind, int64_t* launches, double* total_ms,
+                   double* flop);
+int ns_timing_reset(ns_solver* s);
+
+/* Kernel-level entry point (tests, benchmarks): one float64 MFMA GEMM with
+ * the solver's fused epilogue,
+ *   D = diag * I + scale * (X Y) + E1 + E2,       X: m x k, Y: k x n,
+ * E1 / E2 optional (NULL), row-major device float64 with leading dimensions.
+ * D must not alias X or Y.  If sumsq_out is non-NULL it must point to
+ * 1 + ns_gemm_f64_partials(m, n) device doubles: sumsq_out[0] receives
+ * sum(D_ij^2), reduced in a fixed order, the rest is scratch for per-tile
+ * partial sums.  Enqueued on hip_stream; does not synchronize.  Errors:
+ * NS_EINVAL (negative size, NULL operand, ld too small, D aliasing X or Y),
+ * NS_EHIP (launch failure). */
+int ns_gemm_f64(void* hip_stream, int64_t m, int64_t n, int64_t k,
+                const double* X, int64_t ldx, const double* Y, int64_t ldy,
+                double* D, int64_t ldd, const double* E1, int64_t lde1,
+                const double* E2, int64_t lde2, double diag, double scale,
+                double* sumsq_out);
+
+/* Number of per-tile partial sums ns_gemm_f64 writes for an m x n output. */
+int64_t ns_gemm_f64_partials(int64_t m, int64_t n);
+
+const char* ns_status_string(int status);
+const char* ns_last_error(void);
+
+/* Library version string. */
+const char* ns_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* NSR_H */

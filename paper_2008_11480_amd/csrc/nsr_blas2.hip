@@ -1,0 +1,247 @@
+// HBM-bound kernels of the solver: norms for the scalar preconditioner
+// (Section 2), the implicit G_0 = I / alpha, and the Richardson mat-vecs
+// r = b - A theta and theta += G r (eq. redttk1).  All reductions go through
+// per-block partials reduced in a fixed order, so results are deterministic.
+#include "nsr_internal.h"
+
+namespace nsr {
+
+namespace {
+
+constexpr int kThreads = 256;
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+__device__ __forceinline__ double block_sum(double v, double* red) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  v = wave_sum(v);
+  if (lane == 0) red[wave] = v;
+  __syncthreads();
+  double out = 0.0;
+  if (threadIdx.x == 0) out = (red[0] + red[1]) + (red[2] + red[3]);
+  return out;
+}
+
+// One block per 'rows_per_block' rows; sum of squares of the block's rows.
+constexpr int kRowsPerBlock = 8;
+
+__global__ void __launch_bounds__(kThreads)
+sumsq_kernel(const double* __restrict__ A, int64_t lda, int64_t n, double* __restrict__ partial) {
+  __shared__ double red[4];
+  const int64_t r0 = (int64_t)blockIdx.x * kRowsPerBlock;
+  double s = 0.0;
+  for (int rr = 0; rr < kRowsPerBlock; ++rr) {
+    const int64_t row = r0 + rr;
+    if (row >= n) break;
+    const double* a = A + row * lda;
+    for (int64_t c = threadIdx.x; c < n; c += kThreads) {
+      const double v = a[c];
+      s += v * v;
+    }
+  }
+  const double t = block_sum(s, red);
+  if (threadIdx.x == 0) partial[blockIdx.x] = t;
+}
+
+// One wave per row: rowsum[row] = sum_j |A[row][j]|.
+__global__ void __launch_bounds__(kThreads)
+rowabs_kernel(const double* __restrict__ A, int64_t lda, int64_t n, double* __restrict__ rowsum) {
+  const int lane = threadIdx.x & 63;
+  const int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (row >= n) return;
+  const double* a = A + row * lda;
+  double s = 0.0;
+  for (int64_t c = lane; c < n; c += 64) s += fabs(a[c]);
+  s = wave_sum(s);
+  if (lane == 0) rowsum[row] = s;
+}
+
+// Single block, fixed order: out = sum / max / sqrt(sum) of partial[0..count).
+__global__ void __launch_bounds__(kThreads)
+reduce_kernel(const double* __restrict__ partial, int64_t count, double* __restrict__ out, int mode,
+              double eps) {
+  __shared__ double sh[kThreads];
+  const bool is_max = (mode == 1 || mode == 3);
+  double v = is_max ? -INFINITY : 0.0;
+  for (int64_t i = threadIdx.x; i < count; i += kThreads) {
+    const double x = partial[i];
+    v = is_max ? fmax(v, x) : v + x;
+  }
+  sh[threadIdx.x] = v;
+  __syncthreads();
+  for (int w = kThreads / 2; w > 0; w >>= 1) {
+    if (threadIdx.x < w) {
+      const double a = sh[threadIdx.x], b = sh[threadIdx.x + w];
+      sh[threadIdx.x] = is_max ? fmax(a, b) : a + b;
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    double r = sh[0];
+    if (mode == 2) r = sqrt(r);
+    if (mode == 3) r = 0.5 * r + eps;   // ||A||_inf / 2 + eps
+    out[0] = r;
+  }
+}
+
+// F = I - A / alpha, sum of F^2 per block (one block per kRowsPerBlock rows).
+__global__ void __launch_bounds__(kThreads)
+init_resid_kernel(const double* __restrict__ A, int64_t lda, int64_t n,
+                  const double* __restrict__ alpha, double* __restrict__ F, int64_t ldf,
+                  double* __restrict__ partial) {
+  __shared__ double red[4];
+  const double inv = 1.0 / alpha[0];
+  const int64_t r0 = (int64_t)blockIdx.x * kRowsPerBlock;
+  double s = 0.0;
+  for (int rr = 0; rr < kRowsPerBlock; ++rr) {
+    const int64_t row = r0 + rr;
+    if (row >= n) break;
+    for (int64_t c = threadIdx.x; c < n; c += kThreads) {
+      double v = -A[row * lda + c] * inv;
+      if (c == row) v += 1.0;
+      F[row * ldf + c] = v;
+      s += v * v;
+    }
+  }
+  const double t = block_sum(s, red);
+  if (partial && threadIdx.x == 0) partial[blockIdx.x] = t;
+}
+
+// G = (I + C) / alpha  (C may be null).
+__global__ void __launch_bounds__(kThreads)
+scaled_identity_plus_kernel(const double* __restrict__ C, int64_t ldc, int64_t n,
+                            const double* __restrict__ alpha, double* __restrict__ G, int64_t ldg) {
+  const double inv = 1.0 / alpha[0];
+  const int64_t row = blockIdx.y;
+  const int64_t c = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (row >= n || c >= n) return;
+  double v = C ? C[row * ldc + c] : 0.0;
+  if (c == row) v += 1.0;
+  G[row * ldg + c] = v * inv;
+}
+
+// r = b - A theta: one wave per row, 4 rows per block; partial sum of r^2.
+__global__ void __launch_bounds__(kThreads)
+gemv_resid_kernel(const double* __restrict__ A, int64_t lda, int64_t n,
+                  const double* __restrict__ b, const double* __restrict__ theta,
+                  double* __restrict__ r, double* __restrict__ partial) {
+  __shared__ double red[4];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int64_t row = (int64_t)blockIdx.x * 4 + wave;
+  double rv = 0.0;
+  if (row < n) {
+    const double* a = A + row * lda;
+    double s = 0.0;
+    for (int64_t c = lane; c < n; c += 64) s += a[c] * theta[c];
+    s = wave_sum(s);
+    rv = b[row] - s;
+    if (lane == 0) r[row] = rv;
+  }
+  if (lane == 0) red[wave] = rv * rv;
+  __syncthreads();
+  if (threadIdx.x == 0 && partial) partial[blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
+}
+
+// theta += G r: one wave per row.
+__global__ void __launch_bounds__(kThreads)
+gemv_update_kernel(const double* __restrict__ G, int64_t ldg, int64_t n,
+                   const double* __restrict__ r, double* __restrict__ theta) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int64_t row = (int64_t)blockIdx.x * 4 + wave;
+  if (row >= n) return;
+  const double* g = G + row * ldg;
+  double s = 0.0;
+  for (int64_t c = lane; c < n; c += 64) s += g[c] * r[c];
+  s = wave_sum(s);
+  if (lane == 0) theta[row] += s;
+}
+
+__global__ void __launch_bounds__(kThreads)
+vec_scale_kernel(const double* __restrict__ b, const double* __restrict__ alpha,
+                 double* __restrict__ theta, int64_t n, int accumulate) {
+  const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (i >= n) return;
+  const double v = b[i] / alpha[0];
+  theta[i] = accumulate ? theta[i] + v : v;
+}
+
+__global__ void __launch_bounds__(kThreads)
+vec_sumsq_kernel(const double* __restrict__ v, int64_t n, double* __restrict__ partial) {
+  __shared__ double red[4];
+  double s = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * kThreads)
+    s += v[i] * v[i];
+  const double t = block_sum(s, red);
+  if (threadIdx.x == 0) partial[blockIdx.x] = t;
+}
+
+}  // namespace
+
+int64_t sumsq_partials(int64_t n) { return (n + kRowsPerBlock - 1) / kRowsPerBlock; }
+int64_t gemv_partials(int64_t n) { return (n + 3) / 4; }
+
+int64_t launch_sumsq(const double* A, int64_t lda, int64_t n, double* partial, hipStream_t st) {
+  const int64_t nb = sumsq_partials(n);
+  hipLaunchKernelGGL(sumsq_kernel, dim3((unsigned)nb), dim3(kThreads), 0, st, A, lda, n, partial);
+  return nb;
+}
+
+void launch_rowabs(const double* A, int64_t lda, int64_t n, double* rowsum, hipStream_t st) {
+  hipLaunchKernelGGL(rowabs_kernel, dim3((unsigned)((n + 3) / 4)), dim3(kThreads), 0, st, A, lda,
+                     n, rowsum);
+}
+
+void launch_reduce(const double* partial, int64_t count, double* out, int mode, double eps,
+                   hipStream_t st) {
+  hipLaunchKernelGGL(reduce_kernel, dim3(1), dim3(kThreads), 0, st, partial, count, out, mode, eps);
+}
+
+int64_t launch_init_resid(const double* A, int64_t lda, int64_t n, const double* alpha, double* F,
+                          int64_t ldf, double* partial, hipStream_t st) {
+  const int64_t nb = sumsq_partials(n);
+  hipLaunchKernelGGL(init_resid_kernel, dim3((unsigned)nb), dim3(kThreads), 0, st, A, lda, n,
+                     alpha, F, ldf, partial);
+  return nb;
+}
+
+void launch_scaled_identity_plus(const double* C, int64_t ldc, int64_t n, const double* alpha,
+                                 double* G, int64_t ldg, hipStream_t st) {
+  dim3 grid((unsigned)((n + kThreads - 1) / kThreads), (unsigned)n);
+  hipLaunchKernelGGL(scaled_identity_plus_kernel, grid, dim3(kThreads), 0, st, C, ldc, n, alpha, G,
+                     ldg);
+}
+
+int64_t launch_gemv_resid(const double* A, int64_t lda, int64_t n, const double* b,
+                          const double* theta, double* r, double* partial, hipStream_t st) {
+  const int64_t nb = gemv_partials(n);
+  hipLaunchKernelGGL(gemv_resid_kernel, dim3((unsigned)nb), dim3(kThreads), 0, st, A, lda, n, b,
+                     theta, r, partial);
+  return nb;
+}
+
+void launch_gemv_update(const double* G, int64_t ldg, int64_t n, const double* r, double* theta,
+                        hipStream_t st) {
+  hipLaunchKernelGGL(gemv_update_kernel, dim3((unsigned)((n + 3) / 4)), dim3(kThreads), 0, st, G,
+                     ldg, n, r, theta);
+}
+
+void launch_vec_scale(const double* b, const double* alpha, double* theta, int64_t n,
+                      int accumulate, hipStream_t st) {
+  hipLaunchKernelGGL(vec_scale_kernel, dim3((unsigned)((n + kThreads - 1) / kThreads)),
+                     dim3(kThreads), 0, st, b, alpha, theta, n, accumulate);
+}
+
+int64_t launch_vec_sumsq(const double* v, int64_t n, double* partial, hipStream_t st) {
+  int64_t nb = (n + kThreads - 1) / kThreads;
+  if (nb > 1024) nb = 1024;
+  if (nb < 1) nb = 1;
+  hipLaunchKernelGGL(vec_sumsq_kernel, dim3((unsigned)nb), dim3(kThreads), 0, st, v, n, partial);
+  return nb;
+}
+
+}  // namespace nsr

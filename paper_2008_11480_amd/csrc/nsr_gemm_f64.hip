@@ -1,0 +1,242 @@
+// Float64 MFMA GEMM for gfx950 with the solver's fused epilogue
+//
+//   D = diag * I + scale * (X Y) + E1 + E2        (row-major, float64)
+//
+// Every product of the Newton-Schulz step is one such GEMM: the residual
+// F = I - A G (diag = 1, scale = -1; eqs. xa2 / fk1), the powers F^2 = F F,
+// the identity-offset assembly C' = C + F^(2^i) + C F^(2^i) of the factor
+// (I + C)(I + F^(2^i)) (Tables 1-2), and the G-side update G + G C (eq. ns).
+// When asked, the epilogue also writes one partial sum of D^2 per tile, which
+// a fixed-order reduction turns into ||F||_F.
+//
+// Design (CDNA4):
+//  * v_mfma_f64_16x16x4_f64: a wave multiplies 16x4 by 4x16 and accumulates a
+//    16x16 float64 block; lane l supplies X[i = l%16][k = l/16] and
+//    Y[k = l/16][j = l%16] and holds D[4*(l/16) + r][l%16], r = 0..3.
+//  * A workgroup of 4 waves owns a BM x BN output tile; each wave owns a
+//    (BM/2) x (BN/2) quadrant = (BM/32) x (BN/32) MFMA blocks kept in
+//    registers for the whole K loop.
+//  * K is walked in slabs of BK.  Each slab of X (BM x BK) and Y (BK x BN) is
+//    loaded from global memory into registers one slab ahead (16-byte loads,
+//    coalesced along rows), stored into one of two LDS buffers and read back
+//    as MFMA fragments; one barrier per slab.
+//  * Tile order is XCD-aware: consecutive workgroup ids land on different
+//    XCDs, so each XCD is given a contiguous run of a grouped (8 tile-rows)
+//    order, keeping the X row panels and Y column panels it reuses in its own
+//    L2.
+#include "nsr_internal.h"
+
+namespace nsr {
+
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+
+namespace {
+
+__device__ __forceinline__ void map_tile(int bid, int tiles_m, int tiles_n, int& tm, int& tn) {
+  const int ntiles = tiles_m * tiles_n;
+  int t = bid;
+  if ((ntiles & 7) == 0) {
+    const int per = ntiles >> 3;
+    t = (bid & 7) * per + (bid >> 3);
+  }
+  constexpr int GM = 8;
+  const int group_size = GM * tiles_n;
+  const int g = t / group_size;
+  const int first_m = g * GM;
+  const int gm = min(tiles_m - first_m, GM);
+  const int r = t - g * group_size;
+  tm = first_m + r % gm;
+  tn = r / gm;
+}
+
+template <int BM, int BN, int BK, bool VEC>
+__global__ void __launch_bounds__(256)
+gemm_f64_kernel(GemmF64Args p, int tiles_m, int tiles_n) {
+  constexpr int NT = 256;
+  constexpr int WTM = BM / 2;          // rows per wave
+  constexpr int WTN = BN / 2;          // cols per wave
+  constexpr int FM = WTM / 16;
+  constexpr int FN = WTN / 16;
+  constexpr int XS = BK + 2;           // LDS row stride of the X slab (doubles)
+  constexpr int YS = BN + 2;           // LDS row stride of the Y slab
+  constexpr int XV = (BM * BK / 2) / NT;   // double2 per thread, X slab
+  constexpr int YV = (BK * BN / 2) / NT;   // double2 per thread, Y slab
+  static_assert(XV >= 1 && YV >= 1, "tile too small for 256 threads");
+  static_assert((BM * BK / 2) % NT == 0 && (BK * BN / 2) % NT == 0, "tile/thread mismatch");
+
+  __shared__ __attribute__((aligned(16))) double Xs[2][BM * XS];
+  __shared__ __attribute__((aligned(16))) double Ys[2][BK * YS];
+  __shared__ double red[4];
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int wm = wave >> 1;
+  const int wn = wave & 1;
+  int tm, tn;
+  map_tile(blockIdx.x, tiles_m, tiles_n, tm, tn);
+  const int64_t m0 = (int64_t)tm * BM;
+  const int64_t n0 = (int64_t)tn * BN;
+  const int64_t M = p.M, N = p.N, K = p.K;
+
+  double2 xr[XV];
+  double2 yr[YV];
+
+  auto load = [&](int64_t k0) {
+#pragma unroll
+    for (int v = 0; v < XV; ++v) {
+      const int idx = tid + NT * v;
+      const int row = idx / (BK / 2);
+      const int c = (idx % (BK / 2)) * 2;
+      const int64_t gm = m0 + row;
+      const int64_t gk = k0 + c;
+      double2 val = make_double2(0.0, 0.0);
+      if (gm < M) {
+        const double* src = p.X + gm * p.ldx + gk;
+        if (VEC && gk + 1 < K) {
+          val = *reinterpret_cast<const double2*>(src);
+        } else {
+          if (gk < K) val.x = src[0];
+          if (gk + 1 < K) val.y = src[1];
+        }
+      }
+      xr[v] = val;
+    }
+#pragma unroll
+    for (int v = 0; v < YV; ++v) {
+      const int idx = tid + NT * v;
+      const int row = idx / (BN / 2);
+      const int c = (idx % (BN / 2)) * 2;
+      const int64_t gk = k0 + row;
+      const int64_t gn = n0 + c;
+      double2 val = make_double2(0.0, 0.0);
+      if (gk < K) {
+        const double* src = p.Y + gk * p.ldy + gn;
+        if (VEC && gn + 1 < N) {
+          val = *reinterpret_cast<const double2*>(src);
+        } else {
+          if (gn < N) val.x = src[0];
+          if (gn + 1 < N) val.y = src[1];
+        }
+      }
+      yr[v] = val;
+    }
+  };
+
+  auto store = [&](int buf) {
+#pragma unroll
+    for (int v = 0; v < XV; ++v) {
+      const int idx = tid + NT * v;
+      const int row = idx / (BK / 2);
+      const int c = (idx % (BK / 2)) * 2;
+      *reinterpret_cast<double2*>(&Xs[buf][row * XS + c]) = xr[v];
+    }
+#pragma unroll
+    for (int v = 0; v < YV; ++v) {
+      const int idx = tid + NT * v;
+      const int row = idx / (BN / 2);
+      const int c = (idx % (BN / 2)) * 2;
+      *reinterpret_cast<double2*>(&Ys[buf][row * YS + c]) = yr[v];
+    }
+  };
+
+  f64x4 acc[FM][FN];
+#pragma unroll
+  for (int i = 0; i < FM; ++i)
+#pragma unroll
+    for (int j = 0; j < FN; ++j) acc[i][j] = f64x4{0.0, 0.0, 0.0, 0.0};
+
+  const int nk = (int)((K + BK - 1) / BK);
+  const int lr = lane & 15;
+  const int lk = lane >> 4;
+  if (nk > 0) load(0);
+  for (int kt = 0; kt < nk; ++kt) {
+    const int buf = kt & 1;
+    store(buf);
+    __syncthreads();
+    if (kt + 1 < nk) load((int64_t)(kt + 1) * BK);
+    const double* xs = &Xs[buf][(wm * WTM + lr) * XS + lk];
+    const double* ys = &Ys[buf][lk * YS + wn * WTN + lr];
+#pragma unroll
+    for (int ks = 0; ks < BK; ks += 4) {
+      double a[FM], b[FN];
+#pragma unroll
+      for (int i = 0; i < FM; ++i) a[i] = xs[i * 16 * XS + ks];
+#pragma unroll
+      for (int j = 0; j < FN; ++j) b[j] = ys[ks * YS + j * 16];
+#pragma unroll
+      for (int i = 0; i < FM; ++i)
+#pragma unroll
+        for (int j = 0; j < FN; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
+    }
+  }
+
+  // Epilogue: D = diag I + scale acc + E1 + E2, optional sum of D^2.
+  double ss = 0.0;
+  const double diag = p.diag, scale = p.scale;
+#pragma unroll
+  for (int i = 0; i < FM; ++i) {
+#pragma unroll
+    for (int j = 0; j < FN; ++j) {
+      const int64_t col = n0 + wn * WTN + j * 16 + lr;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t row = m0 + wm * WTM + i * 16 + 4 * lk + r;
+        if (row < M && col < N) {
+          double v = scale * acc[i][j][r];
+          if (row == col) v += diag;
+          if (p.E1) v += p.E1[row * p.lde1 + col];
+          if (p.E2) v += p.E2[row * p.lde2 + col];
+          p.D[row * p.ldd + col] = v;
+          ss += v * v;
+        }
+      }
+    }
+  }
+  if (p.partial) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) ss += __shfl_xor(ss, off, 64);
+    if (lane == 0) red[wave] = ss;
+    __syncthreads();
+    if (tid == 0) p.partial[(int64_t)tm * tiles_n + tn] = (red[0] + red[1]) + (red[2] + red[3]);
+  }
+}
+
+template <int BM, int BN, int BK>
+int64_t launch_cfg(const GemmF64Args& a, hipStream_t st) {
+  const int tiles_m = (int)((a.M + BM - 1) / BM);
+  const int tiles_n = (int)((a.N + BN - 1) / BN);
+  const int64_t nt = (int64_t)tiles_m * tiles_n;
+  const bool vec = ((a.ldx & 1) == 0) && ((a.ldy & 1) == 0) &&
+                   ((reinterpret_cast<uintptr_t>(a.X) & 15) == 0) &&
+                   ((reinterpret_cast<uintptr_t>(a.Y) & 15) == 0);
+  dim3 grid((unsigned)nt), block(256);
+  if (vec)
+    hipLaunchKernelGGL((gemm_f64_kernel<BM, BN, BK, true>), grid, block, 0, st, a, tiles_m, tiles_n);
+  else
+    hipLaunchKernelGGL((gemm_f64_kernel<BM, BN, BK, false>), grid, block, 0, st, a, tiles_m, tiles_n);
+  if (hipGetLastError() != hipSuccess) return -1;
+  return a.partial ? nt : 0;
+}
+
+// Big tiles when they still give at least two workgroups per CU.
+bool use_big(int64_t m, int64_t n) {
+  const int64_t tiles = ((m + 127) / 128) * ((n + 127) / 128);
+  return tiles >= 512;
+}
+
+}  // namespace
+
+int64_t gemm_f64_partials(int64_t m, int64_t n) {
+  if (use_big(m, n)) return ((m + 127) / 128) * ((n + 127) / 128);
+  return ((m + 63) / 64) * ((n + 63) / 64);
+}
+
+int64_t launch_gemm_f64(const GemmF64Args& a, hipStream_t st) {
+  if (a.M <= 0 || a.N <= 0) return 0;
+  if (use_big(a.M, a.N)) return launch_cfg<128, 128, 16>(a, st);
+  return launch_cfg<64, 64, 16>(a, st);
+}
+
+}  // namespace nsr

@@ -1,0 +1,69 @@
+// Internal declarations shared by the kernels and the solver runtime of libnsr.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace nsr {
+
+// D = diag * I + scale * (X Y) + E1 + E2 for row-major float64 operands.
+struct GemmF64Args {
+  const double* X;
+  const double* Y;
+  double* D;
+  const double* E1;  // may be null
+  const double* E2;  // may be null
+  int64_t ldx, ldy, ldd, lde1, lde2;
+  int64_t M, N, K;
+  double diag;
+  double scale;
+  double* partial;   // per-tile sum of D^2 (null: not wanted)
+};
+
+// Number of per-tile partials the GEMM writes for an m x n output (the size
+// the partial buffer must have).
+int64_t gemm_f64_partials(int64_t m, int64_t n);
+
+// Enqueue the GEMM; returns the number of partials written (0 if partial is
+// null) or a negative value on a launch error.
+int64_t launch_gemm_f64(const GemmF64Args& a, hipStream_t st);
+
+// Partial sums of squares of an n x n matrix (one per block); returns the
+// number of partials.
+int64_t launch_sumsq(const double* A, int64_t lda, int64_t n, double* partial, hipStream_t st);
+int64_t sumsq_partials(int64_t n);
+
+// Row sums of |A| -> rowsum (n entries).
+void launch_rowabs(const double* A, int64_t lda, int64_t n, double* rowsum, hipStream_t st);
+
+// out[0] = reduce(partial[0..count)) in a fixed order.  mode 0: sum,
+// 1: max, 2: sqrt(sum), 3: max / 2 + half_plus_eps.
+
+void launch_reduce(const double* partial, int64_t count, double* out, int mode,
+                   double half_plus_eps, hipStream_t st);
+
+// F = I - A / alpha (alpha read from device memory), partial sum of F^2.
+int64_t launch_init_resid(const double* A, int64_t lda, int64_t n, const double* alpha,
+                          double* F, int64_t ldf, double* partial, hipStream_t st);
+
+// G = (I + C) / alpha; C may be null (G = I / alpha).
+void launch_scaled_identity_plus(const double* C, int64_t ldc, int64_t n, const double* alpha,
+                                 double* G, int64_t ldg, hipStream_t st);
+
+// r = b - A theta, partial sums of r^2 (one per block); returns count.
+int64_t launch_gemv_resid(const double* A, int64_t lda, int64_t n, const double* b,
+                          const double* theta, double* r, double* partial, hipStream_t st);
+int64_t gemv_partials(int64_t n);
+
+// theta += G r
+void launch_gemv_update(const double* G, int64_t ldg, int64_t n, const double* r, double* theta,
+                        hipStream_t st);
+
+// theta = b / alpha (alpha on device); theta += r / alpha
+void launch_vec_scale(const double* b, const double* alpha, double* theta, int64_t n,
+                      int accumulate, hipStream_t st);
+
+// Sum of squares of a vector -> partials
+int64_t launch_vec_sumsq(const double* v, int64_t n, double* partial, hipStream_t st);
+
+}  // namespace nsr

@@ -1,0 +1,756 @@
+// Solver runtime behind the C ABI of include/nsr.h.
+//
+// Holds the iteration state in the caller's workspace, turns each Newton-Schulz
+// step into a chain of fused GEMM launches (one per matrix-matrix product the
+// paper counts), runs the coupled Richardson update, and applies the stop
+// rules.  Kernels live in nsr_gemm_f64.hip and nsr_blas2.hip.
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <new>
+#include <vector>
+
+#include "../../include/nsr.h"
+#include "nsr_internal.h"
+
+using namespace nsr;
+
+namespace {
+
+thread_local char g_err[512] = "";
+
+int fail(int code, const char* fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_err, sizeof(g_err), fmt, ap);
+  va_end(ap);
+  return code;
+}
+
+#define HIP_TRY(expr)                                                               \
+  do {                                                                              \
+    hipError_t e_ = (expr);                                                         \
+    if (e_ != hipSuccess)                                                           \
+      return fail(NS_EHIP, "%s failed: %s", #expr, hipGetErrorString(e_));          \
+  } while (0)
+
+constexpr size_t kAlign = 256;
+inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+inline int64_t ld_for(int64_t n) { return (n + 31) / 32 * 32; }
+
+// Number of float64 n x n buffers per mode.
+//   plain:     G0 G1 F P1 P2 C1 C2                  = 7
+//   composite: + L0 L1 Gam H                        = 11
+int n_mats(int composite) { return composite ? 11 : 7; }
+
+int64_t partial_capacity(int64_t n) {
+  int64_t c = gemm_f64_partials(n, n);
+  c = c > sumsq_partials(n) ? c : sumsq_partials(n);
+  c = c > gemv_partials(n) ? c : gemv_partials(n);
+  c = c > 1024 ? c : 1024;
+  c = c > n ? c : n;  // row sums for the infinity norm
+  return c;
+}
+
+size_t layout_bytes(int64_t n, int composite) {
+  const int64_t ld = ld_for(n);
+  size_t bytes = 0;
+  bytes += (size_t)n_mats(composite) * align_up((size_t)n * ld * sizeof(double), kAlign);
+  bytes += align_up((size_t)n * sizeof(double), kAlign);                   // r
+  bytes += align_up((size_t)partial_capacity(n) * sizeof(double), kAlign); // partials
+  bytes += align_up(16 * sizeof(double), kAlign);                          // scalars
+  return bytes;
+}
+
+struct TimedLaunch {
+  hipEvent_t beg, end;
+  int kind;
+  double flop;
+};
+
+}  // namespace
+
+struct ns_solver {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  int64_t n = 0;
+  int64_t ld = 0;
+  int precision = NS_PREC_FP64;
+  int composite_capable = 0;
+  char* ws = nullptr;
+  size_t ws_bytes = 0;
+
+  double* G[2] = {nullptr, nullptr};
+  int gcur = 0;
+  double* F = nullptr;
+  double* P1 = nullptr;
+  double* P2 = nullptr;
+  double* C1 = nullptr;
+  double* C2 = nullptr;
+  double* L[2] = {nullptr, nullptr};
+  int lcur = 0;
+  double* Gam = nullptr;
+  double* H = nullptr;
+  double* r = nullptr;
+  double* partial = nullptr;
+  double* scal = nullptr;  // [0] alpha, [1] ||F||_F, [2] ||r||_2, [3] ||b||_2
+
+  const double* A = nullptr;
+  int64_t lda = 0;
+  bool bound = false;
+  bool scaled = false;
+  bool g_implicit = true;  // G = I / alpha, not materialised
+  bool dns_started = false;
+  double alpha = 0.0;
+  int64_t mmm = 0;
+
+  bool timing = false;
+  std::vector<TimedLaunch> timed;
+  std::vector<hipEvent_t> pool;
+  size_t pool_used = 0;
+};
+
+namespace {
+
+hipEvent_t take_event(ns_solver* s) {
+  if (s->pool_used == s->pool.size()) {
+    hipEvent_t e;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    s->pool.push_back(e);
+  }
+  return s->pool[s->pool_used++];
+}
+
+// One fused float64 GEMM on the solver's stream (timed when enabled).
+int gemm(ns_solver* s, double* D, const double* X, const double* Y, const double* E1,
+         const double* E2, double diag, double scale, bool want_norm) {
+  GemmF64Args a{};
+  a.X = X;
+  a.Y = Y;
+  a.D = D;
+  a.E1 = E1;
+  a.E2 = E2;
+  a.ldx = (X == s->A) ? s->lda : s->ld;
+  a.ldy = (Y == s->A) ? s->lda : s->ld;
+  a.ldd = s->ld;
+  a.lde1 = s->ld;
+  a.lde2 = s->ld;
+  a.M = a.N = a.K = s->n;
+  a.diag = diag;
+  a.scale = scale;
+  a.partial = want_norm ? s->partial : nullptr;
+  hipEvent_t eb = nullptr, ee = nullptr;
+  if (s->timing) {
+    eb = take_event(s);
+    ee = take_event(s);
+    if (!eb || !ee) return fail(NS_EHIP, "hipEventCreate failed");
+    HIP_TRY(hipEventRecord(eb, s->stream));
+  }
+  const int64_t np = launch_gemm_f64(a, s->stream);
+  if (np < 0) return fail(NS_EHIP, "GEMM launch failed: %s", hipGetErrorString(hipGetLastError()));
+  if (s->timing) {
+    HIP_TRY(hipEventRecord(ee, s->stream));
+    const double nn = (double)s->n;
+    s->timed.push_back(TimedLaunch{eb, ee, 1, 2.0 * nn * nn * nn});
+  }
+  s->mmm += 1;
+  if (want_norm) launch_reduce(s->partial, np, s->scal + 1, 2, 0.0, s->stream);
+  return NS_OK;
+}
+
+int read_scalars(ns_solver* s, double* host, int first, int count) {
+  HIP_TRY(hipMemcpyAsync(host, s->scal + first, count * sizeof(double), hipMemcpyDeviceToHost,
+                         s->stream));
+  HIP_TRY(hipStreamSynchronize(s->stream));
+  return NS_OK;
+}
+
+// G_next = G (I + C): GEMM, or (I + C) / alpha while G is still I / alpha.
+int apply_g(ns_solver* s, const double* Gcur, bool implicit, const double* C, double* Gnext) {
+  if (implicit) {
+    launch_scaled_identity_plus(C, s->ld, s->n, s->scal + 0, Gnext, s->ld, s->stream);
+    return NS_OK;
+  }
+  return gemm(s, Gnext, Gcur, C, Gcur, nullptr, 0.0, 1.0, false);
+}
+
+// C with P(Y) = I + C = (I + Y)(I + Y^2)...(I + Y^(2^(s-1))), order 2^s.
+// Uses P1/P2 for the powers and C1/C2 for the assembly; returns the buffer
+// holding C (Y itself for order 2).
+int poly_squaring(ns_solver* s, int order, const double* Y, const double** out) {
+  int sexp = 0;
+  while ((1 << sexp) < order) ++sexp;
+  const double* pw = Y;
+  const double* c = Y;
+  for (int i = 1; i < sexp; ++i) {
+    double* npw = (pw == s->P1) ? s->P2 : s->P1;
+    int rc = gemm(s, npw, pw, pw, nullptr, nullptr, 0.0, 1.0, false);       // Y^(2^i)
+    if (rc) return rc;
+    double* nc = (c == s->C1) ? s->C2 : s->C1;
+    rc = gemm(s, nc, c, npw, c, npw, 0.0, 1.0, false);                      // C + Y^(2^i) + C Y^(2^i)
+    if (rc) return rc;
+    pw = npw;
+    c = nc;
+  }
+  *out = c;
+  return NS_OK;
+}
+
+bool is_pow2(int n) { return n >= 2 && (n & (n - 1)) == 0; }
+
+int resid_into(ns_solver* s, double* D, const double* X, bool want_norm) {
+  return gemm(s, D, s->A, X, nullptr, nullptr, 1.0, -1.0, want_norm);  // I - A X
+}
+
+// Classical step G_k = G_{k-1} P(F_{k-1}) for the non-composite forms;
+// leaves G in s->G[s->gcur].
+int step_classic(ns_solver* s, int order, int fact, int p, int w) {
+  double* Gc = s->G[s->gcur];
+  double* Gn = s->G[s->gcur ^ 1];
+  const bool impl = s->g_implicit;
+  const double inv_alpha = 1.0 / s->alpha;
+  int rc = NS_OK;
+  if (fact == NS_FACT_SQUARING) {
+    const double* c = nullptr;
+    rc = poly_squaring(s, order, s->F, &c);
+    if (rc) return rc;
+    rc = apply_g(s, Gc, impl, c, Gn);
+    if (rc) return rc;
+  } else if (fact == NS_FACT_HORNER || fact == NS_FACT_UNIFIED || fact == NS_FACT_UNIFIED_PLUS1) {
+    // Horner chain U_d = G + U_{d-1} F (eq. z1 / u1), d = 1..hd.
+    int hd = order - 1;
+    if (fact == NS_FACT_UNIFIED) hd = p;
+    if (fact == NS_FACT_UNIFIED_PLUS1) hd = p;
+    const bool plain = (fact == NS_FACT_HORNER) || (fact == NS_FACT_UNIFIED && w == 1);
+    double* bufs[2] = {s->C1, s->C2};
+    const double* u = Gc;  // U_0 = G (may be implicit)
+    bool u_impl = impl;
+    for (int d = 1; d <= hd; ++d) {
+      double* dst = (plain && d == hd) ? Gn : bufs[d & 1];
+      if (u_impl) {
+        launch_scaled_identity_plus(s->F, s->ld, s->n, s->scal + 0, dst, s->ld, s->stream);
+      } else {
+        rc = gemm(s, dst, u, s->F, impl ? nullptr : Gc, nullptr, impl ? inv_alpha : 0.0, 1.0,
+                  false);
+        if (rc) return rc;
+      }
+      u = dst;
+      u_impl = false;
+    }
+    if (plain) {
+      if (hd == 0) return fail(NS_EINVAL, "order too small");
+    } else {
+      // Unified: Y^{p+1} = I - A U (eq. ua1), Z_i = Z_{i-1} Y^{p+1} + U (eq. zi1).
+      const double* uu = u;
+      bool uu_impl = u_impl;  // only when p == 0
+      if (uu_impl) {  // materialise U = G = I / alpha
+        launch_scaled_identity_plus(nullptr, s->ld, s->n, s->scal + 0, s->C1, s->ld, s->stream);
+        uu = s->C1;
+      }
+      const double* yp1 = s->F;
+      if (p > 0 && w > 1) {
+        rc = resid_into(s, s->P1, uu, false);
+        if (rc) return rc;
+        yp1 = s->P1;
+      }
+      const double* z = uu;
+      const bool plus1 = (fact == NS_FACT_UNIFIED_PLUS1);
+      double* zb[2] = {s->P2, (uu == s->C1) ? s->C2 : s->C1};
+      for (int i = 1; i <= w - 1; ++i) {
+        double* dst = (!plus1 && i == w - 1) ? Gn : zb[i & 1];
+        rc = gemm(s, dst, z, yp1, uu, nullptr, 0.0, 1.0, false);
+        if (rc) return rc;
+        z = dst;
+      }
+      if (plus1) {
+        // Z_1 = G + Z F (eq. ztab2).
+        if (impl) {
+          rc = gemm(s, Gn, z, s->F, nullptr, nullptr, inv_alpha, 1.0, false);
+        } else {
+          rc = gemm(s, Gn, z, s->F, Gc, nullptr, 0.0, 1.0, false);
+        }
+        if (rc) return rc;
+      }
+    }
+  } else {
+    return fail(NS_EINVAL, "unsupported factorization %d", fact);
+  }
+  s->gcur ^= 1;
+  s->g_implicit = false;
+  return resid_into(s, s->F, s->G[s->gcur], true);  // F_k = I - A G_k
+}
+
+// Double Newton-Schulz step (Section 5.1, right orientation).
+int step_composite(ns_solver* s, int order) {
+  int rc;
+  const double* c = nullptr;
+  if (!s->dns_started) {
+    if (!s->g_implicit) return fail(NS_ESTATE, "composite form must start from G_0");
+    // T_0 = G_0, Gamma_0 = F_0: L_0 = T_0 P(Gamma_0), Gamma_1 = I - A L_0.
+    rc = poly_squaring(s, order, s->F, &c);
+    if (rc) return rc;
+    s->lcur = 0;
+    launch_scaled_identity_plus(c, s->ld, s->n, s->scal + 0, s->L[0], s->ld, s->stream);
+    rc = resid_into(s, s->Gam, s->L[0], false);
+    if (rc) return rc;
+    s->dns_started = true;
+  }
+  // L-loop: L_k = L_{k-1} P(Gamma_k) (lkk1), Gamma_k^n = I - A L_k (gamk21).
+  rc = poly_squaring(s, order, s->Gam, &c);
+  if (rc) return rc;
+  double* Lc = s->L[s->lcur];
+  double* Ln = s->L[s->lcur ^ 1];
+  rc = gemm(s, Ln, Lc, c, Lc, nullptr, 0.0, 1.0, false);
+  if (rc) return rc;
+  s->lcur ^= 1;
+  rc = resid_into(s, s->Gam, Ln, false);
+  if (rc) return rc;
+  // Ordinary loop: H = G_{k-1} P(F_{k-1}).
+  rc = poly_squaring(s, order, s->F, &c);
+  if (rc) return rc;
+  rc = apply_g(s, s->G[s->gcur], s->g_implicit, c, s->H);
+  if (rc) return rc;
+  // Merge: G_k = L_k + H Gamma_k^n (gkgen21); F_k = I - A G_k (fks1).
+  double* Gn = s->G[s->gcur ^ 1];
+  rc = gemm(s, Gn, s->H, s->Gam, Ln, nullptr, 0.0, 1.0, false);
+  if (rc) return rc;
+  s->gcur ^= 1;
+  s->g_implicit = false;
+  return resid_into(s, s->F, Gn, true);
+}
+
+int check_solver(ns_solver* s) {
+  if (!s) return fail(NS_EINVAL, "null solver");
+  return NS_OK;
+}
+
+int richardson_once(ns_solver* s, const double* b, double* theta) {
+  const int64_t np = launch_gemv_resid(s->A, s->lda, s->n, b, theta, s->r, s->partial, s->stream);
+  launch_reduce(s->partial, np, s->scal + 2, 2, 0.0, s->stream);
+  if (s->g_implicit) {
+    launch_vec_scale(s->r, s->scal + 0, theta, s->n, 1, s->stream);
+  } else {
+    launch_gemv_update(s->G[s->gcur], s->ld, s->n, s->r, theta, s->stream);
+  }
+  return NS_OK;
+}
+
+int validate_step_args(ns_solver* s, int order, int fact, int p, int w) {
+  if (order < 2) return fail(NS_EINVAL, "order must be >= 2 (got %d)", order);
+  switch (fact) {
+    case NS_FACT_HORNER:
+      return NS_OK;
+    case NS_FACT_SQUARING:
+      if (!is_pow2(order)) return fail(NS_EINVAL, "squaring form needs order = 2^s (got %d)", order);
+      return NS_OK;
+    case NS_FACT_UNIFIED:
+      if (p < 0 || w < 1 || w * (p + 1) != order)
+        return fail(NS_EINVAL, "unified form needs order = w (p + 1)");
+      return NS_OK;
+    case NS_FACT_UNIFIED_PLUS1:
+      if (p < 0 || w < 1 || w * (p + 1) + 1 != order)
+        return fail(NS_EINVAL, "unified+1 form needs order = w (p + 1) + 1");
+      return NS_OK;
+    case NS_FACT_COMPOSITE_DOUBLE:
+      if (!s->composite_capable)
+        return fail(NS_EINVAL, "workspace was sized without the composite buffers");
+      if (!is_pow2(order))
+        return fail(NS_EINVAL, "composite form uses the squaring inner sums: order = 2^s");
+      return NS_OK;
+    default:
+      return fail(NS_EINVAL, "unknown factorization %d", fact);
+  }
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* ns_version(void) { return "nsr 0.1 (gfx950)"; }
+
+const char* ns_last_error(void) { return g_err; }
+
+const char* ns_status_string(int st) {
+  switch (st) {
+    case NS_OK: return "ok";
+    case NS_EINVAL: return "invalid argument";
+    case NS_ENOTSPD: return "matrix is not SPD (alpha not positive/finite)";
+    case NS_EDIVERGED: return "iteration diverged";
+    case NS_ENOCONV: return "tolerance not reached";
+    case NS_ENOMEM: return "workspace too small";
+    case NS_EHIP: return "HIP runtime error";
+    case NS_EBUSY: return "not finished";
+    case NS_EPRECISION: return "precision insufficient";
+    case NS_ESTATE: return "call out of order";
+    default: return "unknown status";
+  }
+}
+
+size_t ns_workspace_bytes(int64_t n, int precision, int composite) {
+  if (n < 1) return 0;
+  if (precision != NS_PREC_FP64) return 0;
+  return layout_bytes(n, composite ? 1 : 0);
+}
+
+int ns_create(int device, void* hip_stream, int64_t n, int precision, void* workspace,
+              size_t bytes, ns_solver** out) {
+  if (!out) return fail(NS_EINVAL, "null out");
+  *out = nullptr;
+  if (n < 1) return fail(NS_EINVAL, "n must be >= 1");
+  if (precision != NS_PREC_FP64)
+    return fail(NS_EINVAL, "precision %d not available in this build", precision);
+  if (!workspace) return fail(NS_EINVAL, "null workspace");
+  if ((reinterpret_cast<uintptr_t>(workspace) % kAlign) != 0)
+    return fail(NS_EINVAL, "workspace must be 256-byte aligned");
+  const size_t need_plain = layout_bytes(n, 0);
+  const size_t need_comp = layout_bytes(n, 1);
+  if (bytes < need_plain)
+    return fail(NS_ENOMEM, "workspace too small: %zu < %zu bytes", bytes, need_plain);
+  HIP_TRY(hipSetDevice(device));
+  ns_solver* s = new (std::nothrow) ns_solver();
+  if (!s) return fail(NS_ENOMEM, "host allocation failed");
+  s->device = device;
+  s->stream = reinterpret_cast<hipStream_t>(hip_stream);
+  s->n = n;
+  s->ld = ld_for(n);
+  s->precision = precision;
+  s->composite_capable = bytes >= need_comp ? 1 : 0;
+  s->ws = reinterpret_cast<char*>(workspace);
+  s->ws_bytes = bytes;
+  const size_t mat = align_up((size_t)n * s->ld * sizeof(double), kAlign);
+  char* p = s->ws;
+  auto take = [&](size_t b) {
+    char* q = p;
+    p += b;
+    return reinterpret_cast<double*>(q);
+  };
+  s->G[0] = take(mat);
+  s->G[1] = take(mat);
+  s->F = take(mat);
+  s->P1 = take(mat);
+  s->P2 = take(mat);
+  s->C1 = take(mat);
+  s->C2 = take(mat);
+  if (s->composite_capable) {
+    s->L[0] = take(mat);
+    s->L[1] = take(mat);
+    s->Gam = take(mat);
+    s->H = take(mat);
+  }
+  s->r = take(align_up((size_t)n * sizeof(double), kAlign));
+  s->partial = take(align_up((size_t)partial_capacity(n) * sizeof(double), kAlign));
+  s->scal = take(align_up(16 * sizeof(double), kAlign));
+  *out = s;
+  return NS_OK;
+}
+
+int ns_destroy(ns_solver* s) {
+  if (!s) return NS_OK;
+  for (hipEvent_t e : s->pool) (void)hipEventDestroy(e);
+  delete s;
+  return NS_OK;
+}
+
+int ns_bind(ns_solver* s, const double* A, int64_t lda) {
+  if (int rc = check_solver(s)) return rc;
+  if (!A) return fail(NS_EINVAL, "null A");
+  if (lda < s->n) return fail(NS_EINVAL, "lda < n");
+  s->A = A;
+  s->lda = lda;
+  s->bound = true;
+  s->scaled = false;
+  s->g_implicit = true;
+  s->dns_started = false;
+  s->gcur = 0;
+  s->lcur = 0;
+  return NS_OK;
+}
+
+int ns_init_scale(ns_solver* s, int scale, double eps, double* alpha_out, double* fnorm0_out) {
+  if (int rc = check_solver(s)) return rc;
+  if (!s->bound) return fail(NS_ESTATE, "ns_bind first");
+  HIP_TRY(hipSetDevice(s->device));
+  if (scale == NS_SCALE_FROBENIUS) {
+    const int64_t np = launch_sumsq(s->A, s->lda, s->n, s->partial, s->stream);
+    launch_reduce(s->partial, np, s->scal + 0, 2, 0.0, s->stream);
+  } else if (scale == NS_SCALE_INF_HALF) {
+    launch_rowabs(s->A, s->lda, s->n, s->partial, s->stream);
+    launch_reduce(s->partial, s->n, s->scal + 0, 3, eps, s->stream);
+  } else {
+    return fail(NS_EINVAL, "unknown scale %d", scale);
+  }
+  double host[1];
+  if (int rc = read_scalars(s, host, 0, 1)) return rc;
+  s->alpha = host[0];
+  if (!(s->alpha > 0.0) || !isfinite(s->alpha))
+    return fail(NS_ENOTSPD, "alpha = %g is not a positive finite number", s->alpha);
+  const int64_t np =
+      launch_init_resid(s->A, s->lda, s->n, s->scal + 0, s->F, s->ld, s->partial, s->stream);
+  launch_reduce(s->partial, np, s->scal + 1, 2, 0.0, s->stream);
+  s->scaled = true;
+  s->g_implicit = true;
+  s->dns_started = false;
+  s->gcur = 0;
+  s->lcur = 0;
+  s->mmm = 0;
+  if (alpha_out) *alpha_out = s->alpha;
+  if (fnorm0_out) {
+    if (int rc = read_scalars(s, host, 1, 1)) return rc;
+    *fnorm0_out = host[0];
+  }
+  if (hipGetLastError() != hipSuccess) return fail(NS_EHIP, "kernel launch failed");
+  return NS_OK;
+}
+
+int ns_step(ns_solver* s, int order, int factorization, int p, int w, double* fnorm_out) {
+  if (int rc = check_solver(s)) return rc;
+  if (!s->scaled) return fail(NS_ESTATE, "ns_init_scale first");
+  if (int rc = validate_step_args(s, order, factorization, p, w)) return rc;
+  HIP_TRY(hipSetDevice(s->device));
+  int rc = (factorization == NS_FACT_COMPOSITE_DOUBLE) ? step_composite(s, order)
+                                                       : step_classic(s, order, factorization, p, w);
+  if (rc) return rc;
+  if (hipGetLastError() != hipSuccess) return fail(NS_EHIP, "kernel launch failed");
+  if (fnorm_out) {
+    double host[1];
+    if ((rc = read_scalars(s, host, 1, 1))) return rc;
+    *fnorm_out = host[0];
+  }
+  return NS_OK;
+}
+
+int ns_get_G(ns_solver* s, double* G_out, int64_t ldg) {
+  if (int rc = check_solver(s)) return rc;
+  if (!G_out || ldg < s->n) return fail(NS_EINVAL, "bad G_out / ldg");
+  if (!s->scaled) return fail(NS_ESTATE, "ns_init_scale first");
+  if (s->g_implicit) {
+    launch_scaled_identity_plus(nullptr, 0, s->n, s->scal + 0, G_out, ldg, s->stream);
+    return NS_OK;
+  }
+  HIP_TRY(hipMemcpy2DAsync(G_out, ldg * sizeof(double), s->G[s->gcur], s->ld * sizeof(double),
+                           s->n * sizeof(double), s->n, hipMemcpyDeviceToDevice, s->stream));
+  return NS_OK;
+}
+
+int ns_get_F(ns_solver* s, double* F_out, int64_t ldf) {
+  if (int rc = check_solver(s)) return rc;
+  if (!F_out || ldf < s->n) return fail(NS_EINVAL, "bad F_out / ldf");
+  if (!s->scaled) return fail(NS_ESTATE, "ns_init_scale first");
+  HIP_TRY(hipMemcpy2DAsync(F_out, ldf * sizeof(double), s->F, s->ld * sizeof(double),
+                           s->n * sizeof(double), s->n, hipMemcpyDeviceToDevice, s->stream));
+  return NS_OK;
+}
+
+int ns_richardson_step(ns_solver* s, const double* b, double* theta, double* rnorm_out) {
+  if (int rc = check_solver(s)) return rc;
+  if (!b || !theta) return fail(NS_EINVAL, "null b / theta");
+  if (!s->scaled) return fail(NS_ESTATE, "ns_init_scale first");
+  richardson_once(s, b, theta);
+  if (hipGetLastError() != hipSuccess) return fail(NS_EHIP, "kernel launch failed");
+  if (rnorm_out) {
+    double host[1];
+    if (int rc = read_scalars(s, host, 2, 1)) return rc;
+    *rnorm_out = host[0];
+  }
+  return NS_OK;
+}
+
+int richardson_ns_solve(ns_solver* s, const double* b, double* theta, const ns_solve_opts* o,
+                        ns_solve_report* rep) {
+  if (int rc = check_solver(s)) return rc;
+  if (!b || !theta || !o) return fail(NS_EINVAL, "null b / theta / opts");
+  if (o->k_max < 1 || o->k_max > NS_HIST_F - 1) return fail(NS_EINVAL, "k_max must be in 1..64");
+  if (o->refine_max < 0) return fail(NS_EINVAL, "refine_max < 0");
+  if (o->theta0_mode < 0 || o->theta0_mode > 2) return fail(NS_EINVAL, "bad theta0_mode");
+  if (int rc = validate_step_args(s, o->order, o->factorization, o->p, o->w)) return rc;
+  ns_solve_report local;
+  ns_solve_report* R = rep ? rep : &local;
+  memset(R, 0, sizeof(*R));
+  R->precision = s->precision;
+
+  double alpha = 0.0, f0 = 0.0;
+  if (int rc = ns_init_scale(s, o->scale, o->eps, &alpha, &f0)) return rc;
+  R->alpha = alpha;
+  R->fnorm_hist[R->n_fnorm++] = f0;
+
+  // ||b||
+  {
+    const int64_t np = launch_vec_sumsq(b, s->n, s->partial, s->stream);
+    launch_reduce(s->partial, np, s->scal + 3, 2, 0.0, s->stream);
+  }
+  if (o->theta0_mode == 0) launch_vec_scale(b, s->scal + 0, theta, s->n, 0, s->stream);
+  if (o->theta0_mode == 1) HIP_TRY(hipMemsetAsync(theta, 0, s->n * sizeof(double), s->stream));
+  double bn[1];
+  if (int rc = read_scalars(s, bn, 3, 1)) return rc;
+  double bnorm = bn[0] > 0.0 ? bn[0] : 1.0;
+
+  int ns_stop = NS_STOP_NONE;
+  if (!isfinite(f0)) ns_stop = NS_STOP_DIVERGED;
+  int k = 0;
+  double host[2];
+  while (ns_stop == NS_STOP_NONE) {
+    ++k;
+    int rc = (o->factorization == NS_FACT_COMPOSITE_DOUBLE)
+                 ? step_composite(s, o->order)
+                 : step_classic(s, o->order, o->factorization, o->p, o->w);
+    if (rc) return rc;
+    richardson_once(s, b, theta);
+    if ((rc = read_scalars(s, host, 1, 2))) return rc;
+    const double fk = host[0];
+    if (R->n_resid < NS_HIST_R) R->resid_hist[R->n_resid++] = host[1] / bnorm;
+    R->fnorm_hist[R->n_fnorm++] = fk;
+    // Stop rule (the paper gives none): divergence, tolerance, rounding
+    // floor (an earlier ratio below 1/2, the current one above), k_max.
+    const double* h = R->fnorm_hist;
+    if (!isfinite(fk) || fk > h[0]) {
+      ns_stop = NS_STOP_DIVERGED;
+    } else if (fk <= o->f_tol) {
+      ns_stop = NS_STOP_F_TOL;
+    } else {
+      bool entered = false;
+      for (int j = 1; j < k; ++j)
+        if (h[j] < 0.5 * h[j - 1]) entered = true;
+      if (o->floor_detect && k >= 2 && entered && fk > 0.5 * h[k - 1])
+        ns_stop = NS_STOP_FLOOR;
+      else if (k >= o->k_max)
+        ns_stop = NS_STOP_K_MAX;
+    }
+  }
+  R->ns_steps = k;
+  R->ns_stop = ns_stop;
+
+  int status = NS_OK;
+  int refine = 0;
+  double rel = NAN;
+  int refine_stop = NS_STOP_DIVERGED;
+  if (ns_stop != NS_STOP_DIVERGED) {
+    const int hist0 = R->n_resid;
+    double last[4] = {0, 0, 0, 0};
+    int nlast = 0;
+    while (true) {
+      // r = b - A theta, ||r||; the update is applied only if we continue.
+      const int64_t np =
+          launch_gemv_resid(s->A, s->lda, s->n, b, theta, s->r, s->partial, s->stream);
+      launch_reduce(s->partial, np, s->scal + 2, 2, 0.0, s->stream);
+      if (int rc = read_scalars(s, host, 2, 1)) return rc;
+      rel = host[0] / bnorm;
+      if (R->n_resid < NS_HIST_R) R->resid_hist[R->n_resid++] = rel;
+      for (int j = 3; j > 0; --j) last[j] = last[j - 1];
+      last[0] = rel;
+      ++nlast;
+      if (!isfinite(rel)) {
+        refine_stop = NS_STOP_DIVERGED;
+        break;
+      }
+      if (rel <= o->resid_tol) {
+        refine_stop = NS_STOP_RESID_TOL;
+        break;
+      }
+      if (refine >= o->refine_max) {
+        refine_stop = NS_STOP_REFINE_MAX;
+        break;
+      }
+      if (refine >= 3 && nlast >= 4 && rel > 0.5 * last[3]) {
+        refine_stop = NS_STOP_REFINE_STALL;
+        break;
+      }
+      launch_gemv_update(s->G[s->gcur], s->ld, s->n, s->r, theta, s->stream);
+      ++refine;
+    }
+    (void)hist0;
+  }
+  R->refine_steps = refine;
+  R->refine_stop = refine_stop;
+  R->rel_resid = rel;
+  R->mmm = s->mmm;
+  const double nn = (double)s->n;
+  R->gemm_flop = 2.0 * nn * nn * nn * (double)s->mmm;
+  if (ns_stop == NS_STOP_DIVERGED || refine_stop == NS_STOP_DIVERGED)
+    status = NS_EDIVERGED;
+  else if (refine_stop != NS_STOP_RESID_TOL)
+    status = NS_ENOCONV;
+  R->status = status;
+  if (hipGetLastError() != hipSuccess) return fail(NS_EHIP, "kernel launch failed");
+  if (status == NS_EDIVERGED) return fail(NS_EDIVERGED, "iteration diverged");
+  if (status == NS_ENOCONV) return fail(NS_ENOCONV, "resid_tol not reached (%g)", rel);
+  return NS_OK;
+}
+
+int ns_timing_enable(ns_solver* s, int enable) {
+  if (int rc = check_solver(s)) return rc;
+  s->timing = enable != 0;
+  return NS_OK;
+}
+
+int ns_timing_reset(ns_solver* s) {
+  if (int rc = check_solver(s)) return rc;
+  HIP_TRY(hipStreamSynchronize(s->stream));
+  s->timed.clear();
+  s->pool_used = 0;
+  return NS_OK;
+}
+
+int ns_timing_read(ns_solver* s, int kind, int64_t* launches, double* total_ms, double* flop) {
+  if (int rc = check_solver(s)) return rc;
+  HIP_TRY(hipStreamSynchronize(s->stream));
+  int64_t cnt = 0;
+  double ms = 0.0, fl = 0.0;
+  for (const TimedLaunch& t : s->timed) {
+    if (kind != 0 && t.kind != kind) continue;
+    float e = 0.0f;
+    HIP_TRY(hipEventElapsedTime(&e, t.beg, t.end));
+    ++cnt;
+    ms += e;
+    fl += t.flop;
+  }
+  if (launches) *launches = cnt;
+  if (total_ms) *total_ms = ms;
+  if (flop) *flop = fl;
+  return NS_OK;
+}
+
+int64_t ns_gemm_f64_partials(int64_t m, int64_t n) {
+  if (m <= 0 || n <= 0) return 0;
+  return gemm_f64_partials(m, n);
+}
+
+int ns_gemm_f64(void* hip_stream, int64_t m, int64_t n, int64_t k, const double* X, int64_t ldx,
+                const double* Y, int64_t ldy, double* D, int64_t ldd, const double* E1,
+                int64_t lde1, const double* E2, int64_t lde2, double diag, double scale,
+                double* sumsq_out) {
+  if (m < 0 || n < 0 || k < 0) return fail(NS_EINVAL, "negative size");
+  if (m == 0 || n == 0) return NS_OK;
+  if (!D || (k > 0 && (!X || !Y))) return fail(NS_EINVAL, "null operand");
+  if ((k > 0 && (ldx < k || ldy < n)) || ldd < n) return fail(NS_EINVAL, "leading dimension too small");
+  if ((E1 && lde1 < n) || (E2 && lde2 < n)) return fail(NS_EINVAL, "addend leading dimension too small");
+  if (D == X || D == Y) return fail(NS_EINVAL, "D must not alias X or Y");
+  hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
+  GemmF64Args a{};
+  a.X = X;
+  a.Y = Y;
+  a.D = D;
+  a.E1 = E1;
+  a.E2 = E2;
+  a.ldx = ldx;
+  a.ldy = ldy;
+  a.ldd = ldd;
+  a.lde1 = lde1;
+  a.lde2 = lde2;
+  a.M = m;
+  a.N = n;
+  a.K = k;
+  a.diag = diag;
+  a.scale = scale;
+  // Per-tile partials live after the first element of sumsq_out.
+  double* part = sumsq_out ? sumsq_out + 1 : nullptr;
+  a.partial = part;
+  const int64_t np = launch_gemm_f64(a, st);
+  if (np < 0) return fail(NS_EHIP, "GEMM launch failed: %s", hipGetErrorString(hipGetLastError()));
+  if (sumsq_out) launch_reduce(part, np, sumsq_out, 0, 0.0, st);
+  if (hipGetLastError() != hipSuccess) return fail(NS_EHIP, "kernel launch failed");
+  return NS_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,316 @@
+"""Thin Python binding of libnsr (include/nsr.h), argument marshalling only.
+
+Every step of the solve runs in the HIP library; this module converts torch
+tensors to device pointers and streams, and C structs to Python objects.
+Importing it does not load the library; the first call does, and raises if
+``libnsr.so`` has not been built (there is no fallback path).
+"""
+from __future__ import annotations
+
+import ctypes
+import dataclasses
+import os
+
+import numpy as np
+
+_LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libnsr.so")
+_lib = None
+
+# ns_status
+NS_OK, NS_EINVAL, NS_ENOTSPD, NS_EDIVERGED, NS_ENOCONV = 0, -1, -2, -3, -4
+NS_ENOMEM, NS_EHIP, NS_EBUSY, NS_EPRECISION, NS_ESTATE = -5, -6, -7, -8, -9
+# ns_precision
+PREC_FP64, PREC_FP32, PREC_MIXED_BF16 = 0, 1, 2
+# ns_scale
+SCALE_FROBENIUS, SCALE_INF_HALF = 0, 1
+# ns_factorization
+FACT = {"horner": 0, "squaring": 1, "unified": 3, "unified_plus1": 4, "composite_double": 5}
+# ns_stop_reason
+STOP_NAMES = {0: "none", 1: "f_tol", 2: "floor", 3: "k_max", 4: "diverged", 5: "resid_tol",
+              6: "refine_max", 7: "refine_stall"}
+
+HIST_F = 65
+HIST_R = 200
+
+# Every exported symbol of include/nsr.h, for the load check.
+EXPORTS = (
+    "ns_workspace_bytes", "ns_create", "ns_destroy", "ns_bind", "ns_init_scale", "ns_step",
+    "ns_get_G", "ns_get_F", "ns_richardson_step", "richardson_ns_solve", "ns_timing_enable",
+    "ns_timing_read", "ns_timing_reset", "ns_gemm_f64", "ns_gemm_f64_partials",
+    "ns_status_string", "ns_last_error", "ns_version",
+)
+
+
+class NSError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"nsr error {status}: {msg}")
+        self.status = status
+
+
+class SolveOpts(ctypes.Structure):
+    _fields_ = [
+        ("order", ctypes.c_int), ("factorization", ctypes.c_int), ("p", ctypes.c_int),
+        ("w", ctypes.c_int), ("k_max", ctypes.c_int), ("refine_max", ctypes.c_int),
+        ("floor_detect", ctypes.c_int), ("scale", ctypes.c_int), ("eps", ctypes.c_double),
+        ("f_tol", ctypes.c_double), ("resid_tol", ctypes.c_double), ("theta0_mode", ctypes.c_int),
+    ]
+
+
+class SolveReportC(ctypes.Structure):
+    _fields_ = [
+        ("status", ctypes.c_int), ("ns_stop", ctypes.c_int), ("refine_stop", ctypes.c_int),
+        ("ns_steps", ctypes.c_int), ("refine_steps", ctypes.c_int), ("precision", ctypes.c_int),
+        ("alpha", ctypes.c_double), ("rel_resid", ctypes.c_double), ("mmm", ctypes.c_int64),
+        ("gemm_flop", ctypes.c_double), ("n_fnorm", ctypes.c_int),
+        ("fnorm_hist", ctypes.c_double * HIST_F), ("n_resid", ctypes.c_int),
+        ("resid_hist", ctypes.c_double * HIST_R),
+    ]
+
+
+@dataclasses.dataclass
+class SolveReport:
+    status: int
+    ns_stop: str
+    refine_stop: str
+    ns_steps: int
+    refine_steps: int
+    precision: int
+    alpha: float
+    rel_resid: float
+    mmm: int
+    gemm_flop: float
+    fnorm_hist: list
+    resid_hist: list
+
+
+def lib() -> ctypes.CDLL:
+    """Load libnsr.so (once).  Raises if it is missing: there is no fallback."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB_PATH):
+        raise ImportError(f"{_LIB_PATH} is not built; run paper_2008_11480_amd.build.build()")
+    L = ctypes.CDLL(_LIB_PATH)
+    vp, i64, dbl, ci = ctypes.c_void_p, ctypes.c_int64, ctypes.c_double, ctypes.c_int
+    pd = ctypes.POINTER(ctypes.c_double)
+    sig = {
+        "ns_workspace_bytes": (ctypes.c_size_t, [i64, ci, ci]),
+        "ns_create": (ci, [ci, vp, i64, ci, vp, ctypes.c_size_t, ctypes.POINTER(vp)]),
+        "ns_destroy": (ci, [vp]),
+        "ns_bind": (ci, [vp, vp, i64]),
+        "ns_init_scale": (ci, [vp, ci, dbl, pd, pd]),
+        "ns_step": (ci, [vp, ci, ci, ci, ci, pd]),
+        "ns_get_G": (ci, [vp, vp, i64]),
+        "ns_get_F": (ci, [vp, vp, i64]),
+        "ns_richardson_step": (ci, [vp, vp, vp, pd]),
+        "richardson_ns_solve": (ci, [vp, vp, vp, ctypes.POINTER(SolveOpts),
+                                     ctypes.POINTER(SolveReportC)]),
+        "ns_timing_enable": (ci, [vp, ci]),
+        "ns_timing_read": (ci, [vp, ci, ctypes.POINTER(i64), pd, pd]),
+        "ns_timing_reset": (ci, [vp]),
+        "ns_gemm_f64": (ci, [vp, i64, i64, i64, vp, i64, vp, i64, vp, i64, vp, i64, vp, i64,
+                             dbl, dbl, vp]),
+        "ns_gemm_f64_partials": (i64, [i64, i64]),
+        "ns_status_string": (ctypes.c_char_p, [ci]),
+        "ns_last_error": (ctypes.c_char_p, []),
+        "ns_version": (ctypes.c_char_p, []),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(L, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = L
+    return L
+
+
+def check(status: int) -> int:
+    if status != NS_OK:
+        msg = lib().ns_last_error().decode(errors="replace")
+        raise NSError(status, msg)
+    return status
+
+
+def _ptr(t) -> int | None:
+    if t is None:
+        return None
+    return int(t.data_ptr())
+
+
+def _stream_handle(stream) -> int | None:
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return int(stream.cuda_stream) or None
+
+
+def _require_cuda_f64(t, name):
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != torch.float64:
+        raise TypeError(f"{name} must be a float64 CUDA tensor")
+
+
+def workspace_bytes(n: int, precision: int = PREC_FP64, composite: bool = False) -> int:
+    return int(lib().ns_workspace_bytes(int(n), int(precision), 1 if composite else 0))
+
+
+class Solver:
+    """One ``ns_solver`` handle with its workspace (allocated by torch)."""
+
+    def __init__(self, n: int, precision: int = PREC_FP64, composite: bool = True,
+                 device: int | None = None, stream=None):
+        import torch
+        L = lib()
+        self.n = int(n)
+        self.device = torch.cuda.current_device() if device is None else int(device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        nbytes = workspace_bytes(n, precision, composite)
+        if nbytes == 0:
+            raise NSError(NS_EINVAL, "unsupported size/precision")
+        self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8,
+                                     device=f"cuda:{self.device}")
+        base = self.workspace.data_ptr()
+        aligned = (base + 255) // 256 * 256
+        h = ctypes.c_void_p()
+        check(L.ns_create(self.device, _stream_handle(self.stream), self.n, int(precision),
+                          aligned, nbytes, ctypes.byref(h)))
+        self._h = h
+        self._A = None
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().ns_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def bind(self, A):
+        _require_cuda_f64(A, "A")
+        if A.dim() != 2 or A.shape[0] != self.n or A.shape[1] != self.n or A.stride(1) != 1:
+            raise ValueError("A must be n x n with unit column stride")
+        self._A = A
+        check(lib().ns_bind(self._h, _ptr(A), A.stride(0)))
+
+    def init_scale(self, scale: int = SCALE_FROBENIUS, eps: float = 0.0):
+        a, f = ctypes.c_double(), ctypes.c_double()
+        check(lib().ns_init_scale(self._h, int(scale), float(eps), ctypes.byref(a),
+                                  ctypes.byref(f)))
+        return a.value, f.value
+
+    def step(self, order: int, form: str = "squaring", p: int = 0, w: int = 0) -> float:
+        f = ctypes.c_double()
+        check(lib().ns_step(self._h, int(order), FACT[form], int(p), int(w), ctypes.byref(f)))
+        return f.value
+
+    def get_G(self, out=None):
+        import torch
+        if out is None:
+            out = torch.empty(self.n, self.n, dtype=torch.float64, device=f"cuda:{self.device}")
+        check(lib().ns_get_G(self._h, _ptr(out), out.stride(0)))
+        return out
+
+    def get_F(self, out=None):
+        import torch
+        if out is None:
+            out = torch.empty(self.n, self.n, dtype=torch.float64, device=f"cuda:{self.device}")
+        check(lib().ns_get_F(self._h, _ptr(out), out.stride(0)))
+        return out
+
+    def richardson_step(self, b, theta) -> float:
+        _require_cuda_f64(b, "b")
+        _require_cuda_f64(theta, "theta")
+        r = ctypes.c_double()
+        check(lib().ns_richardson_step(self._h, _ptr(b), _ptr(theta), ctypes.byref(r)))
+        return r.value
+
+    def solve(self, b, theta, order: int = 8, form: str = "squaring", p: int = 0, w: int = 0,
+              k_max: int = 64, refine_max: int = 64, floor_detect: bool = True,
+              scale: int = SCALE_FROBENIUS, eps: float = 0.0, f_tol: float = 0.0,
+              resid_tol: float = 1e-12, theta0_mode: int = 0, raise_on_error: bool = True):
+        _require_cuda_f64(b, "b")
+        _require_cuda_f64(theta, "theta")
+        o = SolveOpts(order=order, factorization=FACT[form], p=p, w=w, k_max=k_max,
+                      refine_max=refine_max, floor_detect=1 if floor_detect else 0, scale=scale,
+                      eps=eps, f_tol=f_tol, resid_tol=resid_tol, theta0_mode=theta0_mode)
+        rep = SolveReportC()
+        st = lib().richardson_ns_solve(self._h, _ptr(b), _ptr(theta), ctypes.byref(o),
+                                       ctypes.byref(rep))
+        if st not in (NS_OK, NS_ENOCONV, NS_EDIVERGED):
+            check(st)                       # argument / state / HIP errors always raise
+        if st == NS_EDIVERGED and raise_on_error:
+            check(st)
+        return SolveReport(
+            status=rep.status, ns_stop=STOP_NAMES.get(rep.ns_stop, "?"),
+            refine_stop=STOP_NAMES.get(rep.refine_stop, "?"), ns_steps=rep.ns_steps,
+            refine_steps=rep.refine_steps, precision=rep.precision, alpha=rep.alpha,
+            rel_resid=rep.rel_resid, mmm=rep.mmm, gemm_flop=rep.gemm_flop,
+            fnorm_hist=list(rep.fnorm_hist[:rep.n_fnorm]),
+            resid_hist=list(rep.resid_hist[:rep.n_resid]))
+
+    # timing -------------------------------------------------------------
+    def timing(self, enable: bool):
+        check(lib().ns_timing_enable(self._h, 1 if enable else 0))
+
+    def timing_reset(self):
+        check(lib().ns_timing_reset(self._h))
+
+    def timing_read(self, kind: int = 0):
+        n = ctypes.c_int64()
+        ms, fl = ctypes.c_double(), ctypes.c_double()
+        check(lib().ns_timing_read(self._h, int(kind), ctypes.byref(n), ctypes.byref(ms),
+                                   ctypes.byref(fl)))
+        return n.value, ms.value, fl.value
+
+
+def gemm_f64(X, Y, D=None, E1=None, E2=None, diag: float = 0.0, scale: float = 1.0,
+             want_sumsq: bool = False, stream=None):
+    """``D = diag I + scale X Y + E1 + E2`` through the library's MFMA GEMM."""
+    import torch
+    for t, nm in ((X, "X"), (Y, "Y")):
+        _require_cuda_f64(t, nm)
+    m, k = X.shape
+    k2, n = Y.shape
+    if k2 != k:
+        raise ValueError("inner dimensions differ")
+    if D is None:
+        D = torch.empty(m, n, dtype=torch.float64, device=X.device)
+    ss = None
+    if want_sumsq:
+        ss = torch.zeros(1 + int(lib().ns_gemm_f64_partials(m, n)), dtype=torch.float64,
+                         device=X.device)
+    check(lib().ns_gemm_f64(_stream_handle(stream), m, n, k, _ptr(X), X.stride(0), _ptr(Y),
+                            Y.stride(0), _ptr(D), D.stride(0), _ptr(E1),
+                            E1.stride(0) if E1 is not None else 0, _ptr(E2),
+                            E2.stride(0) if E2 is not None else 0, float(diag), float(scale),
+                            _ptr(ss)))
+    return (D, ss[0]) if want_sumsq else D
+
+
+def exported_symbols() -> list[str]:
+    """Names of EXPORTS that the loaded library actually exports."""
+    L = lib()
+    out = []
+    for name in EXPORTS:
+        try:
+            getattr(L, name)
+            out.append(name)
+        except AttributeError:
+            pass
+    return out
+
+
+def solve_np(A: np.ndarray, b: np.ndarray, **kw):
+    """Convenience: copy host arrays to the GPU, solve, copy theta back."""
+    import torch
+    dev = torch.device("cuda")
+    At = torch.from_numpy(np.ascontiguousarray(A)).to(dev)
+    bt = torch.from_numpy(np.ascontiguousarray(b)).to(dev)
+    th = torch.zeros_like(bt)
+    s = Solver(A.shape[0], composite=kw.get("form") == "composite_double")
+    s.bind(At)
+    rep = s.solve(bt, th, **kw)
+    torch.cuda.synchronize()
+    return th.cpu().numpy(), rep

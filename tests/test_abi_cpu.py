@@ -1,0 +1,82 @@
+"""The C-ABI library loads and exports every symbol include/nsr.h declares;
+host-side argument checks work without a GPU (no compute calls here)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2008_11480_amd import nsr
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "nsr.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"\b([A-Za-z_]\w*)\s*\([^;{]*\)\s*;", text)
+    return sorted(set(n for n in names if n not in ("sizeof",)))
+
+
+def test_header_declares_the_binding_exports():
+    decl = declared_functions()
+    assert decl, "no declarations parsed"
+    assert sorted(decl) == sorted(nsr.EXPORTS)
+
+
+def test_library_exports_every_declared_symbol():
+    L = nsr.lib()
+    for name in declared_functions():
+        assert hasattr(L, name), name
+    assert L.ns_version().startswith(b"nsr")
+
+
+def test_workspace_bytes():
+    plain = nsr.workspace_bytes(4096)
+    comp = nsr.workspace_bytes(4096, composite=True)
+    assert plain >= 7 * 4096 * 4096 * 8
+    assert comp >= 11 * 4096 * 4096 * 8
+    assert nsr.workspace_bytes(0) == 0
+    assert nsr.workspace_bytes(64, precision=99) == 0
+    # ragged sizes are padded to a 32-element leading dimension
+    assert nsr.workspace_bytes(33) >= 7 * 33 * 64 * 8
+
+
+def test_status_strings():
+    L = nsr.lib()
+    for st in range(0, -10, -1):
+        assert L.ns_status_string(st)
+    assert L.ns_status_string(-3) == b"iteration diverged"
+
+
+def test_host_argument_checks_without_gpu():
+    L = nsr.lib()
+    h = ctypes.c_void_p()
+    assert L.ns_create(0, None, 0, 0, 256, 1 << 20, ctypes.byref(h)) == nsr.NS_EINVAL
+    assert L.ns_create(0, None, 64, 0, None, 1 << 20, ctypes.byref(h)) == nsr.NS_EINVAL
+    assert L.ns_create(0, None, 64, 0, 257, 1 << 20, ctypes.byref(h)) == nsr.NS_EINVAL
+    assert L.ns_create(0, None, 64, 0, 256, 16, ctypes.byref(h)) == nsr.NS_ENOMEM
+    assert L.ns_create(0, None, 64, 7, 256, 1 << 20, ctypes.byref(h)) == nsr.NS_EINVAL
+    assert b"precision" in L.ns_last_error()
+    # GEMM argument checks
+    assert L.ns_gemm_f64(None, -1, 1, 1, None, 1, None, 1, None, 1, None, 0, None, 0, 0.0, 1.0,
+                         None) == nsr.NS_EINVAL
+    assert L.ns_gemm_f64(None, 4, 4, 4, 256, 2, 512, 4, 768, 4, None, 0, None, 0, 0.0, 1.0,
+                         None) == nsr.NS_EINVAL          # ldx < k
+    assert L.ns_gemm_f64(None, 4, 4, 4, 256, 4, 512, 4, 256, 4, None, 0, None, 0, 0.0, 1.0,
+                         None) == nsr.NS_EINVAL          # D aliases X
+    assert L.ns_gemm_f64(None, 0, 4, 4, None, 4, None, 4, None, 4, None, 0, None, 0, 0.0, 1.0,
+                         None) == nsr.NS_OK              # empty output: nothing to do
+    # null handles
+    assert L.ns_bind(None, 256, 64) == nsr.NS_EINVAL
+    assert L.ns_step(None, 8, 1, 0, 0, None) == nsr.NS_EINVAL
+    assert L.ns_destroy(None) == nsr.NS_OK
+
+
+def test_gemm_partials_count():
+    L = nsr.lib()
+    assert L.ns_gemm_f64_partials(64, 64) == 1
+    assert L.ns_gemm_f64_partials(65, 64) == 2
+    assert L.ns_gemm_f64_partials(4096, 4096) == 32 * 32
+    assert L.ns_gemm_f64_partials(0, 5) == 0

@@ -1,0 +1,293 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle.
+
+Tolerances (derived in DESIGN.md, "Parity tolerances"):
+* GEMM: |D - D_ref|_ij <= gamma_{k+4} (|s| |X||Y| + |diag| I + |E1| + |E2|)_ij,
+  gamma_m = m u / (1 - m u), for both the kernel and the reference dot product.
+* ||F_k||_F traces: |d| <= 1e-10 ||F_k|| + 10 * floor, floor = the smallest
+  ||F|| either run reached (rounding differences are amplified at most ~n^k
+  before the iteration contracts, and sit at the floor afterwards).
+* theta: ||theta - theta_oracle|| / ||theta_oracle|| <= 10 kappa u.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2008_11480_amd import inputs, nsr
+
+pytestmark = pytest.mark.gpu
+
+U = np.finfo(np.float64).eps / 2
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as _torch
+    if not _torch.cuda.is_available():
+        pytest.skip("no GPU")
+    nsr.lib()
+    return _torch
+
+
+def gamma(m):
+    return m * U / (1 - m * U)
+
+
+def to_dev(torch, a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
+
+
+# --------------------------------------------------------------------------
+# GEMM kernel
+# --------------------------------------------------------------------------
+
+GEMM_SHAPES = [(1, 1, 1), (5, 3, 7), (64, 64, 64), (100, 37, 250), (129, 130, 131),
+               (257, 300, 129), (512, 512, 512), (1000, 999, 1001), (2900, 2950, 300)]
+
+
+@pytest.mark.parametrize("m,n,k", GEMM_SHAPES)
+@pytest.mark.parametrize("odd_ld", [False, True])
+def test_gemm_f64_elementwise(torch, m, n, k, odd_ld):
+    rng = np.random.default_rng(m * 7 + n * 13 + k)
+    pad = 1 if odd_ld else 0
+    Xb = rng.standard_normal((m, k + pad))
+    Yb = rng.standard_normal((k, n + pad))
+    E1 = rng.standard_normal((m, n))
+    E2 = rng.standard_normal((m, n))
+    X, Y = Xb[:, :k], Yb[:, :n]
+    diag, scale = 0.7, -1.3
+    Xd = to_dev(torch, Xb)[:, :k]
+    Yd = to_dev(torch, Yb)[:, :n]
+    D, ss = nsr.gemm_f64(Xd, Yd, E1=to_dev(torch, E1), E2=to_dev(torch, E2), diag=diag,
+                         scale=scale, want_sumsq=True)
+    torch.cuda.synchronize()
+    got = D.cpu().numpy()
+    ref = scale * (X @ Y) + diag * np.eye(m, n) + E1 + E2
+    bound = gamma(k + 4) * (abs(scale) * (np.abs(X) @ np.abs(Y)) + abs(diag) * np.eye(m, n)
+                            + np.abs(E1) + np.abs(E2))
+    err = np.abs(got - ref)
+    assert np.all(err <= 2 * bound + 1e-300), float(np.max(err / (bound + 1e-300)))
+    ss_ref = float(np.sum(got * got))
+    assert abs(float(ss.cpu()) - ss_ref) <= 1e-13 * ss_ref
+
+
+def test_gemm_f64_no_addends(torch):
+    rng = np.random.default_rng(5)
+    X = rng.standard_normal((200, 300))
+    Y = rng.standard_normal((300, 150))
+    D = nsr.gemm_f64(to_dev(torch, X), to_dev(torch, Y)).cpu().numpy()
+    bound = gamma(304) * (np.abs(X) @ np.abs(Y))
+    assert np.all(np.abs(D - X @ Y) <= 2 * bound)
+
+
+def test_gemm_f64_full_size_sampled(torch):
+    """n = 4096 (the single-solve workload's GEMM shape, same launch
+    configuration): 3000 sampled entries against CPU dot products."""
+    n = 4096
+    g = torch.Generator(device="cuda").manual_seed(1234)
+    X = torch.randn(n, n, dtype=torch.float64, device="cuda", generator=g)
+    Y = torch.randn(n, n, dtype=torch.float64, device="cuda", generator=g)
+    D = nsr.gemm_f64(X, Y, diag=1.0, scale=-1.0)
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(0)
+    ii = rng.integers(0, n, 3000)
+    jj = rng.integers(0, n, 3000)
+    ii[:64] = np.arange(64)       # include diagonal entries
+    jj[:64] = np.arange(64)
+    Xc, Yc, Dc = X.cpu().numpy(), Y.cpu().numpy(), D.cpu().numpy()
+    for i, j in zip(ii, jj):
+        ref = -math.fsum(Xc[i, :] * Yc[:, j]) + (1.0 if i == j else 0.0)
+        bound = gamma(n + 4) * (float(np.abs(Xc[i, :]) @ np.abs(Yc[:, j])) + (i == j))
+        assert abs(Dc[i, j] - ref) <= bound, (i, j)
+
+
+# --------------------------------------------------------------------------
+# Solver against the oracle
+# --------------------------------------------------------------------------
+
+def compare_traces(h_gpu, h_orc, rel=1e-10, floor_mult=10.0, n_cmp=None):
+    n_cmp = n_cmp if n_cmp is not None else min(len(h_gpu), len(h_orc))
+    floor = max(min(h_gpu), min(h_orc))
+    for k in range(n_cmp):
+        d = abs(h_gpu[k] - h_orc[k])
+        assert d <= rel * abs(h_orc[k]) + floor_mult * floor, (k, h_gpu[k], h_orc[k], floor)
+
+
+def gpu_solve(torch, sysm, **kw):
+    A = to_dev(torch, sysm.A)
+    b = to_dev(torch, sysm.b)
+    th = torch.zeros_like(b)
+    s = nsr.Solver(sysm.n, composite=kw.get("form") == "composite_double")
+    s.bind(A)
+    rep = s.solve(b, th, **kw)
+    torch.cuda.synchronize()
+    return th.cpu().numpy(), rep
+
+
+def test_spd64_twelve_steps_matches_oracle(torch):
+    """N=64, kappa=100, order 4 (I+F)(I+F^2), 12 steps, coupled Richardson,
+    target relative residual 1e-13."""
+    w = inputs.WORKLOADS["spd64_k1e2_o4"]
+    sysm = inputs.spd_qlq(w["n"], w["kappa"], w["seed"])
+    th, rep = gpu_solve(torch, sysm, order=4, form="squaring", k_max=12, floor_detect=False,
+                        resid_tol=1e-13)
+    orc = oracle.solve(sysm.A, sysm.b, oracle.SolveOptions(order=4, k_max=12,
+                                                           floor_detect=False,
+                                                           resid_tol=1e-13))
+    assert rep.ns_steps == 12 and orc.ns_steps == 12
+    assert rep.alpha == pytest.approx(orc.alpha, rel=1e-14)
+    compare_traces(rep.fnorm_hist, orc.fnorm_hist)
+    compare_traces(rep.resid_hist, orc.resid_hist, rel=1e-8)
+    assert rep.rel_resid <= 1e-13
+    kappa = w["kappa"]
+    assert np.linalg.norm(th - orc.theta) <= 10 * kappa * U * np.linalg.norm(orc.theta)
+    # eigen closed form of ||F_k|| (eq. fk1) before the floor
+    mu = 1.0 - sysm.lam / rep.alpha
+    for k, fk in enumerate(rep.fnorm_hist):
+        ref = math.sqrt(float(np.sum(mu ** (2 * 4 ** k))))
+        if ref > 1e-8:
+            assert fk == pytest.approx(ref, rel=1e-9)
+
+
+SOLVE_CASES = [
+    # n, kappa, order, form, p, w
+    (1, 1.0, 4, "squaring", 0, 0),
+    (2, 10.0, 4, "squaring", 0, 0),
+    (3, 10.0, 8, "squaring", 0, 0),
+    (257, 1e2, 2, "squaring", 0, 0),
+    (300, 1e3, 4, "squaring", 0, 0),
+    (300, 1e3, 8, "squaring", 0, 0),
+    (200, 1e2, 3, "horner", 0, 0),
+    (200, 1e2, 6, "unified", 2, 2),
+    (200, 1e2, 4, "unified", 1, 2),
+    (200, 1e2, 4, "unified", 0, 4),
+    (200, 1e2, 3, "unified", 2, 1),
+    (200, 1e2, 5, "unified_plus1", 1, 2),
+    (200, 1e2, 3, "unified_plus1", 0, 2),
+    (200, 1e2, 4, "unified_plus1", 2, 1),
+    (130, 1e2, 4, "composite_double", 0, 0),
+    (300, 1e3, 8, "composite_double", 0, 0),
+    (97, 1e2, 2, "composite_double", 0, 0),
+]
+
+
+@pytest.mark.parametrize("n,kappa,order,form,p,w", SOLVE_CASES)
+def test_solve_matches_oracle(torch, n, kappa, order, form, p, w):
+    sysm = inputs.spd_qlq(n, kappa, seed=100 + n)
+    th, rep = gpu_solve(torch, sysm, order=order, form=form, p=p, w=w, resid_tol=1e-13)
+    oform = "squaring" if form == "composite_double" else form
+    orc = oracle.solve(sysm.A, sysm.b, oracle.SolveOptions(
+        order=order, form=oform, p=p if form.startswith("unified") else None,
+        w=w if form.startswith("unified") else None, composite=form == "composite_double",
+        resid_tol=1e-13))
+    assert abs(rep.ns_steps - orc.ns_steps) <= 1, (rep.ns_steps, orc.ns_steps)
+    compare_traces(rep.fnorm_hist, orc.fnorm_hist)
+    assert rep.rel_resid <= max(1e-13, 2 * orc.rel_resid)
+    assert np.linalg.norm(th - orc.theta) <= 10 * kappa * U * np.linalg.norm(orc.theta) + 1e-300
+
+
+def test_step_level_G_matches_oracle(torch):
+    """ns_step / ns_get_G / ns_get_F element-wise against the oracle's G_k, F_k."""
+    n = 257
+    sysm = inputs.spd_qlq(n, 1e2, seed=21)
+    s = nsr.Solver(n)
+    s.bind(to_dev(torch, sysm.A))
+    alpha, f0 = s.init_scale()
+    a_orc = oracle.alpha_frobenius(sysm.A)
+    assert alpha == pytest.approx(a_orc, rel=1e-14)
+    g = np.eye(n) / a_orc
+    for k in range(1, 3):
+        fk = s.step(8, "squaring")
+        g = oracle.ns_step(sysm.A, g, 8, "squaring")
+        f = oracle.residual(sysm.A, g)
+        G = s.get_G().cpu().numpy()
+        F = s.get_F().cpu().numpy()
+        assert np.linalg.norm(G - g) <= 1e-12 * np.linalg.norm(g), k
+        assert np.linalg.norm(F - f) <= 1e-12 * max(1.0, np.linalg.norm(f)) * n, k
+        assert fk == pytest.approx(np.linalg.norm(f), rel=1e-10, abs=1e-12)
+
+
+def test_solve_is_deterministic(torch):
+    sysm = inputs.spd_qlq(300, 1e3, seed=3)
+    th1, r1 = gpu_solve(torch, sysm, order=8)
+    th2, r2 = gpu_solve(torch, sysm, order=8)
+    assert np.array_equal(th1, th2)
+    assert r1.fnorm_hist == r2.fnorm_hist
+
+
+def test_full_size_spd4096(torch):
+    """N=4096, kappa=1e4, order 8 squaring to the ||F|| floor with Richardson
+    refinement: the launch configuration the benchmark times.  Checked against
+    properties that hold at any size: the eigen closed form of ||F_k||
+    (eq. fk1), theta* = Q diag(1/lam) Q^T b, and a LAPACK Cholesky residual."""
+    import scipy.linalg
+    w = inputs.WORKLOADS["spd4096_k1e4_o8"]
+    sysm = inputs.spd_qlq(w["n"], w["kappa"], w["seed"])
+    th, rep = gpu_solve(torch, sysm, order=8, form="squaring", k_max=64,
+                        resid_tol=w["resid_tol"])
+    assert rep.ns_stop in ("floor", "f_tol")
+    mu = 1.0 - sysm.lam / rep.alpha
+    for k, fk in enumerate(rep.fnorm_hist):
+        ref = math.sqrt(float(np.sum(mu ** (2 * 8 ** k))))
+        if ref > 1e-6:
+            assert fk == pytest.approx(ref, rel=1e-8), k
+    theta_star = sysm.Q @ ((sysm.Q.T @ sysm.b) / sysm.lam)
+    fwd = np.linalg.norm(th - theta_star) / np.linalg.norm(theta_star)
+    assert fwd <= 10 * w["kappa"] * U * 4, fwd
+    chol = scipy.linalg.cho_solve(scipy.linalg.cho_factor(sysm.A), sysm.b)
+    rc = np.linalg.norm(sysm.b - sysm.A @ chol) / np.linalg.norm(sysm.b)
+    rr = np.linalg.norm(sysm.b - sysm.A @ th) / np.linalg.norm(sysm.b)
+    assert rr <= max(1e-12, 2 * rc), (rr, rc)
+    assert rep.rel_resid <= max(1e-12, 2 * rc)
+
+
+def test_error_paths(torch):
+    n = 64
+    sysm = inputs.spd_qlq(n, 10.0, seed=2)
+    s = nsr.Solver(n)
+    with pytest.raises(nsr.NSError) as e:
+        s.step(4)
+    assert e.value.status == nsr.NS_ESTATE
+    s.bind(to_dev(torch, sysm.A))
+    s.init_scale()
+    with pytest.raises(nsr.NSError) as e:
+        s.step(6, "squaring")
+    assert e.value.status == nsr.NS_EINVAL
+    with pytest.raises(nsr.NSError) as e:
+        s.step(5, "unified", p=1, w=2)
+    assert e.value.status == nsr.NS_EINVAL
+    # alpha below lambda_max / 2: the splitting condition fails, diverges
+    lmax = float(sysm.lam.max())
+    eps = 0.4 * lmax - float(np.max(np.sum(np.abs(sysm.A), axis=1))) / 2.0
+    b = to_dev(torch, sysm.b)
+    th = torch.zeros_like(b)
+    rep = s.solve(b, th, order=4, scale=nsr.SCALE_INF_HALF, eps=eps, raise_on_error=False)
+    assert rep.ns_stop == "diverged" and rep.status == nsr.NS_EDIVERGED
+    # non-finite A: alpha is not finite
+    bad = sysm.A.copy()
+    bad[3, 5] = np.nan
+    s.bind(to_dev(torch, bad))
+    with pytest.raises(nsr.NSError) as e:
+        s.init_scale()
+    assert e.value.status == nsr.NS_ENOTSPD
+    # composite needs the composite workspace
+    s2 = nsr.Solver(n, composite=False)
+    s2.bind(to_dev(torch, sysm.A))
+    s2.init_scale()
+    with pytest.raises(nsr.NSError) as e:
+        s2.step(8, "composite_double")
+    assert e.value.status == nsr.NS_EINVAL
+
+
+def test_timing_counts_every_gemm(torch):
+    sysm = inputs.spd_qlq(256, 1e2, seed=8)
+    A, b = to_dev(torch, sysm.A), to_dev(torch, sysm.b)
+    th = torch.zeros_like(b)
+    s = nsr.Solver(256)
+    s.bind(A)
+    s.timing(True)
+    rep = s.solve(b, th, order=8)
+    cnt, ms, fl = s.timing_read(0)
+    assert cnt == rep.mmm and ms > 0.0
+    assert fl == pytest.approx(2.0 * 256 ** 3 * rep.mmm)
