@@ -12,7 +12,8 @@
 // Design (CDNA4):
 //  * v_mfma_f64_16x16x4_f64: a wave multiplies 16x4 by 4x16 and accumulates a
 //    16x16 float64 block; lane l supplies X[i = l%16][k = l/16] and
-//    Y[k = l/16][j = l%16] and holds D[4*(l/16) + r][l%16], r = 0..3.
+//    Y[k = l/16][j = l%16] and holds D[l/16 + 4 r][l%16], r = 0..3
+//    (accumulator element r strides the rows by 4).
 //  * A workgroup of 4 waves owns a BM x BN output tile; each wave owns a
 //    (BM/2) x (BN/2) quadrant = (BM/32) x (BN/32) MFMA blocks kept in
 //    registers for the whole K loop.
@@ -182,7 +183,7 @@ gemm_f64_kernel(GemmF64Args p, int tiles_m, int tiles_n) {
       const int64_t col = n0 + wn * WTN + j * 16 + lr;
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int64_t row = m0 + wm * WTM + i * 16 + 4 * lk + r;
+        const int64_t row = m0 + wm * WTM + i * 16 + lk + 4 * r;
         if (row < M && col < N) {
           double v = scale * acc[i][j][r];
           if (row == col) v += diag;
