@@ -27,6 +27,19 @@
 //    L2.
 #include "nsr_internal.h"
 
+// Tuning knobs of the large-tile configuration (chosen by measurement):
+// K-slab depth, number of LDS slab buffers (2: one barrier per slab; 1: two
+// barriers per slab, half the LDS) and the occupancy target in waves per SIMD.
+#ifndef NSR_F64_BIG_BK
+#define NSR_F64_BIG_BK 16
+#endif
+#ifndef NSR_F64_BIG_NBUF
+#define NSR_F64_BIG_NBUF 2
+#endif
+#ifndef NSR_F64_WAVES_PER_EU
+#define NSR_F64_WAVES_PER_EU 2
+#endif
+
 namespace nsr {
 
 typedef double f64x4 __attribute__((ext_vector_type(4)));
@@ -50,8 +63,9 @@ __device__ __forceinline__ void map_tile(int bid, int tiles_m, int tiles_n, int&
   tn = r / gm;
 }
 
-template <int BM, int BN, int BK, bool VEC>
+template <int BM, int BN, int BK, int NBUF, bool VEC>
 __global__ void __launch_bounds__(256)
+__attribute__((amdgpu_waves_per_eu(NSR_F64_WAVES_PER_EU)))
 gemm_f64_kernel(GemmF64Args p, int tiles_m, int tiles_n) {
   constexpr int NT = 256;
   constexpr int WTM = BM / 2;          // rows per wave
@@ -65,8 +79,8 @@ gemm_f64_kernel(GemmF64Args p, int tiles_m, int tiles_n) {
   static_assert(XV >= 1 && YV >= 1, "tile too small for 256 threads");
   static_assert((BM * BK / 2) % NT == 0 && (BK * BN / 2) % NT == 0, "tile/thread mismatch");
 
-  __shared__ __attribute__((aligned(16))) double Xs[2][BM * XS];
-  __shared__ __attribute__((aligned(16))) double Ys[2][BK * YS];
+  __shared__ __attribute__((aligned(16))) double Xs[NBUF][BM * XS];
+  __shared__ __attribute__((aligned(16))) double Ys[NBUF][BK * YS];
   __shared__ double red[4];
 
   const int tid = threadIdx.x;
@@ -152,7 +166,8 @@ gemm_f64_kernel(GemmF64Args p, int tiles_m, int tiles_n) {
   const int lk = lane >> 4;
   if (nk > 0) load(0);
   for (int kt = 0; kt < nk; ++kt) {
-    const int buf = kt & 1;
+    const int buf = (NBUF == 2) ? (kt & 1) : 0;
+    if (NBUF == 1 && kt > 0) __syncthreads();   // everyone done reading the slab
     store(buf);
     __syncthreads();
     if (kt + 1 < nk) load((int64_t)(kt + 1) * BK);
@@ -204,7 +219,7 @@ gemm_f64_kernel(GemmF64Args p, int tiles_m, int tiles_n) {
   }
 }
 
-template <int BM, int BN, int BK>
+template <int BM, int BN, int BK, int NBUF>
 int64_t launch_cfg(const GemmF64Args& a, hipStream_t st) {
   const int tiles_m = (int)((a.M + BM - 1) / BM);
   const int tiles_n = (int)((a.N + BN - 1) / BN);
@@ -214,9 +229,11 @@ int64_t launch_cfg(const GemmF64Args& a, hipStream_t st) {
                    ((reinterpret_cast<uintptr_t>(a.Y) & 15) == 0);
   dim3 grid((unsigned)nt), block(256);
   if (vec)
-    hipLaunchKernelGGL((gemm_f64_kernel<BM, BN, BK, true>), grid, block, 0, st, a, tiles_m, tiles_n);
+    hipLaunchKernelGGL((gemm_f64_kernel<BM, BN, BK, NBUF, true>), grid, block, 0, st, a, tiles_m,
+                       tiles_n);
   else
-    hipLaunchKernelGGL((gemm_f64_kernel<BM, BN, BK, false>), grid, block, 0, st, a, tiles_m, tiles_n);
+    hipLaunchKernelGGL((gemm_f64_kernel<BM, BN, BK, NBUF, false>), grid, block, 0, st, a, tiles_m,
+                       tiles_n);
   if (hipGetLastError() != hipSuccess) return -1;
   return a.partial ? nt : 0;
 }
@@ -236,8 +253,8 @@ int64_t gemm_f64_partials(int64_t m, int64_t n) {
 
 int64_t launch_gemm_f64(const GemmF64Args& a, hipStream_t st) {
   if (a.M <= 0 || a.N <= 0) return 0;
-  if (use_big(a.M, a.N)) return launch_cfg<128, 128, 16>(a, st);
-  return launch_cfg<64, 64, 16>(a, st);
+  if (use_big(a.M, a.N)) return launch_cfg<128, 128, NSR_F64_BIG_BK, NSR_F64_BIG_NBUF>(a, st);
+  return launch_cfg<64, 64, 16, 2>(a, st);
 }
 
 }  // namespace nsr
