@@ -1,22 +1,26 @@
 #!/usr/bin/env python3
 """Benchmark: coupled high-order Newton-Schulz / Richardson SPD solves on one MI355X.
 
-One "step" is one whole solve (richardson_ns_solve through the C ABI) of a
-seeded synthetic system already resident in HBM: N = 4096, kappa = 1e4,
+Headline: one "step" is one whole solve (richardson_ns_solve through the C ABI)
+of a seeded synthetic system already resident in HBM: N = 4096, kappa = 1e4,
 A = Q diag(lam) Q^T, order-8 factorized Newton-Schulz (I+F)(I+F^2)(I+F^4) in
 float64 until the ||F|| rounding floor, coupled Richardson updates and float64
 refinement to a relative residual of 1e-12.
 
-Prints ONE JSON line (see the keys below).  The float64 GEMM's roofline comes
-from per-launch HIP events recorded by the library on its stream during the
-timed region; the CPU baseline is the oracle timed on a bounded sample.
+Also measured (extra keys of the same JSON line): the mixed-precision path
+(bf16 powers, float32 residual / G-side, float64 Richardson) on the same
+system, and the N = 8192, kappa = 1e6 composite (double Newton-Schulz, order
+8) workload in mixed precision next to the same solve in float64.
+
+The float64 GEMM's roofline comes from per-launch HIP events recorded by the
+library on its stream during the timed region; the CPU baseline is the oracle
+timed on a bounded sample.
 """
 from __future__ import annotations
 
 import argparse
 import hashlib
 import json
-import math
 import os
 import sys
 import time
@@ -29,9 +33,9 @@ sys.path.insert(0, ROOT)
 from paper_2008_11480_amd import inputs  # noqa: E402
 
 PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3, "bf16": 2500.0}
-HBM_PEAK_GBS = 8000.0
 GEMM_KERNEL_SRC = os.path.join(ROOT, "paper_2008_11480_amd", "csrc", "nsr_gemm_f64.hip")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "gemm_f64_spd4096_traffic.json")
+KIND = {"f64": 1, "f32": 2, "bf16": 3}
 
 
 def log(msg):
@@ -98,6 +102,84 @@ def cpu_baseline(sysm, order, steps_per_solve, refine_steps):
     }
 
 
+def measure(torch, solver, b, theta, kw, steps, warmup, label):
+    """Warm up, then time `steps` whole solves with per-launch GEMM events."""
+    for i in range(warmup):
+        rep = solver.solve(b, theta, **kw)
+        log(f"{label} warmup {i}: ns_steps={rep.ns_steps} refine={rep.refine_steps} "
+            f"rel_resid={rep.rel_resid:.2e}")
+    torch.cuda.synchronize()
+    solver.timing(True)
+    solver.timing_reset()
+    lat, reps = [], []
+    torch.cuda.synchronize()
+    t_begin = time.perf_counter()
+    for i in range(steps):
+        t0 = time.perf_counter()
+        rep = solver.solve(b, theta, **kw)
+        lat.append(time.perf_counter() - t0)     # solve() returns after a stream sync
+        reps.append(rep)
+        log(f"{label} step {i}: {lat[-1] * 1e3:.1f} ms ns_steps={rep.ns_steps} mmm={rep.mmm} "
+            f"rel_resid={rep.rel_resid:.2e}")
+    torch.cuda.synchronize()
+    t_total = time.perf_counter() - t_begin
+    gemm = {}
+    for name, kind in KIND.items():
+        cnt, ms, fl = solver.timing_read(kind)
+        if cnt:
+            avg = ms / cnt
+            tf = fl / cnt / (avg * 1e-3) / 1e12
+            gemm[name] = {"launches": cnt, "avg_launch_ms": avg, "tflops": tf,
+                          "frac_of_peak": tf / PEAK_TFLOPS[name],
+                          "share_of_solve_time": ms / (t_total * 1e3)}
+    solver.timing(False)
+    lat_ms = np.array(lat) * 1e3
+    return {
+        "solves_per_s": steps / t_total,
+        "ms_per_solve": t_total / steps * 1e3,
+        "latency_ms_p50": float(np.percentile(lat_ms, 50)),
+        "latency_ms_p99": float(np.percentile(lat_ms, 99)),
+        "last": reps[-1],
+        "gemm": gemm,
+    }
+
+
+def report_of(rep):
+    return {"ns_steps": rep.ns_steps, "refine_steps": rep.refine_steps, "mmm": rep.mmm,
+            "ns_stop": rep.ns_stop, "refine_stop": rep.refine_stop,
+            "rel_resid_reported": rep.rel_resid}
+
+
+def run_composite(torch, nsr, steps, warmup):
+    """N = 8192, kappa = 1e6: composite (double Newton-Schulz) order 8 and the
+    factorized order 8, mixed precision, next to the composite in float64."""
+    w = inputs.WORKLOADS["spd8192_k1e6_dns8"]
+    n = w["n"]
+    log(f"generating spd8192_k1e6_dns8 on the GPU: N={n} kappa={w['kappa']:g}")
+    A, b, lam, Q = inputs.spd_qlq_device(n, w["kappa"], w["seed"])
+    theta_star = Q @ ((Q.T.contiguous() @ b) / lam)
+    out = {"workload": "spd8192_k1e6_dns8", "n": n, "kappa": w["kappa"], "order": 8}
+    theta = torch.zeros_like(b)
+    for label, prec, form in (("mixed_composite", nsr.PREC_MIXED_BF16, "composite_double"),
+                              ("mixed_factorized", nsr.PREC_MIXED_BF16, "squaring"),
+                              ("fp64_composite", nsr.PREC_FP64, "composite_double")):
+        solver = nsr.Solver(n, precision=prec, composite=form == "composite_double")
+        solver.bind(A)
+        kw = dict(order=8, form=form, k_max=64, resid_tol=1e-10, refine_max=100)
+        m = measure(torch, solver, b, theta, kw, steps if prec != nsr.PREC_FP64 else 1,
+                    1 if prec != nsr.PREC_FP64 else 0, label)
+        rel = float(torch.linalg.norm(b - A @ theta) / torch.linalg.norm(b))
+        fwd = float(torch.linalg.norm(theta - theta_star) / torch.linalg.norm(theta_star))
+        out[label] = {"solves_per_s": m["solves_per_s"], "ms_per_solve": m["ms_per_solve"],
+                      "rel_resid": rel, "fwd_err_vs_closed_form": fwd,
+                      "gemm": m["gemm"], **report_of(m["last"])}
+        del solver
+        torch.cuda.empty_cache()
+    out["speedup_mixed_composite_vs_fp64_composite"] = (
+        out["mixed_composite"]["solves_per_s"] / out["fp64_composite"]["solves_per_s"])
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -106,6 +188,7 @@ def main():
     ap.add_argument("--workload", default="spd4096_k1e4_o8",
                     choices=["spd4096_k1e4_o8", "spd64_k1e2_o4"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision legs")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="also run a plain device copy of this many MiB (PMC calibration)")
     args = ap.parse_args()
@@ -113,7 +196,7 @@ def main():
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print("bench.py measures one GPU: the solver runs on a single MI355X "
-              "(see DESIGN.md for how the path would shard); --gpus must be 1.",
+              "(DESIGN.md describes how the path would shard); --gpus must be 1.",
               file=sys.stderr)
         sys.exit(2)
 
@@ -144,52 +227,24 @@ def main():
         log(f"calibration copy of {args.calibrate_copy_mib} MiB done")
         del src, dst
 
-    for i in range(args.warmup):
-        rep = solver.solve(b, theta, **kw)
-        log(f"warmup {i}: ns_steps={rep.ns_steps} refine={rep.refine_steps} "
-            f"rel_resid={rep.rel_resid:.2e}")
-    torch.cuda.synchronize()
-
-    solver.timing(True)
-    solver.timing_reset()
-    lat = []
-    reps = []
-    torch.cuda.synchronize()
-    t_begin = time.perf_counter()
-    for i in range(args.steps):
-        t0 = time.perf_counter()
-        rep = solver.solve(b, theta, **kw)
-        lat.append(time.perf_counter() - t0)     # solve() returns after a stream sync
-        reps.append(rep)
-        log(f"step {i}: {lat[-1] * 1e3:.1f} ms ns_steps={rep.ns_steps} mmm={rep.mmm} "
-            f"rel_resid={rep.rel_resid:.2e}")
-    torch.cuda.synchronize()
-    t_total = time.perf_counter() - t_begin
-    launches, gemm_ms, gemm_flop = solver.timing_read(1)
-    solver.timing(False)
-
+    m = measure(torch, solver, b, theta, kw, args.steps, args.warmup, "fp64")
+    last = m["last"]
     th = theta.cpu().numpy()
     theta_star = sysm.Q @ ((sysm.Q.T @ sysm.b) / sysm.lam)
     fwd = float(np.linalg.norm(th - theta_star) / np.linalg.norm(theta_star))
     rel = float(np.linalg.norm(sysm.b - sysm.A @ th) / np.linalg.norm(sysm.b))
-    last = reps[-1]
-
-    ms_per_step = t_total / args.steps * 1e3
-    value = args.steps / t_total
+    g64 = m["gemm"]["f64"]
     flop_per_solve = last.gemm_flop + 4.0 * n * n * (last.ns_steps + last.refine_steps + 1)
-    avg_launch_ms = gemm_ms / max(launches, 1)
-    flop_per_launch = gemm_flop / max(launches, 1)
-    achieved = flop_per_launch / (avg_launch_ms * 1e-3) / 1e12 if launches else None
     traffic = traffic_per_launch()
 
     out = {
-        "metric": "solves/s at rel. residual <= 1e-10 (plain FP64 path)",
-        "value": value,
+        "metric": "solves/s at rel. residual <= 1e-10 (plain FP64 path; mixed in 'mixed')",
+        "value": m["solves_per_s"],
         "unit": "solves/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": ms_per_step,
+        "ms_per_step": m["ms_per_solve"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -204,25 +259,49 @@ def main():
         "roofline": {
             "bound": "mfma",
             "kernel": "gemm_f64_kernel<128,128,16>",
-            "achieved": achieved,
+            "achieved": g64["tflops"],
             "peak": PEAK_TFLOPS["f64"],
             "unit": "TFLOP/s",
-            "frac": (achieved / PEAK_TFLOPS["f64"]) if achieved else None,
+            "frac": g64["tflops"] / PEAK_TFLOPS["f64"],
             "traffic": traffic,
-            "launches": launches,
-            "avg_launch_ms": avg_launch_ms,
-            "flop_per_launch": flop_per_launch,
+            "launches": g64["launches"],
+            "avg_launch_ms": g64["avg_launch_ms"],
+            "flop_per_launch": 2.0 * n ** 3,
         },
         "solve": {
-            "ns_steps": last.ns_steps, "refine_steps": last.refine_steps, "mmm": last.mmm,
-            "ns_stop": last.ns_stop, "rel_resid": rel, "fwd_err_vs_closed_form": fwd,
-            "alg_tflops_per_solve": flop_per_solve / (ms_per_step * 1e-3) / 1e12,
-            "latency_ms_p50": float(np.percentile(np.array(lat) * 1e3, 50)),
-            "latency_ms_p99": float(np.percentile(np.array(lat) * 1e3, 99)),
+            **report_of(last), "rel_resid": rel, "fwd_err_vs_closed_form": fwd,
+            "alg_tflops_per_solve": flop_per_solve / (m["ms_per_solve"] * 1e-3) / 1e12,
+            "latency_ms_p50": m["latency_ms_p50"], "latency_ms_p99": m["latency_ms_p99"],
             "fnorm_hist": last.fnorm_hist,
         },
     }
-    if not args.no_cpu_baseline:
+    del solver
+    torch.cuda.empty_cache()
+
+    if not args.no_mixed and not fixed:
+        # Same N=4096 system, mixed precision, to the same 1e-12 residual.
+        ms = nsr.Solver(n, precision=nsr.PREC_MIXED_BF16, composite=False)
+        ms.bind(A)
+        thm = torch.zeros_like(b)
+        kwm = dict(kw, refine_max=100)
+        mm = measure(torch, ms, b, thm, kwm, args.steps, args.warmup, "mixed")
+        thc = thm.cpu().numpy()
+        out["mixed"] = {
+            "workload": args.workload, "precision": "mixed (bf16 powers, fp32 residual and "
+                                                  "G-side, fp64 Richardson)",
+            "solves_per_s": mm["solves_per_s"], "ms_per_solve": mm["ms_per_solve"],
+            "speedup_vs_fp64": mm["solves_per_s"] / m["solves_per_s"],
+            "rel_resid": float(np.linalg.norm(sysm.b - sysm.A @ thc) / np.linalg.norm(sysm.b)),
+            "fwd_err_vs_closed_form": float(np.linalg.norm(thc - theta_star)
+                                            / np.linalg.norm(theta_star)),
+            "latency_ms_p50": mm["latency_ms_p50"], "latency_ms_p99": mm["latency_ms_p99"],
+            "gemm": mm["gemm"], **report_of(mm["last"]),
+        }
+        del ms
+        torch.cuda.empty_cache()
+        out["composite"] = run_composite(torch, nsr, max(2, args.steps // 2), 1)
+
+    if not args.no_cpu_baseline and not fixed:
         log("timing the CPU oracle on a bounded sample")
         out["cpu_baseline"] = cpu_baseline(sysm, order, last.ns_steps, last.refine_steps)
     print(json.dumps(out), flush=True)

@@ -24,6 +24,9 @@
  *     abort() crosses this boundary.
  *   - Matrices are row-major float64 with a leading dimension (ld >= n).
  *     All matrix and vector pointers are DEVICE pointers unless stated.
+ *     The iterates G, F live in the workspace in the solver's precision
+ *     (float64, or float32 with bf16 copies); A, b, theta and the Richardson
+ *     residual are always float64.
  *   - The caller owns A, b, theta and the workspace; the library never calls
  *     hipMalloc on the solve path.  A is borrowed from ns_bind() until the
  *     next ns_bind() or ns_destroy(); it is never written.
@@ -114,8 +117,9 @@ int ns_destroy(ns_solver* s);
 
 /* Borrow A (device, row-major float64, lda >= n, symmetric positive definite;
  * symmetry is assumed, not checked).  Resets the iteration state.  In the
- * float32 / mixed modes this also stores a float32 copy of A in the
- * workspace.  Errors: NS_EINVAL (NULL, lda < n). */
+ * float32 / mixed modes this also enqueues a float32 copy of A into the
+ * workspace (used by the residual products I - A G).  Errors: NS_EINVAL
+ * (NULL, lda < n), NS_EHIP. */
 int ns_bind(ns_solver* s, const double* A, int64_t lda);
 
 /* Section 2 (scalar preconditioner): compute alpha (NS_SCALE_FROBENIUS:
@@ -136,7 +140,8 @@ int ns_init_scale(ns_solver* s, int scale, double eps, double* alpha_out,
 int ns_step(ns_solver* s, int order, int factorization, int p, int w,
             double* fnorm_out);
 
-/* Copy the current G_k into G_out (device, row-major float64, ldg >= n). */
+/* Copy the current G_k into G_out (device, row-major float64, ldg >= n;
+ * converted from float32 in the float32 / mixed modes). */
 int ns_get_G(ns_solver* s, double* G_out, int64_t ldg);
 
 /* Copy the current F_k = I - A G_k into F_out (device, float64, ldf >= n). */
@@ -222,6 +227,32 @@ int ns_gemm_f64(void* hip_stream, int64_t m, int64_t n, int64_t k,
 
 /* Number of per-tile partial sums ns_gemm_f64 writes for an m x n output. */
 int64_t ns_gemm_f64_partials(int64_t m, int64_t n);
+
+/* Kernel-level entry points of the float32 and bf16 MFMA GEMMs used by the
+ * float32 and mixed modes (tests, benchmarks), with the same fused epilogue
+ * computed in float32:
+ *   ns_gemm_f32:      D = diag I + scale (X Y)   + E1 + E2,  X: m x k, Y: k x n
+ *   ns_gemm_bf16_nt:  D = diag I + scale (X Y^T) + E1 + E2,  X: m x k, Y: n x k
+ * X / Y are row-major device float32 (ns_gemm_f32) or bf16 stored as raw
+ * 16-bit patterns (ns_gemm_bf16_nt); accumulation is float32.  D (float32)
+ * and Db (bf16 copy of D, rounded to nearest even) are optional but not both
+ * NULL; E1, E2 are optional float32 addends.  Outputs must not alias X or Y.
+ * sumsq_out, when non-NULL, must hold 1 + ns_gemm_lp_partials(m, n) device
+ * doubles; [0] receives sum(D_ij^2) accumulated in float64 in a fixed order.
+ * Enqueued on hip_stream; no synchronization.  Errors as ns_gemm_f64. */
+int ns_gemm_f32(void* hip_stream, int64_t m, int64_t n, int64_t k,
+                const float* X, int64_t ldx, const float* Y, int64_t ldy,
+                float* D, int64_t ldd, uint16_t* Db, int64_t lddb,
+                const float* E1, int64_t lde1, const float* E2, int64_t lde2,
+                float diag, float scale, double* sumsq_out);
+int ns_gemm_bf16_nt(void* hip_stream, int64_t m, int64_t n, int64_t k,
+                    const uint16_t* X, int64_t ldx, const uint16_t* Y, int64_t ldy,
+                    float* D, int64_t ldd, uint16_t* Db, int64_t lddb,
+                    const float* E1, int64_t lde1, const float* E2, int64_t lde2,
+                    float diag, float scale, double* sumsq_out);
+
+/* Number of per-tile partial sums ns_gemm_f32 / ns_gemm_bf16_nt write. */
+int64_t ns_gemm_lp_partials(int64_t m, int64_t n);
 
 const char* ns_status_string(int status);
 const char* ns_last_error(void);

@@ -88,11 +88,13 @@ reduce_kernel(const double* __restrict__ partial, int64_t count, double* __restr
   }
 }
 
-// F = I - A / alpha, sum of F^2 per block (one block per kRowsPerBlock rows).
+// F = I - A / alpha (computed in float64, stored as T, optional bf16 copy),
+// sum of F^2 per block (one block per kRowsPerBlock rows).
+template <typename T>
 __global__ void __launch_bounds__(kThreads)
 init_resid_kernel(const double* __restrict__ A, int64_t lda, int64_t n,
-                  const double* __restrict__ alpha, double* __restrict__ F, int64_t ldf,
-                  double* __restrict__ partial) {
+                  const double* __restrict__ alpha, T* __restrict__ F, int64_t ldf,
+                  uint16_t* __restrict__ Fb, double* __restrict__ partial) {
   __shared__ double red[4];
   const double inv = 1.0 / alpha[0];
   const int64_t r0 = (int64_t)blockIdx.x * kRowsPerBlock;
@@ -103,25 +105,38 @@ init_resid_kernel(const double* __restrict__ A, int64_t lda, int64_t n,
     for (int64_t c = threadIdx.x; c < n; c += kThreads) {
       double v = -A[row * lda + c] * inv;
       if (c == row) v += 1.0;
-      F[row * ldf + c] = v;
-      s += v * v;
+      const T t = (T)v;
+      F[row * ldf + c] = t;
+      if (Fb) Fb[row * ldf + c] = __builtin_bit_cast(uint16_t, (__bf16)(float)t);
+      s += (double)t * (double)t;
     }
   }
-  const double t = block_sum(s, red);
-  if (partial && threadIdx.x == 0) partial[blockIdx.x] = t;
+  const double tt = block_sum(s, red);
+  if (partial && threadIdx.x == 0) partial[blockIdx.x] = tt;
 }
 
 // G = (I + C) / alpha  (C may be null).
+template <typename T>
 __global__ void __launch_bounds__(kThreads)
-scaled_identity_plus_kernel(const double* __restrict__ C, int64_t ldc, int64_t n,
-                            const double* __restrict__ alpha, double* __restrict__ G, int64_t ldg) {
+scaled_identity_plus_kernel(const T* __restrict__ C, int64_t ldc, int64_t n,
+                            const double* __restrict__ alpha, T* __restrict__ G, int64_t ldg) {
   const double inv = 1.0 / alpha[0];
   const int64_t row = blockIdx.y;
   const int64_t c = (int64_t)blockIdx.x * kThreads + threadIdx.x;
   if (row >= n || c >= n) return;
-  double v = C ? C[row * ldc + c] : 0.0;
+  double v = C ? (double)C[row * ldc + c] : 0.0;
   if (c == row) v += 1.0;
-  G[row * ldg + c] = v * inv;
+  G[row * ldg + c] = (T)(v * inv);
+}
+
+// dst (float64 or float32) = (T) src, n x n.
+template <typename S, typename D>
+__global__ void __launch_bounds__(kThreads)
+convert_kernel(const S* __restrict__ src, int64_t lds, int64_t n, D* __restrict__ dst, int64_t ldd) {
+  const int64_t row = blockIdx.y;
+  const int64_t c = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (row >= n || c >= n) return;
+  dst[row * ldd + c] = (D)src[row * lds + c];
 }
 
 // r = b - A theta: one wave per row, 4 rows per block; partial sum of r^2.
@@ -146,16 +161,17 @@ gemv_resid_kernel(const double* __restrict__ A, int64_t lda, int64_t n,
   if (threadIdx.x == 0 && partial) partial[blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
 }
 
-// theta += G r: one wave per row.
+// theta += G r: one wave per row (G float64 or float32, float64 accumulate).
+template <typename T>
 __global__ void __launch_bounds__(kThreads)
-gemv_update_kernel(const double* __restrict__ G, int64_t ldg, int64_t n,
+gemv_update_kernel(const T* __restrict__ G, int64_t ldg, int64_t n,
                    const double* __restrict__ r, double* __restrict__ theta) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int64_t row = (int64_t)blockIdx.x * 4 + wave;
   if (row >= n) return;
-  const double* g = G + row * ldg;
+  const T* g = G + row * ldg;
   double s = 0.0;
-  for (int64_t c = lane; c < n; c += 64) s += g[c] * r[c];
+  for (int64_t c = lane; c < n; c += 64) s += (double)g[c] * r[c];
   s = wave_sum(s);
   if (lane == 0) theta[row] += s;
 }
@@ -201,20 +217,40 @@ void launch_reduce(const double* partial, int64_t count, double* out, int mode, 
   hipLaunchKernelGGL(reduce_kernel, dim3(1), dim3(kThreads), 0, st, partial, count, out, mode, eps);
 }
 
-int64_t launch_init_resid(const double* A, int64_t lda, int64_t n, const double* alpha, double* F,
-                          int64_t ldf, double* partial, hipStream_t st) {
+template <typename T>
+int64_t launch_init_resid(const double* A, int64_t lda, int64_t n, const double* alpha, T* F,
+                          int64_t ldf, uint16_t* Fb, double* partial, hipStream_t st) {
   const int64_t nb = sumsq_partials(n);
-  hipLaunchKernelGGL(init_resid_kernel, dim3((unsigned)nb), dim3(kThreads), 0, st, A, lda, n,
-                     alpha, F, ldf, partial);
+  hipLaunchKernelGGL(init_resid_kernel<T>, dim3((unsigned)nb), dim3(kThreads), 0, st, A, lda, n,
+                     alpha, F, ldf, Fb, partial);
   return nb;
 }
+template int64_t launch_init_resid<double>(const double*, int64_t, int64_t, const double*, double*,
+                                           int64_t, uint16_t*, double*, hipStream_t);
+template int64_t launch_init_resid<float>(const double*, int64_t, int64_t, const double*, float*,
+                                          int64_t, uint16_t*, double*, hipStream_t);
 
-void launch_scaled_identity_plus(const double* C, int64_t ldc, int64_t n, const double* alpha,
-                                 double* G, int64_t ldg, hipStream_t st) {
+template <typename T>
+void launch_scaled_identity_plus(const T* C, int64_t ldc, int64_t n, const double* alpha, T* G,
+                                 int64_t ldg, hipStream_t st) {
   dim3 grid((unsigned)((n + kThreads - 1) / kThreads), (unsigned)n);
-  hipLaunchKernelGGL(scaled_identity_plus_kernel, grid, dim3(kThreads), 0, st, C, ldc, n, alpha, G,
-                     ldg);
+  hipLaunchKernelGGL(scaled_identity_plus_kernel<T>, grid, dim3(kThreads), 0, st, C, ldc, n, alpha,
+                     G, ldg);
 }
+template void launch_scaled_identity_plus<double>(const double*, int64_t, int64_t, const double*,
+                                                  double*, int64_t, hipStream_t);
+template void launch_scaled_identity_plus<float>(const float*, int64_t, int64_t, const double*,
+                                                 float*, int64_t, hipStream_t);
+
+template <typename S, typename D>
+void launch_convert(const S* src, int64_t lds, int64_t n, D* dst, int64_t ldd, hipStream_t st) {
+  dim3 grid((unsigned)((n + kThreads - 1) / kThreads), (unsigned)n);
+  hipLaunchKernelGGL((convert_kernel<S, D>), grid, dim3(kThreads), 0, st, src, lds, n, dst, ldd);
+}
+template void launch_convert<double, float>(const double*, int64_t, int64_t, float*, int64_t,
+                                            hipStream_t);
+template void launch_convert<float, double>(const float*, int64_t, int64_t, double*, int64_t,
+                                            hipStream_t);
 
 int64_t launch_gemv_resid(const double* A, int64_t lda, int64_t n, const double* b,
                           const double* theta, double* r, double* partial, hipStream_t st) {
@@ -224,11 +260,16 @@ int64_t launch_gemv_resid(const double* A, int64_t lda, int64_t n, const double*
   return nb;
 }
 
-void launch_gemv_update(const double* G, int64_t ldg, int64_t n, const double* r, double* theta,
+template <typename T>
+void launch_gemv_update(const T* G, int64_t ldg, int64_t n, const double* r, double* theta,
                         hipStream_t st) {
-  hipLaunchKernelGGL(gemv_update_kernel, dim3((unsigned)((n + 3) / 4)), dim3(kThreads), 0, st, G,
+  hipLaunchKernelGGL(gemv_update_kernel<T>, dim3((unsigned)((n + 3) / 4)), dim3(kThreads), 0, st, G,
                      ldg, n, r, theta);
 }
+template void launch_gemv_update<double>(const double*, int64_t, int64_t, const double*, double*,
+                                         hipStream_t);
+template void launch_gemv_update<float>(const float*, int64_t, int64_t, const double*, double*,
+                                        hipStream_t);
 
 void launch_vec_scale(const double* b, const double* alpha, double* theta, int64_t n,
                       int accumulate, hipStream_t st) {

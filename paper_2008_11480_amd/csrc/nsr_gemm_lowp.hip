@@ -1,0 +1,374 @@
+// Float32 and bf16 MFMA GEMMs for gfx950 with the solver's fused epilogue
+//
+//   D = diag * I + scale * (X op(Y)) + E1 + E2
+//
+// * gemm_f32_nn: X (m x k) and Y (k x n) row-major float32, float32
+//   accumulate (v_mfma_f32_16x16x4_f32).  Used where rounding would be
+//   amplified by the condition number: the residual F = I - A G, the G-side
+//   update G + G C and the composite merge (float32 / mixed modes).
+// * gemm_bf16_nt: X (m x k) and Y (n x k) row-major bf16, D = X Y^T, float32
+//   accumulate (v_mfma_f32_32x32x16_bf16).  Used for the powers of F and the
+//   identity-offset assembly of the mixed mode.  Those operands are
+//   polynomials in F (symmetric in exact arithmetic), so Y^T = Y up to a
+//   rounding asymmetry far below the bf16 rounding of the operands, and the
+//   NT form lets both operands be read with K contiguous.
+//
+// Both write float32 D, optionally a bf16 copy Db (next GEMM's operand), and
+// optionally one float64 partial sum of D^2 per tile.
+//
+// Accumulator layouts (gfx950, measured): for 16x16x4 f32, element r of lane
+// l is D[4 (l/16) + r][l % 16]; for 32x32x16 bf16 it is
+// D[8 (r/4) + 4 (l/32) + r % 4][l % 32], and the bf16 operand element e of
+// lane l is K index 8 (l/32) + e.
+//
+// Tiling as in the float64 GEMM: 128 x 128 workgroup tile, 4 waves of 64 x 64,
+// K slabs staged global -> registers (one slab ahead) -> two LDS buffers,
+// XCD-aware grouped tile order, two workgroups per CU.
+#include "nsr_internal.h"
+
+namespace nsr {
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+namespace {
+
+__device__ __forceinline__ void map_tile_lp(int bid, int tiles_m, int tiles_n, int& tm, int& tn) {
+  const int ntiles = tiles_m * tiles_n;
+  int t = bid;
+  if ((ntiles & 7) == 0) {
+    const int per = ntiles >> 3;
+    t = (bid & 7) * per + (bid >> 3);
+  }
+  constexpr int GM = 8;
+  const int group_size = GM * tiles_n;
+  const int g = t / group_size;
+  const int first_m = g * GM;
+  const int gm = min(tiles_m - first_m, GM);
+  const int r = t - g * group_size;
+  tm = first_m + r % gm;
+  tn = r / gm;
+}
+
+// Shared epilogue of one output element.
+__device__ __forceinline__ void put(const GemmLpArgs& p, int64_t row, int64_t col, float acc,
+                                    double& ss) {
+  float v = p.scale * acc;
+  if (row == col) v += p.diag;
+  if (p.E1) v += p.E1[row * p.lde1 + col];
+  if (p.E2) v += p.E2[row * p.lde2 + col];
+  if (p.D) p.D[row * p.ldd + col] = v;
+  if (p.Db) p.Db[row * p.lddb + col] = __builtin_bit_cast(uint16_t, (__bf16)v);
+  ss += (double)v * (double)v;
+}
+
+__device__ __forceinline__ void write_partial(const GemmLpArgs& p, double ss, double* red,
+                                              int tm, int tn, int tiles_n) {
+  if (!p.partial) return;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) ss += __shfl_xor(ss, off, 64);
+  if (lane == 0) red[wave] = ss;
+  __syncthreads();
+  if (threadIdx.x == 0) p.partial[(int64_t)tm * tiles_n + tn] = (red[0] + red[1]) + (red[2] + red[3]);
+}
+
+// ---------------------------------------------------------------------------
+// float32, NN
+// ---------------------------------------------------------------------------
+template <int BM, int BN, int BK, bool VEC>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
+gemm_f32_nn_kernel(GemmLpArgs p, int tiles_m, int tiles_n) {
+  constexpr int NT = 256;
+  constexpr int WTM = BM / 2, WTN = BN / 2;
+  constexpr int FM = WTM / 16, FN = WTN / 16;
+  constexpr int XS = BK + 4;    // floats
+  constexpr int YS = BN + 4;
+  constexpr int XV = (BM * BK / 4) / NT;  // float4 per thread
+  constexpr int YV = (BK * BN / 4) / NT;
+  static_assert(XV >= 1 && YV >= 1, "tile too small");
+  __shared__ __attribute__((aligned(16))) float Xs[2][BM * XS];
+  __shared__ __attribute__((aligned(16))) float Ys[2][BK * YS];
+  __shared__ double red[4];
+
+  const float* X = static_cast<const float*>(p.X);
+  const float* Y = static_cast<const float*>(p.Y);
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+  int tm, tn;
+  map_tile_lp(blockIdx.x, tiles_m, tiles_n, tm, tn);
+  const int64_t m0 = (int64_t)tm * BM, n0 = (int64_t)tn * BN;
+  const int64_t M = p.M, N = p.N, K = p.K;
+  float4 xr[XV], yr[YV];
+
+  auto load = [&](int64_t k0) {
+#pragma unroll
+    for (int v = 0; v < XV; ++v) {
+      const int idx = tid + NT * v;
+      const int row = idx / (BK / 4), c = (idx % (BK / 4)) * 4;
+      const int64_t gm = m0 + row, gk = k0 + c;
+      float4 val = make_float4(0.f, 0.f, 0.f, 0.f);
+      if (gm < M) {
+        const float* src = X + gm * p.ldx + gk;
+        if (VEC && gk + 3 < K) {
+          val = *reinterpret_cast<const float4*>(src);
+        } else {
+          if (gk < K) val.x = src[0];
+          if (gk + 1 < K) val.y = src[1];
+          if (gk + 2 < K) val.z = src[2];
+          if (gk + 3 < K) val.w = src[3];
+        }
+      }
+      xr[v] = val;
+    }
+#pragma unroll
+    for (int v = 0; v < YV; ++v) {
+      const int idx = tid + NT * v;
+      const int row = idx / (BN / 4), c = (idx % (BN / 4)) * 4;
+      const int64_t gk = k0 + row, gn = n0 + c;
+      float4 val = make_float4(0.f, 0.f, 0.f, 0.f);
+      if (gk < K) {
+        const float* src = Y + gk * p.ldy + gn;
+        if (VEC && gn + 3 < N) {
+          val = *reinterpret_cast<const float4*>(src);
+        } else {
+          if (gn < N) val.x = src[0];
+          if (gn + 1 < N) val.y = src[1];
+          if (gn + 2 < N) val.z = src[2];
+          if (gn + 3 < N) val.w = src[3];
+        }
+      }
+      yr[v] = val;
+    }
+  };
+  auto store = [&](int buf) {
+#pragma unroll
+    for (int v = 0; v < XV; ++v) {
+      const int idx = tid + NT * v;
+      const int row = idx / (BK / 4), c = (idx % (BK / 4)) * 4;
+      *reinterpret_cast<float4*>(&Xs[buf][row * XS + c]) = xr[v];
+    }
+#pragma unroll
+    for (int v = 0; v < YV; ++v) {
+      const int idx = tid + NT * v;
+      const int row = idx / (BN / 4), c = (idx % (BN / 4)) * 4;
+      *reinterpret_cast<float4*>(&Ys[buf][row * YS + c]) = yr[v];
+    }
+  };
+
+  f32x4 acc[FM][FN];
+#pragma unroll
+  for (int i = 0; i < FM; ++i)
+#pragma unroll
+    for (int j = 0; j < FN; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+  const int nk = (int)((K + BK - 1) / BK);
+  const int lr = lane & 15, lk = lane >> 4;
+  if (nk > 0) load(0);
+  for (int kt = 0; kt < nk; ++kt) {
+    const int buf = kt & 1;
+    store(buf);
+    __syncthreads();
+    if (kt + 1 < nk) load((int64_t)(kt + 1) * BK);
+    const float* xs = &Xs[buf][(wm * WTM + lr) * XS + lk];
+    const float* ys = &Ys[buf][lk * YS + wn * WTN + lr];
+#pragma unroll
+    for (int ks = 0; ks < BK; ks += 4) {
+      float a[FM], b[FN];
+#pragma unroll
+      for (int i = 0; i < FM; ++i) a[i] = xs[i * 16 * XS + ks];
+#pragma unroll
+      for (int j = 0; j < FN; ++j) b[j] = ys[ks * YS + j * 16];
+#pragma unroll
+      for (int i = 0; i < FM; ++i)
+#pragma unroll
+        for (int j = 0; j < FN; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i], b[j], acc[i][j], 0, 0, 0);
+    }
+  }
+
+  double ss = 0.0;
+#pragma unroll
+  for (int i = 0; i < FM; ++i)
+#pragma unroll
+    for (int j = 0; j < FN; ++j) {
+      const int64_t col = n0 + wn * WTN + j * 16 + lr;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t row = m0 + wm * WTM + i * 16 + 4 * lk + r;
+        if (row < M && col < N) put(p, row, col, acc[i][j][r], ss);
+      }
+    }
+  write_partial(p, ss, red, tm, tn, tiles_n);
+}
+
+// ---------------------------------------------------------------------------
+// bf16, NT: D = X Y^T, X: m x k, Y: n x k (both row-major, K contiguous)
+// ---------------------------------------------------------------------------
+template <int BM, int BN, int BK, bool VEC>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
+gemm_bf16_nt_kernel(GemmLpArgs p, int tiles_m, int tiles_n) {
+  constexpr int NT = 256;
+  constexpr int WTM = BM / 2, WTN = BN / 2;
+  constexpr int FM = WTM / 32, FN = WTN / 32;
+  constexpr int S = BK + 8;                  // LDS row stride (bf16), 16-B aligned rows
+  constexpr int XV = (BM * BK / 8) / NT;     // 16-byte vectors per thread
+  constexpr int YV = (BN * BK / 8) / NT;
+  static_assert(XV >= 1 && YV >= 1, "tile too small");
+  __shared__ __attribute__((aligned(16))) __bf16 Xs[2][BM * S];
+  __shared__ __attribute__((aligned(16))) __bf16 Ys[2][BN * S];
+  __shared__ double red[4];
+
+  const __bf16* X = static_cast<const __bf16*>(p.X);
+  const __bf16* Y = static_cast<const __bf16*>(p.Y);
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+  int tm, tn;
+  map_tile_lp(blockIdx.x, tiles_m, tiles_n, tm, tn);
+  const int64_t m0 = (int64_t)tm * BM, n0 = (int64_t)tn * BN;
+  const int64_t M = p.M, N = p.N, K = p.K;
+  uint4 xr[XV], yr[YV];
+
+  auto load_one = [&](const __bf16* base, int64_t ld, int64_t r0, int64_t rmax, int64_t k0,
+                      int v) -> uint4 {
+    {
+      const int idx = tid + NT * v;
+      const int row = idx / (BK / 8), c = (idx % (BK / 8)) * 8;
+      const int64_t gr = r0 + row, gk = k0 + c;
+      uint4 val = make_uint4(0u, 0u, 0u, 0u);
+      if (gr < rmax) {
+        const __bf16* src = base + gr * ld + gk;
+        if (VEC && gk + 7 < K) {
+          val = *reinterpret_cast<const uint4*>(src);
+        } else {
+          unsigned short tmp[8];
+          const unsigned short* s16 = reinterpret_cast<const unsigned short*>(src);
+#pragma unroll
+          for (int e = 0; e < 8; ++e) tmp[e] = (gk + e < K) ? s16[e] : (unsigned short)0;
+          val.x = tmp[0] | ((unsigned)tmp[1] << 16);
+          val.y = tmp[2] | ((unsigned)tmp[3] << 16);
+          val.z = tmp[4] | ((unsigned)tmp[5] << 16);
+          val.w = tmp[6] | ((unsigned)tmp[7] << 16);
+        }
+      }
+      return val;
+    }
+  };
+  auto load = [&](int64_t k0) {
+#pragma unroll
+    for (int v = 0; v < XV; ++v) xr[v] = load_one(X, p.ldx, m0, M, k0, v);
+#pragma unroll
+    for (int v = 0; v < YV; ++v) yr[v] = load_one(Y, p.ldy, n0, N, k0, v);
+  };
+  auto store = [&](int buf) {
+#pragma unroll
+    for (int v = 0; v < XV; ++v) {
+      const int idx = tid + NT * v;
+      const int row = idx / (BK / 8), c = (idx % (BK / 8)) * 8;
+      *reinterpret_cast<uint4*>(&Xs[buf][row * S + c]) = xr[v];
+    }
+#pragma unroll
+    for (int v = 0; v < YV; ++v) {
+      const int idx = tid + NT * v;
+      const int row = idx / (BK / 8), c = (idx % (BK / 8)) * 8;
+      *reinterpret_cast<uint4*>(&Ys[buf][row * S + c]) = yr[v];
+    }
+  };
+
+  f32x16 acc[FM][FN];
+#pragma unroll
+  for (int i = 0; i < FM; ++i)
+#pragma unroll
+    for (int j = 0; j < FN; ++j) acc[i][j] = f32x16{};
+
+  const int nk = (int)((K + BK - 1) / BK);
+  const int lr = lane & 31, lk = lane >> 5;
+  if (nk > 0) load(0);
+  for (int kt = 0; kt < nk; ++kt) {
+    const int buf = kt & 1;
+    store(buf);
+    __syncthreads();
+    if (kt + 1 < nk) load((int64_t)(kt + 1) * BK);
+    const __bf16* xs = &Xs[buf][(wm * WTM + lr) * S + 8 * lk];
+    const __bf16* ys = &Ys[buf][(wn * WTN + lr) * S + 8 * lk];
+#pragma unroll
+    for (int ks = 0; ks < BK; ks += 16) {
+      bf16x8 a[FM], b[FN];
+#pragma unroll
+      for (int i = 0; i < FM; ++i) a[i] = *reinterpret_cast<const bf16x8*>(xs + i * 32 * S + ks);
+#pragma unroll
+      for (int j = 0; j < FN; ++j) b[j] = *reinterpret_cast<const bf16x8*>(ys + j * 32 * S + ks);
+#pragma unroll
+      for (int i = 0; i < FM; ++i)
+#pragma unroll
+        for (int j = 0; j < FN; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+    }
+  }
+
+  double ss = 0.0;
+#pragma unroll
+  for (int i = 0; i < FM; ++i)
+#pragma unroll
+    for (int j = 0; j < FN; ++j) {
+      const int64_t col = n0 + wn * WTN + j * 32 + lr;
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int64_t row = m0 + wm * WTM + i * 32 + 8 * (r >> 2) + 4 * lk + (r & 3);
+        if (row < M && col < N) put(p, row, col, acc[i][j][r], ss);
+      }
+    }
+  write_partial(p, ss, red, tm, tn, tiles_n);
+}
+
+bool big_tiles(int64_t m, int64_t n) { return ((m + 127) / 128) * ((n + 127) / 128) >= 256; }
+
+}  // namespace
+
+int64_t gemm_lp_partials(int64_t m, int64_t n) {
+  if (big_tiles(m, n)) return ((m + 127) / 128) * ((n + 127) / 128);
+  return ((m + 63) / 64) * ((n + 63) / 64);
+}
+
+int64_t launch_gemm_f32_nn(const GemmLpArgs& a, hipStream_t st) {
+  if (a.M <= 0 || a.N <= 0) return 0;
+  const bool vec = ((a.ldx & 3) == 0) && ((a.ldy & 3) == 0) &&
+                   ((reinterpret_cast<uintptr_t>(a.X) & 15) == 0) &&
+                   ((reinterpret_cast<uintptr_t>(a.Y) & 15) == 0);
+  const bool big = big_tiles(a.M, a.N);
+  const int bm = big ? 128 : 64;
+  const int tiles_m = (int)((a.M + bm - 1) / bm), tiles_n = (int)((a.N + bm - 1) / bm);
+  dim3 grid((unsigned)((int64_t)tiles_m * tiles_n)), block(256);
+  if (big) {
+    if (vec) hipLaunchKernelGGL((gemm_f32_nn_kernel<128, 128, 32, true>), grid, block, 0, st, a, tiles_m, tiles_n);
+    else hipLaunchKernelGGL((gemm_f32_nn_kernel<128, 128, 32, false>), grid, block, 0, st, a, tiles_m, tiles_n);
+  } else {
+    if (vec) hipLaunchKernelGGL((gemm_f32_nn_kernel<64, 64, 32, true>), grid, block, 0, st, a, tiles_m, tiles_n);
+    else hipLaunchKernelGGL((gemm_f32_nn_kernel<64, 64, 32, false>), grid, block, 0, st, a, tiles_m, tiles_n);
+  }
+  if (hipGetLastError() != hipSuccess) return -1;
+  return a.partial ? (int64_t)tiles_m * tiles_n : 0;
+}
+
+int64_t launch_gemm_bf16_nt(const GemmLpArgs& a, hipStream_t st) {
+  if (a.M <= 0 || a.N <= 0) return 0;
+  const bool vec = ((a.ldx & 7) == 0) && ((a.ldy & 7) == 0) &&
+                   ((reinterpret_cast<uintptr_t>(a.X) & 15) == 0) &&
+                   ((reinterpret_cast<uintptr_t>(a.Y) & 15) == 0);
+  const bool big = big_tiles(a.M, a.N);
+  const int bm = big ? 128 : 64;
+  const int tiles_m = (int)((a.M + bm - 1) / bm), tiles_n = (int)((a.N + bm - 1) / bm);
+  dim3 grid((unsigned)((int64_t)tiles_m * tiles_n)), block(256);
+  if (big) {
+    if (vec) hipLaunchKernelGGL((gemm_bf16_nt_kernel<128, 128, 64, true>), grid, block, 0, st, a, tiles_m, tiles_n);
+    else hipLaunchKernelGGL((gemm_bf16_nt_kernel<128, 128, 64, false>), grid, block, 0, st, a, tiles_m, tiles_n);
+  } else {
+    if (vec) hipLaunchKernelGGL((gemm_bf16_nt_kernel<64, 64, 64, true>), grid, block, 0, st, a, tiles_m, tiles_n);
+    else hipLaunchKernelGGL((gemm_bf16_nt_kernel<64, 64, 64, false>), grid, block, 0, st, a, tiles_m, tiles_n);
+  }
+  if (hipGetLastError() != hipSuccess) return -1;
+  return a.partial ? (int64_t)tiles_m * tiles_n : 0;
+}
+
+}  // namespace nsr

@@ -20,6 +20,27 @@ struct GemmF64Args {
   double* partial;   // per-tile sum of D^2 (null: not wanted)
 };
 
+// D = diag * I + scale * (X op(Y)) + E1 + E2 with float32 output (and an
+// optional bf16 copy Db, raw bits), float32 addends.  X / Y are float32 for
+// the NN kernel, bf16 (raw 16-bit) for the NT kernel.
+struct GemmLpArgs {
+  const void* X;
+  const void* Y;
+  float* D;          // may be null when only Db is wanted
+  uint16_t* Db;      // may be null
+  const float* E1;   // may be null
+  const float* E2;   // may be null
+  int64_t ldx, ldy, ldd, lddb, lde1, lde2;
+  int64_t M, N, K;
+  float diag;
+  float scale;
+  double* partial;   // per-tile sum of D^2 (float64), may be null
+};
+
+int64_t gemm_lp_partials(int64_t m, int64_t n);
+int64_t launch_gemm_f32_nn(const GemmLpArgs& a, hipStream_t st);
+int64_t launch_gemm_bf16_nt(const GemmLpArgs& a, hipStream_t st);
+
 // Number of per-tile partials the GEMM writes for an m x n output (the size
 // the partial buffer must have).
 int64_t gemm_f64_partials(int64_t m, int64_t n);
@@ -42,21 +63,30 @@ void launch_rowabs(const double* A, int64_t lda, int64_t n, double* rowsum, hipS
 void launch_reduce(const double* partial, int64_t count, double* out, int mode,
                    double half_plus_eps, hipStream_t st);
 
-// F = I - A / alpha (alpha read from device memory), partial sum of F^2.
-int64_t launch_init_resid(const double* A, int64_t lda, int64_t n, const double* alpha,
-                          double* F, int64_t ldf, double* partial, hipStream_t st);
+// F = I - A / alpha (alpha read from device memory, computed in float64 and
+// stored as T; Fb: optional bf16 copy with the same leading dimension),
+// partial sums of F^2.
+template <typename T>
+int64_t launch_init_resid(const double* A, int64_t lda, int64_t n, const double* alpha, T* F,
+                          int64_t ldf, uint16_t* Fb, double* partial, hipStream_t st);
 
 // G = (I + C) / alpha; C may be null (G = I / alpha).
-void launch_scaled_identity_plus(const double* C, int64_t ldc, int64_t n, const double* alpha,
-                                 double* G, int64_t ldg, hipStream_t st);
+template <typename T>
+void launch_scaled_identity_plus(const T* C, int64_t ldc, int64_t n, const double* alpha, T* G,
+                                 int64_t ldg, hipStream_t st);
+
+// dst = (D) src for an n x n matrix (double <-> float).
+template <typename S, typename D>
+void launch_convert(const S* src, int64_t lds, int64_t n, D* dst, int64_t ldd, hipStream_t st);
 
 // r = b - A theta, partial sums of r^2 (one per block); returns count.
 int64_t launch_gemv_resid(const double* A, int64_t lda, int64_t n, const double* b,
                           const double* theta, double* r, double* partial, hipStream_t st);
 int64_t gemv_partials(int64_t n);
 
-// theta += G r
-void launch_gemv_update(const double* G, int64_t ldg, int64_t n, const double* r, double* theta,
+// theta += G r (G float64 or float32; float64 accumulation)
+template <typename T>
+void launch_gemv_update(const T* G, int64_t ldg, int64_t n, const double* r, double* theta,
                         hipStream_t st);
 
 // theta = b / alpha (alpha on device); theta += r / alpha

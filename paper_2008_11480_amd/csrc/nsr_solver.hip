@@ -40,13 +40,22 @@ constexpr size_t kAlign = 256;
 inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 inline int64_t ld_for(int64_t n) { return (n + 31) / 32 * 32; }
 
-// Number of float64 n x n buffers per mode.
-//   plain:     G0 G1 F P1 P2 C1 C2                  = 7
-//   composite: + L0 L1 Gam H                        = 11
-int n_mats(int composite) { return composite ? 11 : 7; }
+// One n x n iterate: float64 storage (plain mode) or float32 storage with an
+// optional bf16 copy (float32 / mixed modes; the copy feeds bf16 products).
+struct Mat {
+  double* d = nullptr;
+  float* f = nullptr;
+  uint16_t* b = nullptr;
+};
+
+// Matrices of the iteration.  Plain: G0 G1 F P0 P1 C0 C1 (7); composite adds
+// L0 L1 Gam H (11).  In mixed mode F, P*, C*, Gam carry bf16 copies.
+constexpr int kPlainMats = 7;
+constexpr int kCompositeMats = 11;
 
 int64_t partial_capacity(int64_t n) {
   int64_t c = gemm_f64_partials(n, n);
+  c = c > gemm_lp_partials(n, n) ? c : gemm_lp_partials(n, n);
   c = c > sumsq_partials(n) ? c : sumsq_partials(n);
   c = c > gemv_partials(n) ? c : gemv_partials(n);
   c = c > 1024 ? c : 1024;
@@ -54,13 +63,20 @@ int64_t partial_capacity(int64_t n) {
   return c;
 }
 
-size_t layout_bytes(int64_t n, int composite) {
+size_t elem_bytes(int precision) { return precision == NS_PREC_FP64 ? 8 : 4; }
+
+size_t layout_bytes(int64_t n, int precision, int composite) {
   const int64_t ld = ld_for(n);
+  const size_t nn = (size_t)n * ld;
   size_t bytes = 0;
-  bytes += (size_t)n_mats(composite) * align_up((size_t)n * ld * sizeof(double), kAlign);
-  bytes += align_up((size_t)n * sizeof(double), kAlign);                   // r
-  bytes += align_up((size_t)partial_capacity(n) * sizeof(double), kAlign); // partials
-  bytes += align_up(16 * sizeof(double), kAlign);                          // scalars
+  const int mats = composite ? kCompositeMats : kPlainMats;
+  bytes += (size_t)mats * align_up(nn * elem_bytes(precision), kAlign);
+  if (precision != NS_PREC_FP64) bytes += align_up(nn * 4, kAlign);          // float32 A
+  if (precision == NS_PREC_MIXED_BF16)
+    bytes += (size_t)(composite ? 6 : 5) * align_up(nn * 2, kAlign);         // bf16 copies
+  bytes += align_up((size_t)n * sizeof(double), kAlign);                     // r
+  bytes += align_up((size_t)partial_capacity(n) * sizeof(double), kAlign);   // partials
+  bytes += align_up(16 * sizeof(double), kAlign);                            // scalars
   return bytes;
 }
 
@@ -69,6 +85,10 @@ struct TimedLaunch {
   int kind;
   double flop;
 };
+
+// Kind of product: the residual I - A X, a power / assembly product of
+// polynomials in F (bf16 in mixed mode), or a G-side / merge product.
+enum Kind { K_RESID = 0, K_POWER = 1, K_APPLY = 2 };
 
 }  // namespace
 
@@ -82,17 +102,13 @@ struct ns_solver {
   char* ws = nullptr;
   size_t ws_bytes = 0;
 
-  double* G[2] = {nullptr, nullptr};
+  Mat G[2];
   int gcur = 0;
-  double* F = nullptr;
-  double* P1 = nullptr;
-  double* P2 = nullptr;
-  double* C1 = nullptr;
-  double* C2 = nullptr;
-  double* L[2] = {nullptr, nullptr};
+  Mat F, P[2], C[2];
+  Mat L[2];
   int lcur = 0;
-  double* Gam = nullptr;
-  double* H = nullptr;
+  Mat Gam, H;
+  float* A32 = nullptr;
   double* r = nullptr;
   double* partial = nullptr;
   double* scal = nullptr;  // [0] alpha, [1] ||F||_F, [2] ||r||_2, [3] ||b||_2
@@ -123,24 +139,14 @@ hipEvent_t take_event(ns_solver* s) {
   return s->pool[s->pool_used++];
 }
 
-// One fused float64 GEMM on the solver's stream (timed when enabled).
-int gemm(ns_solver* s, double* D, const double* X, const double* Y, const double* E1,
-         const double* E2, double diag, double scale, bool want_norm) {
-  GemmF64Args a{};
-  a.X = X;
-  a.Y = Y;
-  a.D = D;
-  a.E1 = E1;
-  a.E2 = E2;
-  a.ldx = (X == s->A) ? s->lda : s->ld;
-  a.ldy = (Y == s->A) ? s->lda : s->ld;
-  a.ldd = s->ld;
-  a.lde1 = s->ld;
-  a.lde2 = s->ld;
-  a.M = a.N = a.K = s->n;
-  a.diag = diag;
-  a.scale = scale;
-  a.partial = want_norm ? s->partial : nullptr;
+bool is_f64(const ns_solver* s) { return s->precision == NS_PREC_FP64; }
+
+// One fused GEMM D = diag I + scale X Y + E1 + E2 on the solver's stream.
+// X == nullptr means A (the residual products).  Dispatch by precision:
+// float64 MFMA; float32 MFMA; mixed: bf16 MFMA (X Y^T) for K_POWER products,
+// float32 MFMA otherwise.
+int mm(ns_solver* s, Mat& D, const Mat* X, const Mat& Y, const Mat* E1, const Mat* E2,
+       double diag, double scale, bool want_norm, Kind kind) {
   hipEvent_t eb = nullptr, ee = nullptr;
   if (s->timing) {
     eb = take_event(s);
@@ -148,12 +154,50 @@ int gemm(ns_solver* s, double* D, const double* X, const double* Y, const double
     if (!eb || !ee) return fail(NS_EHIP, "hipEventCreate failed");
     HIP_TRY(hipEventRecord(eb, s->stream));
   }
-  const int64_t np = launch_gemm_f64(a, s->stream);
+  int64_t np;
+  int tkind;
+  if (is_f64(s)) {
+    GemmF64Args a{};
+    a.X = X ? X->d : s->A;
+    a.ldx = X ? s->ld : s->lda;
+    a.Y = Y.d;
+    a.ldy = s->ld;
+    a.D = D.d;
+    a.ldd = s->ld;
+    a.E1 = E1 ? E1->d : nullptr;
+    a.E2 = E2 ? E2->d : nullptr;
+    a.lde1 = a.lde2 = s->ld;
+    a.M = a.N = a.K = s->n;
+    a.diag = diag;
+    a.scale = scale;
+    a.partial = want_norm ? s->partial : nullptr;
+    np = launch_gemm_f64(a, s->stream);
+    tkind = 1;
+  } else {
+    GemmLpArgs a{};
+    const bool bf = (s->precision == NS_PREC_MIXED_BF16) && kind == K_POWER;
+    a.X = bf ? (const void*)X->b : (const void*)(X ? X->f : s->A32);
+    a.Y = bf ? (const void*)Y.b : (const void*)Y.f;
+    a.ldx = a.ldy = s->ld;
+    a.D = D.f;
+    a.ldd = s->ld;
+    a.Db = D.b;
+    a.lddb = s->ld;
+    a.E1 = E1 ? E1->f : nullptr;
+    a.E2 = E2 ? E2->f : nullptr;
+    a.lde1 = a.lde2 = s->ld;
+    a.M = a.N = a.K = s->n;
+    a.diag = (float)diag;
+    a.scale = (float)scale;
+    a.partial = want_norm ? s->partial : nullptr;
+    np = bf ? launch_gemm_bf16_nt(a, s->stream) : launch_gemm_f32_nn(a, s->stream);
+    tkind = bf ? 3 : 2;
+  }
   if (np < 0) return fail(NS_EHIP, "GEMM launch failed: %s", hipGetErrorString(hipGetLastError()));
   if (s->timing) {
     HIP_TRY(hipEventRecord(ee, s->stream));
     const double nn = (double)s->n;
-    s->timed.push_back(TimedLaunch{eb, ee, 1, 2.0 * nn * nn * nn});
+    s->timed.push_back(TimedLaunch{eb, ee, tkind, 2.0 * nn * nn * nn});
   }
   s->mmm += 1;
   if (want_norm) launch_reduce(s->partial, np, s->scal + 1, 2, 0.0, s->stream);
@@ -167,29 +211,39 @@ int read_scalars(ns_solver* s, double* host, int first, int count) {
   return NS_OK;
 }
 
-// G_next = G (I + C): GEMM, or (I + C) / alpha while G is still I / alpha.
-int apply_g(ns_solver* s, const double* Gcur, bool implicit, const double* C, double* Gnext) {
-  if (implicit) {
-    launch_scaled_identity_plus(C, s->ld, s->n, s->scal + 0, Gnext, s->ld, s->stream);
-    return NS_OK;
-  }
-  return gemm(s, Gnext, Gcur, C, Gcur, nullptr, 0.0, 1.0, false);
+// Dst = (I + C) / alpha (C may be null: Dst = I / alpha).
+void scaled_identity(ns_solver* s, const Mat* C, Mat& Dst) {
+  if (is_f64(s))
+    launch_scaled_identity_plus<double>(C ? C->d : nullptr, s->ld, s->n, s->scal + 0, Dst.d, s->ld,
+                                        s->stream);
+  else
+    launch_scaled_identity_plus<float>(C ? C->f : nullptr, s->ld, s->n, s->scal + 0, Dst.f, s->ld,
+                                       s->stream);
 }
 
-// C with P(Y) = I + C = (I + Y)(I + Y^2)...(I + Y^(2^(s-1))), order 2^s.
-// Uses P1/P2 for the powers and C1/C2 for the assembly; returns the buffer
-// holding C (Y itself for order 2).
-int poly_squaring(ns_solver* s, int order, const double* Y, const double** out) {
+// G_next = G (I + C): GEMM, or (I + C) / alpha while G is still I / alpha.
+int apply_g(ns_solver* s, const Mat& Gcur, bool implicit, const Mat& C, Mat& Gnext) {
+  if (implicit) {
+    scaled_identity(s, &C, Gnext);
+    return NS_OK;
+  }
+  return mm(s, Gnext, &Gcur, C, &Gcur, nullptr, 0.0, 1.0, false, K_APPLY);
+}
+
+// C with P(Y) = I + C = (I + Y)(I + Y^2)...(I + Y^(2^(s-1))), order 2^s
+// (Tables 1-2): powers into P0/P1, identity-offset assembly into C0/C1.
+// Returns the matrix holding C (Y itself for order 2).
+int poly_squaring(ns_solver* s, int order, const Mat& Y, const Mat** out) {
   int sexp = 0;
   while ((1 << sexp) < order) ++sexp;
-  const double* pw = Y;
-  const double* c = Y;
+  const Mat* pw = &Y;
+  const Mat* c = &Y;
   for (int i = 1; i < sexp; ++i) {
-    double* npw = (pw == s->P1) ? s->P2 : s->P1;
-    int rc = gemm(s, npw, pw, pw, nullptr, nullptr, 0.0, 1.0, false);       // Y^(2^i)
+    Mat* npw = (pw == &s->P[0]) ? &s->P[1] : &s->P[0];
+    int rc = mm(s, *npw, pw, *pw, nullptr, nullptr, 0.0, 1.0, false, K_POWER);  // Y^(2^i)
     if (rc) return rc;
-    double* nc = (c == s->C1) ? s->C2 : s->C1;
-    rc = gemm(s, nc, c, npw, c, npw, 0.0, 1.0, false);                      // C + Y^(2^i) + C Y^(2^i)
+    Mat* nc = (c == &s->C[0]) ? &s->C[1] : &s->C[0];
+    rc = mm(s, *nc, c, *npw, c, npw, 0.0, 1.0, false, K_POWER);  // C + Y^(2^i) + C Y^(2^i)
     if (rc) return rc;
     pw = npw;
     c = nc;
@@ -200,77 +254,72 @@ int poly_squaring(ns_solver* s, int order, const double* Y, const double** out) 
 
 bool is_pow2(int n) { return n >= 2 && (n & (n - 1)) == 0; }
 
-int resid_into(ns_solver* s, double* D, const double* X, bool want_norm) {
-  return gemm(s, D, s->A, X, nullptr, nullptr, 1.0, -1.0, want_norm);  // I - A X
+int resid_into(ns_solver* s, Mat& D, const Mat& X, bool want_norm) {
+  return mm(s, D, nullptr, X, nullptr, nullptr, 1.0, -1.0, want_norm, K_RESID);  // I - A X
 }
 
 // Classical step G_k = G_{k-1} P(F_{k-1}) for the non-composite forms;
 // leaves G in s->G[s->gcur].
 int step_classic(ns_solver* s, int order, int fact, int p, int w) {
-  double* Gc = s->G[s->gcur];
-  double* Gn = s->G[s->gcur ^ 1];
+  Mat& Gc = s->G[s->gcur];
+  Mat& Gn = s->G[s->gcur ^ 1];
   const bool impl = s->g_implicit;
   const double inv_alpha = 1.0 / s->alpha;
   int rc = NS_OK;
   if (fact == NS_FACT_SQUARING) {
-    const double* c = nullptr;
+    const Mat* c = nullptr;
     rc = poly_squaring(s, order, s->F, &c);
     if (rc) return rc;
-    rc = apply_g(s, Gc, impl, c, Gn);
+    rc = apply_g(s, Gc, impl, *c, Gn);
     if (rc) return rc;
   } else if (fact == NS_FACT_HORNER || fact == NS_FACT_UNIFIED || fact == NS_FACT_UNIFIED_PLUS1) {
     // Horner chain U_d = G + U_{d-1} F (eq. z1 / u1), d = 1..hd.
     int hd = order - 1;
-    if (fact == NS_FACT_UNIFIED) hd = p;
-    if (fact == NS_FACT_UNIFIED_PLUS1) hd = p;
+    if (fact == NS_FACT_UNIFIED || fact == NS_FACT_UNIFIED_PLUS1) hd = p;
     const bool plain = (fact == NS_FACT_HORNER) || (fact == NS_FACT_UNIFIED && w == 1);
-    double* bufs[2] = {s->C1, s->C2};
-    const double* u = Gc;  // U_0 = G (may be implicit)
+    Mat* bufs[2] = {&s->C[0], &s->C[1]};
+    const Mat* u = &Gc;  // U_0 = G (may be implicit)
     bool u_impl = impl;
     for (int d = 1; d <= hd; ++d) {
-      double* dst = (plain && d == hd) ? Gn : bufs[d & 1];
+      Mat* dst = (plain && d == hd) ? &Gn : bufs[d & 1];
       if (u_impl) {
-        launch_scaled_identity_plus(s->F, s->ld, s->n, s->scal + 0, dst, s->ld, s->stream);
+        scaled_identity(s, &s->F, *dst);
       } else {
-        rc = gemm(s, dst, u, s->F, impl ? nullptr : Gc, nullptr, impl ? inv_alpha : 0.0, 1.0,
-                  false);
+        rc = mm(s, *dst, u, s->F, impl ? nullptr : &Gc, nullptr, impl ? inv_alpha : 0.0, 1.0,
+                false, K_APPLY);
         if (rc) return rc;
       }
       u = dst;
       u_impl = false;
     }
-    if (plain) {
-      if (hd == 0) return fail(NS_EINVAL, "order too small");
-    } else {
+    if (!plain) {
       // Unified: Y^{p+1} = I - A U (eq. ua1), Z_i = Z_{i-1} Y^{p+1} + U (eq. zi1).
-      const double* uu = u;
-      bool uu_impl = u_impl;  // only when p == 0
-      if (uu_impl) {  // materialise U = G = I / alpha
-        launch_scaled_identity_plus(nullptr, s->ld, s->n, s->scal + 0, s->C1, s->ld, s->stream);
-        uu = s->C1;
+      const Mat* uu = u;
+      if (u_impl) {  // p == 0 with G = I / alpha: materialise U = G
+        scaled_identity(s, nullptr, s->C[0]);
+        uu = &s->C[0];
       }
-      const double* yp1 = s->F;
+      const Mat* yp1 = &s->F;
       if (p > 0 && w > 1) {
-        rc = resid_into(s, s->P1, uu, false);
+        rc = resid_into(s, s->P[0], *uu, false);
         if (rc) return rc;
-        yp1 = s->P1;
+        yp1 = &s->P[0];
       }
-      const double* z = uu;
+      const Mat* z = uu;
       const bool plus1 = (fact == NS_FACT_UNIFIED_PLUS1);
-      double* zb[2] = {s->P2, (uu == s->C1) ? s->C2 : s->C1};
+      Mat* zb[2] = {&s->P[1], (uu == &s->C[0]) ? &s->C[1] : &s->C[0]};
       for (int i = 1; i <= w - 1; ++i) {
-        double* dst = (!plus1 && i == w - 1) ? Gn : zb[i & 1];
-        rc = gemm(s, dst, z, yp1, uu, nullptr, 0.0, 1.0, false);
+        Mat* dst = (!plus1 && i == w - 1) ? &Gn : zb[i & 1];
+        rc = mm(s, *dst, z, *yp1, uu, nullptr, 0.0, 1.0, false, K_APPLY);
         if (rc) return rc;
         z = dst;
       }
       if (plus1) {
         // Z_1 = G + Z F (eq. ztab2).
-        if (impl) {
-          rc = gemm(s, Gn, z, s->F, nullptr, nullptr, inv_alpha, 1.0, false);
-        } else {
-          rc = gemm(s, Gn, z, s->F, Gc, nullptr, 0.0, 1.0, false);
-        }
+        if (impl)
+          rc = mm(s, Gn, z, s->F, nullptr, nullptr, inv_alpha, 1.0, false, K_APPLY);
+        else
+          rc = mm(s, Gn, z, s->F, &Gc, nullptr, 0.0, 1.0, false, K_APPLY);
         if (rc) return rc;
       }
     }
@@ -285,14 +334,14 @@ int step_classic(ns_solver* s, int order, int fact, int p, int w) {
 // Double Newton-Schulz step (Section 5.1, right orientation).
 int step_composite(ns_solver* s, int order) {
   int rc;
-  const double* c = nullptr;
+  const Mat* c = nullptr;
   if (!s->dns_started) {
     if (!s->g_implicit) return fail(NS_ESTATE, "composite form must start from G_0");
     // T_0 = G_0, Gamma_0 = F_0: L_0 = T_0 P(Gamma_0), Gamma_1 = I - A L_0.
     rc = poly_squaring(s, order, s->F, &c);
     if (rc) return rc;
     s->lcur = 0;
-    launch_scaled_identity_plus(c, s->ld, s->n, s->scal + 0, s->L[0], s->ld, s->stream);
+    scaled_identity(s, c, s->L[0]);
     rc = resid_into(s, s->Gam, s->L[0], false);
     if (rc) return rc;
     s->dns_started = true;
@@ -300,9 +349,9 @@ int step_composite(ns_solver* s, int order) {
   // L-loop: L_k = L_{k-1} P(Gamma_k) (lkk1), Gamma_k^n = I - A L_k (gamk21).
   rc = poly_squaring(s, order, s->Gam, &c);
   if (rc) return rc;
-  double* Lc = s->L[s->lcur];
-  double* Ln = s->L[s->lcur ^ 1];
-  rc = gemm(s, Ln, Lc, c, Lc, nullptr, 0.0, 1.0, false);
+  Mat& Lc = s->L[s->lcur];
+  Mat& Ln = s->L[s->lcur ^ 1];
+  rc = mm(s, Ln, &Lc, *c, &Lc, nullptr, 0.0, 1.0, false, K_APPLY);
   if (rc) return rc;
   s->lcur ^= 1;
   rc = resid_into(s, s->Gam, Ln, false);
@@ -310,15 +359,23 @@ int step_composite(ns_solver* s, int order) {
   // Ordinary loop: H = G_{k-1} P(F_{k-1}).
   rc = poly_squaring(s, order, s->F, &c);
   if (rc) return rc;
-  rc = apply_g(s, s->G[s->gcur], s->g_implicit, c, s->H);
+  rc = apply_g(s, s->G[s->gcur], s->g_implicit, *c, s->H);
   if (rc) return rc;
   // Merge: G_k = L_k + H Gamma_k^n (gkgen21); F_k = I - A G_k (fks1).
-  double* Gn = s->G[s->gcur ^ 1];
-  rc = gemm(s, Gn, s->H, s->Gam, Ln, nullptr, 0.0, 1.0, false);
+  Mat& Gn = s->G[s->gcur ^ 1];
+  rc = mm(s, Gn, &s->H, s->Gam, &Ln, nullptr, 0.0, 1.0, false, K_APPLY);
   if (rc) return rc;
   s->gcur ^= 1;
   s->g_implicit = false;
   return resid_into(s, s->F, Gn, true);
+}
+
+void gemv_update(ns_solver* s, double* theta) {
+  const Mat& G = s->G[s->gcur];
+  if (is_f64(s))
+    launch_gemv_update<double>(G.d, s->ld, s->n, s->r, theta, s->stream);
+  else
+    launch_gemv_update<float>(G.f, s->ld, s->n, s->r, theta, s->stream);
 }
 
 int check_solver(ns_solver* s) {
@@ -332,7 +389,7 @@ int richardson_once(ns_solver* s, const double* b, double* theta) {
   if (s->g_implicit) {
     launch_vec_scale(s->r, s->scal + 0, theta, s->n, 1, s->stream);
   } else {
-    launch_gemv_update(s->G[s->gcur], s->ld, s->n, s->r, theta, s->stream);
+    gemv_update(s, theta);
   }
   return NS_OK;
 }
@@ -390,8 +447,8 @@ const char* ns_status_string(int st) {
 
 size_t ns_workspace_bytes(int64_t n, int precision, int composite) {
   if (n < 1) return 0;
-  if (precision != NS_PREC_FP64) return 0;
-  return layout_bytes(n, composite ? 1 : 0);
+  if (precision < NS_PREC_FP64 || precision > NS_PREC_MIXED_BF16) return 0;
+  return layout_bytes(n, precision, composite ? 1 : 0);
 }
 
 int ns_create(int device, void* hip_stream, int64_t n, int precision, void* workspace,
@@ -399,13 +456,14 @@ int ns_create(int device, void* hip_stream, int64_t n, int precision, void* work
   if (!out) return fail(NS_EINVAL, "null out");
   *out = nullptr;
   if (n < 1) return fail(NS_EINVAL, "n must be >= 1");
-  if (precision != NS_PREC_FP64)
-    return fail(NS_EINVAL, "precision %d not available in this build", precision);
+  if (n > 65535) return fail(NS_EINVAL, "n must be <= 65535");
+  if (precision < NS_PREC_FP64 || precision > NS_PREC_MIXED_BF16)
+    return fail(NS_EINVAL, "unknown precision %d", precision);
   if (!workspace) return fail(NS_EINVAL, "null workspace");
   if ((reinterpret_cast<uintptr_t>(workspace) % kAlign) != 0)
     return fail(NS_EINVAL, "workspace must be 256-byte aligned");
-  const size_t need_plain = layout_bytes(n, 0);
-  const size_t need_comp = layout_bytes(n, 1);
+  const size_t need_plain = layout_bytes(n, precision, 0);
+  const size_t need_comp = layout_bytes(n, precision, 1);
   if (bytes < need_plain)
     return fail(NS_ENOMEM, "workspace too small: %zu < %zu bytes", bytes, need_plain);
   HIP_TRY(hipSetDevice(device));
@@ -419,29 +477,45 @@ int ns_create(int device, void* hip_stream, int64_t n, int precision, void* work
   s->composite_capable = bytes >= need_comp ? 1 : 0;
   s->ws = reinterpret_cast<char*>(workspace);
   s->ws_bytes = bytes;
-  const size_t mat = align_up((size_t)n * s->ld * sizeof(double), kAlign);
+  const size_t nn = (size_t)n * s->ld;
+  const size_t mat = align_up(nn * elem_bytes(precision), kAlign);
+  const size_t shadow = align_up(nn * 2, kAlign);
   char* p = s->ws;
   auto take = [&](size_t b) {
     char* q = p;
     p += b;
-    return reinterpret_cast<double*>(q);
+    return q;
   };
-  s->G[0] = take(mat);
-  s->G[1] = take(mat);
-  s->F = take(mat);
-  s->P1 = take(mat);
-  s->P2 = take(mat);
-  s->C1 = take(mat);
-  s->C2 = take(mat);
+  auto mat_of = [&](Mat& m, bool with_shadow) {
+    char* q = take(mat);
+    if (precision == NS_PREC_FP64)
+      m.d = reinterpret_cast<double*>(q);
+    else
+      m.f = reinterpret_cast<float*>(q);
+    if (with_shadow && precision == NS_PREC_MIXED_BF16) m.b = reinterpret_cast<uint16_t*>(take(shadow));
+  };
+  mat_of(s->G[0], false);
+  mat_of(s->G[1], false);
+  mat_of(s->F, true);
+  mat_of(s->P[0], true);
+  mat_of(s->P[1], true);
+  mat_of(s->C[0], true);
+  mat_of(s->C[1], true);
   if (s->composite_capable) {
-    s->L[0] = take(mat);
-    s->L[1] = take(mat);
-    s->Gam = take(mat);
-    s->H = take(mat);
+    mat_of(s->L[0], false);
+    mat_of(s->L[1], false);
+    mat_of(s->Gam, true);
+    mat_of(s->H, false);
   }
-  s->r = take(align_up((size_t)n * sizeof(double), kAlign));
-  s->partial = take(align_up((size_t)partial_capacity(n) * sizeof(double), kAlign));
-  s->scal = take(align_up(16 * sizeof(double), kAlign));
+  if (precision != NS_PREC_FP64) s->A32 = reinterpret_cast<float*>(take(align_up(nn * 4, kAlign)));
+  s->r = reinterpret_cast<double*>(take(align_up((size_t)n * sizeof(double), kAlign)));
+  s->partial =
+      reinterpret_cast<double*>(take(align_up((size_t)partial_capacity(n) * sizeof(double), kAlign)));
+  s->scal = reinterpret_cast<double*>(take(align_up(16 * sizeof(double), kAlign)));
+  if ((size_t)(p - s->ws) > bytes) {  // layout_bytes and this carving must agree
+    delete s;
+    return fail(NS_ENOMEM, "internal layout exceeds workspace");
+  }
   *out = s;
   return NS_OK;
 }
@@ -465,6 +539,11 @@ int ns_bind(ns_solver* s, const double* A, int64_t lda) {
   s->dns_started = false;
   s->gcur = 0;
   s->lcur = 0;
+  if (!is_f64(s)) {
+    HIP_TRY(hipSetDevice(s->device));
+    launch_convert<double, float>(A, lda, s->n, s->A32, s->ld, s->stream);
+    if (hipGetLastError() != hipSuccess) return fail(NS_EHIP, "kernel launch failed");
+  }
   return NS_OK;
 }
 
@@ -486,8 +565,13 @@ int ns_init_scale(ns_solver* s, int scale, double eps, double* alpha_out, double
   s->alpha = host[0];
   if (!(s->alpha > 0.0) || !isfinite(s->alpha))
     return fail(NS_ENOTSPD, "alpha = %g is not a positive finite number", s->alpha);
-  const int64_t np =
-      launch_init_resid(s->A, s->lda, s->n, s->scal + 0, s->F, s->ld, s->partial, s->stream);
+  int64_t np;
+  if (is_f64(s))
+    np = launch_init_resid<double>(s->A, s->lda, s->n, s->scal + 0, s->F.d, s->ld, nullptr,
+                                   s->partial, s->stream);
+  else
+    np = launch_init_resid<float>(s->A, s->lda, s->n, s->scal + 0, s->F.f, s->ld, s->F.b,
+                                  s->partial, s->stream);
   launch_reduce(s->partial, np, s->scal + 1, 2, 0.0, s->stream);
   s->scaled = true;
   s->g_implicit = true;
@@ -521,26 +605,33 @@ int ns_step(ns_solver* s, int order, int factorization, int p, int w, double* fn
   return NS_OK;
 }
 
+static int copy_out(ns_solver* s, const Mat& m, double* out, int64_t ldo) {
+  if (is_f64(s)) {
+    HIP_TRY(hipMemcpy2DAsync(out, ldo * sizeof(double), m.d, s->ld * sizeof(double),
+                             s->n * sizeof(double), s->n, hipMemcpyDeviceToDevice, s->stream));
+  } else {
+    launch_convert<float, double>(m.f, s->ld, s->n, out, ldo, s->stream);
+    if (hipGetLastError() != hipSuccess) return fail(NS_EHIP, "kernel launch failed");
+  }
+  return NS_OK;
+}
+
 int ns_get_G(ns_solver* s, double* G_out, int64_t ldg) {
   if (int rc = check_solver(s)) return rc;
   if (!G_out || ldg < s->n) return fail(NS_EINVAL, "bad G_out / ldg");
   if (!s->scaled) return fail(NS_ESTATE, "ns_init_scale first");
   if (s->g_implicit) {
-    launch_scaled_identity_plus(nullptr, 0, s->n, s->scal + 0, G_out, ldg, s->stream);
+    launch_scaled_identity_plus<double>(nullptr, 0, s->n, s->scal + 0, G_out, ldg, s->stream);
     return NS_OK;
   }
-  HIP_TRY(hipMemcpy2DAsync(G_out, ldg * sizeof(double), s->G[s->gcur], s->ld * sizeof(double),
-                           s->n * sizeof(double), s->n, hipMemcpyDeviceToDevice, s->stream));
-  return NS_OK;
+  return copy_out(s, s->G[s->gcur], G_out, ldg);
 }
 
 int ns_get_F(ns_solver* s, double* F_out, int64_t ldf) {
   if (int rc = check_solver(s)) return rc;
   if (!F_out || ldf < s->n) return fail(NS_EINVAL, "bad F_out / ldf");
   if (!s->scaled) return fail(NS_ESTATE, "ns_init_scale first");
-  HIP_TRY(hipMemcpy2DAsync(F_out, ldf * sizeof(double), s->F, s->ld * sizeof(double),
-                           s->n * sizeof(double), s->n, hipMemcpyDeviceToDevice, s->stream));
-  return NS_OK;
+  return copy_out(s, s->F, F_out, ldf);
 }
 
 int ns_richardson_step(ns_solver* s, const double* b, double* theta, double* rnorm_out) {
@@ -656,7 +747,10 @@ int richardson_ns_solve(ns_solver* s, const double* b, double* theta, const ns_s
         refine_stop = NS_STOP_REFINE_STALL;
         break;
       }
-      launch_gemv_update(s->G[s->gcur], s->ld, s->n, s->r, theta, s->stream);
+      if (s->g_implicit)
+        launch_vec_scale(s->r, s->scal + 0, theta, s->n, 1, s->stream);
+      else
+        gemv_update(s, theta);
       ++refine;
     }
     (void)hist0;
@@ -751,6 +845,69 @@ int ns_gemm_f64(void* hip_stream, int64_t m, int64_t n, int64_t k, const double*
   if (sumsq_out) launch_reduce(part, np, sumsq_out, 0, 0.0, st);
   if (hipGetLastError() != hipSuccess) return fail(NS_EHIP, "kernel launch failed");
   return NS_OK;
+}
+
+int64_t ns_gemm_lp_partials(int64_t m, int64_t n) {
+  if (m <= 0 || n <= 0) return 0;
+  return gemm_lp_partials(m, n);
+}
+
+static int gemm_lp_entry(bool bf16, void* hip_stream, int64_t m, int64_t n, int64_t k,
+                         const void* X, int64_t ldx, const void* Y, int64_t ldy, float* D,
+                         int64_t ldd, uint16_t* Db, int64_t lddb, const float* E1, int64_t lde1,
+                         const float* E2, int64_t lde2, float diag, float scale,
+                         double* sumsq_out) {
+  if (m < 0 || n < 0 || k < 0) return fail(NS_EINVAL, "negative size");
+  if (m == 0 || n == 0) return NS_OK;
+  if ((!D && !Db) || (k > 0 && (!X || !Y))) return fail(NS_EINVAL, "null operand");
+  const int64_t ycols = bf16 ? k : n;  // NT: Y is n x k
+  if (k > 0 && (ldx < k || ldy < ycols)) return fail(NS_EINVAL, "leading dimension too small");
+  if ((D && ldd < n) || (Db && lddb < n)) return fail(NS_EINVAL, "output leading dimension too small");
+  if ((E1 && lde1 < n) || (E2 && lde2 < n)) return fail(NS_EINVAL, "addend leading dimension too small");
+  if ((const void*)D == X || (const void*)D == Y || (const void*)Db == X || (const void*)Db == Y)
+    return fail(NS_EINVAL, "outputs must not alias X or Y");
+  hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
+  GemmLpArgs a{};
+  a.X = X;
+  a.Y = Y;
+  a.D = D;
+  a.Db = Db;
+  a.E1 = E1;
+  a.E2 = E2;
+  a.ldx = ldx;
+  a.ldy = ldy;
+  a.ldd = ldd;
+  a.lddb = lddb;
+  a.lde1 = lde1;
+  a.lde2 = lde2;
+  a.M = m;
+  a.N = n;
+  a.K = k;
+  a.diag = diag;
+  a.scale = scale;
+  double* part = sumsq_out ? sumsq_out + 1 : nullptr;
+  a.partial = part;
+  const int64_t np = bf16 ? launch_gemm_bf16_nt(a, st) : launch_gemm_f32_nn(a, st);
+  if (np < 0) return fail(NS_EHIP, "GEMM launch failed: %s", hipGetErrorString(hipGetLastError()));
+  if (sumsq_out) launch_reduce(part, np, sumsq_out, 0, 0.0, st);
+  if (hipGetLastError() != hipSuccess) return fail(NS_EHIP, "kernel launch failed");
+  return NS_OK;
+}
+
+int ns_gemm_f32(void* hip_stream, int64_t m, int64_t n, int64_t k, const float* X, int64_t ldx,
+                const float* Y, int64_t ldy, float* D, int64_t ldd, uint16_t* Db, int64_t lddb,
+                const float* E1, int64_t lde1, const float* E2, int64_t lde2, float diag,
+                float scale, double* sumsq_out) {
+  return gemm_lp_entry(false, hip_stream, m, n, k, X, ldx, Y, ldy, D, ldd, Db, lddb, E1, lde1, E2,
+                       lde2, diag, scale, sumsq_out);
+}
+
+int ns_gemm_bf16_nt(void* hip_stream, int64_t m, int64_t n, int64_t k, const uint16_t* X,
+                    int64_t ldx, const uint16_t* Y, int64_t ldy, float* D, int64_t ldd,
+                    uint16_t* Db, int64_t lddb, const float* E1, int64_t lde1, const float* E2,
+                    int64_t lde2, float diag, float scale, double* sumsq_out) {
+  return gemm_lp_entry(true, hip_stream, m, n, k, X, ldx, Y, ldy, D, ldd, Db, lddb, E1, lde1, E2,
+                       lde2, diag, scale, sumsq_out);
 }
 
 }  // extern "C"

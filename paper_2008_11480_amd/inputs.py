@@ -80,6 +80,28 @@ def spd_qlq(n: int, kappa: float, seed: int, with_eig: bool = True) -> SPDSystem
                      seed=seed, kappa=float(kappa))
 
 
+def spd_qlq_device(n: int, kappa: float, seed: int, device="cuda"):
+    """The ``spd_qlq`` recipe with the QR and the product done by torch on
+    ``device`` (for large N): the same PCG64 draws (Gaussian, spectrum, b) in
+    the same order, Q sign-fixed by ``sign(diag R)``.  Q differs from
+    ``spd_qlq``'s only by the QR implementation's rounding.  Returns torch
+    tensors ``(A, b, lam, Q)`` on ``device`` (float64)."""
+    import torch
+    rng = np.random.default_rng(seed)
+    z = rng.standard_normal((n, n))
+    lam = loguniform_spectrum(n, kappa, rng)
+    b = rng.standard_normal(n)
+    zt = torch.from_numpy(z).to(device)
+    q, r = torch.linalg.qr(zt)
+    d = torch.sign(torch.diagonal(r))
+    d[d == 0] = 1.0
+    q = q * d[None, :]
+    lt = torch.from_numpy(lam).to(device)
+    a = (q * lt[None, :]) @ q.T.contiguous()
+    a = 0.5 * (a + a.T)
+    return a.contiguous(), torch.from_numpy(b).to(device), lt, q.contiguous()
+
+
 def spd_diag(lam: np.ndarray, seed: int) -> SPDSystem:
     """Diagonal SPD system with the given spectrum and ``b ~ N(0,1)``."""
     rng = np.random.default_rng(seed)

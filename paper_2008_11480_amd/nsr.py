@@ -37,6 +37,7 @@ EXPORTS = (
     "ns_workspace_bytes", "ns_create", "ns_destroy", "ns_bind", "ns_init_scale", "ns_step",
     "ns_get_G", "ns_get_F", "ns_richardson_step", "richardson_ns_solve", "ns_timing_enable",
     "ns_timing_read", "ns_timing_reset", "ns_gemm_f64", "ns_gemm_f64_partials",
+    "ns_gemm_f32", "ns_gemm_bf16_nt", "ns_gemm_lp_partials",
     "ns_status_string", "ns_last_error", "ns_version",
 )
 
@@ -111,6 +112,11 @@ def lib() -> ctypes.CDLL:
         "ns_gemm_f64": (ci, [vp, i64, i64, i64, vp, i64, vp, i64, vp, i64, vp, i64, vp, i64,
                              dbl, dbl, vp]),
         "ns_gemm_f64_partials": (i64, [i64, i64]),
+        "ns_gemm_f32": (ci, [vp, i64, i64, i64, vp, i64, vp, i64, vp, i64, vp, i64, vp, i64, vp,
+                             i64, ctypes.c_float, ctypes.c_float, vp]),
+        "ns_gemm_bf16_nt": (ci, [vp, i64, i64, i64, vp, i64, vp, i64, vp, i64, vp, i64, vp, i64,
+                                 vp, i64, ctypes.c_float, ctypes.c_float, vp]),
+        "ns_gemm_lp_partials": (i64, [i64, i64]),
         "ns_status_string": (ctypes.c_char_p, [ci]),
         "ns_last_error": (ctypes.c_char_p, []),
         "ns_version": (ctypes.c_char_p, []),
@@ -287,6 +293,37 @@ def gemm_f64(X, Y, D=None, E1=None, E2=None, diag: float = 0.0, scale: float = 1
                             E2.stride(0) if E2 is not None else 0, float(diag), float(scale),
                             _ptr(ss)))
     return (D, ss[0]) if want_sumsq else D
+
+
+def gemm_lp(X, Y, nt: bool, D=None, want_bf16: bool = False, E1=None, E2=None,
+            diag: float = 0.0, scale: float = 1.0, want_sumsq: bool = False, stream=None):
+    """float32 NN (``nt=False``: D = X Y) or bf16 NT (``nt=True``: D = X Y^T)
+    MFMA GEMM with the fused epilogue.  Returns (D, Db or None, sumsq or None)."""
+    import torch
+    want_dtype = torch.bfloat16 if nt else torch.float32
+    for t, nm in ((X, "X"), (Y, "Y")):
+        if not t.is_cuda or t.dtype != want_dtype or t.stride(-1) != 1:
+            raise TypeError(f"{nm} must be a row-major {want_dtype} CUDA tensor")
+    m, k = X.shape
+    n = Y.shape[0] if nt else Y.shape[1]
+    if (Y.shape[1] if nt else Y.shape[0]) != k:
+        raise ValueError("inner dimensions differ")
+    for t in (E1, E2):
+        if t is not None and (t.dtype != torch.float32 or not t.is_cuda):
+            raise TypeError("addends must be float32 CUDA tensors")
+    if D is None:
+        D = torch.empty(m, n, dtype=torch.float32, device=X.device)
+    Db = torch.empty(m, n, dtype=torch.bfloat16, device=X.device) if want_bf16 else None
+    ss = None
+    if want_sumsq:
+        ss = torch.zeros(1 + int(lib().ns_gemm_lp_partials(m, n)), dtype=torch.float64,
+                         device=X.device)
+    fn = lib().ns_gemm_bf16_nt if nt else lib().ns_gemm_f32
+    check(fn(_stream_handle(stream), m, n, k, _ptr(X), X.stride(0), _ptr(Y), Y.stride(0),
+             _ptr(D), D.stride(0), _ptr(Db), Db.stride(0) if Db is not None else 0,
+             _ptr(E1), E1.stride(0) if E1 is not None else 0, _ptr(E2),
+             E2.stride(0) if E2 is not None else 0, float(diag), float(scale), _ptr(ss)))
+    return D, Db, (ss[0] if ss is not None else None)
 
 
 def exported_symbols() -> list[str]:
