@@ -198,6 +198,64 @@ typedef struct {
 int richardson_ns_solve(ns_solver* s, const double* b, double* theta,
                         const ns_solve_opts* opts, ns_solve_report* report);
 
+/* ---- Batched solves of many independent systems (uneven sizes) ----------
+ *
+ * One submission solves `count` independent SPD systems in ONE persistent
+ * kernel launch: each workgroup pulls whole systems (largest n first) and
+ * runs the complete coupled solve of richardson_ns_solve for each (squaring
+ * form of order opts->order, scale ||A||_F, theta_0 = b / alpha).  Products
+ * run in float32 MFMA for NS_PREC_FP32, and a system whose float32 solve does
+ * not reach opts->resid_tol is re-solved in float64 MFMA by the same
+ * workgroup (report.precision tells which); NS_PREC_FP64 uses float64 only.
+ * Richardson residuals and theta are float64 throughout. */
+typedef struct ns_batch ns_batch;
+
+/* Device workspace for up to `max_count` systems of size <= max_n, solved by
+ * up to `slots` concurrent workgroups (each owns one slot of iterate
+ * buffers).  Returns 0 for invalid arguments. */
+size_t ns_batch_workspace_bytes(int64_t max_n, int max_count, int slots);
+
+/* Create a batch handle.  precision: NS_PREC_FP32 (with float64 escalation)
+ * or NS_PREC_FP64.  max_n <= 4096.  workspace: caller-owned device buffer of
+ * >= ns_batch_workspace_bytes(max_n, max_count, slots) bytes, 256-B aligned.
+ * Errors: NS_EINVAL, NS_ENOMEM (workspace too small), NS_EHIP. */
+int ns_batch_create(int device, void* hip_stream, int64_t max_n, int max_count,
+                    int slots, int precision, void* workspace, size_t bytes,
+                    ns_batch** out);
+
+/* Launch shape: waves per workgroup (1, 2 or 4) and number of workgroups
+ * (0: one per slot).  Set by ns_batch_autotune or by the caller. */
+int ns_batch_set_launch(ns_batch* b, int waves_per_group, int groups);
+
+/* Enqueue the solves of `count` systems.  n, A, lda, b, theta are HOST arrays
+ * of length count holding each system's size and DEVICE pointers (A: row-major
+ * float64 n x n, lda >= n; b, theta: float64 n).  The caller keeps A, b,
+ * theta alive and unmodified (theta: untouched) until ns_batch_poll reports
+ * completion.  One submission may be in flight per handle.  Errors:
+ * NS_EBUSY (previous ticket not polled to completion), NS_ENOMEM (count >
+ * max_count or a system larger than max_n: the admission check), NS_EINVAL
+ * (options other than the squaring form, Frobenius scale, theta0_mode 0). */
+int ns_batch_submit(ns_batch* b, int count, const int64_t* n, const double* const* A,
+                    const int64_t* lda, const double* const* b_vec,
+                    double* const* theta, const ns_solve_opts* opts, uint64_t* ticket);
+
+/* Completion of a ticket.  wait = 0: returns NS_EBUSY if the kernel has not
+ * finished; wait != 0: blocks.  On completion fills reports[0..count) (host
+ * array, may be NULL; fnorm_hist only, no resid_hist) and returns NS_OK if
+ * every system reached resid_tol, else NS_ENOCONV (see each report.status). */
+int ns_batch_poll(ns_batch* b, uint64_t ticket, int wait, ns_solve_report* reports);
+
+/* Project autotuner: time every launch shape (1, 2, 4 waves per workgroup x
+ * 1, 2, 4, 8 workgroups per CU, within the slots) on the given batch (each
+ * candidate solves it completely, synchronously), keep the fastest with
+ * ns_batch_set_launch and return it.  Same arguments as ns_batch_submit. */
+int ns_batch_autotune(ns_batch* b, int count, const int64_t* n, const double* const* A,
+                      const int64_t* lda, const double* const* b_vec,
+                      double* const* theta, const ns_solve_opts* opts,
+                      int* best_waves, int* best_groups, double* best_ms);
+
+int ns_batch_destroy(ns_batch* b);
+
 /* Per-kernel timing with HIP events on the solver's stream.  While enabled,
  * every GEMM launch is bracketed by an event pair.  ns_timing_read returns
  * the number of timed GEMM launches, their summed duration (ms) and their

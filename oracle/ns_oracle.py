@@ -34,7 +34,7 @@ __all__ = [
     "residual", "z_horner", "z_unified", "z_unified_plus1", "z_squaring",
     "z_table", "TABLE_ORDERS", "z_form", "form_mmm", "ns_step",
     "dns_init", "dns_step", "richardson_update", "SolveOptions", "SolveReport",
-    "solve", "stop_check", "STOP", "efficiency_index",
+    "solve", "stop_check", "floor_probe_needed", "STOP", "efficiency_index",
 ]
 
 
@@ -313,14 +313,19 @@ STOP = {
 }
 
 
-def stop_check(fhist, f_tol, k, k_max, floor_detect=True):
+def stop_check(fhist, f_tol, k, k_max, floor_detect=True, f_sq=None):
     """Stop rule for the Newton-Schulz phase; the paper gives none.
 
-    ``fhist[j] = ||F_j||_F`` for ``j = 0..k``.  Stop when
+    ``fhist[j] = ||F_j||_F`` for ``j = 0..k``; ``f_sq = ||F_k^2||_F`` (needed
+    only when ``||F_k|| > ||F_{k-1}|| / 2``).  Stop when
     (i) ``||F_k|| <= f_tol``;
-    (ii) the rounding floor is reached: some earlier ratio
-    ``||F_j|| / ||F_{j-1}||`` was below 1/2 (the iteration had entered its
-    fast regime) and now the ratio is above 1/2;
+    (ii) the rounding floor is reached.  In exact arithmetic
+    ``F_k = F_{k-1}^n`` gives ``||F_k|| / ||F_{k-1}|| <= ||F_k||_2^{(n-1)/n}``.
+    ``s = ||F_k^2||_F / ||F_k||_F`` estimates ``||F_k||_2`` (it is a lower
+    bound that is close whenever the dominant eigenvalues carry the
+    Frobenius sum).  A ratio above 1/2 together with ``s <= 1/4`` contradicts
+    exact arithmetic, so rounding dominates: floor.  A ratio above 1/2 with
+    ``s`` near 1 is a slow mode that is still converging: continue;
     (iii) ``k = k_max``;
     (iv) divergence: a non-finite norm or ``||F_k|| > ||F_0||``.
     Returns the reason name or ``None``.
@@ -330,13 +335,19 @@ def stop_check(fhist, f_tol, k, k_max, floor_detect=True):
         return "diverged"
     if fk <= f_tol:
         return "f_tol"
-    if floor_detect and k >= 2:
-        entered = any(fhist[j] < 0.5 * fhist[j - 1] for j in range(1, k))
-        if entered and fk > 0.5 * fhist[k - 1]:
+    if floor_detect and k >= 1 and fk > 0.5 * fhist[k - 1]:
+        if f_sq is None:
+            raise ValueError("||F_k^2|| is needed to test the floor")
+        if f_sq <= 0.25 * fk:
             return "floor"
     if k >= k_max:
         return "k_max"
     return None
+
+
+def floor_probe_needed(fhist, k, floor_detect=True):
+    """True when :func:`stop_check` needs ``||F_k^2||``."""
+    return floor_detect and k >= 1 and math.isfinite(fhist[k]) and fhist[k] > 0.5 * fhist[k - 1]
 
 
 @dataclasses.dataclass
@@ -378,8 +389,9 @@ def solve(a, b, opts: SolveOptions = SolveOptions()) -> SolveReport:
        and ``theta_0 = G_0 b``.
     2. Step ``k``: ``G_k`` from eq. (ns) (or eqs. (gamk11)-(fks1) for the
        composite form), then the Richardson update with the new ``G_k``
-       (eq. redttk1 with ``omega_k = G_k``), then ``F_k = I - A G_k`` and the
-       stop rule of :func:`stop_check`.
+       (eq. redttk1 with ``omega_k = G_k``; its residual ``b - A theta_{k-1}``
+       is recorded), then ``F_k = I - A G_k`` and the stop rule of
+       :func:`stop_check`.
     3. Refinement-only Richardson steps with the final ``G`` until
        ``||b - A theta|| / ||b|| <= resid_tol``, ``refine_max`` steps, or a
        stall (less than a factor 2 of progress over 3 steps).
@@ -422,7 +434,10 @@ def solve(a, b, opts: SolveOptions = SolveOptions()) -> SolveReport:
             f = residual(a, g, ctr)          # also the next step's residual
         rhist.append(float(np.linalg.norm(r)) / bnorm)
         fhist.append(float(np.linalg.norm(f)))
-        ns_stop = stop_check(fhist, opts.f_tol, k, opts.k_max, opts.floor_detect)
+        f_sq = None
+        if floor_probe_needed(fhist, k, opts.floor_detect):
+            f_sq = float(np.linalg.norm(_mm(ctr, f, f)))
+        ns_stop = stop_check(fhist, opts.f_tol, k, opts.k_max, opts.floor_detect, f_sq)
 
     refine = 0
     rel = float("nan")

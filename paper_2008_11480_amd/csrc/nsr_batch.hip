@@ -1,0 +1,794 @@
+// Batched solves of many independent SPD systems of uneven size in one
+// persistent launch.
+//
+// Each workgroup pulls whole systems from a device counter (systems are
+// pre-sorted by decreasing n^3, so the largest start first) and runs the
+// complete coupled solve of one system inside the workgroup: the scalar
+// preconditioner (Section 2), Newton-Schulz steps of order 2^s in the
+// factorized form (I+F)(I+F^2)... (eq. ns, Tables 1-2), the coupled
+// Richardson update (eq. redttk1), the stop rule and float64 refinement.  The
+// products run in float32 MFMA (v_mfma_f32_16x16x4_f32); a system whose
+// float32 solve cannot reach the tolerance is re-solved in float64 MFMA
+// (v_mfma_f64_16x16x4_f64) by the same workgroup.  Workgroups never wait for
+// each other: a workgroup exits when the counter has passed the batch size.
+//
+// Matrices live in the workgroup's slot of the workspace (row-major, leading
+// dimension ldw); products are tiled over 32 x 32 output tiles, one wave per
+// tile, with operands read through the cache hierarchy.
+#include <math.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <new>
+#include <vector>
+
+#include "../../include/nsr.h"
+#include "nsr_internal.h"
+
+namespace nsr {
+
+struct BatchDesc {
+  const double* A;
+  const double* b;
+  double* theta;
+  int64_t lda;
+  int32_t n;
+  int32_t pad;
+};
+
+struct BatchResult {
+  int32_t status, ns_stop, refine_stop, ns_steps, refine_steps, precision, n_fnorm, n_resid;
+  double alpha, rel_resid;
+  int64_t mmm;
+  double fnorm_hist[NS_HIST_F];
+};
+
+struct BatchArgs {
+  const BatchDesc* desc;
+  BatchResult* res;
+  const int32_t* order;   // processing order (indices into desc)
+  int32_t* counter;       // work counter, zeroed before the launch
+  char* slots;
+  int64_t slot_bytes;
+  int32_t count;
+  int32_t ldw;            // slot leading dimension (>= max n, multiple of 4)
+  int32_t ns_order;       // 2^s
+  int32_t k_max;
+  int32_t refine_max;
+  int32_t floor_detect;
+  int32_t escalate;       // 1: float32 first, float64 when it fails
+  int32_t fp64_only;      // 1: float64 from the start
+  double f_tol;
+  double resid_tol;
+};
+
+namespace {
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ double wsum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// Sum over the workgroup, same value returned to every thread.
+template <int NW>
+__device__ __forceinline__ double block_sum_all(double v, double* red) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  v = wsum(v);
+  if (lane == 0) red[wave] = v;
+  __syncthreads();
+  double s = 0.0;
+#pragma unroll
+  for (int w = 0; w < NW; ++w) s += red[w];
+  __syncthreads();
+  return s;
+}
+
+__device__ __forceinline__ f32x4 mfma(float a, float b, f32x4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ f64x4 mfma(double a, double b, f64x4 c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+template <typename T> struct Acc;
+template <> struct Acc<float> { typedef f32x4 type; };
+template <> struct Acc<double> { typedef f64x4 type; };
+
+// Row of accumulator element r of lane group lk (lane / 16) in a 16x16 block:
+// float32: 4 lk + r; float64: lk + 4 r (gfx950 layouts).
+__device__ __forceinline__ int acc_row(float, int lk, int r) { return 4 * lk + r; }
+__device__ __forceinline__ int acc_row(double, int lk, int r) { return lk + 4 * r; }
+
+// D = diag I + scale X Y + E1 + E2 (n x n); returns sum D^2 over the
+// workgroup when want_ss (uniform).  XA: X is the float64 input A (read
+// through lda and converted), otherwise X is T with leading dimension ldx.
+template <typename T, int NW>
+__device__ double wg_gemm(int n, const T* X, int ldx, const double* XA, int64_t lda, const T* Y,
+                          int ldy, T* D, int ldd, const T* E1, const T* E2, int lde, T diag,
+                          T scale, bool want_ss, double* red) {
+  typedef typename Acc<T>::type acc_t;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int lr = lane & 15, lk = lane >> 4;
+  const int nt = (n + 31) / 32;
+  double ss = 0.0;
+  for (int t = wave; t < nt * nt; t += NW) {
+    const int r0 = (t / nt) * 32, c0 = (t % nt) * 32;
+    acc_t acc[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j) acc[i][j] = acc_t{0, 0, 0, 0};
+    const int xr0 = r0 + lr, xr1 = r0 + 16 + lr;
+    const int yc0 = c0 + lr, yc1 = c0 + 16 + lr;
+    for (int k = 0; k < n; k += 4) {
+      const int kk = k + lk;
+      T a0 = 0, a1 = 0, b0 = 0, b1 = 0;
+      if (kk < n) {
+        if (XA) {
+          if (xr0 < n) a0 = (T)XA[(int64_t)xr0 * lda + kk];
+          if (xr1 < n) a1 = (T)XA[(int64_t)xr1 * lda + kk];
+        } else {
+          if (xr0 < n) a0 = X[xr0 * ldx + kk];
+          if (xr1 < n) a1 = X[xr1 * ldx + kk];
+        }
+        if (yc0 < n) b0 = Y[kk * ldy + yc0];
+        if (yc1 < n) b1 = Y[kk * ldy + yc1];
+      }
+      acc[0][0] = mfma(a0, b0, acc[0][0]);
+      acc[0][1] = mfma(a0, b1, acc[0][1]);
+      acc[1][0] = mfma(a1, b0, acc[1][0]);
+      acc[1][1] = mfma(a1, b1, acc[1][1]);
+    }
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        const int col = c0 + 16 * j + lr;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int row = r0 + 16 * i + acc_row(T(0), lk, r);
+          if (row < n && col < n) {
+            T v = scale * acc[i][j][r];
+            if (row == col) v += diag;
+            if (E1) v += E1[row * lde + col];
+            if (E2) v += E2[row * lde + col];
+            D[row * ldd + col] = v;
+            ss += (double)v * (double)v;
+          }
+        }
+      }
+  }
+  __syncthreads();  // D complete for every wave of the workgroup
+  if (!want_ss) return 0.0;
+  return block_sum_all<NW>(ss, red);
+}
+
+// Elementwise over the n x n slot matrices, all threads.
+template <typename T, int NW>
+__device__ double wg_init_resid(int n, const double* A, int64_t lda, double alpha, T* F, int ldw,
+                                double* red) {
+  double ss = 0.0;
+  for (int i = threadIdx.x; i < n * n; i += NW * 64) {
+    const int row = i / n, col = i % n;
+    double v = -A[(int64_t)row * lda + col] / alpha;
+    if (row == col) v += 1.0;
+    const T t = (T)v;
+    F[row * ldw + col] = t;
+    ss += (double)t * (double)t;
+  }
+  __syncthreads();
+  return block_sum_all<NW>(ss, red);
+}
+
+template <typename T, int NW>
+__device__ void wg_scaled_identity_plus(int n, const T* C, double alpha, T* G, int ldw) {
+  for (int i = threadIdx.x; i < n * n; i += NW * 64) {
+    const int row = i / n, col = i % n;
+    double v = (double)C[row * ldw + col];
+    if (row == col) v += 1.0;
+    G[row * ldw + col] = (T)(v / alpha);
+  }
+  __syncthreads();
+}
+
+// r = b - A theta (float64), returns ||r||^2 (uniform).
+template <int NW>
+__device__ double wg_resid(int n, const double* A, int64_t lda, const double* b,
+                           const double* theta, double* r, double* red) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  double ss = 0.0;
+  for (int row = wave; row < n; row += NW) {
+    double s = 0.0;
+    for (int c = lane; c < n; c += 64) s += A[(int64_t)row * lda + c] * theta[c];
+    s = wsum(s);
+    const double rv = b[row] - s;
+    if (lane == 0) {
+      r[row] = rv;
+      ss += rv * rv;
+    }
+  }
+  __syncthreads();
+  return block_sum_all<NW>(ss, red);
+}
+
+// theta += G r (G of type T, or G = I / alpha when implicit).
+template <typename T, int NW>
+__device__ void wg_update(int n, const T* G, int ldw, bool implicit, double alpha, const double* r,
+                          double* theta) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (int row = wave; row < n; row += NW) {
+    double s = 0.0;
+    if (implicit) {
+      s = (lane == 0) ? r[row] / alpha : 0.0;
+    } else {
+      for (int c = lane; c < n; c += 64) s += (double)G[row * ldw + c] * r[c];
+    }
+    s = wsum(s);
+    if (lane == 0) theta[row] += s;
+  }
+  __syncthreads();
+}
+
+struct SlotMats {
+  void* G[2];
+  void* F;
+  void* P[2];
+  void* C[2];
+  float* A32;
+  double* r;
+};
+
+// Control values of one solve.  Every thread holds the same values (they are
+// computed from workgroup-wide sums); only thread 0 writes the history.
+struct Ctl {
+  double alpha, rel_resid;
+  int64_t mmm;
+  int ns_steps, ns_stop, refine_steps, refine_stop, n_fnorm, precision;
+};
+
+// One complete solve of system d in precision T.  Returns true when the
+// refinement reached resid_tol.  hist: LDS history of ||F_k||_F (thread 0
+// writes).
+template <typename T, int NW>
+__device__ bool wg_solve(const BatchArgs& P, const BatchDesc& d, const SlotMats& sm, double* red,
+                         double* hist, Ctl& c) {
+  const int n = d.n, ldw = P.ldw;
+  T* G[2] = {(T*)sm.G[0], (T*)sm.G[1]};
+  T* F = (T*)sm.F;
+  T* Pw[2] = {(T*)sm.P[0], (T*)sm.P[1]};
+  T* Cc[2] = {(T*)sm.C[0], (T*)sm.C[1]};
+  const bool is32 = sizeof(T) == 4;
+  c.precision = is32 ? NS_PREC_FP32 : NS_PREC_FP64;
+  c.mmm = 0;
+  c.n_fnorm = 0;
+  c.ns_steps = 0;
+  c.refine_steps = 0;
+  c.rel_resid = NAN;
+  // alpha = ||A||_F (Section 2, S = alpha I)
+  double ssa = 0.0;
+  for (int i = threadIdx.x; i < n * n; i += NW * 64) {
+    const double v = d.A[(int64_t)(i / n) * d.lda + (i % n)];
+    ssa += v * v;
+  }
+  const double alpha = sqrt(block_sum_all<NW>(ssa, red));
+  c.alpha = alpha;
+  if (!(alpha > 0.0) || !isfinite(alpha)) {
+    c.ns_stop = NS_STOP_DIVERGED;
+    c.refine_stop = NS_STOP_DIVERGED;
+    return false;
+  }
+  if (is32) {  // float32 copy of A for the residual products
+    for (int i = threadIdx.x; i < n * n; i += NW * 64)
+      sm.A32[(i / n) * ldw + (i % n)] = (float)d.A[(int64_t)(i / n) * d.lda + (i % n)];
+    __syncthreads();
+  }
+  const T* AX = is32 ? (const T*)sm.A32 : nullptr;
+  const double* AXd = is32 ? nullptr : d.A;
+  // F_0 = I - A / alpha, theta_0 = b / alpha, ||b||
+  const double f0 = sqrt(wg_init_resid<T, NW>(n, d.A, d.lda, alpha, F, ldw, red));
+  double bb = 0.0;
+  for (int i = threadIdx.x; i < n; i += NW * 64) {
+    d.theta[i] = d.b[i] / alpha;
+    bb += d.b[i] * d.b[i];
+  }
+  double bnorm = sqrt(block_sum_all<NW>(bb, red));
+  if (bnorm == 0.0) bnorm = 1.0;
+  if (threadIdx.x == 0) hist[0] = f0;
+  c.n_fnorm = 1;
+  int sexp = 0;
+  while ((1 << sexp) < P.ns_order) ++sexp;
+  bool implicit = true;
+  int gc = 0;
+  int ns_stop = isfinite(f0) ? NS_STOP_NONE : NS_STOP_DIVERGED;
+  bool f2_ready = false;  // Pw[0] holds F_k^2 from the floor test
+  double fprev = f0;
+  int k = 0;
+  while (ns_stop == NS_STOP_NONE) {
+    ++k;
+    // C with P(F) = I + C (identity-offset squaring form).
+    const T* pw = F;
+    const T* cc = F;
+    for (int i = 1; i < sexp; ++i) {
+      T* npw = (pw == Pw[0]) ? Pw[1] : Pw[0];
+      if (!(i == 1 && f2_ready)) {
+        wg_gemm<T, NW>(n, pw, ldw, nullptr, 0, pw, ldw, npw, ldw, nullptr, nullptr, ldw, T(0),
+                       T(1), false, red);
+        c.mmm += 1;
+      }
+      T* nc = (cc == Cc[0]) ? Cc[1] : Cc[0];
+      wg_gemm<T, NW>(n, cc, ldw, nullptr, 0, npw, ldw, nc, ldw, cc, npw, ldw, T(0), T(1), false,
+                     red);
+      c.mmm += 1;
+      pw = npw;
+      cc = nc;
+    }
+    T* Gn = G[gc ^ 1];
+    if (implicit) {
+      wg_scaled_identity_plus<T, NW>(n, cc, alpha, Gn, ldw);
+    } else {
+      wg_gemm<T, NW>(n, G[gc], ldw, nullptr, 0, cc, ldw, Gn, ldw, G[gc], nullptr, ldw, T(0), T(1),
+                     false, red);
+      c.mmm += 1;
+    }
+    gc ^= 1;
+    implicit = false;
+    // Richardson with G_k (eq. redttk1)
+    wg_resid<NW>(n, d.A, d.lda, d.b, d.theta, sm.r, red);
+    wg_update<T, NW>(n, G[gc], ldw, false, alpha, sm.r, d.theta);
+    // F_k = I - A G_k
+    const double fk =
+        sqrt(wg_gemm<T, NW>(n, AX, ldw, AXd, d.lda, G[gc], ldw, F, ldw, nullptr, nullptr, ldw,
+                            T(1), T(-1), true, red));
+    c.mmm += 1;
+    if (threadIdx.x == 0 && k < NS_HIST_F) hist[k] = fk;
+    c.n_fnorm = (k + 1 < NS_HIST_F) ? k + 1 : NS_HIST_F;
+    // Stop rule: divergence, tolerance, rounding floor (||F_k|| > ||F_{k-1}||/2
+    // although ||F_k^2|| <= ||F_k|| / 4, impossible in exact arithmetic), k_max.
+    f2_ready = false;
+    if (!isfinite(fk) || fk > f0) {
+      ns_stop = NS_STOP_DIVERGED;
+    } else if (fk <= P.f_tol) {
+      ns_stop = NS_STOP_F_TOL;
+    } else {
+      if (P.floor_detect && fk > 0.5 * fprev) {
+        const double f2 = sqrt(wg_gemm<T, NW>(n, F, ldw, nullptr, 0, F, ldw, Pw[0], ldw, nullptr,
+                                              nullptr, ldw, T(0), T(1), true, red));
+        c.mmm += 1;
+        f2_ready = true;
+        if (f2 <= 0.25 * fk) ns_stop = NS_STOP_FLOOR;
+      }
+      if (ns_stop == NS_STOP_NONE && k >= P.k_max) ns_stop = NS_STOP_K_MAX;
+    }
+    fprev = fk;
+  }
+  c.ns_steps = k;
+  c.ns_stop = ns_stop;
+  if (ns_stop == NS_STOP_DIVERGED) {
+    c.refine_stop = NS_STOP_DIVERGED;
+    return false;
+  }
+  double last[4] = {0, 0, 0, 0};
+  int refine = 0;
+  while (true) {
+    const double rel = sqrt(wg_resid<NW>(n, d.A, d.lda, d.b, d.theta, sm.r, red)) / bnorm;
+    c.rel_resid = rel;
+    for (int j = 3; j > 0; --j) last[j] = last[j - 1];
+    last[0] = rel;
+    if (!isfinite(rel)) {
+      c.refine_stop = NS_STOP_DIVERGED;
+      break;
+    }
+    if (rel <= P.resid_tol) {
+      c.refine_stop = NS_STOP_RESID_TOL;
+      break;
+    }
+    if (refine >= P.refine_max) {
+      c.refine_stop = NS_STOP_REFINE_MAX;
+      break;
+    }
+    if (refine >= 3 && rel > 0.5 * last[3]) {
+      c.refine_stop = NS_STOP_REFINE_STALL;
+      break;
+    }
+    wg_update<T, NW>(n, G[gc], ldw, false, alpha, sm.r, d.theta);
+    ++refine;
+  }
+  c.refine_steps = refine;
+  return c.refine_stop == NS_STOP_RESID_TOL;
+}
+
+template <int NW>
+__global__ void __launch_bounds__(NW * 64) batch_kernel(BatchArgs P) {
+  __shared__ double red[NW];
+  __shared__ double hist[NS_HIST_F];
+  __shared__ int s_idx;
+  char* slot = P.slots + (int64_t)blockIdx.x * P.slot_bytes;
+  const int64_t nn = (int64_t)P.ldw * P.ldw;
+  SlotMats s32, s64;
+  {
+    float* f = reinterpret_cast<float*>(slot);
+    s32.A32 = f;
+    s32.G[0] = f + nn;
+    s32.G[1] = f + 2 * nn;
+    s32.F = f + 3 * nn;
+    s32.P[0] = f + 4 * nn;
+    s32.P[1] = f + 5 * nn;
+    s32.C[0] = f + 6 * nn;
+    s32.C[1] = f + 7 * nn;
+    double* d = reinterpret_cast<double*>(f + 8 * nn);
+    s64.A32 = nullptr;
+    s64.G[0] = d;
+    s64.G[1] = d + nn;
+    s64.F = d + 2 * nn;
+    s64.P[0] = d + 3 * nn;
+    s64.P[1] = d + 4 * nn;
+    s64.C[0] = d + 5 * nn;
+    s64.C[1] = d + 6 * nn;
+    double* r = d + 7 * nn;
+    s32.r = r;
+    s64.r = r;
+  }
+  for (;;) {
+    if (threadIdx.x == 0) s_idx = atomicAdd(P.counter, 1);
+    __syncthreads();
+    const int q = s_idx;
+    __syncthreads();
+    if (q >= P.count) break;
+    const int sid = P.order[q];
+    const BatchDesc d = P.desc[sid];
+    Ctl c;
+    bool ok = false;
+    int64_t mmm32 = 0;
+    if (!P.fp64_only) {
+      ok = wg_solve<float, NW>(P, d, s32, red, hist, c);
+      mmm32 = c.mmm;
+    }
+    if (P.fp64_only || (!ok && P.escalate)) {
+      __syncthreads();
+      ok = wg_solve<double, NW>(P, d, s64, red, hist, c);
+      c.mmm += mmm32;
+    }
+    __syncthreads();  // hist complete
+    if (threadIdx.x == 0) {
+      BatchResult* R = &P.res[sid];
+      R->status = ok ? NS_OK
+                     : ((c.ns_stop == NS_STOP_DIVERGED || c.refine_stop == NS_STOP_DIVERGED)
+                            ? NS_EDIVERGED
+                            : NS_ENOCONV);
+      R->ns_stop = c.ns_stop;
+      R->refine_stop = c.refine_stop;
+      R->ns_steps = c.ns_steps;
+      R->refine_steps = c.refine_steps;
+      R->precision = c.precision;
+      R->n_fnorm = c.n_fnorm;
+      R->n_resid = 0;
+      R->alpha = c.alpha;
+      R->rel_resid = c.rel_resid;
+      R->mmm = c.mmm;
+      for (int j = 0; j < c.n_fnorm; ++j) R->fnorm_hist[j] = hist[j];
+    }
+    __syncthreads();
+  }
+}
+
+}  // namespace
+
+size_t batch_slot_bytes(int ldw) {
+  const size_t nn = (size_t)ldw * ldw;
+  size_t b = 8 * nn * sizeof(float) + 7 * nn * sizeof(double) + (size_t)ldw * sizeof(double);
+  return (b + 255) / 256 * 256;
+}
+
+int launch_batch(const BatchArgs& a, int grid, int waves, hipStream_t st) {
+  switch (waves) {
+    case 1: hipLaunchKernelGGL(batch_kernel<1>, dim3(grid), dim3(64), 0, st, a); break;
+    case 2: hipLaunchKernelGGL(batch_kernel<2>, dim3(grid), dim3(128), 0, st, a); break;
+    case 4: hipLaunchKernelGGL(batch_kernel<4>, dim3(grid), dim3(256), 0, st, a); break;
+    default: return -1;
+  }
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+}  // namespace nsr
+
+// ---------------------------------------------------------------------------
+// Host side: the ns_batch_* entry points of include/nsr.h.
+// ---------------------------------------------------------------------------
+
+using namespace nsr;
+
+namespace {
+
+int bfail(int code, const char* msg) {
+  ns_set_error(msg);
+  return code;
+}
+
+constexpr size_t kBAlign = 256;
+inline size_t balign(size_t x) { return (x + kBAlign - 1) / kBAlign * kBAlign; }
+inline int ldw_for(int64_t max_n) { return (int)((max_n + 31) / 32 * 32); }
+
+size_t batch_layout(int64_t max_n, int max_count, int slots) {
+  size_t b = 0;
+  b += balign((size_t)max_count * sizeof(BatchDesc));
+  b += balign((size_t)max_count * sizeof(BatchResult));
+  b += balign((size_t)max_count * sizeof(int32_t));
+  b += balign(sizeof(int32_t));
+  b += (size_t)slots * batch_slot_bytes(ldw_for(max_n));
+  return b;
+}
+
+}  // namespace
+
+struct ns_batch {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  int64_t max_n = 0;
+  int max_count = 0;
+  int slots = 0;
+  int ldw = 0;
+  int precision = NS_PREC_FP32;
+  int waves = 4;
+  int groups = 0;  // launch size (<= slots); 0: all slots
+  BatchDesc* d_desc = nullptr;
+  BatchResult* d_res = nullptr;
+  int32_t* d_order = nullptr;
+  int32_t* d_counter = nullptr;
+  char* d_slots = nullptr;
+  hipEvent_t done = nullptr;
+  uint64_t next_ticket = 0;
+  uint64_t inflight = 0;
+  int inflight_count = 0;
+  bool busy = false;
+  std::vector<BatchDesc> h_desc;
+  std::vector<int32_t> h_order;
+  std::vector<BatchResult> h_res;
+};
+
+namespace {
+
+int batch_enqueue(ns_batch* B, int count, const int64_t* n, const double* const* A,
+                  const int64_t* lda, const double* const* b, double* const* theta,
+                  const ns_solve_opts* o) {
+  if (count < 0) return bfail(NS_EINVAL, "count < 0");
+  if (count > B->max_count) return bfail(NS_ENOMEM, "count exceeds the batch capacity");
+  if (!o) return bfail(NS_EINVAL, "null opts");
+  if (o->factorization != NS_FACT_SQUARING)
+    return bfail(NS_EINVAL, "batched solves use the squaring form");
+  if (o->order < 2 || (o->order & (o->order - 1)) != 0)
+    return bfail(NS_EINVAL, "order must be 2^s >= 2");
+  if (o->k_max < 1 || o->k_max > NS_HIST_F - 1) return bfail(NS_EINVAL, "k_max must be in 1..64");
+  if (o->refine_max < 0) return bfail(NS_EINVAL, "refine_max < 0");
+  if (o->scale != NS_SCALE_FROBENIUS) return bfail(NS_EINVAL, "batched solves scale by ||A||_F");
+  if (o->theta0_mode != 0) return bfail(NS_EINVAL, "batched solves start from theta_0 = b/alpha");
+  if (count > 0 && (!n || !A || !lda || !b || !theta)) return bfail(NS_EINVAL, "null array");
+  B->h_desc.resize(count);
+  B->h_order.resize(count);
+  for (int i = 0; i < count; ++i) {
+    if (n[i] < 1) return bfail(NS_EINVAL, "system size < 1");
+    if (n[i] > B->max_n) return bfail(NS_ENOMEM, "system larger than the batch's max_n");
+    if (lda[i] < n[i]) return bfail(NS_EINVAL, "lda < n");
+    if (!A[i] || !b[i] || !theta[i]) return bfail(NS_EINVAL, "null system pointer");
+    B->h_desc[i] = BatchDesc{A[i], b[i], theta[i], lda[i], (int32_t)n[i], 0};
+    B->h_order[i] = i;
+  }
+  // Largest systems first (longest-processing-time order for the work pull).
+  std::stable_sort(B->h_order.begin(), B->h_order.end(),
+                   [&](int32_t x, int32_t y) { return B->h_desc[x].n > B->h_desc[y].n; });
+  if (hipSetDevice(B->device) != hipSuccess) return bfail(NS_EHIP, "hipSetDevice failed");
+  if (count > 0) {
+    if (hipMemcpyAsync(B->d_desc, B->h_desc.data(), count * sizeof(BatchDesc),
+                       hipMemcpyHostToDevice, B->stream) != hipSuccess ||
+        hipMemcpyAsync(B->d_order, B->h_order.data(), count * sizeof(int32_t),
+                       hipMemcpyHostToDevice, B->stream) != hipSuccess)
+      return bfail(NS_EHIP, "descriptor upload failed");
+  }
+  if (hipMemsetAsync(B->d_counter, 0, sizeof(int32_t), B->stream) != hipSuccess)
+    return bfail(NS_EHIP, "counter reset failed");
+  BatchArgs a{};
+  a.desc = B->d_desc;
+  a.res = B->d_res;
+  a.order = B->d_order;
+  a.counter = B->d_counter;
+  a.slots = B->d_slots;
+  a.slot_bytes = (int64_t)batch_slot_bytes(B->ldw);
+  a.count = count;
+  a.ldw = B->ldw;
+  a.ns_order = o->order;
+  a.k_max = o->k_max;
+  a.refine_max = o->refine_max;
+  a.floor_detect = o->floor_detect;
+  a.escalate = (B->precision == NS_PREC_FP32) ? 1 : 0;
+  a.fp64_only = (B->precision == NS_PREC_FP64) ? 1 : 0;
+  a.f_tol = o->f_tol;
+  a.resid_tol = o->resid_tol;
+  int grid = B->groups > 0 ? B->groups : B->slots;
+  if (grid > B->slots) grid = B->slots;
+  if (grid > count) grid = count;
+  if (grid > 0 && launch_batch(a, grid, B->waves, B->stream) != 0)
+    return bfail(NS_EHIP, "batch kernel launch failed");
+  return NS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t ns_batch_workspace_bytes(int64_t max_n, int max_count, int slots) {
+  if (max_n < 1 || max_count < 1 || slots < 1) return 0;
+  return batch_layout(max_n, max_count, slots);
+}
+
+int ns_batch_create(int device, void* hip_stream, int64_t max_n, int max_count, int slots,
+                    int precision, void* workspace, size_t bytes, ns_batch** out) {
+  if (!out) return bfail(NS_EINVAL, "null out");
+  *out = nullptr;
+  if (max_n < 1 || max_n > 4096) return bfail(NS_EINVAL, "max_n must be in 1..4096");
+  if (max_count < 1 || slots < 1) return bfail(NS_EINVAL, "max_count and slots must be >= 1");
+  if (precision != NS_PREC_FP32 && precision != NS_PREC_FP64)
+    return bfail(NS_EINVAL, "batched precision must be NS_PREC_FP32 or NS_PREC_FP64");
+  if (!workspace || (reinterpret_cast<uintptr_t>(workspace) % kBAlign) != 0)
+    return bfail(NS_EINVAL, "workspace must be non-NULL and 256-byte aligned");
+  if (bytes < batch_layout(max_n, max_count, slots)) return bfail(NS_ENOMEM, "workspace too small");
+  if (hipSetDevice(device) != hipSuccess) return bfail(NS_EHIP, "hipSetDevice failed");
+  ns_batch* B = new (std::nothrow) ns_batch();
+  if (!B) return bfail(NS_ENOMEM, "host allocation failed");
+  B->device = device;
+  B->stream = reinterpret_cast<hipStream_t>(hip_stream);
+  B->max_n = max_n;
+  B->max_count = max_count;
+  B->slots = slots;
+  B->ldw = ldw_for(max_n);
+  B->precision = precision;
+  char* p = reinterpret_cast<char*>(workspace);
+  B->d_desc = reinterpret_cast<BatchDesc*>(p);
+  p += balign((size_t)max_count * sizeof(BatchDesc));
+  B->d_res = reinterpret_cast<BatchResult*>(p);
+  p += balign((size_t)max_count * sizeof(BatchResult));
+  B->d_order = reinterpret_cast<int32_t*>(p);
+  p += balign((size_t)max_count * sizeof(int32_t));
+  B->d_counter = reinterpret_cast<int32_t*>(p);
+  p += balign(sizeof(int32_t));
+  B->d_slots = p;
+  if (hipEventCreate(&B->done) != hipSuccess) {
+    delete B;
+    return bfail(NS_EHIP, "hipEventCreate failed");
+  }
+  *out = B;
+  return NS_OK;
+}
+
+int ns_batch_set_launch(ns_batch* B, int waves_per_group, int groups) {
+  if (!B) return bfail(NS_EINVAL, "null batch");
+  if (waves_per_group != 1 && waves_per_group != 2 && waves_per_group != 4)
+    return bfail(NS_EINVAL, "waves_per_group must be 1, 2 or 4");
+  if (groups < 0 || groups > B->slots) return bfail(NS_EINVAL, "groups must be in 0..slots");
+  B->waves = waves_per_group;
+  B->groups = groups;
+  return NS_OK;
+}
+
+int ns_batch_submit(ns_batch* B, int count, const int64_t* n, const double* const* A,
+                    const int64_t* lda, const double* const* b, double* const* theta,
+                    const ns_solve_opts* opts, uint64_t* ticket) {
+  if (!B) return bfail(NS_EINVAL, "null batch");
+  if (B->busy) return bfail(NS_EBUSY, "a submission is still in flight; poll it first");
+  if (int rc = batch_enqueue(B, count, n, A, lda, b, theta, opts)) return rc;
+  if (hipEventRecord(B->done, B->stream) != hipSuccess) return bfail(NS_EHIP, "hipEventRecord failed");
+  B->busy = true;
+  B->inflight = ++B->next_ticket;
+  B->inflight_count = count;
+  if (ticket) *ticket = B->inflight;
+  return NS_OK;
+}
+
+int ns_batch_poll(ns_batch* B, uint64_t ticket, int wait, ns_solve_report* reports) {
+  if (!B) return bfail(NS_EINVAL, "null batch");
+  if (!B->busy || ticket != B->inflight) return bfail(NS_EINVAL, "unknown ticket");
+  if (wait) {
+    if (hipEventSynchronize(B->done) != hipSuccess) return bfail(NS_EHIP, "hipEventSynchronize failed");
+  } else {
+    hipError_t q = hipEventQuery(B->done);
+    if (q == hipErrorNotReady) return NS_EBUSY;
+    if (q != hipSuccess) return bfail(NS_EHIP, "hipEventQuery failed");
+  }
+  const int cnt = B->inflight_count;
+  B->h_res.resize(cnt);
+  if (cnt > 0 && hipMemcpy(B->h_res.data(), B->d_res, cnt * sizeof(BatchResult),
+                           hipMemcpyDeviceToHost) != hipSuccess)
+    return bfail(NS_EHIP, "result download failed");
+  B->busy = false;
+  int worst = NS_OK;
+  for (int i = 0; i < cnt; ++i) {
+    const BatchResult& r = B->h_res[i];
+    if (r.status != NS_OK && worst == NS_OK) worst = r.status;
+    if (!reports) continue;
+    ns_solve_report& R = reports[i];
+    memset(&R, 0, sizeof(R));
+    R.status = r.status;
+    R.ns_stop = r.ns_stop;
+    R.refine_stop = r.refine_stop;
+    R.ns_steps = r.ns_steps;
+    R.refine_steps = r.refine_steps;
+    R.precision = r.precision;
+    R.alpha = r.alpha;
+    R.rel_resid = r.rel_resid;
+    R.mmm = r.mmm;
+    const double nn = (double)B->h_desc[i].n;
+    R.gemm_flop = 2.0 * nn * nn * nn * (double)r.mmm;
+    R.n_fnorm = r.n_fnorm;
+    for (int j = 0; j < r.n_fnorm && j < NS_HIST_F; ++j) R.fnorm_hist[j] = r.fnorm_hist[j];
+    R.n_resid = 0;
+  }
+  return worst == NS_OK ? NS_OK : NS_ENOCONV;
+}
+
+int ns_batch_autotune(ns_batch* B, int count, const int64_t* n, const double* const* A,
+                      const int64_t* lda, const double* const* b, double* const* theta,
+                      const ns_solve_opts* opts, int* best_waves, int* best_groups,
+                      double* best_ms) {
+  if (!B) return bfail(NS_EINVAL, "null batch");
+  if (B->busy) return bfail(NS_EBUSY, "a submission is still in flight; poll it first");
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+    return bfail(NS_EHIP, "hipEventCreate failed");
+  int bw = 4, bg = 0;
+  float bms = 1e30f;
+  const int waves_c[3] = {1, 2, 4};
+  int cus = 256;
+  {
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, B->device) == hipSuccess && prop.multiProcessorCount > 0)
+      cus = prop.multiProcessorCount;
+  }
+  const int per_cu_c[4] = {1, 2, 4, 8};
+  int rc = NS_OK;
+  for (int wi = 0; wi < 3 && rc == NS_OK; ++wi) {
+    int prev_groups = -1;
+    for (int gi = 0; gi < 4 && rc == NS_OK; ++gi) {
+      int groups = per_cu_c[gi] * cus;
+      if (groups > B->slots) groups = B->slots;
+      if (groups == prev_groups) continue;
+      prev_groups = groups;
+      B->waves = waves_c[wi];
+      B->groups = groups;
+      if (hipEventRecord(e0, B->stream) != hipSuccess) { rc = bfail(NS_EHIP, "event"); break; }
+      rc = batch_enqueue(B, count, n, A, lda, b, theta, opts);
+      if (rc) break;
+      if (hipEventRecord(e1, B->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
+        rc = bfail(NS_EHIP, "event");
+        break;
+      }
+      float ms = 0.f;
+      hipEventElapsedTime(&ms, e0, e1);
+      if (ms < bms) {
+        bms = ms;
+        bw = waves_c[wi];
+        bg = groups;
+      }
+    }
+  }
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  if (rc) return rc;
+  B->waves = bw;
+  B->groups = bg;
+  if (best_waves) *best_waves = bw;
+  if (best_groups) *best_groups = bg;
+  if (best_ms) *best_ms = bms;
+  return NS_OK;
+}
+
+int ns_batch_destroy(ns_batch* B) {
+  if (!B) return NS_OK;
+  if (B->busy) (void)hipEventSynchronize(B->done);
+  if (B->done) (void)hipEventDestroy(B->done);
+  delete B;
+  return NS_OK;
+}
+
+}  // extern "C"

@@ -96,4 +96,7 @@ void launch_vec_scale(const double* b, const double* alpha, double* theta, int64
 // Sum of squares of a vector -> partials
 int64_t launch_vec_sumsq(const double* v, int64_t n, double* partial, hipStream_t st);
 
+// Set the calling thread's ns_last_error() message.
+void ns_set_error(const char* msg);
+
 }  // namespace nsr

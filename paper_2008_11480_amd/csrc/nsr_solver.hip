@@ -29,6 +29,14 @@ int fail(int code, const char* fmt, ...) {
   return code;
 }
 
+}  // namespace
+
+namespace nsr {
+void ns_set_error(const char* msg) { snprintf(g_err, sizeof(g_err), "%s", msg); }
+}  // namespace nsr
+
+namespace {
+
 #define HIP_TRY(expr)                                                               \
   do {                                                                              \
     hipError_t e_ = (expr);                                                         \
@@ -119,6 +127,7 @@ struct ns_solver {
   bool scaled = false;
   bool g_implicit = true;  // G = I / alpha, not materialised
   bool dns_started = false;
+  bool p0_is_f2 = false;   // P[0] holds F_k^2 (computed by the floor test)
   double alpha = 0.0;
   int64_t mmm = 0;
 
@@ -233,14 +242,16 @@ int apply_g(ns_solver* s, const Mat& Gcur, bool implicit, const Mat& C, Mat& Gne
 // C with P(Y) = I + C = (I + Y)(I + Y^2)...(I + Y^(2^(s-1))), order 2^s
 // (Tables 1-2): powers into P0/P1, identity-offset assembly into C0/C1.
 // Returns the matrix holding C (Y itself for order 2).
-int poly_squaring(ns_solver* s, int order, const Mat& Y, const Mat** out) {
+int poly_squaring(ns_solver* s, int order, const Mat& Y, const Mat** out, bool y2_ready = false) {
   int sexp = 0;
   while ((1 << sexp) < order) ++sexp;
   const Mat* pw = &Y;
   const Mat* c = &Y;
   for (int i = 1; i < sexp; ++i) {
     Mat* npw = (pw == &s->P[0]) ? &s->P[1] : &s->P[0];
-    int rc = mm(s, *npw, pw, *pw, nullptr, nullptr, 0.0, 1.0, false, K_POWER);  // Y^(2^i)
+    int rc = NS_OK;
+    if (!(i == 1 && y2_ready))  // Y^2 may already sit in P[0]
+      rc = mm(s, *npw, pw, *pw, nullptr, nullptr, 0.0, 1.0, false, K_POWER);  // Y^(2^i)
     if (rc) return rc;
     Mat* nc = (c == &s->C[0]) ? &s->C[1] : &s->C[0];
     rc = mm(s, *nc, c, *npw, c, npw, 0.0, 1.0, false, K_POWER);  // C + Y^(2^i) + C Y^(2^i)
@@ -261,6 +272,7 @@ int resid_into(ns_solver* s, Mat& D, const Mat& X, bool want_norm) {
 // Classical step G_k = G_{k-1} P(F_{k-1}) for the non-composite forms;
 // leaves G in s->G[s->gcur].
 int step_classic(ns_solver* s, int order, int fact, int p, int w) {
+  if (fact != NS_FACT_SQUARING) s->p0_is_f2 = false;
   Mat& Gc = s->G[s->gcur];
   Mat& Gn = s->G[s->gcur ^ 1];
   const bool impl = s->g_implicit;
@@ -268,7 +280,8 @@ int step_classic(ns_solver* s, int order, int fact, int p, int w) {
   int rc = NS_OK;
   if (fact == NS_FACT_SQUARING) {
     const Mat* c = nullptr;
-    rc = poly_squaring(s, order, s->F, &c);
+    rc = poly_squaring(s, order, s->F, &c, s->p0_is_f2);
+    s->p0_is_f2 = false;
     if (rc) return rc;
     rc = apply_g(s, Gc, impl, *c, Gn);
     if (rc) return rc;
@@ -334,6 +347,7 @@ int step_classic(ns_solver* s, int order, int fact, int p, int w) {
 // Double Newton-Schulz step (Section 5.1, right orientation).
 int step_composite(ns_solver* s, int order) {
   int rc;
+  s->p0_is_f2 = false;  // P[0] is reused by the L-loop first
   const Mat* c = nullptr;
   if (!s->dns_started) {
     if (!s->g_implicit) return fail(NS_ESTATE, "composite form must start from G_0");
@@ -537,6 +551,7 @@ int ns_bind(ns_solver* s, const double* A, int64_t lda) {
   s->scaled = false;
   s->g_implicit = true;
   s->dns_started = false;
+  s->p0_is_f2 = false;
   s->gcur = 0;
   s->lcur = 0;
   if (!is_f64(s)) {
@@ -576,6 +591,7 @@ int ns_init_scale(ns_solver* s, int scale, double eps, double* alpha_out, double
   s->scaled = true;
   s->g_implicit = true;
   s->dns_started = false;
+  s->p0_is_f2 = false;
   s->gcur = 0;
   s->lcur = 0;
   s->mmm = 0;
@@ -693,20 +709,25 @@ int richardson_ns_solve(ns_solver* s, const double* b, double* theta, const ns_s
     if (R->n_resid < NS_HIST_R) R->resid_hist[R->n_resid++] = host[1] / bnorm;
     R->fnorm_hist[R->n_fnorm++] = fk;
     // Stop rule (the paper gives none): divergence, tolerance, rounding
-    // floor (an earlier ratio below 1/2, the current one above), k_max.
+    // floor, k_max.  Floor: ||F_k|| > ||F_{k-1}|| / 2 although
+    // ||F_k^2|| <= ||F_k|| / 4; in exact arithmetic (F_k = F_{k-1}^n, log of
+    // the power sums convex in the exponent) the second forces the ratio
+    // below 1/2, so rounding dominates.  F_k^2 lands in P[0], where the next
+    // squaring step picks it up.
     const double* h = R->fnorm_hist;
     if (!isfinite(fk) || fk > h[0]) {
       ns_stop = NS_STOP_DIVERGED;
     } else if (fk <= o->f_tol) {
       ns_stop = NS_STOP_F_TOL;
     } else {
-      bool entered = false;
-      for (int j = 1; j < k; ++j)
-        if (h[j] < 0.5 * h[j - 1]) entered = true;
-      if (o->floor_detect && k >= 2 && entered && fk > 0.5 * h[k - 1])
-        ns_stop = NS_STOP_FLOOR;
-      else if (k >= o->k_max)
-        ns_stop = NS_STOP_K_MAX;
+      if (o->floor_detect && fk > 0.5 * h[k - 1]) {
+        if ((rc = mm(s, s->P[0], &s->F, s->F, nullptr, nullptr, 0.0, 1.0, true, K_POWER)))
+          return rc;
+        if ((rc = read_scalars(s, host, 1, 1))) return rc;
+        s->p0_is_f2 = true;
+        if (host[0] <= 0.25 * fk) ns_stop = NS_STOP_FLOOR;
+      }
+      if (ns_stop == NS_STOP_NONE && k >= o->k_max) ns_stop = NS_STOP_K_MAX;
     }
   }
   R->ns_steps = k;

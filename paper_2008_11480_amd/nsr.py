@@ -38,6 +38,8 @@ EXPORTS = (
     "ns_get_G", "ns_get_F", "ns_richardson_step", "richardson_ns_solve", "ns_timing_enable",
     "ns_timing_read", "ns_timing_reset", "ns_gemm_f64", "ns_gemm_f64_partials",
     "ns_gemm_f32", "ns_gemm_bf16_nt", "ns_gemm_lp_partials",
+    "ns_batch_workspace_bytes", "ns_batch_create", "ns_batch_set_launch", "ns_batch_submit",
+    "ns_batch_poll", "ns_batch_autotune", "ns_batch_destroy",
     "ns_status_string", "ns_last_error", "ns_version",
 )
 
@@ -117,6 +119,16 @@ def lib() -> ctypes.CDLL:
         "ns_gemm_bf16_nt": (ci, [vp, i64, i64, i64, vp, i64, vp, i64, vp, i64, vp, i64, vp, i64,
                                  vp, i64, ctypes.c_float, ctypes.c_float, vp]),
         "ns_gemm_lp_partials": (i64, [i64, i64]),
+        "ns_batch_workspace_bytes": (ctypes.c_size_t, [i64, ci, ci]),
+        "ns_batch_create": (ci, [ci, vp, i64, ci, ci, ci, vp, ctypes.c_size_t,
+                                 ctypes.POINTER(vp)]),
+        "ns_batch_set_launch": (ci, [vp, ci, ci]),
+        "ns_batch_submit": (ci, [vp, ci, vp, vp, vp, vp, vp, ctypes.POINTER(SolveOpts),
+                                 ctypes.POINTER(ctypes.c_uint64)]),
+        "ns_batch_poll": (ci, [vp, ctypes.c_uint64, ci, vp]),
+        "ns_batch_autotune": (ci, [vp, ci, vp, vp, vp, vp, vp, ctypes.POINTER(SolveOpts),
+                                   ctypes.POINTER(ci), ctypes.POINTER(ci), pd]),
+        "ns_batch_destroy": (ci, [vp]),
         "ns_status_string": (ctypes.c_char_p, [ci]),
         "ns_last_error": (ctypes.c_char_p, []),
         "ns_version": (ctypes.c_char_p, []),
@@ -293,6 +305,116 @@ def gemm_f64(X, Y, D=None, E1=None, E2=None, diag: float = 0.0, scale: float = 1
                             E2.stride(0) if E2 is not None else 0, float(diag), float(scale),
                             _ptr(ss)))
     return (D, ss[0]) if want_sumsq else D
+
+
+def _report_from_c(rep) -> SolveReport:
+    return SolveReport(
+        status=rep.status, ns_stop=STOP_NAMES.get(rep.ns_stop, "?"),
+        refine_stop=STOP_NAMES.get(rep.refine_stop, "?"), ns_steps=rep.ns_steps,
+        refine_steps=rep.refine_steps, precision=rep.precision, alpha=rep.alpha,
+        rel_resid=rep.rel_resid, mmm=rep.mmm, gemm_flop=rep.gemm_flop,
+        fnorm_hist=list(rep.fnorm_hist[:rep.n_fnorm]),
+        resid_hist=list(rep.resid_hist[:rep.n_resid]))
+
+
+class Batch:
+    """``ns_batch`` handle: many independent systems per persistent launch."""
+
+    def __init__(self, max_n: int, max_count: int, slots: int | None = None,
+                 precision: int = PREC_FP32, device: int | None = None, stream=None):
+        import torch
+        L = lib()
+        self.device = torch.cuda.current_device() if device is None else int(device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        if slots is None:
+            cus = torch.cuda.get_device_properties(self.device).multi_processor_count
+            slots = min(max_count, 4 * cus)
+        self.max_n, self.max_count, self.slots = int(max_n), int(max_count), int(slots)
+        nbytes = int(L.ns_batch_workspace_bytes(self.max_n, self.max_count, self.slots))
+        if nbytes == 0:
+            raise NSError(NS_EINVAL, "bad batch sizes")
+        self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8,
+                                     device=f"cuda:{self.device}")
+        aligned = (self.workspace.data_ptr() + 255) // 256 * 256
+        h = ctypes.c_void_p()
+        check(L.ns_batch_create(self.device, _stream_handle(self.stream), self.max_n,
+                                self.max_count, self.slots, int(precision), aligned, nbytes,
+                                ctypes.byref(h)))
+        self._h = h
+        self._keep = None
+        self._count = 0
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().ns_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @staticmethod
+    def _arrays(As, bs, thetas):
+        count = len(As)
+        if not (len(bs) == count and len(thetas) == count):
+            raise ValueError("A, b, theta lists differ in length")
+        n = (ctypes.c_int64 * count)()
+        lda = (ctypes.c_int64 * count)()
+        pa = (ctypes.c_void_p * count)()
+        pb = (ctypes.c_void_p * count)()
+        pt = (ctypes.c_void_p * count)()
+        for i, (A, b, t) in enumerate(zip(As, bs, thetas)):
+            _require_cuda_f64(A, "A")
+            _require_cuda_f64(b, "b")
+            _require_cuda_f64(t, "theta")
+            if A.dim() != 2 or A.shape[0] != A.shape[1] or A.stride(1) != 1:
+                raise ValueError("each A must be square with unit column stride")
+            if b.numel() != A.shape[0] or t.numel() != A.shape[0]:
+                raise ValueError("b / theta length must match A")
+            n[i], lda[i] = A.shape[0], A.stride(0)
+            pa[i], pb[i], pt[i] = A.data_ptr(), b.data_ptr(), t.data_ptr()
+        return count, n, pa, lda, pb, pt
+
+    @staticmethod
+    def _opts(order=4, k_max=64, refine_max=64, floor_detect=True, f_tol=0.0, resid_tol=1e-10):
+        return SolveOpts(order=order, factorization=FACT["squaring"], p=0, w=0, k_max=k_max,
+                         refine_max=refine_max, floor_detect=1 if floor_detect else 0,
+                         scale=SCALE_FROBENIUS, eps=0.0, f_tol=f_tol, resid_tol=resid_tol,
+                         theta0_mode=0)
+
+    def set_launch(self, waves: int, groups: int = 0):
+        check(lib().ns_batch_set_launch(self._h, int(waves), int(groups)))
+
+    def submit(self, As, bs, thetas, **opts) -> int:
+        count, n, pa, lda, pb, pt = self._arrays(As, bs, thetas)
+        o = self._opts(**opts)
+        t = ctypes.c_uint64()
+        check(lib().ns_batch_submit(self._h, count, n, pa, lda, pb, pt, ctypes.byref(o),
+                                    ctypes.byref(t)))
+        self._keep = (As, bs, thetas)
+        self._count = count
+        return t.value
+
+    def poll(self, ticket: int, wait: bool = True):
+        """List of SolveReport on completion, None if still running (wait=False)."""
+        reps = (SolveReportC * max(self._count, 1))()
+        st = lib().ns_batch_poll(self._h, int(ticket), 1 if wait else 0, reps)
+        if st == NS_EBUSY:
+            return None
+        if st not in (NS_OK, NS_ENOCONV):
+            check(st)
+        self._keep = None
+        return [_report_from_c(reps[i]) for i in range(self._count)]
+
+    def autotune(self, As, bs, thetas, **opts):
+        count, n, pa, lda, pb, pt = self._arrays(As, bs, thetas)
+        o = self._opts(**opts)
+        w, g, ms = ctypes.c_int(), ctypes.c_int(), ctypes.c_double()
+        check(lib().ns_batch_autotune(self._h, count, n, pa, lda, pb, pt, ctypes.byref(o),
+                                      ctypes.byref(w), ctypes.byref(g), ctypes.byref(ms)))
+        return w.value, g.value, ms.value
 
 
 def gemm_lp(X, Y, nt: bool, D=None, want_bf16: bool = False, E1=None, E2=None,

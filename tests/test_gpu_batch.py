@@ -1,0 +1,153 @@
+"""GPU parity of the batched persistent solver (many uneven systems, one launch).
+
+Each system's result is checked against the CPU oracle's solve of the same
+system: relative residual <= resid_tol when the report says NS_OK, forward
+error vs the oracle within 50 kappa u64 (kappa from numpy's eigvalsh), and the
+||F_0|| of the report against its definition.  Systems whose float32 solve
+fails must be escalated (report.precision == float64).
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2008_11480_amd import inputs, nsr
+
+pytestmark = pytest.mark.gpu
+U64 = np.finfo(np.float64).eps / 2
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as _torch
+    if not _torch.cuda.is_available():
+        pytest.skip("no GPU")
+    nsr.lib()
+    return _torch
+
+
+def upload(torch, systems):
+    As = [torch.from_numpy(s.A).to("cuda") for s in systems]
+    bs = [torch.from_numpy(s.b).to("cuda") for s in systems]
+    ths = [torch.zeros_like(b) for b in bs]
+    return As, bs, ths
+
+
+def check_against_oracle(systems, ths, reps, order, resid_tol, sample=None):
+    idx = range(len(systems)) if sample is None else sample
+    for i in idx:
+        s, rep = systems[i], reps[i]
+        th = ths[i].cpu().numpy()
+        lam = np.linalg.eigvalsh(s.A)
+        kappa = lam.max() / lam.min()
+        rel = np.linalg.norm(s.b - s.A @ th) / np.linalg.norm(s.b)
+        alpha = np.sqrt(np.sum(s.A ** 2))
+        assert rep.alpha == pytest.approx(alpha, rel=1e-13)
+        f0 = np.linalg.norm(np.eye(s.n) - s.A / alpha)
+        assert rep.fnorm_hist[0] == pytest.approx(f0, rel=1e-5 if rep.precision == 1 else 1e-12)
+        if rep.status == nsr.NS_OK:
+            assert rel <= resid_tol * 1.01, (i, rel)
+            orc = oracle.solve(s.A, s.b, oracle.SolveOptions(order=order, resid_tol=resid_tol * 1e-3))
+            fwd = np.linalg.norm(th - orc.theta) / np.linalg.norm(orc.theta)
+            assert fwd <= max(50 * kappa * U64, 10 * resid_tol * kappa), (i, fwd, kappa)
+        else:
+            # not reachable in float32: must have been retried in float64
+            assert rep.precision == nsr.PREC_FP64, (i, rep)
+            assert rel <= 1e3 * kappa * U64, (i, rel, kappa)
+
+
+def test_batch_uneven_sizes_matches_oracle(torch):
+    rng = np.random.default_rng(11)
+    systems = [inputs.harmonic_gram(int(m), seed=int(rng.integers(1 << 30)))
+               for m in rng.integers(8, 41, size=24)]
+    systems += [inputs.spd_qlq(n, k, seed=40 + n) for n, k in
+                ((17, 1e2), (33, 1e3), (100, 1e4), (255, 1e3), (1, 1.0), (2, 5.0), (200, 1e5))]
+    As, bs, ths = upload(torch, systems)
+    B = nsr.Batch(max_n=256, max_count=64, slots=32)
+    t = B.submit(As, bs, ths, order=4, resid_tol=1e-10)
+    reps = B.poll(t, wait=True)
+    assert len(reps) == len(systems)
+    check_against_oracle(systems, ths, reps, 4, 1e-10)
+
+
+def test_batch_fp64_mode_and_order8(torch):
+    systems = [inputs.spd_qlq(n, 1e3, seed=n) for n in (16, 40, 64, 130, 256)]
+    As, bs, ths = upload(torch, systems)
+    B = nsr.Batch(max_n=256, max_count=8, slots=8, precision=nsr.PREC_FP64)
+    reps = B.poll(B.submit(As, bs, ths, order=8, resid_tol=1e-12), wait=True)
+    for s, r, th in zip(systems, reps, ths):
+        assert r.status == nsr.NS_OK and r.precision == nsr.PREC_FP64
+        orc = oracle.solve(s.A, s.b, oracle.SolveOptions(order=8, resid_tol=1e-13))
+        compare = min(len(r.fnorm_hist), len(orc.fnorm_hist))
+        floor = max(min(r.fnorm_hist), min(orc.fnorm_hist))
+        for k in range(compare):
+            assert abs(r.fnorm_hist[k] - orc.fnorm_hist[k]) <= 1e-10 * orc.fnorm_hist[k] + 10 * floor
+        assert abs(r.ns_steps - orc.ns_steps) <= 1
+        assert np.linalg.norm(th.cpu().numpy() - orc.theta) <= 50 * 1e3 * U64 * np.linalg.norm(orc.theta)
+
+
+def test_batch_escalation_to_fp64(torch):
+    """kappa = 1e6 needs ~6 float32 refinement steps; with refine_max = 2 the
+    float32 solve fails and the workgroup re-solves the system in float64."""
+    systems = [inputs.spd_qlq(64, 1e6, seed=7), inputs.spd_qlq(48, 10.0, seed=8)]
+    As, bs, ths = upload(torch, systems)
+    B = nsr.Batch(max_n=64, max_count=4, slots=2)
+    reps = B.poll(B.submit(As, bs, ths, order=4, resid_tol=1e-10, refine_max=2), wait=True)
+    assert reps[0].precision == nsr.PREC_FP64 and reps[0].status == nsr.NS_OK
+    assert reps[1].precision == nsr.PREC_FP32 and reps[1].status == nsr.NS_OK
+    check_against_oracle(systems, ths, reps, 4, 1e-10)
+
+
+def test_batch_harmonic_distribution_sampled(torch):
+    """512 harmonic-regressor Gram systems, m ~ U{8..128} (N = 16..256): all
+    results pass the residual / escalation checks; 24 sampled systems are
+    compared with the oracle."""
+    systems = inputs.harmonic_batch(512, seed=4)
+    As, bs, ths = upload(torch, systems)
+    B = nsr.Batch(max_n=256, max_count=512)
+    reps = B.poll(B.submit(As, bs, ths, order=4, resid_tol=1e-10), wait=True)
+    rng = np.random.default_rng(0)
+    sample = list(rng.choice(512, size=24, replace=False))
+    sample += [i for i, r in enumerate(reps) if r.status != nsr.NS_OK][:8]
+    check_against_oracle(systems, ths, reps, 4, 1e-10, sample=sample)
+    for i, (s, r) in enumerate(zip(systems, reps)):
+        th = ths[i].cpu().numpy()
+        rel = np.linalg.norm(s.b - s.A @ th) / np.linalg.norm(s.b)
+        if r.status == nsr.NS_OK:
+            assert rel <= 1.01e-10, (i, rel)
+        else:
+            assert r.precision == nsr.PREC_FP64
+
+
+def test_batch_admission_and_busy(torch):
+    systems = [inputs.spd_qlq(40, 10.0, seed=i) for i in range(3)]
+    As, bs, ths = upload(torch, systems)
+    B = nsr.Batch(max_n=32, max_count=2, slots=2)
+    with pytest.raises(nsr.NSError) as e:
+        B.submit(As[:2], bs[:2], ths[:2])           # n = 40 > max_n = 32
+    assert e.value.status == nsr.NS_ENOMEM
+    B2 = nsr.Batch(max_n=64, max_count=2, slots=2)
+    with pytest.raises(nsr.NSError) as e:
+        B2.submit(As, bs, ths)                       # 3 systems > max_count = 2
+    assert e.value.status == nsr.NS_ENOMEM
+    t = B2.submit(As[:2], bs[:2], ths[:2])
+    with pytest.raises(nsr.NSError) as e:
+        B2.submit(As[:2], bs[:2], ths[:2])
+    assert e.value.status == nsr.NS_EBUSY
+    reps = B2.poll(t, wait=True)
+    assert all(r.status == nsr.NS_OK for r in reps)
+    with pytest.raises(nsr.NSError):
+        B2.poll(t, wait=True)                        # already collected
+
+
+def test_batch_autotune(torch):
+    rng = np.random.default_rng(5)
+    systems = [inputs.harmonic_gram(int(m), seed=int(rng.integers(1 << 30)))
+               for m in rng.integers(8, 64, size=48)]
+    As, bs, ths = upload(torch, systems)
+    B = nsr.Batch(max_n=128, max_count=64, slots=64)
+    waves, groups, ms = B.autotune(As, bs, ths, order=4, resid_tol=1e-10)
+    assert waves in (1, 2, 4) and 1 <= groups <= 64 and ms > 0
+    for t in ths:
+        t.zero_()
+    reps = B.poll(B.submit(As, bs, ths, order=4, resid_tol=1e-10), wait=True)
+    check_against_oracle(systems, ths, reps, 4, 1e-10, sample=range(0, 48, 6))

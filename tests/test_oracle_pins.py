@@ -278,18 +278,55 @@ def test_iterates_symmetric():
 
 def test_stop_rule():
     chk = oracle.stop_check
-    # slow start with ratios near 1 is not a floor
-    h = [64.0, 63.9, 63.7, 60.0]
-    assert chk(h, 0.0, 3, 64) is None
-    # fast regime entered, then stagnation: floor
-    h = [64.0, 50.0, 10.0, 1e-3, 4e-11, 3.9e-11]
-    assert chk(h, 0.0, 4, 64) is None
-    assert chk(h, 0.0, 5, 64) == "floor"
-    assert chk(h, 0.0, 5, 64, floor_detect=False) is None
-    assert chk(h, 1e-10, 4, 64) == "f_tol"
+    # fast contraction: continue, no probe needed
+    f = [64.0, 20.0, 1.0]
+    assert not oracle.floor_probe_needed(f, 2)
+    assert chk(f, 0.0, 2, 64) is None
+    # ratio > 1/2 and F^2 as large as F (slow mode): continue
+    f = [64.0, 50.0, 10.0, 8.0]
+    assert oracle.floor_probe_needed(f, 3)
+    assert chk(f, 0.0, 3, 64, f_sq=7.9) is None
+    # ratio > 1/2 but ||F^2|| << ||F||: rounding floor
+    f = [64.0, 50.0, 10.0, 1e-3, 4e-11, 3.9e-11]
+    assert chk(f, 0.0, 5, 64, f_sq=1e-20) == "floor"
+    assert chk(f, 0.0, 5, 64, floor_detect=False) is None
+    assert chk(f, 1e-10, 4, 64) == "f_tol"
     assert chk([1.0, 2.0], 0.0, 1, 64) == "diverged"
     assert chk([1.0, float("nan")], 0.0, 1, 64) == "diverged"
-    assert chk([1.0, 0.9], 0.0, 1, 1) == "k_max"
+    assert chk([1.0, 0.9], 0.0, 1, 1, f_sq=0.8) == "k_max"
+    with pytest.raises(ValueError):
+        chk([1.0, 0.9], 0.0, 1, 64)
+
+
+def test_floor_rule_is_sound_in_exact_arithmetic():
+    """For symmetric F with eigenvalues in (-1, 1) and F_k = F_{k-1}^n:
+    ||F_k|| > ||F_{k-1}|| / 2 never happens together with ||F_k^2|| <= ||F_k|| / 4
+    when the ratio bound of the stop rule holds, i.e. the floor test cannot
+    fire on an exact iteration.  Checked on random spectra in exact-ish
+    float64 (no rounding floor at these sizes)."""
+    rng = np.random.default_rng(3)
+    for trial in range(300):
+        m = int(rng.integers(2, 40))
+        mu = rng.uniform(-1, 1, size=m) ** int(rng.integers(1, 6))
+        n = int(rng.choice([2, 3, 4, 8]))
+        prev = np.sqrt(np.sum(mu ** 2))
+        cur_mu = mu ** n
+        cur = np.sqrt(np.sum(cur_mu ** 2))
+        if cur < 1e-100 or prev < 1e-100:
+            continue
+        sq = np.sqrt(np.sum(cur_mu ** 4))
+        assert not (cur > 0.5 * prev and sq <= 0.25 * cur), (mu, n)
+
+
+def test_harmonic_slow_tail_not_a_floor():
+    """A harmonic-regressor Gram matrix whose ||F|| ratio exceeds 1/2 while a
+    slow mode persists: the solve must not stop there (it reaches 1e-10)."""
+    rng = np.random.default_rng(11)
+    ms = rng.integers(8, 41, size=24)
+    seeds = [int(rng.integers(1 << 30)) for _ in ms]
+    s = inputs.harmonic_gram(int(ms[6]), seed=seeds[6])
+    rep = oracle.solve(s.A, s.b, oracle.SolveOptions(order=4, resid_tol=1e-10))
+    assert rep.rel_resid <= 1e-10, (rep.ns_stop, rep.refine_stop, rep.fnorm_hist)
 
 
 def test_spd64_trace_and_floor():
