@@ -9,8 +9,9 @@ refinement to a relative residual of 1e-12.
 
 Also measured (extra keys of the same JSON line): the mixed-precision path
 (bf16 powers, float32 residual / G-side, float64 Richardson) on the same
-system, and the N = 8192, kappa = 1e6 composite (double Newton-Schulz, order
-8) workload in mixed precision next to the same solve in float64.
+system; the N = 8192, kappa = 1e6 composite (double Newton-Schulz, order 8)
+workload in mixed precision next to the same solve in float64; and a batch of
+2048 harmonic-regressor Gram systems of uneven size in one persistent launch.
 
 The float64 GEMM's roofline comes from per-launch HIP events recorded by the
 library on its stream during the timed region; the CPU baseline is the oracle
@@ -180,6 +181,54 @@ def run_composite(torch, nsr, steps, warmup):
     return out
 
 
+def run_batch(torch, nsr, reps_timed):
+    """2048 harmonic-regressor Gram systems, m ~ U{8..128} (N = 16..256), in
+    one persistent launch per solve of the whole batch: float32 MFMA order 4,
+    float64 refinement to 1e-10, float64 re-solve where float32 cannot."""
+    count = 2048
+    log(f"generating {count} harmonic Gram systems (seed 4)")
+    systems = inputs.harmonic_batch(count, seed=4)
+    As = [torch.from_numpy(s.A).to("cuda") for s in systems]
+    bs = [torch.from_numpy(s.b).to("cuda") for s in systems]
+    ths = [torch.zeros_like(b) for b in bs]
+    B = nsr.Batch(max_n=256, max_count=count,
+                  slots=min(count, 8 * torch.cuda.get_device_properties(0).multi_processor_count))
+    opts = dict(order=4, resid_tol=1e-10, refine_max=100)
+    waves, groups, tune_ms = B.autotune(As, bs, ths, **opts)
+    log(f"batch autotune: {waves} waves/workgroup, {groups} workgroups ({tune_ms:.1f} ms)")
+    times = []
+    reps = None
+    for i in range(reps_timed + 1):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        t = B.submit(As, bs, ths, **opts)
+        reps = B.poll(t, wait=True)
+        dt = time.perf_counter() - t0
+        if i > 0:
+            times.append(dt)
+        log(f"batch {'warmup' if i == 0 else 'run'} {i}: {dt * 1e3:.1f} ms")
+    mk = float(np.median(times))
+    flop = sum(r.gemm_flop for r in reps)
+    ok = sum(1 for r in reps if r.status == nsr.NS_OK)
+    esc = sum(1 for r in reps if r.precision == nsr.PREC_FP64)
+    rel = []
+    for s, th in zip(systems, ths):
+        x = th.cpu().numpy()
+        rel.append(float(np.linalg.norm(s.b - s.A @ x) / np.linalg.norm(s.b)))
+    rel = np.array(rel)
+    steps = np.array([r.ns_steps for r in reps])
+    return {
+        "workload": "harmonic_batch2048_m8-128_o4", "count": count,
+        "launch": {"waves_per_group": waves, "groups": groups},
+        "makespan_ms": mk * 1e3, "solves_per_s": count / mk,
+        "alg_tflops": flop / mk / 1e12,
+        "ok": ok, "escalated_to_fp64": esc, "not_converged": count - ok,
+        "rel_resid_max_ok": float(rel[[r.status == nsr.NS_OK for r in reps]].max()),
+        "rel_resid_p50": float(np.median(rel)),
+        "ns_steps_p50": float(np.median(steps)), "ns_steps_max": int(steps.max()),
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -300,6 +349,7 @@ def main():
         del ms
         torch.cuda.empty_cache()
         out["composite"] = run_composite(torch, nsr, max(2, args.steps // 2), 1)
+        out["batch"] = run_batch(torch, nsr, 3)
 
     if not args.no_cpu_baseline and not fixed:
         log("timing the CPU oracle on a bounded sample")
