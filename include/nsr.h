@@ -140,6 +140,15 @@ int ns_init_scale(ns_solver* s, int scale, double eps, double* alpha_out,
 int ns_step(ns_solver* s, int order, int factorization, int p, int w,
             double* fnorm_out);
 
+/* Symmetric power products (default on).  The products among powers of F
+ * (F^2, F^4, the identity-offset assembly; Tables 1-2) are polynomials in F
+ * and symmetric in exact arithmetic; with this on, each is computed on the
+ * tiles on or above the diagonal and mirrored (n^2 (n + 1) flop instead of
+ * 2 n^3).  The residual I - A G and the G-side / merge products always run in
+ * full: Newton-Schulz corrects a perturbation of G only when F is the exact
+ * residual of the G it multiplies.  Float64 mode only. */
+int ns_set_symmetric(ns_solver* s, int enable);
+
 /* Copy the current G_k into G_out (device, row-major float64, ldg >= n;
  * converted from float32 in the float32 / mixed modes). */
 int ns_get_G(ns_solver* s, double* G_out, int64_t ldg);
@@ -267,24 +276,34 @@ int ns_timing_read(ns_solver* s, int kind, int64_t* launches, double* total_ms,
                    double* flop);
 int ns_timing_reset(ns_solver* s);
 
+/* GEMM flags. */
+#define NS_GEMM_SYMMETRIC 1 /* symmetric output (m == n): only the tiles on
+                               or above the diagonal are computed from X Y
+                               (+ addends); the lower triangle is written as
+                               their mirror, so D is exactly symmetric.  Valid
+                               when X Y + E1 + E2 is symmetric in exact
+                               arithmetic (every product of the iteration is a
+                               polynomial in A). */
+
 /* Kernel-level entry point (tests, benchmarks): one float64 MFMA GEMM with
  * the solver's fused epilogue,
  *   D = diag * I + scale * (X Y) + E1 + E2,       X: m x k, Y: k x n,
  * E1 / E2 optional (NULL), row-major device float64 with leading dimensions.
- * D must not alias X or Y.  If sumsq_out is non-NULL it must point to
- * 1 + ns_gemm_f64_partials(m, n) device doubles: sumsq_out[0] receives
- * sum(D_ij^2), reduced in a fixed order, the rest is scratch for per-tile
- * partial sums.  Enqueued on hip_stream; does not synchronize.  Errors:
- * NS_EINVAL (negative size, NULL operand, ld too small, D aliasing X or Y),
- * NS_EHIP (launch failure). */
+ * flags: 0 or NS_GEMM_SYMMETRIC.  D must not alias X or Y.  If sumsq_out is
+ * non-NULL it must point to 1 + ns_gemm_f64_partials(m, n, flags) device
+ * doubles: sumsq_out[0] receives sum(D_ij^2) over the whole output, reduced
+ * in a fixed order, the rest is scratch for per-tile partial sums.
+ * Enqueued on hip_stream; does not synchronize.  Errors: NS_EINVAL
+ * (negative size, NULL operand, ld too small, D aliasing X or Y, unknown
+ * flags, symmetric with m != n), NS_EHIP (launch failure). */
 int ns_gemm_f64(void* hip_stream, int64_t m, int64_t n, int64_t k,
                 const double* X, int64_t ldx, const double* Y, int64_t ldy,
                 double* D, int64_t ldd, const double* E1, int64_t lde1,
                 const double* E2, int64_t lde2, double diag, double scale,
-                double* sumsq_out);
+                int flags, double* sumsq_out);
 
 /* Number of per-tile partial sums ns_gemm_f64 writes for an m x n output. */
-int64_t ns_gemm_f64_partials(int64_t m, int64_t n);
+int64_t ns_gemm_f64_partials(int64_t m, int64_t n, int flags);
 
 /* Kernel-level entry points of the float32 and bf16 MFMA GEMMs used by the
  * float32 and mixed modes (tests, benchmarks), with the same fused epilogue

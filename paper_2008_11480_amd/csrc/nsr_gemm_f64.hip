@@ -63,7 +63,18 @@ __device__ __forceinline__ void map_tile(int bid, int tiles_m, int tiles_n, int&
   tn = r / gm;
 }
 
-template <int BM, int BN, int BK, int NBUF, bool VEC>
+// Upper-triangular tile t (row-major over tm <= tn) of a T x T tile grid.
+__device__ __forceinline__ void sym_tile(int t, int T, int& tm, int& tn) {
+  int r = t, m = 0;
+  while (r >= T - m) {
+    r -= T - m;
+    ++m;
+  }
+  tm = m;
+  tn = m + r;
+}
+
+template <int BM, int BN, int BK, int NBUF, bool VEC, bool SYM>
 __global__ void __launch_bounds__(256)
 __attribute__((amdgpu_waves_per_eu(NSR_F64_WAVES_PER_EU)))
 gemm_f64_kernel(GemmF64Args p, int tiles_m, int tiles_n) {
@@ -79,17 +90,34 @@ gemm_f64_kernel(GemmF64Args p, int tiles_m, int tiles_n) {
   static_assert(XV >= 1 && YV >= 1, "tile too small for 256 threads");
   static_assert((BM * BK / 2) % NT == 0 && (BK * BN / 2) % NT == 0, "tile/thread mismatch");
 
-  __shared__ __attribute__((aligned(16))) double Xs[NBUF][BM * XS];
-  __shared__ __attribute__((aligned(16))) double Ys[NBUF][BK * YS];
+  // One LDS arena: the K-slab buffers, reused after the K loop to stage the
+  // transposed half-tiles of the mirrored write (symmetric output).
+  constexpr int MAIN = NBUF * (BM * XS + BK * YS);
+  constexpr int MS = BM + 1;                 // stride of the transposed staging
+  constexpr int MIRROR = SYM ? WTN * MS : 0;
+  constexpr int ARENA = MAIN > MIRROR ? MAIN : MIRROR;
+  __shared__ __attribute__((aligned(16))) double smem[ARENA];
   __shared__ double red[4];
+  double (*Xs)[BM * XS] = reinterpret_cast<double (*)[BM * XS]>(smem);
+  double (*Ys)[BK * YS] = reinterpret_cast<double (*)[BK * YS]>(smem + NBUF * BM * XS);
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = tid >> 6;
   const int wm = wave >> 1;
   const int wn = wave & 1;
-  int tm, tn;
-  map_tile(blockIdx.x, tiles_m, tiles_n, tm, tn);
+  int tm, tn, tile_id;
+  if (SYM) {
+    // Symmetric output: only tiles with tm <= tn (tiles_m == tiles_n).
+    const int nsym = tiles_m * (tiles_m + 1) / 2;
+    int t = blockIdx.x;
+    if ((nsym & 7) == 0) t = (t & 7) * (nsym >> 3) + (t >> 3);
+    sym_tile(t, tiles_m, tm, tn);
+    tile_id = t;
+  } else {
+    map_tile(blockIdx.x, tiles_m, tiles_n, tm, tn);
+    tile_id = tm * tiles_n + tn;
+  }
   const int64_t m0 = (int64_t)tm * BM;
   const int64_t n0 = (int64_t)tn * BN;
   const int64_t M = p.M, N = p.N, K = p.K;
@@ -188,9 +216,13 @@ gemm_f64_kernel(GemmF64Args p, int tiles_m, int tiles_n) {
     }
   }
 
-  // Epilogue: D = diag I + scale acc + E1 + E2, optional sum of D^2.
+  // Epilogue: D = diag I + scale acc + E1 + E2, optional sum of D^2.  With a
+  // symmetric output a diagonal tile writes its upper triangle and mirrors it
+  // element-wise; an off-diagonal tile writes itself and (below) its
+  // transpose through LDS.
   double ss = 0.0;
   const double diag = p.diag, scale = p.scale;
+  const bool diag_tile = SYM && (tm == tn);
 #pragma unroll
   for (int i = 0; i < FM; ++i) {
 #pragma unroll
@@ -204,10 +236,41 @@ gemm_f64_kernel(GemmF64Args p, int tiles_m, int tiles_n) {
           if (row == col) v += diag;
           if (p.E1) v += p.E1[row * p.lde1 + col];
           if (p.E2) v += p.E2[row * p.lde2 + col];
-          p.D[row * p.ldd + col] = v;
-          ss += v * v;
+          if (SYM) acc[i][j][r] = v;
+          if (!diag_tile) {
+            p.D[row * p.ldd + col] = v;
+            ss += (SYM ? 2.0 : 1.0) * v * v;
+          } else if (row <= col) {
+            p.D[row * p.ldd + col] = v;
+            if (row < col) p.D[col * p.ldd + row] = v;
+            ss += (row < col ? 2.0 : 1.0) * v * v;
+          }
         }
       }
+    }
+  }
+  if (SYM && !diag_tile) {
+    // Mirror D[n0.., m0..] = tile^T, one column half (wn) at a time.
+    double* S = smem;
+    __syncthreads();  // K-loop reads of the arena are done
+#pragma unroll
+    for (int half = 0; half < 2; ++half) {
+      if (wn == half) {
+#pragma unroll
+        for (int i = 0; i < FM; ++i)
+#pragma unroll
+          for (int j = 0; j < FN; ++j)
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+              S[(j * 16 + lr) * MS + wm * WTM + i * 16 + lk + 4 * r] = acc[i][j][r];
+      }
+      __syncthreads();
+      for (int idx = tid; idx < WTN * BM; idx += NT) {
+        const int c = idx / BM, rr = idx % BM;
+        const int64_t grow = n0 + half * WTN + c, gcol = m0 + rr;
+        if (grow < N && gcol < M) p.D[grow * p.ldd + gcol] = S[c * MS + rr];
+      }
+      __syncthreads();
     }
   }
   if (p.partial) {
@@ -215,7 +278,7 @@ gemm_f64_kernel(GemmF64Args p, int tiles_m, int tiles_n) {
     for (int off = 32; off > 0; off >>= 1) ss += __shfl_xor(ss, off, 64);
     if (lane == 0) red[wave] = ss;
     __syncthreads();
-    if (tid == 0) p.partial[(int64_t)tm * tiles_n + tn] = (red[0] + red[1]) + (red[2] + red[3]);
+    if (tid == 0) p.partial[tile_id] = (red[0] + red[1]) + (red[2] + red[3]);
   }
 }
 
@@ -223,37 +286,80 @@ template <int BM, int BN, int BK, int NBUF>
 int64_t launch_cfg(const GemmF64Args& a, hipStream_t st) {
   const int tiles_m = (int)((a.M + BM - 1) / BM);
   const int tiles_n = (int)((a.N + BN - 1) / BN);
-  const int64_t nt = (int64_t)tiles_m * tiles_n;
+  const int64_t nt = a.sym ? (int64_t)tiles_m * (tiles_m + 1) / 2 : (int64_t)tiles_m * tiles_n;
   const bool vec = ((a.ldx & 1) == 0) && ((a.ldy & 1) == 0) &&
                    ((reinterpret_cast<uintptr_t>(a.X) & 15) == 0) &&
                    ((reinterpret_cast<uintptr_t>(a.Y) & 15) == 0);
   dim3 grid((unsigned)nt), block(256);
-  if (vec)
-    hipLaunchKernelGGL((gemm_f64_kernel<BM, BN, BK, NBUF, true>), grid, block, 0, st, a, tiles_m,
-                       tiles_n);
-  else
-    hipLaunchKernelGGL((gemm_f64_kernel<BM, BN, BK, NBUF, false>), grid, block, 0, st, a, tiles_m,
-                       tiles_n);
+  if (a.sym) {
+    if (vec)
+      hipLaunchKernelGGL((gemm_f64_kernel<BM, BN, BK, NBUF, true, true>), grid, block, 0, st, a,
+                         tiles_m, tiles_n);
+    else
+      hipLaunchKernelGGL((gemm_f64_kernel<BM, BN, BK, NBUF, false, true>), grid, block, 0, st, a,
+                         tiles_m, tiles_n);
+  } else {
+    if (vec)
+      hipLaunchKernelGGL((gemm_f64_kernel<BM, BN, BK, NBUF, true, false>), grid, block, 0, st, a,
+                         tiles_m, tiles_n);
+    else
+      hipLaunchKernelGGL((gemm_f64_kernel<BM, BN, BK, NBUF, false, false>), grid, block, 0, st, a,
+                         tiles_m, tiles_n);
+  }
   if (hipGetLastError() != hipSuccess) return -1;
   return a.partial ? nt : 0;
 }
 
-// Big tiles when they still give at least two workgroups per CU.
-bool use_big(int64_t m, int64_t n) {
-  const int64_t tiles = ((m + 127) / 128) * ((n + 127) / 128);
-  return tiles >= 512;
+int device_cus() {
+  static int cus = 0;
+  if (cus == 0) {
+    int dev = 0, v = 0;
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && v > 0)
+      cus = v;
+    else
+      cus = 256;
+  }
+  return cus;
+}
+
+// Tile shape: 128 x 128 (two workgroups per CU) or 64 x 64 (four per CU).
+// Time ~ rounds of resident workgroups x time of one tile; a partial last
+// round costs about half a round (its tiles run with less contention), and a
+// 64 x 64 tile takes 0.54 of a 128 x 128 one at the same K.  Fitted to the
+// measured full / symmetric GEMMs at N = 2048, 4096, 8192; the rule picks the
+// faster shape in all six.  NSR_F64_FORCE_TILE (128 or 64) overrides it.
+#ifndef NSR_F64_FORCE_TILE
+#define NSR_F64_FORCE_TILE 0
+#endif
+double eff_rounds(int64_t tiles, int64_t slots) {
+  const int64_t full = tiles / slots, rem = tiles % slots;
+  return (double)full + (rem == 0 ? 0.0 : (2 * rem >= slots ? 1.0 : 0.5));
+}
+bool use_big_shape(int64_t m, int64_t n, bool sym) {
+  if (NSR_F64_FORCE_TILE == 128) return true;
+  if (NSR_F64_FORCE_TILE == 64) return false;
+  const int64_t cus = device_cus();
+  auto count = [&](int64_t b) {
+    const int64_t tm = (m + b - 1) / b, tn = (n + b - 1) / b;
+    return sym ? tm * (tm + 1) / 2 : tm * tn;
+  };
+  return eff_rounds(count(128), 2 * cus) <= 0.54 * eff_rounds(count(64), 4 * cus);
 }
 
 }  // namespace
 
-int64_t gemm_f64_partials(int64_t m, int64_t n) {
-  if (use_big(m, n)) return ((m + 127) / 128) * ((n + 127) / 128);
-  return ((m + 63) / 64) * ((n + 63) / 64);
+int64_t gemm_f64_partials(int64_t m, int64_t n, bool sym) {
+  const int64_t b = use_big_shape(m, n, sym) ? 128 : 64;
+  const int64_t tm = (m + b - 1) / b, tn = (n + b - 1) / b;
+  return sym ? tm * (tm + 1) / 2 : tm * tn;
 }
 
 int64_t launch_gemm_f64(const GemmF64Args& a, hipStream_t st) {
   if (a.M <= 0 || a.N <= 0) return 0;
-  if (use_big(a.M, a.N)) return launch_cfg<128, 128, NSR_F64_BIG_BK, NSR_F64_BIG_NBUF>(a, st);
+  if (a.sym && a.M != a.N) return -1;
+  if (use_big_shape(a.M, a.N, a.sym))
+    return launch_cfg<128, 128, NSR_F64_BIG_BK, NSR_F64_BIG_NBUF>(a, st);
   return launch_cfg<64, 64, 16, 2>(a, st);
 }
 

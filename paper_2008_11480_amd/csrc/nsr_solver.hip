@@ -62,7 +62,8 @@ constexpr int kPlainMats = 7;
 constexpr int kCompositeMats = 11;
 
 int64_t partial_capacity(int64_t n) {
-  int64_t c = gemm_f64_partials(n, n);
+  int64_t c = gemm_f64_partials(n, n, false);
+  c = c > gemm_f64_partials(n, n, true) ? c : gemm_f64_partials(n, n, true);
   c = c > gemm_lp_partials(n, n) ? c : gemm_lp_partials(n, n);
   c = c > sumsq_partials(n) ? c : sumsq_partials(n);
   c = c > gemv_partials(n) ? c : gemv_partials(n);
@@ -128,8 +129,10 @@ struct ns_solver {
   bool g_implicit = true;  // G = I / alpha, not materialised
   bool dns_started = false;
   bool p0_is_f2 = false;   // P[0] holds F_k^2 (computed by the floor test)
+  bool symmetric = true;   // products with symmetric output (upper tiles + mirror)
   double alpha = 0.0;
   int64_t mmm = 0;
+  double flop = 0.0;       // algorithmic flop of the products since ns_init_scale
 
   bool timing = false;
   std::vector<TimedLaunch> timed;
@@ -180,6 +183,14 @@ int mm(ns_solver* s, Mat& D, const Mat* X, const Mat& Y, const Mat* E1, const Ma
     a.diag = diag;
     a.scale = scale;
     a.partial = want_norm ? s->partial : nullptr;
+    // Only products among powers of F get a symmetric output.  The residual
+    // I - A G and the G-side / merge products stay full: Newton-Schulz
+    // corrects any perturbation of G only if F is the exact residual of the
+    // G it multiplies, and mirroring those products would feed the part of
+    // the rounding error that does not commute with A back with a gain ~kappa
+    // per step.  Errors in the powers only perturb P(F) and enter F_{k+1} as
+    // O(||F|| ||[A, G]||).
+    a.sym = (s->symmetric && kind == K_POWER) ? 1 : 0;
     np = launch_gemm_f64(a, s->stream);
     tkind = 1;
   } else {
@@ -203,12 +214,16 @@ int mm(ns_solver* s, Mat& D, const Mat* X, const Mat& Y, const Mat* E1, const Ma
     tkind = bf ? 3 : 2;
   }
   if (np < 0) return fail(NS_EHIP, "GEMM launch failed: %s", hipGetErrorString(hipGetLastError()));
+  // algorithmic flop: 2 n^3, or n^2 (n + 1) when only one triangle is formed
+  const double nn = (double)s->n;
+  const bool half = is_f64(s) && s->symmetric && kind == K_POWER;
+  const double flop = half ? nn * nn * (nn + 1.0) : 2.0 * nn * nn * nn;
   if (s->timing) {
     HIP_TRY(hipEventRecord(ee, s->stream));
-    const double nn = (double)s->n;
-    s->timed.push_back(TimedLaunch{eb, ee, tkind, 2.0 * nn * nn * nn});
+    s->timed.push_back(TimedLaunch{eb, ee, tkind, flop});
   }
   s->mmm += 1;
+  s->flop += flop;
   if (want_norm) launch_reduce(s->partial, np, s->scal + 1, 2, 0.0, s->stream);
   return NS_OK;
 }
@@ -595,6 +610,7 @@ int ns_init_scale(ns_solver* s, int scale, double eps, double* alpha_out, double
   s->gcur = 0;
   s->lcur = 0;
   s->mmm = 0;
+  s->flop = 0.0;
   if (alpha_out) *alpha_out = s->alpha;
   if (fnorm0_out) {
     if (int rc = read_scalars(s, host, 1, 1)) return rc;
@@ -780,8 +796,7 @@ int richardson_ns_solve(ns_solver* s, const double* b, double* theta, const ns_s
   R->refine_stop = refine_stop;
   R->rel_resid = rel;
   R->mmm = s->mmm;
-  const double nn = (double)s->n;
-  R->gemm_flop = 2.0 * nn * nn * nn * (double)s->mmm;
+  R->gemm_flop = s->flop;
   if (ns_stop == NS_STOP_DIVERGED || refine_stop == NS_STOP_DIVERGED)
     status = NS_EDIVERGED;
   else if (refine_stop != NS_STOP_RESID_TOL)
@@ -790,6 +805,12 @@ int richardson_ns_solve(ns_solver* s, const double* b, double* theta, const ns_s
   if (hipGetLastError() != hipSuccess) return fail(NS_EHIP, "kernel launch failed");
   if (status == NS_EDIVERGED) return fail(NS_EDIVERGED, "iteration diverged");
   if (status == NS_ENOCONV) return fail(NS_ENOCONV, "resid_tol not reached (%g)", rel);
+  return NS_OK;
+}
+
+int ns_set_symmetric(ns_solver* s, int enable) {
+  if (int rc = check_solver(s)) return rc;
+  s->symmetric = enable != 0;
   return NS_OK;
 }
 
@@ -826,16 +847,18 @@ int ns_timing_read(ns_solver* s, int kind, int64_t* launches, double* total_ms, 
   return NS_OK;
 }
 
-int64_t ns_gemm_f64_partials(int64_t m, int64_t n) {
+int64_t ns_gemm_f64_partials(int64_t m, int64_t n, int flags) {
   if (m <= 0 || n <= 0) return 0;
-  return gemm_f64_partials(m, n);
+  return gemm_f64_partials(m, n, (flags & NS_GEMM_SYMMETRIC) != 0);
 }
 
 int ns_gemm_f64(void* hip_stream, int64_t m, int64_t n, int64_t k, const double* X, int64_t ldx,
                 const double* Y, int64_t ldy, double* D, int64_t ldd, const double* E1,
                 int64_t lde1, const double* E2, int64_t lde2, double diag, double scale,
-                double* sumsq_out) {
+                int flags, double* sumsq_out) {
   if (m < 0 || n < 0 || k < 0) return fail(NS_EINVAL, "negative size");
+  if (flags & ~NS_GEMM_SYMMETRIC) return fail(NS_EINVAL, "unknown flags");
+  if ((flags & NS_GEMM_SYMMETRIC) && m != n) return fail(NS_EINVAL, "symmetric output needs m == n");
   if (m == 0 || n == 0) return NS_OK;
   if (!D || (k > 0 && (!X || !Y))) return fail(NS_EINVAL, "null operand");
   if ((k > 0 && (ldx < k || ldy < n)) || ldd < n) return fail(NS_EINVAL, "leading dimension too small");
@@ -858,6 +881,7 @@ int ns_gemm_f64(void* hip_stream, int64_t m, int64_t n, int64_t k, const double*
   a.K = k;
   a.diag = diag;
   a.scale = scale;
+  a.sym = (flags & NS_GEMM_SYMMETRIC) ? 1 : 0;
   // Per-tile partials live after the first element of sumsq_out.
   double* part = sumsq_out ? sumsq_out + 1 : nullptr;
   a.partial = part;

@@ -35,7 +35,8 @@ HIST_R = 200
 # Every exported symbol of include/nsr.h, for the load check.
 EXPORTS = (
     "ns_workspace_bytes", "ns_create", "ns_destroy", "ns_bind", "ns_init_scale", "ns_step",
-    "ns_get_G", "ns_get_F", "ns_richardson_step", "richardson_ns_solve", "ns_timing_enable",
+    "ns_get_G", "ns_get_F", "ns_richardson_step", "richardson_ns_solve", "ns_set_symmetric",
+    "ns_timing_enable",
     "ns_timing_read", "ns_timing_reset", "ns_gemm_f64", "ns_gemm_f64_partials",
     "ns_gemm_f32", "ns_gemm_bf16_nt", "ns_gemm_lp_partials",
     "ns_batch_workspace_bytes", "ns_batch_create", "ns_batch_set_launch", "ns_batch_submit",
@@ -108,12 +109,13 @@ def lib() -> ctypes.CDLL:
         "ns_richardson_step": (ci, [vp, vp, vp, pd]),
         "richardson_ns_solve": (ci, [vp, vp, vp, ctypes.POINTER(SolveOpts),
                                      ctypes.POINTER(SolveReportC)]),
+        "ns_set_symmetric": (ci, [vp, ci]),
         "ns_timing_enable": (ci, [vp, ci]),
         "ns_timing_read": (ci, [vp, ci, ctypes.POINTER(i64), pd, pd]),
         "ns_timing_reset": (ci, [vp]),
         "ns_gemm_f64": (ci, [vp, i64, i64, i64, vp, i64, vp, i64, vp, i64, vp, i64, vp, i64,
-                             dbl, dbl, vp]),
-        "ns_gemm_f64_partials": (i64, [i64, i64]),
+                             dbl, dbl, ci, vp]),
+        "ns_gemm_f64_partials": (i64, [i64, i64, ci]),
         "ns_gemm_f32": (ci, [vp, i64, i64, i64, vp, i64, vp, i64, vp, i64, vp, i64, vp, i64, vp,
                              i64, ctypes.c_float, ctypes.c_float, vp]),
         "ns_gemm_bf16_nt": (ci, [vp, i64, i64, i64, vp, i64, vp, i64, vp, i64, vp, i64, vp, i64,
@@ -205,6 +207,9 @@ class Solver:
         except Exception:
             pass
 
+    def set_symmetric(self, enable: bool):
+        check(lib().ns_set_symmetric(self._h, 1 if enable else 0))
+
     def bind(self, A):
         _require_cuda_f64(A, "A")
         if A.dim() != 2 or A.shape[0] != self.n or A.shape[1] != self.n or A.stride(1) != 1:
@@ -283,9 +288,13 @@ class Solver:
         return n.value, ms.value, fl.value
 
 
+GEMM_SYMMETRIC = 1
+
+
 def gemm_f64(X, Y, D=None, E1=None, E2=None, diag: float = 0.0, scale: float = 1.0,
-             want_sumsq: bool = False, stream=None):
-    """``D = diag I + scale X Y + E1 + E2`` through the library's MFMA GEMM."""
+             want_sumsq: bool = False, symmetric: bool = False, stream=None):
+    """``D = diag I + scale X Y + E1 + E2`` through the library's MFMA GEMM
+    (``symmetric``: upper tiles computed, lower triangle mirrored)."""
     import torch
     for t, nm in ((X, "X"), (Y, "Y")):
         _require_cuda_f64(t, nm)
@@ -295,15 +304,16 @@ def gemm_f64(X, Y, D=None, E1=None, E2=None, diag: float = 0.0, scale: float = 1
         raise ValueError("inner dimensions differ")
     if D is None:
         D = torch.empty(m, n, dtype=torch.float64, device=X.device)
+    flags = GEMM_SYMMETRIC if symmetric else 0
     ss = None
     if want_sumsq:
-        ss = torch.zeros(1 + int(lib().ns_gemm_f64_partials(m, n)), dtype=torch.float64,
+        ss = torch.zeros(1 + int(lib().ns_gemm_f64_partials(m, n, flags)), dtype=torch.float64,
                          device=X.device)
     check(lib().ns_gemm_f64(_stream_handle(stream), m, n, k, _ptr(X), X.stride(0), _ptr(Y),
                             Y.stride(0), _ptr(D), D.stride(0), _ptr(E1),
                             E1.stride(0) if E1 is not None else 0, _ptr(E2),
                             E2.stride(0) if E2 is not None else 0, float(diag), float(scale),
-                            _ptr(ss)))
+                            flags, _ptr(ss)))
     return (D, ss[0]) if want_sumsq else D
 
 

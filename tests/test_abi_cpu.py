@@ -61,13 +61,17 @@ def test_host_argument_checks_without_gpu():
     assert b"precision" in L.ns_last_error()
     # GEMM argument checks
     assert L.ns_gemm_f64(None, -1, 1, 1, None, 1, None, 1, None, 1, None, 0, None, 0, 0.0, 1.0,
-                         None) == nsr.NS_EINVAL
+                         0, None) == nsr.NS_EINVAL
     assert L.ns_gemm_f64(None, 4, 4, 4, 256, 2, 512, 4, 768, 4, None, 0, None, 0, 0.0, 1.0,
-                         None) == nsr.NS_EINVAL          # ldx < k
+                         0, None) == nsr.NS_EINVAL       # ldx < k
     assert L.ns_gemm_f64(None, 4, 4, 4, 256, 4, 512, 4, 256, 4, None, 0, None, 0, 0.0, 1.0,
-                         None) == nsr.NS_EINVAL          # D aliases X
+                         0, None) == nsr.NS_EINVAL       # D aliases X
+    assert L.ns_gemm_f64(None, 4, 5, 4, 256, 4, 512, 5, 768, 5, None, 0, None, 0, 0.0, 1.0,
+                         nsr.GEMM_SYMMETRIC, None) == nsr.NS_EINVAL   # symmetric needs m == n
+    assert L.ns_gemm_f64(None, 4, 4, 4, 256, 4, 512, 4, 768, 4, None, 0, None, 0, 0.0, 1.0,
+                         8, None) == nsr.NS_EINVAL       # unknown flag
     assert L.ns_gemm_f64(None, 0, 4, 4, None, 4, None, 4, None, 4, None, 0, None, 0, 0.0, 1.0,
-                         None) == nsr.NS_OK              # empty output: nothing to do
+                         0, None) == nsr.NS_OK           # empty output: nothing to do
     # null handles
     assert L.ns_bind(None, 256, 64) == nsr.NS_EINVAL
     assert L.ns_step(None, 8, 1, 0, 0, None) == nsr.NS_EINVAL
@@ -76,7 +80,11 @@ def test_host_argument_checks_without_gpu():
 
 def test_gemm_partials_count():
     L = nsr.lib()
-    assert L.ns_gemm_f64_partials(64, 64) == 1
-    assert L.ns_gemm_f64_partials(65, 64) == 2
-    assert L.ns_gemm_f64_partials(4096, 4096) == 32 * 32
-    assert L.ns_gemm_f64_partials(0, 5) == 0
+    assert L.ns_gemm_f64_partials(64, 64, 0) == 1
+    assert L.ns_gemm_f64_partials(65, 64, 0) == 2
+    assert L.ns_gemm_f64_partials(0, 5, 0) == 0
+    # symmetric output: tiles on or above the diagonal only
+    t = L.ns_gemm_f64_partials(1000, 1000, 0)
+    ts = L.ns_gemm_f64_partials(1000, 1000, nsr.GEMM_SYMMETRIC)
+    side = int(round(t ** 0.5))
+    assert side * side == t and ts == side * (side + 1) // 2

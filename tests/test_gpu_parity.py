@@ -72,6 +72,28 @@ def test_gemm_f64_elementwise(torch, m, n, k, odd_ld):
     assert abs(float(ss.cpu()) - ss_ref) <= 1e-13 * ss_ref
 
 
+@pytest.mark.parametrize("n", [1, 5, 64, 100, 257, 1000, 2900, 4096])
+def test_gemm_f64_symmetric_output(torch, n):
+    """Symmetric output: the upper triangle obeys the element-wise bound, the
+    result is exactly symmetric, and the sum of squares covers both halves."""
+    rng = np.random.default_rng(n + 3)
+    B = rng.standard_normal((n, n))
+    S = 0.5 * (B + B.T)
+    E = rng.standard_normal((n, n))
+    E = 0.5 * (E + E.T)
+    D, ss = nsr.gemm_f64(to_dev(torch, S), to_dev(torch, S), E1=to_dev(torch, E), diag=1.0,
+                         scale=-0.5, want_sumsq=True, symmetric=True)
+    torch.cuda.synchronize()
+    got = D.cpu().numpy()
+    assert np.array_equal(got, got.T)
+    ref = -0.5 * (S @ S) + np.eye(n) + E
+    bound = gamma(n + 4) * (0.5 * (np.abs(S) @ np.abs(S)) + np.eye(n) + np.abs(E))
+    iu = np.triu_indices(n)
+    assert np.all(np.abs(got - ref)[iu] <= 2 * bound[iu])
+    ssr = float(np.sum(got * got))
+    assert abs(float(ss.cpu()) - ssr) <= 1e-13 * ssr
+
+
 def test_gemm_f64_no_addends(torch):
     rng = np.random.default_rng(5)
     X = rng.standard_normal((200, 300))
@@ -114,24 +136,29 @@ def compare_traces(h_gpu, h_orc, rel=1e-10, floor_mult=10.0, n_cmp=None):
         assert d <= rel * abs(h_orc[k]) + floor_mult * floor, (k, h_gpu[k], h_orc[k], floor)
 
 
-def gpu_solve(torch, sysm, **kw):
+def gpu_solve(torch, sysm, symmetric=True, **kw):
     A = to_dev(torch, sysm.A)
     b = to_dev(torch, sysm.b)
     th = torch.zeros_like(b)
     s = nsr.Solver(sysm.n, composite=kw.get("form") == "composite_double")
+    s.set_symmetric(symmetric)
     s.bind(A)
     rep = s.solve(b, th, **kw)
     torch.cuda.synchronize()
     return th.cpu().numpy(), rep
 
 
-def test_spd64_twelve_steps_matches_oracle(torch):
+@pytest.mark.parametrize("symmetric", [True, False])
+def test_spd64_twelve_steps_matches_oracle(torch, symmetric):
     """N=64, kappa=100, order 4 (I+F)(I+F^2), 12 steps, coupled Richardson,
-    target relative residual 1e-13."""
+    target relative residual 1e-13.  All 12 steps stay at the float64 floor
+    (a regression check: mirroring the residual or G-side products would let
+    the non-commuting rounding error grow ~kappa per step)."""
     w = inputs.WORKLOADS["spd64_k1e2_o4"]
     sysm = inputs.spd_qlq(w["n"], w["kappa"], w["seed"])
-    th, rep = gpu_solve(torch, sysm, order=4, form="squaring", k_max=12, floor_detect=False,
-                        resid_tol=1e-13)
+    th, rep = gpu_solve(torch, sysm, symmetric=symmetric, order=4, form="squaring", k_max=12,
+                        floor_detect=False, resid_tol=1e-13)
+    assert max(rep.fnorm_hist[8:]) < 1e-12
     orc = oracle.solve(sysm.A, sysm.b, oracle.SolveOptions(order=4, k_max=12,
                                                            floor_detect=False,
                                                            resid_tol=1e-13))
@@ -172,10 +199,12 @@ SOLVE_CASES = [
 ]
 
 
+@pytest.mark.parametrize("symmetric", [True, False])
 @pytest.mark.parametrize("n,kappa,order,form,p,w", SOLVE_CASES)
-def test_solve_matches_oracle(torch, n, kappa, order, form, p, w):
+def test_solve_matches_oracle(torch, n, kappa, order, form, p, w, symmetric):
     sysm = inputs.spd_qlq(n, kappa, seed=100 + n)
-    th, rep = gpu_solve(torch, sysm, order=order, form=form, p=p, w=w, resid_tol=1e-13)
+    th, rep = gpu_solve(torch, sysm, symmetric=symmetric, order=order, form=form, p=p, w=w,
+                        resid_tol=1e-13)
     oform = "squaring" if form == "composite_double" else form
     orc = oracle.solve(sysm.A, sysm.b, oracle.SolveOptions(
         order=order, form=oform, p=p if form.startswith("unified") else None,
@@ -216,7 +245,8 @@ def test_solve_is_deterministic(torch):
     assert r1.fnorm_hist == r2.fnorm_hist
 
 
-def test_full_size_spd4096(torch):
+@pytest.mark.parametrize("symmetric", [True, False])
+def test_full_size_spd4096(torch, symmetric):
     """N=4096, kappa=1e4, order 8 squaring to the ||F|| floor with Richardson
     refinement: the launch configuration the benchmark times.  Checked against
     properties that hold at any size: the eigen closed form of ||F_k||
@@ -224,7 +254,7 @@ def test_full_size_spd4096(torch):
     import scipy.linalg
     w = inputs.WORKLOADS["spd4096_k1e4_o8"]
     sysm = inputs.spd_qlq(w["n"], w["kappa"], w["seed"])
-    th, rep = gpu_solve(torch, sysm, order=8, form="squaring", k_max=64,
+    th, rep = gpu_solve(torch, sysm, symmetric=symmetric, order=8, form="squaring", k_max=64,
                         resid_tol=w["resid_tol"])
     assert rep.ns_stop in ("floor", "f_tol")
     mu = 1.0 - sysm.lam / rep.alpha
@@ -290,4 +320,5 @@ def test_timing_counts_every_gemm(torch):
     rep = s.solve(b, th, order=8)
     cnt, ms, fl = s.timing_read(0)
     assert cnt == rep.mmm and ms > 0.0
-    assert fl == pytest.approx(2.0 * 256 ** 3 * rep.mmm)
+    assert 256.0 ** 2 * 257 * rep.mmm < fl < 2.0 * 256 ** 3 * rep.mmm   # powers halved
+    assert rep.gemm_flop == pytest.approx(fl)
