@@ -10,8 +10,9 @@ refinement to a relative residual of 1e-12.
 Also measured (extra keys of the same JSON line): the mixed-precision path
 (bf16 powers, float32 residual / G-side, float64 Richardson) on the same
 system; the N = 8192, kappa = 1e6 composite (double Newton-Schulz, order 8)
-workload in mixed precision next to the same solve in float64; and a batch of
-2048 harmonic-regressor Gram systems of uneven size in one persistent launch.
+workload in mixed precision next to the same solve in float64; a batch of
+2048 harmonic-regressor Gram systems of uneven size in one persistent launch;
+and a serving run (Poisson arrivals, sizes 32..2048) with p50/p99 latency.
 
 The float64 GEMM's roofline comes from per-launch HIP events recorded by the
 library on its stream during the timed region; the CPU baseline is the oracle
@@ -230,6 +231,33 @@ def run_batch(torch, nsr, reps_timed):
     }
 
 
+def run_serving(torch, nsr, duration_s=3.0, rate=2000.0):
+    """Poisson arrivals at `rate` req/s for `duration_s` s; N log-uniform in
+    32..2048, kappa log-uniform in 10..1e6, mixed precision to 1e-10."""
+    from paper_2008_11480_amd.serve import GpuExecutor, Server, make_requests
+    trace = inputs.serving_trace(rate, duration_s, seed=5)
+    log(f"generating {len(trace)} serving requests on the GPU")
+    reqs = make_requests(trace)
+    torch.cuda.synchronize()
+    ex = GpuExecutor(workers=6, precision=nsr.PREC_MIXED_BF16)
+    # warm up the kernels and the allocator on a few requests of each path
+    warm = make_requests(inputs.serving_trace(rate, 0.02, seed=55))
+    Server(ex, budget_bytes=32 << 30, workers=6).run(warm)
+    srv = Server(ex, budget_bytes=32 << 30, workers=6)
+    log("serving")
+    st = srv.run(reqs)
+    torch.cuda.synchronize()
+    rel = []
+    for r in reqs:
+        if r.status == "ok":
+            A, b, th = r.payload[:3]
+            rel.append(float(torch.linalg.norm(b - A @ th) / torch.linalg.norm(b)))
+    st["rel_resid_max"] = max(rel) if rel else None
+    st["workload"] = f"serving_poisson{int(rate)}_{duration_s:g}s_n32-2048_k10-1e6"
+    st.pop("not_ok", None)
+    return st
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -355,6 +383,7 @@ def main():
         torch.cuda.empty_cache()
         out["composite"] = run_composite(torch, nsr, max(2, args.steps // 2), 1)
         out["batch"] = run_batch(torch, nsr, 3)
+        out["serving"] = run_serving(torch, nsr)
 
     if not args.no_cpu_baseline and not fixed:
         log("timing the CPU oracle on a bounded sample")

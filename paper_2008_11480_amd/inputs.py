@@ -102,6 +102,48 @@ def spd_qlq_device(n: int, kappa: float, seed: int, device="cuda"):
     return a.contiguous(), torch.from_numpy(b).to(device), lt, q.contiguous()
 
 
+def spd_householder_device(n: int, kappa: float, seed: int, reflectors: int = 4,
+                           device="cuda"):
+    """Serving-size SPD system on ``device``: ``A = Q diag(lam) Q^T`` with ``Q``
+    a product of ``reflectors`` seeded Householder reflections (``O(n^2)`` work
+    each, so requests are cheap to make), ``lam`` log-uniform in
+    ``[1, kappa]`` with both ends pinned, ``b ~ N(0, 1)``.  The method's
+    convergence depends only on ``lam`` and ``alpha``.  Returns torch tensors
+    ``(A, b, lam, V)`` (float64); ``V`` holds the reflection vectors as rows,
+    applied in order (``Q = H_1 H_2 ... H_r`` acting on ``diag(lam)``)."""
+    import torch
+    rng = np.random.default_rng(seed)
+    lam = loguniform_spectrum(n, kappa, rng)
+    vs = rng.standard_normal((reflectors, n))
+    b = rng.standard_normal(n)
+    a = torch.diag(torch.from_numpy(lam).to(device))
+    V = torch.from_numpy(vs).to(device)
+    for i in range(reflectors - 1, -1, -1):
+        v = V[i]
+        sv = torch.dot(v, v)
+        w = a @ v
+        # H a H with H = I - 2 v v^T / s: a rank-2 update
+        a = (a - (2.0 / sv) * (torch.outer(v, w) + torch.outer(w, v))
+             + (4.0 * torch.dot(v, w) / (sv * sv)) * torch.outer(v, v))
+    a = 0.5 * (a + a.T)
+    return (a.contiguous(), torch.from_numpy(b).to(device), torch.from_numpy(lam).to(device), V)
+
+
+def householder_solve_device(lam, V, b):
+    """``A^{-1} b`` for a system from :func:`spd_householder_device`
+    (``Q diag(1/lam) Q^T b`` with the same reflections): a closed form."""
+    import torch
+    x = b.clone()
+    for i in range(V.shape[0]):            # Q^T b = H_r ... H_1 b
+        v = V[i]
+        x = x - (2.0 * torch.dot(v, x) / torch.dot(v, v)) * v
+    x = x / lam
+    for i in range(V.shape[0] - 1, -1, -1):   # Q y = H_1 ... H_r y
+        v = V[i]
+        x = x - (2.0 * torch.dot(v, x) / torch.dot(v, v)) * v
+    return x
+
+
 def spd_diag(lam: np.ndarray, seed: int) -> SPDSystem:
     """Diagonal SPD system with the given spectrum and ``b ~ N(0,1)``."""
     rng = np.random.default_rng(seed)
