@@ -174,6 +174,12 @@ typedef struct {
   double f_tol;       /* stop Newton-Schulz when ||F_k||_F <= f_tol          */
   double resid_tol;   /* target of ||b - A theta||_2 / ||b||_2               */
   int theta0_mode;    /* 0: theta_0 = G_0 b;  1: theta_0 = 0;  2: caller's   */
+  int accel_q;        /* 0: Richardson with omega_k = G_k (eq. redttk1).
+                         q >= 1 (composite form only): the high-order
+                         accelerator of eq. (ttk1), omega_k = L_k +
+                         Gamma_k^n {sum_{j<q} F_k^j} G_k (mirrored), applied
+                         as q + 2 mat-vecs, with theta_0 = L_0 b; the error
+                         contracts by F_k^q Gamma_k^n per step (eq. riem1) */
 } ns_solve_opts;
 
 #define NS_HIST_F 65

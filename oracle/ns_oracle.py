@@ -33,7 +33,8 @@ __all__ = [
     "MMCounter", "alpha_frobenius", "alpha_inf_half", "splitting_condition",
     "residual", "z_horner", "z_unified", "z_unified_plus1", "z_squaring",
     "z_table", "TABLE_ORDERS", "z_form", "form_mmm", "ns_step",
-    "dns_init", "dns_step", "richardson_update", "SolveOptions", "SolveReport",
+    "dns_init", "dns_step", "richardson_update", "accelerator_apply", "SolveOptions",
+    "SolveReport", "riem6_gamma",
     "solve", "stop_check", "floor_probe_needed", "STOP", "efficiency_index",
 ]
 
@@ -246,6 +247,15 @@ def form_mmm(order, form, p=None, w=None) -> int:
     return ctr.n
 
 
+def riem6_gamma(k: int, n: int, h: int = 1) -> int:
+    """Eq. (riem6): exponent of ``S^{-1} D`` in the parameter error after k
+    accelerated steps with q = n, ``theta~_k = (S^{-1}D)^{gamma_k} theta~_0``."""
+    num = k * n ** (k + 2) - (k - 1) * n ** (k + 1) - 2 * n ** k - n + 2
+    g, rem = divmod(h * n * n * num, (n - 1) ** 2)
+    assert rem == 0
+    return g
+
+
 def efficiency_index(order: int, mmm: int) -> float:
     """Efficiency index ``order^(1/mmm)`` (eq. ei)."""
     return float(order) ** (1.0 / float(mmm))
@@ -303,6 +313,20 @@ def richardson_update(a, b, theta, g):
     ``omega_k = G_k``.  Returns ``(theta_k, r)`` where ``r = b - A theta_{k-1}``."""
     r = b - a @ theta
     return theta + g @ r, r
+
+
+def accelerator_apply(a, st: DNSState, r, q):
+    """Eq. (ttk1)'s operator on a vector, right orientation:
+    ``omega r = L_k r + G_k {sum_{j<q} F_k^j} Gamma_k^n r``, with ``L_k``,
+    ``Gamma_k^n = I - A L_k``, ``G_k`` and ``F_k = I - A G_k`` of the double
+    Newton-Schulz step (Section 5.1).  Then ``I - A omega = F_k^q Gamma_k^n``
+    (eq. riem1 mirrored), so the parameter error contracts by
+    ``F_k^q Gamma_k^n`` per step."""
+    t = st.Gam @ r
+    w = t
+    for _ in range(q - 1):
+        w = t + st.F @ w
+    return st.L @ r + st.G @ w
 
 
 # Stop reasons (shared meaning with the solver's report; values are the
@@ -364,7 +388,9 @@ class SolveOptions:
     resid_tol: float = 1e-12
     scale: str = "frobenius"       # or "inf_half"
     eps: float = 0.0               # for "inf_half"
-    theta0: str = "g0b"            # "g0b": theta_0 = G_0 b;  "zero"
+    theta0: str = "g0b"            # "g0b": theta_0 = G_0 b;  "zero";  "l0b": L_0 b
+    accel_q: int = 0               # >0: Richardson with the accelerator of eq. (ttk1),
+                                   # Neumann order q (composite form only)
 
 
 @dataclasses.dataclass
@@ -411,10 +437,14 @@ def solve(a, b, opts: SolveOptions = SolveOptions()) -> SolveReport:
         bnorm = 1.0
     g0 = eye / alpha
     theta = g0 @ b if opts.theta0 == "g0b" else np.zeros_like(b)
+    if opts.accel_q and not opts.composite:
+        raise ValueError("the accelerator of eq. (ttk1) needs the composite form")
 
     if opts.composite:
         st = dns_init(a, g0, opts.order, opts.form, opts.p, opts.w, ctr)
         g, f = st.G, st.F
+        if opts.theta0 == "l0b" or opts.accel_q:
+            theta = st.L @ b              # theta_0 = L_0 b (Section 6, below eq. riem6)
     else:
         g = g0
         f = residual(a, g, ctr)
@@ -427,7 +457,11 @@ def solve(a, b, opts: SolveOptions = SolveOptions()) -> SolveReport:
         if opts.composite:
             st = dns_step(a, st, opts.order, opts.form, opts.p, opts.w, ctr)
             g, f = st.G, st.F
-            theta, r = richardson_update(a, b, theta, g)
+            if opts.accel_q:
+                r = b - a @ theta                      # eq. (ttk1)
+                theta = theta + accelerator_apply(a, st, r, opts.accel_q)
+            else:
+                theta, r = richardson_update(a, b, theta, g)
         else:
             g = ns_step(a, g, opts.order, opts.form, opts.p, opts.w, ctr, f=f)
             theta, r = richardson_update(a, b, theta, g)
@@ -459,7 +493,10 @@ def solve(a, b, opts: SolveOptions = SolveOptions()) -> SolveReport:
             if refine >= 3 and rel > 0.5 * rhist[-4]:
                 refine_stop = "refine_stall"
                 break
-            theta = theta + g @ r
+            if opts.composite and opts.accel_q:
+                theta = theta + accelerator_apply(a, st, r, opts.accel_q)
+            else:
+                theta = theta + g @ r
             refine += 1
     return SolveReport(alpha=alpha, theta=theta, G=g, fnorm_hist=fhist, resid_hist=rhist,
                        ns_steps=k, refine_steps=refine, ns_stop=ns_stop,

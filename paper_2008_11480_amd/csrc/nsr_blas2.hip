@@ -176,6 +176,25 @@ gemv_update_kernel(const T* __restrict__ G, int64_t ldg, int64_t n,
   if (lane == 0) theta[row] += s;
 }
 
+// y = M x + z (z may be null), or y += M x + z with accumulate: one wave per
+// row, float64 accumulation (M float64 or float32).
+template <typename T>
+__global__ void __launch_bounds__(kThreads)
+gemv_kernel(const T* __restrict__ M, int64_t ldm, int64_t n, const double* __restrict__ x,
+            const double* __restrict__ z, double* __restrict__ y, int accumulate) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int64_t row = (int64_t)blockIdx.x * 4 + wave;
+  if (row >= n) return;
+  const T* m = M + row * ldm;
+  double s = 0.0;
+  for (int64_t c = lane; c < n; c += 64) s += (double)m[c] * x[c];
+  s = wave_sum(s);
+  if (lane == 0) {
+    if (z) s += z[row];
+    y[row] = accumulate ? y[row] + s : s;
+  }
+}
+
 __global__ void __launch_bounds__(kThreads)
 vec_scale_kernel(const double* __restrict__ b, const double* __restrict__ alpha,
                  double* __restrict__ theta, int64_t n, int accumulate) {
@@ -270,6 +289,17 @@ template void launch_gemv_update<double>(const double*, int64_t, int64_t, const 
                                          hipStream_t);
 template void launch_gemv_update<float>(const float*, int64_t, int64_t, const double*, double*,
                                         hipStream_t);
+
+template <typename T>
+void launch_gemv(const T* M, int64_t ldm, int64_t n, const double* x, const double* z, double* y,
+                 int accumulate, hipStream_t st) {
+  hipLaunchKernelGGL(gemv_kernel<T>, dim3((unsigned)((n + 3) / 4)), dim3(kThreads), 0, st, M, ldm,
+                     n, x, z, y, accumulate);
+}
+template void launch_gemv<double>(const double*, int64_t, int64_t, const double*, const double*,
+                                  double*, int, hipStream_t);
+template void launch_gemv<float>(const float*, int64_t, int64_t, const double*, const double*,
+                                 double*, int, hipStream_t);
 
 void launch_vec_scale(const double* b, const double* alpha, double* theta, int64_t n,
                       int accumulate, hipStream_t st) {

@@ -91,6 +91,12 @@ template <typename T>
 void launch_gemv_update(const T* G, int64_t ldg, int64_t n, const double* r, double* theta,
                         hipStream_t st);
 
+// y = M x + z (z may be null); with accumulate y += M x + z.  M float64 or
+// float32, vectors float64.
+template <typename T>
+void launch_gemv(const T* M, int64_t ldm, int64_t n, const double* x, const double* z, double* y,
+                 int accumulate, hipStream_t st);
+
 // theta = b / alpha (alpha on device); theta += r / alpha
 void launch_vec_scale(const double* b, const double* alpha, double* theta, int64_t n,
                       int accumulate, hipStream_t st);

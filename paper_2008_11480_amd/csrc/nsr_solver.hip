@@ -83,7 +83,7 @@ size_t layout_bytes(int64_t n, int precision, int composite) {
   if (precision != NS_PREC_FP64) bytes += align_up(nn * 4, kAlign);          // float32 A
   if (precision == NS_PREC_MIXED_BF16)
     bytes += (size_t)(composite ? 6 : 5) * align_up(nn * 2, kAlign);         // bf16 copies
-  bytes += align_up((size_t)n * sizeof(double), kAlign);                     // r
+  bytes += 4 * align_up((size_t)n * sizeof(double), kAlign);                 // r, t, w0, w1
   bytes += align_up((size_t)partial_capacity(n) * sizeof(double), kAlign);   // partials
   bytes += align_up(16 * sizeof(double), kAlign);                            // scalars
   return bytes;
@@ -119,6 +119,8 @@ struct ns_solver {
   Mat Gam, H;
   float* A32 = nullptr;
   double* r = nullptr;
+  double* vt = nullptr;      // accelerator temporaries (eq. ttk1)
+  double* vw[2] = {nullptr, nullptr};
   double* partial = nullptr;
   double* scal = nullptr;  // [0] alpha, [1] ||F||_F, [2] ||r||_2, [3] ||b||_2
 
@@ -359,21 +361,28 @@ int step_classic(ns_solver* s, int order, int fact, int p, int w) {
   return resid_into(s, s->F, s->G[s->gcur], true);  // F_k = I - A G_k
 }
 
+// Precalculation of Section 5.1: T_0 = G_0, Gamma_0 = F_0,
+// L_0 = T_0 P(Gamma_0), Gamma_1 = I - A L_0.
+int composite_start(ns_solver* s, int order) {
+  if (!s->g_implicit) return fail(NS_ESTATE, "composite form must start from G_0");
+  const Mat* c = nullptr;
+  int rc = poly_squaring(s, order, s->F, &c);
+  if (rc) return rc;
+  s->lcur = 0;
+  scaled_identity(s, c, s->L[0]);
+  rc = resid_into(s, s->Gam, s->L[0], false);
+  if (rc) return rc;
+  s->dns_started = true;
+  return NS_OK;
+}
+
 // Double Newton-Schulz step (Section 5.1, right orientation).
 int step_composite(ns_solver* s, int order) {
   int rc;
   s->p0_is_f2 = false;  // P[0] is reused by the L-loop first
   const Mat* c = nullptr;
   if (!s->dns_started) {
-    if (!s->g_implicit) return fail(NS_ESTATE, "composite form must start from G_0");
-    // T_0 = G_0, Gamma_0 = F_0: L_0 = T_0 P(Gamma_0), Gamma_1 = I - A L_0.
-    rc = poly_squaring(s, order, s->F, &c);
-    if (rc) return rc;
-    s->lcur = 0;
-    scaled_identity(s, c, s->L[0]);
-    rc = resid_into(s, s->Gam, s->L[0], false);
-    if (rc) return rc;
-    s->dns_started = true;
+    if ((rc = composite_start(s, order))) return rc;
   }
   // L-loop: L_k = L_{k-1} P(Gamma_k) (lkk1), Gamma_k^n = I - A L_k (gamk21).
   rc = poly_squaring(s, order, s->Gam, &c);
@@ -397,6 +406,30 @@ int step_composite(ns_solver* s, int order) {
   s->gcur ^= 1;
   s->g_implicit = false;
   return resid_into(s, s->F, Gn, true);
+}
+
+// y = M x + z (accumulate: y += M x + z) for an iterate M of the solver.
+void mat_vec(ns_solver* s, const Mat& M, const double* x, const double* z, double* y,
+             int accumulate) {
+  if (is_f64(s))
+    launch_gemv<double>(M.d, s->ld, s->n, x, z, y, accumulate, s->stream);
+  else
+    launch_gemv<float>(M.f, s->ld, s->n, x, z, y, accumulate, s->stream);
+}
+
+// theta += omega_k r with the accelerator of eq. (ttk1), right orientation:
+// omega r = L_k r + G_k {sum_{j<q} F_k^j} Gamma_k^n r (r = s->r).
+void accel_apply(ns_solver* s, int q, double* theta) {
+  mat_vec(s, s->Gam, s->r, nullptr, s->vt, 0);                 // t = Gamma^n r
+  const double* w = s->vt;
+  for (int j = 1; j < q; ++j) {                                // w = t + F w (Horner)
+    double* nw = s->vw[j & 1];
+    mat_vec(s, s->F, w, s->vt, nw, 0);
+    w = nw;
+  }
+  double* v = (w == s->vw[0]) ? s->vw[1] : s->vw[0];
+  mat_vec(s, s->G[s->gcur], w, nullptr, v, 0);                 // v = G w
+  mat_vec(s, s->L[s->lcur], s->r, v, theta, 1);                // theta += L r + v
 }
 
 void gemv_update(ns_solver* s, double* theta) {
@@ -538,6 +571,9 @@ int ns_create(int device, void* hip_stream, int64_t n, int precision, void* work
   }
   if (precision != NS_PREC_FP64) s->A32 = reinterpret_cast<float*>(take(align_up(nn * 4, kAlign)));
   s->r = reinterpret_cast<double*>(take(align_up((size_t)n * sizeof(double), kAlign)));
+  s->vt = reinterpret_cast<double*>(take(align_up((size_t)n * sizeof(double), kAlign)));
+  s->vw[0] = reinterpret_cast<double*>(take(align_up((size_t)n * sizeof(double), kAlign)));
+  s->vw[1] = reinterpret_cast<double*>(take(align_up((size_t)n * sizeof(double), kAlign)));
   s->partial =
       reinterpret_cast<double*>(take(align_up((size_t)partial_capacity(n) * sizeof(double), kAlign)));
   s->scal = reinterpret_cast<double*>(take(align_up(16 * sizeof(double), kAlign)));
@@ -687,6 +723,9 @@ int richardson_ns_solve(ns_solver* s, const double* b, double* theta, const ns_s
   if (o->k_max < 1 || o->k_max > NS_HIST_F - 1) return fail(NS_EINVAL, "k_max must be in 1..64");
   if (o->refine_max < 0) return fail(NS_EINVAL, "refine_max < 0");
   if (o->theta0_mode < 0 || o->theta0_mode > 2) return fail(NS_EINVAL, "bad theta0_mode");
+  if (o->accel_q < 0) return fail(NS_EINVAL, "accel_q < 0");
+  if (o->accel_q > 0 && o->factorization != NS_FACT_COMPOSITE_DOUBLE)
+    return fail(NS_EINVAL, "the accelerator (accel_q > 0) needs the composite form");
   if (int rc = validate_step_args(s, o->order, o->factorization, o->p, o->w)) return rc;
   ns_solve_report local;
   ns_solve_report* R = rep ? rep : &local;
@@ -703,8 +742,16 @@ int richardson_ns_solve(ns_solver* s, const double* b, double* theta, const ns_s
     const int64_t np = launch_vec_sumsq(b, s->n, s->partial, s->stream);
     launch_reduce(s->partial, np, s->scal + 3, 2, 0.0, s->stream);
   }
-  if (o->theta0_mode == 0) launch_vec_scale(b, s->scal + 0, theta, s->n, 0, s->stream);
-  if (o->theta0_mode == 1) HIP_TRY(hipMemsetAsync(theta, 0, s->n * sizeof(double), s->stream));
+  const int q = o->accel_q;
+  if (q > 0) {
+    // theta_0 = L_0 b (the accelerated scheme's start, below eq. riem6)
+    if (int rc = composite_start(s, o->order)) return rc;
+    mat_vec(s, s->L[s->lcur], b, nullptr, theta, 0);
+  } else if (o->theta0_mode == 0) {
+    launch_vec_scale(b, s->scal + 0, theta, s->n, 0, s->stream);
+  } else if (o->theta0_mode == 1) {
+    HIP_TRY(hipMemsetAsync(theta, 0, s->n * sizeof(double), s->stream));
+  }
   double bn[1];
   if (int rc = read_scalars(s, bn, 3, 1)) return rc;
   double bnorm = bn[0] > 0.0 ? bn[0] : 1.0;
@@ -719,7 +766,13 @@ int richardson_ns_solve(ns_solver* s, const double* b, double* theta, const ns_s
                  ? step_composite(s, o->order)
                  : step_classic(s, o->order, o->factorization, o->p, o->w);
     if (rc) return rc;
-    richardson_once(s, b, theta);
+    if (q > 0) {
+      const int64_t np = launch_gemv_resid(s->A, s->lda, s->n, b, theta, s->r, s->partial, s->stream);
+      launch_reduce(s->partial, np, s->scal + 2, 2, 0.0, s->stream);
+      accel_apply(s, q, theta);
+    } else {
+      richardson_once(s, b, theta);
+    }
     if ((rc = read_scalars(s, host, 1, 2))) return rc;
     const double fk = host[0];
     if (R->n_resid < NS_HIST_R) R->resid_hist[R->n_resid++] = host[1] / bnorm;
@@ -784,7 +837,9 @@ int richardson_ns_solve(ns_solver* s, const double* b, double* theta, const ns_s
         refine_stop = NS_STOP_REFINE_STALL;
         break;
       }
-      if (s->g_implicit)
+      if (q > 0)
+        accel_apply(s, q, theta);
+      else if (s->g_implicit)
         launch_vec_scale(s->r, s->scal + 0, theta, s->n, 1, s->stream);
       else
         gemv_update(s, theta);

@@ -57,6 +57,7 @@ class SolveOpts(ctypes.Structure):
         ("w", ctypes.c_int), ("k_max", ctypes.c_int), ("refine_max", ctypes.c_int),
         ("floor_detect", ctypes.c_int), ("scale", ctypes.c_int), ("eps", ctypes.c_double),
         ("f_tol", ctypes.c_double), ("resid_tol", ctypes.c_double), ("theta0_mode", ctypes.c_int),
+        ("accel_q", ctypes.c_int),
     ]
 
 
@@ -252,12 +253,14 @@ class Solver:
     def solve(self, b, theta, order: int = 8, form: str = "squaring", p: int = 0, w: int = 0,
               k_max: int = 64, refine_max: int = 64, floor_detect: bool = True,
               scale: int = SCALE_FROBENIUS, eps: float = 0.0, f_tol: float = 0.0,
-              resid_tol: float = 1e-12, theta0_mode: int = 0, raise_on_error: bool = True):
+              resid_tol: float = 1e-12, theta0_mode: int = 0, accel_q: int = 0,
+              raise_on_error: bool = True):
         _require_cuda_f64(b, "b")
         _require_cuda_f64(theta, "theta")
         o = SolveOpts(order=order, factorization=FACT[form], p=p, w=w, k_max=k_max,
                       refine_max=refine_max, floor_detect=1 if floor_detect else 0, scale=scale,
-                      eps=eps, f_tol=f_tol, resid_tol=resid_tol, theta0_mode=theta0_mode)
+                      eps=eps, f_tol=f_tol, resid_tol=resid_tol, theta0_mode=theta0_mode,
+                      accel_q=accel_q)
         rep = SolveReportC()
         st = lib().richardson_ns_solve(self._h, _ptr(b), _ptr(theta), ctypes.byref(o),
                                        ctypes.byref(rep))

@@ -179,3 +179,16 @@ def test_mixed_bind_converts_A(torch):
     ref = (np.eye(100) - sysm.A / alpha).astype(np.float32).astype(np.float64)
     assert np.all(np.abs(F - ref) <= U32 * 2 * np.abs(ref) + 1e-45)     # one float32 rounding
     assert f0 == pytest.approx(np.linalg.norm(ref), rel=1e-12)
+
+
+def test_mixed_accelerated_composite(torch):
+    """Mixed precision with the accelerator of eq. (ttk1): reaches 1e-10 and
+    agrees with the float64 oracle to the refinement's accuracy."""
+    sysm = inputs.spd_qlq(300, 1e4, seed=31)
+    s, th, rep = run(torch, sysm, nsr.PREC_MIXED_BF16, order=8, form="composite_double",
+                     accel_q=8, resid_tol=1e-10, refine_max=100)
+    assert rep.status == nsr.NS_OK and rep.rel_resid <= 1e-10
+    orc = oracle.solve(sysm.A, sysm.b, oracle.SolveOptions(order=8, composite=True, accel_q=8,
+                                                           resid_tol=1e-13))
+    fwd = np.linalg.norm(th - orc.theta) / np.linalg.norm(orc.theta)
+    assert fwd <= 1e4 * 2e-10, fwd

@@ -322,3 +322,44 @@ def test_timing_counts_every_gemm(torch):
     assert cnt == rep.mmm and ms > 0.0
     assert 256.0 ** 2 * 257 * rep.mmm < fl < 2.0 * 256 ** 3 * rep.mmm   # powers halved
     assert rep.gemm_flop == pytest.approx(fl)
+
+
+# --------------------------------------------------------------------------
+# Richardson with the high-order accelerator (eq. ttk1)
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("n,kappa,order,q", [(130, 1e2, 4, 4), (300, 1e3, 8, 8), (200, 1e3, 2, 1),
+                                             (97, 50.0, 4, 2)])
+def test_accelerated_solve_matches_oracle(torch, n, kappa, order, q):
+    sysm = inputs.spd_qlq(n, kappa, seed=900 + n)
+    th, rep = gpu_solve(torch, sysm, order=order, form="composite_double", accel_q=q,
+                        resid_tol=1e-13)
+    orc = oracle.solve(sysm.A, sysm.b, oracle.SolveOptions(order=order, composite=True,
+                                                           accel_q=q, resid_tol=1e-13))
+    assert abs(rep.ns_steps - orc.ns_steps) <= 1
+    compare_traces(rep.fnorm_hist, orc.fnorm_hist)
+    compare_traces(rep.resid_hist, orc.resid_hist, rel=1e-8)
+    assert rep.rel_resid <= max(1e-13, 2 * orc.rel_resid)
+    assert np.linalg.norm(th - orc.theta) <= 10 * kappa * U * np.linalg.norm(orc.theta)
+
+
+def test_accelerated_theta_eigen_closed_form(torch):
+    """theta_K = theta* - Q diag(mu^{n + gamma_K}) Q^T theta* (eqs. riem5, riem6)
+    for K steps before the rounding floor."""
+    sysm = inputs.spd_qlq(256, 1e3, seed=77)
+    n = 2
+    for K in (1, 2):
+        th, rep = gpu_solve(torch, sysm, order=n, form="composite_double", accel_q=n, k_max=K,
+                            floor_detect=False, refine_max=0, resid_tol=0.0)
+        mu = 1.0 - sysm.lam / rep.alpha
+        theta_star = sysm.Q @ ((sysm.Q.T @ sysm.b) / sysm.lam)
+        ex = n + oracle.riem6_gamma(K, n)
+        ref = theta_star - sysm.Q @ ((mu ** ex) * (sysm.Q.T @ theta_star))
+        assert np.linalg.norm(th - ref) <= 1e-10 * np.linalg.norm(theta_star), K
+
+
+def test_accelerator_needs_composite(torch):
+    sysm = inputs.spd_qlq(64, 10.0, seed=1)
+    with pytest.raises(nsr.NSError) as e:
+        gpu_solve(torch, sysm, order=4, form="squaring", accel_q=2)
+    assert e.value.status == nsr.NS_EINVAL

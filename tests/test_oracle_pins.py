@@ -343,3 +343,47 @@ def test_spd64_trace_and_floor():
         if ref > 1e-9:
             assert rep.fnorm_hist[k] == pytest.approx(ref, rel=1e-9)
     assert max(rep.fnorm_hist[8:]) < 1e-12
+
+
+@pytest.mark.parametrize("n,K,q", [(2, 1, 2), (2, 2, 2), (3, 1, 3), (2, 2, 1), (2, 1, 3)])
+def test_accelerated_richardson_exponent_exact(n, K, q):
+    """Eqs. (ttk1), (riem1)-(riem6): with theta_0 = L_0 b the mismatch after K
+    accelerated steps is -J^{n + E} theta*, E = sum_k (q e_k + n^{k+1}),
+    e_k = k n^{k+1} + n^k; for q = n, E is gamma_K of eq. (riem6)."""
+    e = [k * n ** (k + 1) + n ** k for k in range(K + 1)]
+    E = sum(q * e[k] + n ** (k + 1) for k in range(1, K + 1))
+    if q == n:
+        assert E == oracle.riem6_gamma(K, n)
+    m = n + E + 8
+    a = np.eye(m) - inputs.shift_matrix(m)
+    rng = np.random.default_rng(1)
+    b = rng.integers(-2, 3, size=m).astype(float)
+    theta_star = np.linalg.solve(a, b)
+    opts = oracle.SolveOptions(order=n, form="horner", composite=True, accel_q=q, k_max=K,
+                               floor_detect=False, refine_max=0, resid_tol=0,
+                               scale="inf_half", eps=0.0)
+    rep = oracle.solve(a, b, opts)
+    np.testing.assert_array_equal(rep.theta - theta_star,
+                                  -(shift_power(m, n + E) @ theta_star))
+
+
+def test_riem6_closed_form_values():
+    """gamma_k of eq. (riem6) equals the summed per-step exponents of eq. (riem4)."""
+    for n in (2, 3, 4, 8):
+        for k in range(1, 6):
+            direct = sum(j * n ** (j + 2) + 2 * n ** (j + 1) for j in range(1, k + 1))
+            assert oracle.riem6_gamma(k, n) == direct
+
+
+def test_accelerated_richardson_eigen_closed_form():
+    """On A = Q diag(lam) Q^T: theta_K = theta* - Q diag(mu^{n + gamma_K}) Q^T theta*."""
+    s = inputs.spd_qlq(64, 50.0, seed=3)
+    n, K = 2, 2
+    rep = oracle.solve(s.A, s.b, oracle.SolveOptions(order=n, composite=True, accel_q=n,
+                                                     k_max=K, floor_detect=False,
+                                                     refine_max=0, resid_tol=0))
+    mu = 1.0 - s.lam / rep.alpha
+    theta_star = s.Q @ ((s.Q.T @ s.b) / s.lam)
+    ex = n + oracle.riem6_gamma(K, n)
+    ref = theta_star - s.Q @ ((mu ** ex) * (s.Q.T @ theta_star))
+    assert np.linalg.norm(rep.theta - ref) <= 1e-12 * np.linalg.norm(theta_star)
