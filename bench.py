@@ -267,6 +267,7 @@ def main():
                     choices=["spd4096_k1e4_o8", "spd64_k1e2_o4"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision legs")
+    ap.add_argument("--no-serving", action="store_true", help="skip the serving leg")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="also run a plain device copy of this many MiB (PMC calibration)")
     args = ap.parse_args()
@@ -383,7 +384,8 @@ def main():
         torch.cuda.empty_cache()
         out["composite"] = run_composite(torch, nsr, max(2, args.steps // 2), 1)
         out["batch"] = run_batch(torch, nsr, 3)
-        out["serving"] = run_serving(torch, nsr)
+        if not args.no_serving:
+            out["serving"] = run_serving(torch, nsr)
 
     if not args.no_cpu_baseline and not fixed:
         log("timing the CPU oracle on a bounded sample")
