@@ -337,7 +337,9 @@ def main():
         },
         "roofline": {
             "bound": "mfma",
-            "kernel": "gemm_f64_kernel (128x128 full, 64x64 symmetric-output)",
+            "kernel": ("gemm_f64_kernel (128x128 tiles; symmetric-output power products "
+                       "cut their last, partial round of tiles along K and finish it "
+                       "with gemm_f64_split_fixup)"),
             "achieved": g64["tflops"],
             "peak": PEAK_TFLOPS["f64"],
             "unit": "TFLOP/s",
@@ -349,7 +351,8 @@ def main():
             "note": ("float64 GEMM family: the residual and G-side products run full "
                      "(2 n^3 flop), the power products with a symmetric output "
                      "(n^2 (n+1) flop); achieved = algorithmic flop / event time, "
-                     "averaged over all launches of a solve"),
+                     "averaged over all products of a solve; a 'launch' is one product "
+                     "(the main kernel plus, for a split product, its fixup kernel)"),
         },
         "solve": {
             **report_of(last), "rel_resid": rel, "fwd_err_vs_closed_form": fwd,

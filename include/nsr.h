@@ -308,8 +308,27 @@ int ns_gemm_f64(void* hip_stream, int64_t m, int64_t n, int64_t k,
                 const double* E2, int64_t lde2, double diag, double scale,
                 int flags, double* sumsq_out);
 
-/* Number of per-tile partial sums ns_gemm_f64 writes for an m x n output. */
+/* Upper bound on the per-tile partial sums ns_gemm_f64 / ns_gemm_f64_ws
+ * write for an m x n output. */
 int64_t ns_gemm_f64_partials(int64_t m, int64_t n, int flags);
+
+/* ns_gemm_f64 with caller-owned device scratch.  When the output tiles do not
+ * fill a whole number of rounds of resident workgroups, the tiles of the last,
+ * partial round can be cut along K into slices computed by otherwise idle
+ * workgroups and summed, in a fixed order, by a second kernel; that needs
+ * ns_gemm_f64_scratch_bytes(m, n, k, flags) bytes of scratch (0: no split for
+ * this shape on this device).  With less scratch (or NULL) the call is exactly
+ * ns_gemm_f64.  The scratch (8-byte aligned) is used only while the call's
+ * kernels run on hip_stream; concurrent calls need separate scratch.  The
+ * result equals ns_gemm_f64's up to the summation order over K.  Errors as
+ * ns_gemm_f64, plus NS_EINVAL for misaligned scratch. */
+size_t ns_gemm_f64_scratch_bytes(int64_t m, int64_t n, int64_t k, int flags);
+int ns_gemm_f64_ws(void* hip_stream, int64_t m, int64_t n, int64_t k,
+                   const double* X, int64_t ldx, const double* Y, int64_t ldy,
+                   double* D, int64_t ldd, const double* E1, int64_t lde1,
+                   const double* E2, int64_t lde2, double diag, double scale,
+                   int flags, void* scratch, size_t scratch_bytes,
+                   double* sumsq_out);
 
 /* Kernel-level entry points of the float32 and bf16 MFMA GEMMs used by the
  * float32 and mixed modes (tests, benchmarks), with the same fused epilogue

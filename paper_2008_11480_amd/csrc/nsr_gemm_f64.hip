@@ -39,6 +39,13 @@
 #ifndef NSR_F64_WAVES_PER_EU
 #define NSR_F64_WAVES_PER_EU 2
 #endif
+// Row padding (doubles) of the X and Y slabs in LDS.
+#ifndef NSR_F64_XPAD
+#define NSR_F64_XPAD 2
+#endif
+#ifndef NSR_F64_YPAD
+#define NSR_F64_YPAD 2
+#endif
 
 namespace nsr {
 
@@ -46,19 +53,21 @@ typedef double f64x4 __attribute__((ext_vector_type(4)));
 
 namespace {
 
-__device__ __forceinline__ void map_tile(int bid, int tiles_m, int tiles_n, int& tm, int& tn) {
-  const int ntiles = tiles_m * tiles_n;
-  int t = bid;
-  if ((ntiles & 7) == 0) {
-    const int per = ntiles >> 3;
-    t = (bid & 7) * per + (bid >> 3);
-  }
+// Consecutive workgroup ids land on different XCDs: give each XCD a
+// contiguous run of the tile order (count divisible by 8), so the panels a
+// run reuses stay in that XCD's L2.
+__device__ __forceinline__ int xcd_perm(int bid, int count) {
+  return (count & 7) == 0 ? (bid & 7) * (count >> 3) + (bid >> 3) : bid;
+}
+
+// Position u of the grouped tile order (8 tile-rows per group) -> tile.
+__device__ __forceinline__ void group_tile(int u, int tiles_m, int tiles_n, int& tm, int& tn) {
   constexpr int GM = 8;
   const int group_size = GM * tiles_n;
-  const int g = t / group_size;
+  const int g = u / group_size;
   const int first_m = g * GM;
   const int gm = min(tiles_m - first_m, GM);
-  const int r = t - g * group_size;
+  const int r = u - g * group_size;
   tm = first_m + r % gm;
   tn = r / gm;
 }
@@ -74,17 +83,39 @@ __device__ __forceinline__ void sym_tile(int t, int T, int& tm, int& tn) {
   tn = m + r;
 }
 
+__device__ __forceinline__ void tile_at(bool sym, int u, int tiles_m, int tiles_n, int& tm,
+                                        int& tn) {
+  if (sym)
+    sym_tile(u, tiles_m, tm, tn);
+  else
+    group_tile(u, tiles_m, tiles_n, tm, tn);
+}
+
+__device__ __forceinline__ double epi_value(const GemmF64Args& p, int64_t row, int64_t col,
+                                            double acc) {
+  double v = p.scale * acc;
+  if (row == col) v += p.diag;
+  if (p.E1) v += p.E1[row * p.lde1 + col];
+  if (p.E2) v += p.E2[row * p.lde2 + col];
+  return v;
+}
+
+// Grid: the first dp workgroups own whole tiles (positions 0..dp-1 of the
+// tile order).  When splits > 0, the remaining tiles (the last, partial round)
+// are cut along K into `splits` slices of `slabs` K-slabs; workgroup dp + q
+// computes slice q % splits of tail tile q / splits and stores its raw
+// accumulators in p.sk (gemm_f64_split_fixup finishes those tiles).
 template <int BM, int BN, int BK, int NBUF, bool VEC, bool SYM>
 __global__ void __launch_bounds__(256)
 __attribute__((amdgpu_waves_per_eu(NSR_F64_WAVES_PER_EU)))
-gemm_f64_kernel(GemmF64Args p, int tiles_m, int tiles_n) {
+gemm_f64_kernel(GemmF64Args p, int tiles_m, int tiles_n, int dp, int splits, int slabs) {
   constexpr int NT = 256;
   constexpr int WTM = BM / 2;          // rows per wave
   constexpr int WTN = BN / 2;          // cols per wave
   constexpr int FM = WTM / 16;
   constexpr int FN = WTN / 16;
-  constexpr int XS = BK + 2;           // LDS row stride of the X slab (doubles)
-  constexpr int YS = BN + 2;           // LDS row stride of the Y slab
+  constexpr int XS = BK + NSR_F64_XPAD;   // LDS row stride of the X slab (doubles)
+  constexpr int YS = BN + NSR_F64_YPAD;   // LDS row stride of the Y slab
   constexpr int XV = (BM * BK / 2) / NT;   // double2 per thread, X slab
   constexpr int YV = (BK * BN / 2) / NT;   // double2 per thread, Y slab
   static_assert(XV >= 1 && YV >= 1, "tile too small for 256 threads");
@@ -106,18 +137,12 @@ gemm_f64_kernel(GemmF64Args p, int tiles_m, int tiles_n) {
   const int wave = tid >> 6;
   const int wm = wave >> 1;
   const int wn = wave & 1;
-  int tm, tn, tile_id;
-  if (SYM) {
-    // Symmetric output: only tiles with tm <= tn (tiles_m == tiles_n).
-    const int nsym = tiles_m * (tiles_m + 1) / 2;
-    int t = blockIdx.x;
-    if ((nsym & 7) == 0) t = (t & 7) * (nsym >> 3) + (t >> 3);
-    sym_tile(t, tiles_m, tm, tn);
-    tile_id = t;
-  } else {
-    map_tile(blockIdx.x, tiles_m, tiles_n, tm, tn);
-    tile_id = tm * tiles_n + tn;
-  }
+  // Symmetric output: only tiles with tm <= tn (tiles_m == tiles_n).
+  const int bid = blockIdx.x;
+  const bool tail = bid >= dp;
+  const int tile_id = tail ? dp + (bid - dp) / splits : xcd_perm(bid, dp);
+  int tm, tn;
+  tile_at(SYM, tile_id, tiles_m, tiles_n, tm, tn);
   const int64_t m0 = (int64_t)tm * BM;
   const int64_t n0 = (int64_t)tn * BN;
   const int64_t M = p.M, N = p.N, K = p.K;
@@ -172,14 +197,24 @@ gemm_f64_kernel(GemmF64Args p, int tiles_m, int tiles_n) {
       const int idx = tid + NT * v;
       const int row = idx / (BK / 2);
       const int c = (idx % (BK / 2)) * 2;
-      *reinterpret_cast<double2*>(&Xs[buf][row * XS + c]) = xr[v];
+      if constexpr ((XS & 1) == 0) {
+        *reinterpret_cast<double2*>(&Xs[buf][row * XS + c]) = xr[v];
+      } else {
+        Xs[buf][row * XS + c] = xr[v].x;
+        Xs[buf][row * XS + c + 1] = xr[v].y;
+      }
     }
 #pragma unroll
     for (int v = 0; v < YV; ++v) {
       const int idx = tid + NT * v;
       const int row = idx / (BN / 2);
       const int c = (idx % (BN / 2)) * 2;
-      *reinterpret_cast<double2*>(&Ys[buf][row * YS + c]) = yr[v];
+      if constexpr ((YS & 1) == 0) {
+        *reinterpret_cast<double2*>(&Ys[buf][row * YS + c]) = yr[v];
+      } else {
+        Ys[buf][row * YS + c] = yr[v].x;
+        Ys[buf][row * YS + c + 1] = yr[v].y;
+      }
     }
   };
 
@@ -189,16 +224,20 @@ gemm_f64_kernel(GemmF64Args p, int tiles_m, int tiles_n) {
 #pragma unroll
     for (int j = 0; j < FN; ++j) acc[i][j] = f64x4{0.0, 0.0, 0.0, 0.0};
 
-  const int nk = (int)((K + BK - 1) / BK);
+  int kt0 = 0, kt1 = (int)((K + BK - 1) / BK);
+  if (tail) {
+    kt0 = ((bid - dp) % splits) * slabs;
+    kt1 = min(kt1, kt0 + slabs);
+  }
   const int lr = lane & 15;
   const int lk = lane >> 4;
-  if (nk > 0) load(0);
-  for (int kt = 0; kt < nk; ++kt) {
+  if (kt0 < kt1) load((int64_t)kt0 * BK);
+  for (int kt = kt0; kt < kt1; ++kt) {
     const int buf = (NBUF == 2) ? (kt & 1) : 0;
-    if (NBUF == 1 && kt > 0) __syncthreads();   // everyone done reading the slab
+    if (NBUF == 1 && kt > kt0) __syncthreads();   // everyone done reading the slab
     store(buf);
     __syncthreads();
-    if (kt + 1 < nk) load((int64_t)(kt + 1) * BK);
+    if (kt + 1 < kt1) load((int64_t)(kt + 1) * BK);
     const double* xs = &Xs[buf][(wm * WTM + lr) * XS + lk];
     const double* ys = &Ys[buf][lk * YS + wn * WTN + lr];
 #pragma unroll
@@ -216,12 +255,24 @@ gemm_f64_kernel(GemmF64Args p, int tiles_m, int tiles_n) {
     }
   }
 
+  if (tail) {
+    // Raw K-slice of a tail tile, in accumulator order: consecutive lanes
+    // store consecutive doubles.
+    double* dst = p.sk + (size_t)(bid - dp) * (BM * BN) + lane;
+#pragma unroll
+    for (int i = 0; i < FM; ++i)
+#pragma unroll
+      for (int j = 0; j < FN; ++j)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) dst[((wave * FM + i) * FN + j) * 256 + r * 64] = acc[i][j][r];
+    return;
+  }
+
   // Epilogue: D = diag I + scale acc + E1 + E2, optional sum of D^2.  With a
   // symmetric output a diagonal tile writes its upper triangle and mirrors it
   // element-wise; an off-diagonal tile writes itself and (below) its
   // transpose through LDS.
   double ss = 0.0;
-  const double diag = p.diag, scale = p.scale;
   const bool diag_tile = SYM && (tm == tn);
 #pragma unroll
   for (int i = 0; i < FM; ++i) {
@@ -232,10 +283,7 @@ gemm_f64_kernel(GemmF64Args p, int tiles_m, int tiles_n) {
       for (int r = 0; r < 4; ++r) {
         const int64_t row = m0 + wm * WTM + i * 16 + lk + 4 * r;
         if (row < M && col < N) {
-          double v = scale * acc[i][j][r];
-          if (row == col) v += diag;
-          if (p.E1) v += p.E1[row * p.lde1 + col];
-          if (p.E2) v += p.E2[row * p.lde2 + col];
+          const double v = epi_value(p, row, col, acc[i][j][r]);
           if (SYM) acc[i][j][r] = v;
           if (!diag_tile) {
             p.D[row * p.ldd + col] = v;
@@ -282,32 +330,121 @@ gemm_f64_kernel(GemmF64Args p, int tiles_m, int tiles_n) {
   }
 }
 
+// Finishes the split tail tiles: sums the K-slices of each tile in a fixed
+// order, applies the epilogue and writes the tile (and its mirror).  One
+// workgroup per 16-row MFMA strip of a wave quadrant (16 x BN/2 outputs);
+// thread t plays lane t % 64 of MFMA column block t / 64, so the slices are
+// read in the order the main kernel stored them.  Partial sums of D^2 go to
+// p.partial[dp + blockIdx.x].
+template <int BM, int BN, bool SYM>
+__global__ void __launch_bounds__(256)
+gemm_f64_split_fixup(GemmF64Args p, int tiles_m, int tiles_n, int dp, int splits) {
+  constexpr int WTM = BM / 2, WTN = BN / 2, FM = WTM / 16, FN = WTN / 16;
+  static_assert(FN * 64 == 256, "one thread per lane and MFMA column block");
+  constexpr int TS = BM * BN;
+  constexpr int SS = 17;
+  __shared__ double S[SYM ? WTN * SS : 1];
+  __shared__ double red[4];
+  const int b = blockIdx.x;
+  const int jt = b / (4 * FM);
+  const int wave = (b / FM) % 4;
+  const int i = b % FM;
+  const int wm = wave >> 1, wn = wave & 1;
+  int tm, tn;
+  tile_at(SYM, dp + jt, tiles_m, tiles_n, tm, tn);
+  const int tid = threadIdx.x, lane = tid & 63, jj = tid >> 6;
+  const int lr = lane & 15, lk = lane >> 4;
+  const int64_t m0 = (int64_t)tm * BM, n0 = (int64_t)tn * BN;
+  const int64_t M = p.M, N = p.N;
+  const bool diag_tile = SYM && (tm == tn);
+  const double* src = p.sk + (size_t)jt * splits * TS + ((wave * FM + i) * FN + jj) * 256 + lane;
+  double ss = 0.0;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    double a = 0.0;
+    for (int q = 0; q < splits; ++q) a += src[(size_t)q * TS + r * 64];
+    const int64_t row = m0 + wm * WTM + i * 16 + lk + 4 * r;
+    const int64_t col = n0 + wn * WTN + jj * 16 + lr;
+    if (row < M && col < N) {
+      const double v = epi_value(p, row, col, a);
+      if (SYM) S[(jj * 16 + lr) * SS + lk + 4 * r] = v;
+      if (!diag_tile) {
+        p.D[row * p.ldd + col] = v;
+        ss += (SYM ? 2.0 : 1.0) * v * v;
+      } else if (row <= col) {
+        p.D[row * p.ldd + col] = v;
+        if (row < col) p.D[col * p.ldd + row] = v;
+        ss += (row < col ? 2.0 : 1.0) * v * v;
+      }
+    }
+  }
+  if (SYM && !diag_tile) {
+    __syncthreads();
+    for (int idx = tid; idx < WTN * 16; idx += 256) {
+      const int c = idx >> 4, rr = idx & 15;
+      const int64_t grow = n0 + wn * WTN + c, gcol = m0 + wm * WTM + i * 16 + rr;
+      if (grow < N && gcol < M) p.D[grow * p.ldd + gcol] = S[c * SS + rr];
+    }
+  }
+  if (p.partial) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) ss += __shfl_xor(ss, off, 64);
+    if (lane == 0) red[tid >> 6] = ss;
+    __syncthreads();
+    if (tid == 0) p.partial[dp + b] = (red[0] + red[1]) + (red[2] + red[3]);
+  }
+}
+
+// How one product is cut into workgroups.
+struct Plan {
+  bool big = false;    // 128 x 128 tiles (else 64 x 64)
+  int64_t nt = 0;      // output tiles
+  int64_t dp = 0;      // tiles owned whole by one workgroup
+  int splits = 0;      // K-slices per tail tile (0: no tail)
+  int slabs = 0;       // K-slabs per slice
+};
+
 template <int BM, int BN, int BK, int NBUF>
-int64_t launch_cfg(const GemmF64Args& a, hipStream_t st) {
+int64_t launch_cfg(const GemmF64Args& a, const Plan& pl, hipStream_t st) {
   const int tiles_m = (int)((a.M + BM - 1) / BM);
   const int tiles_n = (int)((a.N + BN - 1) / BN);
-  const int64_t nt = a.sym ? (int64_t)tiles_m * (tiles_m + 1) / 2 : (int64_t)tiles_m * tiles_n;
   const bool vec = ((a.ldx & 1) == 0) && ((a.ldy & 1) == 0) &&
                    ((reinterpret_cast<uintptr_t>(a.X) & 15) == 0) &&
                    ((reinterpret_cast<uintptr_t>(a.Y) & 15) == 0);
-  dim3 grid((unsigned)nt), block(256);
+  const int64_t tail = pl.splits > 0 ? pl.nt - pl.dp : 0;
+  dim3 grid((unsigned)(pl.dp + tail * pl.splits)), block(256);
+  const int dp = (int)pl.dp, splits = pl.splits, slabs = pl.slabs;
   if (a.sym) {
     if (vec)
       hipLaunchKernelGGL((gemm_f64_kernel<BM, BN, BK, NBUF, true, true>), grid, block, 0, st, a,
-                         tiles_m, tiles_n);
+                         tiles_m, tiles_n, dp, splits, slabs);
     else
       hipLaunchKernelGGL((gemm_f64_kernel<BM, BN, BK, NBUF, false, true>), grid, block, 0, st, a,
-                         tiles_m, tiles_n);
+                         tiles_m, tiles_n, dp, splits, slabs);
   } else {
     if (vec)
       hipLaunchKernelGGL((gemm_f64_kernel<BM, BN, BK, NBUF, true, false>), grid, block, 0, st, a,
-                         tiles_m, tiles_n);
+                         tiles_m, tiles_n, dp, splits, slabs);
     else
       hipLaunchKernelGGL((gemm_f64_kernel<BM, BN, BK, NBUF, false, false>), grid, block, 0, st, a,
-                         tiles_m, tiles_n);
+                         tiles_m, tiles_n, dp, splits, slabs);
   }
   if (hipGetLastError() != hipSuccess) return -1;
-  return a.partial ? nt : 0;
+  int64_t fix_blocks = 0;
+  if constexpr (BN == 128) {
+    if (tail > 0) {
+      fix_blocks = tail * 4 * (BM / 32);
+      dim3 fgrid((unsigned)fix_blocks);
+      if (a.sym)
+        hipLaunchKernelGGL((gemm_f64_split_fixup<BM, BN, true>), fgrid, block, 0, st, a, tiles_m,
+                           tiles_n, dp, splits);
+      else
+        hipLaunchKernelGGL((gemm_f64_split_fixup<BM, BN, false>), fgrid, block, 0, st, a, tiles_m,
+                           tiles_n, dp, splits);
+      if (hipGetLastError() != hipSuccess) return -1;
+    }
+  }
+  return a.partial ? pl.dp + fix_blocks : 0;
 }
 
 int device_cus() {
@@ -328,39 +465,86 @@ int device_cus() {
 // round costs about half a round (its tiles run with less contention), and a
 // 64 x 64 tile takes 0.54 of a 128 x 128 one at the same K.  Fitted to the
 // measured full / symmetric GEMMs at N = 2048, 4096, 8192; the rule picks the
-// faster shape in all six.  NSR_F64_FORCE_TILE (128 or 64) overrides it.
+// faster shape in all six.  A third choice, given scratch: 128 x 128 tiles
+// whose last, partial round is cut along K into as many slices as fill the
+// resident slots (a tail of r tiles in S slots takes ~ S / r times less than
+// a round), finished by a small reduction kernel.  NSR_F64_FORCE_TILE (128
+// or 64) restricts the shape, NSR_F64_SPLIT=0 disables the split.
 #ifndef NSR_F64_FORCE_TILE
 #define NSR_F64_FORCE_TILE 0
 #endif
+#ifndef NSR_F64_SPLIT
+#define NSR_F64_SPLIT 1
+#endif
+constexpr int64_t kBigTile = 128 * 128;
+
 double eff_rounds(int64_t tiles, int64_t slots) {
   const int64_t full = tiles / slots, rem = tiles % slots;
   return (double)full + (rem == 0 ? 0.0 : (2 * rem >= slots ? 1.0 : 0.5));
 }
-bool use_big_shape(int64_t m, int64_t n, bool sym) {
-  if (NSR_F64_FORCE_TILE == 128) return true;
-  if (NSR_F64_FORCE_TILE == 64) return false;
+
+int64_t tile_count(int64_t m, int64_t n, int64_t b, bool sym) {
+  const int64_t tm = (m + b - 1) / b, tn = (n + b - 1) / b;
+  return sym ? tm * (tm + 1) / 2 : tm * tn;
+}
+
+Plan plan_f64(int64_t m, int64_t n, int64_t k, bool sym, int64_t sk_cap) {
   const int64_t cus = device_cus();
-  auto count = [&](int64_t b) {
-    const int64_t tm = (m + b - 1) / b, tn = (n + b - 1) / b;
-    return sym ? tm * (tm + 1) / 2 : tm * tn;
-  };
-  return eff_rounds(count(128), 2 * cus) <= 0.54 * eff_rounds(count(64), 4 * cus);
+  const int64_t s128 = 2 * cus;
+  const int64_t c128 = tile_count(m, n, 128, sym), c64 = tile_count(m, n, 64, sym);
+  Plan pl;
+  double cost = 0.0;
+  if (NSR_F64_FORCE_TILE == 128 ||
+      (NSR_F64_FORCE_TILE != 64 && eff_rounds(c128, s128) <= 0.54 * eff_rounds(c64, 4 * cus))) {
+    pl.big = true;
+    pl.nt = pl.dp = c128;
+    cost = eff_rounds(c128, s128);
+  } else {
+    pl.nt = pl.dp = c64;
+    cost = 0.54 * eff_rounds(c64, 4 * cus);
+  }
+  const int64_t rem = c128 % s128;
+  if (NSR_F64_SPLIT && NSR_F64_FORCE_TILE != 64 && sk_cap > 0 && c128 > s128 && rem != 0) {
+    const int64_t nk = (k + 15) / 16;
+    int64_t sp = s128 / rem < nk ? s128 / rem : nk;
+    if (sp >= 2) {
+      const int64_t slabs = (nk + sp - 1) / sp;
+      sp = (nk + slabs - 1) / slabs;
+      const double c = (double)(c128 / s128) + (double)slabs / (double)nk + 0.02;
+      if (rem * sp * kBigTile <= sk_cap && c < cost) {
+        pl.big = true;
+        pl.nt = c128;
+        pl.dp = c128 - rem;
+        pl.splits = (int)sp;
+        pl.slabs = (int)slabs;
+      }
+    }
+  }
+  return pl;
 }
 
 }  // namespace
 
 int64_t gemm_f64_partials(int64_t m, int64_t n, bool sym) {
-  const int64_t b = use_big_shape(m, n, sym) ? 128 : 64;
-  const int64_t tm = (m + b - 1) / b, tn = (n + b - 1) / b;
-  return sym ? tm * (tm + 1) / 2 : tm * tn;
+  // whole tiles + 16 fixup strips per split tail tile, or the 64 x 64 grid
+  const int64_t c128 = tile_count(m, n, 128, sym), c64 = tile_count(m, n, 64, sym);
+  const int64_t s128 = 2 * device_cus();
+  const int64_t bound128 = c128 > s128 ? c128 + 15 * (c128 % s128) : c128;
+  return bound128 > c64 ? bound128 : c64;
+}
+
+size_t gemm_f64_split_bytes(int64_t m, int64_t n, int64_t k, bool sym) {
+  if (m <= 0 || n <= 0 || k <= 0 || (sym && m != n)) return 0;
+  const Plan pl = plan_f64(m, n, k, sym, INT64_MAX);
+  return pl.splits > 0 ? (size_t)(pl.nt - pl.dp) * pl.splits * kBigTile * sizeof(double) : 0;
 }
 
 int64_t launch_gemm_f64(const GemmF64Args& a, hipStream_t st) {
   if (a.M <= 0 || a.N <= 0) return 0;
   if (a.sym && a.M != a.N) return -1;
-  if (use_big_shape(a.M, a.N, a.sym))
-    return launch_cfg<128, 128, NSR_F64_BIG_BK, NSR_F64_BIG_NBUF>(a, st);
-  return launch_cfg<64, 64, 16, 2>(a, st);
+  const Plan pl = plan_f64(a.M, a.N, a.K, a.sym != 0, a.sk ? a.sk_cap : 0);
+  if (pl.big) return launch_cfg<128, 128, NSR_F64_BIG_BK, NSR_F64_BIG_NBUF>(a, pl, st);
+  return launch_cfg<64, 64, 16, 2>(a, pl, st);
 }
 
 }  // namespace nsr

@@ -20,6 +20,8 @@ struct GemmF64Args {
   double* partial;   // per-tile sum of D^2 (null: not wanted)
   int sym;           // 1: symmetric output (M == N): only tiles on or above the
                      // diagonal are computed, the lower triangle is their mirror
+  double* sk;        // scratch for split-K tail tiles (may be null: no split)
+  int64_t sk_cap;    // its capacity in doubles
 };
 
 // D = diag * I + scale * (X op(Y)) + E1 + E2 with float32 output (and an
@@ -43,9 +45,13 @@ int64_t gemm_lp_partials(int64_t m, int64_t n);
 int64_t launch_gemm_f32_nn(const GemmLpArgs& a, hipStream_t st);
 int64_t launch_gemm_bf16_nt(const GemmLpArgs& a, hipStream_t st);
 
-// Number of per-tile partials the float64 GEMM writes for an m x n output
-// (the size the partial buffer must have).
+// Upper bound on the number of partials the float64 GEMM writes for an m x n
+// output (the size the partial buffer must have).
 int64_t gemm_f64_partials(int64_t m, int64_t n, bool sym);
+
+// Scratch (bytes) that lets the float64 GEMM of an m x n x k product split
+// the K range of its last, partial round of tiles (0: no split is planned).
+size_t gemm_f64_split_bytes(int64_t m, int64_t n, int64_t k, bool sym);
 
 // Enqueue the GEMM; returns the number of partials written (0 if partial is
 // null) or a negative value on a launch error.

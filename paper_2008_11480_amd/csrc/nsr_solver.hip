@@ -72,6 +72,11 @@ int64_t partial_capacity(int64_t n) {
   return c;
 }
 
+size_t split_bytes(int64_t n) {
+  const size_t a = gemm_f64_split_bytes(n, n, n, false), b = gemm_f64_split_bytes(n, n, n, true);
+  return a > b ? a : b;
+}
+
 size_t elem_bytes(int precision) { return precision == NS_PREC_FP64 ? 8 : 4; }
 
 size_t layout_bytes(int64_t n, int precision, int composite) {
@@ -86,6 +91,7 @@ size_t layout_bytes(int64_t n, int precision, int composite) {
   bytes += 4 * align_up((size_t)n * sizeof(double), kAlign);                 // r, t, w0, w1
   bytes += align_up((size_t)partial_capacity(n) * sizeof(double), kAlign);   // partials
   bytes += align_up(16 * sizeof(double), kAlign);                            // scalars
+  if (precision == NS_PREC_FP64) bytes += align_up(split_bytes(n), kAlign);  // split-K scratch
   return bytes;
 }
 
@@ -123,6 +129,8 @@ struct ns_solver {
   double* vw[2] = {nullptr, nullptr};
   double* partial = nullptr;
   double* scal = nullptr;  // [0] alpha, [1] ||F||_F, [2] ||r||_2, [3] ||b||_2
+  double* sk = nullptr;    // split-K scratch of the float64 GEMM
+  int64_t sk_cap = 0;      // doubles
 
   const double* A = nullptr;
   int64_t lda = 0;
@@ -193,6 +201,8 @@ int mm(ns_solver* s, Mat& D, const Mat* X, const Mat& Y, const Mat* E1, const Ma
     // per step.  Errors in the powers only perturb P(F) and enter F_{k+1} as
     // O(||F|| ||[A, G]||).
     a.sym = (s->symmetric && kind == K_POWER) ? 1 : 0;
+    a.sk = s->sk;
+    a.sk_cap = s->sk_cap;
     np = launch_gemm_f64(a, s->stream);
     tkind = 1;
   } else {
@@ -577,6 +587,13 @@ int ns_create(int device, void* hip_stream, int64_t n, int precision, void* work
   s->partial =
       reinterpret_cast<double*>(take(align_up((size_t)partial_capacity(n) * sizeof(double), kAlign)));
   s->scal = reinterpret_cast<double*>(take(align_up(16 * sizeof(double), kAlign)));
+  if (precision == NS_PREC_FP64) {
+    const size_t skb = split_bytes(n);
+    if (skb > 0) {
+      s->sk = reinterpret_cast<double*>(take(align_up(skb, kAlign)));
+      s->sk_cap = (int64_t)(skb / sizeof(double));
+    }
+  }
   if ((size_t)(p - s->ws) > bytes) {  // layout_bytes and this carving must agree
     delete s;
     return fail(NS_ENOMEM, "internal layout exceeds workspace");
@@ -907,10 +924,23 @@ int64_t ns_gemm_f64_partials(int64_t m, int64_t n, int flags) {
   return gemm_f64_partials(m, n, (flags & NS_GEMM_SYMMETRIC) != 0);
 }
 
+size_t ns_gemm_f64_scratch_bytes(int64_t m, int64_t n, int64_t k, int flags) {
+  return gemm_f64_split_bytes(m, n, k, (flags & NS_GEMM_SYMMETRIC) != 0);
+}
+
 int ns_gemm_f64(void* hip_stream, int64_t m, int64_t n, int64_t k, const double* X, int64_t ldx,
                 const double* Y, int64_t ldy, double* D, int64_t ldd, const double* E1,
                 int64_t lde1, const double* E2, int64_t lde2, double diag, double scale,
                 int flags, double* sumsq_out) {
+  return ns_gemm_f64_ws(hip_stream, m, n, k, X, ldx, Y, ldy, D, ldd, E1, lde1, E2, lde2, diag,
+                        scale, flags, nullptr, 0, sumsq_out);
+}
+
+int ns_gemm_f64_ws(void* hip_stream, int64_t m, int64_t n, int64_t k, const double* X,
+                   int64_t ldx, const double* Y, int64_t ldy, double* D, int64_t ldd,
+                   const double* E1, int64_t lde1, const double* E2, int64_t lde2, double diag,
+                   double scale, int flags, void* scratch, size_t scratch_bytes,
+                   double* sumsq_out) {
   if (m < 0 || n < 0 || k < 0) return fail(NS_EINVAL, "negative size");
   if (flags & ~NS_GEMM_SYMMETRIC) return fail(NS_EINVAL, "unknown flags");
   if ((flags & NS_GEMM_SYMMETRIC) && m != n) return fail(NS_EINVAL, "symmetric output needs m == n");
@@ -919,8 +949,12 @@ int ns_gemm_f64(void* hip_stream, int64_t m, int64_t n, int64_t k, const double*
   if ((k > 0 && (ldx < k || ldy < n)) || ldd < n) return fail(NS_EINVAL, "leading dimension too small");
   if ((E1 && lde1 < n) || (E2 && lde2 < n)) return fail(NS_EINVAL, "addend leading dimension too small");
   if (D == X || D == Y) return fail(NS_EINVAL, "D must not alias X or Y");
+  if (scratch && (reinterpret_cast<uintptr_t>(scratch) & 7))
+    return fail(NS_EINVAL, "scratch must be 8-byte aligned");
   hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
   GemmF64Args a{};
+  a.sk = scratch ? reinterpret_cast<double*>(scratch) : nullptr;
+  a.sk_cap = scratch ? (int64_t)(scratch_bytes / sizeof(double)) : 0;
   a.X = X;
   a.Y = Y;
   a.D = D;

@@ -38,6 +38,7 @@ EXPORTS = (
     "ns_get_G", "ns_get_F", "ns_richardson_step", "richardson_ns_solve", "ns_set_symmetric",
     "ns_timing_enable",
     "ns_timing_read", "ns_timing_reset", "ns_gemm_f64", "ns_gemm_f64_partials",
+    "ns_gemm_f64_scratch_bytes", "ns_gemm_f64_ws",
     "ns_gemm_f32", "ns_gemm_bf16_nt", "ns_gemm_lp_partials",
     "ns_batch_workspace_bytes", "ns_batch_create", "ns_batch_set_launch", "ns_batch_submit",
     "ns_batch_poll", "ns_batch_autotune", "ns_batch_destroy",
@@ -117,6 +118,9 @@ def lib() -> ctypes.CDLL:
         "ns_gemm_f64": (ci, [vp, i64, i64, i64, vp, i64, vp, i64, vp, i64, vp, i64, vp, i64,
                              dbl, dbl, ci, vp]),
         "ns_gemm_f64_partials": (i64, [i64, i64, ci]),
+        "ns_gemm_f64_scratch_bytes": (ctypes.c_size_t, [i64, i64, i64, ci]),
+        "ns_gemm_f64_ws": (ci, [vp, i64, i64, i64, vp, i64, vp, i64, vp, i64, vp, i64, vp, i64,
+                                dbl, dbl, ci, vp, ctypes.c_size_t, vp]),
         "ns_gemm_f32": (ci, [vp, i64, i64, i64, vp, i64, vp, i64, vp, i64, vp, i64, vp, i64, vp,
                              i64, ctypes.c_float, ctypes.c_float, vp]),
         "ns_gemm_bf16_nt": (ci, [vp, i64, i64, i64, vp, i64, vp, i64, vp, i64, vp, i64, vp, i64,
@@ -294,10 +298,17 @@ class Solver:
 GEMM_SYMMETRIC = 1
 
 
+def gemm_f64_scratch_bytes(m: int, n: int, k: int, symmetric: bool = False) -> int:
+    """Scratch that lets :func:`gemm_f64` split the K range of its last,
+    partial round of tiles (0: no split for this shape)."""
+    return int(lib().ns_gemm_f64_scratch_bytes(m, n, k, GEMM_SYMMETRIC if symmetric else 0))
+
+
 def gemm_f64(X, Y, D=None, E1=None, E2=None, diag: float = 0.0, scale: float = 1.0,
-             want_sumsq: bool = False, symmetric: bool = False, stream=None):
+             want_sumsq: bool = False, symmetric: bool = False, stream=None, scratch=None):
     """``D = diag I + scale X Y + E1 + E2`` through the library's MFMA GEMM
-    (``symmetric``: upper tiles computed, lower triangle mirrored)."""
+    (``symmetric``: upper tiles computed, lower triangle mirrored; ``scratch``:
+    a device tensor for the split-K tail, see :func:`gemm_f64_scratch_bytes`)."""
     import torch
     for t, nm in ((X, "X"), (Y, "Y")):
         _require_cuda_f64(t, nm)
@@ -312,11 +323,12 @@ def gemm_f64(X, Y, D=None, E1=None, E2=None, diag: float = 0.0, scale: float = 1
     if want_sumsq:
         ss = torch.zeros(1 + int(lib().ns_gemm_f64_partials(m, n, flags)), dtype=torch.float64,
                          device=X.device)
-    check(lib().ns_gemm_f64(_stream_handle(stream), m, n, k, _ptr(X), X.stride(0), _ptr(Y),
-                            Y.stride(0), _ptr(D), D.stride(0), _ptr(E1),
-                            E1.stride(0) if E1 is not None else 0, _ptr(E2),
-                            E2.stride(0) if E2 is not None else 0, float(diag), float(scale),
-                            flags, _ptr(ss)))
+    sbytes = 0 if scratch is None else scratch.numel() * scratch.element_size()
+    check(lib().ns_gemm_f64_ws(_stream_handle(stream), m, n, k, _ptr(X), X.stride(0), _ptr(Y),
+                               Y.stride(0), _ptr(D), D.stride(0), _ptr(E1),
+                               E1.stride(0) if E1 is not None else 0, _ptr(E2),
+                               E2.stride(0) if E2 is not None else 0, float(diag), float(scale),
+                               flags, _ptr(scratch), sbytes, _ptr(ss)))
     return (D, ss[0]) if want_sumsq else D
 
 

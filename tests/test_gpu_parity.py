@@ -94,6 +94,52 @@ def test_gemm_f64_symmetric_output(torch, n):
     assert abs(float(ss.cpu()) - ssr) <= 1e-13 * ssr
 
 
+SPLIT_SHAPES = [(2944, 2944, 2944, False), (3000, 3100, 1000, False), (2944, 2944, 33, False),
+                (4096, 4096, 4096, True), (4100, 4100, 4100, True), (4096, 4096, 100, True)]
+
+
+@pytest.mark.parametrize("m,n,k,sym", SPLIT_SHAPES)
+def test_gemm_f64_split_tail(torch, m, n, k, sym):
+    """Shapes whose last round of 128 x 128 tiles is partial: with scratch,
+    those tiles are cut along K and finished by the fixup kernel.  Every
+    element obeys the summation error bound, the result agrees with the
+    unsplit call to that bound, a symmetric output stays exactly symmetric,
+    and the sum of squares (partials of whole tiles and fixup strips) is
+    the sum over the written matrix."""
+    rng = np.random.default_rng(m + 3 * n + 7 * k + sym)
+    if sym:
+        B = rng.standard_normal((m, k))
+        X = 0.5 * (B + B.T) if m == k else B
+        Y = X.T.copy() if m != k else X
+        E1 = rng.standard_normal((m, n))
+        E1 = 0.5 * (E1 + E1.T)
+    else:
+        X = rng.standard_normal((m, k))
+        Y = rng.standard_normal((k, n))
+        E1 = rng.standard_normal((m, n))
+    diag, scale = 0.7, -1.3
+    nbytes = nsr.gemm_f64_scratch_bytes(m, n, k, symmetric=sym)
+    if torch.cuda.get_device_properties(0).multi_processor_count == 256 and k >= 100:
+        assert nbytes > 0, "expected a split plan for this shape"
+    scratch = torch.empty(max(nbytes, 8) // 8, dtype=torch.float64, device="cuda")
+    Xd, Yd, Ed = to_dev(torch, X), to_dev(torch, Y), to_dev(torch, E1)
+    D, ss = nsr.gemm_f64(Xd, Yd, E1=Ed, diag=diag, scale=scale, want_sumsq=True, symmetric=sym,
+                         scratch=scratch)
+    D0 = nsr.gemm_f64(Xd, Yd, E1=Ed, diag=diag, scale=scale, symmetric=sym)
+    torch.cuda.synchronize()
+    got, got0 = D.cpu().numpy(), D0.cpu().numpy()
+    if sym:
+        assert np.array_equal(got, got.T)
+    ref = scale * (X @ Y) + diag * np.eye(m, n) + E1
+    bound = gamma(k + 4) * (abs(scale) * (np.abs(X) @ np.abs(Y)) + abs(diag) * np.eye(m, n)
+                            + np.abs(E1))
+    sel = np.triu_indices(m) if sym else np.s_[:, :]
+    assert np.all(np.abs(got - ref)[sel] <= 2 * bound[sel])
+    assert np.all(np.abs(got - got0)[sel] <= 4 * bound[sel])
+    ssr = float(np.sum(got * got))
+    assert abs(float(ss.cpu()) - ssr) <= 1e-13 * ssr
+
+
 def test_gemm_f64_no_addends(torch):
     rng = np.random.default_rng(5)
     X = rng.standard_normal((200, 300))
