@@ -77,6 +77,10 @@ typedef enum {
   NS_FACT_HORNER = 0,        /* Horner's scheme, eq. (z1): n mmm per step      */
   NS_FACT_SQUARING = 1,      /* (I+F)(I+F^2)(I+F^4)..., n = 2^s: 2s mmm
                                 (Tables 1-2, orders 2, 4, 8)                   */
+  NS_FACT_TABLE = 2,         /* nested programs: order 11 (Table 2, second
+                                form, 6 mmm), 15 (Table 3, 7 mmm), 45
+                                (eqs. ex1-ex3, 10 mmm); mmm counts include the
+                                step's residual                                */
   NS_FACT_UNIFIED = 3,       /* eqs. (xa2)-(zi1), n = w(p+1): p+w+1 mmm        */
   NS_FACT_UNIFIED_PLUS1 = 4, /* eq. (ztab2), n = w(p+1)+1                      */
   NS_FACT_COMPOSITE_DOUBLE = 5 /* double Newton-Schulz, Section 5.1; inner

@@ -129,6 +129,20 @@ scaled_identity_plus_kernel(const T* __restrict__ C, int64_t ldc, int64_t n,
   G[row * ldg + c] = (T)(v * inv);
 }
 
+// D = X + Y element-wise (n x n, common leading dimension; D may alias X or
+// Y), with an optional bf16 copy of D.
+template <typename T>
+__global__ void __launch_bounds__(kThreads)
+add_kernel(const T* X, const T* Y, T* D, uint16_t* Db, int64_t ld, int64_t n) {
+  const int64_t row = blockIdx.y;
+  const int64_t c = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (row >= n || c >= n) return;
+  const int64_t i = row * ld + c;
+  const T v = X[i] + Y[i];
+  D[i] = v;
+  if (Db) Db[i] = __builtin_bit_cast(uint16_t, (__bf16)(float)v);
+}
+
 // dst (float64 or float32) = (T) src, n x n.
 template <typename S, typename D>
 __global__ void __launch_bounds__(kThreads)
@@ -260,6 +274,16 @@ template void launch_scaled_identity_plus<double>(const double*, int64_t, int64_
                                                   double*, int64_t, hipStream_t);
 template void launch_scaled_identity_plus<float>(const float*, int64_t, int64_t, const double*,
                                                  float*, int64_t, hipStream_t);
+
+template <typename T>
+void launch_add(const T* X, const T* Y, T* D, uint16_t* Db, int64_t ld, int64_t n, hipStream_t st) {
+  dim3 grid((unsigned)((n + kThreads - 1) / kThreads), (unsigned)n);
+  hipLaunchKernelGGL(add_kernel<T>, grid, dim3(kThreads), 0, st, X, Y, D, Db, ld, n);
+}
+template void launch_add<double>(const double*, const double*, double*, uint16_t*, int64_t, int64_t,
+                                 hipStream_t);
+template void launch_add<float>(const float*, const float*, float*, uint16_t*, int64_t, int64_t,
+                                hipStream_t);
 
 template <typename S, typename D>
 void launch_convert(const S* src, int64_t lds, int64_t n, D* dst, int64_t ldd, hipStream_t st) {

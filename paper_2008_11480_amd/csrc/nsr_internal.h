@@ -83,6 +83,11 @@ template <typename T>
 void launch_scaled_identity_plus(const T* C, int64_t ldc, int64_t n, const double* alpha, T* G,
                                  int64_t ldg, hipStream_t st);
 
+// D = X + Y for n x n matrices with leading dimension ld (D may alias X or
+// Y); Db: optional bf16 copy of D.
+template <typename T>
+void launch_add(const T* X, const T* Y, T* D, uint16_t* Db, int64_t ld, int64_t n, hipStream_t st);
+
 // dst = (D) src for an n x n matrix (double <-> float).
 template <typename S, typename D>
 void launch_convert(const S* src, int64_t lds, int64_t n, D* dst, int64_t ldd, hipStream_t st);

@@ -371,6 +371,76 @@ int step_classic(ns_solver* s, int order, int fact, int p, int w) {
   return resid_into(s, s->F, s->G[s->gcur], true);  // F_k = I - A G_k
 }
 
+// D = X + Y element-wise for matrices of the solver (bf16 copy kept in mixed
+// mode).
+void add_into(ns_solver* s, Mat& D, const Mat& X, const Mat& Y) {
+  if (is_f64(s))
+    launch_add<double>(X.d, Y.d, D.d, nullptr, s->ld, s->n, s->stream);
+  else
+    launch_add<float>(X.f, Y.f, D.f, D.b, s->ld, s->n, s->stream);
+}
+
+// Nested programs of the tables, right orientation (Y = F_k = I - A X):
+//  * order 11 (Table 2, second form): the polynomial
+//    (Y + Y^2)(I + (Y^2 + Y^4)(I + Y^4)) is formed from Y^2, Y^4 first and
+//    applied to X last; with the next residual, 6 products per step.
+//  * order 15 (Table 3): U = X (I + Y + Y^2), Y^3 = I - A U (eq. ua1), then
+//    Z = U (I + (I + Y^6)(Y^3 + Y^6)); 7 products.
+//  * order 45 (eqs. ex1-ex3): U3 = X (I + Y + Y^2) (the polynomial of
+//    eq. ex1 written in Y), Y^3 = I - A U3, U9 = U3 (I + Y^3 + Y^6),
+//    Y^9 = I - A U9, Z = U9 (I + (I + Y^18)(Y^9 + Y^18)); 10 products.
+// Every factor I + W is applied as X + X W, the powers and sums of powers are
+// products among polynomials in one residual (K_POWER), and each
+// intermediate residual is a full product, as in the other forms.
+int step_table(ns_solver* s, int order) {
+  const bool f2_ready = s->p0_is_f2;  // P[0] holds F^2 from the floor test
+  s->p0_is_f2 = false;
+  Mat& Gc = s->G[s->gcur];
+  Mat& Gn = s->G[s->gcur ^ 1];
+  const bool impl = s->g_implicit;
+  Mat &F = s->F, &P0 = s->P[0], &P1 = s->P[1], &C0 = s->C[0], &C1 = s->C[1];
+  int rc = NS_OK;
+#define NSR_TRY(x) \
+  if ((rc = (x)) != NS_OK) return rc
+  if (order == 11) {
+    if (!f2_ready) NSR_TRY(mm(s, P0, &F, F, nullptr, nullptr, 0.0, 1.0, false, K_POWER));  // Y^2
+    NSR_TRY(mm(s, P1, &P0, P0, nullptr, nullptr, 0.0, 1.0, false, K_POWER));  // Y^4
+    add_into(s, C0, P0, P1);                                                 // S = Y^2 + Y^4
+    NSR_TRY(mm(s, C1, &C0, P1, &C0, nullptr, 0.0, 1.0, false, K_POWER));      // V = S + S Y^4
+    add_into(s, P1, F, P0);                                                  // T = Y + Y^2
+    NSR_TRY(mm(s, C0, &P1, C1, &P1, nullptr, 0.0, 1.0, false, K_POWER));      // C = T + T V
+    NSR_TRY(apply_g(s, Gc, impl, C0, Gn));                                   // X (I + C)
+    s->gcur ^= 1;
+  } else if (order == 15 || order == 45) {
+    if (f2_ready)
+      add_into(s, P0, P0, F);                                                // Y + Y^2
+    else
+      NSR_TRY(mm(s, P0, &F, F, &F, nullptr, 0.0, 1.0, false, K_POWER));
+    NSR_TRY(apply_g(s, Gc, impl, P0, Gn));                                   // U = X (I + Y + Y^2)
+    NSR_TRY(resid_into(s, F, Gn, false));                                    // Y^3 = I - A U
+    if (order == 15) {
+      NSR_TRY(mm(s, P1, &F, F, nullptr, nullptr, 0.0, 1.0, false, K_POWER));  // Y^6
+      add_into(s, C0, P1, F);                                                // S = Y^3 + Y^6
+      NSR_TRY(mm(s, C1, &P1, C0, &C0, nullptr, 0.0, 1.0, false, K_POWER));    // W = S + Y^6 S
+      NSR_TRY(mm(s, Gc, &Gn, C1, &Gn, nullptr, 0.0, 1.0, false, K_APPLY));    // Z = U + U W
+    } else {
+      NSR_TRY(mm(s, C0, &F, F, &F, nullptr, 0.0, 1.0, false, K_POWER));       // Y^3 + Y^6
+      NSR_TRY(mm(s, Gc, &Gn, C0, &Gn, nullptr, 0.0, 1.0, false, K_APPLY));    // U9
+      NSR_TRY(resid_into(s, F, Gc, false));                                  // Y^9 = I - A U9
+      NSR_TRY(mm(s, P1, &F, F, nullptr, nullptr, 0.0, 1.0, false, K_POWER));  // Y^18
+      add_into(s, C0, F, P1);                                                // S = Y^9 + Y^18
+      NSR_TRY(mm(s, C1, &P1, C0, &C0, nullptr, 0.0, 1.0, false, K_POWER));    // W = S + Y^18 S
+      NSR_TRY(mm(s, Gn, &Gc, C1, &Gc, nullptr, 0.0, 1.0, false, K_APPLY));    // Z = U9 + U9 W
+      s->gcur ^= 1;
+    }
+  } else {
+    return fail(NS_EINVAL, "no nested table program for order %d (11, 15, 45)", order);
+  }
+#undef NSR_TRY
+  s->g_implicit = false;
+  return resid_into(s, s->F, s->G[s->gcur], true);  // F_k = I - A G_k
+}
+
 // Precalculation of Section 5.1: T_0 = G_0, Gamma_0 = F_0,
 // L_0 = T_0 P(Gamma_0), Gamma_1 = I - A L_0.
 int composite_start(ns_solver* s, int order) {
@@ -481,6 +551,10 @@ int validate_step_args(ns_solver* s, int order, int fact, int p, int w) {
     case NS_FACT_UNIFIED_PLUS1:
       if (p < 0 || w < 1 || w * (p + 1) + 1 != order)
         return fail(NS_EINVAL, "unified+1 form needs order = w (p + 1) + 1");
+      return NS_OK;
+    case NS_FACT_TABLE:
+      if (order != 11 && order != 15 && order != 45)
+        return fail(NS_EINVAL, "table programs exist for orders 11, 15, 45 (got %d)", order);
       return NS_OK;
     case NS_FACT_COMPOSITE_DOUBLE:
       if (!s->composite_capable)
@@ -679,7 +753,8 @@ int ns_step(ns_solver* s, int order, int factorization, int p, int w, double* fn
   if (int rc = validate_step_args(s, order, factorization, p, w)) return rc;
   HIP_TRY(hipSetDevice(s->device));
   int rc = (factorization == NS_FACT_COMPOSITE_DOUBLE) ? step_composite(s, order)
-                                                       : step_classic(s, order, factorization, p, w);
+           : (factorization == NS_FACT_TABLE)            ? step_table(s, order)
+                                                         : step_classic(s, order, factorization, p, w);
   if (rc) return rc;
   if (hipGetLastError() != hipSuccess) return fail(NS_EHIP, "kernel launch failed");
   if (fnorm_out) {
@@ -781,6 +856,8 @@ int richardson_ns_solve(ns_solver* s, const double* b, double* theta, const ns_s
     ++k;
     int rc = (o->factorization == NS_FACT_COMPOSITE_DOUBLE)
                  ? step_composite(s, o->order)
+             : (o->factorization == NS_FACT_TABLE)
+                 ? step_table(s, o->order)
                  : step_classic(s, o->order, o->factorization, o->p, o->w);
     if (rc) return rc;
     if (q > 0) {

@@ -24,7 +24,7 @@ PREC_FP64, PREC_FP32, PREC_MIXED_BF16 = 0, 1, 2
 # ns_scale
 SCALE_FROBENIUS, SCALE_INF_HALF = 0, 1
 # ns_factorization
-FACT = {"horner": 0, "squaring": 1, "unified": 3, "unified_plus1": 4, "composite_double": 5}
+FACT = {"horner": 0, "squaring": 1, "table": 2, "unified": 3, "unified_plus1": 4, "composite_double": 5}
 # ns_stop_reason
 STOP_NAMES = {0: "none", 1: "f_tol", 2: "floor", 3: "k_max", 4: "diverged", 5: "resid_tol",
               6: "refine_max", 7: "refine_stall"}

@@ -239,6 +239,10 @@ SOLVE_CASES = [
     (200, 1e2, 5, "unified_plus1", 1, 2),
     (200, 1e2, 3, "unified_plus1", 0, 2),
     (200, 1e2, 4, "unified_plus1", 2, 1),
+    (3, 10.0, 11, "table", 0, 0),
+    (200, 1e3, 11, "table", 0, 0),
+    (300, 1e4, 15, "table", 0, 0),
+    (257, 1e4, 45, "table", 0, 0),
     (130, 1e2, 4, "composite_double", 0, 0),
     (300, 1e3, 8, "composite_double", 0, 0),
     (97, 1e2, 2, "composite_double", 0, 0),
@@ -281,6 +285,43 @@ def test_step_level_G_matches_oracle(torch):
         assert np.linalg.norm(G - g) <= 1e-12 * np.linalg.norm(g), k
         assert np.linalg.norm(F - f) <= 1e-12 * max(1.0, np.linalg.norm(f)) * n, k
         assert fk == pytest.approx(np.linalg.norm(f), rel=1e-10, abs=1e-12)
+
+
+@pytest.mark.parametrize("symmetric", [True, False])
+@pytest.mark.parametrize("order", [11, 15, 45])
+def test_table_step_matches_oracle(torch, order, symmetric):
+    """Nested table programs (orders 11, 15, 45): G_k and F_k element-wise
+    against the oracle's step for the first two steps (the first with the
+    implicit G_0), and the products per explicit step equal the program's
+    mmm count (which includes the step's residual)."""
+    n = 193
+    sysm = inputs.spd_qlq(n, 1e4, seed=31 + order)
+    s = nsr.Solver(n)
+    s.set_symmetric(symmetric)
+    s.bind(to_dev(torch, sysm.A))
+    alpha, _ = s.init_scale()
+    g = np.eye(n) / oracle.alpha_frobenius(sysm.A)
+    for k in range(1, 3):
+        if k == 2:
+            s.timing(True)
+        fk = s.step(order, "table")
+        g = oracle.ns_step(sysm.A, g, order, "table")
+        f = oracle.residual(sysm.A, g)
+        G = s.get_G().cpu().numpy()
+        F = s.get_F().cpu().numpy()
+        assert np.linalg.norm(G - g) <= 1e-11 * np.linalg.norm(g), k
+        assert np.linalg.norm(F - f) <= 1e-11 * max(1.0, np.linalg.norm(f)) * n, k
+        assert fk == pytest.approx(np.linalg.norm(f), rel=1e-9, abs=1e-11)
+    launches, _, _ = s.timing_read(0)
+    assert launches == oracle.form_mmm(order, "table")
+
+
+def test_table_order_rejected(torch):
+    s = nsr.Solver(64)
+    s.bind(torch.eye(64, dtype=torch.float64, device="cuda"))
+    s.init_scale()
+    with pytest.raises(nsr.NSError):
+        s.step(8, "table")
 
 
 def test_solve_is_deterministic(torch):
