@@ -268,6 +268,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision legs")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving leg")
+    ap.add_argument("--no-programs", action="store_true",
+                    help="skip timing the other evaluation programs on the headline system")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="also run a plain device copy of this many MiB (PMC calibration)")
     args = ap.parse_args()
@@ -280,7 +282,7 @@ def main():
         sys.exit(2)
 
     import torch
-    from paper_2008_11480_amd import nsr
+    from paper_2008_11480_amd import autotune, nsr
 
     assert torch.cuda.is_available(), "no GPU"
     torch.cuda.set_device(0)
@@ -361,6 +363,27 @@ def main():
             "fnorm_hist": last.fnorm_hist,
         },
     }
+    if not args.no_programs and not fixed:
+        # The same system with every candidate program (Tables 1-3, eqs.
+        # ex1-ex3, ztab2), fastest first; the headline stays order-8 squaring.
+        trials = autotune.time_programs(solver, b, theta, autotune.CANDIDATES, reps=1,
+                                        resid_tol=w["resid_tol"], k_max=w["k_max"])
+        mu = 1.0 - sysm.lam / last.alpha
+        floor = 0.5 * min(last.fnorm_hist)
+        out["programs"] = {
+            "workload": args.workload, "precision": "fp64",
+            "trials": [{"program": t.program.name, "ms_per_solve": t.ms,
+                        "solves_per_s": 1e3 / t.ms, "ns_steps": t.ns_steps,
+                        "refine_steps": t.refine_steps, "mmm": t.mmm,
+                        "rel_resid": t.rel_resid, "ok": t.ok,
+                        "predicted_ns_steps": autotune.predicted_steps_spectrum(
+                            t.program.order, mu, floor)}
+                       for t in trials],
+            "chosen": trials[0].program.name,
+        }
+        for t in trials:
+            log(f"program {t.program.name}: {t.ms:.1f} ms ns_steps={t.ns_steps} mmm={t.mmm} "
+                f"rel_resid={t.rel_resid:.2e}")
     del solver
     torch.cuda.empty_cache()
 

@@ -450,3 +450,25 @@ def test_accelerator_needs_composite(torch):
     with pytest.raises(nsr.NSError) as e:
         gpu_solve(torch, sysm, order=4, form="squaring", accel_q=2)
     assert e.value.status == nsr.NS_EINVAL
+
+
+def test_program_trials_match_oracle_steps(torch):
+    """Every candidate program solves the same system to the tolerance; its
+    Newton-Schulz step count agrees with the oracle's for that program (+-1)
+    and the trials come back fastest first."""
+    from paper_2008_11480_amd import autotune
+    sysm = inputs.spd_qlq(256, 1e3, seed=77)
+    A, b = to_dev(torch, sysm.A), to_dev(torch, sysm.b)
+    th = torch.zeros_like(b)
+    s = nsr.Solver(256)
+    s.bind(A)
+    trials = autotune.time_programs(s, b, th, resid_tol=1e-12)
+    assert len(trials) == len(autotune.CANDIDATES)
+    assert all(t.ok for t in trials), [(t.program.name, t.rel_resid) for t in trials]
+    assert [t.ms for t in trials] == sorted(t.ms for t in trials)
+    for t in trials:
+        pr = t.program
+        orc = oracle.solve(sysm.A, sysm.b, oracle.SolveOptions(
+            order=pr.order, form=pr.form, p=pr.p if pr.form.startswith("unified") else None,
+            w=pr.w if pr.form.startswith("unified") else None, resid_tol=1e-12))
+        assert abs(t.ns_steps - orc.ns_steps) <= 1, (pr.name, t.ns_steps, orc.ns_steps)
