@@ -183,6 +183,25 @@ def run_composite(torch, nsr, steps, warmup):
     return out
 
 
+def timeline_summary(tl, ns, groups):
+    """Critical-path view of a batch from the device timeline (ms)."""
+    f32 = tl[:, 1] - tl[:, 0]
+    f64 = tl[:, 3] - tl[:, 2]
+    esc = ~np.isnan(tl[:, 2])
+    end = np.nanmax(tl[:, [1, 3]])
+    busy = np.nansum(f32) + np.nansum(f64)
+    big = np.argsort(-np.nan_to_num(f32))[:3]
+    return {
+        "f32_pass_end": float(np.nanmax(tl[:, 1])) / 1e3,
+        "f64_pass": [float(np.nanmin(tl[esc, 2])) / 1e3, float(np.nanmax(tl[esc, 3])) / 1e3]
+        if esc.any() else None,
+        "end": float(end) / 1e3,
+        "longest_f32_solves": [{"n": int(ns[i]), "ms": float(f32[i]) / 1e3} for i in big],
+        "longest_f64_solve_ms": float(np.nanmax(f64)) / 1e3 if esc.any() else None,
+        "occupancy": float(busy / (end * groups)) if end > 0 else None,
+    }
+
+
 def run_batch(torch, nsr, reps_timed):
     """2048 harmonic-regressor Gram systems, m ~ U{8..128} (N = 16..256), in
     one persistent launch per solve of the whole batch: float32 MFMA order 4,
@@ -210,6 +229,7 @@ def run_batch(torch, nsr, reps_timed):
             times.append(dt)
         log(f"batch {'warmup' if i == 0 else 'run'} {i}: {dt * 1e3:.1f} ms")
     mk = float(np.median(times))
+    tl, wgs = B.timeline(t)
     flop = sum(r.gemm_flop for r in reps)
     ok = sum(1 for r in reps if r.status == nsr.NS_OK)
     esc = sum(1 for r in reps if r.precision == nsr.PREC_FP64)
@@ -219,8 +239,35 @@ def run_batch(torch, nsr, reps_timed):
         rel.append(float(np.linalg.norm(s.b - s.A @ x) / np.linalg.norm(s.b)))
     rel = np.array(rel)
     steps = np.array([r.ns_steps for r in reps])
+    # Variant: the paper's own scalar preconditioner alpha = ||A||_inf / 2 + eps
+    # (Section 2), same launch shape.
+    opts_inf = dict(opts, scale=nsr.SCALE_INF_HALF, eps=1e-9)
+    ths_inf = [torch.zeros_like(b) for b in bs]
+    t_inf = []
+    for i in range(reps_timed + 1):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        reps_inf = B.poll(B.submit(As, bs, ths_inf, **opts_inf), wait=True)
+        if i > 0:
+            t_inf.append(time.perf_counter() - t0)
+    mk_inf = float(np.median(t_inf))
+    steps_inf = np.array([r.ns_steps for r in reps_inf])
+    rel_inf = np.array([float(np.linalg.norm(s.b - s.A @ th.cpu().numpy()) / np.linalg.norm(s.b))
+                        for s, th in zip(systems, ths_inf)])
+    ok_inf = [r.status == nsr.NS_OK for r in reps_inf]
+    log(f"batch inf_half scaling: {mk_inf * 1e3:.1f} ms, ns_steps p50 "
+        f"{np.median(steps_inf):.0f} (frobenius {np.median(steps):.0f})")
     return {
         "workload": "harmonic_batch2048_m8-128_o4", "count": count,
+        "scale": "frobenius",
+        "inf_half_variant": {
+            "makespan_ms": mk_inf * 1e3, "solves_per_s": count / mk_inf,
+            "ok": int(sum(ok_inf)), "escalated_to_fp64": sum(1 for r in reps_inf
+                                                          if r.precision == nsr.PREC_FP64),
+            "rel_resid_max_ok": float(rel_inf[ok_inf].max()),
+            "ns_steps_p50": float(np.median(steps_inf)), "ns_steps_max": int(steps_inf.max()),
+            "ns_steps_total": int(steps_inf.sum()), "ns_steps_total_frobenius": int(steps.sum()),
+        },
         "launch": {"waves_per_group": waves, "groups": groups},
         "makespan_ms": mk * 1e3, "solves_per_s": count / mk,
         "alg_tflops": flop / mk / 1e12,
@@ -228,6 +275,7 @@ def run_batch(torch, nsr, reps_timed):
         "rel_resid_max_ok": float(rel[[r.status == nsr.NS_OK for r in reps]].max()),
         "rel_resid_p50": float(np.median(rel)),
         "ns_steps_p50": float(np.median(steps)), "ns_steps_max": int(steps.max()),
+        "timeline_ms": timeline_summary(tl, [s.n for s in systems], groups),
     }
 
 
@@ -266,7 +314,13 @@ def main():
     ap.add_argument("--workload", default="spd4096_k1e4_o8",
                     choices=["spd4096_k1e4_o8", "spd64_k1e2_o4"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision legs")
+    ap.add_argument("--no-mixed", action="store_true",
+                    help="skip every leg after the float64 headline (mixed, composite, batch, "
+                         "serving)")
+    ap.add_argument("--no-mixed4096", action="store_true",
+                    help="skip the mixed-precision solve of the headline system")
+    ap.add_argument("--no-composite", action="store_true", help="skip the N=8192 legs")
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched leg")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving leg")
     ap.add_argument("--no-programs", action="store_true",
                     help="skip timing the other evaluation programs on the headline system")
@@ -387,7 +441,7 @@ def main():
     del solver
     torch.cuda.empty_cache()
 
-    if not args.no_mixed and not fixed:
+    if not args.no_mixed and not args.no_mixed4096 and not fixed:
         # Same N=4096 system, mixed precision, to the same 1e-12 residual.
         ms = nsr.Solver(n, precision=nsr.PREC_MIXED_BF16, composite=False)
         ms.bind(A)
@@ -408,8 +462,11 @@ def main():
         }
         del ms
         torch.cuda.empty_cache()
-        out["composite"] = run_composite(torch, nsr, max(2, args.steps // 2), 1)
-        out["batch"] = run_batch(torch, nsr, 3)
+    if not args.no_mixed and not fixed:
+        if not args.no_composite:
+            out["composite"] = run_composite(torch, nsr, max(2, args.steps // 2), 1)
+        if not args.no_batch:
+            out["batch"] = run_batch(torch, nsr, 3)
         if not args.no_serving:
             out["serving"] = run_serving(torch, nsr)
 

@@ -97,7 +97,11 @@ typedef enum {
   NS_STOP_DIVERGED = 4,     /* ||F_k|| > ||F_0|| or non-finite                 */
   NS_STOP_RESID_TOL = 5,    /* ||b - A theta|| / ||b|| <= resid_tol            */
   NS_STOP_REFINE_MAX = 6,
-  NS_STOP_REFINE_STALL = 7  /* less than a factor 2 over 3 refinement steps    */
+  NS_STOP_REFINE_STALL = 7, /* less than a factor 2 over 3 refinement steps    */
+  NS_STOP_PRECISION = 8     /* batched float32 attempt: ||F_k||_F >= 1/2 and not
+                               halving after the steps that resolve every
+                               eigenvalue float32 can represent; re-solved in
+                               float64                                        */
 } ns_stop_reason;
 
 typedef struct ns_solver ns_solver;
@@ -242,8 +246,10 @@ int ns_batch_create(int device, void* hip_stream, int64_t max_n, int max_count,
                     int slots, int precision, void* workspace, size_t bytes,
                     ns_batch** out);
 
-/* Launch shape: waves per workgroup (1, 2 or 4) and number of workgroups
- * (0: one per slot).  Set by ns_batch_autotune or by the caller. */
+/* Launch shape of the float32 (or float64-only) pass: waves per workgroup
+ * (1, 2, 4 or 8) and number of workgroups (0: one per slot).  Set by
+ * ns_batch_autotune or by the caller.  The float64 pass that re-solves the
+ * systems float32 could not runs eight-wave workgroups, one per CU. */
 int ns_batch_set_launch(ns_batch* b, int waves_per_group, int groups);
 
 /* Enqueue the solves of `count` systems.  n, A, lda, b, theta are HOST arrays
@@ -272,6 +278,16 @@ int ns_batch_autotune(ns_batch* b, int count, const int64_t* n, const double* co
                       const int64_t* lda, const double* const* b_vec,
                       double* const* theta, const ns_solve_opts* opts,
                       int* best_waves, int* best_groups, double* best_ms);
+
+/* Per-system timeline of the last ticket returned by ns_batch_poll (a tracing
+ * aid for the scheduler): times_us[4 i + 0..3] = begin and end of the float32
+ * attempt, begin and end of the float64 attempt of system i (NAN when that
+ * attempt did not run), in microseconds from the earliest begin in the batch,
+ * read from the device's constant-rate wall clock; workgroup[2 i + 0..1]
+ * (optional) = the workgroup that ran each attempt (-1: not run).  Arrays
+ * hold 4 x count and 2 x count entries.  Errors: NS_EINVAL (another ticket,
+ * NULL times_us), NS_EHIP. */
+int ns_batch_timeline(ns_batch* b, uint64_t ticket, double* times_us, int32_t* workgroup);
 
 int ns_batch_destroy(ns_batch* b);
 

@@ -41,6 +41,8 @@ struct BatchResult {
   int32_t status, ns_stop, refine_stop, ns_steps, refine_steps, precision, n_fnorm, n_resid;
   double alpha, rel_resid;
   int64_t mmm;
+  int64_t clock[4];    // wall-clock ticks: float32 attempt begin / end, float64 begin / end
+  int32_t wg[2];       // workgroup of each attempt (-1: not run)
   double fnorm_hist[NS_HIST_F];
 };
 
@@ -48,7 +50,9 @@ struct BatchArgs {
   const BatchDesc* desc;
   BatchResult* res;
   const int32_t* order;   // processing order (indices into desc)
-  int32_t* counter;       // work counter, zeroed before the launch
+  int32_t* counter;       // [0] float32 / float64-only work counter, [1] float64
+                          // queue counter, [2] queue length; zeroed before launch
+  int32_t* retry;         // queue of systems for the float64 pass (count entries)
   char* slots;
   int64_t slot_bytes;
   int32_t count;
@@ -59,6 +63,9 @@ struct BatchArgs {
   int32_t floor_detect;
   int32_t escalate;       // 1: float32 first, float64 when it fails
   int32_t fp64_only;      // 1: float64 from the start
+  int32_t scale;           // ns_scale
+  int32_t pad;
+  double eps;              // NS_SCALE_INF_HALF: alpha = ||A||_inf / 2 + eps
   double f_tol;
   double resid_tol;
 };
@@ -88,6 +95,21 @@ __device__ __forceinline__ double block_sum_all(double v, double* red) {
   return s;
 }
 
+// Maximum over the workgroup, same value returned to every thread.
+template <int NW>
+__device__ __forceinline__ double block_max_all(double v, double* red) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
+  if (lane == 0) red[wave] = v;
+  __syncthreads();
+  double m = red[0];
+#pragma unroll
+  for (int w = 1; w < NW; ++w) m = fmax(m, red[w]);
+  __syncthreads();
+  return m;
+}
+
 __device__ __forceinline__ f32x4 mfma(float a, float b, f32x4 c) {
   return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
 }
@@ -103,66 +125,182 @@ template <> struct Acc<double> { typedef f64x4 type; };
 __device__ __forceinline__ int acc_row(float, int lk, int r) { return 4 * lk + r; }
 __device__ __forceinline__ int acc_row(double, int lk, int r) { return lk + 4 * r; }
 
+// In-workgroup GEMM tiling: the n x n output is walked in BM x BN blocks
+// (32 x 32 for one wave, 64 x 32 for two, 64 x 64 for four, 128 x 64 for
+// eight), one 32 x 32 sub-block (2 x 2 MFMA blocks of 16 x 16) per wave.
+// The K range of a block is walked in slabs of KB (16 float32 / 8 float64)
+// staged global -> registers (one slab ahead, 16-byte loads) -> two LDS
+// buffers -> MFMA fragments, one barrier per slab.
+template <int NW> struct Block {
+  static constexpr int BM = NW >= 8 ? 128 : (NW >= 2 ? 64 : 32);
+  static constexpr int BN = NW >= 4 ? 64 : 32;
+  static_assert((BM / 32) * (BN / 32) == NW, "one 32 x 32 sub-block per wave");
+};
+template <typename T, int NW> struct Stage {
+  static constexpr int KB = sizeof(T) == 4 ? 16 : 8;   // K slab
+  static constexpr int VE = 16 / (int)sizeof(T);       // elements per 16-byte load
+  static constexpr int XS = KB + (sizeof(T) == 4 ? 4 : 2);
+  static constexpr int YS = Block<NW>::BN + (sizeof(T) == 4 ? 4 : 2);
+  static constexpr int BUF = Block<NW>::BM * XS + KB * YS;   // one buffer, elements
+  static constexpr int BYTES = 2 * BUF * (int)sizeof(T);
+};
+template <int NW> struct StageBytes {
+  static constexpr int a = Stage<float, NW>::BYTES, b = Stage<double, NW>::BYTES;
+  static constexpr int value = a > b ? a : b;
+};
+
+typedef float f32v4 __attribute__((ext_vector_type(4)));
+typedef double f64v2 __attribute__((ext_vector_type(2)));
+template <typename T> struct Vec16;
+template <> struct Vec16<float> { typedef f32v4 type; };
+template <> struct Vec16<double> { typedef f64v2 type; };
+
 // D = diag I + scale X Y + E1 + E2 (n x n); returns sum D^2 over the
 // workgroup when want_ss (uniform).  XA: X is the float64 input A (read
-// through lda and converted), otherwise X is T with leading dimension ldx.
+// through lda), otherwise X is T with leading dimension ldx (multiple of 4).
+// lds: StageBytes<NW> of LDS shared by the workgroup.
 template <typename T, int NW>
 __device__ double wg_gemm(int n, const T* X, int ldx, const double* XA, int64_t lda, const T* Y,
                           int ldy, T* D, int ldd, const T* E1, const T* E2, int lde, T diag,
-                          T scale, bool want_ss, double* red) {
+                          T scale, bool want_ss, double* red, void* lds) {
   typedef typename Acc<T>::type acc_t;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  typedef typename Vec16<T>::type vec_t;
+  typedef Stage<T, NW> S;
+  constexpr int KB = S::KB, VE = S::VE, XS = S::XS, YS = S::YS;
+  constexpr int BM = Block<NW>::BM, BN = Block<NW>::BN;
+  constexpr int NTH = NW * 64;
+  constexpr int XV = KB / VE, YV = BN / VE;      // 16-byte vectors per slab row
+  constexpr int XTOT = BM * XV, YTOT = KB * YV;  // vectors per slab
+  constexpr int XPER = (XTOT + NTH - 1) / NTH, YPER = (YTOT + NTH - 1) / NTH;
+  // Keep the per-thread index arithmetic inside each call: the solver calls
+  // this from several places in one loop, and hoisting every call's
+  // invariants out of that loop would exhaust the register file.
+  int tid = threadIdx.x;
+  asm volatile("" : "+v"(tid));
+  T* Xs[2] = {reinterpret_cast<T*>(lds), reinterpret_cast<T*>(lds) + S::BUF};
+  T* Ys[2] = {Xs[0] + BM * XS, Xs[1] + BM * XS};
+  const int lane = tid & 63, wave = tid >> 6;
   const int lr = lane & 15, lk = lane >> 4;
-  const int nt = (n + 31) / 32;
+  const int sr = (wave / (BN / 32)) * 32, sc = (wave % (BN / 32)) * 32;
+  const bool xa_vec = XA && ((lda & 1) == 0) && ((reinterpret_cast<uintptr_t>(XA) & 15) == 0);
+  const int nbm = (n + BM - 1) / BM, nbn = (n + BN - 1) / BN;
+  const int nk = (n + KB - 1) / KB;
   double ss = 0.0;
-  for (int t = wave; t < nt * nt; t += NW) {
-    const int r0 = (t / nt) * 32, c0 = (t % nt) * 32;
+  for (int blk = 0; blk < nbm * nbn; ++blk) {
+    const int r0 = (blk / nbn) * BM, c0 = (blk % nbn) * BN;
+    const bool active = (r0 + sr < n) && (c0 + sc < n);   // wave-uniform
+    vec_t xr[XPER], yr[YPER];
+    auto load = [&](int k0) {
+#pragma unroll
+      for (int u = 0; u < XPER; ++u) {
+        const int v = tid + NTH * u;
+        const int row = r0 + v / XV, col = k0 + (v % XV) * VE;
+        vec_t val;
+#pragma unroll
+        for (int e = 0; e < VE; ++e) val[e] = T(0);
+        if (v < XTOT && row < n) {
+          if (XA) {
+            const double* src = XA + (int64_t)row * lda + col;
+            if (sizeof(T) == 8 && xa_vec && col + VE <= n) {
+              val = *reinterpret_cast<const vec_t*>(src);
+            } else {
+#pragma unroll
+              for (int e = 0; e < VE; ++e)
+                if (col + e < n) val[e] = (T)src[e];
+            }
+          } else {
+            const T* src = X + row * ldx + col;
+            if (col + VE <= n) {
+              val = *reinterpret_cast<const vec_t*>(src);
+            } else {
+#pragma unroll
+              for (int e = 0; e < VE; ++e)
+                if (col + e < n) val[e] = src[e];
+            }
+          }
+        }
+        xr[u] = val;
+      }
+#pragma unroll
+      for (int u = 0; u < YPER; ++u) {
+        const int v = tid + NTH * u;
+        const int row = k0 + v / YV, col = c0 + (v % YV) * VE;
+        vec_t val;
+#pragma unroll
+        for (int e = 0; e < VE; ++e) val[e] = T(0);
+        if (v < YTOT && row < n) {
+          const T* src = Y + row * ldy + col;
+          if (col + VE <= n) {
+            val = *reinterpret_cast<const vec_t*>(src);
+          } else {
+#pragma unroll
+            for (int e = 0; e < VE; ++e)
+              if (col + e < n) val[e] = src[e];
+          }
+        }
+        yr[u] = val;
+      }
+    };
+    auto store = [&](T* xs, T* ys) {
+#pragma unroll
+      for (int u = 0; u < XPER; ++u) {
+        const int v = tid + NTH * u;
+        if (v < XTOT) *reinterpret_cast<vec_t*>(&xs[(v / XV) * XS + (v % XV) * VE]) = xr[u];
+      }
+#pragma unroll
+      for (int u = 0; u < YPER; ++u) {
+        const int v = tid + NTH * u;
+        if (v < YTOT) *reinterpret_cast<vec_t*>(&ys[(v / YV) * YS + (v % YV) * VE]) = yr[u];
+      }
+    };
     acc_t acc[2][2];
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
       for (int j = 0; j < 2; ++j) acc[i][j] = acc_t{0, 0, 0, 0};
-    const int xr0 = r0 + lr, xr1 = r0 + 16 + lr;
-    const int yc0 = c0 + lr, yc1 = c0 + 16 + lr;
-    for (int k = 0; k < n; k += 4) {
-      const int kk = k + lk;
-      T a0 = 0, a1 = 0, b0 = 0, b1 = 0;
-      if (kk < n) {
-        if (XA) {
-          if (xr0 < n) a0 = (T)XA[(int64_t)xr0 * lda + kk];
-          if (xr1 < n) a1 = (T)XA[(int64_t)xr1 * lda + kk];
-        } else {
-          if (xr0 < n) a0 = X[xr0 * ldx + kk];
-          if (xr1 < n) a1 = X[xr1 * ldx + kk];
+    load(0);
+    for (int kt = 0; kt < nk; ++kt) {
+      T* xsb = (kt & 1) ? Xs[1] : Xs[0];
+      T* ysb = (kt & 1) ? Ys[1] : Ys[0];
+      store(xsb, ysb);
+      __syncthreads();
+      if (kt + 1 < nk) load((kt + 1) * KB);
+      if (active) {
+        const T* xs = xsb + (sr + lr) * XS + lk;
+        const T* ys = ysb + lk * YS + sc + lr;
+#pragma unroll
+        for (int ks = 0; ks < KB; ks += 4) {
+          const T a0 = xs[ks], a1 = xs[16 * XS + ks];
+          const T b0 = ys[ks * YS], b1 = ys[ks * YS + 16];
+          acc[0][0] = mfma(a0, b0, acc[0][0]);
+          acc[0][1] = mfma(a0, b1, acc[0][1]);
+          acc[1][0] = mfma(a1, b0, acc[1][0]);
+          acc[1][1] = mfma(a1, b1, acc[1][1]);
         }
-        if (yc0 < n) b0 = Y[kk * ldy + yc0];
-        if (yc1 < n) b1 = Y[kk * ldy + yc1];
       }
-      acc[0][0] = mfma(a0, b0, acc[0][0]);
-      acc[0][1] = mfma(a0, b1, acc[0][1]);
-      acc[1][0] = mfma(a1, b0, acc[1][0]);
-      acc[1][1] = mfma(a1, b1, acc[1][1]);
     }
+    if (active) {
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+      for (int i = 0; i < 2; ++i)
 #pragma unroll
-      for (int j = 0; j < 2; ++j) {
-        const int col = c0 + 16 * j + lr;
+        for (int j = 0; j < 2; ++j) {
+          const int col = c0 + sc + 16 * j + lr;
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int row = r0 + 16 * i + acc_row(T(0), lk, r);
-          if (row < n && col < n) {
-            T v = scale * acc[i][j][r];
-            if (row == col) v += diag;
-            if (E1) v += E1[row * lde + col];
-            if (E2) v += E2[row * lde + col];
-            D[row * ldd + col] = v;
-            ss += (double)v * (double)v;
+          for (int r = 0; r < 4; ++r) {
+            const int row = r0 + sr + 16 * i + acc_row(T(0), lk, r);
+            if (row < n && col < n) {
+              T v = scale * acc[i][j][r];
+              if (row == col) v += diag;
+              if (E1) v += E1[row * lde + col];
+              if (E2) v += E2[row * lde + col];
+              D[row * ldd + col] = v;
+              ss += (double)v * (double)v;
+            }
           }
         }
-      }
+    }
+    __syncthreads();  // LDS buffers free for the next block, D complete
   }
-  __syncthreads();  // D complete for every wave of the workgroup
   if (!want_ss) return 0.0;
   return block_sum_all<NW>(ss, red);
 }
@@ -240,6 +378,7 @@ struct SlotMats {
   void* C[2];
   float* A32;
   double* r;
+  void* lds;   // StageBytes<NW> of LDS for the GEMM stages
 };
 
 // Control values of one solve.  Every thread holds the same values (they are
@@ -268,13 +407,26 @@ __device__ bool wg_solve(const BatchArgs& P, const BatchDesc& d, const SlotMats&
   c.ns_steps = 0;
   c.refine_steps = 0;
   c.rel_resid = NAN;
-  // alpha = ||A||_F (Section 2, S = alpha I)
-  double ssa = 0.0;
-  for (int i = threadIdx.x; i < n * n; i += NW * 64) {
-    const double v = d.A[(int64_t)(i / n) * d.lda + (i % n)];
-    ssa += v * v;
+  // Scalar preconditioner S = alpha I (Section 2): alpha = ||A||_F, or the
+  // maximum row sum of |A| over 2 plus eps.
+  double alpha;
+  if (P.scale == NS_SCALE_INF_HALF) {
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    double mx = 0.0;
+    for (int row = wave; row < n; row += NW) {
+      double rs = 0.0;
+      for (int col = lane; col < n; col += 64) rs += fabs(d.A[(int64_t)row * d.lda + col]);
+      mx = fmax(mx, wsum(rs));
+    }
+    alpha = 0.5 * block_max_all<NW>(mx, red) + P.eps;
+  } else {
+    double ssa = 0.0;
+    for (int i = threadIdx.x; i < n * n; i += NW * 64) {
+      const double v = d.A[(int64_t)(i / n) * d.lda + (i % n)];
+      ssa += v * v;
+    }
+    alpha = sqrt(block_sum_all<NW>(ssa, red));
   }
-  const double alpha = sqrt(block_sum_all<NW>(ssa, red));
   c.alpha = alpha;
   if (!(alpha > 0.0) || !isfinite(alpha)) {
     c.ns_stop = NS_STOP_DIVERGED;
@@ -305,6 +457,19 @@ __device__ bool wg_solve(const BatchArgs& P, const BatchDesc& d, const SlotMats&
   int gc = 0;
   int ns_stop = isfinite(f0) ? NS_STOP_NONE : NS_STOP_DIVERGED;
   bool f2_ready = false;  // Pw[0] holds F_k^2 from the floor test
+  // Float32 attempt that can escalate: with order^(k32 - 1) >= ln 2 / 2^-24,
+  // every eigenvalue mu <= 1 - 2^-24 of F_0 has mu^(order^(k32 - 1)) <= 1/2
+  // (eq. fk1), so at step k32 + 1 it is below 2^-(order^2).
+  int bail_k = 0;
+  if (is32 && P.escalate) {
+    double e = 1.0;
+    int k32 = 1;
+    while (e < 0.6931471805599453 * 16777216.0) {
+      e *= (double)P.ns_order;
+      ++k32;
+    }
+    bail_k = k32 + 1;
+  }
   double fprev = f0;
   int k = 0;
   while (ns_stop == NS_STOP_NONE) {
@@ -316,12 +481,12 @@ __device__ bool wg_solve(const BatchArgs& P, const BatchDesc& d, const SlotMats&
       T* npw = (pw == Pw[0]) ? Pw[1] : Pw[0];
       if (!(i == 1 && f2_ready)) {
         wg_gemm<T, NW>(n, pw, ldw, nullptr, 0, pw, ldw, npw, ldw, nullptr, nullptr, ldw, T(0),
-                       T(1), false, red);
+                       T(1), false, red, sm.lds);
         c.mmm += 1;
       }
       T* nc = (cc == Cc[0]) ? Cc[1] : Cc[0];
       wg_gemm<T, NW>(n, cc, ldw, nullptr, 0, npw, ldw, nc, ldw, cc, npw, ldw, T(0), T(1), false,
-                     red);
+                     red, sm.lds);
       c.mmm += 1;
       pw = npw;
       cc = nc;
@@ -331,7 +496,7 @@ __device__ bool wg_solve(const BatchArgs& P, const BatchDesc& d, const SlotMats&
       wg_scaled_identity_plus<T, NW>(n, cc, alpha, Gn, ldw);
     } else {
       wg_gemm<T, NW>(n, G[gc], ldw, nullptr, 0, cc, ldw, Gn, ldw, G[gc], nullptr, ldw, T(0), T(1),
-                     false, red);
+                     false, red, sm.lds);
       c.mmm += 1;
     }
     gc ^= 1;
@@ -342,7 +507,7 @@ __device__ bool wg_solve(const BatchArgs& P, const BatchDesc& d, const SlotMats&
     // F_k = I - A G_k
     const double fk =
         sqrt(wg_gemm<T, NW>(n, AX, ldw, AXd, d.lda, G[gc], ldw, F, ldw, nullptr, nullptr, ldw,
-                            T(1), T(-1), true, red));
+                            T(1), T(-1), true, red, sm.lds));
     c.mmm += 1;
     if (threadIdx.x == 0 && k < NS_HIST_F) hist[k] = fk;
     c.n_fnorm = (k + 1 < NS_HIST_F) ? k + 1 : NS_HIST_F;
@@ -353,10 +518,15 @@ __device__ bool wg_solve(const BatchArgs& P, const BatchDesc& d, const SlotMats&
       ns_stop = NS_STOP_DIVERGED;
     } else if (fk <= P.f_tol) {
       ns_stop = NS_STOP_F_TOL;
+    } else if (bail_k > 0 && k >= bail_k && fk >= 0.5 && fk > 0.5 * fprev) {
+      // Every eigenvalue float32 can tell from 1 (mu <= 1 - 2^-24) is below
+      // 2^-(order^2) by now; a norm still >= 1/2 that does not halve belongs
+      // to eigenvalues float32 rounds to 1.
+      ns_stop = NS_STOP_PRECISION;
     } else {
       if (P.floor_detect && fk > 0.5 * fprev) {
         const double f2 = sqrt(wg_gemm<T, NW>(n, F, ldw, nullptr, 0, F, ldw, Pw[0], ldw, nullptr,
-                                              nullptr, ldw, T(0), T(1), true, red));
+                                              nullptr, ldw, T(0), T(1), true, red, sm.lds));
         c.mmm += 1;
         f2_ready = true;
         if (f2 <= 0.25 * fk) ns_stop = NS_STOP_FLOOR;
@@ -369,6 +539,10 @@ __device__ bool wg_solve(const BatchArgs& P, const BatchDesc& d, const SlotMats&
   c.ns_stop = ns_stop;
   if (ns_stop == NS_STOP_DIVERGED) {
     c.refine_stop = NS_STOP_DIVERGED;
+    return false;
+  }
+  if (ns_stop == NS_STOP_PRECISION) {
+    c.refine_stop = NS_STOP_NONE;
     return false;
   }
   double last[4] = {0, 0, 0, 0};
@@ -401,60 +575,77 @@ __device__ bool wg_solve(const BatchArgs& P, const BatchDesc& d, const SlotMats&
   return c.refine_stop == NS_STOP_RESID_TOL;
 }
 
-template <int NW>
+// Persistent solver: each workgroup pulls systems from a work counter (the
+// host sorted them largest first) and solves each one completely.  The
+// float32 pass (T = float) queues the systems it cannot bring to the
+// tolerance in P.retry when escalation is on; the float64 pass (T = double)
+// then re-solves the queued systems (or, in float64-only mode, all systems).
+// The two precisions are separate kernels so that each gets the register
+// budget of its own solve.
+template <typename T, int NW>
 __global__ void __launch_bounds__(NW * 64) batch_kernel(BatchArgs P) {
+  constexpr bool dbl = sizeof(T) == 8;
   __shared__ double red[NW];
   __shared__ double hist[NS_HIST_F];
   __shared__ int s_idx;
+  __shared__ __attribute__((aligned(16))) char stage[StageBytes<NW>::value];
   char* slot = P.slots + (int64_t)blockIdx.x * P.slot_bytes;
   const int64_t nn = (int64_t)P.ldw * P.ldw;
-  SlotMats s32, s64;
+  SlotMats sm;
   {
     float* f = reinterpret_cast<float*>(slot);
-    s32.A32 = f;
-    s32.G[0] = f + nn;
-    s32.G[1] = f + 2 * nn;
-    s32.F = f + 3 * nn;
-    s32.P[0] = f + 4 * nn;
-    s32.P[1] = f + 5 * nn;
-    s32.C[0] = f + 6 * nn;
-    s32.C[1] = f + 7 * nn;
     double* d = reinterpret_cast<double*>(f + 8 * nn);
-    s64.A32 = nullptr;
-    s64.G[0] = d;
-    s64.G[1] = d + nn;
-    s64.F = d + 2 * nn;
-    s64.P[0] = d + 3 * nn;
-    s64.P[1] = d + 4 * nn;
-    s64.C[0] = d + 5 * nn;
-    s64.C[1] = d + 6 * nn;
-    double* r = d + 7 * nn;
-    s32.r = r;
-    s64.r = r;
+    if (!dbl) {
+      sm.A32 = f;
+      sm.G[0] = f + nn;
+      sm.G[1] = f + 2 * nn;
+      sm.F = f + 3 * nn;
+      sm.P[0] = f + 4 * nn;
+      sm.P[1] = f + 5 * nn;
+      sm.C[0] = f + 6 * nn;
+      sm.C[1] = f + 7 * nn;
+    } else {
+      sm.A32 = nullptr;
+      sm.G[0] = d;
+      sm.G[1] = d + nn;
+      sm.F = d + 2 * nn;
+      sm.P[0] = d + 3 * nn;
+      sm.P[1] = d + 4 * nn;
+      sm.C[0] = d + 5 * nn;
+      sm.C[1] = d + 6 * nn;
+    }
+    sm.r = d + 7 * nn;
+    sm.lds = stage;
   }
+  // Work list: all systems in P.order, or (float64 after float32) the queue.
+  const bool from_queue = dbl && !P.fp64_only;
+  int* counter = P.counter + (from_queue ? 1 : 0);
+  const int total = from_queue ? P.counter[2] : P.count;
   for (;;) {
-    if (threadIdx.x == 0) s_idx = atomicAdd(P.counter, 1);
+    if (threadIdx.x == 0) s_idx = atomicAdd(counter, 1);
     __syncthreads();
     const int q = s_idx;
     __syncthreads();
-    if (q >= P.count) break;
-    const int sid = P.order[q];
+    if (q >= total) break;
+    const int sid = from_queue ? P.retry[q] : P.order[q];
     const BatchDesc d = P.desc[sid];
+    const int64_t t_begin = wall_clock64();
     Ctl c;
-    bool ok = false;
-    int64_t mmm32 = 0;
-    if (!P.fp64_only) {
-      ok = wg_solve<float, NW>(P, d, s32, red, hist, c);
-      mmm32 = c.mmm;
-    }
-    if (P.fp64_only || (!ok && P.escalate)) {
-      __syncthreads();
-      ok = wg_solve<double, NW>(P, d, s64, red, hist, c);
-      c.mmm += mmm32;
-    }
+    const bool ok = wg_solve<T, NW>(P, d, sm, red, hist, c);
     __syncthreads();  // hist complete
     if (threadIdx.x == 0) {
       BatchResult* R = &P.res[sid];
+      const int slot_t = dbl ? 2 : 0;
+      R->clock[slot_t] = t_begin;
+      R->clock[slot_t + 1] = wall_clock64();
+      R->wg[dbl ? 1 : 0] = blockIdx.x;
+      if (!from_queue) {   // first attempt of this system: clear the other one
+        R->clock[2 - slot_t] = 0;
+        R->clock[3 - slot_t] = 0;
+        R->wg[dbl ? 0 : 1] = -1;
+      }
+      if (from_queue) c.mmm += R->mmm;   // the float32 attempt's products
+      if (!dbl && !ok && P.escalate) P.retry[atomicAdd(P.counter + 2, 1)] = sid;
       R->status = ok ? NS_OK
                      : ((c.ns_stop == NS_STOP_DIVERGED || c.refine_stop == NS_STOP_DIVERGED)
                             ? NS_EDIVERGED
@@ -483,14 +674,29 @@ size_t batch_slot_bytes(int ldw) {
   return (b + 255) / 256 * 256;
 }
 
-int launch_batch(const BatchArgs& a, int grid, int waves, hipStream_t st) {
+template <typename T>
+int launch_pass(const BatchArgs& a, int grid, int waves, hipStream_t st) {
   switch (waves) {
-    case 1: hipLaunchKernelGGL(batch_kernel<1>, dim3(grid), dim3(64), 0, st, a); break;
-    case 2: hipLaunchKernelGGL(batch_kernel<2>, dim3(grid), dim3(128), 0, st, a); break;
-    case 4: hipLaunchKernelGGL(batch_kernel<4>, dim3(grid), dim3(256), 0, st, a); break;
+    case 1: hipLaunchKernelGGL((batch_kernel<T, 1>), dim3(grid), dim3(64), 0, st, a); break;
+    case 2: hipLaunchKernelGGL((batch_kernel<T, 2>), dim3(grid), dim3(128), 0, st, a); break;
+    case 4: hipLaunchKernelGGL((batch_kernel<T, 4>), dim3(grid), dim3(256), 0, st, a); break;
+    case 8: hipLaunchKernelGGL((batch_kernel<T, 8>), dim3(grid), dim3(512), 0, st, a); break;
     default: return -1;
   }
   return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+// float32 pass (then the float64 pass over its queue when escalating), or the
+// float64 pass alone.  The float64 pass after float32 solves the few systems
+// float32 could not, so it runs wider workgroups (waves64), one per CU.
+int launch_batch(const BatchArgs& a, int grid, int waves, int grid64, int waves64,
+                 hipStream_t st) {
+  if (!a.fp64_only) {
+    if (launch_pass<float>(a, grid, waves, st)) return -1;
+    if (!a.escalate) return 0;
+    return launch_pass<double>(a, grid64, waves64, st);
+  }
+  return launch_pass<double>(a, grid, waves, st);
 }
 
 }  // namespace nsr
@@ -516,8 +722,9 @@ size_t batch_layout(int64_t max_n, int max_count, int slots) {
   size_t b = 0;
   b += balign((size_t)max_count * sizeof(BatchDesc));
   b += balign((size_t)max_count * sizeof(BatchResult));
-  b += balign((size_t)max_count * sizeof(int32_t));
-  b += balign(sizeof(int32_t));
+  b += balign((size_t)max_count * sizeof(int32_t));   // order
+  b += balign((size_t)max_count * sizeof(int32_t));   // float64 queue
+  b += balign(3 * sizeof(int32_t));                   // counters
   b += (size_t)slots * batch_slot_bytes(ldw_for(max_n));
   return b;
 }
@@ -534,16 +741,20 @@ struct ns_batch {
   int precision = NS_PREC_FP32;
   int waves = 4;
   int groups = 0;  // launch size (<= slots); 0: all slots
+  int cus = 256;   // compute units of the device
   BatchDesc* d_desc = nullptr;
   BatchResult* d_res = nullptr;
   int32_t* d_order = nullptr;
-  int32_t* d_counter = nullptr;
+  int32_t* d_counter = nullptr;   // 3 counters (see BatchArgs)
+  int32_t* d_retry = nullptr;
   char* d_slots = nullptr;
   hipEvent_t done = nullptr;
   uint64_t next_ticket = 0;
   uint64_t inflight = 0;
   int inflight_count = 0;
   bool busy = false;
+  uint64_t last_polled = 0;   // ticket whose results h_res holds
+  bool have_results = false;
   std::vector<BatchDesc> h_desc;
   std::vector<int32_t> h_order;
   std::vector<BatchResult> h_res;
@@ -563,7 +774,9 @@ int batch_enqueue(ns_batch* B, int count, const int64_t* n, const double* const*
     return bfail(NS_EINVAL, "order must be 2^s >= 2");
   if (o->k_max < 1 || o->k_max > NS_HIST_F - 1) return bfail(NS_EINVAL, "k_max must be in 1..64");
   if (o->refine_max < 0) return bfail(NS_EINVAL, "refine_max < 0");
-  if (o->scale != NS_SCALE_FROBENIUS) return bfail(NS_EINVAL, "batched solves scale by ||A||_F");
+  if (o->scale != NS_SCALE_FROBENIUS && o->scale != NS_SCALE_INF_HALF)
+    return bfail(NS_EINVAL, "unknown scale");
+  if (o->scale == NS_SCALE_INF_HALF && !(o->eps >= 0.0)) return bfail(NS_EINVAL, "eps < 0");
   if (o->theta0_mode != 0) return bfail(NS_EINVAL, "batched solves start from theta_0 = b/alpha");
   if (count > 0 && (!n || !A || !lda || !b || !theta)) return bfail(NS_EINVAL, "null array");
   B->h_desc.resize(count);
@@ -587,13 +800,14 @@ int batch_enqueue(ns_batch* B, int count, const int64_t* n, const double* const*
                        hipMemcpyHostToDevice, B->stream) != hipSuccess)
       return bfail(NS_EHIP, "descriptor upload failed");
   }
-  if (hipMemsetAsync(B->d_counter, 0, sizeof(int32_t), B->stream) != hipSuccess)
+  if (hipMemsetAsync(B->d_counter, 0, 3 * sizeof(int32_t), B->stream) != hipSuccess)
     return bfail(NS_EHIP, "counter reset failed");
   BatchArgs a{};
   a.desc = B->d_desc;
   a.res = B->d_res;
   a.order = B->d_order;
   a.counter = B->d_counter;
+  a.retry = B->d_retry;
   a.slots = B->d_slots;
   a.slot_bytes = (int64_t)batch_slot_bytes(B->ldw);
   a.count = count;
@@ -604,12 +818,16 @@ int batch_enqueue(ns_batch* B, int count, const int64_t* n, const double* const*
   a.floor_detect = o->floor_detect;
   a.escalate = (B->precision == NS_PREC_FP32) ? 1 : 0;
   a.fp64_only = (B->precision == NS_PREC_FP64) ? 1 : 0;
+  a.scale = o->scale;
+  a.eps = o->eps;
   a.f_tol = o->f_tol;
   a.resid_tol = o->resid_tol;
   int grid = B->groups > 0 ? B->groups : B->slots;
   if (grid > B->slots) grid = B->slots;
   if (grid > count) grid = count;
-  if (grid > 0 && launch_batch(a, grid, B->waves, B->stream) != 0)
+  int grid64 = B->cus < B->slots ? B->cus : B->slots;
+  if (grid64 > count) grid64 = count;
+  if (grid > 0 && launch_batch(a, grid, B->waves, grid64, 8, B->stream) != 0)
     return bfail(NS_EHIP, "batch kernel launch failed");
   return NS_OK;
 }
@@ -644,6 +862,12 @@ int ns_batch_create(int device, void* hip_stream, int64_t max_n, int max_count, 
   B->slots = slots;
   B->ldw = ldw_for(max_n);
   B->precision = precision;
+  {
+    int v = 0;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess &&
+        v > 0)
+      B->cus = v;
+  }
   char* p = reinterpret_cast<char*>(workspace);
   B->d_desc = reinterpret_cast<BatchDesc*>(p);
   p += balign((size_t)max_count * sizeof(BatchDesc));
@@ -651,8 +875,10 @@ int ns_batch_create(int device, void* hip_stream, int64_t max_n, int max_count, 
   p += balign((size_t)max_count * sizeof(BatchResult));
   B->d_order = reinterpret_cast<int32_t*>(p);
   p += balign((size_t)max_count * sizeof(int32_t));
+  B->d_retry = reinterpret_cast<int32_t*>(p);
+  p += balign((size_t)max_count * sizeof(int32_t));
   B->d_counter = reinterpret_cast<int32_t*>(p);
-  p += balign(sizeof(int32_t));
+  p += balign(3 * sizeof(int32_t));
   B->d_slots = p;
   if (hipEventCreate(&B->done) != hipSuccess) {
     delete B;
@@ -664,8 +890,9 @@ int ns_batch_create(int device, void* hip_stream, int64_t max_n, int max_count, 
 
 int ns_batch_set_launch(ns_batch* B, int waves_per_group, int groups) {
   if (!B) return bfail(NS_EINVAL, "null batch");
-  if (waves_per_group != 1 && waves_per_group != 2 && waves_per_group != 4)
-    return bfail(NS_EINVAL, "waves_per_group must be 1, 2 or 4");
+  if (waves_per_group != 1 && waves_per_group != 2 && waves_per_group != 4 &&
+      waves_per_group != 8)
+    return bfail(NS_EINVAL, "waves_per_group must be 1, 2, 4 or 8");
   if (groups < 0 || groups > B->slots) return bfail(NS_EINVAL, "groups must be in 0..slots");
   B->waves = waves_per_group;
   B->groups = groups;
@@ -686,6 +913,34 @@ int ns_batch_submit(ns_batch* B, int count, const int64_t* n, const double* cons
   return NS_OK;
 }
 
+int ns_batch_timeline(ns_batch* B, uint64_t ticket, double* times_us, int32_t* workgroup) {
+  if (!B) return bfail(NS_EINVAL, "null batch");
+  if (!B->have_results || ticket != B->last_polled)
+    return bfail(NS_EINVAL, "timeline of a ticket that was not the last one polled");
+  if (!times_us) return bfail(NS_EINVAL, "null times_us");
+  int khz = 0;
+  if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, B->device) != hipSuccess ||
+      khz <= 0)
+    return bfail(NS_EHIP, "wall clock rate unavailable");
+  const double us_per_tick = 1e3 / (double)khz;
+  int64_t t0 = INT64_MAX;
+  for (const BatchResult& r : B->h_res)
+    for (int j = 0; j < 4; j += 2)
+      if (r.clock[j] != 0 && r.clock[j] < t0) t0 = r.clock[j];
+  for (size_t i = 0; i < B->h_res.size(); ++i) {
+    const BatchResult& r = B->h_res[i];
+    for (int j = 0; j < 4; ++j) {
+      const bool ran = r.clock[j & ~1] != 0;
+      times_us[4 * i + j] = ran ? (double)(r.clock[j] - t0) * us_per_tick : NAN;
+    }
+    if (workgroup) {
+      workgroup[2 * i] = r.wg[0];
+      workgroup[2 * i + 1] = r.wg[1];
+    }
+  }
+  return NS_OK;
+}
+
 int ns_batch_poll(ns_batch* B, uint64_t ticket, int wait, ns_solve_report* reports) {
   if (!B) return bfail(NS_EINVAL, "null batch");
   if (!B->busy || ticket != B->inflight) return bfail(NS_EINVAL, "unknown ticket");
@@ -702,6 +957,8 @@ int ns_batch_poll(ns_batch* B, uint64_t ticket, int wait, ns_solve_report* repor
                            hipMemcpyDeviceToHost) != hipSuccess)
     return bfail(NS_EHIP, "result download failed");
   B->busy = false;
+  B->last_polled = ticket;
+  B->have_results = true;
   int worst = NS_OK;
   for (int i = 0; i < cnt; ++i) {
     const BatchResult& r = B->h_res[i];
@@ -738,16 +995,11 @@ int ns_batch_autotune(ns_batch* B, int count, const int64_t* n, const double* co
     return bfail(NS_EHIP, "hipEventCreate failed");
   int bw = 4, bg = 0;
   float bms = 1e30f;
-  const int waves_c[3] = {1, 2, 4};
-  int cus = 256;
-  {
-    hipDeviceProp_t prop;
-    if (hipGetDeviceProperties(&prop, B->device) == hipSuccess && prop.multiProcessorCount > 0)
-      cus = prop.multiProcessorCount;
-  }
+  const int waves_c[4] = {1, 2, 4, 8};
+  const int cus = B->cus;
   const int per_cu_c[4] = {1, 2, 4, 8};
   int rc = NS_OK;
-  for (int wi = 0; wi < 3 && rc == NS_OK; ++wi) {
+  for (int wi = 0; wi < 4 && rc == NS_OK; ++wi) {
     int prev_groups = -1;
     for (int gi = 0; gi < 4 && rc == NS_OK; ++gi) {
       int groups = per_cu_c[gi] * cus;

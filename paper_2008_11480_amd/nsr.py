@@ -27,7 +27,7 @@ SCALE_FROBENIUS, SCALE_INF_HALF = 0, 1
 FACT = {"horner": 0, "squaring": 1, "table": 2, "unified": 3, "unified_plus1": 4, "composite_double": 5}
 # ns_stop_reason
 STOP_NAMES = {0: "none", 1: "f_tol", 2: "floor", 3: "k_max", 4: "diverged", 5: "resid_tol",
-              6: "refine_max", 7: "refine_stall"}
+              6: "refine_max", 7: "refine_stall", 8: "precision"}
 
 HIST_F = 65
 HIST_R = 200
@@ -41,7 +41,7 @@ EXPORTS = (
     "ns_gemm_f64_scratch_bytes", "ns_gemm_f64_ws",
     "ns_gemm_f32", "ns_gemm_bf16_nt", "ns_gemm_lp_partials",
     "ns_batch_workspace_bytes", "ns_batch_create", "ns_batch_set_launch", "ns_batch_submit",
-    "ns_batch_poll", "ns_batch_autotune", "ns_batch_destroy",
+    "ns_batch_poll", "ns_batch_autotune", "ns_batch_timeline", "ns_batch_destroy",
     "ns_status_string", "ns_last_error", "ns_version",
 )
 
@@ -135,6 +135,7 @@ def lib() -> ctypes.CDLL:
         "ns_batch_poll": (ci, [vp, ctypes.c_uint64, ci, vp]),
         "ns_batch_autotune": (ci, [vp, ci, vp, vp, vp, vp, vp, ctypes.POINTER(SolveOpts),
                                    ctypes.POINTER(ci), ctypes.POINTER(ci), pd]),
+        "ns_batch_timeline": (ci, [vp, ctypes.c_uint64, vp, vp]),
         "ns_batch_destroy": (ci, [vp]),
         "ns_status_string": (ctypes.c_char_p, [ci]),
         "ns_last_error": (ctypes.c_char_p, []),
@@ -403,10 +404,11 @@ class Batch:
         return count, n, pa, lda, pb, pt
 
     @staticmethod
-    def _opts(order=4, k_max=64, refine_max=64, floor_detect=True, f_tol=0.0, resid_tol=1e-10):
+    def _opts(order=4, k_max=64, refine_max=64, floor_detect=True, f_tol=0.0, resid_tol=1e-10,
+              scale=SCALE_FROBENIUS, eps=0.0):
         return SolveOpts(order=order, factorization=FACT["squaring"], p=0, w=0, k_max=k_max,
                          refine_max=refine_max, floor_detect=1 if floor_detect else 0,
-                         scale=SCALE_FROBENIUS, eps=0.0, f_tol=f_tol, resid_tol=resid_tol,
+                         scale=scale, eps=eps, f_tol=f_tol, resid_tol=resid_tol,
                          theta0_mode=0)
 
     def set_launch(self, waves: int, groups: int = 0):
@@ -432,6 +434,14 @@ class Batch:
             check(st)
         self._keep = None
         return [_report_from_c(reps[i]) for i in range(self._count)]
+
+    def timeline(self, ticket: int):
+        """(times_us [count, 4], workgroup [count, 2]) of the last polled ticket:
+        begin / end of the float32 and float64 attempts (NaN: not run)."""
+        times = np.zeros((self._count, 4), dtype=np.float64)
+        wg = np.zeros((self._count, 2), dtype=np.int32)
+        check(lib().ns_batch_timeline(self._h, int(ticket), times.ctypes.data, wg.ctypes.data))
+        return times, wg
 
     def autotune(self, As, bs, thetas, **opts):
         count, n, pa, lda, pb, pt = self._arrays(As, bs, thetas)

@@ -32,7 +32,7 @@ def upload(torch, systems):
     return As, bs, ths
 
 
-def check_against_oracle(systems, ths, reps, order, resid_tol, sample=None):
+def check_against_oracle(systems, ths, reps, order, resid_tol, sample=None, eps=None):
     idx = range(len(systems)) if sample is None else sample
     for i in idx:
         s, rep = systems[i], reps[i]
@@ -40,13 +40,15 @@ def check_against_oracle(systems, ths, reps, order, resid_tol, sample=None):
         lam = np.linalg.eigvalsh(s.A)
         kappa = lam.max() / lam.min()
         rel = np.linalg.norm(s.b - s.A @ th) / np.linalg.norm(s.b)
-        alpha = np.sqrt(np.sum(s.A ** 2))
+        alpha = (oracle.alpha_frobenius(s.A) if eps is None else oracle.alpha_inf_half(s.A, eps))
         assert rep.alpha == pytest.approx(alpha, rel=1e-13)
         f0 = np.linalg.norm(np.eye(s.n) - s.A / alpha)
         assert rep.fnorm_hist[0] == pytest.approx(f0, rel=1e-5 if rep.precision == 1 else 1e-12)
         if rep.status == nsr.NS_OK:
             assert rel <= resid_tol * 1.01, (i, rel)
-            orc = oracle.solve(s.A, s.b, oracle.SolveOptions(order=order, resid_tol=resid_tol * 1e-3))
+            orc = oracle.solve(s.A, s.b, oracle.SolveOptions(
+                order=order, resid_tol=resid_tol * 1e-3,
+                scale="frobenius" if eps is None else "inf_half", eps=eps or 0.0))
             fwd = np.linalg.norm(th - orc.theta) / np.linalg.norm(orc.theta)
             assert fwd <= max(50 * kappa * U64, 10 * resid_tol * kappa), (i, fwd, kappa)
         else:
@@ -67,6 +69,54 @@ def test_batch_uneven_sizes_matches_oracle(torch):
     reps = B.poll(t, wait=True)
     assert len(reps) == len(systems)
     check_against_oracle(systems, ths, reps, 4, 1e-10)
+
+
+def test_batch_inf_half_scaling(torch):
+    """alpha = ||A||_inf / 2 + eps (Section 2) in the batched kernel: alpha,
+    ||F_0|| and every solve against the oracle with the same scaling, and on
+    harmonic Gram systems no more Newton-Schulz steps than with ||A||_F."""
+    rng = np.random.default_rng(12)
+    systems = [inputs.harmonic_gram(int(m), seed=int(rng.integers(1 << 30)))
+               for m in rng.integers(8, 65, size=20)]
+    systems += [inputs.spd_qlq(n, k, seed=60 + n) for n, k in ((31, 1e2), (130, 1e4), (1, 1.0))]
+    As, bs, ths = upload(torch, systems)
+    B = nsr.Batch(max_n=256, max_count=64, slots=32)
+    eps = 1e-9
+    t = B.submit(As, bs, ths, order=4, resid_tol=1e-10, scale=nsr.SCALE_INF_HALF, eps=eps)
+    reps = B.poll(t, wait=True)
+    check_against_oracle(systems, ths, reps, 4, 1e-10, eps=eps)
+    ths2 = [torch.zeros_like(b) for b in bs]
+    t = B.submit(As, bs, ths2, order=4, resid_tol=1e-10)
+    reps_f = B.poll(t, wait=True)
+    harm = range(20)
+    assert sum(reps[i].ns_steps for i in harm) <= sum(reps_f[i].ns_steps for i in harm)
+    with pytest.raises(nsr.NSError):
+        B.submit(As, bs, ths2, order=4, scale=nsr.SCALE_INF_HALF, eps=-1.0)
+
+
+def test_batch_timeline(torch):
+    """Per-system device timeline: every float32 attempt has begin <= end,
+    escalated systems (and only they) have a float64 attempt, and the float64
+    pass starts after every float32 attempt ended (separate kernels)."""
+    rng = np.random.default_rng(13)
+    systems = [inputs.harmonic_gram(int(m), seed=int(rng.integers(1 << 30)))
+               for m in rng.integers(8, 129, size=40)]
+    As, bs, ths = upload(torch, systems)
+    B = nsr.Batch(max_n=256, max_count=64, slots=16)
+    t = B.submit(As, bs, ths, order=4, resid_tol=1e-10, refine_max=100)
+    reps = B.poll(t, wait=True)
+    times, wg = B.timeline(t)
+    assert times.shape == (40, 4) and wg.shape == (40, 2)
+    assert np.nanmin(times[:, 0]) == 0.0
+    assert np.all(times[:, 1] >= times[:, 0])
+    assert np.all((wg[:, 0] >= 0) & (wg[:, 0] < 16))
+    esc = np.array([r.precision == nsr.PREC_FP64 for r in reps])
+    assert np.all(np.isnan(times[~esc, 2])) and np.all(wg[~esc, 1] == -1)
+    if esc.any():
+        assert np.all(times[esc, 3] >= times[esc, 2])
+        assert np.min(times[esc, 2]) >= np.max(times[:, 1])
+    with pytest.raises(nsr.NSError):
+        B.timeline(t + 1)
 
 
 def test_batch_fp64_mode_and_order8(torch):
@@ -146,7 +196,7 @@ def test_batch_autotune(torch):
     As, bs, ths = upload(torch, systems)
     B = nsr.Batch(max_n=128, max_count=64, slots=64)
     waves, groups, ms = B.autotune(As, bs, ths, order=4, resid_tol=1e-10)
-    assert waves in (1, 2, 4) and 1 <= groups <= 64 and ms > 0
+    assert waves in (1, 2, 4, 8) and 1 <= groups <= 64 and ms > 0
     for t in ths:
         t.zero_()
     reps = B.poll(B.submit(As, bs, ths, order=4, resid_tol=1e-10), wait=True)
