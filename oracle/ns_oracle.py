@@ -32,6 +32,7 @@ import numpy as np
 __all__ = [
     "MMCounter", "alpha_frobenius", "alpha_inf_half", "splitting_condition",
     "residual", "z_horner", "z_unified", "z_unified_plus1", "z_squaring",
+    "diag_preconditioner", "initial_series",
     "z_table", "TABLE_ORDERS", "z_form", "form_mmm", "ns_step",
     "dns_init", "dns_step", "richardson_update", "accelerator_apply", "SolveOptions",
     "SolveReport", "riem6_gamma",
@@ -77,6 +78,28 @@ def alpha_frobenius(a: np.ndarray) -> float:
 def alpha_inf_half(a: np.ndarray, eps: float) -> float:
     """``alpha = ||A||_inf / 2 + eps`` (maximum row sum; Section 2)."""
     return float(np.max(np.sum(np.abs(a), axis=1))) / 2.0 + float(eps)
+
+
+def diag_preconditioner(a: np.ndarray) -> np.ndarray:
+    """``S = diag(a_11, ..., a_NN)`` of an SDD positive definite ``A``
+    (Section 2); returned as the vector of diagonal entries."""
+    d = np.diag(np.asarray(a, dtype=np.float64)).copy()
+    if not np.all(d > 0.0) or not np.all(np.isfinite(d)):
+        raise ValueError("the diagonal preconditioner needs a positive diagonal")
+    return d
+
+
+def initial_series(a: np.ndarray, s_inv: np.ndarray, h: int, p: int, w: int,
+                   ctr=None) -> np.ndarray:
+    """Initial series of eq. (g01)-(g02), right orientation: with
+    ``Y = I - A S^-1``, ``G_0 = S^-1 sum_{j<w} Y^{(p+1) j} sum_{d<=p} Y^d``
+    ``= S^-1 sum_{j<h} Y^j`` for ``h = w (p + 1)``, so that
+    ``F_0 = I - A G_0 = Y^h`` (eq. g03)."""
+    if h != w * (p + 1):
+        raise ValueError("initial series needs h = w (p + 1)")
+    if h == 1:
+        return s_inv.copy()
+    return z_unified(a, s_inv, p, w, ctr)
 
 
 def splitting_condition(a: np.ndarray, alpha: float) -> bool:
@@ -386,8 +409,11 @@ class SolveOptions:
     floor_detect: bool = True
     refine_max: int = 64
     resid_tol: float = 1e-12
-    scale: str = "frobenius"       # or "inf_half"
+    scale: str = "frobenius"       # or "inf_half", or "diag" (S = diag(A), SDD case)
     eps: float = 0.0               # for "inf_half"
+    init_order: int = 1            # h of the initial series, eq. (g01)
+    init_p: int | None = None      # its factorization, h = init_w (init_p + 1)
+    init_w: int | None = None
     theta0: str = "g0b"            # "g0b": theta_0 = G_0 b;  "zero";  "l0b": L_0 b
     accel_q: int = 0               # >0: Richardson with the accelerator of eq. (ttk1),
                                    # Neumann order q (composite form only)
@@ -428,14 +454,25 @@ def solve(a, b, opts: SolveOptions = SolveOptions()) -> SolveReport:
     eye = _eye_like(a)
     if opts.scale == "frobenius":
         alpha = alpha_frobenius(a)
+        g0 = eye / alpha
     elif opts.scale == "inf_half":
         alpha = alpha_inf_half(a, opts.eps)
+        g0 = eye / alpha
+    elif opts.scale == "diag":
+        sd = diag_preconditioner(a)
+        alpha = float(np.max(sd))         # reported only
+        g0 = np.diag(1.0 / sd)
     else:
         raise ValueError(opts.scale)
     bnorm = float(np.linalg.norm(b))
     if bnorm == 0.0:
         bnorm = 1.0
-    g0 = eye / alpha
+    if opts.init_order > 1:
+        if opts.composite:
+            raise ValueError("the initial series is used with the classical forms")
+        ip = opts.init_p if opts.init_p is not None else opts.init_order - 1
+        iw = opts.init_w if opts.init_w is not None else 1
+        g0 = initial_series(a, g0, opts.init_order, ip, iw, ctr)
     theta = g0 @ b if opts.theta0 == "g0b" else np.zeros_like(b)
     if opts.accel_q and not opts.composite:
         raise ValueError("the accelerator of eq. (ttk1) needs the composite form")

@@ -153,6 +153,29 @@ def spd_diag(lam: np.ndarray, seed: int) -> SPDSystem:
                      Q=np.eye(n), seed=seed, kappa=float(lam.max() / lam.min()))
 
 
+def spd_jacobi(n: int, seed: int, decades: float = 3.0, offdiag: float = 0.9) -> SPDSystem:
+    """``A = D^(1/2) (I + E) D^(1/2)``: ``E`` symmetric with zero diagonal and
+    every row sum of ``|E|`` equal to ``offdiag < 1`` (so ``I + E`` is strictly
+    diagonally dominant and ``2 S - A`` is positive definite for
+    ``S = diag(A) = D``, Section 2), ``D`` log-uniform over ``decades``
+    decades.  The diagonal preconditioner sees the spectrum of ``I + E``; the
+    scalar one sees that of ``A``.  ``b ~ N(0, 1)``."""
+    rng = np.random.default_rng(seed)
+    e = rng.standard_normal((n, n))
+    e = 0.5 * (e + e.T)
+    np.fill_diagonal(e, 0.0)
+    if n > 1:
+        rs = np.abs(e).sum(axis=1)
+        e = e / np.sqrt(np.outer(rs, rs))        # symmetric scaling keeps E = E^T
+        e *= offdiag / np.abs(e).sum(axis=1).max()
+    d = 10.0 ** rng.uniform(0.0, decades, size=n)
+    sq = np.sqrt(d)
+    a = (np.eye(n) + e) * np.outer(sq, sq)
+    a = 0.5 * (a + a.T)
+    b = rng.standard_normal(n)
+    return SPDSystem(A=np.ascontiguousarray(a), b=b, seed=seed)
+
+
 def harmonic_gram(m: int, seed: int, ridge: float = 1e-6, noise_var: float = 0.01,
                   samples_per_dim: int = 4) -> SPDSystem:
     """Gram matrix of a harmonic regressor with ``m`` frequencies (``N = 2m``).

@@ -387,3 +387,78 @@ def test_accelerated_richardson_eigen_closed_form():
     ex = n + oracle.riem6_gamma(K, n)
     ref = theta_star - s.Q @ ((mu ** ex) * (s.Q.T @ theta_star))
     assert np.linalg.norm(rep.theta - ref) <= 1e-12 * np.linalg.norm(theta_star)
+
+
+# --------------------------------------------------------------------------
+# Section 2 diagonal preconditioner and the initial series of eq. (g01)-(g03)
+# --------------------------------------------------------------------------
+
+def test_diag_preconditioner_on_diagonal_matrix_is_exact():
+    """For a diagonal A the diagonal preconditioner is A^-1: F_0 = 0 up to one
+    rounding per entry and theta_0 = b / a_ii."""
+    rng = np.random.default_rng(3)
+    d = 10.0 ** rng.uniform(-2, 3, size=40)
+    a = np.diag(d)
+    b = rng.standard_normal(40)
+    rep = oracle.solve(a, b, oracle.SolveOptions(order=4, scale="diag", resid_tol=1e-15))
+    assert rep.fnorm_hist[0] <= 40 * np.finfo(float).eps
+    assert np.allclose(rep.theta, b / d, rtol=4 * np.finfo(float).eps, atol=0)
+
+
+@pytest.mark.parametrize("order", [2, 4, 8])
+def test_diag_preconditioner_closed_form(order):
+    """G_0 = S^-1 with S = diag(A): F_0 = I - A S^-1 is not symmetric, yet
+    F_{k+1} = F_k^n holds as matrices (right orientation), and with
+    A~ = S^-1/2 A S^-1/2 = Q diag(lam) Q^T the iterates are
+    F_k = S^1/2 Q diag((1 - lam)^(n^k)) Q^T S^-1/2 (eq. fk1 after the
+    similarity)."""
+    sysm = inputs.spd_jacobi(60, seed=order)
+    a = sysm.A
+    s = oracle.diag_preconditioner(a)
+    sh = np.sqrt(s)
+    lam, q = np.linalg.eigh(a / np.outer(sh, sh))
+    assert np.all(np.abs(1.0 - lam) < 1.0)              # 2S - A > 0
+    g = np.diag(1.0 / s)
+    f_prev = oracle.residual(a, g)
+    for k in range(1, 4):
+        g = oracle.ns_step(a, g, order, "squaring")
+        f = oracle.residual(a, g)
+        closed = (sh[:, None] * (q * (1.0 - lam) ** (order ** k)) @ q.T) / sh[None, :]
+        scale = max(1.0, np.linalg.norm(closed))
+        assert np.linalg.norm(f - closed) <= 1e-12 * scale * 60, k
+        pw = np.linalg.matrix_power(f_prev, order)
+        assert np.linalg.norm(f - pw) <= 1e-12 * max(1.0, np.linalg.norm(pw)) * 60, k
+        f_prev = f
+
+
+@pytest.mark.parametrize("h,p,w", [(4, 1, 2), (6, 2, 2), (3, 2, 1), (4, 0, 4), (9, 2, 3)])
+def test_initial_series_power(h, p, w):
+    """Eq. (g02)-(g03): G_0 = S^-1 sum_{j<h} Y^j with Y = I - A S^-1, so
+    F_0 = Y^h exactly; the factorized evaluation (p, w) of eq. (g01) equals
+    the plain sum."""
+    sysm = inputs.spd_qlq(50, 1e2, seed=h + p)
+    a = sysm.A
+    alpha = oracle.alpha_frobenius(a)
+    s_inv = np.eye(50) / alpha
+    y = np.eye(50) - a / alpha
+    g0 = oracle.initial_series(a, s_inv, h, p, w)
+    plain = s_inv @ sum(np.linalg.matrix_power(y, j) for j in range(h))
+    assert np.linalg.norm(g0 - plain) <= 1e-13 * np.linalg.norm(plain)
+    f0 = oracle.residual(a, g0)
+    yh = np.linalg.matrix_power(y, h)
+    assert np.linalg.norm(f0 - yh) <= 1e-13 * max(1.0, np.linalg.norm(yh)) * 50
+
+
+@pytest.mark.parametrize("h,order", [(2, 4), (3, 4), (4, 8)])
+def test_initial_series_solve_exponent(h, order):
+    """With the initial series of order h the iterates follow
+    ||F_k||_F = sqrt(sum mu_i^(2 h n^k)) (eq. f10 and the steps after it)."""
+    sysm = inputs.spd_qlq(64, 1e3, seed=11 + h)
+    rep = oracle.solve(sysm.A, sysm.b, oracle.SolveOptions(order=order, init_order=h,
+                                                           resid_tol=1e-13))
+    mu = 1.0 - sysm.lam / rep.alpha
+    for k, fk in enumerate(rep.fnorm_hist):
+        ref = math.sqrt(float(np.sum(mu ** (2 * h * order ** k))))
+        if ref > 1e-8:
+            assert fk == pytest.approx(ref, rel=1e-9), k
+    assert rep.rel_resid <= 1e-13
