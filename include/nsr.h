@@ -70,7 +70,11 @@ typedef enum {
 typedef enum {
   NS_SCALE_FROBENIUS = 0, /* alpha = ||A||_F  (lambda_max <= ||A||_F, so the
                              splitting condition 2S - A > 0 holds)           */
-  NS_SCALE_INF_HALF = 1   /* alpha = ||A||_inf / 2 + eps (Section 2)         */
+  NS_SCALE_INF_HALF = 1,  /* alpha = ||A||_inf / 2 + eps (Section 2)         */
+  NS_SCALE_DIAG = 2       /* S = diag(A) (Section 2, SDD matrices; converges
+                             when 2S - A is positive definite).  F = I - A S^-1
+                             is then not symmetric: every product runs in full.
+                             Float64 and float32 modes.                       */
 } ns_scale;
 
 typedef enum {
@@ -130,11 +134,14 @@ int ns_destroy(ns_solver* s);
  * (NULL, lda < n), NS_EHIP. */
 int ns_bind(ns_solver* s, const double* A, int64_t lda);
 
-/* Section 2 (scalar preconditioner): compute alpha (NS_SCALE_FROBENIUS:
- * ||A||_F; NS_SCALE_INF_HALF: max row sum / 2 + eps), set G_0 = I / alpha
+/* Section 2 (preconditioner S): compute alpha (NS_SCALE_FROBENIUS: ||A||_F;
+ * NS_SCALE_INF_HALF: max row sum / 2 + eps) and S = alpha I, or
+ * (NS_SCALE_DIAG) S = diag(A), reporting alpha = max_i A_ii; set G_0 = S^-1
  * (kept implicit, never materialised) and F_0 = I - A G_0, and return alpha
  * and ||F_0||_F (either out pointer may be NULL).  Errors: NS_ESTATE (no A
- * bound), NS_ENOTSPD (alpha not finite or <= 0). */
+ * bound), NS_ENOTSPD (alpha, or a diagonal entry, not finite or <= 0),
+ * NS_EINVAL (unknown scale; NS_SCALE_DIAG in the mixed mode, whose bf16
+ * products assume symmetric powers of F). */
 int ns_init_scale(ns_solver* s, int scale, double eps, double* alpha_out,
                   double* fnorm0_out);
 
@@ -188,6 +195,12 @@ typedef struct {
                          Gamma_k^n {sum_{j<q} F_k^j} G_k (mirrored), applied
                          as q + 2 mat-vecs, with theta_0 = L_0 b; the error
                          contracts by F_k^q Gamma_k^n per step (eq. riem1) */
+  int init_order;     /* h of the initial series, eqs. (g01)-(g03): G_0 =
+                         S^-1 sum_{j<h} (I - A S^-1)^j, so F_0 = (I - A S^-1)^h
+                         and F_k = F_0^(n^k).  0 or 1: G_0 = S^-1.  Classical
+                         and table forms only.                               */
+  int init_p, init_w; /* its factorization, h = init_w (init_p + 1); both 0:
+                         init_p = h - 1, init_w = 1                           */
 } ns_solve_opts;
 
 #define NS_HIST_F 65

@@ -93,8 +93,9 @@ reduce_kernel(const double* __restrict__ partial, int64_t count, double* __restr
 template <typename T>
 __global__ void __launch_bounds__(kThreads)
 init_resid_kernel(const double* __restrict__ A, int64_t lda, int64_t n,
-                  const double* __restrict__ alpha, T* __restrict__ F, int64_t ldf,
-                  uint16_t* __restrict__ Fb, double* __restrict__ partial) {
+                  const double* __restrict__ alpha, const double* __restrict__ sdiag,
+                  T* __restrict__ F, int64_t ldf, uint16_t* __restrict__ Fb,
+                  double* __restrict__ partial) {
   __shared__ double red[4];
   const double inv = 1.0 / alpha[0];
   const int64_t r0 = (int64_t)blockIdx.x * kRowsPerBlock;
@@ -103,7 +104,7 @@ init_resid_kernel(const double* __restrict__ A, int64_t lda, int64_t n,
     const int64_t row = r0 + rr;
     if (row >= n) break;
     for (int64_t c = threadIdx.x; c < n; c += kThreads) {
-      double v = -A[row * lda + c] * inv;
+      double v = sdiag ? -A[row * lda + c] / sdiag[c] : -A[row * lda + c] * inv;
       if (c == row) v += 1.0;
       const T t = (T)v;
       F[row * ldf + c] = t;
@@ -119,11 +120,12 @@ init_resid_kernel(const double* __restrict__ A, int64_t lda, int64_t n,
 template <typename T>
 __global__ void __launch_bounds__(kThreads)
 scaled_identity_plus_kernel(const T* __restrict__ C, int64_t ldc, int64_t n,
-                            const double* __restrict__ alpha, T* __restrict__ G, int64_t ldg) {
-  const double inv = 1.0 / alpha[0];
+                            const double* __restrict__ alpha, const double* __restrict__ sdiag,
+                            T* __restrict__ G, int64_t ldg) {
   const int64_t row = blockIdx.y;
   const int64_t c = (int64_t)blockIdx.x * kThreads + threadIdx.x;
   if (row >= n || c >= n) return;
+  const double inv = 1.0 / (sdiag ? sdiag[row] : alpha[0]);
   double v = C ? (double)C[row * ldc + c] : 0.0;
   if (c == row) v += 1.0;
   G[row * ldg + c] = (T)(v * inv);
@@ -141,6 +143,17 @@ add_kernel(const T* X, const T* Y, T* D, uint16_t* Db, int64_t ld, int64_t n) {
   const T v = X[i] + Y[i];
   D[i] = v;
   if (Db) Db[i] = __builtin_bit_cast(uint16_t, (__bf16)(float)v);
+}
+
+// sdiag[i] = A_ii; neg[i] = -A_ii (a max-reduction of neg gives -min A_ii).
+__global__ void __launch_bounds__(kThreads)
+diag_kernel(const double* __restrict__ A, int64_t lda, int64_t n, double* __restrict__ sdiag,
+            double* __restrict__ neg) {
+  const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (i >= n) return;
+  const double v = A[i * lda + i];
+  sdiag[i] = v;
+  neg[i] = -v;
 }
 
 // dst (float64 or float32) = (T) src, n x n.
@@ -211,10 +224,11 @@ gemv_kernel(const T* __restrict__ M, int64_t ldm, int64_t n, const double* __res
 
 __global__ void __launch_bounds__(kThreads)
 vec_scale_kernel(const double* __restrict__ b, const double* __restrict__ alpha,
-                 double* __restrict__ theta, int64_t n, int accumulate) {
+                 const double* __restrict__ sdiag, double* __restrict__ theta, int64_t n,
+                 int accumulate) {
   const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
   if (i >= n) return;
-  const double v = b[i] / alpha[0];
+  const double v = b[i] / (sdiag ? sdiag[i] : alpha[0]);
   theta[i] = accumulate ? theta[i] + v : v;
 }
 
@@ -251,29 +265,38 @@ void launch_reduce(const double* partial, int64_t count, double* out, int mode, 
 }
 
 template <typename T>
-int64_t launch_init_resid(const double* A, int64_t lda, int64_t n, const double* alpha, T* F,
-                          int64_t ldf, uint16_t* Fb, double* partial, hipStream_t st) {
+int64_t launch_init_resid(const double* A, int64_t lda, int64_t n, const double* alpha,
+                          const double* sdiag, T* F, int64_t ldf, uint16_t* Fb, double* partial,
+                          hipStream_t st) {
   const int64_t nb = sumsq_partials(n);
   hipLaunchKernelGGL(init_resid_kernel<T>, dim3((unsigned)nb), dim3(kThreads), 0, st, A, lda, n,
-                     alpha, F, ldf, Fb, partial);
+                     alpha, sdiag, F, ldf, Fb, partial);
   return nb;
 }
-template int64_t launch_init_resid<double>(const double*, int64_t, int64_t, const double*, double*,
-                                           int64_t, uint16_t*, double*, hipStream_t);
-template int64_t launch_init_resid<float>(const double*, int64_t, int64_t, const double*, float*,
-                                          int64_t, uint16_t*, double*, hipStream_t);
+template int64_t launch_init_resid<double>(const double*, int64_t, int64_t, const double*,
+                                           const double*, double*, int64_t, uint16_t*, double*,
+                                           hipStream_t);
+template int64_t launch_init_resid<float>(const double*, int64_t, int64_t, const double*,
+                                          const double*, float*, int64_t, uint16_t*, double*,
+                                          hipStream_t);
 
 template <typename T>
-void launch_scaled_identity_plus(const T* C, int64_t ldc, int64_t n, const double* alpha, T* G,
-                                 int64_t ldg, hipStream_t st) {
+void launch_scaled_identity_plus(const T* C, int64_t ldc, int64_t n, const double* alpha,
+                                 const double* sdiag, T* G, int64_t ldg, hipStream_t st) {
   dim3 grid((unsigned)((n + kThreads - 1) / kThreads), (unsigned)n);
   hipLaunchKernelGGL(scaled_identity_plus_kernel<T>, grid, dim3(kThreads), 0, st, C, ldc, n, alpha,
-                     G, ldg);
+                     sdiag, G, ldg);
 }
 template void launch_scaled_identity_plus<double>(const double*, int64_t, int64_t, const double*,
-                                                  double*, int64_t, hipStream_t);
+                                                  const double*, double*, int64_t, hipStream_t);
 template void launch_scaled_identity_plus<float>(const float*, int64_t, int64_t, const double*,
-                                                 float*, int64_t, hipStream_t);
+                                                 const double*, float*, int64_t, hipStream_t);
+
+void launch_diag(const double* A, int64_t lda, int64_t n, double* sdiag, double* neg,
+                 hipStream_t st) {
+  hipLaunchKernelGGL(diag_kernel, dim3((unsigned)((n + kThreads - 1) / kThreads)),
+                     dim3(kThreads), 0, st, A, lda, n, sdiag, neg);
+}
 
 template <typename T>
 void launch_add(const T* X, const T* Y, T* D, uint16_t* Db, int64_t ld, int64_t n, hipStream_t st) {
@@ -325,10 +348,10 @@ template void launch_gemv<double>(const double*, int64_t, int64_t, const double*
 template void launch_gemv<float>(const float*, int64_t, int64_t, const double*, const double*,
                                  double*, int, hipStream_t);
 
-void launch_vec_scale(const double* b, const double* alpha, double* theta, int64_t n,
-                      int accumulate, hipStream_t st) {
+void launch_vec_scale(const double* b, const double* alpha, const double* sdiag, double* theta,
+                      int64_t n, int accumulate, hipStream_t st) {
   hipLaunchKernelGGL(vec_scale_kernel, dim3((unsigned)((n + kThreads - 1) / kThreads)),
-                     dim3(kThreads), 0, st, b, alpha, theta, n, accumulate);
+                     dim3(kThreads), 0, st, b, alpha, sdiag, theta, n, accumulate);
 }
 
 int64_t launch_vec_sumsq(const double* v, int64_t n, double* partial, hipStream_t st) {

@@ -71,17 +71,23 @@ void launch_rowabs(const double* A, int64_t lda, int64_t n, double* rowsum, hipS
 void launch_reduce(const double* partial, int64_t count, double* out, int mode,
                    double half_plus_eps, hipStream_t st);
 
-// F = I - A / alpha (alpha read from device memory, computed in float64 and
-// stored as T; Fb: optional bf16 copy with the same leading dimension),
-// partial sums of F^2.
+// F = I - A S^-1 with S = alpha I (alpha read from device memory) or, when
+// sdiag is not null, S = diag(sdiag); computed in float64 and stored as T
+// (Fb: optional bf16 copy with the same leading dimension), partial sums of
+// F^2.
 template <typename T>
-int64_t launch_init_resid(const double* A, int64_t lda, int64_t n, const double* alpha, T* F,
-                          int64_t ldf, uint16_t* Fb, double* partial, hipStream_t st);
+int64_t launch_init_resid(const double* A, int64_t lda, int64_t n, const double* alpha,
+                          const double* sdiag, T* F, int64_t ldf, uint16_t* Fb, double* partial,
+                          hipStream_t st);
 
-// G = (I + C) / alpha; C may be null (G = I / alpha).
+// G = S^-1 (I + C) (S as above); C may be null (G = S^-1).
 template <typename T>
-void launch_scaled_identity_plus(const T* C, int64_t ldc, int64_t n, const double* alpha, T* G,
-                                 int64_t ldg, hipStream_t st);
+void launch_scaled_identity_plus(const T* C, int64_t ldc, int64_t n, const double* alpha,
+                                 const double* sdiag, T* G, int64_t ldg, hipStream_t st);
+
+// sdiag[i] = A_ii, neg[i] = -A_ii.
+void launch_diag(const double* A, int64_t lda, int64_t n, double* sdiag, double* neg,
+                 hipStream_t st);
 
 // D = X + Y for n x n matrices with leading dimension ld (D may alias X or
 // Y); Db: optional bf16 copy of D.
@@ -108,9 +114,10 @@ template <typename T>
 void launch_gemv(const T* M, int64_t ldm, int64_t n, const double* x, const double* z, double* y,
                  int accumulate, hipStream_t st);
 
-// theta = b / alpha (alpha on device); theta += r / alpha
-void launch_vec_scale(const double* b, const double* alpha, double* theta, int64_t n,
-                      int accumulate, hipStream_t st);
+// theta = S^-1 b (S = alpha I, or diag(sdiag) when sdiag is not null);
+// with accumulate theta += S^-1 b.
+void launch_vec_scale(const double* b, const double* alpha, const double* sdiag, double* theta,
+                      int64_t n, int accumulate, hipStream_t st);
 
 // Sum of squares of a vector -> partials
 int64_t launch_vec_sumsq(const double* v, int64_t n, double* partial, hipStream_t st);

@@ -88,7 +88,7 @@ size_t layout_bytes(int64_t n, int precision, int composite) {
   if (precision != NS_PREC_FP64) bytes += align_up(nn * 4, kAlign);          // float32 A
   if (precision == NS_PREC_MIXED_BF16)
     bytes += (size_t)(composite ? 6 : 5) * align_up(nn * 2, kAlign);         // bf16 copies
-  bytes += 4 * align_up((size_t)n * sizeof(double), kAlign);                 // r, t, w0, w1
+  bytes += 5 * align_up((size_t)n * sizeof(double), kAlign);                 // r, t, w0, w1, S
   bytes += align_up((size_t)partial_capacity(n) * sizeof(double), kAlign);   // partials
   bytes += align_up(16 * sizeof(double), kAlign);                            // scalars
   if (precision == NS_PREC_FP64) bytes += align_up(split_bytes(n), kAlign);  // split-K scratch
@@ -128,7 +128,9 @@ struct ns_solver {
   double* vt = nullptr;      // accelerator temporaries (eq. ttk1)
   double* vw[2] = {nullptr, nullptr};
   double* partial = nullptr;
-  double* scal = nullptr;  // [0] alpha, [1] ||F||_F, [2] ||r||_2, [3] ||b||_2
+  double* scal = nullptr;  // [0] alpha, [1] ||F||_F, [2] ||r||_2, [3] ||b||_2, [4] -min A_ii
+  double* sdiag = nullptr; // S = diag(A) (NS_SCALE_DIAG)
+  bool diag_scale = false; // G_0 = diag(A)^-1 instead of I / alpha
   double* sk = nullptr;    // split-K scratch of the float64 GEMM
   int64_t sk_cap = 0;      // doubles
 
@@ -200,7 +202,7 @@ int mm(ns_solver* s, Mat& D, const Mat* X, const Mat& Y, const Mat* E1, const Ma
     // the rounding error that does not commute with A back with a gain ~kappa
     // per step.  Errors in the powers only perturb P(F) and enter F_{k+1} as
     // O(||F|| ||[A, G]||).
-    a.sym = (s->symmetric && kind == K_POWER) ? 1 : 0;
+    a.sym = (s->symmetric && kind == K_POWER && !s->diag_scale) ? 1 : 0;
     a.sk = s->sk;
     a.sk_cap = s->sk_cap;
     np = launch_gemm_f64(a, s->stream);
@@ -228,7 +230,7 @@ int mm(ns_solver* s, Mat& D, const Mat* X, const Mat& Y, const Mat* E1, const Ma
   if (np < 0) return fail(NS_EHIP, "GEMM launch failed: %s", hipGetErrorString(hipGetLastError()));
   // algorithmic flop: 2 n^3, or n^2 (n + 1) when only one triangle is formed
   const double nn = (double)s->n;
-  const bool half = is_f64(s) && s->symmetric && kind == K_POWER;
+  const bool half = is_f64(s) && s->symmetric && kind == K_POWER && !s->diag_scale;
   const double flop = half ? nn * nn * (nn + 1.0) : 2.0 * nn * nn * nn;
   if (s->timing) {
     HIP_TRY(hipEventRecord(ee, s->stream));
@@ -247,14 +249,16 @@ int read_scalars(ns_solver* s, double* host, int first, int count) {
   return NS_OK;
 }
 
-// Dst = (I + C) / alpha (C may be null: Dst = I / alpha).
+const double* sdiag_of(const ns_solver* s) { return s->diag_scale ? s->sdiag : nullptr; }
+
+// Dst = S^-1 (I + C) (C may be null: Dst = S^-1); S = alpha I or diag(A).
 void scaled_identity(ns_solver* s, const Mat* C, Mat& Dst) {
   if (is_f64(s))
-    launch_scaled_identity_plus<double>(C ? C->d : nullptr, s->ld, s->n, s->scal + 0, Dst.d, s->ld,
-                                        s->stream);
+    launch_scaled_identity_plus<double>(C ? C->d : nullptr, s->ld, s->n, s->scal + 0, sdiag_of(s),
+                                        Dst.d, s->ld, s->stream);
   else
-    launch_scaled_identity_plus<float>(C ? C->f : nullptr, s->ld, s->n, s->scal + 0, Dst.f, s->ld,
-                                       s->stream);
+    launch_scaled_identity_plus<float>(C ? C->f : nullptr, s->ld, s->n, s->scal + 0, sdiag_of(s),
+                                       Dst.f, s->ld, s->stream);
 }
 
 // G_next = G (I + C): GEMM, or (I + C) / alpha while G is still I / alpha.
@@ -302,6 +306,12 @@ int step_classic(ns_solver* s, int order, int fact, int p, int w) {
   if (fact != NS_FACT_SQUARING) s->p0_is_f2 = false;
   Mat& Gc = s->G[s->gcur];
   Mat& Gn = s->G[s->gcur ^ 1];
+  if (s->g_implicit && s->diag_scale && fact != NS_FACT_SQUARING) {
+    // The Horner / unified chains add G_0 through the GEMM's scalar diagonal
+    // term, which cannot hold diag(A)^-1: materialise G_0 first.
+    scaled_identity(s, nullptr, Gc);
+    s->g_implicit = false;
+  }
   const bool impl = s->g_implicit;
   const double inv_alpha = 1.0 / s->alpha;
   int rc = NS_OK;
@@ -529,7 +539,7 @@ int richardson_once(ns_solver* s, const double* b, double* theta) {
   const int64_t np = launch_gemv_resid(s->A, s->lda, s->n, b, theta, s->r, s->partial, s->stream);
   launch_reduce(s->partial, np, s->scal + 2, 2, 0.0, s->stream);
   if (s->g_implicit) {
-    launch_vec_scale(s->r, s->scal + 0, theta, s->n, 1, s->stream);
+    launch_vec_scale(s->r, s->scal + 0, sdiag_of(s), theta, s->n, 1, s->stream);
   } else {
     gemv_update(s, theta);
   }
@@ -658,6 +668,7 @@ int ns_create(int device, void* hip_stream, int64_t n, int precision, void* work
   s->vt = reinterpret_cast<double*>(take(align_up((size_t)n * sizeof(double), kAlign)));
   s->vw[0] = reinterpret_cast<double*>(take(align_up((size_t)n * sizeof(double), kAlign)));
   s->vw[1] = reinterpret_cast<double*>(take(align_up((size_t)n * sizeof(double), kAlign)));
+  s->sdiag = reinterpret_cast<double*>(take(align_up((size_t)n * sizeof(double), kAlign)));
   s->partial =
       reinterpret_cast<double*>(take(align_up((size_t)partial_capacity(n) * sizeof(double), kAlign)));
   s->scal = reinterpret_cast<double*>(take(align_up(16 * sizeof(double), kAlign)));
@@ -708,12 +719,24 @@ int ns_init_scale(ns_solver* s, int scale, double eps, double* alpha_out, double
   if (int rc = check_solver(s)) return rc;
   if (!s->bound) return fail(NS_ESTATE, "ns_bind first");
   HIP_TRY(hipSetDevice(s->device));
+  s->diag_scale = false;
   if (scale == NS_SCALE_FROBENIUS) {
     const int64_t np = launch_sumsq(s->A, s->lda, s->n, s->partial, s->stream);
     launch_reduce(s->partial, np, s->scal + 0, 2, 0.0, s->stream);
   } else if (scale == NS_SCALE_INF_HALF) {
     launch_rowabs(s->A, s->lda, s->n, s->partial, s->stream);
     launch_reduce(s->partial, s->n, s->scal + 0, 3, eps, s->stream);
+  } else if (scale == NS_SCALE_DIAG) {
+    if (s->precision == NS_PREC_MIXED_BF16)
+      return fail(NS_EINVAL, "NS_SCALE_DIAG needs the float64 or float32 mode");
+    launch_diag(s->A, s->lda, s->n, s->sdiag, s->partial, s->stream);
+    launch_reduce(s->sdiag, s->n, s->scal + 0, 1, 0.0, s->stream);     // max A_ii
+    launch_reduce(s->partial, s->n, s->scal + 4, 1, 0.0, s->stream);   // -min A_ii
+    double h2[5];
+    if (int rc = read_scalars(s, h2, 0, 5)) return rc;
+    if (!(-h2[4] > 0.0) || !isfinite(h2[0]) || !isfinite(h2[4]))
+      return fail(NS_ENOTSPD, "diagonal entry %g is not a positive finite number", -h2[4]);
+    s->diag_scale = true;
   } else {
     return fail(NS_EINVAL, "unknown scale %d", scale);
   }
@@ -724,11 +747,11 @@ int ns_init_scale(ns_solver* s, int scale, double eps, double* alpha_out, double
     return fail(NS_ENOTSPD, "alpha = %g is not a positive finite number", s->alpha);
   int64_t np;
   if (is_f64(s))
-    np = launch_init_resid<double>(s->A, s->lda, s->n, s->scal + 0, s->F.d, s->ld, nullptr,
-                                   s->partial, s->stream);
+    np = launch_init_resid<double>(s->A, s->lda, s->n, s->scal + 0, sdiag_of(s), s->F.d, s->ld,
+                                   nullptr, s->partial, s->stream);
   else
-    np = launch_init_resid<float>(s->A, s->lda, s->n, s->scal + 0, s->F.f, s->ld, s->F.b,
-                                  s->partial, s->stream);
+    np = launch_init_resid<float>(s->A, s->lda, s->n, s->scal + 0, sdiag_of(s), s->F.f, s->ld,
+                                  s->F.b, s->partial, s->stream);
   launch_reduce(s->partial, np, s->scal + 1, 2, 0.0, s->stream);
   s->scaled = true;
   s->g_implicit = true;
@@ -781,7 +804,8 @@ int ns_get_G(ns_solver* s, double* G_out, int64_t ldg) {
   if (!G_out || ldg < s->n) return fail(NS_EINVAL, "bad G_out / ldg");
   if (!s->scaled) return fail(NS_ESTATE, "ns_init_scale first");
   if (s->g_implicit) {
-    launch_scaled_identity_plus<double>(nullptr, 0, s->n, s->scal + 0, G_out, ldg, s->stream);
+    launch_scaled_identity_plus<double>(nullptr, 0, s->n, s->scal + 0, sdiag_of(s), G_out, ldg,
+                                        s->stream);
     return NS_OK;
   }
   return copy_out(s, s->G[s->gcur], G_out, ldg);
@@ -819,6 +843,18 @@ int richardson_ns_solve(ns_solver* s, const double* b, double* theta, const ns_s
   if (o->accel_q > 0 && o->factorization != NS_FACT_COMPOSITE_DOUBLE)
     return fail(NS_EINVAL, "the accelerator (accel_q > 0) needs the composite form");
   if (int rc = validate_step_args(s, o->order, o->factorization, o->p, o->w)) return rc;
+  const int h = o->init_order > 1 ? o->init_order : 1;
+  int hp = o->init_p, hw = o->init_w;
+  if (o->init_order < 0 || hp < 0 || hw < 0) return fail(NS_EINVAL, "negative initial series");
+  if (h > 1) {
+    if (o->factorization == NS_FACT_COMPOSITE_DOUBLE || o->accel_q > 0)
+      return fail(NS_EINVAL, "the initial series (init_order > 1) is for the classical forms");
+    if (hp == 0 && hw == 0) {
+      hp = h - 1;
+      hw = 1;
+    }
+    if (int rc = validate_step_args(s, h, NS_FACT_UNIFIED, hp, hw)) return rc;
+  }
   ns_solve_report local;
   ns_solve_report* R = rep ? rep : &local;
   memset(R, 0, sizeof(*R));
@@ -827,6 +863,14 @@ int richardson_ns_solve(ns_solver* s, const double* b, double* theta, const ns_s
   double alpha = 0.0, f0 = 0.0;
   if (int rc = ns_init_scale(s, o->scale, o->eps, &alpha, &f0)) return rc;
   R->alpha = alpha;
+  if (h > 1) {
+    // G_0 = S^-1 sum_{j<h} (I - A S^-1)^j by the unified program (eq. g01),
+    // F_0 = (I - A S^-1)^h (eq. g03).
+    if (int rc = step_classic(s, h, NS_FACT_UNIFIED, hp, hw)) return rc;
+    double hf[1];
+    if (int rc = read_scalars(s, hf, 1, 1)) return rc;
+    f0 = hf[0];
+  }
   R->fnorm_hist[R->n_fnorm++] = f0;
 
   // ||b||
@@ -840,7 +884,10 @@ int richardson_ns_solve(ns_solver* s, const double* b, double* theta, const ns_s
     if (int rc = composite_start(s, o->order)) return rc;
     mat_vec(s, s->L[s->lcur], b, nullptr, theta, 0);
   } else if (o->theta0_mode == 0) {
-    launch_vec_scale(b, s->scal + 0, theta, s->n, 0, s->stream);
+    if (s->g_implicit)
+      launch_vec_scale(b, s->scal + 0, sdiag_of(s), theta, s->n, 0, s->stream);
+    else
+      mat_vec(s, s->G[s->gcur], b, nullptr, theta, 0);   // theta_0 = G_0 b
   } else if (o->theta0_mode == 1) {
     HIP_TRY(hipMemsetAsync(theta, 0, s->n * sizeof(double), s->stream));
   }
@@ -934,7 +981,7 @@ int richardson_ns_solve(ns_solver* s, const double* b, double* theta, const ns_s
       if (q > 0)
         accel_apply(s, q, theta);
       else if (s->g_implicit)
-        launch_vec_scale(s->r, s->scal + 0, theta, s->n, 1, s->stream);
+        launch_vec_scale(s->r, s->scal + 0, sdiag_of(s), theta, s->n, 1, s->stream);
       else
         gemv_update(s, theta);
       ++refine;

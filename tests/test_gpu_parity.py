@@ -472,3 +472,91 @@ def test_program_trials_match_oracle_steps(torch):
             order=pr.order, form=pr.form, p=pr.p if pr.form.startswith("unified") else None,
             w=pr.w if pr.form.startswith("unified") else None, resid_tol=1e-12))
         assert abs(t.ns_steps - orc.ns_steps) <= 1, (pr.name, t.ns_steps, orc.ns_steps)
+
+
+# --------------------------------------------------------------------------
+# Diagonal preconditioner and initial series (Section 2, eqs. g01-g03)
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("prec", [nsr.PREC_FP64, nsr.PREC_FP32])
+@pytest.mark.parametrize("order,form", [(4, "squaring"), (8, "squaring"), (6, "unified"),
+                                        (11, "table")])
+def test_diag_preconditioner_matches_oracle(torch, prec, order, form):
+    """S = diag(A) on a Jacobi-scaled SPD matrix (kappa(A) ~ 1e3, spectrum of
+    S^-1/2 A S^-1/2 in [0.85, 1.15]): ||F_k|| trace against the oracle, the
+    solve converges in fewer steps than with S = ||A||_F I."""
+    sysm = inputs.spd_jacobi(211, seed=order)
+    p, w = (2, 2) if form == "unified" else (0, 0)
+    A, b = to_dev(torch, sysm.A), to_dev(torch, sysm.b)
+    th = torch.zeros_like(b)
+    s = nsr.Solver(211, precision=prec)
+    s.bind(A)
+    tol = 1e-13 if prec == nsr.PREC_FP64 else 1e-10
+    rep = s.solve(b, th, order=order, form=form, p=p, w=w, scale=nsr.SCALE_DIAG,
+                  resid_tol=tol, refine_max=100)
+    orc = oracle.solve(sysm.A, sysm.b, oracle.SolveOptions(
+        order=order, form=form, p=p or None, w=w or None, scale="diag", resid_tol=1e-13))
+    assert rep.alpha == pytest.approx(float(np.max(np.diag(sysm.A))), rel=1e-15)
+    if prec == nsr.PREC_FP64:
+        assert abs(rep.ns_steps - orc.ns_steps) <= 1
+        compare_traces(rep.fnorm_hist, orc.fnorm_hist)
+    else:
+        assert rep.fnorm_hist[0] == pytest.approx(orc.fnorm_hist[0], rel=1e-6)
+    assert rep.status == nsr.NS_OK and rep.rel_resid <= tol
+    th_c = th.cpu().numpy()
+    assert np.linalg.norm(sysm.b - sysm.A @ th_c) / np.linalg.norm(sysm.b) <= 1.01 * tol
+    th2 = torch.zeros_like(b)
+    rep_f = s.solve(b, th2, order=order, form=form, p=p, w=w, resid_tol=tol, refine_max=100)
+    assert rep.ns_steps < rep_f.ns_steps
+
+
+def test_diag_preconditioner_errors(torch):
+    a = np.eye(8)
+    a[3, 3] = 0.0
+    s = nsr.Solver(8)
+    s.bind(to_dev(torch, a))
+    with pytest.raises(nsr.NSError) as e:
+        s.init_scale(nsr.SCALE_DIAG)
+    assert e.value.status == nsr.NS_ENOTSPD
+    m = nsr.Solver(8, precision=nsr.PREC_MIXED_BF16)
+    m.bind(to_dev(torch, np.eye(8)))
+    with pytest.raises(nsr.NSError) as e:
+        m.init_scale(nsr.SCALE_DIAG)
+    assert e.value.status == nsr.NS_EINVAL
+
+
+@pytest.mark.parametrize("h,p,w,order", [(4, 1, 2, 4), (3, 2, 1, 8), (6, 2, 2, 4), (2, 0, 0, 8)])
+def test_initial_series_matches_oracle(torch, h, p, w, order):
+    """Initial series of order h (eq. g01) before order-n steps: F_0 = Y^h, the
+    trace ||F_k|| against the oracle and the exponent h n^k of the eigen closed
+    form."""
+    sysm = inputs.spd_qlq(180, 1e3, seed=h * 10 + order)
+    A, b = to_dev(torch, sysm.A), to_dev(torch, sysm.b)
+    th = torch.zeros_like(b)
+    s = nsr.Solver(180)
+    s.bind(A)
+    rep = s.solve(b, th, order=order, init_order=h, init_p=p, init_w=w, resid_tol=1e-13)
+    orc = oracle.solve(sysm.A, sysm.b, oracle.SolveOptions(
+        order=order, init_order=h, init_p=p if (p or w) else None,
+        init_w=w if (p or w) else None, resid_tol=1e-13))
+    compare_traces(rep.fnorm_hist, orc.fnorm_hist)
+    mu = 1.0 - sysm.lam / rep.alpha
+    for k, fk in enumerate(rep.fnorm_hist):
+        ref = math.sqrt(float(np.sum(mu ** (2 * h * order ** k))))
+        if ref > 1e-8:
+            assert fk == pytest.approx(ref, rel=1e-9), k
+    assert rep.rel_resid <= 1e-13
+    assert np.linalg.norm(th.cpu().numpy() - orc.theta) <= 1e3 * 1e3 * U * np.linalg.norm(orc.theta)
+
+
+def test_initial_series_mixed(torch):
+    sysm = inputs.spd_qlq(300, 1e4, seed=9)
+    A, b = to_dev(torch, sysm.A), to_dev(torch, sysm.b)
+    th = torch.zeros_like(b)
+    s = nsr.Solver(300, precision=nsr.PREC_MIXED_BF16)
+    s.bind(A)
+    rep = s.solve(b, th, order=8, init_order=4, init_p=1, init_w=2, resid_tol=1e-10,
+                  refine_max=100)
+    assert rep.status == nsr.NS_OK and rep.rel_resid <= 1e-10
+    with pytest.raises(nsr.NSError):
+        s.solve(b, th, order=8, form="composite_double", init_order=4)
