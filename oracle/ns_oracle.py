@@ -32,7 +32,8 @@ import numpy as np
 __all__ = [
     "MMCounter", "alpha_frobenius", "alpha_inf_half", "splitting_condition",
     "residual", "z_horner", "z_unified", "z_unified_plus1", "z_squaring",
-    "diag_preconditioner", "initial_series",
+    "diag_preconditioner", "initial_series", "gc_init", "gc_step", "gc_exponent",
+    "sri_init", "sri_step", "sri_exponent",
     "z_table", "TABLE_ORDERS", "z_form", "form_mmm", "ns_step",
     "dns_init", "dns_step", "richardson_update", "accelerator_apply", "SolveOptions",
     "SolveReport", "riem6_gamma",
@@ -328,6 +329,107 @@ def dns_step(a, st: DNSState, order, form="squaring", p=None, w=None, ctr=None) 
 
 
 # ---------------------------------------------------------------------------
+# Section 5: general composite expansion, eqs. (gkgen1)-(ga1)
+# ---------------------------------------------------------------------------
+
+@dataclasses.dataclass
+class GCState:
+    T: list            # T_i = S^-1 sum_{j < x_i} (S^-1 D)^j, x_i = m_i^(k-1)
+    Gam: list          # Gamma_i = I - A T_i = (S^-1 D)^(x_i)   (eq. ga1, mirrored)
+    G: np.ndarray      # G_{k-1}
+    F: np.ndarray      # F_{k-1} = I - A G_{k-1}
+
+
+def _loop_step(a, t, gam, m, form, ctr):
+    """One order-m Newton-Schulz step of a composite loop: ``T P_m(Gamma)``;
+    order 1 leaves ``T`` unchanged (``x_i = 1^k = 1``)."""
+    if m == 1:
+        return t
+    return z_form(a, t, m, form, None, None, ctr, y=gam)
+
+
+def gc_init(a, g0, rates, ctr=None) -> GCState:
+    """Step 0 of the composite: every ``T_i = G_0 = S^-1`` (``x_i = m_i^0 = 1``),
+    ``Gamma_i = F_0``."""
+    f0 = residual(a, g0, ctr)
+    return GCState(T=[g0.copy() for _ in rates], Gam=[f0.copy() for _ in rates], G=g0, F=f0)
+
+
+def gc_step(a, st: GCState, order, rates, form="squaring", ctr=None) -> GCState:
+    """One step of the composite expansion with w = len(rates) parallel power
+    series, right orientation.
+
+    Each loop advances its series to ``x_i = m_i^k`` (``T_i <- T_i P_{m_i}(Gamma_i)``,
+    ``Gamma_i = I - A T_i``, eqs. ti / ga1); the composite polynomial and residual
+    are ``T_c = T_1 + T_2 Gamma_1 + T_3 Gamma_2 Gamma_1 + ...`` and
+    ``Gamma_c = Gamma_w ... Gamma_1`` (eqs. tc / gc, mirrored so that
+    ``A T_c = I - Gamma_c``, eq. rel1); then
+    ``G_k = T_c + G_{k-1} P_n(F_{k-1}) Gamma_c`` (eq. gkgen1) and
+    ``F_k = I - A G_k = F_{k-1}^n Gamma_c`` (eq. gem1).
+    """
+    ts, gams = [], []
+    for t, gam, m in zip(st.T, st.Gam, rates):
+        t_new = _loop_step(a, t, gam, m, form, ctr)
+        ts.append(t_new)
+        gams.append(gam if m == 1 else residual(a, t_new, ctr))
+    tc, gc = ts[0], gams[0]
+    for t_i, g_i in zip(ts[1:], gams[1:]):
+        tc = tc + _mm(ctr, t_i, gc)          # + T_i Gamma_{i-1} ... Gamma_1
+        gc = _mm(ctr, g_i, gc)               # Gamma_i ... Gamma_1
+    if order == 1:
+        hmat = st.G
+    else:
+        hmat = z_form(a, st.G, order, form, None, None, ctr, y=st.F)
+    g_k = tc + _mm(ctr, hmat, gc)
+    f_k = residual(a, g_k, ctr)
+    return GCState(T=ts, Gam=gams, G=g_k, F=f_k)
+
+
+def gc_exponent(k: int, order: int, rates) -> int:
+    """Exponent e_k of ``F_k = F_0^(e_k)`` for :func:`gc_step`:
+    ``e_0 = 1``, ``e_k = n e_{k-1} + sum_i m_i^k`` (eq. gem1 with
+    ``Gamma_c = F_0^(sum x_i)``)."""
+    e = 1
+    for j in range(1, k + 1):
+        e = order * e + sum(m ** j for m in rates)
+    return e
+
+
+# ---------------------------------------------------------------------------
+# Remark 2: the two-loop algorithm of [sri], for comparison
+# ---------------------------------------------------------------------------
+
+@dataclasses.dataclass
+class SRIState:
+    Z: np.ndarray      # Z_{k-1}
+    L: np.ndarray      # L_{k-1} = I - A Z_{k-1}
+    G: np.ndarray      # G_{k-1}
+    F: np.ndarray      # F_{k-1} = I - A G_{k-1}
+
+
+def sri_init(a, g0, ctr=None) -> SRIState:
+    f0 = residual(a, g0, ctr)
+    return SRIState(Z=g0, L=f0, G=g0, F=f0)
+
+
+def sri_step(a, st: SRIState, order, form="squaring", ctr=None) -> SRIState:
+    """Eqs. (sri1)-(sri2) in the right orientation: ``Z_k = Z_{k-1} P_p(L_{k-1})``,
+    ``G_k = G_{k-1} + Z_k F_{k-1}``; then ``L_k = I - A Z_k = L_{k-1}^p``
+    (srilk) and ``F_k = I - A G_k = L_k F_{k-1}`` (srifk1, mirrored)."""
+    z_k = z_form(a, st.Z, order, form, None, None, ctr, y=st.L)
+    l_k = residual(a, z_k, ctr)
+    g_k = st.G + _mm(ctr, z_k, st.F)
+    f_k = residual(a, g_k, ctr)
+    return SRIState(Z=z_k, L=l_k, G=g_k, F=f_k)
+
+
+def sri_exponent(k: int, order: int) -> int:
+    """``F_k = F_0^(E_k)`` with ``E_k = 1 + p + ... + p^k`` (from srilk / srifk1
+    with ``Z_0 = G_0``, so ``L_0 = F_0``)."""
+    return sum(order ** j for j in range(k + 1))
+
+
+# ---------------------------------------------------------------------------
 # Section 6: Richardson iteration coupled with the inverse estimate
 # ---------------------------------------------------------------------------
 
@@ -417,6 +519,8 @@ class SolveOptions:
     theta0: str = "g0b"            # "g0b": theta_0 = G_0 b;  "zero";  "l0b": L_0 b
     accel_q: int = 0               # >0: Richardson with the accelerator of eq. (ttk1),
                                    # Neumann order q (composite form only)
+    rates: tuple | None = None     # general composite (eqs. gkgen1-ga1): loop orders m_i
+    sri: bool = False              # the two-loop algorithm of Remark 2 ([sri])
 
 
 @dataclasses.dataclass
@@ -477,11 +581,19 @@ def solve(a, b, opts: SolveOptions = SolveOptions()) -> SolveReport:
     if opts.accel_q and not opts.composite:
         raise ValueError("the accelerator of eq. (ttk1) needs the composite form")
 
+    if sum([bool(opts.composite), opts.rates is not None, bool(opts.sri)]) > 1:
+        raise ValueError("composite, rates and sri are exclusive")
     if opts.composite:
         st = dns_init(a, g0, opts.order, opts.form, opts.p, opts.w, ctr)
         g, f = st.G, st.F
         if opts.theta0 == "l0b" or opts.accel_q:
             theta = st.L @ b              # theta_0 = L_0 b (Section 6, below eq. riem6)
+    elif opts.rates is not None:
+        st = gc_init(a, g0, opts.rates, ctr)
+        g, f = st.G, st.F
+    elif opts.sri:
+        st = sri_init(a, g0, ctr)
+        g, f = st.G, st.F
     else:
         g = g0
         f = residual(a, g, ctr)
@@ -499,6 +611,13 @@ def solve(a, b, opts: SolveOptions = SolveOptions()) -> SolveReport:
                 theta = theta + accelerator_apply(a, st, r, opts.accel_q)
             else:
                 theta, r = richardson_update(a, b, theta, g)
+        elif opts.rates is not None or opts.sri:
+            if opts.sri:
+                st = sri_step(a, st, opts.order, opts.form, ctr)
+            else:
+                st = gc_step(a, st, opts.order, opts.rates, opts.form, ctr)
+            g, f = st.G, st.F
+            theta, r = richardson_update(a, b, theta, g)
         else:
             g = ns_step(a, g, opts.order, opts.form, opts.p, opts.w, ctr, f=f)
             theta, r = richardson_update(a, b, theta, g)

@@ -462,3 +462,80 @@ def test_initial_series_solve_exponent(h, order):
         if ref > 1e-8:
             assert fk == pytest.approx(ref, rel=1e-9), k
     assert rep.rel_resid <= 1e-13
+
+
+# --------------------------------------------------------------------------
+# General composite expansion (eqs. gkgen1-ga1) and the [sri] algorithm of
+# Remark 2
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("order,rates", [(2, (2,)), (4, (2, 4)), (2, (4, 2, 2)), (4, (1, 2))])
+def test_general_composite_exponent(order, rates):
+    """F_k = F_{k-1}^n Gamma_c as matrices (eq. gem1, mirrored) and
+    ||F_k||_F = sqrt(sum mu^(2 e_k)) with e_k = n e_{k-1} + sum_i m_i^k."""
+    sysm = inputs.spd_qlq(48, 1e4, seed=len(rates) * 7 + order)
+    a = sysm.A
+    alpha = oracle.alpha_frobenius(a)
+    mu = 1.0 - sysm.lam / alpha
+    st = oracle.gc_init(a, np.eye(48) / alpha, rates)
+    for k in range(1, 4):
+        f_prev = st.F
+        st = oracle.gc_step(a, st, order, rates)
+        gc = np.eye(48)
+        for g_i in st.Gam:
+            gc = g_i @ gc
+        ref_mat = np.linalg.matrix_power(f_prev, order) @ gc
+        assert np.linalg.norm(st.F - ref_mat) <= 1e-12 * max(1.0, np.linalg.norm(ref_mat)) * 48
+        e = oracle.gc_exponent(k, order, rates)
+        ref = math.sqrt(float(np.sum(mu ** (2 * e))))
+        if ref > 1e-8:
+            assert np.linalg.norm(st.F) == pytest.approx(ref, rel=1e-9), k
+
+
+def test_general_composite_n_w_m_one_is_the_splitting_iteration():
+    """n = w = m = 1 reduces eq. (gkgen1) to G_k = S^-1 + G_{k-1} (S^-1 D)
+    (right orientation of the splitting iteration quoted after eq. ga1)."""
+    sysm = inputs.spd_qlq(20, 10.0, seed=2)
+    a = sysm.A
+    alpha = oracle.alpha_frobenius(a)
+    s_inv = np.eye(20) / alpha
+    y = np.eye(20) - a / alpha
+    st = oracle.gc_init(a, s_inv, (1,))
+    g = s_inv.copy()
+    for k in range(1, 6):
+        st = oracle.gc_step(a, st, 1, (1,))
+        g = s_inv + g @ y
+        assert np.allclose(st.G, g, rtol=1e-14, atol=1e-18)
+        assert oracle.gc_exponent(k, 1, (1,)) == k + 1
+
+
+@pytest.mark.parametrize("order", [2, 4, 8])
+def test_sri_error_model(order):
+    """Remark 2: L_k = L_{k-1}^p and F_k = L_k F_{k-1} (mirrored), so with
+    Z_0 = G_0 the exponent is E_k = 1 + p + ... + p^k."""
+    sysm = inputs.spd_qlq(40, 1e4, seed=order)
+    a = sysm.A
+    alpha = oracle.alpha_frobenius(a)
+    mu = 1.0 - sysm.lam / alpha
+    st = oracle.sri_init(a, np.eye(40) / alpha)
+    for k in range(1, 4):
+        prev = st
+        st = oracle.sri_step(a, st, order)
+        lp = np.linalg.matrix_power(prev.L, order)
+        assert np.linalg.norm(st.L - lp) <= 1e-12 * max(1.0, np.linalg.norm(lp)) * 40
+        lf = st.L @ prev.F
+        assert np.linalg.norm(st.F - lf) <= 1e-12 * max(1.0, np.linalg.norm(lf)) * 40
+        e = oracle.sri_exponent(k, order)
+        assert e == (order ** (k + 1) - 1) // (order - 1)
+        ref = math.sqrt(float(np.sum(mu ** (2 * e))))
+        if ref > 1e-8:
+            assert np.linalg.norm(st.F) == pytest.approx(ref, rel=1e-9), k
+
+
+@pytest.mark.parametrize("n", [2, 3, 4, 8])
+def test_remark2_double_ns_exponent_exceeds_sri(n):
+    """Remark 2: the double Newton-Schulz error exponent k n^(k+1) + n^k
+    (eq. ermoex1) exceeds the [sri] exponent (n^(k+1) - 1) / (n - 1) from
+    the first step on (the F_{k-1}^n versus F_{k-1} factor)."""
+    for k in range(1, 8):
+        assert k * n ** (k + 1) + n ** k > oracle.sri_exponent(k, n)
