@@ -87,8 +87,16 @@ typedef enum {
                                 step's residual                                */
   NS_FACT_UNIFIED = 3,       /* eqs. (xa2)-(zi1), n = w(p+1): p+w+1 mmm        */
   NS_FACT_UNIFIED_PLUS1 = 4, /* eq. (ztab2), n = w(p+1)+1                      */
-  NS_FACT_COMPOSITE_DOUBLE = 5 /* double Newton-Schulz, Section 5.1; inner
+  NS_FACT_COMPOSITE_DOUBLE = 5, /* double Newton-Schulz, Section 5.1; inner
                                   sums in the squaring form (n = 2^s)          */
+  NS_FACT_SRI = 6,           /* the two-loop algorithm of Remark 2 ([sri]):
+                                Z_k = Z_{k-1} P_p(I - A Z_{k-1}),
+                                G_k = G_{k-1} + Z_k F_{k-1} (mirrored), p = 2^s;
+                                for comparison                                 */
+  NS_FACT_COMPOSITE_GENERAL = 7 /* composite expansion of eqs. (gkgen1)-(ga1):
+                                w parallel power series of rates x_i = m_i^k
+                                (ns_set_composite_rates) and an order-n NS
+                                loop, n = 1 or 2^s: F_k = F_{k-1}^n Gamma_c    */
 } ns_factorization;
 
 /* Why a phase of richardson_ns_solve ended (ns_solve_report.*_stop). */
@@ -111,8 +119,11 @@ typedef enum {
 typedef struct ns_solver ns_solver;
 
 /* Bytes of device workspace a solver of dimension n needs for the given
- * precision; composite != 0 adds the buffers of the double Newton-Schulz
- * loop.  Returns 0 for n < 1 or an unknown precision. */
+ * precision.  composite = 0: the classical and table forms; 1: also the
+ * double Newton-Schulz loop (Section 5.1), the [sri] form and the general
+ * composite with one loop; 2 or 3: the general composite with that many
+ * loops.  ns_create takes the largest level the given bytes cover.  Returns
+ * 0 for n < 1, an unknown precision or composite outside 0..3. */
 size_t ns_workspace_bytes(int64_t n, int precision, int composite);
 
 /* Create a solver for n x n systems on HIP device `device`, enqueuing on
@@ -163,6 +174,13 @@ int ns_step(ns_solver* s, int order, int factorization, int p, int w,
  * full: Newton-Schulz corrects a perturbation of G only when F is the exact
  * residual of the G it multiplies.  Float64 mode only. */
 int ns_set_symmetric(ns_solver* s, int enable);
+
+/* Loops of NS_FACT_COMPOSITE_GENERAL: w in 1..3 power series with orders
+ * rates[i] in {1, 2, 4, 8, ...} (x_i = rates[i]^k after k steps; a rate of 1
+ * keeps T_i = S^-1).  Needs a workspace of ns_workspace_bytes(n, precision,
+ * w) or more; set before the first composite step after ns_init_scale.
+ * Errors: NS_EINVAL, NS_ESTATE. */
+int ns_set_composite_rates(ns_solver* s, int w, const int* rates);
 
 /* Copy the current G_k into G_out (device, row-major float64, ldg >= n;
  * converted from float32 in the float32 / mixed modes). */

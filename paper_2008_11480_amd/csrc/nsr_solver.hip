@@ -59,7 +59,14 @@ struct Mat {
 // Matrices of the iteration.  Plain: G0 G1 F P0 P1 C0 C1 (7); composite adds
 // L0 L1 Gam H (11).  In mixed mode F, P*, C*, Gam carry bf16 copies.
 constexpr int kPlainMats = 7;
-constexpr int kCompositeMats = 11;
+constexpr int kMaxLoops = 3;   // parallel power series of the general composite
+
+// Matrices for a composite level (0: plain; 1: double Newton-Schulz, [sri]
+// and the general composite with one loop: L0 L1 Gam H; each further loop of
+// the general composite: T0 T1 Gamma).  bf16 copies (mixed mode): F, P*, C*
+// and one Gamma per loop.
+int level_mats(int level) { return kPlainMats + (level >= 1 ? 4 : 0) + 3 * (level > 1 ? level - 1 : 0); }
+int level_shadows(int level) { return 5 + level; }
 
 int64_t partial_capacity(int64_t n) {
   int64_t c = gemm_f64_partials(n, n, false);
@@ -83,11 +90,11 @@ size_t layout_bytes(int64_t n, int precision, int composite) {
   const int64_t ld = ld_for(n);
   const size_t nn = (size_t)n * ld;
   size_t bytes = 0;
-  const int mats = composite ? kCompositeMats : kPlainMats;
+  const int mats = level_mats(composite);
   bytes += (size_t)mats * align_up(nn * elem_bytes(precision), kAlign);
   if (precision != NS_PREC_FP64) bytes += align_up(nn * 4, kAlign);          // float32 A
   if (precision == NS_PREC_MIXED_BF16)
-    bytes += (size_t)(composite ? 6 : 5) * align_up(nn * 2, kAlign);         // bf16 copies
+    bytes += (size_t)level_shadows(composite) * align_up(nn * 2, kAlign);    // bf16 copies
   bytes += 5 * align_up((size_t)n * sizeof(double), kAlign);                 // r, t, w0, w1, S
   bytes += align_up((size_t)partial_capacity(n) * sizeof(double), kAlign);   // partials
   bytes += align_up(16 * sizeof(double), kAlign);                            // scalars
@@ -123,6 +130,13 @@ struct ns_solver {
   Mat L[2];
   int lcur = 0;
   Mat Gam, H;
+  Mat LT[kMaxLoops - 1][2], LG[kMaxLoops - 1];   // loops 2.. of the general composite
+  Mat* loopT[kMaxLoops][2] = {};
+  Mat* loopG[kMaxLoops] = {};
+  int tcur[kMaxLoops] = {0, 0, 0};
+  int gc_w = 0;                    // general composite: number of loops (0: not set)
+  int gc_m[kMaxLoops] = {0, 0, 0}; // their orders m_i (x_i = m_i^k)
+  bool gc_started = false;
   float* A32 = nullptr;
   double* r = nullptr;
   double* vt = nullptr;      // accelerator temporaries (eq. ttk1)
@@ -498,6 +512,138 @@ int step_composite(ns_solver* s, int order) {
   return resid_into(s, s->F, Gn, true);
 }
 
+// D = X (same layout; data and bf16 copy).
+int copy_mat(ns_solver* s, Mat& D, const Mat& X) {
+  const size_t nn = (size_t)s->n * s->ld;
+  if (is_f64(s)) {
+    HIP_TRY(hipMemcpyAsync(D.d, X.d, nn * 8, hipMemcpyDeviceToDevice, s->stream));
+  } else {
+    HIP_TRY(hipMemcpyAsync(D.f, X.f, nn * 4, hipMemcpyDeviceToDevice, s->stream));
+  }
+  if (D.b && X.b) HIP_TRY(hipMemcpyAsync(D.b, X.b, nn * 2, hipMemcpyDeviceToDevice, s->stream));
+  return NS_OK;
+}
+
+// Dst = G_k, materialising G_0 = S^-1 when it is still implicit.
+const Mat* explicit_g(ns_solver* s) {
+  if (s->g_implicit) {
+    scaled_identity(s, nullptr, s->G[s->gcur]);
+    s->g_implicit = false;
+  }
+  return &s->G[s->gcur];
+}
+
+// Remark 2 ([sri]), right orientation: Z_k = Z_{k-1} P_p(L_{k-1}),
+// L_k = I - A Z_k, G_k = G_{k-1} + Z_k F_{k-1}, F_k = I - A G_k.  Z lives in
+// L[0..1], L_k in Gam; Z_0 = G_0 and L_0 = F_0.
+int step_sri(ns_solver* s, int order) {
+  int rc;
+  s->p0_is_f2 = false;
+  const Mat* c = nullptr;
+  if (!s->dns_started) {
+    if (!s->g_implicit) return fail(NS_ESTATE, "the [sri] form must start from G_0");
+    if ((rc = poly_squaring(s, order, s->F, &c))) return rc;
+    s->lcur = 0;
+    scaled_identity(s, c, s->L[0]);                                 // Z_1 = G_0 P(F_0)
+    s->dns_started = true;
+  } else {
+    if ((rc = poly_squaring(s, order, s->Gam, &c))) return rc;
+    Mat& Zc = s->L[s->lcur];
+    Mat& Zn = s->L[s->lcur ^ 1];
+    if ((rc = mm(s, Zn, &Zc, *c, &Zc, nullptr, 0.0, 1.0, false, K_APPLY))) return rc;
+    s->lcur ^= 1;
+  }
+  Mat& Z = s->L[s->lcur];
+  if ((rc = resid_into(s, s->Gam, Z, false))) return rc;            // L_k = I - A Z_k
+  const Mat* Gc = explicit_g(s);
+  Mat& Gn = s->G[s->gcur ^ 1];
+  if ((rc = mm(s, Gn, &Z, s->F, Gc, nullptr, 0.0, 1.0, false, K_APPLY))) return rc;
+  s->gcur ^= 1;
+  return resid_into(s, s->F, Gn, true);
+}
+
+// General composite expansion (eqs. gkgen1-ga1), right orientation, with
+// s->gc_w loops of orders m_i: loop i holds T_i = S^-1 sum_{j < x_i}
+// (S^-1 D)^j and Gamma_i = I - A T_i with x_i = m_i^(k-1) before step k.
+//   T_i <- T_i P_{m_i}(Gamma_i),  Gamma_i <- I - A T_i
+//   T_c = T_1 + (T_2 + T_3 Gamma_2) Gamma_1,  Gamma_c = Gamma_3 Gamma_2 Gamma_1
+//   G_k = T_c + G_{k-1} P_n(F_{k-1}) Gamma_c,   F_k = I - A G_k = F_{k-1}^n Gamma_c
+int step_gc(ns_solver* s, int order) {
+  int rc;
+  s->p0_is_f2 = false;
+  const int w = s->gc_w;
+  const Mat* c = nullptr;
+  if (!s->gc_started) {
+    if (!s->g_implicit) return fail(NS_ESTATE, "the composite form must start from G_0");
+    for (int i = 0; i < w; ++i) {
+      s->tcur[i] = 0;
+      if (s->gc_m[i] == 1) {   // x_i = 1 for ever: T_i = S^-1, Gamma_i = F_0
+        scaled_identity(s, nullptr, *s->loopT[i][0]);
+        if ((rc = copy_mat(s, *s->loopG[i], s->F))) return rc;
+      }
+    }
+  }
+  // 1. loops (Gamma_i of a fresh loop is F_0 = s->F)
+  for (int i = 0; i < w; ++i) {
+    const int m = s->gc_m[i];
+    if (m == 1) continue;
+    if (!s->gc_started) {
+      if ((rc = poly_squaring(s, m, s->F, &c))) return rc;
+      scaled_identity(s, c, *s->loopT[i][0]);
+    } else {
+      if ((rc = poly_squaring(s, m, *s->loopG[i], &c))) return rc;
+      Mat& Tc = *s->loopT[i][s->tcur[i]];
+      Mat& Tn = *s->loopT[i][s->tcur[i] ^ 1];
+      if ((rc = mm(s, Tn, &Tc, *c, &Tc, nullptr, 0.0, 1.0, false, K_APPLY))) return rc;
+      s->tcur[i] ^= 1;
+    }
+    if ((rc = resid_into(s, *s->loopG[i], *s->loopT[i][s->tcur[i]], false))) return rc;
+  }
+  // 2. ordinary loop H = G_{k-1} P_n(F_{k-1})
+  const Mat* H;
+  if (order >= 2) {
+    if ((rc = poly_squaring(s, order, s->F, &c))) return rc;
+    if ((rc = apply_g(s, s->G[s->gcur], s->g_implicit, *c, s->H))) return rc;
+    H = &s->H;
+  } else {
+    H = explicit_g(s);
+  }
+  // 3. composite polynomial and residual
+  const Mat* T1 = s->loopT[0][s->tcur[0]];
+  const Mat* tc = T1;
+  const Mat* gcm = s->loopG[0];
+  if (w >= 2) {
+    const Mat* T2 = s->loopT[1][s->tcur[1]];
+    const Mat* inner = T2;
+    if (w == 3) {   // T_2 + T_3 Gamma_2
+      if ((rc = mm(s, s->C[0], s->loopT[2][s->tcur[2]], *s->loopG[1], T2, nullptr, 0.0, 1.0,
+                   false, K_APPLY)))
+        return rc;
+      inner = &s->C[0];
+    }
+    if ((rc = mm(s, s->P[0], inner, *s->loopG[0], T1, nullptr, 0.0, 1.0, false, K_APPLY)))
+      return rc;
+    tc = &s->P[0];
+    const Mat* g21 = s->loopG[1];
+    if (w == 3) {   // Gamma_3 Gamma_2
+      if ((rc = mm(s, s->C[1], s->loopG[2], *s->loopG[1], nullptr, nullptr, 0.0, 1.0, false,
+                   K_POWER)))
+        return rc;
+      g21 = &s->C[1];
+    }
+    if ((rc = mm(s, s->P[1], g21, *s->loopG[0], nullptr, nullptr, 0.0, 1.0, false, K_POWER)))
+      return rc;
+    gcm = &s->P[1];
+  }
+  // 4. merge and residual
+  Mat& Gn = s->G[s->gcur ^ 1];
+  if ((rc = mm(s, Gn, H, *gcm, tc, nullptr, 0.0, 1.0, false, K_APPLY))) return rc;
+  s->gcur ^= 1;
+  s->g_implicit = false;
+  s->gc_started = true;
+  return resid_into(s, s->F, Gn, true);
+}
+
 // y = M x + z (accumulate: y += M x + z) for an iterate M of the solver.
 void mat_vec(ns_solver* s, const Mat& M, const double* x, const double* z, double* y,
              int accumulate) {
@@ -530,6 +676,16 @@ void gemv_update(ns_solver* s, double* theta) {
     launch_gemv_update<float>(G.f, s->ld, s->n, s->r, theta, s->stream);
 }
 
+int any_step(ns_solver* s, int order, int fact, int p, int w) {
+  switch (fact) {
+    case NS_FACT_COMPOSITE_DOUBLE: return step_composite(s, order);
+    case NS_FACT_TABLE: return step_table(s, order);
+    case NS_FACT_SRI: return step_sri(s, order);
+    case NS_FACT_COMPOSITE_GENERAL: return step_gc(s, order);
+    default: return step_classic(s, order, fact, p, w);
+  }
+}
+
 int check_solver(ns_solver* s) {
   if (!s) return fail(NS_EINVAL, "null solver");
   return NS_OK;
@@ -547,7 +703,8 @@ int richardson_once(ns_solver* s, const double* b, double* theta) {
 }
 
 int validate_step_args(ns_solver* s, int order, int fact, int p, int w) {
-  if (order < 2) return fail(NS_EINVAL, "order must be >= 2 (got %d)", order);
+  if (order < (fact == NS_FACT_COMPOSITE_GENERAL ? 1 : 2))
+    return fail(NS_EINVAL, "order must be >= 2 (got %d)", order);
   switch (fact) {
     case NS_FACT_HORNER:
       return NS_OK;
@@ -565,6 +722,18 @@ int validate_step_args(ns_solver* s, int order, int fact, int p, int w) {
     case NS_FACT_TABLE:
       if (order != 11 && order != 15 && order != 45)
         return fail(NS_EINVAL, "table programs exist for orders 11, 15, 45 (got %d)", order);
+      return NS_OK;
+    case NS_FACT_SRI:
+      if (!s->composite_capable)
+        return fail(NS_EINVAL, "workspace was sized without the composite buffers");
+      if (!is_pow2(order)) return fail(NS_EINVAL, "[sri] form uses squaring sums: order = 2^s");
+      return NS_OK;
+    case NS_FACT_COMPOSITE_GENERAL:
+      if (s->gc_w < 1) return fail(NS_ESTATE, "ns_set_composite_rates first");
+      if (s->composite_capable < s->gc_w)
+        return fail(NS_EINVAL, "workspace was sized for fewer composite loops");
+      if (order != 1 && !is_pow2(order))
+        return fail(NS_EINVAL, "composite form uses squaring sums: order = 1 or 2^s");
       return NS_OK;
     case NS_FACT_COMPOSITE_DOUBLE:
       if (!s->composite_capable)
@@ -604,7 +773,8 @@ const char* ns_status_string(int st) {
 size_t ns_workspace_bytes(int64_t n, int precision, int composite) {
   if (n < 1) return 0;
   if (precision < NS_PREC_FP64 || precision > NS_PREC_MIXED_BF16) return 0;
-  return layout_bytes(n, precision, composite ? 1 : 0);
+  if (composite < 0 || composite > kMaxLoops) return 0;
+  return layout_bytes(n, precision, composite);
 }
 
 int ns_create(int device, void* hip_stream, int64_t n, int precision, void* workspace,
@@ -619,7 +789,6 @@ int ns_create(int device, void* hip_stream, int64_t n, int precision, void* work
   if ((reinterpret_cast<uintptr_t>(workspace) % kAlign) != 0)
     return fail(NS_EINVAL, "workspace must be 256-byte aligned");
   const size_t need_plain = layout_bytes(n, precision, 0);
-  const size_t need_comp = layout_bytes(n, precision, 1);
   if (bytes < need_plain)
     return fail(NS_ENOMEM, "workspace too small: %zu < %zu bytes", bytes, need_plain);
   HIP_TRY(hipSetDevice(device));
@@ -630,7 +799,9 @@ int ns_create(int device, void* hip_stream, int64_t n, int precision, void* work
   s->n = n;
   s->ld = ld_for(n);
   s->precision = precision;
-  s->composite_capable = bytes >= need_comp ? 1 : 0;
+  s->composite_capable = 0;
+  for (int lv = 1; lv <= kMaxLoops; ++lv)
+    if (bytes >= layout_bytes(n, precision, lv)) s->composite_capable = lv;
   s->ws = reinterpret_cast<char*>(workspace);
   s->ws_bytes = bytes;
   const size_t nn = (size_t)n * s->ld;
@@ -657,11 +828,22 @@ int ns_create(int device, void* hip_stream, int64_t n, int precision, void* work
   mat_of(s->P[1], true);
   mat_of(s->C[0], true);
   mat_of(s->C[1], true);
-  if (s->composite_capable) {
+  if (s->composite_capable >= 1) {
     mat_of(s->L[0], false);
     mat_of(s->L[1], false);
     mat_of(s->Gam, true);
     mat_of(s->H, false);
+    s->loopT[0][0] = &s->L[0];
+    s->loopT[0][1] = &s->L[1];
+    s->loopG[0] = &s->Gam;
+  }
+  for (int i = 1; i < s->composite_capable; ++i) {
+    mat_of(s->LT[i - 1][0], false);
+    mat_of(s->LT[i - 1][1], false);
+    mat_of(s->LG[i - 1], true);
+    s->loopT[i][0] = &s->LT[i - 1][0];
+    s->loopT[i][1] = &s->LT[i - 1][1];
+    s->loopG[i] = &s->LG[i - 1];
   }
   if (precision != NS_PREC_FP64) s->A32 = reinterpret_cast<float*>(take(align_up(nn * 4, kAlign)));
   s->r = reinterpret_cast<double*>(take(align_up((size_t)n * sizeof(double), kAlign)));
@@ -756,6 +938,7 @@ int ns_init_scale(ns_solver* s, int scale, double eps, double* alpha_out, double
   s->scaled = true;
   s->g_implicit = true;
   s->dns_started = false;
+  s->gc_started = false;
   s->p0_is_f2 = false;
   s->gcur = 0;
   s->lcur = 0;
@@ -775,9 +958,7 @@ int ns_step(ns_solver* s, int order, int factorization, int p, int w, double* fn
   if (!s->scaled) return fail(NS_ESTATE, "ns_init_scale first");
   if (int rc = validate_step_args(s, order, factorization, p, w)) return rc;
   HIP_TRY(hipSetDevice(s->device));
-  int rc = (factorization == NS_FACT_COMPOSITE_DOUBLE) ? step_composite(s, order)
-           : (factorization == NS_FACT_TABLE)            ? step_table(s, order)
-                                                         : step_classic(s, order, factorization, p, w);
+  int rc = any_step(s, order, factorization, p, w);
   if (rc) return rc;
   if (hipGetLastError() != hipSuccess) return fail(NS_EHIP, "kernel launch failed");
   if (fnorm_out) {
@@ -901,11 +1082,7 @@ int richardson_ns_solve(ns_solver* s, const double* b, double* theta, const ns_s
   double host[2];
   while (ns_stop == NS_STOP_NONE) {
     ++k;
-    int rc = (o->factorization == NS_FACT_COMPOSITE_DOUBLE)
-                 ? step_composite(s, o->order)
-             : (o->factorization == NS_FACT_TABLE)
-                 ? step_table(s, o->order)
-                 : step_classic(s, o->order, o->factorization, o->p, o->w);
+    int rc = any_step(s, o->order, o->factorization, o->p, o->w);
     if (rc) return rc;
     if (q > 0) {
       const int64_t np = launch_gemv_resid(s->A, s->lda, s->n, b, theta, s->r, s->partial, s->stream);
@@ -1001,6 +1178,21 @@ int richardson_ns_solve(ns_solver* s, const double* b, double* theta, const ns_s
   if (hipGetLastError() != hipSuccess) return fail(NS_EHIP, "kernel launch failed");
   if (status == NS_EDIVERGED) return fail(NS_EDIVERGED, "iteration diverged");
   if (status == NS_ENOCONV) return fail(NS_ENOCONV, "resid_tol not reached (%g)", rel);
+  return NS_OK;
+}
+
+int ns_set_composite_rates(ns_solver* s, int w, const int* rates) {
+  if (int rc = check_solver(s)) return rc;
+  if (w < 1 || w > kMaxLoops) return fail(NS_EINVAL, "w must be in 1..%d", kMaxLoops);
+  if (!rates) return fail(NS_EINVAL, "null rates");
+  if (w > s->composite_capable)
+    return fail(NS_EINVAL, "workspace was sized for %d composite loops", s->composite_capable);
+  if (s->gc_started) return fail(NS_ESTATE, "rates are set before the first composite step");
+  for (int i = 0; i < w; ++i)
+    if (rates[i] != 1 && !is_pow2(rates[i]))
+      return fail(NS_EINVAL, "loop orders must be 1 or 2^s (got %d)", rates[i]);
+  s->gc_w = w;
+  for (int i = 0; i < kMaxLoops; ++i) s->gc_m[i] = i < w ? rates[i] : 0;
   return NS_OK;
 }
 

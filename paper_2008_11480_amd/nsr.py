@@ -24,7 +24,8 @@ PREC_FP64, PREC_FP32, PREC_MIXED_BF16 = 0, 1, 2
 # ns_scale
 SCALE_FROBENIUS, SCALE_INF_HALF, SCALE_DIAG = 0, 1, 2
 # ns_factorization
-FACT = {"horner": 0, "squaring": 1, "table": 2, "unified": 3, "unified_plus1": 4, "composite_double": 5}
+FACT = {"horner": 0, "squaring": 1, "table": 2, "unified": 3, "unified_plus1": 4,
+        "composite_double": 5, "sri": 6, "composite_general": 7}
 # ns_stop_reason
 STOP_NAMES = {0: "none", 1: "f_tol", 2: "floor", 3: "k_max", 4: "diverged", 5: "resid_tol",
               6: "refine_max", 7: "refine_stall", 8: "precision"}
@@ -36,7 +37,7 @@ HIST_R = 200
 EXPORTS = (
     "ns_workspace_bytes", "ns_create", "ns_destroy", "ns_bind", "ns_init_scale", "ns_step",
     "ns_get_G", "ns_get_F", "ns_richardson_step", "richardson_ns_solve", "ns_set_symmetric",
-    "ns_timing_enable",
+    "ns_timing_enable", "ns_set_composite_rates",
     "ns_timing_read", "ns_timing_reset", "ns_gemm_f64", "ns_gemm_f64_partials",
     "ns_gemm_f64_scratch_bytes", "ns_gemm_f64_ws",
     "ns_gemm_f32", "ns_gemm_bf16_nt", "ns_gemm_lp_partials",
@@ -113,6 +114,7 @@ def lib() -> ctypes.CDLL:
         "richardson_ns_solve": (ci, [vp, vp, vp, ctypes.POINTER(SolveOpts),
                                      ctypes.POINTER(SolveReportC)]),
         "ns_set_symmetric": (ci, [vp, ci]),
+        "ns_set_composite_rates": (ci, [vp, ci, vp]),
         "ns_timing_enable": (ci, [vp, ci]),
         "ns_timing_read": (ci, [vp, ci, ctypes.POINTER(i64), pd, pd]),
         "ns_timing_reset": (ci, [vp]),
@@ -176,14 +178,17 @@ def _require_cuda_f64(t, name):
         raise TypeError(f"{name} must be a float64 CUDA tensor")
 
 
-def workspace_bytes(n: int, precision: int = PREC_FP64, composite: bool = False) -> int:
-    return int(lib().ns_workspace_bytes(int(n), int(precision), 1 if composite else 0))
+def workspace_bytes(n: int, precision: int = PREC_FP64, composite: int = 0) -> int:
+    """Workspace of a solver; ``composite``: 0 (classical / table forms),
+    1 or True (also double Newton-Schulz, [sri], one-loop general composite),
+    2 or 3 (general composite with that many loops)."""
+    return int(lib().ns_workspace_bytes(int(n), int(precision), int(composite)))
 
 
 class Solver:
     """One ``ns_solver`` handle with its workspace (allocated by torch)."""
 
-    def __init__(self, n: int, precision: int = PREC_FP64, composite: bool = True,
+    def __init__(self, n: int, precision: int = PREC_FP64, composite: int = 1,
                  device: int | None = None, stream=None):
         import torch
         L = lib()
@@ -216,6 +221,11 @@ class Solver:
 
     def set_symmetric(self, enable: bool):
         check(lib().ns_set_symmetric(self._h, 1 if enable else 0))
+
+    def set_composite_rates(self, rates):
+        """Loop orders m_i of the general composite form (``form="composite_general"``)."""
+        arr = (ctypes.c_int * len(rates))(*[int(m) for m in rates])
+        check(lib().ns_set_composite_rates(self._h, len(rates), arr))
 
     def bind(self, A):
         _require_cuda_f64(A, "A")

@@ -560,3 +560,91 @@ def test_initial_series_mixed(torch):
     assert rep.status == nsr.NS_OK and rep.rel_resid <= 1e-10
     with pytest.raises(nsr.NSError):
         s.solve(b, th, order=8, form="composite_double", init_order=4)
+
+
+# --------------------------------------------------------------------------
+# General composite (eqs. gkgen1-ga1) and the [sri] algorithm of Remark 2
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("symmetric", [True, False])
+@pytest.mark.parametrize("order,rates", [(2, (2,)), (4, (2, 4)), (2, (4, 2, 2)), (4, (1, 2)),
+                                         (1, (1,))])
+def test_composite_general_matches_oracle(torch, order, rates, symmetric):
+    """||F_k|| trace against the oracle and the exponent e_k = n e_{k-1} +
+    sum m_i^k of the eigen closed form."""
+    n = 150
+    kappa = 10.0 if order == 1 else 1e3
+    sysm = inputs.spd_qlq(n, kappa, seed=len(rates) + 3 * order)
+    A, b = to_dev(torch, sysm.A), to_dev(torch, sysm.b)
+    th = torch.zeros_like(b)
+    s = nsr.Solver(n, composite=len(rates))
+    s.set_symmetric(symmetric)
+    s.bind(A)
+    s.set_composite_rates(rates)
+    kmax = 64 if order > 1 else 40
+    rep = s.solve(b, th, order=order, form="composite_general", resid_tol=1e-13, k_max=kmax,
+                  refine_max=200)
+    orc = oracle.solve(sysm.A, sysm.b, oracle.SolveOptions(order=order, rates=tuple(rates),
+                                                           resid_tol=1e-13, k_max=kmax,
+                                                           refine_max=200))
+    assert abs(rep.ns_steps - orc.ns_steps) <= 1
+    compare_traces(rep.fnorm_hist, orc.fnorm_hist)
+    mu = 1.0 - sysm.lam / rep.alpha
+    for k, fk in enumerate(rep.fnorm_hist):
+        ref = math.sqrt(float(np.sum(mu ** (2 * oracle.gc_exponent(k, order, rates)))))
+        if ref > 1e-8:
+            assert fk == pytest.approx(ref, rel=1e-9), k
+    assert rep.status == nsr.NS_OK and rep.rel_resid <= 1e-13
+
+
+@pytest.mark.parametrize("order", [2, 4, 8])
+def test_sri_matches_oracle(torch, order):
+    sysm = inputs.spd_qlq(170, 1e3, seed=40 + order)
+    A, b = to_dev(torch, sysm.A), to_dev(torch, sysm.b)
+    th = torch.zeros_like(b)
+    s = nsr.Solver(170, composite=1)
+    s.bind(A)
+    rep = s.solve(b, th, order=order, form="sri", resid_tol=1e-13)
+    orc = oracle.solve(sysm.A, sysm.b, oracle.SolveOptions(order=order, sri=True,
+                                                           resid_tol=1e-13))
+    assert abs(rep.ns_steps - orc.ns_steps) <= 1
+    compare_traces(rep.fnorm_hist, orc.fnorm_hist)
+    mu = 1.0 - sysm.lam / rep.alpha
+    for k, fk in enumerate(rep.fnorm_hist):
+        ref = math.sqrt(float(np.sum(mu ** (2 * oracle.sri_exponent(k, order)))))
+        if ref > 1e-8:
+            assert fk == pytest.approx(ref, rel=1e-9), k
+    assert rep.rel_resid <= 1e-13
+    assert np.linalg.norm(th.cpu().numpy() - orc.theta) <= 1e4 * 1e3 * U * np.linalg.norm(orc.theta)
+
+
+def test_composite_general_and_sri_mixed(torch):
+    sysm = inputs.spd_qlq(300, 1e4, seed=17)
+    A, b = to_dev(torch, sysm.A), to_dev(torch, sysm.b)
+    s = nsr.Solver(300, precision=nsr.PREC_MIXED_BF16, composite=2)
+    s.bind(A)
+    s.set_composite_rates((2, 4))
+    th = torch.zeros_like(b)
+    rep = s.solve(b, th, order=4, form="composite_general", resid_tol=1e-10, refine_max=100)
+    assert rep.status == nsr.NS_OK and rep.rel_resid <= 1e-10
+    th = torch.zeros_like(b)
+    rep = s.solve(b, th, order=8, form="sri", resid_tol=1e-10, refine_max=100)
+    assert rep.status == nsr.NS_OK and rep.rel_resid <= 1e-10
+
+
+def test_composite_general_errors(torch):
+    s = nsr.Solver(64, composite=2)
+    s.bind(torch.eye(64, dtype=torch.float64, device="cuda") * 2.0)
+    with pytest.raises(nsr.NSError) as e:
+        s.set_composite_rates((2, 2, 2))            # three loops, workspace for two
+    assert e.value.status == nsr.NS_EINVAL
+    with pytest.raises(nsr.NSError):
+        s.set_composite_rates((3,))                 # not 1 or 2^s
+    b = torch.ones(64, dtype=torch.float64, device="cuda")
+    with pytest.raises(nsr.NSError) as e:
+        s.solve(b, torch.zeros_like(b), order=4, form="composite_general")
+    assert e.value.status == nsr.NS_ESTATE
+    p = nsr.Solver(64, composite=0)
+    p.bind(torch.eye(64, dtype=torch.float64, device="cuda"))
+    with pytest.raises(nsr.NSError):
+        p.solve(b, torch.zeros_like(b), order=4, form="sri")
