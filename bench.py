@@ -183,6 +183,73 @@ def run_composite(torch, nsr, steps, warmup):
     return out
 
 
+def run_comparisons(torch, nsr, A, b, sysm, n, resid_tol, k_max):
+    """Newton-Schulz variants of Sections 5-6 and Remark 2 on the headline
+    system (float64): steps, products, time and accuracy of each."""
+    variants = [
+        ("classical order 8 (squaring)", dict(order=8, form="squaring"), None),
+        ("double NS order 8 (Section 5.1)", dict(order=8, form="composite_double"), None),
+        ("double NS order 8 + accelerator q=2 (eq. ttk1)",
+         dict(order=8, form="composite_double", accel_q=2), None),
+        ("[sri] order 8 (Remark 2)", dict(order=8, form="sri"), None),
+        ("general composite n=8, rates (2, 4) (eqs. gkgen1-ga1)",
+         dict(order=8, form="composite_general"), (2, 4)),
+    ]
+    s = nsr.Solver(n, composite=2)
+    s.bind(A)
+    out = []
+    for name, kw, rates in variants:
+        th = torch.zeros_like(b)
+        times = []
+        for rep_i in range(2):
+            if rates:
+                s.init_scale()
+                s.set_composite_rates(rates)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            rep = s.solve(b, th, resid_tol=resid_tol, k_max=k_max, refine_max=64,
+                          raise_on_error=False, **kw)
+            torch.cuda.synchronize()
+            times.append(time.perf_counter() - t0)
+        x = th.cpu().numpy()
+        rel = float(np.linalg.norm(sysm.b - sysm.A @ x) / np.linalg.norm(sysm.b))
+        out.append({"variant": name, "ms_per_solve": times[-1] * 1e3, "ns_steps": rep.ns_steps,
+                    "refine_steps": rep.refine_steps, "mmm": rep.mmm, "rel_resid": rel,
+                    "status": rep.status})
+        log(f"compare {name}: {times[-1] * 1e3:.1f} ms ns_steps={rep.ns_steps} mmm={rep.mmm} "
+            f"rel_resid={rel:.2e}")
+    s.close()
+    return out
+
+
+def run_fig4_analogue(torch, nsr, steps=7):
+    """Synthetic analogue of the paper's last comparison (Section 7): three
+    close frequencies (N = 6, kappa ~ 4e3); per-step parameter error of the
+    Richardson iteration with the third-order accelerator (double NS n = 3,
+    q = 3, eq. ttk1) and of classical eighth-order Newton-Schulz coupled with
+    Richardson, float64."""
+    sysm = inputs.harmonic_three()
+    theta_star = np.linalg.solve(sysm.A, sysm.b)
+    A = torch.from_numpy(sysm.A).to("cuda")
+    b = torch.from_numpy(sysm.b).to("cuda")
+    s = nsr.Solver(6, composite=1)
+    s.bind(A)
+    rows = []
+    for k in range(1, steps + 1):
+        errs = {}
+        for name, kw in (("accelerator_q3_n3", dict(order=3, form="composite_double", accel_q=3)),
+                         ("classical_n8", dict(order=8, form="squaring"))):
+            th = torch.zeros_like(b)
+            s.solve(b, th, k_max=k, floor_detect=False, refine_max=0, resid_tol=0.0,
+                    raise_on_error=False, **kw)
+            x = th.cpu().numpy()
+            errs[name] = float(np.linalg.norm(x - theta_star) / np.linalg.norm(theta_star))
+        rows.append({"step": k, **errs})
+    s.close()
+    return {"workload": "harmonic_three_T30_w0.40-0.43-0.47", "n": 6,
+            "kappa": float(np.linalg.cond(sysm.A)), "param_rel_error": rows}
+
+
 def timeline_summary(tl, ns, groups):
     """Critical-path view of a batch from the device timeline (ms)."""
     f32 = tl[:, 1] - tl[:, 0]
@@ -322,6 +389,9 @@ def main():
     ap.add_argument("--no-composite", action="store_true", help="skip the N=8192 legs")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched leg")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving leg")
+    ap.add_argument("--no-comparisons", action="store_true",
+                    help="skip the Newton-Schulz variant comparison and the three-frequency "
+                         "analogue")
     ap.add_argument("--no-programs", action="store_true",
                     help="skip timing the other evaluation programs on the headline system")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
@@ -440,6 +510,12 @@ def main():
                 f"rel_resid={t.rel_resid:.2e}")
     del solver
     torch.cuda.empty_cache()
+    if not args.no_comparisons and not fixed:
+        out["comparisons"] = {"workload": args.workload, "precision": "fp64",
+                              "variants": run_comparisons(torch, nsr, A, b, sysm, n,
+                                                          w["resid_tol"], w["k_max"])}
+        out["fig4_analogue"] = run_fig4_analogue(torch, nsr)
+        torch.cuda.empty_cache()
 
     if not args.no_mixed and not args.no_mixed4096 and not fixed:
         # Same N=4096 system, mixed precision, to the same 1e-12 residual.

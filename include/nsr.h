@@ -88,15 +88,15 @@ typedef enum {
   NS_FACT_UNIFIED = 3,       /* eqs. (xa2)-(zi1), n = w(p+1): p+w+1 mmm        */
   NS_FACT_UNIFIED_PLUS1 = 4, /* eq. (ztab2), n = w(p+1)+1                      */
   NS_FACT_COMPOSITE_DOUBLE = 5, /* double Newton-Schulz, Section 5.1; inner
-                                  sums in the squaring form (n = 2^s)          */
+                                  sums by squaring (n = 2^s), else Horner     */
   NS_FACT_SRI = 6,           /* the two-loop algorithm of Remark 2 ([sri]):
                                 Z_k = Z_{k-1} P_p(I - A Z_{k-1}),
-                                G_k = G_{k-1} + Z_k F_{k-1} (mirrored), p = 2^s;
-                                for comparison                                 */
+                                G_k = G_{k-1} + Z_k F_{k-1} (mirrored); for
+                                comparison                                     */
   NS_FACT_COMPOSITE_GENERAL = 7 /* composite expansion of eqs. (gkgen1)-(ga1):
                                 w parallel power series of rates x_i = m_i^k
                                 (ns_set_composite_rates) and an order-n NS
-                                loop, n = 1 or 2^s: F_k = F_{k-1}^n Gamma_c    */
+                                loop, n >= 1: F_k = F_{k-1}^n Gamma_c          */
 } ns_factorization;
 
 /* Why a phase of richardson_ns_solve ended (ns_solve_report.*_stop). */
@@ -176,9 +176,10 @@ int ns_step(ns_solver* s, int order, int factorization, int p, int w,
 int ns_set_symmetric(ns_solver* s, int enable);
 
 /* Loops of NS_FACT_COMPOSITE_GENERAL: w in 1..3 power series with orders
- * rates[i] in {1, 2, 4, 8, ...} (x_i = rates[i]^k after k steps; a rate of 1
- * keeps T_i = S^-1).  Needs a workspace of ns_workspace_bytes(n, precision,
+ * rates[i] in 1..64 (x_i = rates[i]^k after k steps; a rate of 1 keeps
+ * T_i = S^-1).  Needs a workspace of ns_workspace_bytes(n, precision,
  * w) or more; set before the first composite step after ns_init_scale.
+ * Orders 2^s use the squaring sums, others Horner.
  * Errors: NS_EINVAL, NS_ESTATE. */
 int ns_set_composite_rates(ns_solver* s, int w, const int* rates);
 

@@ -310,6 +310,21 @@ int poly_squaring(ns_solver* s, int order, const Mat& Y, const Mat** out, bool y
 
 bool is_pow2(int n) { return n >= 2 && (n & (n - 1)) == 0; }
 
+// C with P(Y) = I + C = I + Y + ... + Y^(order-1) for the composite loops:
+// the squaring program when order = 2^s, otherwise Horner in identity-offset
+// form, C <- Y + Y C (order - 2 products; eq. z1).
+int poly_any(ns_solver* s, int order, const Mat& Y, const Mat** out) {
+  if (is_pow2(order)) return poly_squaring(s, order, Y, out);
+  const Mat* c = &Y;
+  for (int j = 2; j < order; ++j) {
+    Mat* nc = (c == &s->C[0]) ? &s->C[1] : &s->C[0];
+    if (int rc = mm(s, *nc, &Y, *c, &Y, nullptr, 0.0, 1.0, false, K_POWER)) return rc;
+    c = nc;
+  }
+  *out = c;
+  return NS_OK;
+}
+
 int resid_into(ns_solver* s, Mat& D, const Mat& X, bool want_norm) {
   return mm(s, D, nullptr, X, nullptr, nullptr, 1.0, -1.0, want_norm, K_RESID);  // I - A X
 }
@@ -470,7 +485,7 @@ int step_table(ns_solver* s, int order) {
 int composite_start(ns_solver* s, int order) {
   if (!s->g_implicit) return fail(NS_ESTATE, "composite form must start from G_0");
   const Mat* c = nullptr;
-  int rc = poly_squaring(s, order, s->F, &c);
+  int rc = poly_any(s, order, s->F, &c);
   if (rc) return rc;
   s->lcur = 0;
   scaled_identity(s, c, s->L[0]);
@@ -489,7 +504,7 @@ int step_composite(ns_solver* s, int order) {
     if ((rc = composite_start(s, order))) return rc;
   }
   // L-loop: L_k = L_{k-1} P(Gamma_k) (lkk1), Gamma_k^n = I - A L_k (gamk21).
-  rc = poly_squaring(s, order, s->Gam, &c);
+  rc = poly_any(s, order, s->Gam, &c);
   if (rc) return rc;
   Mat& Lc = s->L[s->lcur];
   Mat& Ln = s->L[s->lcur ^ 1];
@@ -499,7 +514,7 @@ int step_composite(ns_solver* s, int order) {
   rc = resid_into(s, s->Gam, Ln, false);
   if (rc) return rc;
   // Ordinary loop: H = G_{k-1} P(F_{k-1}).
-  rc = poly_squaring(s, order, s->F, &c);
+  rc = poly_any(s, order, s->F, &c);
   if (rc) return rc;
   rc = apply_g(s, s->G[s->gcur], s->g_implicit, *c, s->H);
   if (rc) return rc;
@@ -542,12 +557,12 @@ int step_sri(ns_solver* s, int order) {
   const Mat* c = nullptr;
   if (!s->dns_started) {
     if (!s->g_implicit) return fail(NS_ESTATE, "the [sri] form must start from G_0");
-    if ((rc = poly_squaring(s, order, s->F, &c))) return rc;
+    if ((rc = poly_any(s, order, s->F, &c))) return rc;
     s->lcur = 0;
     scaled_identity(s, c, s->L[0]);                                 // Z_1 = G_0 P(F_0)
     s->dns_started = true;
   } else {
-    if ((rc = poly_squaring(s, order, s->Gam, &c))) return rc;
+    if ((rc = poly_any(s, order, s->Gam, &c))) return rc;
     Mat& Zc = s->L[s->lcur];
     Mat& Zn = s->L[s->lcur ^ 1];
     if ((rc = mm(s, Zn, &Zc, *c, &Zc, nullptr, 0.0, 1.0, false, K_APPLY))) return rc;
@@ -588,10 +603,10 @@ int step_gc(ns_solver* s, int order) {
     const int m = s->gc_m[i];
     if (m == 1) continue;
     if (!s->gc_started) {
-      if ((rc = poly_squaring(s, m, s->F, &c))) return rc;
+      if ((rc = poly_any(s, m, s->F, &c))) return rc;
       scaled_identity(s, c, *s->loopT[i][0]);
     } else {
-      if ((rc = poly_squaring(s, m, *s->loopG[i], &c))) return rc;
+      if ((rc = poly_any(s, m, *s->loopG[i], &c))) return rc;
       Mat& Tc = *s->loopT[i][s->tcur[i]];
       Mat& Tn = *s->loopT[i][s->tcur[i] ^ 1];
       if ((rc = mm(s, Tn, &Tc, *c, &Tc, nullptr, 0.0, 1.0, false, K_APPLY))) return rc;
@@ -602,7 +617,7 @@ int step_gc(ns_solver* s, int order) {
   // 2. ordinary loop H = G_{k-1} P_n(F_{k-1})
   const Mat* H;
   if (order >= 2) {
-    if ((rc = poly_squaring(s, order, s->F, &c))) return rc;
+    if ((rc = poly_any(s, order, s->F, &c))) return rc;
     if ((rc = apply_g(s, s->G[s->gcur], s->g_implicit, *c, s->H))) return rc;
     H = &s->H;
   } else {
@@ -726,20 +741,15 @@ int validate_step_args(ns_solver* s, int order, int fact, int p, int w) {
     case NS_FACT_SRI:
       if (!s->composite_capable)
         return fail(NS_EINVAL, "workspace was sized without the composite buffers");
-      if (!is_pow2(order)) return fail(NS_EINVAL, "[sri] form uses squaring sums: order = 2^s");
       return NS_OK;
     case NS_FACT_COMPOSITE_GENERAL:
       if (s->gc_w < 1) return fail(NS_ESTATE, "ns_set_composite_rates first");
       if (s->composite_capable < s->gc_w)
         return fail(NS_EINVAL, "workspace was sized for fewer composite loops");
-      if (order != 1 && !is_pow2(order))
-        return fail(NS_EINVAL, "composite form uses squaring sums: order = 1 or 2^s");
       return NS_OK;
     case NS_FACT_COMPOSITE_DOUBLE:
       if (!s->composite_capable)
         return fail(NS_EINVAL, "workspace was sized without the composite buffers");
-      if (!is_pow2(order))
-        return fail(NS_EINVAL, "composite form uses the squaring inner sums: order = 2^s");
       return NS_OK;
     default:
       return fail(NS_EINVAL, "unknown factorization %d", fact);
@@ -1189,8 +1199,8 @@ int ns_set_composite_rates(ns_solver* s, int w, const int* rates) {
     return fail(NS_EINVAL, "workspace was sized for %d composite loops", s->composite_capable);
   if (s->gc_started) return fail(NS_ESTATE, "rates are set before the first composite step");
   for (int i = 0; i < w; ++i)
-    if (rates[i] != 1 && !is_pow2(rates[i]))
-      return fail(NS_EINVAL, "loop orders must be 1 or 2^s (got %d)", rates[i]);
+    if (rates[i] < 1 || rates[i] > 64)
+      return fail(NS_EINVAL, "loop orders must be in 1..64 (got %d)", rates[i]);
   s->gc_w = w;
   for (int i = 0; i < kMaxLoops; ++i) s->gc_m[i] = i < w ? rates[i] : 0;
   return NS_OK;

@@ -199,6 +199,26 @@ def harmonic_gram(m: int, seed: int, ridge: float = 1e-6, noise_var: float = 0.0
     return SPDSystem(A=np.ascontiguousarray(a), b=b, seed=seed)
 
 
+def harmonic_three(samples: int = 30, omegas=(0.40, 0.43, 0.47), seed: int = 6) -> SPDSystem:
+    """Gram matrix of a harmonic regressor with three close frequencies
+    (``N = 6``), the shape of the paper's comparison problem (Section 7):
+    ``phi(t) = [cos w_i t, sin w_i t]_{i=1..3}``, ``t = 1..samples``,
+    ``A = sum_t phi phi^T``, noise-free ``y = phi^T theta_true`` with
+    ``theta_true ~ N(0, I)``, ``b = sum_t phi y``.  With the defaults
+    kappa(A) ~ 4e3."""
+    rng = np.random.default_rng(seed)
+    t = np.arange(1, samples + 1, dtype=np.float64)
+    phi = np.empty((t.size, 2 * len(omegas)))
+    for i, w in enumerate(omegas):
+        phi[:, 2 * i] = np.cos(w * t)
+        phi[:, 2 * i + 1] = np.sin(w * t)
+    theta_true = rng.standard_normal(phi.shape[1])
+    a = phi.T @ phi
+    a = 0.5 * (a + a.T)
+    b = phi.T @ (phi @ theta_true)
+    return SPDSystem(A=np.ascontiguousarray(a), b=b, seed=seed)
+
+
 def harmonic_batch(count: int, seed: int, m_lo: int = 8, m_hi: int = 128) -> list[SPDSystem]:
     """``count`` harmonic Gram systems, ``m ~ U{m_lo..m_hi}``, per-system seeds
     spawned from ``seed``."""

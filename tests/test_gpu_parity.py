@@ -639,7 +639,7 @@ def test_composite_general_errors(torch):
         s.set_composite_rates((2, 2, 2))            # three loops, workspace for two
     assert e.value.status == nsr.NS_EINVAL
     with pytest.raises(nsr.NSError):
-        s.set_composite_rates((3,))                 # not 1 or 2^s
+        s.set_composite_rates((0,))                 # below 1
     b = torch.ones(64, dtype=torch.float64, device="cuda")
     with pytest.raises(nsr.NSError) as e:
         s.solve(b, torch.zeros_like(b), order=4, form="composite_general")
@@ -648,3 +648,42 @@ def test_composite_general_errors(torch):
     p.bind(torch.eye(64, dtype=torch.float64, device="cuda"))
     with pytest.raises(nsr.NSError):
         p.solve(b, torch.zeros_like(b), order=4, form="sri")
+
+
+@pytest.mark.parametrize("order", [3, 5])
+def test_composite_horner_orders_match_oracle(torch, order):
+    """Composite loops of orders that are not powers of two (Horner sums):
+    double NS and [sri] against the oracle's Horner form."""
+    sysm = inputs.spd_qlq(140, 1e3, seed=order)
+    A, b = to_dev(torch, sysm.A), to_dev(torch, sysm.b)
+    s = nsr.Solver(140, composite=1)
+    s.bind(A)
+    for form, kw in (("composite_double", dict(composite=True)), ("sri", dict(sri=True))):
+        th = torch.zeros_like(b)
+        rep = s.solve(b, th, order=order, form=form, resid_tol=1e-13)
+        orc = oracle.solve(sysm.A, sysm.b, oracle.SolveOptions(order=order, form="horner",
+                                                               resid_tol=1e-13, **kw))
+        assert abs(rep.ns_steps - orc.ns_steps) <= 1, form
+        compare_traces(rep.fnorm_hist, orc.fnorm_hist)
+        assert rep.rel_resid <= 1e-13
+
+
+def test_three_frequency_analogue_matches_oracle(torch):
+    """Per-step parameters of the accelerated Richardson iteration (double NS
+    n = 3, q = 3) and of classical order-8 Newton-Schulz on the three-frequency
+    regressor, against the oracle (fixed step counts, no refinement)."""
+    sysm = inputs.harmonic_three()
+    A, b = to_dev(torch, sysm.A), to_dev(torch, sysm.b)
+    s = nsr.Solver(6, composite=1)
+    s.bind(A)
+    for k in range(1, 7):
+        for kw, okw in ((dict(order=3, form="composite_double", accel_q=3),
+                         dict(order=3, form="horner", composite=True, accel_q=3)),
+                        (dict(order=8, form="squaring"), dict(order=8))):
+            th = torch.zeros_like(b)
+            s.solve(b, th, k_max=k, floor_detect=False, refine_max=0, resid_tol=0.0,
+                    raise_on_error=False, **kw)
+            orc = oracle.solve(sysm.A, sysm.b, oracle.SolveOptions(
+                k_max=k, floor_detect=False, refine_max=0, resid_tol=0.0, **okw))
+            x = th.cpu().numpy()
+            assert np.linalg.norm(x - orc.theta) <= 1e-9 * np.linalg.norm(orc.theta), (k, kw)
