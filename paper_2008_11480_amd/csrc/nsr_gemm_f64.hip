@@ -150,7 +150,26 @@ gemm_f64_kernel(GemmF64Args p, int tiles_m, int tiles_n, int dp, int splits, int
   double2 xr[XV];
   double2 yr[YV];
 
+  // Tiles whose rows and columns lie inside the matrix load full slabs with
+  // unchecked 16-byte loads (a wave-uniform branch); edge tiles and the last,
+  // partial K slab take the checked path.
+  const bool interior = VEC && (m0 + BM <= M) && (n0 + BN <= N);
   auto load = [&](int64_t k0) {
+    if (interior && k0 + BK <= K) {
+#pragma unroll
+      for (int v = 0; v < XV; ++v) {
+        const int idx = tid + NT * v;
+        xr[v] = *reinterpret_cast<const double2*>(p.X + (m0 + idx / (BK / 2)) * p.ldx + k0 +
+                                                  (idx % (BK / 2)) * 2);
+      }
+#pragma unroll
+      for (int v = 0; v < YV; ++v) {
+        const int idx = tid + NT * v;
+        yr[v] = *reinterpret_cast<const double2*>(p.Y + (k0 + idx / (BN / 2)) * p.ldy + n0 +
+                                                  (idx % (BN / 2)) * 2);
+      }
+      return;
+    }
 #pragma unroll
     for (int v = 0; v < XV; ++v) {
       const int idx = tid + NT * v;

@@ -102,7 +102,25 @@ gemm_f32_nn_kernel(GemmLpArgs p, int tiles_m, int tiles_n) {
   const int64_t M = p.M, N = p.N, K = p.K;
   float4 xr[XV], yr[YV];
 
+  // Interior tiles load full slabs with unchecked 16-byte loads (wave-uniform
+  // branch); edge tiles and a partial last K slab take the checked path.
+  const bool interior = VEC && (m0 + BM <= M) && (n0 + BN <= N);
   auto load = [&](int64_t k0) {
+    if (interior && k0 + BK <= K) {
+#pragma unroll
+      for (int v = 0; v < XV; ++v) {
+        const int idx = tid + NT * v;
+        xr[v] = *reinterpret_cast<const float4*>(X + (m0 + idx / (BK / 4)) * p.ldx + k0 +
+                                                 (idx % (BK / 4)) * 4);
+      }
+#pragma unroll
+      for (int v = 0; v < YV; ++v) {
+        const int idx = tid + NT * v;
+        yr[v] = *reinterpret_cast<const float4*>(Y + (k0 + idx / (BN / 4)) * p.ldy + n0 +
+                                                 (idx % (BN / 4)) * 4);
+      }
+      return;
+    }
 #pragma unroll
     for (int v = 0; v < XV; ++v) {
       const int idx = tid + NT * v;
@@ -255,7 +273,25 @@ gemm_bf16_nt_kernel(GemmLpArgs p, int tiles_m, int tiles_n) {
       return val;
     }
   };
+  // Interior tiles load full slabs with unchecked 16-byte loads (wave-uniform
+  // branch); edge tiles and a partial last K slab take the checked path.
+  const bool interior = VEC && (m0 + BM <= M) && (n0 + BN <= N);
   auto load = [&](int64_t k0) {
+    if (interior && k0 + BK <= K) {
+#pragma unroll
+      for (int v = 0; v < XV; ++v) {
+        const int idx = tid + NT * v;
+        xr[v] = *reinterpret_cast<const uint4*>(X + (m0 + idx / (BK / 8)) * p.ldx + k0 +
+                                                (idx % (BK / 8)) * 8);
+      }
+#pragma unroll
+      for (int v = 0; v < YV; ++v) {
+        const int idx = tid + NT * v;
+        yr[v] = *reinterpret_cast<const uint4*>(Y + (n0 + idx / (BK / 8)) * p.ldy + k0 +
+                                                (idx % (BK / 8)) * 8);
+      }
+      return;
+    }
 #pragma unroll
     for (int v = 0; v < XV; ++v) xr[v] = load_one(X, p.ldx, m0, M, k0, v);
 #pragma unroll
