@@ -26,6 +26,13 @@
 // XCD-aware grouped tile order, two workgroups per CU.
 #include "nsr_internal.h"
 
+#ifndef NSR_BF16_HUGE
+#define NSR_BF16_HUGE 1
+#endif
+#ifndef NSR_BF16_HUGE_BK
+#define NSR_BF16_HUGE_BK 64
+#endif
+
 namespace nsr {
 
 typedef float f32x4 __attribute__((ext_vector_type(4)));
@@ -63,6 +70,7 @@ __device__ __forceinline__ void put(const GemmLpArgs& p, int64_t row, int64_t co
   ss += (double)v * (double)v;
 }
 
+template <int NWAVES = 4>
 __device__ __forceinline__ void write_partial(const GemmLpArgs& p, double ss, double* red,
                                               int tm, int tn, int tiles_n) {
   if (!p.partial) return;
@@ -71,7 +79,12 @@ __device__ __forceinline__ void write_partial(const GemmLpArgs& p, double ss, do
   for (int off = 32; off > 0; off >>= 1) ss += __shfl_xor(ss, off, 64);
   if (lane == 0) red[wave] = ss;
   __syncthreads();
-  if (threadIdx.x == 0) p.partial[(int64_t)tm * tiles_n + tn] = (red[0] + red[1]) + (red[2] + red[3]);
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+#pragma unroll
+    for (int w = 0; w < NWAVES; ++w) t += red[w];
+    p.partial[(int64_t)tm * tiles_n + tn] = t;
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -224,24 +237,26 @@ gemm_f32_nn_kernel(GemmLpArgs p, int tiles_m, int tiles_n) {
 // ---------------------------------------------------------------------------
 // bf16, NT: D = X Y^T, X: m x k, Y: n x k (both row-major, K contiguous)
 // ---------------------------------------------------------------------------
-template <int BM, int BN, int BK, bool VEC>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
+// WGM x WGN waves per workgroup, each owning a (BM / WGM) x (BN / WGN) block.
+template <int BM, int BN, int BK, bool VEC, int WGM = 2, int WGN = 2>
+__global__ void __launch_bounds__(64 * WGM * WGN) __attribute__((amdgpu_waves_per_eu(2)))
 gemm_bf16_nt_kernel(GemmLpArgs p, int tiles_m, int tiles_n) {
-  constexpr int NT = 256;
-  constexpr int WTM = BM / 2, WTN = BN / 2;
+  constexpr int NT = 64 * WGM * WGN;
+  constexpr int WTM = BM / WGM, WTN = BN / WGN;
   constexpr int FM = WTM / 32, FN = WTN / 32;
   constexpr int S = BK + 8;                  // LDS row stride (bf16), 16-B aligned rows
   constexpr int XV = (BM * BK / 8) / NT;     // 16-byte vectors per thread
   constexpr int YV = (BN * BK / 8) / NT;
   static_assert(XV >= 1 && YV >= 1, "tile too small");
+  static_assert(XV * NT == BM * BK / 8 && YV * NT == BN * BK / 8, "slab / thread mismatch");
   __shared__ __attribute__((aligned(16))) __bf16 Xs[2][BM * S];
   __shared__ __attribute__((aligned(16))) __bf16 Ys[2][BN * S];
-  __shared__ double red[4];
+  __shared__ double red[WGM * WGN];
 
   const __bf16* X = static_cast<const __bf16*>(p.X);
   const __bf16* Y = static_cast<const __bf16*>(p.Y);
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int wm = wave >> 1, wn = wave & 1;
+  const int wm = wave / WGN, wn = wave % WGN;
   int tm, tn;
   map_tile_lp(blockIdx.x, tiles_m, tiles_n, tm, tn);
   const int64_t m0 = (int64_t)tm * BM, n0 = (int64_t)tn * BN;
@@ -355,7 +370,7 @@ gemm_bf16_nt_kernel(GemmLpArgs p, int tiles_m, int tiles_n) {
         if (row < M && col < N) put(p, row, col, acc[i][j][r], ss);
       }
     }
-  write_partial(p, ss, red, tm, tn, tiles_n);
+  write_partial<WGM * WGN>(p, ss, red, tm, tn, tiles_n);
 }
 
 bool big_tiles(int64_t m, int64_t n) { return ((m + 127) / 128) * ((n + 127) / 128) >= 256; }
@@ -392,11 +407,22 @@ int64_t launch_gemm_bf16_nt(const GemmLpArgs& a, hipStream_t st) {
   const bool vec = ((a.ldx & 7) == 0) && ((a.ldy & 7) == 0) &&
                    ((reinterpret_cast<uintptr_t>(a.X) & 15) == 0) &&
                    ((reinterpret_cast<uintptr_t>(a.Y) & 15) == 0);
+  const bool huge = NSR_BF16_HUGE && ((a.M + 255) / 256) * ((a.N + 255) / 256) >= 256;
   const bool big = big_tiles(a.M, a.N);
-  const int bm = big ? 128 : 64;
+  const int bm = huge ? 256 : (big ? 128 : 64);
   const int tiles_m = (int)((a.M + bm - 1) / bm), tiles_n = (int)((a.N + bm - 1) / bm);
   dim3 grid((unsigned)((int64_t)tiles_m * tiles_n)), block(256);
-  if (big) {
+  if (huge) {
+    // 256 x 256 tiles, eight waves of 128 x 64: a quarter of the L2 -> LDS
+    // bytes per flop of the 128 x 128 tile, which saturates the L2.
+    dim3 block8(512);
+    if (vec)
+      hipLaunchKernelGGL((gemm_bf16_nt_kernel<256, 256, NSR_BF16_HUGE_BK, true, 2, 4>), grid,
+                         block8, 0, st, a, tiles_m, tiles_n);
+    else
+      hipLaunchKernelGGL((gemm_bf16_nt_kernel<256, 256, NSR_BF16_HUGE_BK, false, 2, 4>), grid,
+                         block8, 0, st, a, tiles_m, tiles_n);
+  } else if (big) {
     if (vec) hipLaunchKernelGGL((gemm_bf16_nt_kernel<128, 128, 64, true>), grid, block, 0, st, a, tiles_m, tiles_n);
     else hipLaunchKernelGGL((gemm_bf16_nt_kernel<128, 128, 64, false>), grid, block, 0, st, a, tiles_m, tiles_n);
   } else {

@@ -64,7 +64,7 @@ def test_gemm_f32_elementwise(torch, m, n, k):
     assert abs(float(ss.cpu()) - ssr) <= 1e-12 * ssr
 
 
-@pytest.mark.parametrize("m,n,k", SHAPES + [(64, 64, 40), (70, 50, 9)])
+@pytest.mark.parametrize("m,n,k", SHAPES + [(64, 64, 40), (70, 50, 9), (4100, 4000, 200)])
 def test_gemm_bf16_nt_elementwise(torch, m, n, k):
     g = torch.Generator(device="cpu").manual_seed(m * 17 + n * 5 + k)
     X = torch.randn(m, k, generator=g).to(torch.bfloat16)
