@@ -250,6 +250,43 @@ def run_fig4_analogue(torch, nsr, steps=7):
             "kappa": float(np.linalg.cond(sysm.A)), "param_rel_error": rows}
 
 
+def run_small_fixed(torch, nsr, reps=300):
+    """The N = 64, kappa = 100 workload (order-4 squaring, exactly 12 coupled
+    steps, refinement to 1e-13), float64: eager launches versus the captured
+    graph of the 12 steps (same kernels, bit-identical results)."""
+    w = inputs.WORKLOADS["spd64_k1e2_o4"]
+    sysm = inputs.spd_qlq(w["n"], w["kappa"], w["seed"])
+    A = torch.from_numpy(sysm.A).to("cuda")
+    b = torch.from_numpy(sysm.b).to("cuda")
+    s = nsr.Solver(w["n"], composite=0)
+    s.bind(A)
+    kw = dict(order=w["order"], form="squaring", k_max=w["k_max"], floor_detect=False,
+              resid_tol=w["resid_tol"])
+    out = {"workload": "spd64_k1e2_o4", "n": w["n"], "steps": w["k_max"]}
+    ref = None
+    for mode in ("eager", "graph"):
+        th = torch.zeros_like(b)
+        for _ in range(5):
+            rep = s.solve(b, th, graph=(mode == "graph"), **kw)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            rep = s.solve(b, th, graph=(mode == "graph"), **kw)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / reps
+        x = th.cpu().numpy()
+        if ref is None:
+            ref = x
+        out[mode] = {"us_per_solve": dt * 1e6, "solves_per_s": 1.0 / dt,
+                     "rel_resid": float(np.linalg.norm(sysm.b - sysm.A @ x)
+                                        / np.linalg.norm(sysm.b)),
+                     "refine_steps": rep.refine_steps, "identical_to_eager": bool(
+                         np.array_equal(x, ref))}
+        log(f"N=64 fixed 12 steps, {mode}: {dt * 1e6:.0f} us/solve")
+    s.close()
+    return out
+
+
 def timeline_summary(tl, ns, groups):
     """Critical-path view of a batch from the device timeline (ms)."""
     f32 = tl[:, 1] - tl[:, 0]
@@ -389,6 +426,8 @@ def main():
     ap.add_argument("--no-composite", action="store_true", help="skip the N=8192 legs")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched leg")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving leg")
+    ap.add_argument("--no-small", action="store_true",
+                    help="skip the N=64 fixed-step leg (eager versus captured graph)")
     ap.add_argument("--no-comparisons", action="store_true",
                     help="skip the Newton-Schulz variant comparison and the three-frequency "
                          "analogue")
@@ -510,6 +549,8 @@ def main():
                 f"rel_resid={t.rel_resid:.2e}")
     del solver
     torch.cuda.empty_cache()
+    if not args.no_small and not fixed:
+        out["small_fixed"] = run_small_fixed(torch, nsr)
     if not args.no_comparisons and not fixed:
         out["comparisons"] = {"workload": args.workload, "precision": "fp64",
                               "variants": run_comparisons(torch, nsr, A, b, sysm, n,

@@ -220,6 +220,14 @@ typedef struct {
                          and table forms only.                               */
   int init_p, init_w; /* its factorization, h = init_w (init_p + 1); both 0:
                          init_p = h - 1, init_w = 1                           */
+  int graph;          /* 1: when the Newton-Schulz phase has a fixed length
+                         (floor_detect = 0, f_tol <= 0, no accelerator, a
+                         classical or table form, no initial series, timing
+                         off), enqueue its k_max steps with their Richardson
+                         updates without host round trips, captured once into
+                         a HIP graph and replayed on later solves with the same
+                         operands and options; the history is recorded on the
+                         device and read once.  Otherwise ignored.          */
 } ns_solve_opts;
 
 #define NS_HIST_F 65

@@ -145,6 +145,16 @@ add_kernel(const T* X, const T* Y, T* D, uint16_t* Db, int64_t ld, int64_t n) {
   if (Db) Db[i] = __builtin_bit_cast(uint16_t, (__bf16)(float)v);
 }
 
+// hist_f[k] = scal[1] (||F_k||_F), hist_r[k - 1] = scal[2] (||r||_2): the
+// per-step history of a captured iteration, read back once at the end.
+__global__ void record_kernel(const double* __restrict__ scal, double* __restrict__ hist_f,
+                              double* __restrict__ hist_r, int k) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    hist_f[k] = scal[1];
+    hist_r[k - 1] = scal[2];
+  }
+}
+
 // sdiag[i] = A_ii; neg[i] = -A_ii (a max-reduction of neg gives -min A_ii).
 __global__ void __launch_bounds__(kThreads)
 diag_kernel(const double* __restrict__ A, int64_t lda, int64_t n, double* __restrict__ sdiag,
@@ -291,6 +301,10 @@ template void launch_scaled_identity_plus<double>(const double*, int64_t, int64_
                                                   const double*, double*, int64_t, hipStream_t);
 template void launch_scaled_identity_plus<float>(const float*, int64_t, int64_t, const double*,
                                                  const double*, float*, int64_t, hipStream_t);
+
+void launch_record(const double* scal, double* hist_f, double* hist_r, int k, hipStream_t st) {
+  hipLaunchKernelGGL(record_kernel, dim3(1), dim3(64), 0, st, scal, hist_f, hist_r, k);
+}
 
 void launch_diag(const double* A, int64_t lda, int64_t n, double* sdiag, double* neg,
                  hipStream_t st) {

@@ -85,6 +85,9 @@ template <typename T>
 void launch_scaled_identity_plus(const T* C, int64_t ldc, int64_t n, const double* alpha,
                                  const double* sdiag, T* G, int64_t ldg, hipStream_t st);
 
+// hist_f[k] = scal[1], hist_r[k - 1] = scal[2] (one thread).
+void launch_record(const double* scal, double* hist_f, double* hist_r, int k, hipStream_t st);
+
 // sdiag[i] = A_ii, neg[i] = -A_ii.
 void launch_diag(const double* A, int64_t lda, int64_t n, double* sdiag, double* neg,
                  hipStream_t st);

@@ -98,6 +98,7 @@ size_t layout_bytes(int64_t n, int precision, int composite) {
   bytes += 5 * align_up((size_t)n * sizeof(double), kAlign);                 // r, t, w0, w1, S
   bytes += align_up((size_t)partial_capacity(n) * sizeof(double), kAlign);   // partials
   bytes += align_up(16 * sizeof(double), kAlign);                            // scalars
+  bytes += align_up((NS_HIST_F + NS_HIST_R) * sizeof(double), kAlign);       // device history
   if (precision == NS_PREC_FP64) bytes += align_up(split_bytes(n), kAlign);  // split-K scratch
   return bytes;
 }
@@ -143,6 +144,26 @@ struct ns_solver {
   double* vw[2] = {nullptr, nullptr};
   double* partial = nullptr;
   double* scal = nullptr;  // [0] alpha, [1] ||F||_F, [2] ||r||_2, [3] ||b||_2, [4] -min A_ii
+  double* dhist = nullptr; // device history of a captured iteration: ||F_k||, then ||r||
+  // Captured fixed-length Newton-Schulz phase (opts.graph): the executable
+  // graph, the key it was captured for and the host state after it.
+  hipGraphExec_t graph_exec = nullptr;
+  struct GraphKey {
+    int order, fact, p, w, k, precision, symmetric, diag_scale;
+    const double *A, *b;
+    double* theta;
+    int64_t lda;
+    bool operator==(const GraphKey& o) const {
+      return order == o.order && fact == o.fact && p == o.p && w == o.w && k == o.k &&
+             precision == o.precision && symmetric == o.symmetric &&
+             diag_scale == o.diag_scale && A == o.A && b == o.b && theta == o.theta &&
+             lda == o.lda;
+    }
+  } graph_key{};
+  hipStream_t capture_stream = nullptr;
+  int graph_gcur = 0;
+  int64_t graph_mmm = 0;
+  double graph_flop = 0.0;
   double* sdiag = nullptr; // S = diag(A) (NS_SCALE_DIAG)
   bool diag_scale = false; // G_0 = diag(A)^-1 instead of I / alpha
   double* sk = nullptr;    // split-K scratch of the float64 GEMM
@@ -717,6 +738,72 @@ int richardson_once(ns_solver* s, const double* b, double* theta) {
   return NS_OK;
 }
 
+// The fixed-length Newton-Schulz phase: k_max steps, each followed by the
+// Richardson update with the new G and a device-side record of ||F_k|| and
+// ||r||.  No host decision depends on a device value, so the sequence is
+// captured once into a HIP graph (per operands and options) and replayed; the
+// host-side state the steps leave behind is saved with it.
+int enqueue_fixed(ns_solver* s, const ns_solve_opts* o, const double* b, double* theta) {
+  for (int k = 1; k <= o->k_max; ++k) {
+    if (int rc = any_step(s, o->order, o->factorization, o->p, o->w)) return rc;
+    richardson_once(s, b, theta);
+    launch_record(s->scal, s->dhist, s->dhist + NS_HIST_F, k, s->stream);
+  }
+  return NS_OK;
+}
+
+int run_fixed_graph(ns_solver* s, const ns_solve_opts* o, const double* b, double* theta) {
+  ns_solver::GraphKey key{o->order, o->factorization, o->p, o->w, o->k_max, s->precision,
+                          s->symmetric ? 1 : 0, s->diag_scale ? 1 : 0, s->A, b, theta, s->lda};
+  if (!s->graph_exec || !(key == s->graph_key)) {
+    if (s->graph_exec) {
+      (void)hipGraphExecDestroy(s->graph_exec);
+      s->graph_exec = nullptr;
+    }
+    const int64_t mmm0 = s->mmm;
+    const double flop0 = s->flop;
+    // Capture on a private stream (the caller's may be the null stream, which
+    // cannot be captured); the graph is launched on the caller's stream.
+    if (!s->capture_stream)
+      HIP_TRY(hipStreamCreateWithFlags(&s->capture_stream, hipStreamNonBlocking));
+    hipStream_t user = s->stream;
+    s->stream = s->capture_stream;
+    hipError_t eb = hipStreamBeginCapture(s->stream, hipStreamCaptureModeThreadLocal);
+    if (eb != hipSuccess) {
+      s->stream = user;
+      return fail(NS_EHIP, "hipStreamBeginCapture failed: %s", hipGetErrorString(eb));
+    }
+    int rc = enqueue_fixed(s, o, b, theta);
+    hipGraph_t g = nullptr;
+    const hipError_t ec = hipStreamEndCapture(s->stream, &g);
+    s->stream = user;
+    if (rc) {
+      if (g) (void)hipGraphDestroy(g);
+      return rc;
+    }
+    if (ec != hipSuccess || !g) return fail(NS_EHIP, "graph capture failed: %s", hipGetErrorString(ec));
+    const hipError_t ei = hipGraphInstantiate(&s->graph_exec, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (ei != hipSuccess) {
+      s->graph_exec = nullptr;
+      return fail(NS_EHIP, "graph instantiation failed: %s", hipGetErrorString(ei));
+    }
+    s->graph_key = key;
+    s->graph_gcur = s->gcur;
+    s->graph_mmm = s->mmm - mmm0;
+    s->graph_flop = s->flop - flop0;
+  } else {
+    // Replay: put the host-side state where the captured steps leave it.
+    s->gcur = s->graph_gcur;
+    s->g_implicit = false;
+    s->p0_is_f2 = false;
+    s->mmm += s->graph_mmm;
+    s->flop += s->graph_flop;
+  }
+  HIP_TRY(hipGraphLaunch(s->graph_exec, s->stream));
+  return NS_OK;
+}
+
 int validate_step_args(ns_solver* s, int order, int fact, int p, int w) {
   if (order < (fact == NS_FACT_COMPOSITE_GENERAL ? 1 : 2))
     return fail(NS_EINVAL, "order must be >= 2 (got %d)", order);
@@ -864,6 +951,8 @@ int ns_create(int device, void* hip_stream, int64_t n, int precision, void* work
   s->partial =
       reinterpret_cast<double*>(take(align_up((size_t)partial_capacity(n) * sizeof(double), kAlign)));
   s->scal = reinterpret_cast<double*>(take(align_up(16 * sizeof(double), kAlign)));
+  s->dhist = reinterpret_cast<double*>(
+      take(align_up((NS_HIST_F + NS_HIST_R) * sizeof(double), kAlign)));
   if (precision == NS_PREC_FP64) {
     const size_t skb = split_bytes(n);
     if (skb > 0) {
@@ -881,6 +970,8 @@ int ns_create(int device, void* hip_stream, int64_t n, int precision, void* work
 
 int ns_destroy(ns_solver* s) {
   if (!s) return NS_OK;
+  if (s->graph_exec) (void)hipGraphExecDestroy(s->graph_exec);
+  if (s->capture_stream) (void)hipStreamDestroy(s->capture_stream);
   for (hipEvent_t e : s->pool) (void)hipEventDestroy(e);
   delete s;
   return NS_OK;
@@ -1090,6 +1181,28 @@ int richardson_ns_solve(ns_solver* s, const double* b, double* theta, const ns_s
   if (!isfinite(f0)) ns_stop = NS_STOP_DIVERGED;
   int k = 0;
   double host[2];
+  const bool fixed_len = o->graph && !o->floor_detect && !(o->f_tol > 0.0) && q == 0 &&
+                         h == 1 && !s->timing &&
+                         (o->factorization == NS_FACT_HORNER ||
+                          o->factorization == NS_FACT_SQUARING ||
+                          o->factorization == NS_FACT_TABLE ||
+                          o->factorization == NS_FACT_UNIFIED ||
+                          o->factorization == NS_FACT_UNIFIED_PLUS1);
+  if (fixed_len && ns_stop == NS_STOP_NONE) {
+    if (int rc = run_fixed_graph(s, o, b, theta)) return rc;
+    k = o->k_max;
+    std::vector<double> hh(NS_HIST_F + NS_HIST_R);
+    HIP_TRY(hipMemcpyAsync(hh.data(), s->dhist, hh.size() * sizeof(double),
+                           hipMemcpyDeviceToHost, s->stream));
+    HIP_TRY(hipStreamSynchronize(s->stream));
+    for (int j = 1; j <= k; ++j) {
+      R->fnorm_hist[R->n_fnorm++] = hh[j];
+      if (R->n_resid < NS_HIST_R) R->resid_hist[R->n_resid++] = hh[NS_HIST_F + j - 1] / bnorm;
+    }
+    ns_stop = NS_STOP_K_MAX;
+    for (int j = 1; j <= k; ++j)
+      if (!isfinite(hh[j]) || hh[j] > f0) ns_stop = NS_STOP_DIVERGED;
+  }
   while (ns_stop == NS_STOP_NONE) {
     ++k;
     int rc = any_step(s, o->order, o->factorization, o->p, o->w);

@@ -60,7 +60,7 @@ class SolveOpts(ctypes.Structure):
         ("floor_detect", ctypes.c_int), ("scale", ctypes.c_int), ("eps", ctypes.c_double),
         ("f_tol", ctypes.c_double), ("resid_tol", ctypes.c_double), ("theta0_mode", ctypes.c_int),
         ("accel_q", ctypes.c_int), ("init_order", ctypes.c_int), ("init_p", ctypes.c_int),
-        ("init_w", ctypes.c_int),
+        ("init_w", ctypes.c_int), ("graph", ctypes.c_int),
     ]
 
 
@@ -270,14 +270,15 @@ class Solver:
               k_max: int = 64, refine_max: int = 64, floor_detect: bool = True,
               scale: int = SCALE_FROBENIUS, eps: float = 0.0, f_tol: float = 0.0,
               resid_tol: float = 1e-12, theta0_mode: int = 0, accel_q: int = 0,
-              init_order: int = 0, init_p: int = 0, init_w: int = 0,
+              init_order: int = 0, init_p: int = 0, init_w: int = 0, graph: bool = False,
               raise_on_error: bool = True):
         _require_cuda_f64(b, "b")
         _require_cuda_f64(theta, "theta")
         o = SolveOpts(order=order, factorization=FACT[form], p=p, w=w, k_max=k_max,
                       refine_max=refine_max, floor_detect=1 if floor_detect else 0, scale=scale,
                       eps=eps, f_tol=f_tol, resid_tol=resid_tol, theta0_mode=theta0_mode,
-                      accel_q=accel_q, init_order=init_order, init_p=init_p, init_w=init_w)
+                      accel_q=accel_q, init_order=init_order, init_p=init_p, init_w=init_w,
+                      graph=1 if graph else 0)
         rep = SolveReportC()
         st = lib().richardson_ns_solve(self._h, _ptr(b), _ptr(theta), ctypes.byref(o),
                                        ctypes.byref(rep))

@@ -687,3 +687,69 @@ def test_three_frequency_analogue_matches_oracle(torch):
                 k_max=k, floor_detect=False, refine_max=0, resid_tol=0.0, **okw))
             x = th.cpu().numpy()
             assert np.linalg.norm(x - orc.theta) <= 1e-9 * np.linalg.norm(orc.theta), (k, kw)
+
+
+# --------------------------------------------------------------------------
+# Captured fixed-length iteration (HIP graph)
+# --------------------------------------------------------------------------
+
+GRAPH_CASES = [
+    # precision, n, kappa, order, form, k_max
+    (nsr.PREC_FP64, 64, 1e2, 4, "squaring", 12),      # the N = 64, 12-step workload
+    (nsr.PREC_FP64, 300, 1e3, 8, "squaring", 6),
+    (nsr.PREC_FP64, 257, 1e3, 11, "table", 5),
+    (nsr.PREC_MIXED_BF16, 300, 1e3, 8, "squaring", 6),
+    (nsr.PREC_FP32, 200, 1e2, 6, "unified", 5),
+]
+
+
+@pytest.mark.parametrize("prec,n,kappa,order,form,kmax", GRAPH_CASES)
+def test_graph_fixed_length_matches_eager(torch, prec, n, kappa, order, form, kmax):
+    """The captured Newton-Schulz phase runs the same kernels in the same order
+    as the eager loop: theta and the ||F_k|| / residual histories are
+    bit-identical, on the first (capturing) solve and on every replay, with
+    eager work and synchronisations between the replays."""
+    sysm = inputs.spd_qlq(n, kappa, seed=n + order)
+    A, b = to_dev(torch, sysm.A), to_dev(torch, sysm.b)
+    p, w = (2, 2) if form == "unified" else (0, 0)
+    kw = dict(order=order, form=form, p=p, w=w, k_max=kmax, floor_detect=False,
+              resid_tol=1e-13 if prec == nsr.PREC_FP64 else 1e-10, refine_max=100)
+    s = nsr.Solver(n, precision=prec, composite=0)
+    s.bind(A)
+    th_e = torch.zeros_like(b)
+    rep_e = s.solve(b, th_e, **kw)
+    ref = th_e.cpu().numpy()
+    th_g = torch.zeros_like(b)
+    other = nsr.Solver(n, precision=prec, composite=0)
+    other.bind(A)
+    for rep_i in range(4):
+        th_g.zero_()
+        rep_g = s.solve(b, th_g, graph=True, **kw)
+        torch.cuda.synchronize()
+        assert np.array_equal(th_g.cpu().numpy(), ref), rep_i
+        assert rep_g.fnorm_hist == rep_e.fnorm_hist, rep_i
+        assert rep_g.resid_hist == rep_e.resid_hist, rep_i
+        assert rep_g.ns_steps == kmax and rep_g.ns_stop == "k_max"
+        assert rep_g.mmm == rep_e.mmm and rep_g.gemm_flop == rep_e.gemm_flop
+        # eager work in between (another solver on the same stream) and a sync
+        other.solve(b, torch.zeros_like(b), **kw)
+        torch.cuda.synchronize()
+    # a different theta buffer: the graph is captured again for it
+    th2 = torch.zeros_like(b)
+    s.solve(b, th2, graph=True, **kw)
+    torch.cuda.synchronize()
+    assert np.array_equal(th2.cpu().numpy(), ref)
+
+
+def test_graph_ignored_for_adaptive_schedules(torch):
+    """With the floor test on, the schedule depends on device values: the
+    graph flag is ignored and the solve equals the eager one."""
+    sysm = inputs.spd_qlq(128, 1e3, seed=5)
+    A, b = to_dev(torch, sysm.A), to_dev(torch, sysm.b)
+    s = nsr.Solver(128, composite=0)
+    s.bind(A)
+    t1, t2 = torch.zeros_like(b), torch.zeros_like(b)
+    r1 = s.solve(b, t1, order=8, resid_tol=1e-13)
+    r2 = s.solve(b, t2, order=8, resid_tol=1e-13, graph=True)
+    assert np.array_equal(t1.cpu().numpy(), t2.cpu().numpy())
+    assert r1.fnorm_hist == r2.fnorm_hist
