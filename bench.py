@@ -284,6 +284,37 @@ def run_small_fixed(torch, nsr, reps=300):
                          np.array_equal(x, ref))}
         log(f"N=64 fixed 12 steps, {mode}: {dt * 1e6:.0f} us/solve")
     s.close()
+    # The same workload for 4096 independent seeds in one float64 batch
+    # (persistent kernel, every solve on one workgroup, no host round trips).
+    count = 4096
+    systems = [inputs.spd_qlq(w["n"], w["kappa"], 1000 + i) for i in range(count)]
+    As = [torch.from_numpy(x.A).to("cuda") for x in systems]
+    bs = [torch.from_numpy(x.b).to("cuda") for x in systems]
+    ths = [torch.zeros_like(v) for v in bs]
+    B = nsr.Batch(max_n=w["n"], max_count=count,
+                  slots=min(count, 8 * torch.cuda.get_device_properties(0).multi_processor_count),
+                  precision=nsr.PREC_FP64)
+    bopts = dict(order=w["order"], k_max=w["k_max"], floor_detect=False,
+                 resid_tol=w["resid_tol"], refine_max=20)
+    waves, groups, _ = B.autotune(As, bs, ths, **bopts)
+    times = []
+    for i in range(4):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        reps = B.poll(B.submit(As, bs, ths, **bopts), wait=True)
+        if i:
+            times.append(time.perf_counter() - t0)
+    mk = float(np.median(times))
+    rel = max(float(np.linalg.norm(x.b - x.A @ t.cpu().numpy()) / np.linalg.norm(x.b))
+              for x, t in zip(systems[:64], ths[:64]))
+    flop = sum(r.gemm_flop for r in reps)
+    out["batch4096_fp64"] = {
+        "count": count, "launch": {"waves_per_group": waves, "groups": groups},
+        "makespan_ms": mk * 1e3, "solves_per_s": count / mk, "us_per_solve": mk / count * 1e6,
+        "alg_tflops": flop / mk / 1e12,
+        "ok": sum(1 for r in reps if r.status == nsr.NS_OK), "rel_resid_max_first64": rel,
+        "ns_steps": int(reps[0].ns_steps)}
+    log(f"N=64 x 4096 float64 batch: {mk * 1e3:.1f} ms ({count / mk:.0f} solves/s)")
     return out
 
 
