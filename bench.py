@@ -422,11 +422,14 @@ def run_serving(torch, nsr, duration_s=3.0, rate=2000.0):
     log(f"generating {len(trace)} serving requests on the GPU")
     reqs = make_requests(trace)
     torch.cuda.synchronize()
-    ex = GpuExecutor(workers=6, precision=nsr.PREC_MIXED_BF16)
+    # N <= 128 requests go to the batched kernel (one workgroup per system is
+    # fast there); larger ones to 12 worker threads with their own streams.
+    workers, small = 12, 128
+    ex = GpuExecutor(workers=workers, precision=nsr.PREC_MIXED_BF16, small_max_n=small)
     # warm up the kernels and the allocator on a few requests of each path
     warm = make_requests(inputs.serving_trace(rate, 0.02, seed=55))
-    Server(ex, budget_bytes=32 << 30, workers=6).run(warm)
-    srv = Server(ex, budget_bytes=32 << 30, workers=6)
+    Server(ex, budget_bytes=32 << 30, workers=workers, small_max_n=small).run(warm)
+    srv = Server(ex, budget_bytes=32 << 30, workers=workers, small_max_n=small)
     log("serving")
     st = srv.run(reqs)
     torch.cuda.synchronize()
