@@ -377,11 +377,28 @@ gemm_f64_split_fixup(GemmF64Args p, int tiles_m, int tiles_n, int dp, int splits
   const int64_t M = p.M, N = p.N;
   const bool diag_tile = SYM && (tm == tn);
   const double* src = p.sk + (size_t)jt * splits * TS + ((wave * FM + i) * FN + jj) * 256 + lane;
+  // Sum the K-slices in slice order (fixed, deterministic); four rows and
+  // four slices per iteration keep 16 loads in flight.
+  double acc4[4] = {0.0, 0.0, 0.0, 0.0};
+  int q = 0;
+  for (; q + 4 <= splits; q += 4) {
+    double v[4][4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) v[u][r] = src[(size_t)(q + u) * TS + r * 64];
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) acc4[r] += v[u][r];
+  }
+  for (; q < splits; ++q)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) acc4[r] += src[(size_t)q * TS + r * 64];
   double ss = 0.0;
 #pragma unroll
   for (int r = 0; r < 4; ++r) {
-    double a = 0.0;
-    for (int q = 0; q < splits; ++q) a += src[(size_t)q * TS + r * 64];
+    const double a = acc4[r];
     const int64_t row = m0 + wm * WTM + i * 16 + lk + 4 * r;
     const int64_t col = n0 + wn * WTN + jj * 16 + lr;
     if (row < M && col < N) {
