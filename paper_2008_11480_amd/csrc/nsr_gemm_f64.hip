@@ -39,6 +39,10 @@
 #ifndef NSR_F64_WAVES_PER_EU
 #define NSR_F64_WAVES_PER_EU 2
 #endif
+// 1: raise the wave's issue priority while it runs the slab's MFMAs.
+#ifndef NSR_F64_SETPRIO
+#define NSR_F64_SETPRIO 1
+#endif
 // Row padding (doubles) of the X and Y slabs in LDS.
 #ifndef NSR_F64_XPAD
 #define NSR_F64_XPAD 2
@@ -259,6 +263,7 @@ gemm_f64_kernel(GemmF64Args p, int tiles_m, int tiles_n, int dp, int splits, int
     if (kt + 1 < kt1) load((int64_t)(kt + 1) * BK);
     const double* xs = &Xs[buf][(wm * WTM + lr) * XS + lk];
     const double* ys = &Ys[buf][lk * YS + wn * WTN + lr];
+    if (NSR_F64_SETPRIO) __builtin_amdgcn_s_setprio(1);
 #pragma unroll
     for (int ks = 0; ks < BK; ks += 4) {
       double a[FM], b[FN];
@@ -272,6 +277,7 @@ gemm_f64_kernel(GemmF64Args p, int tiles_m, int tiles_n, int dp, int splits, int
         for (int j = 0; j < FN; ++j)
           acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
     }
+    if (NSR_F64_SETPRIO) __builtin_amdgcn_s_setprio(0);
   }
 
   if (tail) {

@@ -29,6 +29,10 @@
 #ifndef NSR_BF16_HUGE
 #define NSR_BF16_HUGE 1
 #endif
+// 1: raise the wave's issue priority while it runs a slab's MFMAs.
+#ifndef NSR_LP_SETPRIO
+#define NSR_LP_SETPRIO 1
+#endif
 #ifndef NSR_BF16_HUGE_BK
 #define NSR_BF16_HUGE_BK 64
 #endif
@@ -204,6 +208,7 @@ gemm_f32_nn_kernel(GemmLpArgs p, int tiles_m, int tiles_n) {
     if (kt + 1 < nk) load((int64_t)(kt + 1) * BK);
     const float* xs = &Xs[buf][(wm * WTM + lr) * XS + lk];
     const float* ys = &Ys[buf][lk * YS + wn * WTN + lr];
+    if (NSR_LP_SETPRIO) __builtin_amdgcn_s_setprio(1);
 #pragma unroll
     for (int ks = 0; ks < BK; ks += 4) {
       float a[FM], b[FN];
@@ -217,6 +222,7 @@ gemm_f32_nn_kernel(GemmLpArgs p, int tiles_m, int tiles_n) {
         for (int j = 0; j < FN; ++j)
           acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i], b[j], acc[i][j], 0, 0, 0);
     }
+    if (NSR_LP_SETPRIO) __builtin_amdgcn_s_setprio(0);
   }
 
   double ss = 0.0;
@@ -343,6 +349,7 @@ gemm_bf16_nt_kernel(GemmLpArgs p, int tiles_m, int tiles_n) {
     if (kt + 1 < nk) load((int64_t)(kt + 1) * BK);
     const __bf16* xs = &Xs[buf][(wm * WTM + lr) * S + 8 * lk];
     const __bf16* ys = &Ys[buf][(wn * WTN + lr) * S + 8 * lk];
+    if (NSR_LP_SETPRIO) __builtin_amdgcn_s_setprio(1);
 #pragma unroll
     for (int ks = 0; ks < BK; ks += 16) {
       bf16x8 a[FM], b[FN];
@@ -356,6 +363,7 @@ gemm_bf16_nt_kernel(GemmLpArgs p, int tiles_m, int tiles_n) {
         for (int j = 0; j < FN; ++j)
           acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
     }
+    if (NSR_LP_SETPRIO) __builtin_amdgcn_s_setprio(0);
   }
 
   double ss = 0.0;
