@@ -26,6 +26,11 @@
 #include "../../include/nsr.h"
 #include "nsr_internal.h"
 
+// 1: raise the wave's issue priority while it runs a slab's MFMAs.
+#ifndef NSR_BATCH_SETPRIO
+#define NSR_BATCH_SETPRIO 0
+#endif
+
 namespace nsr {
 
 struct BatchDesc {
@@ -268,6 +273,7 @@ __device__ double wg_gemm(int n, const T* X, int ldx, const double* XA, int64_t 
       if (active) {
         const T* xs = xsb + (sr + lr) * XS + lk;
         const T* ys = ysb + lk * YS + sc + lr;
+        if (NSR_BATCH_SETPRIO) __builtin_amdgcn_s_setprio(1);
 #pragma unroll
         for (int ks = 0; ks < KB; ks += 4) {
           const T a0 = xs[ks], a1 = xs[16 * XS + ks];
@@ -277,6 +283,7 @@ __device__ double wg_gemm(int n, const T* X, int ldx, const double* XA, int64_t 
           acc[1][0] = mfma(a1, b0, acc[1][0]);
           acc[1][1] = mfma(a1, b1, acc[1][1]);
         }
+        if (NSR_BATCH_SETPRIO) __builtin_amdgcn_s_setprio(0);
       }
     }
     if (active) {
