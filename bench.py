@@ -12,7 +12,10 @@ Also measured (extra keys of the same JSON line): the mixed-precision path
 system; the N = 8192, kappa = 1e6 composite (double Newton-Schulz, order 8)
 workload in mixed precision next to the same solve in float64; a batch of
 2048 harmonic-regressor Gram systems of uneven size in one persistent launch;
-and a serving run (Poisson arrivals, sizes 32..2048) with p50/p99 latency.
+a serving run (Poisson arrivals, sizes 32..2048) with p50/p99 latency; the
+program library and the composite variants on the headline system; the
+N = 64 fixed-step workload (eager, captured graph, 4096-seed batch); and a
+three-frequency analogue of the paper's last comparison.
 
 The float64 GEMM's roofline comes from per-launch HIP events recorded by the
 library on its stream during the timed region; the CPU baseline is the oracle
@@ -31,6 +34,12 @@ import numpy as np
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
+# Hardware queues per process (HIP's default is 4): the serving leg runs its
+# single solves on 12 streams, which would otherwise share 4 queues and
+# serialise.  Read by the HIP runtime when it initialises, i.e. before torch
+# touches the GPU.
+if int(os.environ.get("GPU_MAX_HW_QUEUES", "4") or 4) < 16:
+    os.environ["GPU_MAX_HW_QUEUES"] = "16"
 
 from paper_2008_11480_amd import inputs  # noqa: E402
 
@@ -422,9 +431,10 @@ def run_serving(torch, nsr, duration_s=3.0, rate=2000.0):
     log(f"generating {len(trace)} serving requests on the GPU")
     reqs = make_requests(trace)
     torch.cuda.synchronize()
-    # N <= 128 requests go to the batched kernel (one workgroup per system is
-    # fast there); larger ones to 12 worker threads with their own streams.
-    workers, small = 12, 128
+    # N <= 192 requests go to the batched kernel (one workgroup per system);
+    # larger ones to 12 worker threads with their own streams (and hardware
+    # queues, see GPU_MAX_HW_QUEUES above).
+    workers, small = 12, 192
     ex = GpuExecutor(workers=workers, precision=nsr.PREC_MIXED_BF16, small_max_n=small)
     # warm up the kernels and the allocator on a few requests of each path
     warm = make_requests(inputs.serving_trace(rate, 0.02, seed=55))
