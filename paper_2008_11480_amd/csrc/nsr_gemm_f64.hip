@@ -104,6 +104,32 @@ __device__ __forceinline__ double epi_value(const GemmF64Args& p, int64_t row, i
   return v;
 }
 
+// The same with the addends loaded beforehand (0 where absent).
+__device__ __forceinline__ double epi_value(const GemmF64Args& p, int64_t row, int64_t col,
+                                            double acc, double e1, double e2) {
+  double v = p.scale * acc;
+  if (row == col) v += p.diag;
+  if (p.E1) v += e1;
+  if (p.E2) v += e2;
+  return v;
+}
+
+// Addends of one 16 x 16 accumulator fragment (rows row0 + 4 r, column col).
+// The epilogue loads the next fragment's addends before it stores the
+// current one: loads and stores share one in-order completion counter, so a
+// load issued after a store waits for that store, and loading per element
+// would put a memory round trip on every element.
+__device__ __forceinline__ void load_addends(const GemmF64Args& p, int64_t row0, int64_t col,
+                                             double (&e1)[4], double (&e2)[4]) {
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int64_t row = row0 + 4 * r;
+    const bool in = row < p.M && col < p.N;
+    e1[r] = (p.E1 && in) ? p.E1[row * p.lde1 + col] : 0.0;
+    e2[r] = (p.E2 && in) ? p.E2[row * p.lde2 + col] : 0.0;
+  }
+}
+
 // Grid: the first dp workgroups own whole tiles (positions 0..dp-1 of the
 // tile order).  When splits > 0, the remaining tiles (the last, partial round)
 // are cut along K into `splits` slices of `slabs` K-slabs; workgroup dp + q
@@ -299,16 +325,22 @@ gemm_f64_kernel(GemmF64Args p, int tiles_m, int tiles_n, int dp, int splits, int
   // transpose through LDS.
   double ss = 0.0;
   const bool diag_tile = SYM && (tm == tn);
+  double e1[2][4], e2[2][4];
+  load_addends(p, m0 + wm * WTM + lk, n0 + wn * WTN + lr, e1[0], e2[0]);
 #pragma unroll
   for (int i = 0; i < FM; ++i) {
 #pragma unroll
     for (int j = 0; j < FN; ++j) {
+      const int f = i * FN + j;
+      if (f + 1 < FM * FN)
+        load_addends(p, m0 + wm * WTM + ((f + 1) / FN) * 16 + lk,
+                     n0 + wn * WTN + ((f + 1) % FN) * 16 + lr, e1[(f + 1) & 1], e2[(f + 1) & 1]);
       const int64_t col = n0 + wn * WTN + j * 16 + lr;
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int64_t row = m0 + wm * WTM + i * 16 + lk + 4 * r;
         if (row < M && col < N) {
-          const double v = epi_value(p, row, col, acc[i][j][r]);
+          const double v = epi_value(p, row, col, acc[i][j][r], e1[f & 1][r], e2[f & 1][r]);
           if (SYM) acc[i][j][r] = v;
           if (!diag_tile) {
             p.D[row * p.ldd + col] = v;

@@ -62,16 +62,35 @@ __device__ __forceinline__ void map_tile_lp(int bid, int tiles_m, int tiles_n, i
   tn = r / gm;
 }
 
-// Shared epilogue of one output element.
+// Shared epilogue of one output element; e1 / e2 are the addends E1, E2 at
+// (row, col), loaded beforehand (0 where absent).
 __device__ __forceinline__ void put(const GemmLpArgs& p, int64_t row, int64_t col, float acc,
-                                    double& ss) {
+                                    float e1, float e2, double& ss) {
   float v = p.scale * acc;
   if (row == col) v += p.diag;
-  if (p.E1) v += p.E1[row * p.lde1 + col];
-  if (p.E2) v += p.E2[row * p.lde2 + col];
+  if (p.E1) v += e1;
+  if (p.E2) v += e2;
   if (p.D) p.D[row * p.ldd + col] = v;
   if (p.Db) p.Db[row * p.lddb + col] = __builtin_bit_cast(uint16_t, (__bf16)v);
   ss += (double)v * (double)v;
+}
+
+// Addends of one accumulator fragment (R elements per lane at rows row_of(r),
+// column col), loaded together ahead of the fragment's stores: loads and
+// stores share one in-order completion counter, so a load issued after a
+// store cannot complete before the store does, and loading per element after
+// the previous element's store would put a memory round trip on every
+// element.
+template <int R, class RowOf>
+__device__ __forceinline__ void load_addends(const GemmLpArgs& p, int64_t col, RowOf row_of,
+                                             float (&e1)[R], float (&e2)[R]) {
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int64_t row = row_of(r);
+    const bool in = row < p.M && col < p.N;
+    e1[r] = (p.E1 && in) ? p.E1[row * p.lde1 + col] : 0.0f;
+    e2[r] = (p.E2 && in) ? p.E2[row * p.lde2 + col] : 0.0f;
+  }
 }
 
 template <int NWAVES = 4>
@@ -225,18 +244,28 @@ gemm_f32_nn_kernel(GemmLpArgs p, int tiles_m, int tiles_n) {
     if (NSR_LP_SETPRIO) __builtin_amdgcn_s_setprio(0);
   }
 
+  // The next fragment's addends are loaded before the current one's stores.
   double ss = 0.0;
+  float e1[2][4], e2[2][4];
+  auto frag_col = [&](int f) { return n0 + wn * WTN + (f % FN) * 16 + lr; };
+  auto frag_rows = [&](int f) {
+    const int64_t r0 = m0 + wm * WTM + (f / FN) * 16 + 4 * lk;
+    return [r0](int r) { return r0 + r; };
+  };
+  load_addends<4>(p, frag_col(0), frag_rows(0), e1[0], e2[0]);
 #pragma unroll
-  for (int i = 0; i < FM; ++i)
+  for (int f = 0; f < FM * FN; ++f) {
+    if (f + 1 < FM * FN)
+      load_addends<4>(p, frag_col(f + 1), frag_rows(f + 1), e1[(f + 1) & 1], e2[(f + 1) & 1]);
+    const int64_t col = frag_col(f);
+    const auto row_of = frag_rows(f);
 #pragma unroll
-    for (int j = 0; j < FN; ++j) {
-      const int64_t col = n0 + wn * WTN + j * 16 + lr;
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int64_t row = m0 + wm * WTM + i * 16 + 4 * lk + r;
-        if (row < M && col < N) put(p, row, col, acc[i][j][r], ss);
-      }
+    for (int r = 0; r < 4; ++r) {
+      const int64_t row = row_of(r);
+      if (row < M && col < N)
+        put(p, row, col, acc[f / FN][f % FN][r], e1[f & 1][r], e2[f & 1][r], ss);
     }
+  }
   write_partial(p, ss, red, tm, tn, tiles_n);
 }
 
@@ -366,18 +395,42 @@ gemm_bf16_nt_kernel(GemmLpArgs p, int tiles_m, int tiles_n) {
     if (NSR_LP_SETPRIO) __builtin_amdgcn_s_setprio(0);
   }
 
+  // Half a fragment's addends (2 x 8) are loaded together before its stores
+  // (the 256-register budget of two waves per SIMD leaves no room for more):
+  // one memory round trip per half fragment.  Without addends the stores
+  // run back to back.
   double ss = 0.0;
+  if (!p.E1 && !p.E2) {
 #pragma unroll
-  for (int i = 0; i < FM; ++i)
+    for (int i = 0; i < FM; ++i)
 #pragma unroll
-    for (int j = 0; j < FN; ++j) {
-      const int64_t col = n0 + wn * WTN + j * 32 + lr;
+      for (int j = 0; j < FN; ++j) {
+        const int64_t col = n0 + wn * WTN + j * 32 + lr;
 #pragma unroll
-      for (int r = 0; r < 16; ++r) {
-        const int64_t row = m0 + wm * WTM + i * 32 + 8 * (r >> 2) + 4 * lk + (r & 3);
-        if (row < M && col < N) put(p, row, col, acc[i][j][r], ss);
+        for (int r = 0; r < 16; ++r) {
+          const int64_t row = m0 + wm * WTM + i * 32 + 8 * (r >> 2) + 4 * lk + (r & 3);
+          if (row < M && col < N) put(p, row, col, acc[i][j][r], 0.0f, 0.0f, ss);
+        }
+      }
+  } else {
+#pragma unroll
+    for (int f = 0; f < FM * FN; ++f) {
+      const int64_t col = n0 + wn * WTN + (f % FN) * 32 + lr;
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int64_t r0 = m0 + wm * WTM + (f / FN) * 32 + 16 * h + 4 * lk;
+        const auto row_of = [r0](int r) { return r0 + 8 * (r >> 2) + (r & 3); };
+        float e1[8], e2[8];
+        load_addends<8>(p, col, row_of, e1, e2);
+#pragma unroll
+        for (int r = 0; r < 8; ++r) {
+          const int64_t row = row_of(r);
+          if (row < M && col < N)
+            put(p, row, col, acc[f / FN][f % FN][8 * h + r], e1[r], e2[r], ss);
+        }
       }
     }
+  }
   write_partial<WGM * WGN>(p, ss, red, tm, tn, tiles_n);
 }
 
