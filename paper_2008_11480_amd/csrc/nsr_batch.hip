@@ -30,6 +30,13 @@
 #ifndef NSR_BATCH_SETPRIO
 #define NSR_BATCH_SETPRIO 0
 #endif
+// K slab of the in-workgroup GEMM (elements), float32 and float64.
+#ifndef NSR_BATCH_KB32
+#define NSR_BATCH_KB32 16
+#endif
+#ifndef NSR_BATCH_KB64
+#define NSR_BATCH_KB64 16
+#endif
 
 namespace nsr {
 
@@ -133,7 +140,7 @@ __device__ __forceinline__ int acc_row(double, int lk, int r) { return lk + 4 * 
 // In-workgroup GEMM tiling: the n x n output is walked in BM x BN blocks
 // (32 x 32 for one wave, 64 x 32 for two, 64 x 64 for four, 128 x 64 for
 // eight), one 32 x 32 sub-block (2 x 2 MFMA blocks of 16 x 16) per wave.
-// The K range of a block is walked in slabs of KB (16 float32 / 8 float64)
+// The K range of a block is walked in slabs of KB (16 float32 / 16 float64)
 // staged global -> registers (one slab ahead, 16-byte loads) -> two LDS
 // buffers -> MFMA fragments, one barrier per slab.
 template <int NW> struct Block {
@@ -142,16 +149,12 @@ template <int NW> struct Block {
   static_assert((BM / 32) * (BN / 32) == NW, "one 32 x 32 sub-block per wave");
 };
 template <typename T, int NW> struct Stage {
-  static constexpr int KB = sizeof(T) == 4 ? 16 : 8;   // K slab
+  static constexpr int KB = sizeof(T) == 4 ? NSR_BATCH_KB32 : NSR_BATCH_KB64;   // K slab
   static constexpr int VE = 16 / (int)sizeof(T);       // elements per 16-byte load
   static constexpr int XS = KB + (sizeof(T) == 4 ? 4 : 2);
   static constexpr int YS = Block<NW>::BN + (sizeof(T) == 4 ? 4 : 2);
   static constexpr int BUF = Block<NW>::BM * XS + KB * YS;   // one buffer, elements
   static constexpr int BYTES = 2 * BUF * (int)sizeof(T);
-};
-template <int NW> struct StageBytes {
-  static constexpr int a = Stage<float, NW>::BYTES, b = Stage<double, NW>::BYTES;
-  static constexpr int value = a > b ? a : b;
 };
 
 typedef float f32v4 __attribute__((ext_vector_type(4)));
@@ -163,7 +166,7 @@ template <> struct Vec16<double> { typedef f64v2 type; };
 // D = diag I + scale X Y + E1 + E2 (n x n); returns sum D^2 over the
 // workgroup when want_ss (uniform).  XA: X is the float64 input A (read
 // through lda), otherwise X is T with leading dimension ldx (multiple of 4).
-// lds: StageBytes<NW> of LDS shared by the workgroup.
+// lds: Stage<T, NW>::BYTES of LDS shared by the workgroup.
 template <typename T, int NW>
 __device__ double wg_gemm(int n, const T* X, int ldx, const double* XA, int64_t lda, const T* Y,
                           int ldy, T* D, int ldd, const T* E1, const T* E2, int lde, T diag,
@@ -287,8 +290,23 @@ __device__ double wg_gemm(int n, const T* X, int ldx, const double* XA, int64_t 
       }
     }
     if (active) {
+      // The addends of a row of fragments are loaded before its stores:
+      // loads and stores share one in-order completion counter, so a load
+      // issued after a store waits for that store.
 #pragma unroll
-      for (int i = 0; i < 2; ++i)
+      for (int i = 0; i < 2; ++i) {
+        T e1[2][4], e2[2][4];
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+          const int col = c0 + sc + 16 * j + lr;
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int row = r0 + sr + 16 * i + acc_row(T(0), lk, r);
+            const bool in = row < n && col < n;
+            e1[j][r] = (E1 && in) ? E1[row * lde + col] : T(0);
+            e2[j][r] = (E2 && in) ? E2[row * lde + col] : T(0);
+          }
+        }
 #pragma unroll
         for (int j = 0; j < 2; ++j) {
           const int col = c0 + sc + 16 * j + lr;
@@ -298,13 +316,14 @@ __device__ double wg_gemm(int n, const T* X, int ldx, const double* XA, int64_t 
             if (row < n && col < n) {
               T v = scale * acc[i][j][r];
               if (row == col) v += diag;
-              if (E1) v += E1[row * lde + col];
-              if (E2) v += E2[row * lde + col];
+              if (E1) v += e1[j][r];
+              if (E2) v += e2[j][r];
               D[row * ldd + col] = v;
               ss += (double)v * (double)v;
             }
           }
         }
+      }
     }
     __syncthreads();  // LDS buffers free for the next block, D complete
   }
@@ -312,18 +331,37 @@ __device__ double wg_gemm(int n, const T* X, int ldx, const double* XA, int64_t 
   return block_sum_all<NW>(ss, red);
 }
 
-// Elementwise over the n x n slot matrices, all threads.
+// Elementwise passes over the n x n slot matrices, all threads.  Each thread
+// loads EW elements before it stores them: loads and stores share one
+// in-order completion counter, so a load issued after a store waits for it,
+// and one element per iteration would cost a memory round trip each.
+constexpr int EW = 8;
+
 template <typename T, int NW>
 __device__ double wg_init_resid(int n, const double* A, int64_t lda, double alpha, T* F, int ldw,
                                 double* red) {
+  constexpr int NTH = NW * 64;
+  const int nn = n * n;
   double ss = 0.0;
-  for (int i = threadIdx.x; i < n * n; i += NW * 64) {
-    const int row = i / n, col = i % n;
-    double v = -A[(int64_t)row * lda + col] / alpha;
-    if (row == col) v += 1.0;
-    const T t = (T)v;
-    F[row * ldw + col] = t;
-    ss += (double)t * (double)t;
+  for (int i0 = threadIdx.x; i0 < nn; i0 += NTH * EW) {
+    double a[EW];
+#pragma unroll
+    for (int u = 0; u < EW; ++u) {
+      const int i = i0 + u * NTH;
+      a[u] = i < nn ? A[(int64_t)(i / n) * lda + i % n] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < EW; ++u) {
+      const int i = i0 + u * NTH;
+      if (i < nn) {
+        const int row = i / n, col = i % n;
+        double v = -a[u] / alpha;
+        if (row == col) v += 1.0;
+        const T t = (T)v;
+        F[row * ldw + col] = t;
+        ss += (double)t * (double)t;
+      }
+    }
   }
   __syncthreads();
   return block_sum_all<NW>(ss, red);
@@ -331,49 +369,107 @@ __device__ double wg_init_resid(int n, const double* A, int64_t lda, double alph
 
 template <typename T, int NW>
 __device__ void wg_scaled_identity_plus(int n, const T* C, double alpha, T* G, int ldw) {
-  for (int i = threadIdx.x; i < n * n; i += NW * 64) {
-    const int row = i / n, col = i % n;
-    double v = (double)C[row * ldw + col];
-    if (row == col) v += 1.0;
-    G[row * ldw + col] = (T)(v / alpha);
+  constexpr int NTH = NW * 64;
+  const int nn = n * n;
+  for (int i0 = threadIdx.x; i0 < nn; i0 += NTH * EW) {
+    T c[EW];
+#pragma unroll
+    for (int u = 0; u < EW; ++u) {
+      const int i = i0 + u * NTH;
+      c[u] = i < nn ? C[(i / n) * ldw + i % n] : T(0);
+    }
+#pragma unroll
+    for (int u = 0; u < EW; ++u) {
+      const int i = i0 + u * NTH;
+      if (i < nn) {
+        const int row = i / n, col = i % n;
+        double v = (double)c[u];
+        if (row == col) v += 1.0;
+        G[row * ldw + col] = (T)(v / alpha);
+      }
+    }
   }
   __syncthreads();
 }
 
-// r = b - A theta (float64), returns ||r||^2 (uniform).
+// float32 copy of A into the slot (leading dimension ldw).
+template <int NW>
+__device__ void wg_copy_f32(int n, const double* A, int64_t lda, float* A32, int ldw) {
+  constexpr int NTH = NW * 64;
+  const int nn = n * n;
+  for (int i0 = threadIdx.x; i0 < nn; i0 += NTH * EW) {
+    double a[EW];
+#pragma unroll
+    for (int u = 0; u < EW; ++u) {
+      const int i = i0 + u * NTH;
+      a[u] = i < nn ? A[(int64_t)(i / n) * lda + i % n] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < EW; ++u) {
+      const int i = i0 + u * NTH;
+      if (i < nn) A32[(i / n) * ldw + i % n] = (float)a[u];
+    }
+  }
+  __syncthreads();
+}
+
+// r = b - A theta (float64), returns ||r||^2 (uniform).  Wave w owns rows
+// w, w + NW, ...; in each chunk of 64 of its rows, lane j keeps row j's value
+// and the chunk is stored at once after its loads (one memory round trip per
+// chunk instead of one per row).
 template <int NW>
 __device__ double wg_resid(int n, const double* A, int64_t lda, const double* b,
                            const double* theta, double* r, double* red) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   double ss = 0.0;
-  for (int row = wave; row < n; row += NW) {
-    double s = 0.0;
-    for (int c = lane; c < n; c += 64) s += A[(int64_t)row * lda + c] * theta[c];
-    s = wsum(s);
-    const double rv = b[row] - s;
-    if (lane == 0) {
-      r[row] = rv;
-      ss += rv * rv;
+  for (int base = wave; base < n; base += 64 * NW) {
+    double mine = 0.0;
+    int myrow = -1;
+    for (int j = 0; j < 64; ++j) {
+      const int row = base + j * NW;
+      if (row >= n) break;
+      double s = 0.0;
+      for (int c = lane; c < n; c += 64) s += A[(int64_t)row * lda + c] * theta[c];
+      s = wsum(s);
+      if (lane == j) {
+        mine = b[row] - s;
+        myrow = row;
+      }
+    }
+    if (myrow >= 0) {
+      r[myrow] = mine;
+      ss += mine * mine;
     }
   }
   __syncthreads();
   return block_sum_all<NW>(ss, red);
 }
 
-// theta += G r (G of type T, or G = I / alpha when implicit).
+// theta += G r (G of type T, or G = I / alpha when implicit); rows chunked
+// per wave as in wg_resid.
 template <typename T, int NW>
 __device__ void wg_update(int n, const T* G, int ldw, bool implicit, double alpha, const double* r,
                           double* theta) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  for (int row = wave; row < n; row += NW) {
-    double s = 0.0;
-    if (implicit) {
-      s = (lane == 0) ? r[row] / alpha : 0.0;
-    } else {
-      for (int c = lane; c < n; c += 64) s += (double)G[row * ldw + c] * r[c];
+  for (int base = wave; base < n; base += 64 * NW) {
+    double mine = 0.0;
+    int myrow = -1;
+    for (int j = 0; j < 64; ++j) {
+      const int row = base + j * NW;
+      if (row >= n) break;
+      double s = 0.0;
+      if (implicit) {
+        s = (lane == 0) ? r[row] / alpha : 0.0;
+      } else {
+        for (int c = lane; c < n; c += 64) s += (double)G[row * ldw + c] * r[c];
+      }
+      s = wsum(s);
+      if (lane == j) {
+        mine = s;
+        myrow = row;
+      }
     }
-    s = wsum(s);
-    if (lane == 0) theta[row] += s;
+    if (myrow >= 0) theta[myrow] += mine;
   }
   __syncthreads();
 }
@@ -385,7 +481,7 @@ struct SlotMats {
   void* C[2];
   float* A32;
   double* r;
-  void* lds;   // StageBytes<NW> of LDS for the GEMM stages
+  void* lds;   // Stage<T, NW>::BYTES of LDS for the GEMM stages
 };
 
 // Control values of one solve.  Every thread holds the same values (they are
@@ -440,11 +536,7 @@ __device__ bool wg_solve(const BatchArgs& P, const BatchDesc& d, const SlotMats&
     c.refine_stop = NS_STOP_DIVERGED;
     return false;
   }
-  if (is32) {  // float32 copy of A for the residual products
-    for (int i = threadIdx.x; i < n * n; i += NW * 64)
-      sm.A32[(i / n) * ldw + (i % n)] = (float)d.A[(int64_t)(i / n) * d.lda + (i % n)];
-    __syncthreads();
-  }
+  if (is32) wg_copy_f32<NW>(n, d.A, d.lda, sm.A32, ldw);  // for the residual products
   const T* AX = is32 ? (const T*)sm.A32 : nullptr;
   const double* AXd = is32 ? nullptr : d.A;
   // F_0 = I - A / alpha, theta_0 = b / alpha, ||b||
@@ -595,7 +687,7 @@ __global__ void __launch_bounds__(NW * 64) batch_kernel(BatchArgs P) {
   __shared__ double red[NW];
   __shared__ double hist[NS_HIST_F];
   __shared__ int s_idx;
-  __shared__ __attribute__((aligned(16))) char stage[StageBytes<NW>::value];
+  __shared__ __attribute__((aligned(16))) char stage[Stage<T, NW>::BYTES];
   char* slot = P.slots + (int64_t)blockIdx.x * P.slot_bytes;
   const int64_t nn = (int64_t)P.ldw * P.ldw;
   SlotMats sm;
@@ -1023,7 +1115,7 @@ int ns_batch_autotune(ns_batch* B, int count, const int64_t* n, const double* co
         break;
       }
       float ms = 0.f;
-      hipEventElapsedTime(&ms, e0, e1);
+      (void)hipEventElapsedTime(&ms, e0, e1);
       if (ms < bms) {
         bms = ms;
         bw = waves_c[wi];
@@ -1031,8 +1123,8 @@ int ns_batch_autotune(ns_batch* B, int count, const int64_t* n, const double* co
       }
     }
   }
-  hipEventDestroy(e0);
-  hipEventDestroy(e1);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
   if (rc) return rc;
   B->waves = bw;
   B->groups = bg;
