@@ -135,6 +135,24 @@ def test_batch_fp64_mode_and_order8(torch):
         assert np.linalg.norm(th.cpu().numpy() - orc.theta) <= 50 * 1e3 * U64 * np.linalg.norm(orc.theta)
 
 
+@pytest.mark.parametrize("precision", [nsr.PREC_FP32, nsr.PREC_FP64])
+@pytest.mark.parametrize("waves", [1, 2, 4, 8])
+def test_batch_every_launch_shape(torch, waves, precision):
+    """Every workgroup width on sizes that take each path of the in-workgroup
+    code: more rows per wave than lanes (n > 64 waves: the residual and update
+    rows run in several chunks), element-wise passes longer than one staged
+    round (n^2 > 512 waves), blocks cut by the matrix edge, and n = 1.  Same
+    oracle checks as the other batch tests."""
+    systems = [inputs.spd_qlq(n, k, seed=300 + n) for n, k in
+               ((1, 1.0), (23, 1e2), (70, 1e3), (140, 1e2), (200, 1e4), (257, 1e3))]
+    As, bs, ths = upload(torch, systems)
+    B = nsr.Batch(max_n=257, max_count=8, slots=4, precision=precision)
+    B.set_launch(waves, 3)
+    reps = B.poll(B.submit(As, bs, ths, order=4, resid_tol=1e-11), wait=True)
+    assert all(r.status == nsr.NS_OK for r in reps), [(r.status, r.ns_stop) for r in reps]
+    check_against_oracle(systems, ths, reps, 4, 1e-11)
+
+
 def test_batch_escalation_to_fp64(torch):
     """kappa = 1e6 needs ~6 float32 refinement steps; with refine_max = 2 the
     float32 solve fails and the workgroup re-solves the system in float64."""

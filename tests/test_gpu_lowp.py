@@ -64,22 +64,32 @@ def test_gemm_f32_elementwise(torch, m, n, k):
     assert abs(float(ss.cpu()) - ssr) <= 1e-12 * ssr
 
 
+@pytest.mark.parametrize("addends", [0, 1, 2])
 @pytest.mark.parametrize("m,n,k", SHAPES + [(64, 64, 40), (70, 50, 9), (4100, 4000, 200)])
-def test_gemm_bf16_nt_elementwise(torch, m, n, k):
+def test_gemm_bf16_nt_elementwise(torch, m, n, k, addends):
+    """Every epilogue form (no addend, E1, E1 + E2) on every tile family
+    (64, 128 and, for the 4100 x 4000 output, 256-wide tiles with ragged
+    edges)."""
     g = torch.Generator(device="cpu").manual_seed(m * 17 + n * 5 + k)
     X = torch.randn(m, k, generator=g).to(torch.bfloat16)
     Y = torch.randn(n, k, generator=g).to(torch.bfloat16)       # n x k: D = X Y^T
-    E1 = torch.randn(m, n, generator=g, dtype=torch.float32)
-    diag, scale = 1.0, 1.0
-    D, Db, ss = nsr.gemm_lp(X.cuda(), Y.cuda(), nt=True, want_bf16=True, E1=E1.cuda(),
+    E = [torch.randn(m, n, generator=g, dtype=torch.float32) for _ in range(addends)]
+    diag, scale = 1.0, -0.5
+    D, Db, ss = nsr.gemm_lp(X.cuda(), Y.cuda(), nt=True, want_bf16=True,
+                            E1=E[0].cuda() if addends > 0 else None,
+                            E2=E[1].cuda() if addends > 1 else None,
                             diag=diag, scale=scale, want_sumsq=True)
     torch.cuda.synchronize()
     Xd, Yd = X.double().numpy(), Y.double().numpy()
-    ref = Xd @ Yd.T + np.eye(m, n) + E1.double().numpy()
-    bound = g32(k + 4) * (np.abs(Xd) @ np.abs(Yd).T + np.eye(m, n) + np.abs(E1.double().numpy()))
+    Ed = [e.double().numpy() for e in E]
+    ref = scale * (Xd @ Yd.T) + diag * np.eye(m, n) + sum(Ed, np.zeros((m, n)))
+    bound = g32(k + 4) * (abs(scale) * (np.abs(Xd) @ np.abs(Yd).T) + diag * np.eye(m, n)
+                          + sum((np.abs(e) for e in Ed), np.zeros((m, n))))
     got = D.double().cpu().numpy()
     assert np.all(np.abs(got - ref) <= 2 * bound), float(np.max(np.abs(got - ref) / bound))
     assert torch.equal(Db.cpu(), D.cpu().to(torch.bfloat16))
+    ssr = float(np.sum(got * got))
+    assert abs(float(ss.cpu()) - ssr) <= 1e-12 * ssr
 
 
 def test_gemm_bf16_full_size_sampled(torch):
