@@ -30,13 +30,19 @@
 #ifndef NSR_BATCH_SETPRIO
 #define NSR_BATCH_SETPRIO 0
 #endif
-// K slab of the in-workgroup GEMM (elements), float32 and float64.
+// K slab of the in-workgroup GEMM (elements), float32 and float64 (eight-wave
+// workgroups).
 #ifndef NSR_BATCH_KB32
 #define NSR_BATCH_KB32 16
 #endif
 #ifndef NSR_BATCH_KB64
 #define NSR_BATCH_KB64 16
 #endif
+// Rows of the residual / update GEMVs whose loads are issued together.
+#ifndef NSR_BATCH_GR
+#define NSR_BATCH_GR 1
+#endif
+
 
 namespace nsr {
 
@@ -140,7 +146,8 @@ __device__ __forceinline__ int acc_row(double, int lk, int r) { return lk + 4 * 
 // In-workgroup GEMM tiling: the n x n output is walked in BM x BN blocks
 // (32 x 32 for one wave, 64 x 32 for two, 64 x 64 for four, 128 x 64 for
 // eight), one 32 x 32 sub-block (2 x 2 MFMA blocks of 16 x 16) per wave.
-// The K range of a block is walked in slabs of KB (16 float32 / 16 float64)
+// The K range of a block is walked in slabs of KB (16 float32; 16 float64 on
+// eight waves, else 8)
 // staged global -> registers (one slab ahead, 16-byte loads) -> two LDS
 // buffers -> MFMA fragments, one barrier per slab.
 template <int NW> struct Block {
@@ -149,7 +156,9 @@ template <int NW> struct Block {
   static_assert((BM / 32) * (BN / 32) == NW, "one 32 x 32 sub-block per wave");
 };
 template <typename T, int NW> struct Stage {
-  static constexpr int KB = sizeof(T) == 4 ? NSR_BATCH_KB32 : NSR_BATCH_KB64;   // K slab
+  // K slab: the float64 slab of 16 pays on the eight-wave workgroups of the
+  // float64 pass; narrower workgroups keep 8 (their registers spill with 16).
+  static constexpr int KB = sizeof(T) == 4 ? NSR_BATCH_KB32 : (NW >= 8 ? NSR_BATCH_KB64 : 8);
   static constexpr int VE = 16 / (int)sizeof(T);       // elements per 16-byte load
   static constexpr int XS = KB + (sizeof(T) == 4 ? 4 : 2);
   static constexpr int YS = Block<NW>::BN + (sizeof(T) == 4 ? 4 : 2);
@@ -392,9 +401,9 @@ __device__ void wg_scaled_identity_plus(int n, const T* C, double alpha, T* G, i
   __syncthreads();
 }
 
-// float32 copy of A into the slot (leading dimension ldw).
-template <int NW>
-__device__ void wg_copy_f32(int n, const double* A, int64_t lda, float* A32, int ldw) {
+// Copy of A in precision T (leading dimension ldw).
+template <typename T, int NW>
+__device__ void wg_copy_A(int n, const double* A, int64_t lda, T* AT, int ldw) {
   constexpr int NTH = NW * 64;
   const int nn = n * n;
   for (int i0 = threadIdx.x; i0 < nn; i0 += NTH * EW) {
@@ -407,17 +416,19 @@ __device__ void wg_copy_f32(int n, const double* A, int64_t lda, float* A32, int
 #pragma unroll
     for (int u = 0; u < EW; ++u) {
       const int i = i0 + u * NTH;
-      if (i < nn) A32[(i / n) * ldw + i % n] = (float)a[u];
+      if (i < nn) AT[(i / n) * ldw + i % n] = (T)a[u];
     }
   }
   __syncthreads();
 }
 
 // r = b - A theta (float64), returns ||r||^2 (uniform).  Wave w owns rows
-// w, w + NW, ...; in each chunk of 64 of its rows, lane j keeps row j's value
-// and the chunk is stored at once after its loads (one memory round trip per
-// chunk instead of one per row).
-template <int NW>
+// w, w + NW, ...; it takes them GR at a time, issuing the GR rows' loads
+// together, and in each chunk of 64 of its rows lane j keeps row j's value;
+// the chunk is stored at once after its loads (loads and stores share one
+// in-order completion counter, so storing per row would cost a memory round
+// trip per row).  GR trades registers for loads in flight.
+template <int NW, int GR>
 __device__ double wg_resid(int n, const double* A, int64_t lda, const double* b,
                            const double* theta, double* r, double* red) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -425,15 +436,26 @@ __device__ double wg_resid(int n, const double* A, int64_t lda, const double* b,
   for (int base = wave; base < n; base += 64 * NW) {
     double mine = 0.0;
     int myrow = -1;
-    for (int j = 0; j < 64; ++j) {
-      const int row = base + j * NW;
-      if (row >= n) break;
-      double s = 0.0;
-      for (int c = lane; c < n; c += 64) s += A[(int64_t)row * lda + c] * theta[c];
-      s = wsum(s);
-      if (lane == j) {
-        mine = b[row] - s;
-        myrow = row;
+    for (int j0 = 0; j0 < 64 && base + j0 * NW < n; j0 += GR) {
+      double s[GR];
+#pragma unroll
+      for (int u = 0; u < GR; ++u) s[u] = 0.0;
+      for (int c = lane; c < n; c += 64) {
+        const double t = theta[c];
+#pragma unroll
+        for (int u = 0; u < GR; ++u) {
+          const int row = base + (j0 + u) * NW;
+          if (row < n) s[u] += A[(int64_t)row * lda + c] * t;
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < GR; ++u) {
+        const int row = base + (j0 + u) * NW;
+        const double sv = wsum(s[u]);
+        if (row < n && lane == j0 + u) {
+          mine = b[row] - sv;
+          myrow = row;
+        }
       }
     }
     if (myrow >= 0) {
@@ -445,28 +467,43 @@ __device__ double wg_resid(int n, const double* A, int64_t lda, const double* b,
   return block_sum_all<NW>(ss, red);
 }
 
-// theta += G r (G of type T, or G = I / alpha when implicit); rows chunked
-// per wave as in wg_resid.
-template <typename T, int NW>
+// theta += G r (G of type T, or G = I / alpha when implicit); rows grouped
+// and chunked per wave as in wg_resid.
+template <typename T, int NW, int GR>
 __device__ void wg_update(int n, const T* G, int ldw, bool implicit, double alpha, const double* r,
                           double* theta) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   for (int base = wave; base < n; base += 64 * NW) {
     double mine = 0.0;
     int myrow = -1;
-    for (int j = 0; j < 64; ++j) {
-      const int row = base + j * NW;
-      if (row >= n) break;
-      double s = 0.0;
+    for (int j0 = 0; j0 < 64 && base + j0 * NW < n; j0 += GR) {
+      double s[GR];
+#pragma unroll
+      for (int u = 0; u < GR; ++u) s[u] = 0.0;
       if (implicit) {
-        s = (lane == 0) ? r[row] / alpha : 0.0;
+#pragma unroll
+        for (int u = 0; u < GR; ++u) {
+          const int row = base + (j0 + u) * NW;
+          if (row < n && lane == 0) s[u] = r[row] / alpha;
+        }
       } else {
-        for (int c = lane; c < n; c += 64) s += (double)G[row * ldw + c] * r[c];
+        for (int c = lane; c < n; c += 64) {
+          const double rc = r[c];
+#pragma unroll
+          for (int u = 0; u < GR; ++u) {
+            const int row = base + (j0 + u) * NW;
+            if (row < n) s[u] += (double)G[row * ldw + c] * rc;
+          }
+        }
       }
-      s = wsum(s);
-      if (lane == j) {
-        mine = s;
-        myrow = row;
+#pragma unroll
+      for (int u = 0; u < GR; ++u) {
+        const int row = base + (j0 + u) * NW;
+        const double sv = wsum(s[u]);
+        if (row < n && lane == j0 + u) {
+          mine = sv;
+          myrow = row;
+        }
       }
     }
     if (myrow >= 0) theta[myrow] += mine;
@@ -492,6 +529,95 @@ struct Ctl {
   int ns_steps, ns_stop, refine_steps, refine_stop, n_fnorm, precision;
 };
 
+// Scalar preconditioner S = alpha I (Section 2): alpha = ||A||_F, or the
+// maximum row sum of |A| over 2 plus eps (uniform result).
+template <int NW>
+__device__ __forceinline__ double wg_alpha(const BatchArgs& P, const BatchDesc& d, double* red) {
+  const int n = d.n;
+  if (P.scale == NS_SCALE_INF_HALF) {
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    double mx = 0.0;
+    for (int row = wave; row < n; row += NW) {
+      double rs = 0.0;
+      for (int col = lane; col < n; col += 64) rs += fabs(d.A[(int64_t)row * d.lda + col]);
+      mx = fmax(mx, wsum(rs));
+    }
+    return 0.5 * block_max_all<NW>(mx, red) + P.eps;
+  }
+  double ssa = 0.0;
+  for (int i = threadIdx.x; i < n * n; i += NW * 64) {
+    const double v = d.A[(int64_t)(i / n) * d.lda + (i % n)];
+    ssa += v * v;
+  }
+  return sqrt(block_sum_all<NW>(ssa, red));
+}
+
+// theta_0 = b / alpha; returns ||b|| (1 for b = 0), uniform.
+template <int NW>
+__device__ __forceinline__ double wg_theta0(int n, const double* b, double* theta, double alpha,
+                                            double* red) {
+  double bb = 0.0;
+  for (int i = threadIdx.x; i < n; i += NW * 64) {
+    theta[i] = b[i] / alpha;
+    bb += b[i] * b[i];
+  }
+  const double bnorm = sqrt(block_sum_all<NW>(bb, red));
+  return bnorm == 0.0 ? 1.0 : bnorm;
+}
+
+// Float32 attempt that can escalate: with order^(k32 - 1) >= ln 2 / 2^-24,
+// every eigenvalue mu <= 1 - 2^-24 of F_0 has mu^(order^(k32 - 1)) <= 1/2
+// (eq. fk1), so at step k32 + 1 it is below 2^-(order^2).  Returns k32 + 1.
+__device__ __forceinline__ int bail_step(int order) {
+  double e = 1.0;
+  int k32 = 1;
+  while (e < 0.6931471805599453 * 16777216.0) {
+    e *= (double)order;
+    ++k32;
+  }
+  return k32 + 1;
+}
+
+// Richardson refinement with the final G (eq. redttk1) until the relative
+// residual reaches resid_tol, refine_max steps, or a stall (less than a
+// factor 2 over 3 steps).  A (float64, leading dimension lda), b, theta and
+// the scratch r hold n values each.  Returns true on resid_tol.
+template <typename T, int NW, int GR>
+__device__ __forceinline__ bool wg_refine(const BatchArgs& P, int n, const double* A, int64_t lda,
+                                          const double* b, double* theta, const T* G, int ldg,
+                                          double alpha, double* r, double bnorm, double* red,
+                                          Ctl& c) {
+  double last[4] = {0, 0, 0, 0};
+  int refine = 0;
+  while (true) {
+    const double rel = sqrt(wg_resid<NW, GR>(n, A, lda, b, theta, r, red)) / bnorm;
+    c.rel_resid = rel;
+    for (int j = 3; j > 0; --j) last[j] = last[j - 1];
+    last[0] = rel;
+    if (!isfinite(rel)) {
+      c.refine_stop = NS_STOP_DIVERGED;
+      break;
+    }
+    if (rel <= P.resid_tol) {
+      c.refine_stop = NS_STOP_RESID_TOL;
+      break;
+    }
+    if (refine >= P.refine_max) {
+      c.refine_stop = NS_STOP_REFINE_MAX;
+      break;
+    }
+    if (refine >= 3 && rel > 0.5 * last[3]) {
+      c.refine_stop = NS_STOP_REFINE_STALL;
+      break;
+    }
+    wg_update<T, NW, GR>(n, G, ldg, false, alpha, r, theta);
+    ++refine;
+  }
+  c.refine_steps = refine;
+  return c.refine_stop == NS_STOP_RESID_TOL;
+}
+
+
 // One complete solve of system d in precision T.  Returns true when the
 // refinement reached resid_tol.  hist: LDS history of ||F_k||_F (thread 0
 // writes).
@@ -510,44 +636,19 @@ __device__ bool wg_solve(const BatchArgs& P, const BatchDesc& d, const SlotMats&
   c.ns_steps = 0;
   c.refine_steps = 0;
   c.rel_resid = NAN;
-  // Scalar preconditioner S = alpha I (Section 2): alpha = ||A||_F, or the
-  // maximum row sum of |A| over 2 plus eps.
-  double alpha;
-  if (P.scale == NS_SCALE_INF_HALF) {
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    double mx = 0.0;
-    for (int row = wave; row < n; row += NW) {
-      double rs = 0.0;
-      for (int col = lane; col < n; col += 64) rs += fabs(d.A[(int64_t)row * d.lda + col]);
-      mx = fmax(mx, wsum(rs));
-    }
-    alpha = 0.5 * block_max_all<NW>(mx, red) + P.eps;
-  } else {
-    double ssa = 0.0;
-    for (int i = threadIdx.x; i < n * n; i += NW * 64) {
-      const double v = d.A[(int64_t)(i / n) * d.lda + (i % n)];
-      ssa += v * v;
-    }
-    alpha = sqrt(block_sum_all<NW>(ssa, red));
-  }
+  const double alpha = wg_alpha<NW>(P, d, red);
   c.alpha = alpha;
   if (!(alpha > 0.0) || !isfinite(alpha)) {
     c.ns_stop = NS_STOP_DIVERGED;
     c.refine_stop = NS_STOP_DIVERGED;
     return false;
   }
-  if (is32) wg_copy_f32<NW>(n, d.A, d.lda, sm.A32, ldw);  // for the residual products
+  if (is32) wg_copy_A<float, NW>(n, d.A, d.lda, sm.A32, ldw);  // for the residual products
   const T* AX = is32 ? (const T*)sm.A32 : nullptr;
   const double* AXd = is32 ? nullptr : d.A;
   // F_0 = I - A / alpha, theta_0 = b / alpha, ||b||
   const double f0 = sqrt(wg_init_resid<T, NW>(n, d.A, d.lda, alpha, F, ldw, red));
-  double bb = 0.0;
-  for (int i = threadIdx.x; i < n; i += NW * 64) {
-    d.theta[i] = d.b[i] / alpha;
-    bb += d.b[i] * d.b[i];
-  }
-  double bnorm = sqrt(block_sum_all<NW>(bb, red));
-  if (bnorm == 0.0) bnorm = 1.0;
+  const double bnorm = wg_theta0<NW>(n, d.b, d.theta, alpha, red);
   if (threadIdx.x == 0) hist[0] = f0;
   c.n_fnorm = 1;
   int sexp = 0;
@@ -556,19 +657,8 @@ __device__ bool wg_solve(const BatchArgs& P, const BatchDesc& d, const SlotMats&
   int gc = 0;
   int ns_stop = isfinite(f0) ? NS_STOP_NONE : NS_STOP_DIVERGED;
   bool f2_ready = false;  // Pw[0] holds F_k^2 from the floor test
-  // Float32 attempt that can escalate: with order^(k32 - 1) >= ln 2 / 2^-24,
-  // every eigenvalue mu <= 1 - 2^-24 of F_0 has mu^(order^(k32 - 1)) <= 1/2
-  // (eq. fk1), so at step k32 + 1 it is below 2^-(order^2).
-  int bail_k = 0;
-  if (is32 && P.escalate) {
-    double e = 1.0;
-    int k32 = 1;
-    while (e < 0.6931471805599453 * 16777216.0) {
-      e *= (double)P.ns_order;
-      ++k32;
-    }
-    bail_k = k32 + 1;
-  }
+  // A float32 attempt that can escalate gives up at bail_step (see there).
+  const int bail_k = (is32 && P.escalate) ? bail_step(P.ns_order) : 0;
   double fprev = f0;
   int k = 0;
   while (ns_stop == NS_STOP_NONE) {
@@ -601,8 +691,8 @@ __device__ bool wg_solve(const BatchArgs& P, const BatchDesc& d, const SlotMats&
     gc ^= 1;
     implicit = false;
     // Richardson with G_k (eq. redttk1)
-    wg_resid<NW>(n, d.A, d.lda, d.b, d.theta, sm.r, red);
-    wg_update<T, NW>(n, G[gc], ldw, false, alpha, sm.r, d.theta);
+    wg_resid<NW, NSR_BATCH_GR>(n, d.A, d.lda, d.b, d.theta, sm.r, red);
+    wg_update<T, NW, NSR_BATCH_GR>(n, G[gc], ldw, false, alpha, sm.r, d.theta);
     // F_k = I - A G_k
     const double fk =
         sqrt(wg_gemm<T, NW>(n, AX, ldw, AXd, d.lda, G[gc], ldw, F, ldw, nullptr, nullptr, ldw,
@@ -644,10 +734,151 @@ __device__ bool wg_solve(const BatchArgs& P, const BatchDesc& d, const SlotMats&
     c.refine_stop = NS_STOP_NONE;
     return false;
   }
+  return wg_refine<T, NW, NSR_BATCH_GR>(P, n, d.A, d.lda, d.b, d.theta, G[gc], ldw, alpha, sm.r,
+                                        bnorm, red, c);
+}
+
+// ---------------------------------------------------------------------------
+// Small systems (n <= SMALL_N, orders 2 and 4): the whole iteration in LDS.
+// Four n x n matrices live in the workgroup's LDS (two G buffers, F, C); the
+// GEMMs read their MFMA operands straight from LDS, so a step costs no global
+// traffic beyond A, b and theta.  For order 4, F^2 is formed in the G buffer
+// that G_{k+1} overwrites afterwards, and A (in precision T) is staged into
+// C's buffer for the residual product once C is consumed.  Matrices are
+// zero-padded to a multiple of 16 and every writer stores only the n x n
+// part, so the 16 x 16 MFMA blocks need no edge handling.
+// ---------------------------------------------------------------------------
+constexpr int SMALL_N = 64;
+template <typename T> struct SmallLd {
+  static constexpr int value = SMALL_N + (sizeof(T) == 8 ? 2 : 4);   // row stride
+};
+
+// D = diag I + scale X Y + E1 + E2 over the padded size np, all in LDS at
+// element offsets of `lds` (row stride SmallLd; e1 / e2 < 0: no addend);
+// returns sum D^2 when want_ss (uniform).  Offsets rather than pointers keep
+// every access a known LDS access (a pointer chosen at run time between two
+// LDS buffers compiles to flat loads).  Every wave takes up to 16 / NW 16 x 16
+// blocks (np = 64 fills them exactly; smaller np repeats blocks, whose results
+// are dropped).
+template <typename T, int NW>
+__device__ double lds_gemm(T* lds, int np, int n, int xo, int yo, int dout, int e1, int e2,
+                           T diag, T scale, bool want_ss, double* red) {
+  typedef typename Acc<T>::type acc_t;
+  constexpr int LD = SmallLd<T>::value;
+  constexpr int MAXF = 16 / NW;
+  static_assert(NW == 4 || NW == 8, "small-system GEMM runs on four or eight waves");
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int lr = lane & 15, lk = lane >> 4;
+  const int nf = np >> 4, nfrag = nf * nf;
+  int x0[MAXF], y0[MAXF];
+#pragma unroll
+  for (int u = 0; u < MAXF; ++u) {
+    const int f = (wave + u * NW) % nfrag;
+    x0[u] = xo + ((f / nf) * 16 + lr) * LD + lk;   // X[row][k + lk]
+    y0[u] = yo + lk * LD + (f % nf) * 16 + lr;     // Y[k + lk][col]
+  }
+  acc_t acc[MAXF];
+#pragma unroll
+  for (int u = 0; u < MAXF; ++u) acc[u] = acc_t{0, 0, 0, 0};
+  // 16 values of k per round: all operand reads of the round are issued
+  // before its MFMAs, so the round waits for LDS once.
+  for (int k0 = 0; k0 < np; k0 += 16) {
+    T a[4][MAXF], b[4][MAXF];
+#pragma unroll
+    for (int kk = 0; kk < 4; ++kk)
+#pragma unroll
+      for (int u = 0; u < MAXF; ++u) {
+        a[kk][u] = lds[x0[u] + k0 + 4 * kk];
+        b[kk][u] = lds[y0[u] + (k0 + 4 * kk) * LD];
+      }
+#pragma unroll
+    for (int kk = 0; kk < 4; ++kk)
+#pragma unroll
+      for (int u = 0; u < MAXF; ++u) acc[u] = mfma(a[kk][u], b[kk][u], acc[u]);
+  }
+  double ss = 0.0;
+#pragma unroll
+  for (int u = 0; u < MAXF; ++u) {
+    const int f = wave + u * NW;
+    if (f >= nfrag) continue;
+    const int col = (f % nf) * 16 + lr;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int row = (f / nf) * 16 + acc_row(T(0), lk, r);
+      if (row < n && col < n) {
+        const int at = row * LD + col;
+        T v = scale * acc[u][r];
+        if (row == col) v += diag;
+        if (e1 >= 0) v += lds[e1 + at];
+        if (e2 >= 0) v += lds[e2 + at];
+        lds[dout + at] = v;
+        if (want_ss) ss += (double)v * (double)v;
+      }
+    }
+  }
+  __syncthreads();
+  return want_ss ? block_sum_all<NW>(ss, red) : 0.0;
+}
+
+// Matrix-vector products of the LDS path (n <= SMALL_N; A, x, y in LDS):
+// lane l of every wave takes row l over the wave's share of the columns, the
+// NW partial sums of a row are added in wave order (part: NW x SMALL_N
+// float64 of LDS).  No cross-lane reduction: a shuffle tree per row would be
+// a chain of dependent LDS permutes.
+// r = b - A theta; returns ||r||^2 (uniform).
+template <int NW>
+__device__ double small_resid(int n, const double* A, int lda, const double* b,
+                              const double* theta, double* r, double* part, double* red) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int cw = (n + NW - 1) / NW, c0 = wave * cw, c1 = min(n, c0 + cw);
+  if (lane < n) {
+    double s = 0.0;
+    for (int c = c0; c < c1; ++c) s += A[lane * lda + c] * theta[c];
+    part[wave * SMALL_N + lane] = s;
+  }
+  __syncthreads();
+  double ss = 0.0;
+  if (wave == 0 && lane < n) {
+    double s = 0.0;
+#pragma unroll
+    for (int w = 0; w < NW; ++w) s += part[w * SMALL_N + lane];
+    const double rv = b[lane] - s;
+    r[lane] = rv;
+    ss = rv * rv;
+  }
+  return block_sum_all<NW>(ss, red);
+}
+
+// theta += G r.
+template <typename T, int NW>
+__device__ void small_update(int n, const T* G, int ldg, const double* r, double* theta,
+                             double* part) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int cw = (n + NW - 1) / NW, c0 = wave * cw, c1 = min(n, c0 + cw);
+  if (lane < n) {
+    double s = 0.0;
+    for (int c = c0; c < c1; ++c) s += (double)G[lane * ldg + c] * r[c];
+    part[wave * SMALL_N + lane] = s;
+  }
+  __syncthreads();
+  if (wave == 0 && lane < n) {
+    double s = 0.0;
+#pragma unroll
+    for (int w = 0; w < NW; ++w) s += part[w * SMALL_N + lane];
+    theta[lane] += s;
+  }
+  __syncthreads();
+}
+
+// Richardson refinement of the LDS path (as wg_refine).
+template <typename T, int NW>
+__device__ bool small_refine(const BatchArgs& P, int n, const double* A, int lda,
+                             const double* b, double* theta, const T* G, int ldg, double* r,
+                             double* part, double bnorm, double* red, Ctl& c) {
   double last[4] = {0, 0, 0, 0};
   int refine = 0;
   while (true) {
-    const double rel = sqrt(wg_resid<NW>(n, d.A, d.lda, d.b, d.theta, sm.r, red)) / bnorm;
+    const double rel = sqrt(small_resid<NW>(n, A, lda, b, theta, r, part, red)) / bnorm;
     c.rel_resid = rel;
     for (int j = 3; j > 0; --j) last[j] = last[j - 1];
     last[0] = rel;
@@ -667,11 +898,166 @@ __device__ bool wg_solve(const BatchArgs& P, const BatchDesc& d, const SlotMats&
       c.refine_stop = NS_STOP_REFINE_STALL;
       break;
     }
-    wg_update<T, NW>(n, G[gc], ldw, false, alpha, sm.r, d.theta);
+    small_update<T, NW>(n, G, ldg, r, theta, part);
     ++refine;
   }
   c.refine_steps = refine;
   return c.refine_stop == NS_STOP_RESID_TOL;
+}
+
+// One complete solve of a small system in LDS (same steps, stop rule and
+// escalation as wg_solve; orders 2 and 4).  lds: the four matrices (two G
+// buffers, F, C; SMALL_N x SmallLd elements each).  vec: 3 x SMALL_N float64
+// of LDS for theta, b and the residual; theta goes to global memory at the
+// end.  A in float64: a64 (float32 solves; copied once, leading dimension
+// SMALL_N) or, in float64 solves, C's buffer, refilled every step once C is
+// consumed; the residual products read A in precision T from C's buffer.
+// part: NW x SMALL_N float64 of LDS for the matrix-vector products.
+template <typename T, int NW>
+__device__ bool wg_solve_small(const BatchArgs& P, const BatchDesc& d, T* lds, double* vec,
+                               double* a64, double* part, double* red, double* hist, Ctl& c) {
+  constexpr int LD = SmallLd<T>::value;
+  constexpr int MS = SMALL_N * LD;   // elements per matrix
+  constexpr bool dbl = sizeof(T) == 8;
+  const int n = d.n, np = (n + 15) & ~15;
+  const int oG[2] = {0, MS};
+  const int oF = 2 * MS, oC = 3 * MS;
+  double* th = vec;
+  double* bv = vec + SMALL_N;
+  double* rv = vec + 2 * SMALL_N;
+  // float64 A: C's buffer (float64 solves) or a64
+  double* A64 = dbl ? reinterpret_cast<double*>(lds) + oC : a64;
+  constexpr int ALD = dbl ? LD : SMALL_N;
+  c.precision = dbl ? NS_PREC_FP64 : NS_PREC_FP32;
+  c.mmm = 0;
+  c.n_fnorm = 0;
+  c.ns_steps = 0;
+  c.refine_steps = 0;
+  c.rel_resid = NAN;
+  for (int i = threadIdx.x; i < 4 * MS; i += NW * 64) lds[i] = T(0);
+  for (int i = threadIdx.x; i < n; i += NW * 64) bv[i] = d.b[i];
+  __syncthreads();
+  const double alpha = wg_alpha<NW>(P, d, red);
+  c.alpha = alpha;
+  if (!(alpha > 0.0) || !isfinite(alpha)) {
+    c.ns_stop = NS_STOP_DIVERGED;
+    c.refine_stop = NS_STOP_DIVERGED;
+    return false;
+  }
+  wg_copy_A<double, NW>(n, d.A, d.lda, A64, ALD);
+  const double f0 = sqrt(wg_init_resid<T, NW>(n, A64, ALD, alpha, lds + oF, LD, red));
+  const double bnorm = wg_theta0<NW>(n, bv, th, alpha, red);
+  if (threadIdx.x == 0) hist[0] = f0;
+  c.n_fnorm = 1;
+  const bool order4 = P.ns_order == 4;
+  const int bail_k = (!dbl && P.escalate) ? bail_step(P.ns_order) : 0;
+  bool implicit = true, f2_ready = false;
+  int gc = 0, k = 0;
+  int ns_stop = isfinite(f0) ? NS_STOP_NONE : NS_STOP_DIVERGED;
+  double fprev = f0;
+  while (ns_stop == NS_STOP_NONE) {
+    ++k;
+    // C with P(F) = I + C: order 4, C = F + F^2 + F F^2 (F^2 in the G buffer
+    // that receives G_{k+1}); order 2, C = F.
+    const int oGn = oG[gc ^ 1];
+    int occ = oF;
+    if (order4) {
+      if (!f2_ready) {
+        lds_gemm<T, NW>(lds, np, n, oF, oF, oGn, -1, -1, T(0), T(1), false, red);
+        c.mmm += 1;
+      }
+      lds_gemm<T, NW>(lds, np, n, oF, oGn, oC, oF, oGn, T(0), T(1), false, red);
+      c.mmm += 1;
+      occ = oC;
+    }
+    if (implicit) {
+      wg_scaled_identity_plus<T, NW>(n, lds + occ, alpha, lds + oGn, LD);
+    } else {
+      lds_gemm<T, NW>(lds, np, n, oG[gc], occ, oGn, oG[gc], -1, T(0), T(1), false, red);
+      c.mmm += 1;
+    }
+    gc ^= 1;
+    implicit = false;
+    // A into C's buffer: float64 (float64 solves) or, from a64, float32
+    if (dbl)
+      wg_copy_A<double, NW>(n, d.A, d.lda, A64, ALD);
+    else
+      wg_copy_A<T, NW>(n, A64, ALD, lds + oC, LD);
+    // Richardson with G_k (eq. redttk1)
+    small_resid<NW>(n, A64, ALD, bv, th, rv, part, red);
+    small_update<T, NW>(n, lds + oG[gc], LD, rv, th, part);
+    // F_k = I - A G_k
+    const double fk =
+        sqrt(lds_gemm<T, NW>(lds, np, n, oC, oG[gc], oF, -1, -1, T(1), T(-1), true, red));
+    c.mmm += 1;
+    if (threadIdx.x == 0 && k < NS_HIST_F) hist[k] = fk;
+    c.n_fnorm = (k + 1 < NS_HIST_F) ? k + 1 : NS_HIST_F;
+    f2_ready = false;
+    if (!isfinite(fk) || fk > f0) {
+      ns_stop = NS_STOP_DIVERGED;
+    } else if (fk <= P.f_tol) {
+      ns_stop = NS_STOP_F_TOL;
+    } else if (bail_k > 0 && k >= bail_k && fk >= 0.5 && fk > 0.5 * fprev) {
+      ns_stop = NS_STOP_PRECISION;
+    } else {
+      if (P.floor_detect && fk > 0.5 * fprev) {
+        // F_k^2 goes to the G buffer G_{k+1} will overwrite (it holds G_{k-1}).
+        const double f2 = sqrt(lds_gemm<T, NW>(lds, np, n, oF, oF, oG[gc ^ 1], -1, -1, T(0),
+                                               T(1), true, red));
+        c.mmm += 1;
+        f2_ready = order4;
+        if (f2 <= 0.25 * fk) ns_stop = NS_STOP_FLOOR;
+      }
+      if (ns_stop == NS_STOP_NONE && k >= P.k_max) ns_stop = NS_STOP_K_MAX;
+    }
+    fprev = fk;
+  }
+  c.ns_steps = k;
+  c.ns_stop = ns_stop;
+  bool ok = false;
+  if (ns_stop == NS_STOP_DIVERGED) {
+    c.refine_stop = NS_STOP_DIVERGED;
+  } else if (ns_stop == NS_STOP_PRECISION) {
+    c.refine_stop = NS_STOP_NONE;
+  } else {
+    ok = small_refine<T, NW>(P, n, A64, ALD, bv, th, lds + oG[gc], LD, rv, part, bnorm, red, c);
+  }
+  for (int i = threadIdx.x; i < n; i += NW * 64) d.theta[i] = th[i];
+  __syncthreads();
+  return ok;
+}
+
+// Report of one attempt (thread 0).  The float32 pass queues a system it
+// could not solve for the float64 pass when escalation is on.
+__device__ __forceinline__ void write_result(const BatchArgs& P, int sid, bool dbl, bool from_queue, bool ok,
+                             Ctl c, const double* hist, int64_t t_begin) {
+  BatchResult* R = &P.res[sid];
+  const int slot_t = dbl ? 2 : 0;
+  R->clock[slot_t] = t_begin;
+  R->clock[slot_t + 1] = wall_clock64();
+  R->wg[dbl ? 1 : 0] = blockIdx.x;
+  if (!from_queue) {   // first attempt of this system: clear the other one
+    R->clock[2 - slot_t] = 0;
+    R->clock[3 - slot_t] = 0;
+    R->wg[dbl ? 0 : 1] = -1;
+  }
+  if (from_queue) c.mmm += R->mmm;   // the float32 attempt's products
+  if (!dbl && !ok && P.escalate) P.retry[atomicAdd(P.counter + 2, 1)] = sid;
+  R->status = ok ? NS_OK
+                 : ((c.ns_stop == NS_STOP_DIVERGED || c.refine_stop == NS_STOP_DIVERGED)
+                        ? NS_EDIVERGED
+                        : NS_ENOCONV);
+  R->ns_stop = c.ns_stop;
+  R->refine_stop = c.refine_stop;
+  R->ns_steps = c.ns_steps;
+  R->refine_steps = c.refine_steps;
+  R->precision = c.precision;
+  R->n_fnorm = c.n_fnorm;
+  R->n_resid = 0;
+  R->alpha = c.alpha;
+  R->rel_resid = c.rel_resid;
+  R->mmm = c.mmm;
+  for (int j = 0; j < c.n_fnorm; ++j) R->fnorm_hist[j] = hist[j];
 }
 
 // Persistent solver: each workgroup pulls systems from a work counter (the
@@ -732,35 +1118,41 @@ __global__ void __launch_bounds__(NW * 64) batch_kernel(BatchArgs P) {
     Ctl c;
     const bool ok = wg_solve<T, NW>(P, d, sm, red, hist, c);
     __syncthreads();  // hist complete
-    if (threadIdx.x == 0) {
-      BatchResult* R = &P.res[sid];
-      const int slot_t = dbl ? 2 : 0;
-      R->clock[slot_t] = t_begin;
-      R->clock[slot_t + 1] = wall_clock64();
-      R->wg[dbl ? 1 : 0] = blockIdx.x;
-      if (!from_queue) {   // first attempt of this system: clear the other one
-        R->clock[2 - slot_t] = 0;
-        R->clock[3 - slot_t] = 0;
-        R->wg[dbl ? 0 : 1] = -1;
-      }
-      if (from_queue) c.mmm += R->mmm;   // the float32 attempt's products
-      if (!dbl && !ok && P.escalate) P.retry[atomicAdd(P.counter + 2, 1)] = sid;
-      R->status = ok ? NS_OK
-                     : ((c.ns_stop == NS_STOP_DIVERGED || c.refine_stop == NS_STOP_DIVERGED)
-                            ? NS_EDIVERGED
-                            : NS_ENOCONV);
-      R->ns_stop = c.ns_stop;
-      R->refine_stop = c.refine_stop;
-      R->ns_steps = c.ns_steps;
-      R->refine_steps = c.refine_steps;
-      R->precision = c.precision;
-      R->n_fnorm = c.n_fnorm;
-      R->n_resid = 0;
-      R->alpha = c.alpha;
-      R->rel_resid = c.rel_resid;
-      R->mmm = c.mmm;
-      for (int j = 0; j < c.n_fnorm; ++j) R->fnorm_hist[j] = hist[j];
-    }
+    if (threadIdx.x == 0) write_result(P, sid, dbl, from_queue, ok, c, hist, t_begin);
+    __syncthreads();
+  }
+}
+
+// Persistent solver for submissions whose systems all fit the LDS path
+// (n <= SMALL_N, order 2 or 4); same work list, queue and reports as
+// batch_kernel.
+template <typename T, int NW>
+__global__ void __launch_bounds__(NW * 64) small_kernel(BatchArgs P) {
+  constexpr bool dbl = sizeof(T) == 8;
+  constexpr int LD = SmallLd<T>::value;
+  __shared__ double red[NW];
+  __shared__ double hist[NS_HIST_F];
+  __shared__ double vec[3 * SMALL_N];
+  __shared__ double part[NW * SMALL_N];
+  __shared__ double a64[dbl ? 1 : SMALL_N * SMALL_N];
+  __shared__ int s_idx;
+  __shared__ __attribute__((aligned(16))) T mats[4 * SMALL_N * LD];
+  const bool from_queue = dbl && !P.fp64_only;
+  int* counter = P.counter + (from_queue ? 1 : 0);
+  const int total = from_queue ? P.counter[2] : P.count;
+  for (;;) {
+    if (threadIdx.x == 0) s_idx = atomicAdd(counter, 1);
+    __syncthreads();
+    const int q = s_idx;
+    __syncthreads();
+    if (q >= total) break;
+    const int sid = from_queue ? P.retry[q] : P.order[q];
+    const BatchDesc d = P.desc[sid];
+    const int64_t t_begin = wall_clock64();
+    Ctl c;
+    const bool ok = wg_solve_small<T, NW>(P, d, mats, vec, a64, part, red, hist, c);
+    __syncthreads();  // hist complete
+    if (threadIdx.x == 0) write_result(P, sid, dbl, from_queue, ok, c, hist, t_begin);
     __syncthreads();
   }
 }
@@ -785,11 +1177,31 @@ int launch_pass(const BatchArgs& a, int grid, int waves, hipStream_t st) {
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
+template <typename T>
+int launch_small(const BatchArgs& a, int grid, int waves, hipStream_t st) {
+  if (waves >= 8)
+    hipLaunchKernelGGL((small_kernel<T, 8>), dim3(grid), dim3(512), 0, st, a);
+  else
+    hipLaunchKernelGGL((small_kernel<T, 4>), dim3(grid), dim3(256), 0, st, a);
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+bool small_fits(int max_n, int order) { return max_n <= SMALL_N && (order == 2 || order == 4); }
+
 // float32 pass (then the float64 pass over its queue when escalating), or the
 // float64 pass alone.  The float64 pass after float32 solves the few systems
-// float32 could not, so it runs wider workgroups (waves64), one per CU.
-int launch_batch(const BatchArgs& a, int grid, int waves, int grid64, int waves64,
+// float32 could not, so it runs wider workgroups (waves64), one per CU.  With
+// small = true every pass runs the LDS-resident kernel (four or eight waves).
+int launch_batch(const BatchArgs& a, int grid, int waves, int grid64, int waves64, bool small,
                  hipStream_t st) {
+  if (small) {
+    if (!a.fp64_only) {
+      if (launch_small<float>(a, grid, waves, st)) return -1;
+      if (!a.escalate) return 0;
+      return launch_small<double>(a, grid64, waves64, st);
+    }
+    return launch_small<double>(a, grid, waves, st);
+  }
   if (!a.fp64_only) {
     if (launch_pass<float>(a, grid, waves, st)) return -1;
     if (!a.escalate) return 0;
@@ -926,7 +1338,10 @@ int batch_enqueue(ns_batch* B, int count, const int64_t* n, const double* const*
   if (grid > count) grid = count;
   int grid64 = B->cus < B->slots ? B->cus : B->slots;
   if (grid64 > count) grid64 = count;
-  if (grid > 0 && launch_batch(a, grid, B->waves, grid64, 8, B->stream) != 0)
+  int max_sys = 0;
+  for (int i = 0; i < count; ++i) max_sys = std::max(max_sys, (int)n[i]);
+  const bool small = small_fits(max_sys, o->order);
+  if (grid > 0 && launch_batch(a, grid, B->waves, grid64, 8, small, B->stream) != 0)
     return bfail(NS_EHIP, "batch kernel launch failed");
   return NS_OK;
 }

@@ -153,6 +153,58 @@ def test_batch_every_launch_shape(torch, waves, precision):
     check_against_oracle(systems, ths, reps, 4, 1e-11)
 
 
+SMALL = ((1, 1.0), (2, 5.0), (5, 10.0), (16, 1e2), (17, 1e3), (33, 1e2), (48, 1e4), (63, 1e3),
+         (64, 1e2))
+
+
+@pytest.mark.parametrize("precision", [nsr.PREC_FP32, nsr.PREC_FP64])
+@pytest.mark.parametrize("order", [2, 4])
+@pytest.mark.parametrize("waves", [4, 8])
+def test_batch_small_systems_in_lds(torch, precision, order, waves):
+    """Submissions whose systems all have n <= 64 (order 2 or 4) run the
+    LDS-resident kernel: sizes on and off the 16-wide MFMA blocks, n = 1 and
+    64, against the oracle; float64 NS traces follow the oracle's."""
+    systems = [inputs.spd_qlq(n, k, seed=500 + n) for n, k in SMALL]
+    As, bs, ths = upload(torch, systems)
+    B = nsr.Batch(max_n=64, max_count=16, slots=4, precision=precision)
+    B.set_launch(waves, 3)
+    reps = B.poll(B.submit(As, bs, ths, order=order, resid_tol=1e-11), wait=True)
+    assert all(r.status == nsr.NS_OK for r in reps), [(r.status, r.ns_stop) for r in reps]
+    check_against_oracle(systems, ths, reps, order, 1e-11)
+    if precision == nsr.PREC_FP64:
+        for s, r in zip(systems, reps):
+            orc = oracle.solve(s.A, s.b, oracle.SolveOptions(order=order, resid_tol=1e-11))
+            assert r.precision == nsr.PREC_FP64
+            assert abs(r.ns_steps - orc.ns_steps) <= 1, (s.n, r.ns_steps, orc.ns_steps)
+            floor = max(min(r.fnorm_hist), min(orc.fnorm_hist))
+            for g, o in zip(r.fnorm_hist, orc.fnorm_hist):
+                assert abs(g - o) <= 1e-10 * o + 10 * floor, (s.n, g, o)
+
+
+def test_batch_small_fixed_steps(torch):
+    """The N = 64 fixed-step workload (order 4, exactly 12 coupled steps, no
+    floor test) on the LDS path in float64: 12 steps, the oracle's ||F_k||
+    sequence above the rounding floor, residual <= 1e-13."""
+    w = inputs.WORKLOADS["spd64_k1e2_o4"]
+    systems = [inputs.spd_qlq(w["n"], w["kappa"], seed) for seed in (w["seed"], 11, 12)]
+    As, bs, ths = upload(torch, systems)
+    B = nsr.Batch(max_n=64, max_count=4, slots=2, precision=nsr.PREC_FP64)
+    reps = B.poll(B.submit(As, bs, ths, order=w["order"], k_max=w["k_max"], floor_detect=False,
+                           resid_tol=w["resid_tol"], refine_max=20), wait=True)
+    for s, r, th in zip(systems, reps, ths):
+        assert r.status == nsr.NS_OK and r.ns_steps == w["k_max"] and r.ns_stop == "k_max"
+        orc = oracle.solve(s.A, s.b, oracle.SolveOptions(order=w["order"], k_max=w["k_max"],
+                                                         floor_detect=False,
+                                                         resid_tol=w["resid_tol"]))
+        assert orc.ns_steps == w["k_max"]
+        floor = 1e3 * max(min(r.fnorm_hist), min(orc.fnorm_hist))
+        for g, o in zip(r.fnorm_hist, orc.fnorm_hist):
+            if o > floor:
+                assert abs(g - o) <= 1e-10 * o, (g, o)
+        x = th.cpu().numpy()
+        assert np.linalg.norm(s.b - s.A @ x) <= w["resid_tol"] * np.linalg.norm(s.b)
+
+
 def test_batch_escalation_to_fp64(torch):
     """kappa = 1e6 needs ~6 float32 refinement steps; with refine_max = 2 the
     float32 solve fails and the workgroup re-solves the system in float64."""
