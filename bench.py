@@ -293,37 +293,65 @@ def run_small_fixed(torch, nsr, reps=300):
                          np.array_equal(x, ref))}
         log(f"N=64 fixed 12 steps, {mode}: {dt * 1e6:.0f} us/solve")
     s.close()
+    # One system through the batched kernel (systems with N <= 64 solve in
+    # one workgroup with every iteration matrix in LDS): the latency of a
+    # single solve without host round trips between steps.
+    bopts = dict(order=w["order"], k_max=w["k_max"], floor_detect=False,
+                 resid_tol=w["resid_tol"], refine_max=20)
+    B1 = nsr.Batch(max_n=w["n"], max_count=1, slots=1, precision=nsr.PREC_FP64)
+    B1.set_launch(8, 1)
+    th1 = torch.zeros_like(b)
+    for _ in range(5):
+        B1.poll_arrays(B1.submit([A], [b], [th1], **bopts), wait=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        t1 = B1.submit([A], [b], [th1], **bopts)
+        r1 = B1.poll_arrays(t1, wait=True)
+    dt1 = (time.perf_counter() - t0) / reps
+    tl1, _ = B1.timeline(t1)
+    x1 = th1.cpu().numpy()
+    out["batch_of_one"] = {
+        "us_per_solve": dt1 * 1e6,
+        "device_us": float(np.nanmax(tl1[0, [1, 3]]) - np.nanmin(tl1[0, [0, 2]])),
+        "rel_resid": float(np.linalg.norm(sysm.b - sysm.A @ x1) / np.linalg.norm(sysm.b)),
+        "ns_steps": int(r1["ns_steps"][0]), "refine_steps": int(r1["refine_steps"][0])}
+    log(f"N=64 fixed 12 steps, batch of one: {dt1 * 1e6:.0f} us/solve")
     # The same workload for 4096 independent seeds in one float64 batch
     # (persistent kernel, every solve on one workgroup, no host round trips).
     count = 4096
     systems = [inputs.spd_qlq(w["n"], w["kappa"], 1000 + i) for i in range(count)]
-    As = [torch.from_numpy(x.A).to("cuda") for x in systems]
-    bs = [torch.from_numpy(x.b).to("cuda") for x in systems]
-    ths = [torch.zeros_like(v) for v in bs]
+    P = nsr.PackedSystems.from_host([x.A for x in systems], [x.b for x in systems])
     B = nsr.Batch(max_n=w["n"], max_count=count,
                   slots=min(count, 8 * torch.cuda.get_device_properties(0).multi_processor_count),
                   precision=nsr.PREC_FP64)
-    bopts = dict(order=w["order"], k_max=w["k_max"], floor_detect=False,
-                 resid_tol=w["resid_tol"], refine_max=20)
-    waves, groups, _ = B.autotune(As, bs, ths, **bopts)
-    times = []
+    waves, groups, _ = B.autotune([P.A_of(i) for i in range(count)],
+                                  [P.b_of(i) for i in range(count)],
+                                  [P.theta_of(i) for i in range(count)], **bopts)
+    times, dev = [], []
     for i in range(4):
+        P.theta.zero_()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        reps = B.poll(B.submit(As, bs, ths, **bopts), wait=True)
+        t = B.submit_packed(P, **bopts)
+        rep = B.poll_arrays(t, wait=True)
         if i:
             times.append(time.perf_counter() - t0)
-    mk = float(np.median(times))
-    rel = max(float(np.linalg.norm(x.b - x.A @ t.cpu().numpy()) / np.linalg.norm(x.b))
-              for x, t in zip(systems[:64], ths[:64]))
-    flop = sum(r.gemm_flop for r in reps)
+            tl, _ = B.timeline(t)
+            dev.append((np.nanmax(tl[:, [1, 3]]) - np.nanmin(tl[:, [0, 2]])) * 1e-6)
+    mk, mk_dev = float(np.median(times)), float(np.median(dev))
+    rel = max(float(np.linalg.norm(x.b - x.A @ P.theta_of(i).cpu().numpy()) / np.linalg.norm(x.b))
+              for i, x in enumerate(systems[:64]))
+    flop = float(rep["gemm_flop"].sum())
     out["batch4096_fp64"] = {
         "count": count, "launch": {"waves_per_group": waves, "groups": groups},
-        "makespan_ms": mk * 1e3, "solves_per_s": count / mk, "us_per_solve": mk / count * 1e6,
-        "alg_tflops": flop / mk / 1e12,
-        "ok": sum(1 for r in reps if r.status == nsr.NS_OK), "rel_resid_max_first64": rel,
-        "ns_steps": int(reps[0].ns_steps)}
-    log(f"N=64 x 4096 float64 batch: {mk * 1e3:.1f} ms ({count / mk:.0f} solves/s)")
+        "makespan_ms": mk * 1e3, "device_ms": mk_dev * 1e3, "solves_per_s": count / mk,
+        "us_per_solve": mk / count * 1e6, "alg_tflops": flop / mk / 1e12,
+        "alg_tflops_device": flop / mk_dev / 1e12,
+        "ok": int((rep["status"] == nsr.NS_OK).sum()), "rel_resid_max_first64": rel,
+        "ns_steps": int(rep["ns_steps"][0])}
+    log(f"N=64 x 4096 float64 batch: {mk * 1e3:.1f} ms ({count / mk:.0f} solves/s), "
+        f"device {mk_dev * 1e3:.2f} ms")
     return out
 
 
@@ -353,70 +381,69 @@ def run_batch(torch, nsr, reps_timed):
     count = 2048
     log(f"generating {count} harmonic Gram systems (seed 4)")
     systems = inputs.harmonic_batch(count, seed=4)
-    As = [torch.from_numpy(s.A).to("cuda") for s in systems]
-    bs = [torch.from_numpy(s.b).to("cuda") for s in systems]
-    ths = [torch.zeros_like(b) for b in bs]
+    # Systems back to back in device memory (a submission's pointer arrays
+    # then come from numpy, not from one call per tensor).
+    P = nsr.PackedSystems.from_host([s.A for s in systems], [s.b for s in systems])
     B = nsr.Batch(max_n=256, max_count=count,
                   slots=min(count, 8 * torch.cuda.get_device_properties(0).multi_processor_count))
     opts = dict(order=4, resid_tol=1e-10, refine_max=100)
-    waves, groups, tune_ms = B.autotune(As, bs, ths, **opts)
+    waves, groups, tune_ms = B.autotune([P.A_of(i) for i in range(count)],
+                                        [P.b_of(i) for i in range(count)],
+                                        [P.theta_of(i) for i in range(count)], **opts)
     log(f"batch autotune: {waves} waves/workgroup, {groups} workgroups ({tune_ms:.1f} ms)")
-    times = []
-    reps = None
-    for i in range(reps_timed + 1):
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        t = B.submit(As, bs, ths, **opts)
-        reps = B.poll(t, wait=True)
-        dt = time.perf_counter() - t0
-        if i > 0:
-            times.append(dt)
-        log(f"batch {'warmup' if i == 0 else 'run'} {i}: {dt * 1e3:.1f} ms")
-    mk = float(np.median(times))
-    tl, wgs = B.timeline(t)
-    flop = sum(r.gemm_flop for r in reps)
-    ok = sum(1 for r in reps if r.status == nsr.NS_OK)
-    esc = sum(1 for r in reps if r.precision == nsr.PREC_FP64)
-    rel = []
-    for s, th in zip(systems, ths):
-        x = th.cpu().numpy()
-        rel.append(float(np.linalg.norm(s.b - s.A @ x) / np.linalg.norm(s.b)))
-    rel = np.array(rel)
-    steps = np.array([r.ns_steps for r in reps])
+
+    def timed(pk, o):
+        times, dev = [], []
+        for i in range(reps_timed + 1):
+            pk.theta.zero_()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            t = B.submit_packed(pk, **o)
+            r = B.poll_arrays(t, wait=True)
+            dt = time.perf_counter() - t0
+            tl, _ = B.timeline(t)
+            if i > 0:
+                times.append(dt)
+                dev.append((np.nanmax(tl[:, [1, 3]]) - np.nanmin(tl[:, [0, 2]])) * 1e-6)
+            log(f"batch {'warmup' if i == 0 else 'run'} {i}: {dt * 1e3:.1f} ms")
+        return float(np.median(times)), float(np.median(dev)), r, tl
+
+    def rel_resid(pk):
+        return np.array([float(np.linalg.norm(s.b - s.A @ pk.theta_of(i).cpu().numpy())
+                               / np.linalg.norm(s.b)) for i, s in enumerate(systems)])
+
+    mk, mk_dev, rep, tl = timed(P, opts)
+    flop = float(rep["gemm_flop"].sum())
+    okm = rep["status"] == nsr.NS_OK
+    ok, esc = int(okm.sum()), int((rep["precision"] == nsr.PREC_FP64).sum())
+    rel = rel_resid(P)
+    steps = rep["ns_steps"]
     # Variant: the paper's own scalar preconditioner alpha = ||A||_inf / 2 + eps
     # (Section 2), same launch shape.
     opts_inf = dict(opts, scale=nsr.SCALE_INF_HALF, eps=1e-9)
-    ths_inf = [torch.zeros_like(b) for b in bs]
-    t_inf = []
-    for i in range(reps_timed + 1):
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        reps_inf = B.poll(B.submit(As, bs, ths_inf, **opts_inf), wait=True)
-        if i > 0:
-            t_inf.append(time.perf_counter() - t0)
-    mk_inf = float(np.median(t_inf))
-    steps_inf = np.array([r.ns_steps for r in reps_inf])
-    rel_inf = np.array([float(np.linalg.norm(s.b - s.A @ th.cpu().numpy()) / np.linalg.norm(s.b))
-                        for s, th in zip(systems, ths_inf)])
-    ok_inf = [r.status == nsr.NS_OK for r in reps_inf]
+    mk_inf, mk_inf_dev, rep_inf, _ = timed(P, opts_inf)
+    steps_inf = rep_inf["ns_steps"]
+    ok_inf = rep_inf["status"] == nsr.NS_OK
+    rel_inf = rel_resid(P)
     log(f"batch inf_half scaling: {mk_inf * 1e3:.1f} ms, ns_steps p50 "
         f"{np.median(steps_inf):.0f} (frobenius {np.median(steps):.0f})")
     return {
         "workload": "harmonic_batch2048_m8-128_o4", "count": count,
         "scale": "frobenius",
         "inf_half_variant": {
-            "makespan_ms": mk_inf * 1e3, "solves_per_s": count / mk_inf,
-            "ok": int(sum(ok_inf)), "escalated_to_fp64": sum(1 for r in reps_inf
-                                                          if r.precision == nsr.PREC_FP64),
+            "makespan_ms": mk_inf * 1e3, "device_ms": mk_inf_dev * 1e3,
+            "solves_per_s": count / mk_inf,
+            "ok": int(ok_inf.sum()),
+            "escalated_to_fp64": int((rep_inf["precision"] == nsr.PREC_FP64).sum()),
             "rel_resid_max_ok": float(rel_inf[ok_inf].max()),
             "ns_steps_p50": float(np.median(steps_inf)), "ns_steps_max": int(steps_inf.max()),
             "ns_steps_total": int(steps_inf.sum()), "ns_steps_total_frobenius": int(steps.sum()),
         },
         "launch": {"waves_per_group": waves, "groups": groups},
-        "makespan_ms": mk * 1e3, "solves_per_s": count / mk,
+        "makespan_ms": mk * 1e3, "device_ms": mk_dev * 1e3, "solves_per_s": count / mk,
         "alg_tflops": flop / mk / 1e12,
         "ok": ok, "escalated_to_fp64": esc, "not_converged": count - ok,
-        "rel_resid_max_ok": float(rel[[r.status == nsr.NS_OK for r in reps]].max()),
+        "rel_resid_max_ok": float(rel[okm].max()),
         "rel_resid_p50": float(np.median(rel)),
         "ns_steps_p50": float(np.median(steps)), "ns_steps_max": int(steps.max()),
         "timeline_ms": timeline_summary(tl, [s.n for s in systems], groups),

@@ -356,6 +356,79 @@ def _report_from_c(rep) -> SolveReport:
         resid_hist=list(rep.resid_hist[:rep.n_resid]))
 
 
+class PackedSystems:
+    """A batch's systems stored back to back in three flat float64 device
+    tensors: ``A`` holds each ``A_i`` row-major (``n_i x n_i``, leading
+    dimension ``n_i``), ``b`` and ``theta`` the vectors.  A submission of a
+    packed batch computes its pointer arrays with numpy from the three base
+    addresses instead of one call per tensor (`Batch.submit_packed`)."""
+
+    def __init__(self, ns, device=None):
+        import torch
+        self.n = np.ascontiguousarray(np.asarray(ns, dtype=np.int64))
+        if self.n.ndim != 1 or (self.n < 1).any():
+            raise ValueError("sizes must be a 1-d list of positive integers")
+        sq = self.n * self.n
+        self.a_off = np.concatenate(([0], np.cumsum(sq)[:-1])).astype(np.int64)
+        self.v_off = np.concatenate(([0], np.cumsum(self.n)[:-1])).astype(np.int64)
+        dev = torch.device("cuda", torch.cuda.current_device() if device is None else device)
+        self.A = torch.empty(int(sq.sum()), dtype=torch.float64, device=dev)
+        self.b = torch.empty(int(self.n.sum()), dtype=torch.float64, device=dev)
+        self.theta = torch.zeros(int(self.n.sum()), dtype=torch.float64, device=dev)
+
+    def __len__(self) -> int:
+        return int(self.n.size)
+
+    def A_of(self, i: int):
+        k, o = int(self.n[i]), int(self.a_off[i])
+        return self.A[o:o + k * k].view(k, k)
+
+    def b_of(self, i: int):
+        return self.b[int(self.v_off[i]):int(self.v_off[i] + self.n[i])]
+
+    def theta_of(self, i: int):
+        return self.theta[int(self.v_off[i]):int(self.v_off[i] + self.n[i])]
+
+    @classmethod
+    def from_host(cls, As, bs, device=None):
+        """Pack host (numpy) systems; theta starts at zero."""
+        import torch
+        P = cls([a.shape[0] for a in As], device)
+        P.A.copy_(torch.from_numpy(np.concatenate([np.ascontiguousarray(a, dtype=np.float64)
+                                                   .ravel() for a in As])))
+        P.b.copy_(torch.from_numpy(np.concatenate([np.asarray(b, dtype=np.float64)
+                                                   for b in bs])))
+        return P
+
+    def pointers(self):
+        """(n, A pointers, b pointers, theta pointers) as numpy arrays."""
+        pa = (self.A.data_ptr() + 8 * self.a_off).astype(np.uint64)
+        pb = (self.b.data_ptr() + 8 * self.v_off).astype(np.uint64)
+        pt = (self.theta.data_ptr() + 8 * self.v_off).astype(np.uint64)
+        return self.n, pa, pb, pt
+
+
+_REPORT_COLUMNS = ("status", "precision", "ns_steps", "refine_steps", "ns_stop", "refine_stop",
+                   "alpha", "rel_resid", "mmm", "gemm_flop")
+
+
+def _report_dtype():
+    """numpy view of SolveReportC's scalar fields (offsets from ctypes)."""
+    kinds = {ctypes.c_int: np.int32, ctypes.c_int64: np.int64, ctypes.c_double: np.float64}
+    types = dict(SolveReportC._fields_)
+    return np.dtype({"names": list(_REPORT_COLUMNS),
+                     "formats": [kinds[types[f]] for f in _REPORT_COLUMNS],
+                     "offsets": [getattr(SolveReportC, f).offset for f in _REPORT_COLUMNS],
+                     "itemsize": ctypes.sizeof(SolveReportC)})
+
+
+def _report_arrays(reps, count: int) -> dict:
+    """Columns of a ctypes SolveReportC array as numpy arrays (no per-report
+    Python objects)."""
+    arr = np.frombuffer(reps, dtype=_report_dtype(), count=count)
+    return {f: arr[f].copy() for f in _REPORT_COLUMNS}
+
+
 class Batch:
     """``ns_batch`` handle: many independent systems per persistent launch."""
 
@@ -436,6 +509,33 @@ class Batch:
         self._keep = (As, bs, thetas)
         self._count = count
         return t.value
+
+    def submit_packed(self, systems: "PackedSystems", **opts) -> int:
+        """Submit a packed batch (see `PackedSystems`); same options as
+        `submit`."""
+        n, pa, pb, pt = systems.pointers()
+        o = self._opts(**opts)
+        t = ctypes.c_uint64()
+        check(lib().ns_batch_submit(self._h, len(systems), n.ctypes.data, pa.ctypes.data,
+                                    n.ctypes.data, pb.ctypes.data, pt.ctypes.data,
+                                    ctypes.byref(o), ctypes.byref(t)))
+        self._keep = systems
+        self._count = len(systems)
+        return t.value
+
+    def poll_arrays(self, ticket: int, wait: bool = True):
+        """Like `poll`, but the reports come back as numpy columns (status,
+        precision, ns_steps, refine_steps, ns_stop, refine_stop, alpha,
+        rel_resid, mmm, gemm_flop) without the NS histories; None if still
+        running (wait=False)."""
+        reps = (SolveReportC * max(self._count, 1))()
+        st = lib().ns_batch_poll(self._h, int(ticket), 1 if wait else 0, reps)
+        if st == NS_EBUSY:
+            return None
+        if st not in (NS_OK, NS_ENOCONV):
+            check(st)
+        self._keep = None
+        return _report_arrays(reps, self._count)
 
     def poll(self, ticket: int, wait: bool = True):
         """List of SolveReport on completion, None if still running (wait=False)."""

@@ -88,3 +88,25 @@ def test_gemm_partials_count():
     ts = L.ns_gemm_f64_partials(1000, 1000, nsr.GEMM_SYMMETRIC)
     side = int(round(t ** 0.5))
     assert side * side == t and ts == side * (side + 1) // 2
+
+
+def test_report_columns_match_the_c_struct():
+    """The numpy view used by Batch.poll_arrays reads the same fields as the
+    ctypes struct (offsets, types), for every report of an array."""
+    reps = (nsr.SolveReportC * 4)()
+    for i in range(4):
+        reps[i].status = -i
+        reps[i].precision = i % 2
+        reps[i].ns_steps = 10 + i
+        reps[i].refine_steps = 20 + i
+        reps[i].ns_stop = i
+        reps[i].refine_stop = 5 - i
+        reps[i].alpha = 1.5 * i
+        reps[i].rel_resid = 1e-11 * (i + 1)
+        reps[i].mmm = 1000 + i
+        reps[i].gemm_flop = 1e9 * i
+        reps[i].fnorm_hist[3] = 7.0      # not a column: must not leak into one
+    cols = nsr._report_arrays(reps, 3)
+    assert set(cols) == set(nsr._REPORT_COLUMNS)
+    for f in nsr._REPORT_COLUMNS:
+        assert cols[f].tolist() == [getattr(reps[i], f) for i in range(3)], f

@@ -271,3 +271,23 @@ def test_batch_autotune(torch):
         t.zero_()
     reps = B.poll(B.submit(As, bs, ths, order=4, resid_tol=1e-10), wait=True)
     check_against_oracle(systems, ths, reps, 4, 1e-10, sample=range(0, 48, 6))
+
+
+def test_packed_submission_matches_lists(torch):
+    """submit_packed / poll_arrays solve exactly what submit / poll do (same
+    kernels, same order): theta bit-identical, same report columns; once on
+    the general kernel (n up to 130) and once on the LDS path (n <= 64)."""
+    for sizes in ((16, 130, 33, 64, 100), (1, 17, 40, 64)):
+        systems = [inputs.spd_qlq(n, 1e3, seed=700 + n) for n in sizes]
+        P = nsr.PackedSystems.from_host([s.A for s in systems], [s.b for s in systems])
+        As, bs, ths = upload(torch, systems)
+        B = nsr.Batch(max_n=max(sizes), max_count=8, slots=4)
+        B.set_launch(4, 3)
+        reps = B.poll(B.submit(As, bs, ths, order=4, resid_tol=1e-11), wait=True)
+        cols = B.poll_arrays(B.submit_packed(P, order=4, resid_tol=1e-11), wait=True)
+        for i, (r, th) in enumerate(zip(reps, ths)):
+            assert torch.equal(P.theta_of(i), th)
+            assert torch.equal(P.A_of(i).cpu(), torch.from_numpy(systems[i].A))
+            for f in ("status", "precision", "ns_steps", "refine_steps", "alpha", "rel_resid",
+                      "mmm"):
+                assert cols[f][i] == getattr(r, f), (f, i)
