@@ -181,6 +181,31 @@ def test_batch_small_systems_in_lds(torch, precision, order, waves):
                 assert abs(g - o) <= 1e-10 * o + 10 * floor, (s.n, g, o)
 
 
+@pytest.mark.parametrize("precision", [nsr.PREC_FP32, nsr.PREC_FP64])
+def test_batch_small_path_scaling_and_divergence(torch, precision):
+    """LDS path: alpha = ||A||_inf / 2 + eps (Section 2) against the oracle with
+    the same scaling, and an indefinite matrix in the same submission
+    diverges (report NS_EDIVERGED) without disturbing the others."""
+    rng = np.random.default_rng(21)
+    systems = [inputs.harmonic_gram(int(m), seed=int(rng.integers(1 << 30)))
+               for m in rng.integers(8, 33, size=6)]
+    systems += [inputs.spd_qlq(n, k, seed=80 + n) for n, k in ((7, 1e2), (64, 1e3))]
+    q, _ = np.linalg.qr(rng.standard_normal((40, 40)))
+    lam = np.linspace(1.0, 10.0, 40)
+    lam[0] = -2.0
+    Abad = (q * lam) @ q.T
+    bad = inputs.SPDSystem(A=np.ascontiguousarray(0.5 * (Abad + Abad.T)),
+                           b=rng.standard_normal(40))
+    As, bs, ths = upload(torch, systems + [bad])
+    B = nsr.Batch(max_n=64, max_count=16, slots=4, precision=precision)
+    eps = 1e-9
+    reps = B.poll(B.submit(As, bs, ths, order=4, resid_tol=1e-10, scale=nsr.SCALE_INF_HALF,
+                           eps=eps), wait=True)
+    assert reps[-1].status == nsr.NS_EDIVERGED and reps[-1].ns_stop == "diverged"
+    assert all(r.status == nsr.NS_OK for r in reps[:-1])
+    check_against_oracle(systems, ths[:-1], reps[:-1], 4, 1e-10, eps=eps)
+
+
 def test_batch_small_fixed_steps(torch):
     """The N = 64 fixed-step workload (order 4, exactly 12 coupled steps, no
     floor test) on the LDS path in float64: 12 steps, the oracle's ||F_k||
