@@ -38,9 +38,11 @@
 #ifndef NSR_BATCH_KB64
 #define NSR_BATCH_KB64 16
 #endif
-// Rows of the residual / update GEMVs whose loads are issued together.
+// Rows of the residual / update GEMVs whose loads are issued together (2
+// measured best on the 2048-system harmonic batch: 3 and more cost the float32
+// pass registers, 1 leaves loads of one row in flight at a time).
 #ifndef NSR_BATCH_GR
-#define NSR_BATCH_GR 1
+#define NSR_BATCH_GR 2
 #endif
 
 
