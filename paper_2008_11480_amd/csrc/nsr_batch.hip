@@ -1,20 +1,23 @@
 // Batched solves of many independent SPD systems of uneven size in one
-// persistent launch.
+// persistent launch per precision.
 //
 // Each workgroup pulls whole systems from a device counter (systems are
-// pre-sorted by decreasing n^3, so the largest start first) and runs the
+// pre-sorted by decreasing n, so the largest start first) and runs the
 // complete coupled solve of one system inside the workgroup: the scalar
 // preconditioner (Section 2), Newton-Schulz steps of order 2^s in the
 // factorized form (I+F)(I+F^2)... (eq. ns, Tables 1-2), the coupled
 // Richardson update (eq. redttk1), the stop rule and float64 refinement.  The
-// products run in float32 MFMA (v_mfma_f32_16x16x4_f32); a system whose
-// float32 solve cannot reach the tolerance is re-solved in float64 MFMA
-// (v_mfma_f64_16x16x4_f64) by the same workgroup.  Workgroups never wait for
-// each other: a workgroup exits when the counter has passed the batch size.
+// float32 pass runs the products in float32 MFMA (v_mfma_f32_16x16x4_f32) and
+// queues the systems it cannot bring to the tolerance; a second kernel
+// re-solves those in float64 MFMA (v_mfma_f64_16x16x4_f64).  Workgroups never
+// wait for each other: a workgroup exits when the counter has passed the
+// number of systems.
 //
-// Matrices live in the workgroup's slot of the workspace (row-major, leading
-// dimension ldw); products are tiled over 32 x 32 output tiles, one wave per
-// tile, with operands read through the cache hierarchy.
+// General kernel: matrices live in the workgroup's slot of the workspace
+// (row-major, leading dimension ldw); products walk the output in blocks
+// staged through LDS (wg_gemm).  Submissions whose systems all have
+// n <= SMALL_N (orders 2 and 4) run a second kernel that keeps the whole
+// iteration in LDS (wg_solve_small).
 #include <math.h>
 #include <stdio.h>
 #include <string.h>
@@ -26,10 +29,6 @@
 #include "../../include/nsr.h"
 #include "nsr_internal.h"
 
-// 1: raise the wave's issue priority while it runs a slab's MFMAs.
-#ifndef NSR_BATCH_SETPRIO
-#define NSR_BATCH_SETPRIO 0
-#endif
 // K slab of the in-workgroup GEMM (elements), float32 and float64 (eight-wave
 // workgroups).
 #ifndef NSR_BATCH_KB32
@@ -44,7 +43,6 @@
 #ifndef NSR_BATCH_GR
 #define NSR_BATCH_GR 2
 #endif
-
 
 namespace nsr {
 
@@ -287,7 +285,6 @@ __device__ double wg_gemm(int n, const T* X, int ldx, const double* XA, int64_t 
       if (active) {
         const T* xs = xsb + (sr + lr) * XS + lk;
         const T* ys = ysb + lk * YS + sc + lr;
-        if (NSR_BATCH_SETPRIO) __builtin_amdgcn_s_setprio(1);
 #pragma unroll
         for (int ks = 0; ks < KB; ks += 4) {
           const T a0 = xs[ks], a1 = xs[16 * XS + ks];
@@ -297,7 +294,6 @@ __device__ double wg_gemm(int n, const T* X, int ldx, const double* XA, int64_t 
           acc[1][0] = mfma(a1, b0, acc[1][0]);
           acc[1][1] = mfma(a1, b1, acc[1][1]);
         }
-        if (NSR_BATCH_SETPRIO) __builtin_amdgcn_s_setprio(0);
       }
     }
     if (active) {
