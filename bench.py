@@ -24,6 +24,7 @@ timed on a bounded sample.
 from __future__ import annotations
 
 import argparse
+import gc
 import hashlib
 import json
 import os
@@ -355,6 +356,13 @@ def run_small_fixed(torch, nsr, reps=300):
     return out
 
 
+def release(torch):
+    """Drop the finished leg's objects and return cached device memory."""
+    gc.collect()
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+
+
 def timeline_summary(tl, ns, groups):
     """Critical-path view of a batch from the device timeline (ms)."""
     f32 = tl[:, 1] - tl[:, 0]
@@ -651,10 +659,14 @@ def main():
         del ms
         torch.cuda.empty_cache()
     if not args.no_mixed and not fixed:
+        # Each leg starts from an empty allocator cache: the serving loop's
+        # latencies should not depend on what earlier legs left allocated.
         if not args.no_composite:
             out["composite"] = run_composite(torch, nsr, max(2, args.steps // 2), 1)
+            release(torch)
         if not args.no_batch:
             out["batch"] = run_batch(torch, nsr, 3)
+            release(torch)
         if not args.no_serving:
             out["serving"] = run_serving(torch, nsr)
 
