@@ -264,13 +264,15 @@ int richardson_ns_solve(ns_solver* s, const double* b, double* theta,
 /* ---- Batched solves of many independent systems (uneven sizes) ----------
  *
  * One submission solves `count` independent SPD systems in ONE persistent
- * kernel launch: each workgroup pulls whole systems (largest n first) and
- * runs the complete coupled solve of richardson_ns_solve for each (squaring
- * form of order opts->order, scale ||A||_F, theta_0 = b / alpha).  Products
- * run in float32 MFMA for NS_PREC_FP32, and a system whose float32 solve does
- * not reach opts->resid_tol is re-solved in float64 MFMA by the same
- * workgroup (report.precision tells which); NS_PREC_FP64 uses float64 only.
- * Richardson residuals and theta are float64 throughout. */
+ * kernel launch per precision: each workgroup pulls whole systems (largest n
+ * first) and runs the complete coupled solve of richardson_ns_solve for each
+ * (squaring form of order opts->order, scale ||A||_F or ||A||_inf / 2 + eps,
+ * theta_0 = b / alpha).  Products run in float32 MFMA for NS_PREC_FP32; the
+ * systems whose float32 solve does not reach opts->resid_tol are re-solved in
+ * float64 MFMA by a second launch (report.precision tells which);
+ * NS_PREC_FP64 uses float64 only.  Richardson residuals and theta are float64
+ * throughout.  A submission whose systems all have n <= 64 (order 2 or 4) runs
+ * a kernel that keeps each system's whole iteration in the workgroup's LDS. */
 typedef struct ns_batch ns_batch;
 
 /* Device workspace for up to `max_count` systems of size <= max_n, solved by
@@ -289,7 +291,8 @@ int ns_batch_create(int device, void* hip_stream, int64_t max_n, int max_count,
 /* Launch shape of the float32 (or float64-only) pass: waves per workgroup
  * (1, 2, 4 or 8) and number of workgroups (0: one per slot).  Set by
  * ns_batch_autotune or by the caller.  The float64 pass that re-solves the
- * systems float32 could not runs eight-wave workgroups, one per CU. */
+ * systems float32 could not runs eight-wave workgroups, one per CU.  The LDS
+ * kernel for n <= 64 runs eight waves when waves_per_group is 8, else four. */
 int ns_batch_set_launch(ns_batch* b, int waves_per_group, int groups);
 
 /* Enqueue the solves of `count` systems.  n, A, lda, b, theta are HOST arrays
@@ -299,7 +302,8 @@ int ns_batch_set_launch(ns_batch* b, int waves_per_group, int groups);
  * completion.  One submission may be in flight per handle.  Errors:
  * NS_EBUSY (previous ticket not polled to completion), NS_ENOMEM (count >
  * max_count or a system larger than max_n: the admission check), NS_EINVAL
- * (options other than the squaring form, Frobenius scale, theta0_mode 0). */
+ * (options other than the squaring form of order 2^s, the Frobenius or
+ * inf / 2 scale, theta0_mode 0). */
 int ns_batch_submit(ns_batch* b, int count, const int64_t* n, const double* const* A,
                     const int64_t* lda, const double* const* b_vec,
                     double* const* theta, const ns_solve_opts* opts, uint64_t* ticket);
@@ -310,8 +314,8 @@ int ns_batch_submit(ns_batch* b, int count, const int64_t* n, const double* cons
  * every system reached resid_tol, else NS_ENOCONV (see each report.status). */
 int ns_batch_poll(ns_batch* b, uint64_t ticket, int wait, ns_solve_report* reports);
 
-/* Project autotuner: time every launch shape (1, 2, 4 waves per workgroup x
- * 1, 2, 4, 8 workgroups per CU, within the slots) on the given batch (each
+/* Project autotuner: time every launch shape (1, 2, 4, 8 waves per workgroup
+ * x 1, 2, 4, 8 workgroups per CU, within the slots) on the given batch (each
  * candidate solves it completely, synchronously), keep the fastest with
  * ns_batch_set_launch and return it.  Same arguments as ns_batch_submit. */
 int ns_batch_autotune(ns_batch* b, int count, const int64_t* n, const double* const* A,
