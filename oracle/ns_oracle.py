@@ -20,7 +20,8 @@ printed counts pin the evaluation orders below.
 parity pins: every function here is pinned by a test in ``tests/`` against
 exact integer identities (nilpotent shift operands), printed mmm counts, the
 eigen-decomposition closed forms of eqs. (fk1)/(ermoex1), diagonal closed
-forms, and an independent Cholesky solve.
+forms, the same iteration in exact rational arithmetic on tiny systems, and
+an independent Cholesky solve.
 """
 from __future__ import annotations
 

@@ -539,3 +539,70 @@ def test_remark2_double_ns_exponent_exceeds_sri(n):
     the first step on (the F_{k-1}^n versus F_{k-1} factor)."""
     for k in range(1, 8):
         assert k * n ** (k + 1) + n ** k > oracle.sri_exponent(k, n)
+
+
+# ---------------------------------------------------------------------------
+# P6: exact rational arithmetic on tiny systems
+# ---------------------------------------------------------------------------
+
+def _q_mat(rows):
+    from fractions import Fraction
+    return [[Fraction(v) for v in r] for r in rows]
+
+
+def _q_mul(x, y):
+    from fractions import Fraction
+    n, m, k = len(x), len(y[0]), len(y)
+    return [[sum((x[i][t] * y[t][j] for t in range(k)), Fraction(0)) for j in range(m)]
+            for i in range(n)]
+
+
+def _q_add(x, y):
+    return [[a + b for a, b in zip(r, s)] for r, s in zip(x, y)]
+
+
+def _q_eye(n):
+    from fractions import Fraction
+    return [[Fraction(int(i == j)) for j in range(n)] for i in range(n)]
+
+
+@pytest.mark.parametrize("rows,bvec,order,steps", [
+    ([[4, 1, 0], [1, 3, 1], [0, 1, 2]], [1, -2, 3], 4, 4),
+    ([[2, 1], [1, 2]], [3, 1], 8, 3),
+    ([[5, 2, 1], [2, 4, 0], [1, 0, 3]], [0, 1, 1], 2, 6),
+])
+def test_iterates_match_exact_rationals(rows, bvec, order, steps):
+    """P6: G_k and theta_k of the float64 oracle (squaring form, Richardson
+    with the new G_k, theta_0 = G_0 b) against the same iteration in exact
+    rational arithmetic, where P(F) is the plain sum I + F + ... + F^(n-1)
+    (eq. ns) and alpha = ||A||_inf / 2 + 1/4 is rational (Section 2)."""
+    from fractions import Fraction
+    n = len(rows)
+    Aq = _q_mat(rows)
+    bq = [Fraction(v) for v in bvec]
+    alpha_q = Fraction(max(sum(abs(v) for v in r) for r in rows), 2) + Fraction(1, 4)
+    A = np.array(rows, dtype=np.float64)
+    b = np.array(bvec, dtype=np.float64)
+    alpha = oracle.alpha_inf_half(A, 0.25)
+    assert alpha == float(alpha_q)
+    Gq = [[Fraction(int(i == j)) / alpha_q for j in range(n)] for i in range(n)]
+    thq = [v / alpha_q for v in bq]
+    G = np.eye(n) / alpha
+    th = G @ b
+    for _ in range(steps):
+        # exact: F = I - A G, P = sum_{j<order} F^j, G <- G P
+        F = _q_add(_q_eye(n), [[-v for v in r] for r in _q_mul(Aq, Gq)])
+        Pq, Fj = _q_eye(n), _q_eye(n)
+        for _j in range(1, order):
+            Fj = _q_mul(Fj, F)
+            Pq = _q_add(Pq, Fj)
+        Gq = _q_mul(Gq, Pq)
+        rq = [bq[i] - sum(Aq[i][t] * thq[t] for t in range(n)) for i in range(n)]
+        thq = [thq[i] + sum(Gq[i][t] * rq[t] for t in range(n)) for i in range(n)]
+        # oracle
+        G = oracle.ns_step(A, G, order, "squaring")
+        th, _ = oracle.richardson_update(A, b, th, G)
+        Ge = np.array([[float(v) for v in r] for r in Gq])
+        te = np.array([float(v) for v in thq])
+        assert np.max(np.abs(G - Ge)) <= 1e-13 * np.max(np.abs(Ge))
+        assert np.max(np.abs(th - te)) <= 1e-13 * np.max(np.abs(te))
