@@ -232,6 +232,52 @@ def run_comparisons(torch, nsr, A, b, sysm, n, resid_tol, k_max):
     return out
 
 
+def run_preconditioning(torch, nsr, A, b, sysm, n, resid_tol, k_max):
+    """Section 2 options at N = 4096 (float64, order 8): the diagonal
+    preconditioner S = diag(A) against alpha = ||A||_F on a diagonally
+    dominant system whose diagonal spans three decades (inputs.spd_jacobi),
+    and the initial series of order h (eq. g01) on the headline system."""
+    def timed(s, bb, **kw):
+        th = torch.zeros_like(bb)
+        times = []
+        for _ in range(2):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            rep = s.solve(bb, th, order=8, resid_tol=resid_tol, k_max=k_max, refine_max=64,
+                          raise_on_error=False, **kw)
+            torch.cuda.synchronize()
+            times.append(time.perf_counter() - t0)
+        return rep, th, times[-1]
+
+    out = {"diagonal": {"workload": f"spd_jacobi{n}_3decades", "n": n}, "initial_series": {
+        "workload": "spd4096_k1e4_o8"}}
+    jac = inputs.spd_jacobi(n, seed=9)
+    Aj = torch.from_numpy(jac.A).to("cuda")
+    bj = torch.from_numpy(jac.b).to("cuda")
+    s = nsr.Solver(n)
+    s.bind(Aj)
+    for name, scale in (("frobenius", nsr.SCALE_FROBENIUS), ("diag", nsr.SCALE_DIAG)):
+        rep, th, dt = timed(s, bj, scale=scale)
+        x = th.cpu().numpy()
+        out["diagonal"][name] = {
+            "ms_per_solve": dt * 1e3, "ns_steps": rep.ns_steps, "refine_steps": rep.refine_steps,
+            "mmm": rep.mmm, "status": rep.status,
+            "rel_resid": float(np.linalg.norm(jac.b - jac.A @ x) / np.linalg.norm(jac.b))}
+        log(f"preconditioner {name}: {dt * 1e3:.1f} ms ns_steps={rep.ns_steps} mmm={rep.mmm}")
+    s.bind(A)
+    for h, p, w_ in ((1, 0, 0), (2, 1, 1), (4, 1, 2)):
+        kw = {} if h == 1 else dict(init_order=h, init_p=p, init_w=w_)
+        rep, th, dt = timed(s, b, **kw)
+        x = th.cpu().numpy()
+        out["initial_series"][f"h{h}"] = {
+            "ms_per_solve": dt * 1e3, "ns_steps": rep.ns_steps, "refine_steps": rep.refine_steps,
+            "mmm": rep.mmm, "status": rep.status,
+            "rel_resid": float(np.linalg.norm(sysm.b - sysm.A @ x) / np.linalg.norm(sysm.b))}
+        log(f"initial series h={h}: {dt * 1e3:.1f} ms ns_steps={rep.ns_steps} mmm={rep.mmm}")
+    s.close()
+    return out
+
+
 def run_fig4_analogue(torch, nsr, steps=7):
     """Synthetic analogue of the paper's last comparison (Section 7): three
     close frequencies (N = 6, kappa ~ 4e3); per-step parameter error of the
@@ -635,6 +681,8 @@ def main():
                               "variants": run_comparisons(torch, nsr, A, b, sysm, n,
                                                           w["resid_tol"], w["k_max"])}
         out["fig4_analogue"] = run_fig4_analogue(torch, nsr)
+        out["preconditioning"] = run_preconditioning(torch, nsr, A, b, sysm, n, w["resid_tol"],
+                                                     w["k_max"])
         torch.cuda.empty_cache()
 
     if not args.no_mixed and not args.no_mixed4096 and not fixed:
