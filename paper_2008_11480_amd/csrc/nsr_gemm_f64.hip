@@ -104,6 +104,13 @@ __device__ __forceinline__ double epi_value(const GemmF64Args& p, int64_t row, i
   return v;
 }
 
+// Mirror of the symmetric-output element D[row][col] = v: D[col][row] (equal
+// to v, or v msc[col] / msc[row] for a diagonally similar output).
+__device__ __forceinline__ double mirror_value(const GemmF64Args& p, int64_t row, int64_t col,
+                                               double v) {
+  return p.msc ? v * (p.msc[col] / p.msc[row]) : v;
+}
+
 // The same with the addends loaded beforehand (0 where absent).
 __device__ __forceinline__ double epi_value(const GemmF64Args& p, int64_t row, int64_t col,
                                             double acc, double e1, double e2) {
@@ -344,11 +351,20 @@ gemm_f64_kernel(GemmF64Args p, int tiles_m, int tiles_n, int dp, int splits, int
           if (SYM) acc[i][j][r] = v;
           if (!diag_tile) {
             p.D[row * p.ldd + col] = v;
-            ss += (SYM ? 2.0 : 1.0) * v * v;
+            if (SYM) {
+              const double w = mirror_value(p, row, col, v);
+              ss += v * v + w * w;
+            } else {
+              ss += v * v;
+            }
           } else if (row <= col) {
             p.D[row * p.ldd + col] = v;
-            if (row < col) p.D[col * p.ldd + row] = v;
-            ss += (row < col ? 2.0 : 1.0) * v * v;
+            double w = 0.0;
+            if (row < col) {
+              w = mirror_value(p, row, col, v);
+              p.D[col * p.ldd + row] = w;
+            }
+            ss += v * v + w * w;
           }
         }
       }
@@ -373,7 +389,8 @@ gemm_f64_kernel(GemmF64Args p, int tiles_m, int tiles_n, int dp, int splits, int
       for (int idx = tid; idx < WTN * BM; idx += NT) {
         const int c = idx / BM, rr = idx % BM;
         const int64_t grow = n0 + half * WTN + c, gcol = m0 + rr;
-        if (grow < N && gcol < M) p.D[grow * p.ldd + gcol] = S[c * MS + rr];
+        if (grow < N && gcol < M)
+          p.D[grow * p.ldd + gcol] = mirror_value(p, gcol, grow, S[c * MS + rr]);
       }
       __syncthreads();
     }
@@ -444,11 +461,20 @@ gemm_f64_split_fixup(GemmF64Args p, int tiles_m, int tiles_n, int dp, int splits
       if (SYM) S[(jj * 16 + lr) * SS + lk + 4 * r] = v;
       if (!diag_tile) {
         p.D[row * p.ldd + col] = v;
-        ss += (SYM ? 2.0 : 1.0) * v * v;
+        if (SYM) {
+          const double w = mirror_value(p, row, col, v);
+          ss += v * v + w * w;
+        } else {
+          ss += v * v;
+        }
       } else if (row <= col) {
         p.D[row * p.ldd + col] = v;
-        if (row < col) p.D[col * p.ldd + row] = v;
-        ss += (row < col ? 2.0 : 1.0) * v * v;
+        double w = 0.0;
+        if (row < col) {
+          w = mirror_value(p, row, col, v);
+          p.D[col * p.ldd + row] = w;
+        }
+        ss += v * v + w * w;
       }
     }
   }
@@ -457,7 +483,8 @@ gemm_f64_split_fixup(GemmF64Args p, int tiles_m, int tiles_n, int dp, int splits
     for (int idx = tid; idx < WTN * 16; idx += 256) {
       const int c = idx >> 4, rr = idx & 15;
       const int64_t grow = n0 + wn * WTN + c, gcol = m0 + wm * WTM + i * 16 + rr;
-      if (grow < N && gcol < M) p.D[grow * p.ldd + gcol] = S[c * SS + rr];
+      if (grow < N && gcol < M)
+        p.D[grow * p.ldd + gcol] = mirror_value(p, gcol, grow, S[c * SS + rr]);
     }
   }
   if (p.partial) {

@@ -22,6 +22,9 @@ struct GemmF64Args {
                      // diagonal are computed, the lower triangle is their mirror
   double* sk;        // scratch for split-K tail tiles (may be null: no split)
   int64_t sk_cap;    // its capacity in doubles
+  const double* msc; // symmetric output only: null for an exactly symmetric D;
+                     // else D[j][i] = D[i][j] msc[j] / msc[i] (D = S^(1/2) D_s
+                     // S^(-1/2) with D_s symmetric, S = diag(msc))
 };
 
 // D = diag * I + scale * (X op(Y)) + E1 + E2 with float32 output (and an

@@ -236,8 +236,11 @@ int mm(ns_solver* s, Mat& D, const Mat* X, const Mat& Y, const Mat* E1, const Ma
     // G it multiplies, and mirroring those products would feed the part of
     // the rounding error that does not commute with A back with a gain ~kappa
     // per step.  Errors in the powers only perturb P(F) and enter F_{k+1} as
-    // O(||F|| ||[A, G]||).
-    a.sym = (s->symmetric && kind == K_POWER && !s->diag_scale) ? 1 : 0;
+    // O(||F|| ||[A, G]||).  With S = diag(A), F = I - A S^-1 = S^(1/2) F_s
+    // S^(-1/2) with F_s symmetric, so every polynomial in F has
+    // D[j][i] = D[i][j] s_j / s_i: the mirror is scaled by S.
+    a.sym = (s->symmetric && kind == K_POWER) ? 1 : 0;
+    a.msc = (a.sym && s->diag_scale) ? s->sdiag : nullptr;
     a.sk = s->sk;
     a.sk_cap = s->sk_cap;
     np = launch_gemm_f64(a, s->stream);
@@ -265,7 +268,7 @@ int mm(ns_solver* s, Mat& D, const Mat* X, const Mat& Y, const Mat* E1, const Ma
   if (np < 0) return fail(NS_EHIP, "GEMM launch failed: %s", hipGetErrorString(hipGetLastError()));
   // algorithmic flop: 2 n^3, or n^2 (n + 1) when only one triangle is formed
   const double nn = (double)s->n;
-  const bool half = is_f64(s) && s->symmetric && kind == K_POWER && !s->diag_scale;
+  const bool half = is_f64(s) && s->symmetric && kind == K_POWER;
   const double flop = half ? nn * nn * (nn + 1.0) : 2.0 * nn * nn * nn;
   if (s->timing) {
     HIP_TRY(hipEventRecord(ee, s->stream));
