@@ -510,6 +510,33 @@ def test_diag_preconditioner_matches_oracle(torch, prec, order, form):
     assert rep.ns_steps < rep_f.ns_steps
 
 
+@pytest.mark.parametrize("n,order", [(211, 8), (300, 4), (1100, 8), (4096, 8)])
+def test_diag_scaled_mirror_matches_full_products(torch, n, order):
+    """With S = diag(A) the float64 power products compute their upper tiles
+    and write the lower triangle as D_ji = D_ij s_j / s_i (F = S^1/2 F_s
+    S^-1/2).  Same solve with every product in full: the ||F_k|| traces and
+    theta agree to rounding (n = 4096 cuts the symmetric products' last,
+    partial round of tiles along K, so the mirror also runs in the fixup)."""
+    sysm = inputs.spd_jacobi(n, seed=n)
+    A, b = to_dev(torch, sysm.A), to_dev(torch, sysm.b)
+    s = nsr.Solver(n)
+    s.bind(A)
+    ths = []
+    reps = []
+    for sym in (True, False):
+        s.set_symmetric(sym)
+        th = torch.zeros_like(b)
+        reps.append(s.solve(b, th, order=order, scale=nsr.SCALE_DIAG, resid_tol=1e-13))
+        ths.append(th.cpu().numpy())
+    r_sym, r_full = reps
+    assert r_sym.ns_steps == r_full.ns_steps
+    floor = max(min(r_sym.fnorm_hist), min(r_full.fnorm_hist))
+    for a_, b_ in zip(r_sym.fnorm_hist, r_full.fnorm_hist):
+        assert abs(a_ - b_) <= 1e-11 * b_ + 10 * floor
+    assert np.linalg.norm(ths[0] - ths[1]) <= 1e-12 * np.linalg.norm(ths[1])
+    assert r_sym.gemm_flop < r_full.gemm_flop
+
+
 def test_diag_preconditioner_errors(torch):
     a = np.eye(8)
     a[3, 3] = 0.0
