@@ -254,11 +254,13 @@ class GpuExecutor:
         with torch.cuda.stream(self.batch_stream):
             t = self.batch.submit(As, bs, ths, order=4, resid_tol=self.resid_tol,
                                   refine_max=self.refine_max)
-            reps = self.batch.poll(t, wait=True)
-        for r, rep in zip(batch, reps):
-            r.status = {nsr.NS_OK: "ok", nsr.NS_ENOCONV: "noconv"}.get(rep.status, "diverged")
-            r.precision = rep.precision
-            r.ns_steps = rep.ns_steps
+            cols = self.batch.poll_arrays(t, wait=True)
+        names = {nsr.NS_OK: "ok", nsr.NS_ENOCONV: "noconv"}
+        for r, st, prec, steps in zip(batch, cols["status"].tolist(), cols["precision"].tolist(),
+                                      cols["ns_steps"].tolist()):
+            r.status = names.get(st, "diverged")
+            r.precision = prec
+            r.ns_steps = steps
 
 
 def make_requests(trace, device="cuda") -> list[Request]:
