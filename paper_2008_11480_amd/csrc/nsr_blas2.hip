@@ -176,19 +176,55 @@ convert_kernel(const S* __restrict__ src, int64_t lds, int64_t n, D* __restrict_
   dst[row * ldd + c] = (D)src[row * lds + c];
 }
 
+template <typename T> struct Pair;
+template <> struct Pair<double> { typedef double2 type; };
+template <> struct Pair<float> { typedef float2 type; };
+
+// Dot product of one matrix row with x (float64 accumulate), by one wave,
+// lane-partial (the caller reduces over the wave).  vec: the row and x are
+// read two elements per lane (16-byte row loads for float64), two chunks of
+// 128 columns in flight with separate partial sums; needs the row and x
+// aligned to two elements.
+template <typename T>
+__device__ __forceinline__ double row_dot(const T* __restrict__ a, const double* __restrict__ x,
+                                          int64_t n, bool vec) {
+  const int lane = threadIdx.x & 63;
+  double s0 = 0.0, s1 = 0.0;
+  if (vec) {
+    typedef typename Pair<T>::type P;
+    const int64_t n2 = n & ~(int64_t)1;
+    int64_t c = 2 * lane;
+    for (; c + 128 < n2; c += 256) {
+      const P a0 = *reinterpret_cast<const P*>(a + c);
+      const P a1 = *reinterpret_cast<const P*>(a + c + 128);
+      const double2 x0 = *reinterpret_cast<const double2*>(x + c);
+      const double2 x1 = *reinterpret_cast<const double2*>(x + c + 128);
+      s0 += (double)a0.x * x0.x + (double)a0.y * x0.y;
+      s1 += (double)a1.x * x1.x + (double)a1.y * x1.y;
+    }
+    if (c < n2) {
+      const P a0 = *reinterpret_cast<const P*>(a + c);
+      const double2 x0 = *reinterpret_cast<const double2*>(x + c);
+      s0 += (double)a0.x * x0.x + (double)a0.y * x0.y;
+    }
+    if ((n & 1) && lane == 0) s1 += (double)a[n - 1] * x[n - 1];
+  } else {
+    for (int64_t c = lane; c < n; c += 64) s0 += (double)a[c] * x[c];
+  }
+  return s0 + s1;
+}
+
 // r = b - A theta: one wave per row, 4 rows per block; partial sum of r^2.
 __global__ void __launch_bounds__(kThreads)
 gemv_resid_kernel(const double* __restrict__ A, int64_t lda, int64_t n,
                   const double* __restrict__ b, const double* __restrict__ theta,
-                  double* __restrict__ r, double* __restrict__ partial) {
+                  double* __restrict__ r, double* __restrict__ partial, int vec) {
   __shared__ double red[4];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int64_t row = (int64_t)blockIdx.x * 4 + wave;
   double rv = 0.0;
   if (row < n) {
-    const double* a = A + row * lda;
-    double s = 0.0;
-    for (int64_t c = lane; c < n; c += 64) s += a[c] * theta[c];
+    double s = row_dot(A + row * lda, theta, n, vec != 0);
     s = wave_sum(s);
     rv = b[row] - s;
     if (lane == 0) r[row] = rv;
@@ -202,13 +238,11 @@ gemv_resid_kernel(const double* __restrict__ A, int64_t lda, int64_t n,
 template <typename T>
 __global__ void __launch_bounds__(kThreads)
 gemv_update_kernel(const T* __restrict__ G, int64_t ldg, int64_t n,
-                   const double* __restrict__ r, double* __restrict__ theta) {
+                   const double* __restrict__ r, double* __restrict__ theta, int vec) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int64_t row = (int64_t)blockIdx.x * 4 + wave;
   if (row >= n) return;
-  const T* g = G + row * ldg;
-  double s = 0.0;
-  for (int64_t c = lane; c < n; c += 64) s += (double)g[c] * r[c];
+  double s = row_dot(G + row * ldg, r, n, vec != 0);
   s = wave_sum(s);
   if (lane == 0) theta[row] += s;
 }
@@ -218,13 +252,11 @@ gemv_update_kernel(const T* __restrict__ G, int64_t ldg, int64_t n,
 template <typename T>
 __global__ void __launch_bounds__(kThreads)
 gemv_kernel(const T* __restrict__ M, int64_t ldm, int64_t n, const double* __restrict__ x,
-            const double* __restrict__ z, double* __restrict__ y, int accumulate) {
+            const double* __restrict__ z, double* __restrict__ y, int accumulate, int vec) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int64_t row = (int64_t)blockIdx.x * 4 + wave;
   if (row >= n) return;
-  const T* m = M + row * ldm;
-  double s = 0.0;
-  for (int64_t c = lane; c < n; c += 64) s += (double)m[c] * x[c];
+  double s = row_dot(M + row * ldm, x, n, vec != 0);
   s = wave_sum(s);
   if (lane == 0) {
     if (z) s += z[row];
@@ -257,6 +289,14 @@ vec_sumsq_kernel(const double* __restrict__ v, int64_t n, double* __restrict__ p
 
 int64_t sumsq_partials(int64_t n) { return (n + kRowsPerBlock - 1) / kRowsPerBlock; }
 int64_t gemv_partials(int64_t n) { return (n + 3) / 4; }
+
+// Rows of M (leading dimension ld) and the vector x can be read two elements
+// at a time: every row starts on a two-element boundary.
+template <typename T>
+bool pair_aligned(const T* M, int64_t ld, const double* x) {
+  return (ld % 2) == 0 && (reinterpret_cast<uintptr_t>(M) % (2 * sizeof(T))) == 0 &&
+         (reinterpret_cast<uintptr_t>(x) % 16) == 0;
+}
 
 int64_t launch_sumsq(const double* A, int64_t lda, int64_t n, double* partial, hipStream_t st) {
   const int64_t nb = sumsq_partials(n);
@@ -336,7 +376,7 @@ int64_t launch_gemv_resid(const double* A, int64_t lda, int64_t n, const double*
                           const double* theta, double* r, double* partial, hipStream_t st) {
   const int64_t nb = gemv_partials(n);
   hipLaunchKernelGGL(gemv_resid_kernel, dim3((unsigned)nb), dim3(kThreads), 0, st, A, lda, n, b,
-                     theta, r, partial);
+                     theta, r, partial, pair_aligned(A, lda, theta) ? 1 : 0);
   return nb;
 }
 
@@ -344,7 +384,7 @@ template <typename T>
 void launch_gemv_update(const T* G, int64_t ldg, int64_t n, const double* r, double* theta,
                         hipStream_t st) {
   hipLaunchKernelGGL(gemv_update_kernel<T>, dim3((unsigned)((n + 3) / 4)), dim3(kThreads), 0, st, G,
-                     ldg, n, r, theta);
+                     ldg, n, r, theta, pair_aligned(G, ldg, r) ? 1 : 0);
 }
 template void launch_gemv_update<double>(const double*, int64_t, int64_t, const double*, double*,
                                          hipStream_t);
@@ -355,7 +395,7 @@ template <typename T>
 void launch_gemv(const T* M, int64_t ldm, int64_t n, const double* x, const double* z, double* y,
                  int accumulate, hipStream_t st) {
   hipLaunchKernelGGL(gemv_kernel<T>, dim3((unsigned)((n + 3) / 4)), dim3(kThreads), 0, st, M, ldm,
-                     n, x, z, y, accumulate);
+                     n, x, z, y, accumulate, pair_aligned(M, ldm, x) ? 1 : 0);
 }
 template void launch_gemv<double>(const double*, int64_t, int64_t, const double*, const double*,
                                   double*, int, hipStream_t);
