@@ -100,16 +100,32 @@ init_resid_kernel(const double* __restrict__ A, int64_t lda, int64_t n,
   const double inv = 1.0 / alpha[0];
   const int64_t r0 = (int64_t)blockIdx.x * kRowsPerBlock;
   double s = 0.0;
+  // Each thread loads kEw elements (and their S entries) before it stores
+  // them: loads and stores share one in-order completion counter, so a load
+  // issued after a store waits for it.
+  constexpr int kEw = 8;
   for (int rr = 0; rr < kRowsPerBlock; ++rr) {
     const int64_t row = r0 + rr;
     if (row >= n) break;
-    for (int64_t c = threadIdx.x; c < n; c += kThreads) {
-      double v = sdiag ? -A[row * lda + c] / sdiag[c] : -A[row * lda + c] * inv;
-      if (c == row) v += 1.0;
-      const T t = (T)v;
-      F[row * ldf + c] = t;
-      if (Fb) Fb[row * ldf + c] = __builtin_bit_cast(uint16_t, (__bf16)(float)t);
-      s += (double)t * (double)t;
+    for (int64_t c0 = threadIdx.x; c0 < n; c0 += (int64_t)kThreads * kEw) {
+      double a[kEw], sd[kEw];
+#pragma unroll
+      for (int u = 0; u < kEw; ++u) {
+        const int64_t c = c0 + (int64_t)u * kThreads;
+        a[u] = c < n ? A[row * lda + c] : 0.0;
+        sd[u] = (sdiag && c < n) ? sdiag[c] : 1.0;
+      }
+#pragma unroll
+      for (int u = 0; u < kEw; ++u) {
+        const int64_t c = c0 + (int64_t)u * kThreads;
+        if (c >= n) break;
+        double v = sdiag ? -a[u] / sd[u] : -a[u] * inv;
+        if (c == row) v += 1.0;
+        const T t = (T)v;
+        F[row * ldf + c] = t;
+        if (Fb) Fb[row * ldf + c] = __builtin_bit_cast(uint16_t, (__bf16)(float)t);
+        s += (double)t * (double)t;
+      }
     }
   }
   const double tt = block_sum(s, red);
