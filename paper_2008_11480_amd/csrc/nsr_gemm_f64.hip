@@ -95,15 +95,6 @@ __device__ __forceinline__ void tile_at(bool sym, int u, int tiles_m, int tiles_
     group_tile(u, tiles_m, tiles_n, tm, tn);
 }
 
-__device__ __forceinline__ double epi_value(const GemmF64Args& p, int64_t row, int64_t col,
-                                            double acc) {
-  double v = p.scale * acc;
-  if (row == col) v += p.diag;
-  if (p.E1) v += p.E1[row * p.lde1 + col];
-  if (p.E2) v += p.E2[row * p.lde2 + col];
-  return v;
-}
-
 // Mirror of the symmetric-output element D[row][col] = v: D[col][row] (equal
 // to v, or v msc[col] / msc[row] for a diagonally similar output).
 __device__ __forceinline__ double mirror_value(const GemmF64Args& p, int64_t row, int64_t col,
@@ -111,7 +102,8 @@ __device__ __forceinline__ double mirror_value(const GemmF64Args& p, int64_t row
   return p.msc ? v * (p.msc[col] / p.msc[row]) : v;
 }
 
-// The same with the addends loaded beforehand (0 where absent).
+// Output element: scale acc + diag [row == col] + E1 + E2, with the addends
+// loaded beforehand (0 where absent).
 __device__ __forceinline__ double epi_value(const GemmF64Args& p, int64_t row, int64_t col,
                                             double acc, double e1, double e2) {
   double v = p.scale * acc;
@@ -451,13 +443,15 @@ gemm_f64_split_fixup(GemmF64Args p, int tiles_m, int tiles_n, int dp, int splits
 #pragma unroll
     for (int r = 0; r < 4; ++r) acc4[r] += src[(size_t)q * TS + r * 64];
   double ss = 0.0;
+  double e1[4], e2[4];
+  load_addends(p, m0 + wm * WTM + i * 16 + lk, n0 + wn * WTN + jj * 16 + lr, e1, e2);
 #pragma unroll
   for (int r = 0; r < 4; ++r) {
     const double a = acc4[r];
     const int64_t row = m0 + wm * WTM + i * 16 + lk + 4 * r;
     const int64_t col = n0 + wn * WTN + jj * 16 + lr;
     if (row < M && col < N) {
-      const double v = epi_value(p, row, col, a);
+      const double v = epi_value(p, row, col, a, e1[r], e2[r]);
       if (SYM) S[(jj * 16 + lr) * SS + lk + 4 * r] = v;
       if (!diag_tile) {
         p.D[row * p.ldd + col] = v;
