@@ -44,10 +44,13 @@ if int(os.environ.get("GPU_MAX_HW_QUEUES", "4") or 4) < 16:
 
 from paper_2008_11480_amd import inputs  # noqa: E402
 
-PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3, "bf16": 2500.0}
+# f32_split: float32-class products of split half-precision operands, three
+# fp16 MFMA products each, so their ceiling is a third of the 2.5 PFLOP/s
+# fp16 peak (frac_of_peak = fp16 matrix-core utilisation).
+PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3, "bf16": 2500.0, "f32_split": 2500.0 / 3}
 GEMM_KERNEL_SRC = os.path.join(ROOT, "paper_2008_11480_amd", "csrc", "nsr_gemm_f64.hip")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "gemm_f64_spd4096_traffic.json")
-KIND = {"f64": 1, "f32": 2, "bf16": 3}
+KIND = {"f64": 1, "f32": 2, "bf16": 3, "f32_split": 4}
 
 
 def log(msg):
@@ -175,6 +178,9 @@ def run_composite(torch, nsr, steps, warmup):
     theta = torch.zeros_like(b)
     for label, prec, form in (("mixed_composite", nsr.PREC_MIXED_BF16, "composite_double"),
                               ("mixed_factorized", nsr.PREC_MIXED_BF16, "squaring"),
+                              ("mixed_split_composite", nsr.PREC_MIXED_SPLIT,
+                               "composite_double"),
+                              ("mixed_split_factorized", nsr.PREC_MIXED_SPLIT, "squaring"),
                               ("fp64_composite", nsr.PREC_FP64, "composite_double")):
         solver = nsr.Solver(n, precision=prec, composite=form == "composite_double")
         solver.bind(A)
@@ -188,8 +194,9 @@ def run_composite(torch, nsr, steps, warmup):
                       "gemm": m["gemm"], **report_of(m["last"])}
         del solver
         torch.cuda.empty_cache()
-    out["speedup_mixed_composite_vs_fp64_composite"] = (
-        out["mixed_composite"]["solves_per_s"] / out["fp64_composite"]["solves_per_s"])
+    for label in ("mixed_composite", "mixed_split_composite"):
+        out[f"speedup_{label}_vs_fp64_composite"] = (
+            out[label]["solves_per_s"] / out["fp64_composite"]["solves_per_s"])
     return out
 
 
@@ -705,6 +712,26 @@ def main():
             "gemm": mm["gemm"], **report_of(mm["last"]),
         }
         del ms
+        torch.cuda.empty_cache()
+        # The same with float32-class products from split half-precision
+        # operands (residual and G-side) instead of float32 MFMA.
+        ss = nsr.Solver(n, precision=nsr.PREC_MIXED_SPLIT, composite=False)
+        ss.bind(A)
+        ths = torch.zeros_like(b)
+        msp = measure(torch, ss, b, ths, kwm, args.steps, args.warmup, "mixed_split")
+        thc = ths.cpu().numpy()
+        out["mixed_split"] = {
+            "workload": args.workload, "precision": "mixed (bf16 powers, residual and G-side "
+                                                  "from split fp16 operands, fp64 Richardson)",
+            "solves_per_s": msp["solves_per_s"], "ms_per_solve": msp["ms_per_solve"],
+            "speedup_vs_fp64": msp["solves_per_s"] / m["solves_per_s"],
+            "rel_resid": float(np.linalg.norm(sysm.b - sysm.A @ thc) / np.linalg.norm(sysm.b)),
+            "fwd_err_vs_closed_form": float(np.linalg.norm(thc - theta_star)
+                                            / np.linalg.norm(theta_star)),
+            "latency_ms_p50": msp["latency_ms_p50"], "latency_ms_p99": msp["latency_ms_p99"],
+            "gemm": msp["gemm"], **report_of(msp["last"]),
+        }
+        del ss
         torch.cuda.empty_cache()
     if not args.no_mixed and not fixed:
         # Each leg starts from an empty allocator cache: the serving loop's

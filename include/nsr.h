@@ -62,9 +62,14 @@ typedef enum {
 typedef enum {
   NS_PREC_FP64 = 0,       /* every product and vector in float64             */
   NS_PREC_FP32 = 1,       /* products in float32 MFMA, Richardson in float64 */
-  NS_PREC_MIXED_BF16 = 2  /* powers of F in bf16 MFMA (fp32 accumulate), the
+  NS_PREC_MIXED_BF16 = 2, /* powers of F in bf16 MFMA (fp32 accumulate), the
                              residual and G-side products in float32,
                              Richardson in float64                           */
+  NS_PREC_MIXED_SPLIT = 3 /* as NS_PREC_MIXED_BF16, but the residual, G-side
+                             and merge products are float32-class products
+                             of split half-precision operands on the
+                             half-precision matrix cores (ns_gemm_f32_split:
+                             22-bit operands, float32 accumulation)          */
 } ns_precision;
 
 typedef enum {
@@ -340,7 +345,8 @@ int ns_batch_destroy(ns_batch* b);
  * the number of timed GEMM launches, their summed duration (ms) and their
  * summed algorithmic flop (2 m n k each) since the last reset, synchronizing
  * the stream.  kind: 0 = all GEMMs, 1 = float64 GEMMs, 2 = float32,
- * 3 = bf16. */
+ * 3 = bf16, 4 = split half-precision (the interval includes the operand
+ * split passes). */
 int ns_timing_enable(ns_solver* s, int enable);
 int ns_timing_read(ns_solver* s, int kind, int64_t* launches, double* total_ms,
                    double* flop);
@@ -417,8 +423,35 @@ int ns_gemm_bf16_nt(void* hip_stream, int64_t m, int64_t n, int64_t k,
                     const float* E1, int64_t lde1, const float* E2, int64_t lde2,
                     float diag, float scale, double* sumsq_out);
 
-/* Number of per-tile partial sums ns_gemm_f32 / ns_gemm_bf16_nt write. */
+/* Number of per-tile partial sums ns_gemm_f32 / ns_gemm_bf16_nt /
+ * ns_gemm_f32_split write. */
 int64_t ns_gemm_lp_partials(int64_t m, int64_t n);
+
+/* float32-class product on the half-precision matrix cores: the operation,
+ * operands and outputs of ns_gemm_f32 (D = diag I + scale (X Y) + E1 + E2,
+ * X: m x k, Y: k x n, row-major float32), computed from split operands.
+ * Each operand is scaled by a power of two 2^e that brings its largest
+ * magnitude into [2^14, 2^15) and written as two IEEE half-precision planes,
+ * hi = half(x 2^e) and lo = half(x 2^e - hi) (22 significant bits; Y is
+ * stored transposed); the product is hi hi + hi lo + lo hi with float32
+ * accumulation (v_mfma_f32_32x32x16_f16), scaled back by 2^-(ex + ey).
+ * Error: float32 accumulation plus operand rounding below 2^-21 relative
+ * (2^-24 for float32 operands).  Scale exponents are clamped to [-100, 100];
+ * entries below 2^-24 of the largest magnitude lose relative accuracy (half
+ * subnormals), and a non-finite operand gives non-finite outputs.
+ * The mixed-precision solver uses this product for the residual, the
+ * G-side update and the composite merge (NS_PREC_MIXED_SPLIT).
+ * scratch: device memory of ns_gemm_f32_split_scratch_bytes(m, n, k) bytes,
+ * 256-byte aligned, used only by the work this call enqueues (calls that
+ * share it must be ordered on one stream).  NS_ENOMEM if smaller, NS_EINVAL
+ * if misaligned; other errors as ns_gemm_f32. */
+size_t ns_gemm_f32_split_scratch_bytes(int64_t m, int64_t n, int64_t k);
+int ns_gemm_f32_split(void* hip_stream, int64_t m, int64_t n, int64_t k,
+                      const float* X, int64_t ldx, const float* Y, int64_t ldy,
+                      float* D, int64_t ldd, uint16_t* Db, int64_t lddb,
+                      const float* E1, int64_t lde1, const float* E2, int64_t lde2,
+                      float diag, float scale, double* sumsq_out,
+                      void* scratch, size_t scratch_bytes);
 
 const char* ns_status_string(int status);
 const char* ns_last_error(void);

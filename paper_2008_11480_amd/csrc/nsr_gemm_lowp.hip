@@ -434,6 +434,371 @@ gemm_bf16_nt_kernel(GemmLpArgs p, int tiles_m, int tiles_n) {
   write_partial<WGM * WGN>(p, ss, red, tm, tn, tiles_n);
 }
 
+// ---------------------------------------------------------------------------
+// float32-class product from split half-precision operands
+// ---------------------------------------------------------------------------
+// A float32 operand scaled by 2^e (max |x| 2^e in [2^14, 2^15), inside the
+// half-precision range) is written as hi + lo with hi = half(x 2^e) and
+// lo = half(x 2^e - hi); x 2^e - hi is exact in float32 and below 2^-11 of
+// |x 2^e|, so hi + lo keeps 22 significant bits.  X Y^T then takes three
+// half-precision products, hi hi^T + hi lo^T + lo hi^T (the dropped lo lo^T
+// is below 2^-22 relative), accumulated in float32.
+
+// Exponent of the split scale from per-block maxima (every thread of the
+// block returns the same value): 0 for a zero or non-finite maximum, so
+// infinities and NaNs reach the output unchanged.
+__device__ int split_exponent(const float* part, int64_t nparts, float* red) {
+  float m = 0.0f;
+  for (int64_t i = threadIdx.x; i < nparts; i += blockDim.x) m = fmaxf(m, part[i]);
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) m = fmaxf(m, __shfl_xor(m, off, 64));
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
+  __syncthreads();
+  float t = 0.0f;
+  for (int w = 0; w < (int)(blockDim.x >> 6); ++w) t = fmaxf(t, red[w]);
+  if (!(t > 0.0f) || !(t < INFINITY)) return 0;
+  const int e = 14 - ilogbf(t);
+  return e < -100 ? -100 : (e > 100 ? 100 : e);
+}
+
+__device__ __forceinline__ void split_one(float x, float s, uint16_t& h, uint16_t& l) {
+  const float xs = x * s;
+  const _Float16 hh = (_Float16)xs;
+  const _Float16 ll = (_Float16)(xs - (float)hh);
+  h = __builtin_bit_cast(uint16_t, hh);
+  l = __builtin_bit_cast(uint16_t, ll);
+}
+
+__global__ void __launch_bounds__(256) absmax_kernel(const float* X, int64_t ld, int64_t rows,
+                                                     int64_t cols, bool vec, float* part) {
+  __shared__ float red[4];
+  float m = 0.0f;
+  for (int64_t r = blockIdx.x; r < rows; r += gridDim.x) {
+    const float* row = X + r * ld;
+    if (vec) {
+      const int64_t c4 = cols >> 2;
+      for (int64_t c = threadIdx.x; c < c4; c += 256) {
+        const float4 v = reinterpret_cast<const float4*>(row)[c];
+        m = fmaxf(m, fmaxf(fmaxf(fabsf(v.x), fabsf(v.y)), fmaxf(fabsf(v.z), fabsf(v.w))));
+      }
+      for (int64_t c = (c4 << 2) + threadIdx.x; c < cols; c += 256) m = fmaxf(m, fabsf(row[c]));
+    } else {
+      for (int64_t c = threadIdx.x; c < cols; c += 256) m = fmaxf(m, fabsf(row[c]));
+    }
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) m = fmaxf(m, __shfl_xor(m, off, 64));
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
+  __syncthreads();
+  if (threadIdx.x == 0)
+    part[blockIdx.x] = fmaxf(fmaxf(red[0], red[1]), fmaxf(red[2], red[3]));
+}
+
+// Row-major planes: each thread splits 8 consecutive elements of a row.
+__global__ void __launch_bounds__(256) split_rows_kernel(const float* X, int64_t ld, int64_t rows,
+                                                         int64_t cols, bool vec, const float* part,
+                                                         int64_t nparts, uint16_t* hi,
+                                                         uint16_t* lo, int64_t ldh,
+                                                         float* exp_out) {
+  __shared__ float red[4];
+  const int e = split_exponent(part, nparts, red);
+  const float s = ldexpf(1.0f, e);
+  if (blockIdx.x == 0 && threadIdx.x == 0) exp_out[0] = (float)e;
+  const int64_t c8 = (cols + 7) >> 3;
+  const int64_t total = rows * c8;
+  for (int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x; q < total;
+       q += (int64_t)gridDim.x * 256) {
+    const int64_t r = q / c8, c = (q - r * c8) * 8;
+    const float* src = X + r * ld + c;
+    const bool full = c + 8 <= cols;
+    float v[8];
+    if (vec && full) {
+      const float4 a = reinterpret_cast<const float4*>(src)[0];
+      const float4 b = reinterpret_cast<const float4*>(src)[1];
+      v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w;
+      v[4] = b.x; v[5] = b.y; v[6] = b.z; v[7] = b.w;
+    } else {
+#pragma unroll
+      for (int i = 0; i < 8; ++i) v[i] = (c + i < cols) ? src[i] : 0.0f;
+    }
+    uint16_t h[8], l[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) split_one(v[i], s, h[i], l[i]);
+    uint16_t* dh = hi + r * ldh + c;
+    uint16_t* dl = lo + r * ldh + c;
+    if (full) {
+      uint4 ph, pl;
+      ph.x = h[0] | ((unsigned)h[1] << 16); ph.y = h[2] | ((unsigned)h[3] << 16);
+      ph.z = h[4] | ((unsigned)h[5] << 16); ph.w = h[6] | ((unsigned)h[7] << 16);
+      pl.x = l[0] | ((unsigned)l[1] << 16); pl.y = l[2] | ((unsigned)l[3] << 16);
+      pl.z = l[4] | ((unsigned)l[5] << 16); pl.w = l[6] | ((unsigned)l[7] << 16);
+      *reinterpret_cast<uint4*>(dh) = ph;
+      *reinterpret_cast<uint4*>(dl) = pl;
+    } else {
+#pragma unroll
+      for (int i = 0; i < 8; ++i)
+        if (c + i < cols) {
+          dh[i] = h[i];
+          dl[i] = l[i];
+        }
+    }
+  }
+}
+
+// Transposed planes: a 64 x 64 tile of X goes through LDS; output row j of
+// the planes is column j of X.
+__global__ void __launch_bounds__(256) split_trans_kernel(const float* X, int64_t ld,
+                                                          int64_t rows, int64_t cols, bool vec,
+                                                          const float* part, int64_t nparts,
+                                                          uint16_t* hi, uint16_t* lo,
+                                                          int64_t ldh, float* exp_out) {
+  __shared__ float red[4];
+  __shared__ float tile[64][65];
+  const int e = split_exponent(part, nparts, red);
+  const float s = ldexpf(1.0f, e);
+  if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) exp_out[0] = (float)e;
+  const int64_t r0 = (int64_t)blockIdx.y * 64, c0 = (int64_t)blockIdx.x * 64;
+  const int tid = threadIdx.x;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int idx = tid + 256 * i;
+    const int row = idx >> 4, c4 = (idx & 15) * 4;
+    const int64_t gr = r0 + row, gc = c0 + c4;
+    float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (gr < rows) {
+      const float* src = X + gr * ld + gc;
+      if (vec && gc + 4 <= cols) {
+        v = *reinterpret_cast<const float4*>(src);
+      } else {
+        if (gc < cols) v.x = src[0];
+        if (gc + 1 < cols) v.y = src[1];
+        if (gc + 2 < cols) v.z = src[2];
+        if (gc + 3 < cols) v.w = src[3];
+      }
+    }
+    tile[row][c4] = v.x;
+    tile[row][c4 + 1] = v.y;
+    tile[row][c4 + 2] = v.z;
+    tile[row][c4 + 3] = v.w;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+    const int q = tid + 256 * i;
+    const int j = q >> 3, k8 = (q & 7) * 8;
+    const int64_t orow = c0 + j, ocol = r0 + k8;
+    if (orow >= cols) continue;
+    uint16_t h[8], l[8];
+#pragma unroll
+    for (int t = 0; t < 8; ++t) split_one(tile[k8 + t][j], s, h[t], l[t]);
+    uint16_t* dh = hi + orow * ldh + ocol;
+    uint16_t* dl = lo + orow * ldh + ocol;
+    if (ocol + 8 <= rows) {
+      uint4 ph, pl;
+      ph.x = h[0] | ((unsigned)h[1] << 16); ph.y = h[2] | ((unsigned)h[3] << 16);
+      ph.z = h[4] | ((unsigned)h[5] << 16); ph.w = h[6] | ((unsigned)h[7] << 16);
+      pl.x = l[0] | ((unsigned)l[1] << 16); pl.y = l[2] | ((unsigned)l[3] << 16);
+      pl.z = l[4] | ((unsigned)l[5] << 16); pl.w = l[6] | ((unsigned)l[7] << 16);
+      *reinterpret_cast<uint4*>(dh) = ph;
+      *reinterpret_cast<uint4*>(dl) = pl;
+    } else {
+#pragma unroll
+      for (int t = 0; t < 8; ++t)
+        if (ocol + t < rows) {
+          dh[t] = h[t];
+          dl[t] = l[t];
+        }
+    }
+  }
+}
+
+typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
+
+// D = X Y^T from split planes; tiling as in the bf16 NT kernel, with the
+// high and low planes of each operand staged side by side in LDS.
+template <int BM, int BN, int BK, bool VEC, int WGM = 2, int WGN = 2>
+__global__ void __launch_bounds__(64 * WGM * WGN) __attribute__((amdgpu_waves_per_eu(2)))
+gemm_f16s_nt_kernel(GemmLpArgs p, int tiles_m, int tiles_n) {
+  constexpr int NT = 64 * WGM * WGN;
+  constexpr int WTM = BM / WGM, WTN = BN / WGN;
+  constexpr int FM = WTM / 32, FN = WTN / 32;
+  constexpr int S = BK + 8;                  // LDS row stride (halves), 16-B aligned rows
+  constexpr int XV = (BM * BK / 8) / NT;     // 16-byte vectors per thread and plane
+  constexpr int YV = (BN * BK / 8) / NT;
+  static_assert(XV >= 1 && YV >= 1, "tile too small");
+  static_assert(XV * NT == BM * BK / 8 && YV * NT == BN * BK / 8, "slab / thread mismatch");
+  __shared__ __attribute__((aligned(16))) _Float16 Xs[2][2][BM * S];  // [buffer][hi, lo]
+  __shared__ __attribute__((aligned(16))) _Float16 Ys[2][2][BN * S];
+  __shared__ double red[WGM * WGN];
+
+  const uint16_t* Xp[2] = {static_cast<const uint16_t*>(p.X), static_cast<const uint16_t*>(p.Xl)};
+  const uint16_t* Yp[2] = {static_cast<const uint16_t*>(p.Y), static_cast<const uint16_t*>(p.Yl)};
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave / WGN, wn = wave % WGN;
+  int tm, tn;
+  map_tile_lp(blockIdx.x, tiles_m, tiles_n, tm, tn);
+  const int64_t m0 = (int64_t)tm * BM, n0 = (int64_t)tn * BN;
+  const int64_t M = p.M, N = p.N, K = p.K;
+  uint4 xr[2][XV], yr[2][YV];
+
+  auto load_one = [&](const uint16_t* base, int64_t ld, int64_t r0, int64_t rmax, int64_t k0,
+                      int v) -> uint4 {
+    const int idx = tid + NT * v;
+    const int row = idx / (BK / 8), c = (idx % (BK / 8)) * 8;
+    const int64_t gr = r0 + row, gk = k0 + c;
+    uint4 val = make_uint4(0u, 0u, 0u, 0u);
+    if (gr < rmax) {
+      const uint16_t* src = base + gr * ld + gk;
+      if (VEC && gk + 7 < K) {
+        val = *reinterpret_cast<const uint4*>(src);
+      } else {
+        unsigned short tmp[8];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) tmp[e] = (gk + e < K) ? src[e] : (unsigned short)0;
+        val.x = tmp[0] | ((unsigned)tmp[1] << 16);
+        val.y = tmp[2] | ((unsigned)tmp[3] << 16);
+        val.z = tmp[4] | ((unsigned)tmp[5] << 16);
+        val.w = tmp[6] | ((unsigned)tmp[7] << 16);
+      }
+    }
+    return val;
+  };
+  const bool interior = VEC && (m0 + BM <= M) && (n0 + BN <= N);
+  auto load = [&](int64_t k0) {
+    if (interior && k0 + BK <= K) {
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+#pragma unroll
+        for (int v = 0; v < XV; ++v) {
+          const int idx = tid + NT * v;
+          xr[h][v] = *reinterpret_cast<const uint4*>(Xp[h] + (m0 + idx / (BK / 8)) * p.ldx +
+                                                     k0 + (idx % (BK / 8)) * 8);
+        }
+#pragma unroll
+        for (int v = 0; v < YV; ++v) {
+          const int idx = tid + NT * v;
+          yr[h][v] = *reinterpret_cast<const uint4*>(Yp[h] + (n0 + idx / (BK / 8)) * p.ldy +
+                                                     k0 + (idx % (BK / 8)) * 8);
+        }
+      }
+      return;
+    }
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+#pragma unroll
+      for (int v = 0; v < XV; ++v) xr[h][v] = load_one(Xp[h], p.ldx, m0, M, k0, v);
+#pragma unroll
+      for (int v = 0; v < YV; ++v) yr[h][v] = load_one(Yp[h], p.ldy, n0, N, k0, v);
+    }
+  };
+  auto store = [&](int buf) {
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+#pragma unroll
+      for (int v = 0; v < XV; ++v) {
+        const int idx = tid + NT * v;
+        const int row = idx / (BK / 8), c = (idx % (BK / 8)) * 8;
+        *reinterpret_cast<uint4*>(&Xs[buf][h][row * S + c]) = xr[h][v];
+      }
+#pragma unroll
+      for (int v = 0; v < YV; ++v) {
+        const int idx = tid + NT * v;
+        const int row = idx / (BK / 8), c = (idx % (BK / 8)) * 8;
+        *reinterpret_cast<uint4*>(&Ys[buf][h][row * S + c]) = yr[h][v];
+      }
+    }
+  };
+
+  f32x16 acc[FM][FN];
+#pragma unroll
+  for (int i = 0; i < FM; ++i)
+#pragma unroll
+    for (int j = 0; j < FN; ++j) acc[i][j] = f32x16{};
+
+  const int nk = (int)((K + BK - 1) / BK);
+  const int lr = lane & 31, lk = lane >> 5;
+  if (nk > 0) load(0);
+  for (int kt = 0; kt < nk; ++kt) {
+    const int buf = kt & 1;
+    store(buf);
+    __syncthreads();
+    if (kt + 1 < nk) load((int64_t)(kt + 1) * BK);
+    const int xo = (wm * WTM + lr) * S + 8 * lk;
+    const int yo = (wn * WTN + lr) * S + 8 * lk;
+    if (NSR_LP_SETPRIO) __builtin_amdgcn_s_setprio(1);
+#pragma unroll
+    for (int ks = 0; ks < BK; ks += 16) {
+      f16x8 ah[FM], al[FM], bh[FN], bl[FN];
+#pragma unroll
+      for (int i = 0; i < FM; ++i) {
+        ah[i] = *reinterpret_cast<const f16x8*>(&Xs[buf][0][xo + i * 32 * S + ks]);
+        al[i] = *reinterpret_cast<const f16x8*>(&Xs[buf][1][xo + i * 32 * S + ks]);
+      }
+#pragma unroll
+      for (int j = 0; j < FN; ++j) {
+        bh[j] = *reinterpret_cast<const f16x8*>(&Ys[buf][0][yo + j * 32 * S + ks]);
+        bl[j] = *reinterpret_cast<const f16x8*>(&Ys[buf][1][yo + j * 32 * S + ks]);
+      }
+      // Small terms first; each accumulator gets FM x FN independent
+      // products between its updates.
+#pragma unroll
+      for (int i = 0; i < FM; ++i)
+#pragma unroll
+        for (int j = 0; j < FN; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_f16(al[i], bh[j], acc[i][j], 0, 0, 0);
+#pragma unroll
+      for (int i = 0; i < FM; ++i)
+#pragma unroll
+        for (int j = 0; j < FN; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_f16(ah[i], bl[j], acc[i][j], 0, 0, 0);
+#pragma unroll
+      for (int i = 0; i < FM; ++i)
+#pragma unroll
+        for (int j = 0; j < FN; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_f16(ah[i], bh[j], acc[i][j], 0, 0, 0);
+    }
+    if (NSR_LP_SETPRIO) __builtin_amdgcn_s_setprio(0);
+  }
+
+  // Undo the operand scales (powers of two: exact unless the result
+  // underflows), then the shared epilogue.
+  const float fx = p.xexp ? ldexpf(1.0f, -(int)p.xexp[0]) : 1.0f;
+  const float fy = p.yexp ? ldexpf(1.0f, -(int)p.yexp[0]) : 1.0f;
+  double ss = 0.0;
+  if (!p.E1 && !p.E2) {
+#pragma unroll
+    for (int i = 0; i < FM; ++i)
+#pragma unroll
+      for (int j = 0; j < FN; ++j) {
+        const int64_t col = n0 + wn * WTN + j * 32 + lr;
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+          const int64_t row = m0 + wm * WTM + i * 32 + 8 * (r >> 2) + 4 * lk + (r & 3);
+          if (row < M && col < N) put(p, row, col, acc[i][j][r] * fx * fy, 0.0f, 0.0f, ss);
+        }
+      }
+  } else {
+#pragma unroll
+    for (int f = 0; f < FM * FN; ++f) {
+      const int64_t col = n0 + wn * WTN + (f % FN) * 32 + lr;
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int64_t r0 = m0 + wm * WTM + (f / FN) * 32 + 16 * h + 4 * lk;
+        const auto row_of = [r0](int r) { return r0 + 8 * (r >> 2) + (r & 3); };
+        float e1[8], e2[8];
+        load_addends<8>(p, col, row_of, e1, e2);
+#pragma unroll
+        for (int r = 0; r < 8; ++r) {
+          const int64_t row = row_of(r);
+          if (row < M && col < N)
+            put(p, row, col, acc[f / FN][f % FN][8 * h + r] * fx * fy, e1[r], e2[r], ss);
+        }
+      }
+    }
+  }
+  write_partial<WGM * WGN>(p, ss, red, tm, tn, tiles_n);
+}
+
 bool big_tiles(int64_t m, int64_t n) { return ((m + 127) / 128) * ((n + 127) / 128) >= 256; }
 
 }  // namespace
@@ -489,6 +854,61 @@ int64_t launch_gemm_bf16_nt(const GemmLpArgs& a, hipStream_t st) {
   } else {
     if (vec) hipLaunchKernelGGL((gemm_bf16_nt_kernel<64, 64, 64, true>), grid, block, 0, st, a, tiles_m, tiles_n);
     else hipLaunchKernelGGL((gemm_bf16_nt_kernel<64, 64, 64, false>), grid, block, 0, st, a, tiles_m, tiles_n);
+  }
+  if (hipGetLastError() != hipSuccess) return -1;
+  return a.partial ? (int64_t)tiles_m * tiles_n : 0;
+}
+
+int64_t launch_absmax(const float* X, int64_t ld, int64_t rows, int64_t cols, float* part,
+                      hipStream_t st) {
+  if (rows <= 0 || cols <= 0) return 0;
+  const bool vec = ((ld & 3) == 0) && ((reinterpret_cast<uintptr_t>(X) & 15) == 0);
+  const int64_t nb = rows < kSplitMaxParts ? rows : kSplitMaxParts;
+  hipLaunchKernelGGL(absmax_kernel, dim3((unsigned)nb), dim3(256), 0, st, X, ld, rows, cols, vec,
+                     part);
+  return nb;
+}
+
+void launch_split_f16(const float* X, int64_t ld, int64_t rows, int64_t cols, const float* part,
+                      int64_t nparts, bool trans, uint16_t* hi, uint16_t* lo, int64_t ldh,
+                      float* exp_out, hipStream_t st) {
+  if (rows <= 0 || cols <= 0) return;
+  const bool vec = ((ld & 3) == 0) && ((reinterpret_cast<uintptr_t>(X) & 15) == 0);
+  if (trans) {
+    dim3 grid((unsigned)((cols + 63) / 64), (unsigned)((rows + 63) / 64));
+    hipLaunchKernelGGL(split_trans_kernel, grid, dim3(256), 0, st, X, ld, rows, cols, vec, part,
+                       nparts, hi, lo, ldh, exp_out);
+  } else {
+    const int64_t chunks = rows * ((cols + 7) / 8);
+    int64_t nb = (chunks + 255) / 256;
+    if (nb > 4096) nb = 4096;
+    hipLaunchKernelGGL(split_rows_kernel, dim3((unsigned)nb), dim3(256), 0, st, X, ld, rows, cols,
+                       vec, part, nparts, hi, lo, ldh, exp_out);
+  }
+}
+
+int64_t launch_gemm_f16s_nt(const GemmLpArgs& a, hipStream_t st) {
+  if (a.M <= 0 || a.N <= 0) return 0;
+  const bool vec = ((a.ldx & 7) == 0) && ((a.ldy & 7) == 0) &&
+                   ((reinterpret_cast<uintptr_t>(a.X) & 15) == 0) &&
+                   ((reinterpret_cast<uintptr_t>(a.Y) & 15) == 0) &&
+                   ((reinterpret_cast<uintptr_t>(a.Xl) & 15) == 0) &&
+                   ((reinterpret_cast<uintptr_t>(a.Yl) & 15) == 0);
+  const bool huge = ((a.M + 255) / 256) * ((a.N + 255) / 256) >= 256;
+  const bool big = big_tiles(a.M, a.N);
+  const int bm = huge ? 256 : (big ? 128 : 64);
+  const int tiles_m = (int)((a.M + bm - 1) / bm), tiles_n = (int)((a.N + bm - 1) / bm);
+  dim3 grid((unsigned)((int64_t)tiles_m * tiles_n)), block(256);
+  if (huge) {
+    dim3 block8(512);
+    if (vec) hipLaunchKernelGGL((gemm_f16s_nt_kernel<256, 256, 16, true, 2, 4>), grid, block8, 0, st, a, tiles_m, tiles_n);
+    else hipLaunchKernelGGL((gemm_f16s_nt_kernel<256, 256, 16, false, 2, 4>), grid, block8, 0, st, a, tiles_m, tiles_n);
+  } else if (big) {
+    if (vec) hipLaunchKernelGGL((gemm_f16s_nt_kernel<128, 128, 16, true>), grid, block, 0, st, a, tiles_m, tiles_n);
+    else hipLaunchKernelGGL((gemm_f16s_nt_kernel<128, 128, 16, false>), grid, block, 0, st, a, tiles_m, tiles_n);
+  } else {
+    if (vec) hipLaunchKernelGGL((gemm_f16s_nt_kernel<64, 64, 32, true>), grid, block, 0, st, a, tiles_m, tiles_n);
+    else hipLaunchKernelGGL((gemm_f16s_nt_kernel<64, 64, 32, false>), grid, block, 0, st, a, tiles_m, tiles_n);
   }
   if (hipGetLastError() != hipSuccess) return -1;
   return a.partial ? (int64_t)tiles_m * tiles_n : 0;

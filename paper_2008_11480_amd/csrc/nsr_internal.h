@@ -42,11 +42,36 @@ struct GemmLpArgs {
   float diag;
   float scale;
   double* partial;   // per-tile sum of D^2 (float64), may be null
+  // Split half-precision NT kernel only: X / Y above are the high planes,
+  // Xl / Yl the low planes (same leading dimensions), and xexp[0] / yexp[0]
+  // the power-of-two exponents the operands were scaled by.
+  const void* Xl;
+  const void* Yl;
+  const float* xexp;
+  const float* yexp;
 };
 
 int64_t gemm_lp_partials(int64_t m, int64_t n);
 int64_t launch_gemm_f32_nn(const GemmLpArgs& a, hipStream_t st);
 int64_t launch_gemm_bf16_nt(const GemmLpArgs& a, hipStream_t st);
+
+// Split float32 operands for the half-precision NT kernel.  absmax writes
+// per-block maxima of |X| (returns their count, at most kSplitMaxParts);
+// split reads them, picks the exponent e that brings max |X| 2^e into
+// [2^14, 2^15), writes e to exp_out[0] and the planes hi = half(X 2^e),
+// lo = half(X 2^e - hi): rows x cols row-major (trans = false) or the
+// transpose, cols x rows (trans = true), leading dimension ldh (a multiple
+// of 8).
+constexpr int kSplitMaxParts = 1024;
+int64_t launch_absmax(const float* X, int64_t ld, int64_t rows, int64_t cols, float* part,
+                      hipStream_t st);
+void launch_split_f16(const float* X, int64_t ld, int64_t rows, int64_t cols, const float* part,
+                      int64_t nparts, bool trans, uint16_t* hi, uint16_t* lo, int64_t ldh,
+                      float* exp_out, hipStream_t st);
+// D = diag I + scale (X Y^T) + E1 + E2 from split planes (X: m x k,
+// Y: n x k, K contiguous): three half-precision MFMA products
+// hi hi + hi lo + lo hi, float32 accumulation, times 2^-(ex + ey).
+int64_t launch_gemm_f16s_nt(const GemmLpArgs& a, hipStream_t st);
 
 // Upper bound on the number of partials the float64 GEMM writes for an m x n
 // output (the size the partial buffer must have).

@@ -84,7 +84,62 @@ size_t split_bytes(int64_t n) {
   return a > b ? a : b;
 }
 
+// Scratch of a split half-precision product (m x n x k): hi / lo planes of
+// X (m x k) and of Y^T (n x k) with a leading dimension padded to 8 halves,
+// the per-block maxima of both operands and their two scale exponents.
+struct SplitPlanes {
+  uint16_t *xh, *xl, *yh, *yl;
+  float* part;   // 2 kSplitMaxParts
+  float* exps;   // 2
+  int64_t ldk;
+};
+
+int64_t split_ld(int64_t k) { return ((k > 0 ? k : 1) + 7) / 8 * 8; }
+
+size_t split_scratch_bytes(int64_t m, int64_t n, int64_t k) {
+  const int64_t ldk = split_ld(k);
+  return 2 * align_up((size_t)m * ldk * 2, kAlign) + 2 * align_up((size_t)n * ldk * 2, kAlign) +
+         align_up(2 * kSplitMaxParts * sizeof(float), kAlign) + align_up(2 * sizeof(float), kAlign);
+}
+
+SplitPlanes carve_split(char* p, int64_t m, int64_t n, int64_t k) {
+  SplitPlanes sp{};
+  sp.ldk = split_ld(k);
+  auto take = [&](size_t bytes) {
+    char* q = p;
+    p += align_up(bytes, kAlign);
+    return q;
+  };
+  sp.xh = reinterpret_cast<uint16_t*>(take((size_t)m * sp.ldk * 2));
+  sp.xl = reinterpret_cast<uint16_t*>(take((size_t)m * sp.ldk * 2));
+  sp.yh = reinterpret_cast<uint16_t*>(take((size_t)n * sp.ldk * 2));
+  sp.yl = reinterpret_cast<uint16_t*>(take((size_t)n * sp.ldk * 2));
+  sp.part = reinterpret_cast<float*>(take(2 * kSplitMaxParts * sizeof(float)));
+  sp.exps = reinterpret_cast<float*>(take(2 * sizeof(float)));
+  return sp;
+}
+
+// Split a rows x cols float32 matrix into hi / lo planes (transposed when
+// trans: the planes are then cols x rows), exponent to exp_out[0].
+void split_operand(const float* X, int64_t ld, int64_t rows, int64_t cols, bool trans,
+                   uint16_t* hi, uint16_t* lo, int64_t ldh, float* part, float* exp_out,
+                   hipStream_t st) {
+  const int64_t np = launch_absmax(X, ld, rows, cols, part, st);
+  launch_split_f16(X, ld, rows, cols, part, np, trans, hi, lo, ldh, exp_out, st);
+}
+
 size_t elem_bytes(int precision) { return precision == NS_PREC_FP64 ? 8 : 4; }
+
+bool mixed_prec(int precision) {
+  return precision == NS_PREC_MIXED_BF16 || precision == NS_PREC_MIXED_SPLIT;
+}
+
+// Split mode: the row-major planes of A (the residual's left operand, split
+// once per ns_bind) and the scratch of one split product.
+size_t split_mode_bytes(int64_t n) {
+  return 2 * align_up((size_t)n * split_ld(n) * 2, kAlign) + align_up(sizeof(float), kAlign) +
+         split_scratch_bytes(n, n, n);
+}
 
 size_t layout_bytes(int64_t n, int precision, int composite) {
   const int64_t ld = ld_for(n);
@@ -93,8 +148,9 @@ size_t layout_bytes(int64_t n, int precision, int composite) {
   const int mats = level_mats(composite);
   bytes += (size_t)mats * align_up(nn * elem_bytes(precision), kAlign);
   if (precision != NS_PREC_FP64) bytes += align_up(nn * 4, kAlign);          // float32 A
-  if (precision == NS_PREC_MIXED_BF16)
+  if (mixed_prec(precision))
     bytes += (size_t)level_shadows(composite) * align_up(nn * 2, kAlign);    // bf16 copies
+  if (precision == NS_PREC_MIXED_SPLIT) bytes += split_mode_bytes(n);        // split planes
   bytes += 5 * align_up((size_t)n * sizeof(double), kAlign);                 // r, t, w0, w1, S
   bytes += align_up((size_t)partial_capacity(n) * sizeof(double), kAlign);   // partials
   bytes += align_up(16 * sizeof(double), kAlign);                            // scalars
@@ -139,6 +195,10 @@ struct ns_solver {
   int gc_m[kMaxLoops] = {0, 0, 0}; // their orders m_i (x_i = m_i^k)
   bool gc_started = false;
   float* A32 = nullptr;
+  uint16_t* Ah = nullptr;  // split mode: half-precision planes of A32
+  uint16_t* Al = nullptr;
+  float* aexp = nullptr;   // and their scale exponent
+  SplitPlanes sp{};        // split mode: scratch of one split product
   double* r = nullptr;
   double* vt = nullptr;      // accelerator temporaries (eq. ttk1)
   double* vw[2] = {nullptr, nullptr};
@@ -203,7 +263,8 @@ bool is_f64(const ns_solver* s) { return s->precision == NS_PREC_FP64; }
 // One fused GEMM D = diag I + scale X Y + E1 + E2 on the solver's stream.
 // X == nullptr means A (the residual products).  Dispatch by precision:
 // float64 MFMA; float32 MFMA; mixed: bf16 MFMA (X Y^T) for K_POWER products,
-// float32 MFMA otherwise.
+// float32 MFMA otherwise (split mode: the float32-class product of split
+// half-precision operands).
 int mm(ns_solver* s, Mat& D, const Mat* X, const Mat& Y, const Mat* E1, const Mat* E2,
        double diag, double scale, bool want_norm, Kind kind) {
   hipEvent_t eb = nullptr, ee = nullptr;
@@ -247,10 +308,32 @@ int mm(ns_solver* s, Mat& D, const Mat* X, const Mat& Y, const Mat* E1, const Ma
     tkind = 1;
   } else {
     GemmLpArgs a{};
-    const bool bf = (s->precision == NS_PREC_MIXED_BF16) && kind == K_POWER;
+    const bool bf = mixed_prec(s->precision) && kind == K_POWER;
+    const bool split = s->precision == NS_PREC_MIXED_SPLIT && kind != K_POWER;
     a.X = bf ? (const void*)X->b : (const void*)(X ? X->f : s->A32);
     a.Y = bf ? (const void*)Y.b : (const void*)Y.f;
     a.ldx = a.ldy = s->ld;
+    if (split) {
+      // X row-major (A's planes are split once per bind), Y transposed.
+      const SplitPlanes& sp = s->sp;
+      if (X) {
+        split_operand(X->f, s->ld, s->n, s->n, false, sp.xh, sp.xl, sp.ldk, sp.part, sp.exps,
+                      s->stream);
+        a.X = sp.xh;
+        a.Xl = sp.xl;
+        a.xexp = sp.exps;
+      } else {
+        a.X = s->Ah;
+        a.Xl = s->Al;
+        a.xexp = s->aexp;
+      }
+      split_operand(Y.f, s->ld, s->n, s->n, true, sp.yh, sp.yl, sp.ldk,
+                    sp.part + kSplitMaxParts, sp.exps + 1, s->stream);
+      a.Y = sp.yh;
+      a.Yl = sp.yl;
+      a.yexp = sp.exps + 1;
+      a.ldx = a.ldy = sp.ldk;
+    }
     a.D = D.f;
     a.ldd = s->ld;
     a.Db = D.b;
@@ -262,8 +345,9 @@ int mm(ns_solver* s, Mat& D, const Mat* X, const Mat& Y, const Mat* E1, const Ma
     a.diag = (float)diag;
     a.scale = (float)scale;
     a.partial = want_norm ? s->partial : nullptr;
-    np = bf ? launch_gemm_bf16_nt(a, s->stream) : launch_gemm_f32_nn(a, s->stream);
-    tkind = bf ? 3 : 2;
+    np = bf ? launch_gemm_bf16_nt(a, s->stream)
+            : (split ? launch_gemm_f16s_nt(a, s->stream) : launch_gemm_f32_nn(a, s->stream));
+    tkind = bf ? 3 : (split ? 4 : 2);
   }
   if (np < 0) return fail(NS_EHIP, "GEMM launch failed: %s", hipGetErrorString(hipGetLastError()));
   // algorithmic flop: 2 n^3, or n^2 (n + 1) when only one triangle is formed
@@ -872,7 +956,7 @@ const char* ns_status_string(int st) {
 
 size_t ns_workspace_bytes(int64_t n, int precision, int composite) {
   if (n < 1) return 0;
-  if (precision < NS_PREC_FP64 || precision > NS_PREC_MIXED_BF16) return 0;
+  if (precision < NS_PREC_FP64 || precision > NS_PREC_MIXED_SPLIT) return 0;
   if (composite < 0 || composite > kMaxLoops) return 0;
   return layout_bytes(n, precision, composite);
 }
@@ -883,7 +967,7 @@ int ns_create(int device, void* hip_stream, int64_t n, int precision, void* work
   *out = nullptr;
   if (n < 1) return fail(NS_EINVAL, "n must be >= 1");
   if (n > 65535) return fail(NS_EINVAL, "n must be <= 65535");
-  if (precision < NS_PREC_FP64 || precision > NS_PREC_MIXED_BF16)
+  if (precision < NS_PREC_FP64 || precision > NS_PREC_MIXED_SPLIT)
     return fail(NS_EINVAL, "unknown precision %d", precision);
   if (!workspace) return fail(NS_EINVAL, "null workspace");
   if ((reinterpret_cast<uintptr_t>(workspace) % kAlign) != 0)
@@ -919,7 +1003,7 @@ int ns_create(int device, void* hip_stream, int64_t n, int precision, void* work
       m.d = reinterpret_cast<double*>(q);
     else
       m.f = reinterpret_cast<float*>(q);
-    if (with_shadow && precision == NS_PREC_MIXED_BF16) m.b = reinterpret_cast<uint16_t*>(take(shadow));
+    if (with_shadow && mixed_prec(precision)) m.b = reinterpret_cast<uint16_t*>(take(shadow));
   };
   mat_of(s->G[0], false);
   mat_of(s->G[1], false);
@@ -946,6 +1030,13 @@ int ns_create(int device, void* hip_stream, int64_t n, int precision, void* work
     s->loopG[i] = &s->LG[i - 1];
   }
   if (precision != NS_PREC_FP64) s->A32 = reinterpret_cast<float*>(take(align_up(nn * 4, kAlign)));
+  if (precision == NS_PREC_MIXED_SPLIT) {
+    const size_t plane = align_up((size_t)n * split_ld(n) * 2, kAlign);
+    s->Ah = reinterpret_cast<uint16_t*>(take(plane));
+    s->Al = reinterpret_cast<uint16_t*>(take(plane));
+    s->aexp = reinterpret_cast<float*>(take(align_up(sizeof(float), kAlign)));
+    s->sp = carve_split(take(split_scratch_bytes(n, n, n)), n, n, n);
+  }
   s->r = reinterpret_cast<double*>(take(align_up((size_t)n * sizeof(double), kAlign)));
   s->vt = reinterpret_cast<double*>(take(align_up((size_t)n * sizeof(double), kAlign)));
   s->vw[0] = reinterpret_cast<double*>(take(align_up((size_t)n * sizeof(double), kAlign)));
@@ -996,6 +1087,9 @@ int ns_bind(ns_solver* s, const double* A, int64_t lda) {
   if (!is_f64(s)) {
     HIP_TRY(hipSetDevice(s->device));
     launch_convert<double, float>(A, lda, s->n, s->A32, s->ld, s->stream);
+    if (s->precision == NS_PREC_MIXED_SPLIT)
+      split_operand(s->A32, s->ld, s->n, s->n, false, s->Ah, s->Al, s->sp.ldk, s->sp.part,
+                    s->aexp, s->stream);
     if (hipGetLastError() != hipSuccess) return fail(NS_EHIP, "kernel launch failed");
   }
   return NS_OK;
@@ -1013,7 +1107,7 @@ int ns_init_scale(ns_solver* s, int scale, double eps, double* alpha_out, double
     launch_rowabs(s->A, s->lda, s->n, s->partial, s->stream);
     launch_reduce(s->partial, s->n, s->scal + 0, 3, eps, s->stream);
   } else if (scale == NS_SCALE_DIAG) {
-    if (s->precision == NS_PREC_MIXED_BF16)
+    if (mixed_prec(s->precision))
       return fail(NS_EINVAL, "NS_SCALE_DIAG needs the float64 or float32 mode");
     launch_diag(s->A, s->lda, s->n, s->sdiag, s->partial, s->stream);
     launch_reduce(s->sdiag, s->n, s->scal + 0, 1, 0.0, s->stream);     // max A_ii
@@ -1440,7 +1534,8 @@ static int gemm_lp_entry(bool bf16, void* hip_stream, int64_t m, int64_t n, int6
   if (k > 0 && (ldx < k || ldy < ycols)) return fail(NS_EINVAL, "leading dimension too small");
   if ((D && ldd < n) || (Db && lddb < n)) return fail(NS_EINVAL, "output leading dimension too small");
   if ((E1 && lde1 < n) || (E2 && lde2 < n)) return fail(NS_EINVAL, "addend leading dimension too small");
-  if ((const void*)D == X || (const void*)D == Y || (const void*)Db == X || (const void*)Db == Y)
+  if ((D && ((const void*)D == X || (const void*)D == Y)) ||
+      (Db && ((const void*)Db == X || (const void*)Db == Y)))
     return fail(NS_EINVAL, "outputs must not alias X or Y");
   hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
   GemmLpArgs a{};
@@ -1476,6 +1571,66 @@ int ns_gemm_f32(void* hip_stream, int64_t m, int64_t n, int64_t k, const float* 
                 float scale, double* sumsq_out) {
   return gemm_lp_entry(false, hip_stream, m, n, k, X, ldx, Y, ldy, D, ldd, Db, lddb, E1, lde1, E2,
                        lde2, diag, scale, sumsq_out);
+}
+
+size_t ns_gemm_f32_split_scratch_bytes(int64_t m, int64_t n, int64_t k) {
+  if (m < 0 || n < 0 || k < 0) return 0;
+  return split_scratch_bytes(m, n, k);
+}
+
+int ns_gemm_f32_split(void* hip_stream, int64_t m, int64_t n, int64_t k, const float* X,
+                      int64_t ldx, const float* Y, int64_t ldy, float* D, int64_t ldd,
+                      uint16_t* Db, int64_t lddb, const float* E1, int64_t lde1, const float* E2,
+                      int64_t lde2, float diag, float scale, double* sumsq_out, void* scratch,
+                      size_t scratch_bytes) {
+  if (m < 0 || n < 0 || k < 0) return fail(NS_EINVAL, "negative size");
+  if (m == 0 || n == 0) return NS_OK;
+  if ((!D && !Db) || (k > 0 && (!X || !Y))) return fail(NS_EINVAL, "null operand");
+  if (k > 0 && (ldx < k || ldy < n)) return fail(NS_EINVAL, "leading dimension too small");
+  if ((D && ldd < n) || (Db && lddb < n)) return fail(NS_EINVAL, "output leading dimension too small");
+  if ((E1 && lde1 < n) || (E2 && lde2 < n)) return fail(NS_EINVAL, "addend leading dimension too small");
+  if ((D && ((const void*)D == X || (const void*)D == Y)) ||
+      (Db && ((const void*)Db == X || (const void*)Db == Y)))
+    return fail(NS_EINVAL, "outputs must not alias X or Y");
+  if (!scratch || scratch_bytes < split_scratch_bytes(m, n, k))
+    return fail(NS_ENOMEM, "scratch too small: %zu bytes needed", split_scratch_bytes(m, n, k));
+  if ((reinterpret_cast<uintptr_t>(scratch) & (kAlign - 1)) != 0)
+    return fail(NS_EINVAL, "scratch must be %zu-byte aligned", (size_t)kAlign);
+  hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
+  SplitPlanes sp = carve_split(static_cast<char*>(scratch), m, n, k);
+  GemmLpArgs a{};
+  if (k > 0) {
+    split_operand(X, ldx, m, k, false, sp.xh, sp.xl, sp.ldk, sp.part, sp.exps, st);
+    split_operand(Y, ldy, k, n, true, sp.yh, sp.yl, sp.ldk, sp.part + kSplitMaxParts,
+                  sp.exps + 1, st);
+    a.xexp = sp.exps;
+    a.yexp = sp.exps + 1;
+  }
+  a.X = sp.xh;
+  a.Xl = sp.xl;
+  a.Y = sp.yh;
+  a.Yl = sp.yl;
+  a.ldx = a.ldy = sp.ldk;
+  a.D = D;
+  a.Db = Db;
+  a.E1 = E1;
+  a.E2 = E2;
+  a.ldd = ldd;
+  a.lddb = lddb;
+  a.lde1 = lde1;
+  a.lde2 = lde2;
+  a.M = m;
+  a.N = n;
+  a.K = k;
+  a.diag = diag;
+  a.scale = scale;
+  double* part = sumsq_out ? sumsq_out + 1 : nullptr;
+  a.partial = part;
+  const int64_t np = launch_gemm_f16s_nt(a, st);
+  if (np < 0) return fail(NS_EHIP, "GEMM launch failed: %s", hipGetErrorString(hipGetLastError()));
+  if (sumsq_out) launch_reduce(part, np, sumsq_out, 0, 0.0, st);
+  if (hipGetLastError() != hipSuccess) return fail(NS_EHIP, "kernel launch failed");
+  return NS_OK;
 }
 
 int ns_gemm_bf16_nt(void* hip_stream, int64_t m, int64_t n, int64_t k, const uint16_t* X,

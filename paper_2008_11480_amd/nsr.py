@@ -20,7 +20,7 @@ _lib = None
 NS_OK, NS_EINVAL, NS_ENOTSPD, NS_EDIVERGED, NS_ENOCONV = 0, -1, -2, -3, -4
 NS_ENOMEM, NS_EHIP, NS_EBUSY, NS_EPRECISION, NS_ESTATE = -5, -6, -7, -8, -9
 # ns_precision
-PREC_FP64, PREC_FP32, PREC_MIXED_BF16 = 0, 1, 2
+PREC_FP64, PREC_FP32, PREC_MIXED_BF16, PREC_MIXED_SPLIT = 0, 1, 2, 3
 # ns_scale
 SCALE_FROBENIUS, SCALE_INF_HALF, SCALE_DIAG = 0, 1, 2
 # ns_factorization
@@ -40,7 +40,8 @@ EXPORTS = (
     "ns_timing_enable", "ns_set_composite_rates",
     "ns_timing_read", "ns_timing_reset", "ns_gemm_f64", "ns_gemm_f64_partials",
     "ns_gemm_f64_scratch_bytes", "ns_gemm_f64_ws",
-    "ns_gemm_f32", "ns_gemm_bf16_nt", "ns_gemm_lp_partials",
+    "ns_gemm_f32", "ns_gemm_bf16_nt", "ns_gemm_lp_partials", "ns_gemm_f32_split",
+    "ns_gemm_f32_split_scratch_bytes",
     "ns_batch_workspace_bytes", "ns_batch_create", "ns_batch_set_launch", "ns_batch_submit",
     "ns_batch_poll", "ns_batch_autotune", "ns_batch_timeline", "ns_batch_destroy",
     "ns_status_string", "ns_last_error", "ns_version",
@@ -129,6 +130,10 @@ def lib() -> ctypes.CDLL:
         "ns_gemm_bf16_nt": (ci, [vp, i64, i64, i64, vp, i64, vp, i64, vp, i64, vp, i64, vp, i64,
                                  vp, i64, ctypes.c_float, ctypes.c_float, vp]),
         "ns_gemm_lp_partials": (i64, [i64, i64]),
+        "ns_gemm_f32_split": (ci, [vp, i64, i64, i64, vp, i64, vp, i64, vp, i64, vp, i64, vp,
+                                   i64, vp, i64, ctypes.c_float, ctypes.c_float, vp, vp,
+                                   ctypes.c_size_t]),
+        "ns_gemm_f32_split_scratch_bytes": (ctypes.c_size_t, [i64, i64, i64]),
         "ns_batch_workspace_bytes": (ctypes.c_size_t, [i64, ci, ci]),
         "ns_batch_create": (ci, [ci, vp, i64, ci, ci, ci, vp, ctypes.c_size_t,
                                  ctypes.POINTER(vp)]),
@@ -593,6 +598,42 @@ def gemm_lp(X, Y, nt: bool, D=None, want_bf16: bool = False, E1=None, E2=None,
              _ptr(D), D.stride(0), _ptr(Db), Db.stride(0) if Db is not None else 0,
              _ptr(E1), E1.stride(0) if E1 is not None else 0, _ptr(E2),
              E2.stride(0) if E2 is not None else 0, float(diag), float(scale), _ptr(ss)))
+    return D, Db, (ss[0] if ss is not None else None)
+
+
+def gemm_f32_split(X, Y, D=None, want_bf16: bool = False, E1=None, E2=None,
+                   diag: float = 0.0, scale: float = 1.0, want_sumsq: bool = False,
+                   scratch=None, stream=None):
+    """float32-class D = diag I + scale X Y + E1 + E2 from split half-precision
+    operands (see ``ns_gemm_f32_split``).  Returns (D, Db or None, sumsq or
+    None); scratch (uint8 device tensor) is allocated when not given."""
+    import torch
+    for t, nm in ((X, "X"), (Y, "Y")):
+        if not t.is_cuda or t.dtype != torch.float32 or t.stride(-1) != 1:
+            raise TypeError(f"{nm} must be a row-major float32 CUDA tensor")
+    m, k = X.shape
+    n = Y.shape[1]
+    if Y.shape[0] != k:
+        raise ValueError("inner dimensions differ")
+    for t in (E1, E2):
+        if t is not None and (t.dtype != torch.float32 or not t.is_cuda):
+            raise TypeError("addends must be float32 CUDA tensors")
+    if D is None:
+        D = torch.empty(m, n, dtype=torch.float32, device=X.device)
+    Db = torch.empty(m, n, dtype=torch.bfloat16, device=X.device) if want_bf16 else None
+    ss = None
+    if want_sumsq:
+        ss = torch.zeros(1 + int(lib().ns_gemm_lp_partials(m, n)), dtype=torch.float64,
+                         device=X.device)
+    nbytes = int(lib().ns_gemm_f32_split_scratch_bytes(m, n, k))
+    if scratch is None:
+        scratch = torch.empty(nbytes, dtype=torch.uint8, device=X.device)
+    check(lib().ns_gemm_f32_split(
+        _stream_handle(stream), m, n, k, _ptr(X), X.stride(0), _ptr(Y), Y.stride(0),
+        _ptr(D), D.stride(0), _ptr(Db), Db.stride(0) if Db is not None else 0,
+        _ptr(E1), E1.stride(0) if E1 is not None else 0, _ptr(E2),
+        E2.stride(0) if E2 is not None else 0, float(diag), float(scale), _ptr(ss),
+        _ptr(scratch), scratch.numel() * scratch.element_size()))
     return D, Db, (ss[0] if ss is not None else None)
 
 

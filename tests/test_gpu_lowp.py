@@ -64,6 +64,112 @@ def test_gemm_f32_elementwise(torch, m, n, k):
     assert abs(float(ss.cpu()) - ssr) <= 1e-12 * ssr
 
 
+def split_bound(Xd, Yd, scale, k):
+    """Element-wise bound of the split half-precision product (see
+    ns_gemm_f32_split): each operand keeps 22 bits (|x - x^| <= 2^-22 |x|,
+    plus half a half-precision subnormal step, 2^-25 2^-e <= 2^-39 max|X|),
+    the dropped lo lo term is below 2^-22 |x| |y|, and the three products are
+    accumulated in float32 (3k terms)."""
+    ax, ay = np.abs(Xd), np.abs(Yd)
+    mx, my = ax.max(initial=0.0), ay.max(initial=0.0)
+    prod = ax @ ay
+    eta = 2.0 ** -38 * (mx * ay.sum(axis=0)[None, :] + my * ax.sum(axis=1)[:, None])
+    return abs(scale) * ((3 * 2.0 ** -22 + g32(3 * k + 4)) * prod + eta)
+
+
+@pytest.mark.parametrize("addends", [0, 1, 2])
+@pytest.mark.parametrize("m,n,k", SHAPES + [(64, 64, 40), (70, 50, 9), (4100, 4000, 200)])
+def test_gemm_f32_split_elementwise(torch, m, n, k, addends):
+    """Split half-precision product against float64 on every tile family
+    (64, 128, 256) with ragged edges and every epilogue form."""
+    g = torch.Generator(device="cpu").manual_seed(m * 13 + n * 11 + k + addends)
+    X = torch.randn(m, k, generator=g, dtype=torch.float32)
+    Y = torch.randn(k, n, generator=g, dtype=torch.float32)
+    E = [torch.randn(m, n, generator=g, dtype=torch.float32) for _ in range(addends)]
+    diag, scale = 0.75, -1.25
+    D, Db, ss = nsr.gemm_f32_split(X.cuda(), Y.cuda(), want_bf16=True,
+                                   E1=E[0].cuda() if addends > 0 else None,
+                                   E2=E[1].cuda() if addends > 1 else None,
+                                   diag=diag, scale=scale, want_sumsq=True)
+    torch.cuda.synchronize()
+    Xd, Yd = X.double().numpy(), Y.double().numpy()
+    Ed = [e.double().numpy() for e in E]
+    ref = scale * (Xd @ Yd) + diag * np.eye(m, n) + sum(Ed, np.zeros((m, n)))
+    bound = split_bound(Xd, Yd, scale, k) + g32(k + 4) * (
+        abs(diag) * np.eye(m, n) + sum((np.abs(e) for e in Ed), np.zeros((m, n))))
+    bound = bound + g32(4) * np.abs(ref)
+    got = D.double().cpu().numpy()
+    assert np.all(np.abs(got - ref) <= 2 * bound), float(np.max(np.abs(got - ref) / bound))
+    assert torch.equal(Db.cpu(), D.cpu().to(torch.bfloat16))
+    ssr = float(np.sum(got * got))
+    assert abs(float(ss.cpu()) - ssr) <= 1e-12 * ssr
+
+
+@pytest.mark.parametrize("sx,sy", [(1e-8, 1e6), (3e12, 2e-15), (1.0, 1e-30)])
+def test_gemm_f32_split_operand_scales(torch, sx, sy):
+    """Operands far outside the half-precision range are scaled into it (the
+    exponents are per operand) and scaled back exactly."""
+    m, n, k = 300, 200, 500
+    g = torch.Generator(device="cpu").manual_seed(5)
+    X = torch.randn(m, k, generator=g, dtype=torch.float32) * sx
+    Y = torch.randn(k, n, generator=g, dtype=torch.float32) * sy
+    D, _, _ = nsr.gemm_f32_split(X.cuda(), Y.cuda())
+    torch.cuda.synchronize()
+    Xd, Yd = X.double().numpy(), Y.double().numpy()
+    ref = Xd @ Yd
+    bound = split_bound(Xd, Yd, 1.0, k) + g32(2) * np.abs(ref)
+    got = D.double().cpu().numpy()
+    assert np.all(np.abs(got - ref) <= 2 * bound), float(np.max(np.abs(got - ref) / bound))
+
+
+def test_gemm_f32_split_degenerate(torch):
+    """A zero operand (exponent 0), k = 0 (D = diag I + E1) and a wide
+    dynamic range inside one operand."""
+    m, n, k = 130, 70, 90
+    g = torch.Generator(device="cpu").manual_seed(9)
+    Y = torch.randn(k, n, generator=g, dtype=torch.float32)
+    E1 = torch.randn(m, n, generator=g, dtype=torch.float32)
+    D, _, _ = nsr.gemm_f32_split(torch.zeros(m, k).cuda(), Y.cuda(), E1=E1.cuda(), diag=2.0)
+    torch.cuda.synchronize()
+    assert torch.equal(D.cpu(), E1 + 2.0 * torch.eye(m, n))
+    D0, _, _ = nsr.gemm_f32_split(torch.empty(m, 0).cuda(), torch.empty(0, n).cuda(),
+                                  E1=E1.cuda(), diag=-1.0)
+    torch.cuda.synchronize()
+    assert torch.equal(D0.cpu(), E1 - torch.eye(m, n))
+    # entries spread over 2^-60 .. 2^20 in one operand
+    X = torch.randn(m, k, generator=g, dtype=torch.float32)
+    X = X * torch.pow(2.0, torch.randint(-60, 21, (m, k), generator=g).float())
+    D, _, _ = nsr.gemm_f32_split(X.cuda(), Y.cuda())
+    torch.cuda.synchronize()
+    Xd, Yd = X.double().numpy(), Y.double().numpy()
+    ref = Xd @ Yd
+    bound = split_bound(Xd, Yd, 1.0, k) + g32(2) * np.abs(ref)
+    got = D.double().cpu().numpy()
+    assert np.all(np.abs(got - ref) <= 2 * bound), float(np.max(np.abs(got - ref) / bound))
+
+
+def test_gemm_f32_split_full_size_sampled(torch):
+    """N = 8192 (256-wide tiles, the mixed composite's size): sampled
+    elements against float64 dot products."""
+    n = 8192
+    g = torch.Generator(device="cuda").manual_seed(21)
+    X = torch.randn(n, n, generator=g, device="cuda", dtype=torch.float32)
+    Y = torch.randn(n, n, generator=g, device="cuda", dtype=torch.float32)
+    E1 = torch.randn(n, n, generator=g, device="cuda", dtype=torch.float32)
+    D, _, _ = nsr.gemm_f32_split(X, Y, E1=E1, diag=1.0, scale=-1.0)
+    torch.cuda.synchronize()
+    rs = np.random.default_rng(4)
+    rows = rs.integers(0, n, 64)
+    cols = rs.integers(0, n, 64)
+    Xs = X[torch.as_tensor(rows, device="cuda")].double().cpu().numpy()
+    Ys = Y[:, torch.as_tensor(cols, device="cuda")].double().cpu().numpy()
+    Es = E1.double().cpu().numpy()[rows][:, cols]
+    ref = -(Xs @ Ys) + np.eye(n)[rows][:, cols] + Es
+    bound = split_bound(Xs, Ys, 1.0, n) + g32(n + 4) * (np.abs(Es) + 1.0)
+    got = D.double().cpu().numpy()[rows][:, cols]
+    assert np.all(np.abs(got - ref) <= 2 * bound), float(np.max(np.abs(got - ref) / bound))
+
+
 @pytest.mark.parametrize("addends", [0, 1, 2])
 @pytest.mark.parametrize("m,n,k", SHAPES + [(64, 64, 40), (70, 50, 9), (4100, 4000, 200)])
 def test_gemm_bf16_nt_elementwise(torch, m, n, k, addends):
@@ -154,6 +260,11 @@ LOWP_CASES = [
     (nsr.PREC_MIXED_BF16, 300, 1e4, 11, "table"),
     (nsr.PREC_MIXED_BF16, 257, 1e5, 15, "table"),
     (nsr.PREC_MIXED_BF16, 200, 1e4, 45, "table"),
+    (nsr.PREC_MIXED_SPLIT, 300, 1e3, 8, "squaring"),
+    (nsr.PREC_MIXED_SPLIT, 511, 1e5, 8, "squaring"),
+    (nsr.PREC_MIXED_SPLIT, 300, 1e4, 8, "composite_double"),
+    (nsr.PREC_MIXED_SPLIT, 33, 10.0, 2, "squaring"),
+    (nsr.PREC_MIXED_SPLIT, 257, 1e5, 15, "table"),
 ]
 
 
@@ -197,6 +308,41 @@ def test_mixed_bind_converts_A(torch):
     ref = (np.eye(100) - sysm.A / alpha).astype(np.float32).astype(np.float64)
     assert np.all(np.abs(F - ref) <= U32 * 2 * np.abs(ref) + 1e-45)     # one float32 rounding
     assert f0 == pytest.approx(np.linalg.norm(ref), rel=1e-12)
+
+
+def test_split_mode_tracks_float32_mixed(torch):
+    """The split mode runs the same iteration as the float32 mixed mode with
+    float32-class residual and G-side products: its ||F_k|| trace follows the
+    float32 mixed trace down to the float32 floor, at N = 1000 (128-wide
+    tiles), and its timed products are of kind 4."""
+    sysm = inputs.spd_qlq(1000, 1e4, seed=77)
+    reps = {}
+    for prec in (nsr.PREC_MIXED_BF16, nsr.PREC_MIXED_SPLIT):
+        s, th, rep = run(torch, sysm, prec, order=8, form="squaring", resid_tol=1e-10,
+                         refine_max=100)
+        assert rep.status == nsr.NS_OK and rep.rel_resid <= 1e-10
+        reps[prec] = rep
+    a, b = reps[nsr.PREC_MIXED_BF16].fnorm_hist, reps[nsr.PREC_MIXED_SPLIT].fnorm_hist
+    floor = 1e4 * 1000 * U32
+    for k in range(min(len(a), len(b))):
+        if a[k] > 100 * floor:
+            assert abs(a[k] - b[k]) <= 1e-3 * a[k], (k, a[k], b[k])
+    assert abs(len(a) - len(b)) <= 1
+
+
+def test_split_mode_timing_kind(torch):
+    sysm = inputs.spd_qlq(200, 1e3, seed=8)
+    A, b = to_dev(torch, sysm.A), to_dev(torch, sysm.b)
+    s = nsr.Solver(200, precision=nsr.PREC_MIXED_SPLIT, composite=False)
+    s.bind(A)
+    s.timing(True)
+    s.init_scale()
+    s.step(8, "squaring")
+    s.step(8, "squaring")
+    cnt = {k: s.timing_read(k)[0] for k in (0, 2, 3, 4)}
+    # powers and assembly in bf16 (4 per step), residual and G-side split
+    assert cnt[2] == 0 and cnt[3] == 8 and cnt[4] >= 2, cnt
+    assert cnt[0] == cnt[3] + cnt[4], cnt
 
 
 def test_mixed_accelerated_composite(torch):
