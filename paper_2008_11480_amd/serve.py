@@ -12,7 +12,9 @@ than the whole budget is rejected.  Admitted requests are routed by size:
 * larger: solved one by one by worker threads, each on its own HIP stream
   with its own device-resident solver state (``richardson_ns_solve``, mixed
   precision by default: bf16 powers, float32 residual / G-side, float64
-  Richardson).
+  Richardson; from ``split_min_n`` on, the residual and G-side products are
+  float32-class products of split half-precision operands, which are faster
+  there).
 
 Latency = completion - arrival.  The scheduling and admission logic is plain
 host code driven through an executor object, so it runs on the CPU with a
@@ -203,6 +205,7 @@ class Server:
             "batched": sum(1 for r in served if r.path == "batch"),
             "single": sum(1 for r in served if r.path == "single"),
             "escalated_to_fp64": sum(1 for r in served if r.precision == 0 and r.path == "batch"),
+            "single_split": sum(1 for r in served if r.precision == 3 and r.path == "single"),
         }
         return out
 
@@ -212,11 +215,13 @@ class GpuExecutor:
     worker thread and HIP stream for the rest."""
 
     def __init__(self, workers: int, precision: int, order: int = 8, resid_tol: float = 1e-10,
-                 small_max_n: int = 256, batch_max: int = 256, refine_max: int = 100):
+                 small_max_n: int = 256, batch_max: int = 256, refine_max: int = 100,
+                 split_min_n: int = 1536):
         import torch
         from . import nsr
         self.torch, self.nsr = torch, nsr
         self.precision, self.order, self.resid_tol = precision, order, resid_tol
+        self.split_min_n = split_min_n
         self.refine_max = refine_max
         self.streams = [torch.cuda.Stream() for _ in range(workers)]
         self.batch_stream = torch.cuda.Stream()
@@ -225,9 +230,16 @@ class GpuExecutor:
             self.batch = nsr.Batch(max_n=small_max_n, max_count=batch_max,
                                    slots=min(batch_max, 4 * cus), stream=self.batch_stream)
 
+    def precision_for(self, n: int) -> int:
+        """Precision of a single solve of size n: the split mode from
+        split_min_n on when the executor runs the mixed mode."""
+        if self.precision == self.nsr.PREC_MIXED_BF16 and n >= self.split_min_n:
+            return self.nsr.PREC_MIXED_SPLIT
+        return self.precision
+
     def footprint(self, r: Request) -> int:
         n = r.n
-        ws = self.nsr.workspace_bytes(n, self.precision, False)
+        ws = self.nsr.workspace_bytes(n, self.precision_for(n), False)
         return ws + (n * n + 2 * n) * 8
 
     def solve_single(self, r: Request, wid: int):
@@ -235,7 +247,7 @@ class GpuExecutor:
         st = self.streams[wid]
         A, b, th = r.payload[:3]
         with torch.cuda.stream(st):
-            s = nsr.Solver(r.n, precision=self.precision, composite=False, stream=st)
+            s = nsr.Solver(r.n, precision=self.precision_for(r.n), composite=False, stream=st)
             s.bind(A)
             rep = s.solve(b, th, order=self.order, form="squaring", k_max=64,
                           resid_tol=self.resid_tol, refine_max=self.refine_max,

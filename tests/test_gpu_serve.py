@@ -48,6 +48,11 @@ def test_serving_short_trace(torch):
             checked += 1
     assert checked > 0
     assert st["batched"] > 0 and st["single"] > 0
+    # single solves from split_min_n on run the split mode (checked above
+    # like every other request)
+    big = [r for r in reqs if r.path == "single" and r.n >= ex.split_min_n]
+    assert big and all(r.precision == nsr.PREC_MIXED_SPLIT for r in big)
+    assert st["single_split"] == len(big)
 
 
 def test_serving_admission_rejects_oversize(torch):
