@@ -26,7 +26,7 @@
 #include <new>
 #include <vector>
 
-#include "../../include/nsr.h"
+#include "nsr.h"
 #include "nsr_internal.h"
 
 // K slab of the in-workgroup GEMM (elements), float32 and float64 (eight-wave

@@ -614,6 +614,18 @@ __global__ void __launch_bounds__(256) split_trans_kernel(const float* X, int64_
 
 typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
 
+// Physical 16-byte chunk of logical chunk c in LDS row `row` (rows of BK
+// halves, no padding): XORed with bits of the row so that eight consecutive
+// lanes hit eight different bank groups both when a slab is stored (BK / 8
+// chunks of a row per lane group) and when a fragment is read (one chunk of
+// eight consecutive rows).
+template <int BK>
+__device__ __forceinline__ int swz_chunk(int row, int c) {
+  constexpr int CPR = BK / 8;                         // chunks per row
+  constexpr int SH = CPR == 2 ? 2 : (CPR == 4 ? 1 : 0);
+  return c ^ ((row >> SH) & (CPR - 1));
+}
+
 // D = X Y^T from split planes; tiling as in the bf16 NT kernel, with the
 // high and low planes of each operand staged side by side in LDS.
 template <int BM, int BN, int BK, bool VEC, int WGM = 2, int WGN = 2>
@@ -622,7 +634,8 @@ gemm_f16s_nt_kernel(GemmLpArgs p, int tiles_m, int tiles_n) {
   constexpr int NT = 64 * WGM * WGN;
   constexpr int WTM = BM / WGM, WTN = BN / WGN;
   constexpr int FM = WTM / 32, FN = WTN / 32;
-  constexpr int S = BK + 8;                  // LDS row stride (halves), 16-B aligned rows
+  static_assert(BK == 16 || BK == 32 || BK == 64, "swizzle defined for 2, 4, 8 chunks per row");
+  constexpr int S = BK;                      // LDS row stride (halves), chunks swizzled
   constexpr int XV = (BM * BK / 8) / NT;     // 16-byte vectors per thread and plane
   constexpr int YV = (BN * BK / 8) / NT;
   static_assert(XV >= 1 && YV >= 1, "tile too small");
@@ -697,13 +710,13 @@ gemm_f16s_nt_kernel(GemmLpArgs p, int tiles_m, int tiles_n) {
 #pragma unroll
       for (int v = 0; v < XV; ++v) {
         const int idx = tid + NT * v;
-        const int row = idx / (BK / 8), c = (idx % (BK / 8)) * 8;
+        const int row = idx / (BK / 8), c = swz_chunk<BK>(row, idx % (BK / 8)) * 8;
         *reinterpret_cast<uint4*>(&Xs[buf][h][row * S + c]) = xr[h][v];
       }
 #pragma unroll
       for (int v = 0; v < YV; ++v) {
         const int idx = tid + NT * v;
-        const int row = idx / (BK / 8), c = (idx % (BK / 8)) * 8;
+        const int row = idx / (BK / 8), c = swz_chunk<BK>(row, idx % (BK / 8)) * 8;
         *reinterpret_cast<uint4*>(&Ys[buf][h][row * S + c]) = yr[h][v];
       }
     }
@@ -723,21 +736,24 @@ gemm_f16s_nt_kernel(GemmLpArgs p, int tiles_m, int tiles_n) {
     store(buf);
     __syncthreads();
     if (kt + 1 < nk) load((int64_t)(kt + 1) * BK);
-    const int xo = (wm * WTM + lr) * S + 8 * lk;
-    const int yo = (wn * WTN + lr) * S + 8 * lk;
+    // Fragment rows are lr + multiples of 32, so the swizzle depends on lr
+    // only.
+    const int xo = (wm * WTM + lr) * S;
+    const int yo = (wn * WTN + lr) * S;
     if (NSR_LP_SETPRIO) __builtin_amdgcn_s_setprio(1);
 #pragma unroll
     for (int ks = 0; ks < BK; ks += 16) {
+      const int co = swz_chunk<BK>(lr, ks / 8 + lk) * 8;
       f16x8 ah[FM], al[FM], bh[FN], bl[FN];
 #pragma unroll
       for (int i = 0; i < FM; ++i) {
-        ah[i] = *reinterpret_cast<const f16x8*>(&Xs[buf][0][xo + i * 32 * S + ks]);
-        al[i] = *reinterpret_cast<const f16x8*>(&Xs[buf][1][xo + i * 32 * S + ks]);
+        ah[i] = *reinterpret_cast<const f16x8*>(&Xs[buf][0][xo + i * 32 * S + co]);
+        al[i] = *reinterpret_cast<const f16x8*>(&Xs[buf][1][xo + i * 32 * S + co]);
       }
 #pragma unroll
       for (int j = 0; j < FN; ++j) {
-        bh[j] = *reinterpret_cast<const f16x8*>(&Ys[buf][0][yo + j * 32 * S + ks]);
-        bl[j] = *reinterpret_cast<const f16x8*>(&Ys[buf][1][yo + j * 32 * S + ks]);
+        bh[j] = *reinterpret_cast<const f16x8*>(&Ys[buf][0][yo + j * 32 * S + co]);
+        bl[j] = *reinterpret_cast<const f16x8*>(&Ys[buf][1][yo + j * 32 * S + co]);
       }
       // Small terms first; each accumulator gets FM x FN independent
       // products between its updates.
@@ -901,11 +917,11 @@ int64_t launch_gemm_f16s_nt(const GemmLpArgs& a, hipStream_t st) {
   dim3 grid((unsigned)((int64_t)tiles_m * tiles_n)), block(256);
   if (huge) {
     dim3 block8(512);
-    if (vec) hipLaunchKernelGGL((gemm_f16s_nt_kernel<256, 256, 16, true, 2, 4>), grid, block8, 0, st, a, tiles_m, tiles_n);
-    else hipLaunchKernelGGL((gemm_f16s_nt_kernel<256, 256, 16, false, 2, 4>), grid, block8, 0, st, a, tiles_m, tiles_n);
+    if (vec) hipLaunchKernelGGL((gemm_f16s_nt_kernel<256, 256, 32, true, 2, 4>), grid, block8, 0, st, a, tiles_m, tiles_n);
+    else hipLaunchKernelGGL((gemm_f16s_nt_kernel<256, 256, 32, false, 2, 4>), grid, block8, 0, st, a, tiles_m, tiles_n);
   } else if (big) {
-    if (vec) hipLaunchKernelGGL((gemm_f16s_nt_kernel<128, 128, 16, true>), grid, block, 0, st, a, tiles_m, tiles_n);
-    else hipLaunchKernelGGL((gemm_f16s_nt_kernel<128, 128, 16, false>), grid, block, 0, st, a, tiles_m, tiles_n);
+    if (vec) hipLaunchKernelGGL((gemm_f16s_nt_kernel<128, 128, 32, true>), grid, block, 0, st, a, tiles_m, tiles_n);
+    else hipLaunchKernelGGL((gemm_f16s_nt_kernel<128, 128, 32, false>), grid, block, 0, st, a, tiles_m, tiles_n);
   } else {
     if (vec) hipLaunchKernelGGL((gemm_f16s_nt_kernel<64, 64, 32, true>), grid, block, 0, st, a, tiles_m, tiles_n);
     else hipLaunchKernelGGL((gemm_f16s_nt_kernel<64, 64, 32, false>), grid, block, 0, st, a, tiles_m, tiles_n);

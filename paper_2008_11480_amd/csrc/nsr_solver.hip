@@ -12,7 +12,7 @@
 #include <new>
 #include <vector>
 
-#include "../../include/nsr.h"
+#include "nsr.h"
 #include "nsr_internal.h"
 
 using namespace nsr;
