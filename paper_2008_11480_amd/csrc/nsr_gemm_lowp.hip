@@ -241,6 +241,9 @@ gemm_f32_nn_kernel(GemmLpArgs p, int tiles_m, int tiles_n) {
         for (int j = 0; j < FN; ++j)
           acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i], b[j], acc[i][j], 0, 0, 0);
     }
+    // Scheduling hint: interleave the slab's LDS reads with its MFMAs
+    // (bf16 -5..9%, split -2%, float32 unchanged, measured standalone).
+    __builtin_amdgcn_iglp_opt(1);
     if (NSR_LP_SETPRIO) __builtin_amdgcn_s_setprio(0);
   }
 
@@ -392,6 +395,9 @@ gemm_bf16_nt_kernel(GemmLpArgs p, int tiles_m, int tiles_n) {
         for (int j = 0; j < FN; ++j)
           acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
     }
+    // Scheduling hint: interleave the slab's LDS reads with its MFMAs
+    // (bf16 -5..9%, split -2%, float32 unchanged, measured standalone).
+    __builtin_amdgcn_iglp_opt(1);
     if (NSR_LP_SETPRIO) __builtin_amdgcn_s_setprio(0);
   }
 
@@ -773,6 +779,9 @@ gemm_f16s_nt_kernel(GemmLpArgs p, int tiles_m, int tiles_n) {
         for (int j = 0; j < FN; ++j)
           acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_f16(ah[i], bh[j], acc[i][j], 0, 0, 0);
     }
+    // Scheduling hint: interleave the slab's LDS reads with its MFMAs
+    // (bf16 -5..9%, split -2%, float32 unchanged, measured standalone).
+    __builtin_amdgcn_iglp_opt(1);
     if (NSR_LP_SETPRIO) __builtin_amdgcn_s_setprio(0);
   }
 
