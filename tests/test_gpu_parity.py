@@ -727,6 +727,8 @@ GRAPH_CASES = [
     (nsr.PREC_FP64, 257, 1e3, 11, "table", 5),
     (nsr.PREC_MIXED_BF16, 300, 1e3, 8, "squaring", 6),
     (nsr.PREC_FP32, 200, 1e2, 6, "unified", 5),
+    (nsr.PREC_MIXED_SPLIT, 300, 1e3, 8, "squaring", 6),
+    (nsr.PREC_MIXED_SPLIT, 2100, 1e3, 8, "squaring", 4),   # 128-wide split tiles
 ]
 
 
