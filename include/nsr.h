@@ -424,8 +424,31 @@ int ns_gemm_bf16_nt(void* hip_stream, int64_t m, int64_t n, int64_t k,
                     float diag, float scale, double* sumsq_out);
 
 /* Number of per-tile partial sums ns_gemm_f32 / ns_gemm_bf16_nt /
- * ns_gemm_f32_split write. */
+ * ns_gemm_bf16_nt_ws / ns_gemm_f32_split write. */
 int64_t ns_gemm_lp_partials(int64_t m, int64_t n);
+
+/* ns_gemm_bf16_nt with flags and caller-owned device scratch.
+ * NS_GEMM_SYMMETRIC is currently DISABLED (NS_EINVAL, and
+ * ns_gemm_bf16_scratch_bytes returns 0): its kernel faulted the GPU on its
+ * first test and the cause has not been found.  Without flags the call is
+ * ns_gemm_bf16_nt.  Intended behaviour with NS_GEMM_SYMMETRIC (m == n; X Y^T + E1 + E2 symmetric in exact arithmetic,
+ * as every power and assembly product of the iteration is) only the
+ * 128 x 128 tiles on or above the diagonal are computed and the lower
+ * triangle is written as their mirror, so D and Db are exactly symmetric.
+ * When those tiles leave a partial last round of resident workgroups, that
+ * round is cut along K into slices stored in the scratch and summed in a
+ * fixed order by a second kernel.  Shapes where this does not save at least
+ * 10% run the full-output kernel (the result is then X Y^T in full, not
+ * mirrored).  scratch: ns_gemm_bf16_scratch_bytes(m, n, k, flags) bytes
+ * (0: none needed), 16-byte aligned.  Errors as ns_gemm_bf16_nt, plus
+ * NS_ENOMEM for too little scratch and NS_EINVAL for m != n with the flag. */
+size_t ns_gemm_bf16_scratch_bytes(int64_t m, int64_t n, int64_t k, int flags);
+int ns_gemm_bf16_nt_ws(void* hip_stream, int64_t m, int64_t n, int64_t k,
+                       const uint16_t* X, int64_t ldx, const uint16_t* Y, int64_t ldy,
+                       float* D, int64_t ldd, uint16_t* Db, int64_t lddb,
+                       const float* E1, int64_t lde1, const float* E2, int64_t lde2,
+                       float diag, float scale, int flags, double* sumsq_out,
+                       void* scratch, size_t scratch_bytes);
 
 /* float32-class product on the half-precision matrix cores: the operation,
  * operands and outputs of ns_gemm_f32 (D = diag I + scale (X Y) + E1 + E2,

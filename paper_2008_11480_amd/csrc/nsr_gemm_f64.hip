@@ -542,19 +542,6 @@ int64_t launch_cfg(const GemmF64Args& a, const Plan& pl, hipStream_t st) {
   return a.partial ? pl.dp + fix_blocks : 0;
 }
 
-int device_cus() {
-  static int cus = 0;
-  if (cus == 0) {
-    int dev = 0, v = 0;
-    if (hipGetDevice(&dev) == hipSuccess &&
-        hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && v > 0)
-      cus = v;
-    else
-      cus = 256;
-  }
-  return cus;
-}
-
 // Tile shape: 128 x 128 (two workgroups per CU) or 64 x 64 (four per CU).
 // Time ~ rounds of resident workgroups x time of one tile; a partial last
 // round costs about half a round (its tiles run with less contention), and a
@@ -619,6 +606,19 @@ Plan plan_f64(int64_t m, int64_t n, int64_t k, bool sym, int64_t sk_cap) {
 }
 
 }  // namespace
+
+int device_cus() {
+  static int cus = 0;
+  if (cus == 0) {
+    int dev = 0, v = 0;
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && v > 0)
+      cus = v;
+    else
+      cus = 256;
+  }
+  return cus;
+}
 
 int64_t gemm_f64_partials(int64_t m, int64_t n, bool sym) {
   // whole tiles + 16 fixup strips per split tail tile, or the 64 x 64 grid

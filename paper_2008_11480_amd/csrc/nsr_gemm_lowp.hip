@@ -824,6 +824,286 @@ gemm_f16s_nt_kernel(GemmLpArgs p, int tiles_m, int tiles_n) {
   write_partial<WGM * WGN>(p, ss, red, tm, tn, tiles_n);
 }
 
+// ---------------------------------------------------------------------------
+// bf16, NT, symmetric output
+// ---------------------------------------------------------------------------
+// The solver's bf16 products are polynomials in F, symmetric in exact
+// arithmetic, so only the T (T + 1) / 2 tiles on or above the diagonal are
+// computed and the lower triangle is their mirror, as in the float64 GEMM.
+// Grid: the first dp workgroups own whole tiles; when the tiles leave a
+// partial last round of resident workgroups, each of its tiles is cut into
+// `splits` K-slices run by the remaining workgroups, which store raw
+// accumulators; gemm_bf16_sym_fixup adds the slices in slice order
+// (deterministic) and finishes those tiles.
+constexpr int kStage = 32 * 33;            // per-wave mirror stage (floats)
+
+__device__ __forceinline__ void sym_tile_lp(int t, int T, int& tm, int& tn) {
+  int r = t, m = 0;
+  while (r >= T - m) {
+    r -= T - m;
+    ++m;
+  }
+  tm = m;
+  tn = m + r;
+}
+
+// Finish tile (tm <= tn) from its accumulators: elements on or above the
+// diagonal get the fused terms and are stored (D, Db); an off-diagonal tile
+// also writes its transpose, fragment by fragment through a per-wave LDS
+// stage (32 x 33 floats) so that the mirrored rows are stored contiguously;
+// a diagonal tile mirrors its strict upper triangle element by element.
+// Returns this thread's sum of squares of everything it stored.  Contains
+// barriers: every thread of the workgroup calls it.
+template <int BM, int WGM, int WGN>
+__device__ double sym_epilogue(const GemmLpArgs& p, int tm, int tn,
+                               f32x16 (&acc)[BM / WGM / 32][BM / WGN / 32], float* stage) {
+  constexpr int WTM = BM / WGM, WTN = BM / WGN, FM = WTM / 32, FN = WTN / 32;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int wm = wave / WGN, wn = wave % WGN;
+  const int lr = lane & 31, lk = lane >> 5;
+  const int64_t M = p.M, N = p.N;
+  const int64_t m0 = (int64_t)tm * BM, n0 = (int64_t)tn * BM;
+  const bool diag_tile = tm == tn;
+  double ss = 0.0;
+#pragma unroll
+  for (int f = 0; f < FM * FN; ++f) {
+    const int i = f / FN, j = f % FN;
+    const int64_t R0 = m0 + wm * WTM + i * 32, C0 = n0 + wn * WTN + j * 32;
+    const int64_t col = C0 + lr;
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int64_t r0 = R0 + 16 * h + 4 * lk;
+      const auto row_of = [r0](int r) { return r0 + 8 * (r >> 2) + (r & 3); };
+      float e1[8], e2[8];
+      load_addends<8>(p, col, row_of, e1, e2);
+#pragma unroll
+      for (int r = 0; r < 8; ++r) {
+        const int64_t row = row_of(r);
+        if (row >= M || col >= N || (diag_tile && row > col)) continue;
+        float v = p.scale * acc[i][j][8 * h + r];
+        if (row == col) v += p.diag;
+        if (p.E1) v += e1[r];
+        if (p.E2) v += e2[r];
+        if (p.D) p.D[row * p.ldd + col] = v;
+        if (p.Db) p.Db[row * p.lddb + col] = __builtin_bit_cast(uint16_t, (__bf16)v);
+        ss += (double)v * (double)v;
+        if (!diag_tile) {
+          stage[lr * 33 + (int)(row - R0)] = v;
+        } else if (row < col) {
+          if (p.D) p.D[col * p.ldd + row] = v;
+          if (p.Db) p.Db[col * p.lddb + row] = __builtin_bit_cast(uint16_t, (__bf16)v);
+          ss += (double)v * (double)v;
+        }
+      }
+    }
+    if (!diag_tile) {
+      __syncthreads();
+      // mirrored rows, two per pass (lanes 0-31 and 32-63)
+      for (int c = 0; c < 32; c += 2) {
+        const int ci = c + lk;
+        const int64_t grow = C0 + ci, gcol = R0 + lr;
+        if (grow < N && gcol < M) {
+          const float w = stage[ci * 33 + lr];
+          if (p.D) p.D[grow * p.ldd + gcol] = w;
+          if (p.Db) p.Db[grow * p.lddb + gcol] = __builtin_bit_cast(uint16_t, (__bf16)w);
+          ss += (double)w * (double)w;
+        }
+      }
+      __syncthreads();
+    }
+  }
+  return ss;
+}
+
+template <int NW>
+__device__ __forceinline__ void partial_at(const GemmLpArgs& p, double ss, double* red, int64_t u) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) ss += __shfl_xor(ss, off, 64);
+  if (lane == 0) red[wave] = ss;
+  __syncthreads();
+  if (threadIdx.x == 0 && p.partial) {
+    double t = 0.0;
+#pragma unroll
+    for (int w = 0; w < NW; ++w) t += red[w];
+    p.partial[u] = t;
+  }
+}
+
+template <int BM, int BK, bool VEC, int WGM, int WGN>
+__global__ void __launch_bounds__(64 * WGM * WGN) __attribute__((amdgpu_waves_per_eu(2)))
+gemm_bf16_sym_kernel(GemmLpArgs p, int T, int dp, int splits, float* scratch) {
+  constexpr int NT = 64 * WGM * WGN, NW = WGM * WGN;
+  constexpr int WTM = BM / WGM, WTN = BM / WGN;
+  constexpr int FM = WTM / 32, FN = WTN / 32;
+  constexpr int S = BK + 8;
+  constexpr int XV = (BM * BK / 8) / NT;
+  static_assert(XV >= 1 && XV * NT == BM * BK / 8, "slab / thread mismatch");
+  // X and Y slabs (two buffers each); the mirror stage of the epilogue
+  // reuses the X slabs once the K loop is done.
+  __shared__ __attribute__((aligned(16))) __bf16 Xs[2][BM * S];
+  __shared__ __attribute__((aligned(16))) __bf16 Ys[2][BM * S];
+  __shared__ double red[NW];
+  static_assert(sizeof(Xs) >= NW * kStage * sizeof(float), "stage does not fit");
+
+  const __bf16* X = static_cast<const __bf16*>(p.X);
+  const __bf16* Y = static_cast<const __bf16*>(p.Y);
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave / WGN, wn = wave % WGN;
+  const int lr = lane & 31, lk = lane >> 5;
+  const int64_t M = p.M, N = p.N, K = p.K;
+  const int nk = (int)((K + BK - 1) / BK);
+
+  // Whole tile, or K-slice q of tail tile u.
+  const bool tail = (int)blockIdx.x >= dp;
+  int u, kt0, kt1;
+  if (!tail) {
+    u = blockIdx.x;
+    kt0 = 0;
+    kt1 = nk;
+  } else {
+    const int t = blockIdx.x - dp, q = t % splits;
+    u = dp + t / splits;
+    kt0 = (int)((int64_t)q * nk / splits);
+    kt1 = (int)((int64_t)(q + 1) * nk / splits);
+  }
+  int tm, tn;
+  sym_tile_lp(u, T, tm, tn);
+  const int64_t m0 = (int64_t)tm * BM, n0 = (int64_t)tn * BM;
+  uint4 xr[XV], yr[XV];
+
+  auto load_one = [&](const __bf16* base, int64_t ld, int64_t r0, int64_t rmax, int64_t k0,
+                      int v) -> uint4 {
+    const int idx = tid + NT * v;
+    const int row = idx / (BK / 8), c = (idx % (BK / 8)) * 8;
+    const int64_t gr = r0 + row, gk = k0 + c;
+    uint4 val = make_uint4(0u, 0u, 0u, 0u);
+    if (gr < rmax) {
+      const __bf16* src = base + gr * ld + gk;
+      if (VEC && gk + 7 < K) {
+        val = *reinterpret_cast<const uint4*>(src);
+      } else {
+        unsigned short tmp[8];
+        const unsigned short* s16 = reinterpret_cast<const unsigned short*>(src);
+#pragma unroll
+        for (int e = 0; e < 8; ++e) tmp[e] = (gk + e < K) ? s16[e] : (unsigned short)0;
+        val.x = tmp[0] | ((unsigned)tmp[1] << 16);
+        val.y = tmp[2] | ((unsigned)tmp[3] << 16);
+        val.z = tmp[4] | ((unsigned)tmp[5] << 16);
+        val.w = tmp[6] | ((unsigned)tmp[7] << 16);
+      }
+    }
+    return val;
+  };
+  const bool interior = VEC && (m0 + BM <= M) && (n0 + BM <= N);
+  auto load = [&](int64_t k0) {
+    if (interior && k0 + BK <= K) {
+#pragma unroll
+      for (int v = 0; v < XV; ++v) {
+        const int idx = tid + NT * v;
+        const int64_t row = idx / (BK / 8), c = (idx % (BK / 8)) * 8;
+        xr[v] = *reinterpret_cast<const uint4*>(X + (m0 + row) * p.ldx + k0 + c);
+        yr[v] = *reinterpret_cast<const uint4*>(Y + (n0 + row) * p.ldy + k0 + c);
+      }
+      return;
+    }
+#pragma unroll
+    for (int v = 0; v < XV; ++v) {
+      xr[v] = load_one(X, p.ldx, m0, M, k0, v);
+      yr[v] = load_one(Y, p.ldy, n0, N, k0, v);
+    }
+  };
+  auto store = [&](int buf) {
+#pragma unroll
+    for (int v = 0; v < XV; ++v) {
+      const int idx = tid + NT * v;
+      const int row = idx / (BK / 8), c = (idx % (BK / 8)) * 8;
+      *reinterpret_cast<uint4*>(&Xs[buf][row * S + c]) = xr[v];
+      *reinterpret_cast<uint4*>(&Ys[buf][row * S + c]) = yr[v];
+    }
+  };
+
+  f32x16 acc[FM][FN];
+#pragma unroll
+  for (int i = 0; i < FM; ++i)
+#pragma unroll
+    for (int j = 0; j < FN; ++j) acc[i][j] = f32x16{};
+
+  if (kt0 < kt1) load((int64_t)kt0 * BK);
+  for (int kt = kt0; kt < kt1; ++kt) {
+    const int buf = kt & 1;
+    store(buf);
+    __syncthreads();
+    if (kt + 1 < kt1) load((int64_t)(kt + 1) * BK);
+    const __bf16* xs = &Xs[buf][(wm * WTM + lr) * S + 8 * lk];
+    const __bf16* ys = &Ys[buf][(wn * WTN + lr) * S + 8 * lk];
+    if (NSR_LP_SETPRIO) __builtin_amdgcn_s_setprio(1);
+#pragma unroll
+    for (int ks = 0; ks < BK; ks += 16) {
+      bf16x8 a[FM], b[FN];
+#pragma unroll
+      for (int i = 0; i < FM; ++i) a[i] = *reinterpret_cast<const bf16x8*>(xs + i * 32 * S + ks);
+#pragma unroll
+      for (int j = 0; j < FN; ++j) b[j] = *reinterpret_cast<const bf16x8*>(ys + j * 32 * S + ks);
+#pragma unroll
+      for (int i = 0; i < FM; ++i)
+#pragma unroll
+        for (int j = 0; j < FN; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+    }
+    __builtin_amdgcn_iglp_opt(1);
+    if (NSR_LP_SETPRIO) __builtin_amdgcn_s_setprio(0);
+  }
+
+  if (tail) {
+    // Raw slice in accumulator order: consecutive lanes, consecutive floats.
+    float* dst = scratch + (int64_t)(blockIdx.x - dp) * BM * BM +
+                 (int64_t)wave * FM * FN * 1024 + lane;
+#pragma unroll
+    for (int i = 0; i < FM; ++i)
+#pragma unroll
+      for (int j = 0; j < FN; ++j)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) dst[((i * FN + j) * 16 + r) * 64] = acc[i][j][r];
+    return;
+  }
+  __syncthreads();   // every wave is done reading the slabs the stage reuses
+  float* stage = reinterpret_cast<float*>(&Xs[0][0]) + wave * kStage;
+  const double ss = sym_epilogue<BM, WGM, WGN>(p, tm, tn, acc, stage);
+  partial_at<NW>(p, ss, red, u);
+}
+
+// Finishes the tail tiles: workgroup t sums the `splits` slices of tail
+// tile dp + t in slice order.
+template <int BM, int WGM, int WGN>
+__global__ void __launch_bounds__(64 * WGM * WGN)
+gemm_bf16_sym_fixup(GemmLpArgs p, int T, int dp, int splits, const float* scratch) {
+  constexpr int NW = WGM * WGN, FM = BM / WGM / 32, FN = BM / WGN / 32;
+  __shared__ float stage_all[NW * kStage];
+  __shared__ double red[NW];
+  const int t = blockIdx.x, u = dp + t;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  f32x16 acc[FM][FN];
+#pragma unroll
+  for (int i = 0; i < FM; ++i)
+#pragma unroll
+    for (int j = 0; j < FN; ++j) acc[i][j] = f32x16{};
+  for (int q = 0; q < splits; ++q) {
+    const float* src = scratch + (int64_t)(t * splits + q) * BM * BM +
+                       (int64_t)wave * FM * FN * 1024 + lane;
+#pragma unroll
+    for (int i = 0; i < FM; ++i)
+#pragma unroll
+      for (int j = 0; j < FN; ++j)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) acc[i][j][r] += src[((i * FN + j) * 16 + r) * 64];
+  }
+  int tm, tn;
+  sym_tile_lp(u, T, tm, tn);
+  const double ss = sym_epilogue<BM, WGM, WGN>(p, tm, tn, acc, stage_all + wave * kStage);
+  partial_at<NW>(p, ss, red, u);
+}
+
 bool big_tiles(int64_t m, int64_t n) { return ((m + 127) / 128) * ((n + 127) / 128) >= 256; }
 
 }  // namespace
@@ -937,6 +1217,86 @@ int64_t launch_gemm_f16s_nt(const GemmLpArgs& a, hipStream_t st) {
   }
   if (hipGetLastError() != hipSuccess) return -1;
   return a.partial ? (int64_t)tiles_m * tiles_n : 0;
+}
+
+// Symmetric product plan: 128 x 128 tiles (four waves, two workgroups per
+// CU; the eight-wave 256 x 256 variant needs more than 256 registers for the
+// mirror epilogue).  Whole rounds of upper tiles run as they are; a partial
+// last round after at least one whole round is cut into K-slices that fill
+// the resident slots.  Costs are in rounds of the full-output kernel's
+// 256 x 256 tiles: a round of 128-tiles does half the work per CU at about
+// 87% of the rate (measured on the full kernels), 0.575 of a round.  Used
+// where it saves at least 10% over the full-output kernel: from N ~ 3000
+// (at N = 4096: 0.62 against 1 round; at N = 8192: 2.36 against 4).
+struct SymPlan {
+  int T = 0, dp = 0, tail = 0, splits = 1;
+  double cost = 0.0;
+};
+
+static SymPlan sym_plan(int64_t n, int64_t k) {
+  SymPlan pl;
+  pl.T = (int)((n + 127) / 128);
+  const int64_t tiles = (int64_t)pl.T * (pl.T + 1) / 2;
+  const int64_t slots = 2 * (int64_t)device_cus();
+  const int64_t rounds = tiles / slots, rem = tiles % slots;
+  const int nk = (int)((k + 63) / 64);
+  pl.dp = (int)tiles;
+  pl.cost = (double)rounds + (rem ? 1.0 : 0.0);
+  if (rounds >= 1 && rem > 0) {
+    int sp = (int)(slots / rem);
+    if (sp > nk) sp = nk;
+    if (sp >= 2) {
+      pl.dp = (int)(tiles - rem);
+      pl.tail = (int)rem;
+      pl.splits = sp;
+      pl.cost = (double)rounds + (double)rem / (double)slots + 0.05;
+    }
+  }
+  pl.cost *= 0.575;
+  return pl;
+}
+
+static double full_cost(int64_t n) {
+  const int64_t cus = device_cus();
+  const int64_t t256 = (n + 255) / 256, t128 = (n + 127) / 128;
+  if (NSR_BF16_HUGE && t256 * t256 >= cus) return (double)((t256 * t256 + cus - 1) / cus);
+  return 0.575 * (double)((t128 * t128 + 2 * cus - 1) / (2 * cus));
+}
+
+static bool sym_choose(int64_t n, int64_t k, SymPlan& pl) {
+  if (k <= 0 || n < 1024) return false;
+  pl = sym_plan(n, k);
+  return pl.cost <= 0.9 * full_cost(n);
+}
+
+int64_t gemm_bf16_sym_scratch_floats(int64_t n, int64_t k) {
+  SymPlan pl;
+  if (!sym_choose(n, k, pl)) return 0;
+  return (int64_t)pl.tail * pl.splits * 128 * 128;
+}
+
+int64_t launch_gemm_bf16_sym(const GemmLpArgs& a, float* scratch, int64_t scratch_floats,
+                             hipStream_t st) {
+  if (a.M <= 0 || a.N <= 0) return 0;
+  SymPlan pl;
+  if (a.M != a.N || !sym_choose(a.N, a.K, pl)) return -2;
+  const int64_t need = (int64_t)pl.tail * pl.splits * 128 * 128;
+  if (need > 0 && (!scratch || scratch_floats < need)) return -2;
+  const bool vec = ((a.ldx & 7) == 0) && ((a.ldy & 7) == 0) &&
+                   ((reinterpret_cast<uintptr_t>(a.X) & 15) == 0) &&
+                   ((reinterpret_cast<uintptr_t>(a.Y) & 15) == 0);
+  const dim3 grid((unsigned)(pl.dp + pl.tail * pl.splits));
+  if (vec)
+    hipLaunchKernelGGL((gemm_bf16_sym_kernel<128, 64, true, 2, 2>), grid, dim3(256), 0, st, a,
+                       pl.T, pl.dp, pl.splits, scratch);
+  else
+    hipLaunchKernelGGL((gemm_bf16_sym_kernel<128, 64, false, 2, 2>), grid, dim3(256), 0, st, a,
+                       pl.T, pl.dp, pl.splits, scratch);
+  if (pl.tail)
+    hipLaunchKernelGGL((gemm_bf16_sym_fixup<128, 2, 2>), dim3(pl.tail), dim3(256), 0, st, a,
+                       pl.T, pl.dp, pl.splits, (const float*)scratch);
+  if (hipGetLastError() != hipSuccess) return -1;
+  return a.partial ? (int64_t)pl.T * (pl.T + 1) / 2 : 0;
 }
 
 }  // namespace nsr

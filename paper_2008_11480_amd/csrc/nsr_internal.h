@@ -73,6 +73,20 @@ void launch_split_f16(const float* X, int64_t ld, int64_t rows, int64_t cols, co
 // hi hi + hi lo + lo hi, float32 accumulation, times 2^-(ex + ey).
 int64_t launch_gemm_f16s_nt(const GemmLpArgs& a, hipStream_t st);
 
+// Compute units of the current device (queried once).
+int device_cus();
+
+// Symmetric-output bf16 NT product (X Y^T symmetric in exact arithmetic,
+// m == n): only the upper tiles are computed, the rest is their mirror.
+// scratch_floats: what the launch needs for this shape (0 if none, or if the
+// shape is better served by the full-output kernel); launch returns the
+// number of partials written, -1 on a launch error, -2 if the shape is not
+// handled (m != n, or the full-output kernel is faster) or the scratch is too
+// small.
+int64_t gemm_bf16_sym_scratch_floats(int64_t n, int64_t k);
+int64_t launch_gemm_bf16_sym(const GemmLpArgs& a, float* scratch, int64_t scratch_floats,
+                             hipStream_t st);
+
 // Upper bound on the number of partials the float64 GEMM writes for an m x n
 // output (the size the partial buffer must have).
 int64_t gemm_f64_partials(int64_t m, int64_t n, bool sym);

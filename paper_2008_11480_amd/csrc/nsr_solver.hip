@@ -345,8 +345,11 @@ int mm(ns_solver* s, Mat& D, const Mat* X, const Mat& Y, const Mat* E1, const Ma
     a.diag = (float)diag;
     a.scale = (float)scale;
     a.partial = want_norm ? s->partial : nullptr;
-    np = bf ? launch_gemm_bf16_nt(a, s->stream)
-            : (split ? launch_gemm_f16s_nt(a, s->stream) : launch_gemm_f32_nn(a, s->stream));
+    if (bf) {
+      np = launch_gemm_bf16_nt(a, s->stream);
+    } else {
+      np = split ? launch_gemm_f16s_nt(a, s->stream) : launch_gemm_f32_nn(a, s->stream);
+    }
     tkind = bf ? 3 : (split ? 4 : 2);
   }
   if (np < 0) return fail(NS_EHIP, "GEMM launch failed: %s", hipGetErrorString(hipGetLastError()));
@@ -1037,6 +1040,7 @@ int ns_create(int device, void* hip_stream, int64_t n, int precision, void* work
     s->aexp = reinterpret_cast<float*>(take(align_up(sizeof(float), kAlign)));
     s->sp = carve_split(take(split_scratch_bytes(n, n, n)), n, n, n);
   }
+
   s->r = reinterpret_cast<double*>(take(align_up((size_t)n * sizeof(double), kAlign)));
   s->vt = reinterpret_cast<double*>(take(align_up((size_t)n * sizeof(double), kAlign)));
   s->vw[0] = reinterpret_cast<double*>(take(align_up((size_t)n * sizeof(double), kAlign)));
@@ -1627,6 +1631,73 @@ int ns_gemm_f32_split(void* hip_stream, int64_t m, int64_t n, int64_t k, const f
   double* part = sumsq_out ? sumsq_out + 1 : nullptr;
   a.partial = part;
   const int64_t np = launch_gemm_f16s_nt(a, st);
+  if (np < 0) return fail(NS_EHIP, "GEMM launch failed: %s", hipGetErrorString(hipGetLastError()));
+  if (sumsq_out) launch_reduce(part, np, sumsq_out, 0, 0.0, st);
+  if (hipGetLastError() != hipSuccess) return fail(NS_EHIP, "kernel launch failed");
+  return NS_OK;
+}
+
+// The symmetric-output bf16 kernel faulted the GPU on its first test and the
+// fault's cause has not been found, so the path is switched off: the flag is
+// rejected and the solver runs every bf16 product in full.
+constexpr bool kBf16SymEnabled = false;
+
+size_t ns_gemm_bf16_scratch_bytes(int64_t m, int64_t n, int64_t k, int flags) {
+  if (!kBf16SymEnabled) return 0;
+  if (m <= 0 || n <= 0 || k < 0 || m != n || !(flags & NS_GEMM_SYMMETRIC)) return 0;
+  return (size_t)gemm_bf16_sym_scratch_floats(n, k) * sizeof(float);
+}
+
+int ns_gemm_bf16_nt_ws(void* hip_stream, int64_t m, int64_t n, int64_t k, const uint16_t* X,
+                       int64_t ldx, const uint16_t* Y, int64_t ldy, float* D, int64_t ldd,
+                       uint16_t* Db, int64_t lddb, const float* E1, int64_t lde1, const float* E2,
+                       int64_t lde2, float diag, float scale, int flags, double* sumsq_out,
+                       void* scratch, size_t scratch_bytes) {
+  if (!(flags & NS_GEMM_SYMMETRIC))
+    return gemm_lp_entry(true, hip_stream, m, n, k, X, ldx, Y, ldy, D, ldd, Db, lddb, E1, lde1,
+                         E2, lde2, diag, scale, sumsq_out);
+  if (flags & ~NS_GEMM_SYMMETRIC) return fail(NS_EINVAL, "unknown flags %d", flags);
+  if (!kBf16SymEnabled)
+    return fail(NS_EINVAL, "the symmetric-output bf16 kernel is disabled in this build");
+  if (m != n) return fail(NS_EINVAL, "a symmetric output needs m == n");
+  if (m < 0 || k < 0) return fail(NS_EINVAL, "negative size");
+  if (m == 0) return NS_OK;
+  if ((!D && !Db) || (k > 0 && (!X || !Y))) return fail(NS_EINVAL, "null operand");
+  if (k > 0 && (ldx < k || ldy < k)) return fail(NS_EINVAL, "leading dimension too small");
+  if ((D && ldd < n) || (Db && lddb < n)) return fail(NS_EINVAL, "output leading dimension too small");
+  if ((E1 && lde1 < n) || (E2 && lde2 < n)) return fail(NS_EINVAL, "addend leading dimension too small");
+  if ((D && ((const void*)D == X || (const void*)D == Y)) ||
+      (Db && ((const void*)Db == X || (const void*)Db == Y)))
+    return fail(NS_EINVAL, "outputs must not alias X or Y");
+  const size_t need = ns_gemm_bf16_scratch_bytes(m, n, k, flags);
+  if (need > 0 && (!scratch || scratch_bytes < need))
+    return fail(NS_ENOMEM, "scratch too small: %zu bytes needed", need);
+  if (scratch && (reinterpret_cast<uintptr_t>(scratch) & 15) != 0)
+    return fail(NS_EINVAL, "scratch must be 16-byte aligned");
+  hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
+  GemmLpArgs a{};
+  a.X = X;
+  a.Y = Y;
+  a.D = D;
+  a.Db = Db;
+  a.E1 = E1;
+  a.E2 = E2;
+  a.ldx = ldx;
+  a.ldy = ldy;
+  a.ldd = ldd;
+  a.lddb = lddb;
+  a.lde1 = lde1;
+  a.lde2 = lde2;
+  a.M = m;
+  a.N = n;
+  a.K = k;
+  a.diag = diag;
+  a.scale = scale;
+  double* part = sumsq_out ? sumsq_out + 1 : nullptr;
+  a.partial = part;
+  int64_t np = launch_gemm_bf16_sym(a, static_cast<float*>(scratch),
+                                    (int64_t)(scratch_bytes / sizeof(float)), st);
+  if (np == -2) np = launch_gemm_bf16_nt(a, st);   // shape served by the full-output kernel
   if (np < 0) return fail(NS_EHIP, "GEMM launch failed: %s", hipGetErrorString(hipGetLastError()));
   if (sumsq_out) launch_reduce(part, np, sumsq_out, 0, 0.0, st);
   if (hipGetLastError() != hipSuccess) return fail(NS_EHIP, "kernel launch failed");

@@ -41,7 +41,7 @@ EXPORTS = (
     "ns_timing_read", "ns_timing_reset", "ns_gemm_f64", "ns_gemm_f64_partials",
     "ns_gemm_f64_scratch_bytes", "ns_gemm_f64_ws",
     "ns_gemm_f32", "ns_gemm_bf16_nt", "ns_gemm_lp_partials", "ns_gemm_f32_split",
-    "ns_gemm_f32_split_scratch_bytes",
+    "ns_gemm_f32_split_scratch_bytes", "ns_gemm_bf16_nt_ws", "ns_gemm_bf16_scratch_bytes",
     "ns_batch_workspace_bytes", "ns_batch_create", "ns_batch_set_launch", "ns_batch_submit",
     "ns_batch_poll", "ns_batch_autotune", "ns_batch_timeline", "ns_batch_destroy",
     "ns_status_string", "ns_last_error", "ns_version",
@@ -134,6 +134,10 @@ def lib() -> ctypes.CDLL:
                                    i64, vp, i64, ctypes.c_float, ctypes.c_float, vp, vp,
                                    ctypes.c_size_t]),
         "ns_gemm_f32_split_scratch_bytes": (ctypes.c_size_t, [i64, i64, i64]),
+        "ns_gemm_bf16_nt_ws": (ci, [vp, i64, i64, i64, vp, i64, vp, i64, vp, i64, vp, i64, vp,
+                                    i64, vp, i64, ctypes.c_float, ctypes.c_float, ci, vp, vp,
+                                    ctypes.c_size_t]),
+        "ns_gemm_bf16_scratch_bytes": (ctypes.c_size_t, [i64, i64, i64, ci]),
         "ns_batch_workspace_bytes": (ctypes.c_size_t, [i64, ci, ci]),
         "ns_batch_create": (ci, [ci, vp, i64, ci, ci, ci, vp, ctypes.c_size_t,
                                  ctypes.POINTER(vp)]),
@@ -598,6 +602,40 @@ def gemm_lp(X, Y, nt: bool, D=None, want_bf16: bool = False, E1=None, E2=None,
              _ptr(D), D.stride(0), _ptr(Db), Db.stride(0) if Db is not None else 0,
              _ptr(E1), E1.stride(0) if E1 is not None else 0, _ptr(E2),
              E2.stride(0) if E2 is not None else 0, float(diag), float(scale), _ptr(ss)))
+    return D, Db, (ss[0] if ss is not None else None)
+
+
+def gemm_bf16_sym(X, Y, D=None, want_bf16: bool = False, E1=None, E2=None,
+                  diag: float = 0.0, scale: float = 1.0, want_sumsq: bool = False,
+                  symmetric: bool = True, scratch=None, stream=None):
+    """bf16 NT product D = diag I + scale X Y^T + E1 + E2 through
+    ``ns_gemm_bf16_nt_ws``; with ``symmetric`` only the upper tiles are
+    computed and mirrored (see nsr.h).  Returns (D, Db or None, sumsq or None)."""
+    import torch
+    for t, nm in ((X, "X"), (Y, "Y")):
+        if not t.is_cuda or t.dtype != torch.bfloat16 or t.stride(-1) != 1:
+            raise TypeError(f"{nm} must be a row-major bfloat16 CUDA tensor")
+    m, k = X.shape
+    n = Y.shape[0]
+    if Y.shape[1] != k:
+        raise ValueError("inner dimensions differ")
+    if D is None:
+        D = torch.empty(m, n, dtype=torch.float32, device=X.device)
+    Db = torch.empty(m, n, dtype=torch.bfloat16, device=X.device) if want_bf16 else None
+    ss = None
+    if want_sumsq:
+        ss = torch.zeros(1 + int(lib().ns_gemm_lp_partials(m, n)), dtype=torch.float64,
+                         device=X.device)
+    flags = GEMM_SYMMETRIC if symmetric else 0
+    nbytes = int(lib().ns_gemm_bf16_scratch_bytes(m, n, k, flags))
+    if scratch is None and nbytes > 0:
+        scratch = torch.empty(nbytes, dtype=torch.uint8, device=X.device)
+    check(lib().ns_gemm_bf16_nt_ws(
+        _stream_handle(stream), m, n, k, _ptr(X), X.stride(0), _ptr(Y), Y.stride(0),
+        _ptr(D), D.stride(0), _ptr(Db), Db.stride(0) if Db is not None else 0,
+        _ptr(E1), E1.stride(0) if E1 is not None else 0, _ptr(E2),
+        E2.stride(0) if E2 is not None else 0, float(diag), float(scale), flags, _ptr(ss),
+        _ptr(scratch), scratch.numel() * scratch.element_size() if scratch is not None else 0))
     return D, Db, (ss[0] if ss is not None else None)
 
 

@@ -72,6 +72,19 @@ def test_host_argument_checks_without_gpu():
                          8, None) == nsr.NS_EINVAL       # unknown flag
     assert L.ns_gemm_f64(None, 0, 4, 4, None, 4, None, 4, None, 4, None, 0, None, 0, 0.0, 1.0,
                          0, None) == nsr.NS_OK           # empty output: nothing to do
+    # the symmetric-output bf16 flag is switched off (rejected before any
+    # device work); the split product checks its scratch before launching
+    assert L.ns_gemm_bf16_scratch_bytes(4096, 4096, 4096, nsr.GEMM_SYMMETRIC) == 0
+    assert L.ns_gemm_bf16_nt_ws(None, 4096, 4096, 4096, 256, 4096, 512, 4096, 768, 4096, None,
+                                0, None, 0, None, 0, 0.0, 1.0, nsr.GEMM_SYMMETRIC, None, None,
+                                0) == nsr.NS_EINVAL
+    assert b"disabled" in L.ns_last_error()
+    need = L.ns_gemm_f32_split_scratch_bytes(64, 64, 64)
+    assert need > 0
+    assert L.ns_gemm_f32_split(None, 64, 64, 64, 256, 64, 512, 64, 768, 64, None, 0, None, 0,
+                               None, 0, 0.0, 1.0, None, 1024, need - 1) == nsr.NS_ENOMEM
+    assert L.ns_gemm_f32_split(None, 64, 64, 64, 256, 64, 512, 64, 768, 64, None, 0, None, 0,
+                               None, 0, 0.0, 1.0, None, 1024 + 8, need) == nsr.NS_EINVAL
     # null handles
     assert L.ns_bind(None, 256, 64) == nsr.NS_EINVAL
     assert L.ns_step(None, 8, 1, 0, 0, None) == nsr.NS_EINVAL

@@ -170,6 +170,122 @@ def test_gemm_f32_split_full_size_sampled(torch):
     assert np.all(np.abs(got - ref) <= 2 * bound), float(np.max(np.abs(got - ref) / bound))
 
 
+SYM_SKIP = pytest.mark.skip(
+    reason="symmetric-output bf16 kernel disabled: its first GPU run (N=3000, K=3000, no "
+           "addends) ended in a memory aperture violation whose cause has not been found")
+
+
+def sym_operands(torch, n, k, addends, seed):
+    """bf16 X, Y with X Y^T symmetric in exact arithmetic (Y = X) and
+    symmetric float32 addends."""
+    g = torch.Generator(device="cpu").manual_seed(seed)
+    X = torch.randn(n, k, generator=g).to(torch.bfloat16)
+    E = []
+    for _ in range(addends):
+        e = torch.randn(n, n, generator=g, dtype=torch.float32)
+        E.append((e + e.T) / 2)
+    return X, E
+
+
+@SYM_SKIP
+@pytest.mark.parametrize("addends", [0, 2])
+@pytest.mark.parametrize("n,k", [(3000, 3000), (4096, 4096), (4100, 640), (3333, 70)])
+def test_gemm_bf16_symmetric_output(torch, n, k, addends):
+    """Symmetric-output bf16 product: the lower triangle is the exact mirror
+    of the upper one (D and Db bitwise symmetric), the upper triangle meets
+    the element-wise bound against float64, Db = bf16(D) and the sum of
+    squares covers both triangles.  Shapes: one partial round (3000, 3333
+    with K = 70, a ragged last K slab), a round plus a split tail (4096:
+    512 whole tiles + 16 tiles in 32 K-slices), ragged tiles with a tail
+    (4100 with K = 640)."""
+    X, E = sym_operands(torch, n, k, addends, seed=n + k + addends)
+    Xc = X.cuda()
+    D, Db, ss = nsr.gemm_bf16_sym(Xc, Xc, want_bf16=True,
+                                  E1=E[0].cuda() if addends > 0 else None,
+                                  E2=E[1].cuda() if addends > 1 else None,
+                                  diag=1.0, scale=-0.5, want_sumsq=True)
+    torch.cuda.synchronize()
+    assert torch.equal(D, D.T) and torch.equal(Db, Db.T)
+    assert torch.equal(Db, D.to(torch.bfloat16))
+    Xd = X.double().cuda()
+    ref = -0.5 * (Xd @ Xd.T) + torch.eye(n, dtype=torch.float64, device="cuda")
+    babs = 0.5 * (Xd.abs() @ Xd.abs().T) + torch.eye(n, dtype=torch.float64, device="cuda")
+    for e in E:
+        ref += e.double().cuda()
+        babs += e.double().cuda().abs()
+    err = (D.double() - ref).abs()
+    up = torch.triu(torch.ones(n, n, dtype=torch.bool, device="cuda"))
+    bound = 2 * g32(k + 4) * babs
+    assert bool(torch.all(err[up] <= bound[up])), float((err / bound)[up].max())
+    ssr = float((D.double() ** 2).sum())
+    assert abs(float(ss.cpu()) - ssr) <= 1e-12 * ssr
+
+
+@SYM_SKIP
+def test_gemm_bf16_symmetric_flag_small_shape_runs_full(torch):
+    """Below the size where the upper-tile kernel saves time the flag runs
+    the full-output kernel: the result equals ns_gemm_bf16_nt's bitwise."""
+    X, E = sym_operands(torch, 1500, 300, 1, seed=3)
+    Xc, Ec = X.cuda(), E[0].cuda()
+    assert nsr.lib().ns_gemm_bf16_scratch_bytes(1500, 1500, 300, nsr.GEMM_SYMMETRIC) == 0
+    D1, _, _ = nsr.gemm_bf16_sym(Xc, Xc, E1=Ec, diag=1.0, scale=-1.0)
+    D2, _, _ = nsr.gemm_lp(Xc, Xc, nt=True, E1=Ec, diag=1.0, scale=-1.0)
+    torch.cuda.synchronize()
+    assert torch.equal(D1, D2)
+
+
+@SYM_SKIP
+def test_gemm_bf16_symmetric_full_size(torch):
+    """N = 8192 (the mixed composite's size: 4 rounds of upper tiles plus 32
+    tiles in 16 K-slices): exact symmetry and sampled upper elements."""
+    n = 8192
+    g = torch.Generator(device="cuda").manual_seed(8)
+    X = torch.randn(n, n, generator=g, device="cuda").to(torch.bfloat16)
+    E1 = torch.randn(n, n, generator=g, device="cuda")
+    E1 = (E1 + E1.T) / 2
+    D, Db, _ = nsr.gemm_bf16_sym(X, X, want_bf16=True, E1=E1, diag=1.0, scale=-1.0)
+    torch.cuda.synchronize()
+    assert torch.equal(D, D.T) and torch.equal(Db, Db.T)
+    rs = np.random.default_rng(5)
+    ii, jj = rs.integers(0, n, 300), rs.integers(0, n, 300)
+    Xc = X.double().cpu().numpy()
+    Dc, Ec = D.double().cpu().numpy(), E1.double().cpu().numpy()
+    for i, j in zip(ii, jj):
+        i, j = min(i, j), max(i, j)
+        ref = -float(Xc[i] @ Xc[j]) + (i == j) + Ec[i, j]
+        bound = 2 * g32(n + 4) * (float(np.abs(Xc[i]) @ np.abs(Xc[j])) + (i == j) + abs(Ec[i, j]))
+        assert abs(Dc[i, j] - ref) <= bound, (i, j)
+
+
+@SYM_SKIP
+def test_mixed_symmetric_powers_match_full(torch):
+    """The mixed solve at N = 3072 with symmetric bf16 power products (the
+    default) against ns_set_symmetric(0) (every product in full): both reach
+    1e-10, with ||F_k|| traces that agree to the bf16 level while above the
+    floor, and the symmetric run counts N^2 (N + 1) flop for its bf16
+    products."""
+    sysm = inputs.spd_qlq(3072, 1e3, seed=12)
+    A, b = to_dev(torch, sysm.A), to_dev(torch, sysm.b)
+    reps = {}
+    for sym in (True, False):
+        s = nsr.Solver(3072, precision=nsr.PREC_MIXED_BF16, composite=False)
+        s.bind(A)
+        s.set_symmetric(sym)
+        s.timing(True)
+        th = torch.zeros_like(b)
+        rep = s.solve(b, th, order=8, resid_tol=1e-10, refine_max=50)
+        assert rep.status == nsr.NS_OK and rep.rel_resid <= 1e-10
+        cnt, _, fl = s.timing_read(3)
+        reps[sym] = (rep, cnt, fl)
+    n = 3072.0
+    (ra, ca, fa), (rb, cb, fb) = reps[True], reps[False]
+    assert fa == pytest.approx(ca * n * n * (n + 1)) and fb == pytest.approx(cb * 2 * n ** 3)
+    for k in range(min(len(ra.fnorm_hist), len(rb.fnorm_hist))):
+        x, y = ra.fnorm_hist[k], rb.fnorm_hist[k]
+        if y > 100 * 1e-3:
+            assert abs(x - y) <= 3e-2 * y, (k, x, y)
+
+
 @pytest.mark.parametrize("addends", [0, 1, 2])
 @pytest.mark.parametrize("m,n,k", SHAPES + [(64, 64, 40), (70, 50, 9), (4100, 4000, 200)])
 def test_gemm_bf16_nt_elementwise(torch, m, n, k, addends):
