@@ -453,16 +453,17 @@ def run_batch(torch, nsr, reps_timed):
                                         [P.theta_of(i) for i in range(count)], **opts)
     log(f"batch autotune: {waves} waves/workgroup, {groups} workgroups ({tune_ms:.1f} ms)")
 
-    def timed(pk, o):
+    def timed(pk, o, bt=None):
+        bt = bt or B
         times, dev = [], []
         for i in range(reps_timed + 1):
             pk.theta.zero_()
             torch.cuda.synchronize()
             t0 = time.perf_counter()
-            t = B.submit_packed(pk, **o)
-            r = B.poll_arrays(t, wait=True)
+            t = bt.submit_packed(pk, **o)
+            r = bt.poll_arrays(t, wait=True)
             dt = time.perf_counter() - t0
-            tl, _ = B.timeline(t)
+            tl, _ = bt.timeline(t)
             if i > 0:
                 times.append(dt)
                 dev.append((np.nanmax(tl[:, [1, 3]]) - np.nanmin(tl[:, [0, 2]])) * 1e-6)
@@ -488,6 +489,18 @@ def run_batch(torch, nsr, reps_timed):
     rel_inf = rel_resid(P)
     log(f"batch inf_half scaling: {mk_inf * 1e3:.1f} ms, ns_steps p50 "
         f"{np.median(steps_inf):.0f} (frobenius {np.median(steps):.0f})")
+    # The same batch in plain float64 (every system solved in float64 from
+    # the start), with its own autotuned launch: the mixed batch's speedup.
+    B64 = nsr.Batch(max_n=256, max_count=count,
+                    slots=min(count, 8 * torch.cuda.get_device_properties(0).multi_processor_count),
+                    precision=nsr.PREC_FP64)
+    w64, g64, _ = B64.autotune([P.A_of(i) for i in range(count)], [P.b_of(i) for i in range(count)],
+                               [P.theta_of(i) for i in range(count)], **opts)
+    mk64, mk64_dev, rep64, _ = timed(P, opts, B64)
+    ok64 = rep64["status"] == nsr.NS_OK
+    rel64 = rel_resid(P)
+    log(f"batch float64 only: {mk64 * 1e3:.1f} ms ({w64} waves, {g64} workgroups)")
+    del B64
     return {
         "workload": "harmonic_batch2048_m8-128_o4", "count": count,
         "scale": "frobenius",
@@ -500,6 +513,13 @@ def run_batch(torch, nsr, reps_timed):
             "ns_steps_p50": float(np.median(steps_inf)), "ns_steps_max": int(steps_inf.max()),
             "ns_steps_total": int(steps_inf.sum()), "ns_steps_total_frobenius": int(steps.sum()),
         },
+        "fp64_only": {
+            "makespan_ms": mk64 * 1e3, "device_ms": mk64_dev * 1e3, "solves_per_s": count / mk64,
+            "launch": {"waves_per_group": w64, "groups": g64}, "ok": int(ok64.sum()),
+            "rel_resid_max_ok": float(rel64[ok64].max()) if ok64.any() else None,
+            "ns_steps_p50": float(np.median(rep64["ns_steps"])),
+        },
+        "speedup_vs_fp64_batch": mk64 / mk,
         "launch": {"waves_per_group": waves, "groups": groups},
         "makespan_ms": mk * 1e3, "device_ms": mk_dev * 1e3, "solves_per_s": count / mk,
         "alg_tflops": flop / mk / 1e12,
