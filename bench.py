@@ -117,6 +117,22 @@ def cpu_baseline(sysm, order, steps_per_solve, refine_steps):
     }
 
 
+def cpu_cholesky(sysm):
+    """The practitioner's CPU comparator (not the oracle): LAPACK Cholesky
+    factorisation and solve (dpotrf + dpotrs through scipy) of the same
+    N = 4096 system on the host's BLAS threads."""
+    import scipy.linalg
+    a, b = sysm.A, sysm.b
+    t0 = time.perf_counter()
+    c = scipy.linalg.cho_factor(a, lower=True, check_finite=False)
+    x = scipy.linalg.cho_solve(c, b, check_finite=False)
+    dt = time.perf_counter() - t0
+    rel = float(np.linalg.norm(b - a @ x) / np.linalg.norm(b))
+    return {"value": 1.0 / dt, "unit": "solves/s", "seconds": dt, "cores": blas_threads(),
+            "kind": "LAPACK Cholesky (dpotrf + dpotrs), comparator, not the oracle",
+            "rel_resid": rel}
+
+
 def measure(torch, solver, b, theta, kw, steps, warmup, label):
     """Warm up, then time `steps` whole solves with per-launch GEMM events."""
     for i in range(warmup):
@@ -559,6 +575,23 @@ def run_serving(torch, nsr, duration_s=3.0, rate=2000.0):
     st["rel_resid_max"] = max(rel) if rel else None
     st["workload"] = f"serving_poisson{int(rate)}_{duration_s:g}s_n32-2048_k10-1e6"
     st.pop("not_ok", None)
+    # The same trace with every solve in float64 (batched systems too): the
+    # offered load exceeds what float64 sustains, so its solves/s over the
+    # span (arrival of the first request to the last completion) is the
+    # float64 path's maximum sustainable rate.
+    del reqs, ex, srv, warm
+    release(torch)
+    reqs = make_requests(trace)
+    torch.cuda.synchronize()
+    ex64 = GpuExecutor(workers=workers, precision=nsr.PREC_FP64, small_max_n=small)
+    warm = make_requests(inputs.serving_trace(rate, 0.02, seed=55))
+    Server(ex64, budget_bytes=32 << 30, workers=workers, small_max_n=small).run(warm)
+    log("serving, float64")
+    st64 = Server(ex64, budget_bytes=32 << 30, workers=workers, small_max_n=small).run(reqs)
+    torch.cuda.synchronize()
+    st["fp64"] = {k: st64[k] for k in ("served", "ok", "solves_per_s", "span_s", "latency_ms_p50",
+                                       "latency_ms_p99", "latency_ms_max")}
+    del reqs, ex64, warm
     return st
 
 
@@ -768,6 +801,7 @@ def main():
     if not args.no_cpu_baseline and not fixed:
         log("timing the CPU oracle on a bounded sample")
         out["cpu_baseline"] = cpu_baseline(sysm, order, last.ns_steps, last.refine_steps)
+        out["cpu_cholesky"] = cpu_cholesky(sysm)
     print(json.dumps(out), flush=True)
 
 

@@ -226,9 +226,13 @@ class GpuExecutor:
         self.streams = [torch.cuda.Stream() for _ in range(workers)]
         self.batch_stream = torch.cuda.Stream()
         cus = torch.cuda.get_device_properties(0).multi_processor_count
+        # float64 executor: batched systems in float64 too; otherwise float32
+        # with float64 re-solves where float32 cannot reach the tolerance
+        bprec = nsr.PREC_FP64 if precision == nsr.PREC_FP64 else nsr.PREC_FP32
         with torch.cuda.stream(self.batch_stream):
             self.batch = nsr.Batch(max_n=small_max_n, max_count=batch_max,
-                                   slots=min(batch_max, 4 * cus), stream=self.batch_stream)
+                                   slots=min(batch_max, 4 * cus), precision=bprec,
+                                   stream=self.batch_stream)
 
     def precision_for(self, n: int) -> int:
         """Precision of a single solve of size n: the split mode from
