@@ -492,6 +492,30 @@ def run_batch(torch, nsr, reps_timed):
 
     mk, mk_dev, rep, tl = timed(P, opts)
     flop = float(rep["gemm_flop"].sum())
+    # Per N bucket: the float32 attempt's algorithmic rate per workgroup
+    # against the two ceilings of one workgroup among `groups`: its share of
+    # the float32 MFMA peak, and its share of HBM bandwidth times the streamed
+    # intensity of an n x n product (read X, Y, write D in float32: n / 6
+    # flop/B).
+    ns_arr = np.array([s.n for s in systems])
+    dur = (tl[:, 1] - tl[:, 0]) * 1e-6          # float32 attempt, s
+    share_mfma = 157.3e12 / groups
+    share_hbm = 8.0e12 / groups
+    per_bucket = []
+    for lo, hi in ((16, 64), (64, 128), (128, 192), (192, 257)):
+        sel = (ns_arr >= lo) & (ns_arr < hi) & np.isfinite(dur) & (dur > 0)
+        if not sel.any():
+            continue
+        n_mid = float(np.median(ns_arr[sel]))
+        f32_flop = rep["mmm"][sel] * 2.0 * ns_arr[sel].astype(float) ** 3
+        rate = f32_flop / dur[sel]
+        per_bucket.append({
+            "n": [lo, hi - 1], "systems": int(sel.sum()),
+            "f32_attempt_ms_p50": float(np.median(dur[sel]) * 1e3),
+            "gflops_per_workgroup_p50": float(np.median(rate) / 1e9),
+            "mfma_share_gflops": share_mfma / 1e9,
+            "hbm_stream_bound_gflops": share_hbm * n_mid / 6 / 1e9,
+        })
     okm = rep["status"] == nsr.NS_OK
     ok, esc = int(okm.sum()), int((rep["precision"] == nsr.PREC_FP64).sum())
     rel = rel_resid(P)
@@ -544,6 +568,7 @@ def run_batch(torch, nsr, reps_timed):
         "rel_resid_p50": float(np.median(rel)),
         "ns_steps_p50": float(np.median(steps)), "ns_steps_max": int(steps.max()),
         "timeline_ms": timeline_summary(tl, [s.n for s in systems], groups),
+        "per_bucket": per_bucket,
     }
 
 
