@@ -827,6 +827,12 @@ def main():
         log("timing the CPU oracle on a bounded sample")
         out["cpu_baseline"] = cpu_baseline(sysm, order, last.ns_steps, last.refine_steps)
         out["cpu_cholesky"] = cpu_cholesky(sysm)
+        # the same oracle sample on one BLAS thread
+        import threadpoolctl
+        with threadpoolctl.threadpool_limits(limits=1, user_api="blas"):
+            one = cpu_baseline(sysm, order, last.ns_steps, last.refine_steps)
+        out["cpu_baseline_1core"] = {"value": one["value"], "unit": one["unit"],
+                                     "cores": one["cores"], "kind": "oracle"}
     print(json.dumps(out), flush=True)
 
 
