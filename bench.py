@@ -797,6 +797,11 @@ def main():
         ss.bind(A)
         ths = torch.zeros_like(b)
         msp = measure(torch, ss, b, ths, kwm, args.steps, args.warmup, "mixed_split")
+        # Program choice in this precision (the autotuner's trial): every
+        # candidate program on the same system, fastest first.
+        sp_trials = autotune.time_programs(ss, b, torch.zeros_like(b), reps=2,
+                                           resid_tol=w["resid_tol"], k_max=w["k_max"],
+                                           refine_max=100)
         thc = ths.cpu().numpy()
         out["mixed_split"] = {
             "workload": args.workload, "precision": "mixed (bf16 powers, residual and G-side "
@@ -808,7 +813,21 @@ def main():
                                             / np.linalg.norm(theta_star)),
             "latency_ms_p50": msp["latency_ms_p50"], "latency_ms_p99": msp["latency_ms_p99"],
             "gemm": msp["gemm"], **report_of(msp["last"]),
+            "programs": [{"program": t.program.name, "ms_per_solve": t.ms,
+                          "solves_per_s": 1e3 / t.ms, "ns_steps": t.ns_steps,
+                          "refine_steps": t.refine_steps, "mmm": t.mmm, "ok": t.ok}
+                         for t in sp_trials],
+            "chosen": sp_trials[0].program.name,
         }
+        # best program per precision against each other (the float64 one from
+        # the programs leg, when it ran)
+        if "programs" in out and sp_trials[0].ok:
+            fb = out["programs"]["trials"][0]
+            out["mixed_split"]["best_vs_fp64_best"] = {
+                "fp64": {"program": fb["program"], "solves_per_s": fb["solves_per_s"]},
+                "mixed_split": {"program": sp_trials[0].program.name,
+                                "solves_per_s": 1e3 / sp_trials[0].ms},
+                "speedup": (1e3 / sp_trials[0].ms) / fb["solves_per_s"]}
         del ss
         torch.cuda.empty_cache()
     if not args.no_mixed and not fixed:
