@@ -13,7 +13,15 @@
 //   rounding asymmetry far below the bf16 rounding of the operands, and the
 //   NT form lets both operands be read with K contiguous.
 //
-// Both write float32 D, optionally a bf16 copy Db (next GEMM's operand), and
+// * gemm_f16s_nt: the float32-class product of the split mode, D = X Y^T
+//   from half-precision hi / lo planes of both operands (three fp16 MFMA
+//   products, v_mfma_f32_32x32x16_f16), after absmax / split_rows /
+//   split_trans have scaled and split the float32 operands.
+// * gemm_bf16_sym / gemm_bf16_sym_fixup: a symmetric-output bf16 product
+//   (upper tiles + mirror); switched off by the library (it faulted the GPU
+//   on its first test, cause not found) and kept for a later fix.
+//
+// All write float32 D, optionally a bf16 copy Db (next GEMM's operand), and
 // optionally one float64 partial sum of D^2 per tile.
 //
 // Accumulator layouts (gfx950, measured): for 16x16x4 f32, element r of lane
