@@ -28,8 +28,7 @@
  *     (float64, or float32 with bf16 copies); A, b, theta and the Richardson
  *     residual are always float64.
  *   - The caller owns A, b, theta and the workspace; the library never calls
- *     hipMalloc on the solve path (ns_create allocates only a 128-byte pinned
- *     host buffer per handle, for reading back the stop-test scalars).  A is borrowed from ns_bind() until the
+ *     hipMalloc on the solve path.  A is borrowed from ns_bind() until the
  *     next ns_bind() or ns_destroy(); it is never written.
  *   - All work is enqueued on the stream given to ns_create() (a hipStream_t
  *     passed as void*; NULL is the default stream).  Calls that return a

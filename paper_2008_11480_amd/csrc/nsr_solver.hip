@@ -45,7 +45,6 @@ namespace {
   } while (0)
 
 constexpr size_t kAlign = 256;
-constexpr int kHostScalars = 16;   // doubles in the pinned read-back buffer
 inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 inline int64_t ld_for(int64_t n) { return (n + 31) / 32 * 32; }
 
@@ -225,7 +224,6 @@ struct ns_solver {
   int graph_gcur = 0;
   int64_t graph_mmm = 0;
   double graph_flop = 0.0;
-  double* hscal = nullptr; // pinned host buffer for scalar read-back (may be null)
   double* sdiag = nullptr; // S = diag(A) (NS_SCALE_DIAG)
   bool diag_scale = false; // G_0 = diag(A)^-1 instead of I / alpha
   double* sk = nullptr;    // split-K scratch of the float64 GEMM
@@ -369,15 +367,10 @@ int mm(ns_solver* s, Mat& D, const Mat* X, const Mat& Y, const Mat* E1, const Ma
   return NS_OK;
 }
 
-// Host copy of device scalars, synchronising the stream.  Through the
-// handle's pinned buffer when it has one: a copy into pageable memory goes
-// through a staging blit and adds its latency to every stop test.
 int read_scalars(ns_solver* s, double* host, int first, int count) {
-  double* dst = (s->hscal && count <= kHostScalars) ? s->hscal : host;
-  HIP_TRY(hipMemcpyAsync(dst, s->scal + first, count * sizeof(double), hipMemcpyDeviceToHost,
+  HIP_TRY(hipMemcpyAsync(host, s->scal + first, count * sizeof(double), hipMemcpyDeviceToHost,
                          s->stream));
   HIP_TRY(hipStreamSynchronize(s->stream));
-  if (dst != host) memcpy(host, dst, count * sizeof(double));
   return NS_OK;
 }
 
@@ -1069,13 +1062,6 @@ int ns_create(int device, void* hip_stream, int64_t n, int precision, void* work
     delete s;
     return fail(NS_ENOMEM, "internal layout exceeds workspace");
   }
-  // Pinned read-back buffer (host memory of the handle); without it the
-  // scalar reads go to pageable memory.
-  if (hipHostMalloc(reinterpret_cast<void**>(&s->hscal), kHostScalars * sizeof(double),
-                    hipHostMallocDefault) != hipSuccess) {
-    s->hscal = nullptr;
-    (void)hipGetLastError();
-  }
   *out = s;
   return NS_OK;
 }
@@ -1085,7 +1071,6 @@ int ns_destroy(ns_solver* s) {
   if (s->graph_exec) (void)hipGraphExecDestroy(s->graph_exec);
   if (s->capture_stream) (void)hipStreamDestroy(s->capture_stream);
   for (hipEvent_t e : s->pool) (void)hipEventDestroy(e);
-  if (s->hscal) (void)hipHostFree(s->hscal);
   delete s;
   return NS_OK;
 }
