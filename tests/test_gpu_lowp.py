@@ -461,6 +461,51 @@ def test_split_mode_timing_kind(torch):
     assert cnt[0] == cnt[3] + cnt[4], cnt
 
 
+@pytest.mark.parametrize("prec", [nsr.PREC_MIXED_BF16, nsr.PREC_MIXED_SPLIT])
+def test_mixed_full_size_spd4096(torch, prec):
+    """N = 4096, kappa = 1e4, order 8 (the mixed legs the benchmark times, in
+    the same launch configuration): refinement reaches the workload's 1e-12,
+    the ||F_k|| trace follows the eigen closed form of eq. (fk1) to the bf16
+    level while above the low-precision floor, and theta matches
+    theta* = Q diag(1/lam) Q^T b within kappa times the attained residual."""
+    w = inputs.WORKLOADS["spd4096_k1e4_o8"]
+    sysm = inputs.spd_qlq(w["n"], w["kappa"], w["seed"])
+    s, th, rep = run(torch, sysm, prec, order=8, form="squaring", k_max=64,
+                     resid_tol=w["resid_tol"], refine_max=100)
+    assert rep.status == nsr.NS_OK and rep.rel_resid <= w["resid_tol"]
+    mu = 1.0 - sysm.lam / rep.alpha
+    floor = min(rep.fnorm_hist)
+    for k, fk in enumerate(rep.fnorm_hist):
+        ref = float(np.sqrt(np.sum(mu ** (2 * 8 ** k))))
+        if ref > 1e3 * floor:
+            assert abs(fk - ref) <= 3e-2 * ref, (k, fk, ref)
+    theta_star = sysm.Q @ ((sysm.Q.T @ sysm.b) / sysm.lam)
+    rel_cpu = np.linalg.norm(sysm.b - sysm.A @ th) / np.linalg.norm(sysm.b)
+    fwd = np.linalg.norm(th - theta_star) / np.linalg.norm(theta_star)
+    assert rel_cpu <= 2 * w["resid_tol"]
+    assert fwd <= 1.01 * w["kappa"] * rel_cpu + 50 * w["kappa"] * U64, (fwd, rel_cpu)
+
+
+def test_split_composite_full_size_spd8192(torch):
+    """N = 8192, kappa = 1e6, double Newton-Schulz order 8 in the split mode
+    (the composite leg the benchmark times): relative residual <= 1e-10 and
+    the forward error against theta* within kappa times the residual."""
+    w = inputs.WORKLOADS["spd8192_k1e6_dns8"]
+    A, b, lam, Q = inputs.spd_qlq_device(w["n"], w["kappa"], w["seed"])
+    s = nsr.Solver(w["n"], precision=nsr.PREC_MIXED_SPLIT, composite=True)
+    s.bind(A)
+    th = torch.zeros_like(b)
+    rep = s.solve(b, th, order=8, form="composite_double", k_max=64, resid_tol=1e-10,
+                  refine_max=100)
+    torch.cuda.synchronize()
+    assert rep.status == nsr.NS_OK and rep.rel_resid <= 1e-10
+    rel = float(torch.linalg.norm(b - A @ th) / torch.linalg.norm(b))
+    theta_star = Q @ ((Q.T.contiguous() @ b) / lam)
+    fwd = float(torch.linalg.norm(th - theta_star) / torch.linalg.norm(theta_star))
+    assert rel <= 2e-10
+    assert fwd <= 1.01 * w["kappa"] * rel + 50 * w["kappa"] * U64, (fwd, rel)
+
+
 def test_mixed_accelerated_composite(torch):
     """Mixed precision with the accelerator of eq. (ttk1): reaches 1e-10 and
     agrees with the float64 oracle to the refinement's accuracy."""
