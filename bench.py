@@ -742,7 +742,7 @@ def main():
         trials = autotune.time_programs(solver, b, theta, autotune.CANDIDATES, reps=1,
                                         resid_tol=w["resid_tol"], k_max=w["k_max"])
         mu = 1.0 - sysm.lam / last.alpha
-        floor = 0.5 * min(last.fnorm_hist)
+        floor = min(last.fnorm_hist)
         out["programs"] = {
             "workload": args.workload, "precision": "fp64",
             "trials": [{"program": t.program.name, "ms_per_solve": t.ms,

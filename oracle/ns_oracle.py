@@ -38,7 +38,7 @@ __all__ = [
     "z_table", "TABLE_ORDERS", "z_form", "form_mmm", "ns_step",
     "dns_init", "dns_step", "richardson_update", "accelerator_apply", "SolveOptions",
     "SolveReport", "riem6_gamma",
-    "solve", "stop_check", "floor_probe_needed", "STOP", "efficiency_index",
+    "solve", "stop_check", "floor_probe_needed", "STOP", "LAW_MARGIN", "efficiency_index",
 ]
 
 
@@ -463,12 +463,23 @@ STOP = {
 }
 
 
-def stop_check(fhist, f_tol, k, k_max, floor_detect=True, f_sq=None):
+# Margin of the error-law floor test (see stop_check).
+LAW_MARGIN = 1e3
+
+
+def stop_check(fhist, f_tol, k, k_max, floor_detect=True, f_sq=None, order=None):
     """Stop rule for the Newton-Schulz phase; the paper gives none.
 
     ``fhist[j] = ||F_j||_F`` for ``j = 0..k``; ``f_sq = ||F_k^2||_F`` (needed
-    only when ``||F_k|| > ||F_{k-1}|| / 2``).  Stop when
+    only when ``||F_k|| > ||F_{k-1}|| / 2``); ``order`` is the step's order n
+    for the programs whose ``F_k`` is ``F_{k-1}^m`` with ``m >= n`` in exact
+    arithmetic (None: not used).  Stop when
     (i) ``||F_k|| <= f_tol``;
+    (ii-a) the error law says rounding dominates: ``F_k = F_{k-1}^n``
+    (eq. fk1) gives ``||F_k||_F <= ||F_{k-1}||_2^{n-1} ||F_{k-1}||_F
+    <= ||F_{k-1}||_F^n`` in exact arithmetic, so with ``||F_{k-1}|| < 1`` a
+    measured ``||F_k|| > LAW_MARGIN ||F_{k-1}||^n`` is rounding error, which
+    another step reproduces: floor, found on the step that reaches it;
     (ii) the rounding floor is reached.  In exact arithmetic
     ``F_k = F_{k-1}^n`` gives ``||F_k|| / ||F_{k-1}|| <= ||F_k||_2^{(n-1)/n}``.
     ``s = ||F_k^2||_F / ||F_k||_F`` estimates ``||F_k||_2`` (it is a lower
@@ -485,6 +496,9 @@ def stop_check(fhist, f_tol, k, k_max, floor_detect=True, f_sq=None):
         return "diverged"
     if fk <= f_tol:
         return "f_tol"
+    if (floor_detect and order and k >= 1 and fhist[k - 1] < 1.0
+            and fk > LAW_MARGIN * fhist[k - 1] ** order):
+        return "floor"
     if floor_detect and k >= 1 and fk > 0.5 * fhist[k - 1]:
         if f_sq is None:
             raise ValueError("||F_k^2|| is needed to test the floor")
@@ -495,9 +509,13 @@ def stop_check(fhist, f_tol, k, k_max, floor_detect=True, f_sq=None):
     return None
 
 
-def floor_probe_needed(fhist, k, floor_detect=True):
+def floor_probe_needed(fhist, k, floor_detect=True, order=None):
     """True when :func:`stop_check` needs ``||F_k^2||``."""
-    return floor_detect and k >= 1 and math.isfinite(fhist[k]) and fhist[k] > 0.5 * fhist[k - 1]
+    if not (floor_detect and k >= 1 and math.isfinite(fhist[k])):
+        return False
+    if order and fhist[k - 1] < 1.0 and fhist[k] > LAW_MARGIN * fhist[k - 1] ** order:
+        return False                       # the error-law test decides
+    return fhist[k] > 0.5 * fhist[k - 1]
 
 
 @dataclasses.dataclass
@@ -626,9 +644,13 @@ def solve(a, b, opts: SolveOptions = SolveOptions()) -> SolveReport:
         rhist.append(float(np.linalg.norm(r)) / bnorm)
         fhist.append(float(np.linalg.norm(f)))
         f_sq = None
-        if floor_probe_needed(fhist, k, opts.floor_detect):
+        # the error-law floor test: classical programs (F_k = F_{k-1}^n) and
+        # the double Newton-Schulz, whose F_k = F_0^(k n^(k+1) + n^k)
+        # (Section 5.1) has an exponent at least n times the previous one
+        law = None if (opts.rates is not None or opts.sri) else opts.order
+        if floor_probe_needed(fhist, k, opts.floor_detect, law):
             f_sq = float(np.linalg.norm(_mm(ctr, f, f)))
-        ns_stop = stop_check(fhist, opts.f_tol, k, opts.k_max, opts.floor_detect, f_sq)
+        ns_stop = stop_check(fhist, opts.f_tol, k, opts.k_max, opts.floor_detect, f_sq, law)
 
     refine = 0
     rel = float("nan")

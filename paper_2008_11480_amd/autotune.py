@@ -51,29 +51,50 @@ CANDIDATES = (
 )
 
 
-def predicted_steps(order: int, rho0: float, floor: float) -> int:
-    """Steps until ``rho0 ** (order ** k) <= floor`` (eq. fk1), plus the step
-    that detects the floor."""
+# Margin of the stop rule's error-law floor test (the library's value).
+LAW_MARGIN = 1e3
+
+
+def _stop_step(exact, order: int, floor: float, k_max: int) -> int:
+    """Step at which the stop rule fires on the modelled history
+    ``f_k = max(exact(k), floor)``: the error-law test (``f_{k-1} < 1`` and
+    ``f_k > LAW_MARGIN f_{k-1}^order``) or, once at the floor, the ratio test
+    (``f_k > f_{k-1} / 2``)."""
+    prev = max(exact(0), floor)
+    for k in range(1, k_max + 1):
+        ex = exact(k)
+        cur = max(ex, floor)
+        if prev < 1.0 and cur > LAW_MARGIN * prev ** order:
+            return k
+        if cur > 0.5 * prev and ex <= floor:
+            return k
+        prev = cur
+    return k_max
+
+
+def predicted_steps(order: int, rho0: float, floor: float, k_max: int = 64) -> int:
+    """Stop step predicted by ``||F_k|| = rho0 ** (order ** k)`` (eq. fk1)
+    with a rounding floor ``floor`` (see :func:`_stop_step`)."""
     if not 0.0 < rho0 < 1.0:
         raise ValueError("rho(F_0) must lie in (0, 1)")
-    need = math.log(floor) / math.log(rho0)          # order^k >= need
-    k = max(0, math.ceil(math.log(max(need, 1.0)) / math.log(order) - 1e-12))
-    return k + 1
+
+    def exact(k):
+        e = float(order) ** k
+        return 0.0 if e > 1e300 else rho0 ** e
+    return _stop_step(exact, order, floor, k_max)
 
 
 def predicted_steps_spectrum(order: int, mu, floor: float, k_max: int = 64) -> int:
-    """Steps until the closed form ``||F_k||_F = sqrt(sum mu_i^(2 order^k))``
-    (eq. fk1, ``mu_i = 1 - lambda_i / alpha``) falls below ``floor`` (a
-    Frobenius-norm rounding floor), plus the step that detects the floor."""
+    """Stop step predicted by the closed form ``||F_k||_F = sqrt(sum
+    mu_i^(2 order^k))`` (eq. fk1, ``mu_i = 1 - lambda_i / alpha``) with a
+    Frobenius-norm rounding floor ``floor`` (see :func:`_stop_step`)."""
     import numpy as np
     mu = np.abs(np.asarray(mu, dtype=np.float64))
-    for k in range(k_max + 1):
+
+    def exact(k):
         e = float(order) ** k
-        if e > 1e300:
-            return k + 1
-        if math.sqrt(float(np.sum(mu ** (2.0 * e)))) <= floor:
-            return k + 1
-    return k_max
+        return 0.0 if e > 1e300 else math.sqrt(float(np.sum(mu ** (2.0 * e))))
+    return _stop_step(exact, order, floor, k_max)
 
 
 @dataclasses.dataclass

@@ -90,6 +90,9 @@ struct BatchArgs {
 
 namespace {
 
+// Margin of the error-law floor test of the stop rule.
+constexpr double kLawMargin = 1e3;
+
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef double f64x4 __attribute__((ext_vector_type(4)));
 
@@ -710,6 +713,10 @@ __device__ bool wg_solve(const BatchArgs& P, const BatchDesc& d, const SlotMats&
       // 2^-(order^2) by now; a norm still >= 1/2 that does not halve belongs
       // to eigenvalues float32 rounds to 1.
       ns_stop = NS_STOP_PRECISION;
+    } else if (P.floor_detect && fprev < 1.0 && fk > kLawMargin * pow(fprev, (double)P.ns_order)) {
+      // Error law (eq. fk1): ||F_k|| <= ||F_{k-1}||^n in exact arithmetic; a
+      // norm far above it is rounding error: floor.
+      ns_stop = NS_STOP_FLOOR;
     } else {
       if (P.floor_detect && fk > 0.5 * fprev) {
         const double f2 = sqrt(wg_gemm<T, NW>(n, F, ldw, nullptr, 0, F, ldw, Pw[0], ldw, nullptr,
@@ -997,6 +1004,8 @@ __device__ bool wg_solve_small(const BatchArgs& P, const BatchDesc& d, T* lds, d
       ns_stop = NS_STOP_F_TOL;
     } else if (bail_k > 0 && k >= bail_k && fk >= 0.5 && fk > 0.5 * fprev) {
       ns_stop = NS_STOP_PRECISION;
+    } else if (P.floor_detect && fprev < 1.0 && fk > kLawMargin * pow(fprev, (double)P.ns_order)) {
+      ns_stop = NS_STOP_FLOOR;   // error law, as in wg_solve
     } else {
       if (P.floor_detect && fk > 0.5 * fprev) {
         // F_k^2 goes to the G buffer G_{k+1} will overwrite (it holds G_{k-1}).

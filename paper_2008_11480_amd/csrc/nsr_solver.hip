@@ -45,6 +45,8 @@ namespace {
   } while (0)
 
 constexpr size_t kAlign = 256;
+// Margin of the error-law floor test of the stop rule.
+constexpr double kLawMargin = 1e3;
 inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 inline int64_t ld_for(int64_t n) { return (n + 31) / 32 * 32; }
 
@@ -1304,6 +1306,17 @@ int richardson_ns_solve(ns_solver* s, const double* b, double* theta, const ns_s
     for (int j = 1; j <= k; ++j)
       if (!isfinite(hh[j]) || hh[j] > f0) ns_stop = NS_STOP_DIVERGED;
   }
+  // Order n of the error law: F_k = F_{k-1}^n for the classical programs,
+  // F_k = F_0^(k n^(k+1) + n^k) for the double Newton-Schulz (Section 5.1),
+  // an exponent at least n times the previous one; so ||F_k|| <=
+  // ||F_{k-1}||^n in exact arithmetic.  0: the general composite and [sri],
+  // whose stop rule is the ratio test alone.
+  const int law = (o->factorization == NS_FACT_HORNER || o->factorization == NS_FACT_SQUARING ||
+                   o->factorization == NS_FACT_TABLE || o->factorization == NS_FACT_UNIFIED ||
+                   o->factorization == NS_FACT_UNIFIED_PLUS1 ||
+                   o->factorization == NS_FACT_COMPOSITE_DOUBLE)
+                      ? o->order
+                      : 0;
   while (ns_stop == NS_STOP_NONE) {
     ++k;
     int rc = any_step(s, o->order, o->factorization, o->p, o->w);
@@ -1330,6 +1343,13 @@ int richardson_ns_solve(ns_solver* s, const double* b, double* theta, const ns_s
       ns_stop = NS_STOP_DIVERGED;
     } else if (fk <= o->f_tol) {
       ns_stop = NS_STOP_F_TOL;
+    } else if (o->floor_detect && law > 0 && h[k - 1] < 1.0 &&
+               fk > kLawMargin * pow(h[k - 1], (double)law)) {
+      // Error law (eq. fk1): F_k = F_{k-1}^n gives ||F_k||_F <= ||F_{k-1}||_F^n
+      // in exact arithmetic; a norm far above that is rounding error, which
+      // another step reproduces, so the floor is found on the step that
+      // reaches it.
+      ns_stop = NS_STOP_FLOOR;
     } else {
       if (o->floor_detect && fk > 0.5 * h[k - 1]) {
         if ((rc = mm(s, s->P[0], &s->F, s->F, nullptr, nullptr, 0.0, 1.0, true, K_POWER)))

@@ -10,30 +10,30 @@ from paper_2008_11480_amd import autotune, inputs
 
 
 def test_predicted_steps_rho0():
-    # rho0 = 1/2, floor 2^-53: order^k >= 53 -> order 8: k = 2 (64 >= 53), +1 detect
-    assert autotune.predicted_steps(8, 0.5, 2.0 ** -53) == 3
-    assert autotune.predicted_steps(2, 0.5, 2.0 ** -53) == 7      # 2^6 = 64
-    assert autotune.predicted_steps(53, 0.5, 2.0 ** -53) == 2     # exactly 53
+    # rho0 = 1/2, floor 2^-53 (f_k = max(rho0^(n^k), floor)).  Order 8:
+    # f_1 = 2^-8, f_2 = floor > 1e3 f_1^8 = 1e3 2^-64: the error law fires at 2.
+    assert autotune.predicted_steps(8, 0.5, 2.0 ** -53) == 2
+    assert autotune.predicted_steps(2, 0.5, 2.0 ** -53) == 6      # 2^6 = 64 >= 53
+    # order 53 reaches the floor exactly at step 1, where the law cannot tell
+    # (f_1 = 2^-53 = f_0^53): found at step 2
+    assert autotune.predicted_steps(53, 0.5, 2.0 ** -53) == 2
     assert autotune.predicted_steps(4, 0.5, 0.75) == 1            # already below
     with pytest.raises(ValueError):
         autotune.predicted_steps(4, 1.0, 1e-16)
 
 
 @pytest.mark.parametrize("order", [4, 8, 11, 15, 45])
-def test_predicted_steps_spectrum_matches_oracle_iterates(order):
-    """The closed-form prediction equals the step at which the oracle's
-    float64 iterates first fall below the same Frobenius level (plus one)."""
+def test_predicted_steps_spectrum_matches_oracle_stop(order):
+    """The closed-form prediction (eq. fk1, with the oracle's own float64
+    floor as the floor level) equals the step at which the oracle's stop rule
+    ends the iteration."""
     sysm = inputs.spd_qlq(48, 1e3, seed=5)
-    alpha = oracle.alpha_frobenius(sysm.A)
-    mu = 1.0 - sysm.lam / alpha
-    level = 1e-6
     form = "table" if order in (11, 15, 45) else "squaring"
-    g = np.eye(48) / alpha
-    k = 0
-    while np.linalg.norm(oracle.residual(sysm.A, g)) > level:
-        g = oracle.ns_step(sysm.A, g, order, form)
-        k += 1
-    assert autotune.predicted_steps_spectrum(order, mu, level) == k + 1
+    rep = oracle.solve(sysm.A, sysm.b, oracle.SolveOptions(order=order, form=form,
+                                                           resid_tol=1e-13))
+    assert rep.ns_stop == "floor"
+    mu = 1.0 - sysm.lam / rep.alpha
+    assert autotune.predicted_steps_spectrum(order, mu, min(rep.fnorm_hist)) == rep.ns_steps
 
 
 def test_bucket_and_names():

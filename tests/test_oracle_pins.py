@@ -298,6 +298,40 @@ def test_stop_rule():
         chk([1.0, 0.9], 0.0, 1, 64)
 
 
+def test_error_law_floor_rule():
+    """The error-law floor test (eq. fk1: ||F_k|| <= ||F_{k-1}||^n exactly):
+    fires on a norm far above ||F_{k-1}||^n, never while ||F_{k-1}|| >= 1,
+    never on a composite program (order None), and needs no F^2 probe."""
+    chk = oracle.stop_check
+    f = [64.0, 20.0, 1.0, 4e-6, 8.8e-11]                 # 8.8e-11 >> 1e3 (4e-6)^8
+    assert chk(f, 0.0, 4, 64, order=8) == "floor"
+    assert not oracle.floor_probe_needed(f, 4, order=8)
+    assert chk(f, 0.0, 4, 64, f_sq=1e-30) is None        # ratio test alone: continue
+    assert chk(f, 0.0, 4, 64, floor_detect=False, order=8) is None
+    # converging exactly: ||F_k|| at the bound is no floor
+    f = [64.0, 20.0, 0.5, 0.5 ** 8]
+    assert chk(f, 0.0, 3, 64, order=8) is None
+    # ||F_{k-1}|| >= 1: the bound says nothing
+    f = [64.0, 1.5, 1.2]
+    assert chk(f, 0.0, 2, 64, f_sq=1.0, order=8) is None
+
+
+def test_error_law_never_fires_on_exact_iterates():
+    """On exact iterates F_k = F_{k-1}^n of symmetric F with eigenvalues in
+    (-1, 1), ||F_k||_F <= ||F_{k-1}||_F^n always, so the error-law test (which
+    needs a norm LAW_MARGIN times above that) cannot stop an exact iteration."""
+    rng = np.random.default_rng(7)
+    for _ in range(300):
+        m = int(rng.integers(2, 60))
+        mu = rng.uniform(-1, 1, size=m) ** int(rng.integers(1, 6))
+        n = int(rng.choice([2, 3, 4, 8, 11, 45]))
+        prev = float(np.sqrt(np.sum(mu ** 2)))
+        cur = float(np.sqrt(np.sum((mu ** n) ** 2)))
+        assert cur <= prev ** n * (1 + 1e-12) + 1e-300, (n, prev, cur)
+        if prev < 1.0:
+            assert not cur > oracle.LAW_MARGIN * prev ** n
+
+
 def test_floor_rule_is_sound_in_exact_arithmetic():
     """For symmetric F with eigenvalues in (-1, 1) and F_k = F_{k-1}^n:
     ||F_k|| > ||F_{k-1}|| / 2 never happens together with ||F_k^2|| <= ||F_k|| / 4
