@@ -447,7 +447,8 @@ def timeline_summary(tl, ns, groups):
         "end": float(end) / 1e3,
         "longest_f32_solves": [{"n": int(ns[i]), "ms": float(f32[i]) / 1e3} for i in big],
         "longest_f64_solve_ms": float(np.nanmax(f64)) / 1e3 if esc.any() else None,
-        "occupancy": float(busy / (end * groups)) if end > 0 else None,
+        # solves in flight on average (float32 and float64 attempts)
+        "mean_concurrent": float(busy / end) if end > 0 else None,
     }
 
 
@@ -499,8 +500,11 @@ def run_batch(torch, nsr, reps_timed):
     # flop/B).
     ns_arr = np.array([s.n for s in systems])
     dur = (tl[:, 1] - tl[:, 0]) * 1e-6          # float32 attempt, s
-    share_mfma = 157.3e12 / groups
-    share_hbm = 8.0e12 / groups
+    # concurrency: float32 attempts running at once on average over the pass
+    span32 = (np.nanmax(tl[:, 1]) - np.nanmin(tl[:, 0])) * 1e-6
+    conc = max(1.0, float(np.nansum(dur)) / span32) if span32 > 0 else float(groups)
+    share_mfma = 157.3e12 / conc
+    share_hbm = 8.0e12 / conc
     per_bucket = []
     for lo, hi in ((16, 64), (64, 128), (128, 192), (192, 257)):
         sel = (ns_arr >= lo) & (ns_arr < hi) & np.isfinite(dur) & (dur > 0)
@@ -513,6 +517,7 @@ def run_batch(torch, nsr, reps_timed):
             "n": [lo, hi - 1], "systems": int(sel.sum()),
             "f32_attempt_ms_p50": float(np.median(dur[sel]) * 1e3),
             "gflops_per_workgroup_p50": float(np.median(rate) / 1e9),
+            "concurrent_attempts": conc,
             "mfma_share_gflops": share_mfma / 1e9,
             "hbm_stream_bound_gflops": share_hbm * n_mid / 6 / 1e9,
         })
