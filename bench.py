@@ -432,7 +432,7 @@ def release(torch):
     torch.cuda.empty_cache()
 
 
-def timeline_summary(tl, ns, groups):
+def timeline_summary(tl, ns):
     """Critical-path view of a batch from the device timeline (ms)."""
     f32 = tl[:, 1] - tl[:, 0]
     f64 = tl[:, 3] - tl[:, 2]
@@ -494,8 +494,8 @@ def run_batch(torch, nsr, reps_timed):
     mk, mk_dev, rep, tl = timed(P, opts)
     flop = float(rep["gemm_flop"].sum())
     # Per N bucket: the float32 attempt's algorithmic rate per workgroup
-    # against the two ceilings of one workgroup among `groups`: its share of
-    # the float32 MFMA peak, and its share of HBM bandwidth times the streamed
+    # against the two ceilings of one attempt among those in flight at once:
+    # its share of the float32 MFMA peak, and its share of HBM bandwidth times the streamed
     # intensity of an n x n product (read X, Y, write D in float32: n / 6
     # flop/B).
     ns_arr = np.array([s.n for s in systems])
@@ -572,7 +572,7 @@ def run_batch(torch, nsr, reps_timed):
         "rel_resid_max_ok": float(rel[okm].max()),
         "rel_resid_p50": float(np.median(rel)),
         "ns_steps_p50": float(np.median(steps)), "ns_steps_max": int(steps.max()),
-        "timeline_ms": timeline_summary(tl, [s.n for s in systems], groups),
+        "timeline_ms": timeline_summary(tl, [s.n for s in systems]),
         "per_bucket": per_bucket,
     }
 
