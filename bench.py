@@ -2,24 +2,29 @@
 """Benchmark: coupled high-order Newton-Schulz / Richardson SPD solves on one MI355X.
 
 Headline: one "step" is one whole solve (richardson_ns_solve through the C ABI)
-of a seeded synthetic system already resident in HBM: N = 4096, kappa = 1e4,
-A = Q diag(lam) Q^T, order-8 factorized Newton-Schulz (I+F)(I+F^2)(I+F^4) in
-float64 until the ||F|| rounding floor, coupled Richardson updates and float64
-refinement to a relative residual of 1e-12.
+of a seeded synthetic system already resident in HBM: N = 8192, kappa = 1e6,
+A = Q diag(lam) Q^T, double Newton-Schulz of order 8 (Section 5.1, inner sums
+in squaring form) in the mixed mode -- bf16 powers and assembly with float32
+accumulation, float32 residual, G-side and merge products, float64 Richardson
+refinement to a relative residual of 1e-10.  The same solve in plain float64
+is timed beside it (its own warm-up and timed solves) and the ratio is
+reported.
 
-Also measured (extra keys of the same JSON line): the mixed-precision path
-(bf16 powers, float32 residual / G-side, float64 Richardson) on the same
-system; the N = 8192, kappa = 1e6 composite (double Newton-Schulz, order 8)
-workload in mixed precision next to the same solve in float64; a batch of
-2048 harmonic-regressor Gram systems of uneven size in one persistent launch;
-a serving run (Poisson arrivals, sizes 32..2048) with p50/p99 latency; the
-program library and the composite variants on the headline system; the
-N = 64 fixed-step workload (eager, captured graph, 4096-seed batch); and a
-three-frequency analogue of the paper's last comparison.
+Also measured (extra keys of the same JSON line): the N = 4096, kappa = 1e4
+order-8 factorized solve in float64 (with its float64 GEMM roofline), in the
+mixed mode and with split-fp16 float32-class products (a separate mode: 22
+significant bits in the residual and G-side operands); the factorized and
+split variants of the N = 8192 system; a batch of 2048 harmonic-regressor
+Gram systems of uneven size in one persistent launch; a serving run (Poisson
+arrivals, sizes 32..2048) with p50/p99 latency; the program library and the
+composite variants on the N = 4096 system; the N = 64 fixed-step workload
+(eager, captured graph, 4096-seed batch); and a three-frequency analogue of
+the paper's last comparison.
 
-The float64 GEMM's roofline comes from per-launch HIP events recorded by the
-library on its stream during the timed region; the CPU baseline is the oracle
-timed on a bounded sample.
+The roofline of the dominant kernel (the float32 GEMM of the headline solve)
+comes from per-launch HIP events recorded by the library on its own stream
+during the timed region; the CPU baseline is the oracle timed on a bounded
+sample of the same workload.
 """
 from __future__ import annotations
 
@@ -48,8 +53,15 @@ from paper_2008_11480_amd import inputs  # noqa: E402
 # fp16 MFMA products each, so their ceiling is a third of the 2.5 PFLOP/s
 # fp16 peak (frac_of_peak = fp16 matrix-core utilisation).
 PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3, "bf16": 2500.0, "f32_split": 2500.0 / 3}
-GEMM_KERNEL_SRC = os.path.join(ROOT, "paper_2008_11480_amd", "csrc", "nsr_gemm_f64.hip")
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "gemm_f64_spd4096_traffic.json")
+CSRC = os.path.join(ROOT, "paper_2008_11480_amd", "csrc")
+# rocprofv3 PMC summaries of HBM traffic per launch, keyed by the GEMM kind
+# they measure: (summary file, kernel source whose hash they were taken on)
+TRAFFIC = {
+    "f64": (os.path.join(ROOT, "profiles", "gemm_f64_spd4096_traffic.json"),
+            os.path.join(CSRC, "nsr_gemm_f64.hip")),
+    "f32": (os.path.join(ROOT, "profiles", "gemm_f32_spd8192_traffic.json"),
+            os.path.join(CSRC, "nsr_gemm_lowp.hip")),
+}
 KIND = {"f64": 1, "f32": 2, "bf16": 3, "f32_split": 4}
 
 
@@ -62,15 +74,16 @@ def kernel_hash(path):
         return hashlib.sha256(fh.read()).hexdigest()[:16]
 
 
-def traffic_per_launch():
+def traffic_per_launch(kind):
     """HBM bytes per GEMM launch from the committed rocprofv3 PMC summary,
     or None when the kernel source changed since the counters were taken."""
+    path, src = TRAFFIC[kind]
     try:
-        with open(TRAFFIC_FILE) as fh:
+        with open(path) as fh:
             t = json.load(fh)
     except (OSError, ValueError):
         return None
-    if t.get("kernel_sha256_16") != kernel_hash(GEMM_KERNEL_SRC):
+    if t.get("kernel_sha256_16") != kernel_hash(src):
         return None
     return t.get("bytes_per_launch")
 
@@ -114,6 +127,44 @@ def cpu_baseline(sysm, order, steps_per_solve, refine_steps):
                    f"Richardson update at N={a.shape[0]} took {t_step:.2f} s; scaled to the "
                    f"GPU solve's {steps_per_solve} steps + {refine_steps + 1} residual "
                    f"evaluations"),
+    }
+
+
+def cpu_baseline_composite(a, b, order, ns_steps, refine_steps):
+    """Oracle (numpy float64) on a bounded sample of the N = 8192 workload:
+    the double Newton-Schulz precalculation (L_0, Gamma_1) and one double
+    Newton-Schulz step with its Richardson update on the same system, scaled
+    to solves/s with the GPU solve's step counts (refinement steps priced as
+    Richardson updates)."""
+    import oracle
+    alpha = oracle.alpha_frobenius(a)
+    g0 = np.eye(a.shape[0]) / alpha
+    ctr = oracle.MMCounter()
+    t0 = time.perf_counter()
+    st = oracle.dns_init(a, g0, order, "squaring", ctr=ctr)
+    t_init = time.perf_counter() - t0
+    mmm_init = ctr.n
+    theta = g0 @ b
+    t0 = time.perf_counter()
+    st = oracle.dns_step(a, st, order, "squaring", ctr=ctr)
+    theta, _ = oracle.richardson_update(a, b, theta, st.G)
+    t_step = time.perf_counter() - t0
+    mmm_step = ctr.n - mmm_init
+    t0 = time.perf_counter()
+    theta, _ = oracle.richardson_update(a, b, theta, st.G)
+    t_ref = time.perf_counter() - t0
+    del st
+    t_solve = t_init + ns_steps * t_step + (refine_steps + 1) * t_ref
+    return {
+        "value": 1.0 / t_solve,
+        "unit": "solves/s",
+        "cores": blas_threads(),
+        "kind": "oracle",
+        "sample": (f"oracle double Newton-Schulz (order {order}) at N={a.shape[0]}: the "
+                   f"precalculation ({mmm_init} mmm, {t_init:.2f} s) and one step with its "
+                   f"Richardson update ({mmm_step} mmm, {t_step:.2f} s); scaled to the GPU "
+                   f"solve's {ns_steps} steps + {refine_steps + 1} residual evaluations "
+                   f"({t_ref * 1e3:.0f} ms each)"),
     }
 
 
@@ -182,27 +233,71 @@ def report_of(rep):
             "rel_resid_reported": rep.rel_resid}
 
 
-def run_composite(torch, nsr, steps, warmup):
-    """N = 8192, kappa = 1e6: composite (double Newton-Schulz) order 8 and the
-    factorized order 8, mixed precision, next to the composite in float64."""
+PEAK_NOTE = ("achieved = algorithmic flop (2 N^3 per product) / the average per-launch "
+             "HIP-event time recorded by the library on its stream over the timed solves")
+
+
+def roofline_of(g, kind, kernel, traffic):
+    return {
+        "bound": "mfma", "kernel": kernel, "achieved": g["tflops"],
+        "peak": PEAK_TFLOPS[kind], "unit": "TFLOP/s", "frac": g["tflops"] / PEAK_TFLOPS[kind],
+        "traffic": traffic, "launches": g["launches"], "avg_launch_ms": g["avg_launch_ms"],
+        "flop_per_launch": g["flop_per_launch"],
+        "share_of_solve_time": g["share_of_solve_time"],
+    }
+
+
+def run_headline_dns8(torch, nsr, steps, warmup):
+    """N = 8192, kappa = 1e6, double Newton-Schulz of order 8: the mixed
+    mode (bf16 powers, float32 residual / G-side / merge, float64
+    Richardson) and the same solve in float64, each with its own warm-up
+    and timed solves."""
     w = inputs.WORKLOADS["spd8192_k1e6_dns8"]
     n = w["n"]
-    log(f"generating spd8192_k1e6_dns8 on the GPU: N={n} kappa={w['kappa']:g}")
+    log(f"generating spd8192_k1e6_dns8 on the GPU: N={n} kappa={w['kappa']:g} seed={w['seed']}")
     A, b, lam, Q = inputs.spd_qlq_device(n, w["kappa"], w["seed"])
     theta_star = Q @ ((Q.T.contiguous() @ b) / lam)
+    del Q
+    kw = dict(order=8, form="composite_double", k_max=w["k_max"], resid_tol=w["resid_tol"],
+              refine_max=100)
+    legs = {}
+    for label, prec, st, wu in (("mixed", nsr.PREC_MIXED_BF16, steps, warmup),
+                                ("fp64", nsr.PREC_FP64, max(3, steps // 2), max(1, warmup))):
+        solver = nsr.Solver(n, precision=prec, composite=True)
+        solver.bind(A)
+        theta = torch.zeros_like(b)
+        m = measure(torch, solver, b, theta, kw, st, wu, f"dns8_{label}")
+        rel = float(torch.linalg.norm(b - A @ theta) / torch.linalg.norm(b))
+        fwd = float(torch.linalg.norm(theta - theta_star) / torch.linalg.norm(theta_star))
+        last = m["last"]
+        flop = last.gemm_flop + 4.0 * n * n * (last.ns_steps + last.refine_steps + 1)
+        legs[label] = {"m": m, "rel_resid": rel, "fwd_err_vs_closed_form": fwd,
+                       "alg_tflops_per_solve": flop / (m["ms_per_solve"] * 1e-3) / 1e12,
+                       "steps": st, "warmup": wu}
+        del solver
+        torch.cuda.empty_cache()
+    return w, A, b, legs
+
+
+def run_composite_variants(torch, nsr, steps, warmup):
+    """The N = 8192, kappa = 1e6 system with the factorized order-8 program
+    (mixed) and with split-fp16 float32-class products (a mode of its own)
+    for the composite and factorized programs."""
+    w = inputs.WORKLOADS["spd8192_k1e6_dns8"]
+    n = w["n"]
+    A, b, lam, Q = inputs.spd_qlq_device(n, w["kappa"], w["seed"])
+    theta_star = Q @ ((Q.T.contiguous() @ b) / lam)
+    del Q
     out = {"workload": "spd8192_k1e6_dns8", "n": n, "kappa": w["kappa"], "order": 8}
     theta = torch.zeros_like(b)
-    for label, prec, form in (("mixed_composite", nsr.PREC_MIXED_BF16, "composite_double"),
-                              ("mixed_factorized", nsr.PREC_MIXED_BF16, "squaring"),
+    for label, prec, form in (("mixed_factorized", nsr.PREC_MIXED_BF16, "squaring"),
                               ("mixed_split_composite", nsr.PREC_MIXED_SPLIT,
                                "composite_double"),
-                              ("mixed_split_factorized", nsr.PREC_MIXED_SPLIT, "squaring"),
-                              ("fp64_composite", nsr.PREC_FP64, "composite_double")):
+                              ("mixed_split_factorized", nsr.PREC_MIXED_SPLIT, "squaring")):
         solver = nsr.Solver(n, precision=prec, composite=form == "composite_double")
         solver.bind(A)
         kw = dict(order=8, form=form, k_max=64, resid_tol=1e-10, refine_max=100)
-        m = measure(torch, solver, b, theta, kw, steps if prec != nsr.PREC_FP64 else 1,
-                    1 if prec != nsr.PREC_FP64 else 0, label)
+        m = measure(torch, solver, b, theta, kw, steps, warmup, label)
         rel = float(torch.linalg.norm(b - A @ theta) / torch.linalg.norm(b))
         fwd = float(torch.linalg.norm(theta - theta_star) / torch.linalg.norm(theta_star))
         out[label] = {"solves_per_s": m["solves_per_s"], "ms_per_solve": m["ms_per_solve"],
@@ -210,9 +305,6 @@ def run_composite(torch, nsr, steps, warmup):
                       "gemm": m["gemm"], **report_of(m["last"])}
         del solver
         torch.cuda.empty_cache()
-    for label in ("mixed_composite", "mixed_split_composite"):
-        out[f"speedup_{label}_vs_fp64_composite"] = (
-            out[label]["solves_per_s"] / out["fp64_composite"]["solves_per_s"])
     return out
 
 
@@ -625,131 +717,57 @@ def run_serving(torch, nsr, duration_s=3.0, rate=2000.0):
     return st
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="spd4096_k1e4_o8",
-                    choices=["spd4096_k1e4_o8", "spd64_k1e2_o4"])
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-mixed", action="store_true",
-                    help="skip every leg after the float64 headline (mixed, composite, batch, "
-                         "serving)")
-    ap.add_argument("--no-mixed4096", action="store_true",
-                    help="skip the mixed-precision solve of the headline system")
-    ap.add_argument("--no-composite", action="store_true", help="skip the N=8192 legs")
-    ap.add_argument("--no-batch", action="store_true", help="skip the batched leg")
-    ap.add_argument("--no-serving", action="store_true", help="skip the serving leg")
-    ap.add_argument("--no-small", action="store_true",
-                    help="skip the N=64 fixed-step leg (eager versus captured graph)")
-    ap.add_argument("--no-comparisons", action="store_true",
-                    help="skip the Newton-Schulz variant comparison and the three-frequency "
-                         "analogue")
-    ap.add_argument("--no-programs", action="store_true",
-                    help="skip timing the other evaluation programs on the headline system")
-    ap.add_argument("--calibrate-copy-mib", type=int, default=0,
-                    help="also run a plain device copy of this many MiB (PMC calibration)")
-    args = ap.parse_args()
-
-    world = int(os.environ.get("WORLD_SIZE", "1"))
-    if args.gpus != 1 or world != 1:
-        print("bench.py measures one GPU: the solver runs on a single MI355X "
-              "(DESIGN.md describes how the path would shard); --gpus must be 1.",
-              file=sys.stderr)
-        sys.exit(2)
-
-    import torch
-    from paper_2008_11480_amd import autotune, nsr
-
-    assert torch.cuda.is_available(), "no GPU"
-    torch.cuda.set_device(0)
-    w = dict(inputs.WORKLOADS[args.workload])
+def run_spd4096(torch, nsr, args):
+    """N = 4096, kappa = 1e4, order-8 factorized Newton-Schulz in float64 to
+    the ||F|| rounding floor, then refinement to 1e-12: the float64 GEMM's
+    roofline, the program library, the composite variants and Section 2's
+    options on this system, and the same solve in the mixed and split-fp16
+    modes."""
+    from paper_2008_11480_amd import autotune
+    w = dict(inputs.WORKLOADS["spd4096_k1e4_o8"])
     n, kappa, order = w["n"], w["kappa"], w["order"]
-    log(f"generating {args.workload}: N={n} kappa={kappa:g} seed={w['seed']}")
+    log(f"generating spd4096_k1e4_o8: N={n} kappa={kappa:g} seed={w['seed']}")
     sysm = inputs.spd_qlq(n, kappa, w["seed"])
     A = torch.from_numpy(sysm.A).to("cuda")
     b = torch.from_numpy(sysm.b).to("cuda")
     theta = torch.zeros_like(b)
     solver = nsr.Solver(n, composite=False)
     solver.bind(A)
-    fixed = args.workload == "spd64_k1e2_o4"
-    kw = dict(order=order, form="squaring", k_max=w["k_max"], floor_detect=not fixed,
+    kw = dict(order=order, form="squaring", k_max=w["k_max"], floor_detect=True,
               resid_tol=w["resid_tol"])
-
-    if args.calibrate_copy_mib > 0:
-        nel = args.calibrate_copy_mib * (1 << 20) // 8
-        src = torch.ones(nel, dtype=torch.float64, device="cuda")
-        dst = torch.empty_like(src)
-        dst.copy_(src)
-        torch.cuda.synchronize()
-        log(f"calibration copy of {args.calibrate_copy_mib} MiB done")
-        del src, dst
-
-    m = measure(torch, solver, b, theta, kw, args.steps, args.warmup, "fp64")
+    m = measure(torch, solver, b, theta, kw, args.steps, args.warmup, "spd4096_fp64")
     last = m["last"]
     th = theta.cpu().numpy()
     theta_star = sysm.Q @ ((sysm.Q.T @ sysm.b) / sysm.lam)
     fwd = float(np.linalg.norm(th - theta_star) / np.linalg.norm(theta_star))
     rel = float(np.linalg.norm(sysm.b - sysm.A @ th) / np.linalg.norm(sysm.b))
-    g64 = m["gemm"]["f64"]
     flop_per_solve = last.gemm_flop + 4.0 * n * n * (last.ns_steps + last.refine_steps + 1)
-    traffic = traffic_per_launch()
-
     out = {
-        "metric": "solves/s at rel. residual <= 1e-10 (plain FP64 path; mixed in 'mixed')",
-        "value": m["solves_per_s"],
-        "unit": "solves/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": m["ms_per_solve"],
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f64",
-        "data": "synthetic",
-        "config": {
-            "workload": args.workload, "n": n, "kappa": kappa, "order": order,
-            "form": "squaring (I+F)(I+F^2)(I+F^4)", "precision": "fp64",
-            "stop": "||F||_F floor, then Richardson to rel. residual "
-                    f"{w['resid_tol']:g}", "seed": w["seed"],
-        },
-        "roofline": {
-            "bound": "mfma",
-            "kernel": ("gemm_f64_kernel (128x128 tiles; symmetric-output power products "
-                       "cut their last, partial round of tiles along K and finish it "
-                       "with gemm_f64_split_fixup)"),
-            "achieved": g64["tflops"],
-            "peak": PEAK_TFLOPS["f64"],
-            "unit": "TFLOP/s",
-            "frac": g64["tflops"] / PEAK_TFLOPS["f64"],
-            "traffic": traffic,
-            "launches": g64["launches"],
-            "avg_launch_ms": g64["avg_launch_ms"],
-            "flop_per_launch": g64["flop_per_launch"],
-            "note": ("float64 GEMM family: the residual and G-side products run full "
-                     "(2 n^3 flop), the power products with a symmetric output "
-                     "(n^2 (n+1) flop); achieved = algorithmic flop / event time, "
-                     "averaged over all products of a solve; a 'launch' is one product "
-                     "(the main kernel plus, for a split product, its fixup kernel)"),
-        },
+        "workload": "spd4096_k1e4_o8", "n": n, "kappa": kappa, "order": order,
+        "form": "squaring (I+F)(I+F^2)(I+F^4)", "precision": "fp64",
+        "stop": f"||F||_F floor, then Richardson to rel. residual {w['resid_tol']:g}",
+        "solves_per_s": m["solves_per_s"], "ms_per_solve": m["ms_per_solve"],
+        "roofline": roofline_of(m["gemm"]["f64"], "f64", (
+            "gemm_f64_kernel (128x128 tiles; symmetric-output power products cut their "
+            "last, partial round of tiles along K and finish it with "
+            "gemm_f64_split_fixup)"), traffic_per_launch("f64")),
         "solve": {
             **report_of(last), "rel_resid": rel, "fwd_err_vs_closed_form": fwd,
             "alg_tflops_per_solve": flop_per_solve / (m["ms_per_solve"] * 1e-3) / 1e12,
             "latency_ms_p50": m["latency_ms_p50"], "latency_ms_p99": m["latency_ms_p99"],
             "fnorm_hist": last.fnorm_hist,
         },
+        "_m": m, "_sysm": sysm,
     }
-    if not args.no_programs and not fixed:
+    if not args.no_programs:
         # The same system with every candidate program (Tables 1-3, eqs.
-        # ex1-ex3, ztab2), fastest first; the headline stays order-8 squaring.
+        # ex1-ex3, ztab2), fastest first.
         trials = autotune.time_programs(solver, b, theta, autotune.CANDIDATES, reps=1,
                                         resid_tol=w["resid_tol"], k_max=w["k_max"])
         mu = 1.0 - sysm.lam / last.alpha
         floor = min(last.fnorm_hist)
         out["programs"] = {
-            "workload": args.workload, "precision": "fp64",
+            "precision": "fp64",
             "trials": [{"program": t.program.name, "ms_per_solve": t.ms,
                         "solves_per_s": 1e3 / t.ms, "ns_steps": t.ns_steps,
                         "refine_steps": t.refine_steps, "mmm": t.mmm,
@@ -764,99 +782,203 @@ def main():
                 f"rel_resid={t.rel_resid:.2e}")
     del solver
     torch.cuda.empty_cache()
-    if not args.no_small and not fixed:
-        out["small_fixed"] = run_small_fixed(torch, nsr)
-    if not args.no_comparisons and not fixed:
-        out["comparisons"] = {"workload": args.workload, "precision": "fp64",
+    if not args.no_comparisons:
+        out["comparisons"] = {"precision": "fp64",
                               "variants": run_comparisons(torch, nsr, A, b, sysm, n,
                                                           w["resid_tol"], w["k_max"])}
-        out["fig4_analogue"] = run_fig4_analogue(torch, nsr)
-        out["preconditioning"] = run_preconditioning(torch, nsr, A, b, sysm, n, w["resid_tol"],
-                                                     w["k_max"])
+        out["preconditioning"] = run_preconditioning(torch, nsr, A, b, sysm, n,
+                                                     w["resid_tol"], w["k_max"])
         torch.cuda.empty_cache()
-
-    if not args.no_mixed and not args.no_mixed4096 and not fixed:
-        # Same N=4096 system, mixed precision, to the same 1e-12 residual.
-        ms = nsr.Solver(n, precision=nsr.PREC_MIXED_BF16, composite=False)
-        ms.bind(A)
-        thm = torch.zeros_like(b)
+    if not args.no_mixed4096:
         kwm = dict(kw, refine_max=100)
-        mm = measure(torch, ms, b, thm, kwm, args.steps, args.warmup, "mixed")
-        thc = thm.cpu().numpy()
-        out["mixed"] = {
-            "workload": args.workload, "precision": "mixed (bf16 powers, fp32 residual and "
-                                                  "G-side, fp64 Richardson)",
-            "solves_per_s": mm["solves_per_s"], "ms_per_solve": mm["ms_per_solve"],
-            "speedup_vs_fp64": mm["solves_per_s"] / m["solves_per_s"],
-            "rel_resid": float(np.linalg.norm(sysm.b - sysm.A @ thc) / np.linalg.norm(sysm.b)),
-            "fwd_err_vs_closed_form": float(np.linalg.norm(thc - theta_star)
-                                            / np.linalg.norm(theta_star)),
-            "latency_ms_p50": mm["latency_ms_p50"], "latency_ms_p99": mm["latency_ms_p99"],
-            "gemm": mm["gemm"], **report_of(mm["last"]),
-        }
-        del ms
-        torch.cuda.empty_cache()
-        # The same with float32-class products from split half-precision
-        # operands (residual and G-side) instead of float32 MFMA.
-        ss = nsr.Solver(n, precision=nsr.PREC_MIXED_SPLIT, composite=False)
-        ss.bind(A)
-        ths = torch.zeros_like(b)
-        msp = measure(torch, ss, b, ths, kwm, args.steps, args.warmup, "mixed_split")
-        # Program choice in this precision (the autotuner's trial): every
-        # candidate program on the same system, fastest first.
-        sp_trials = autotune.time_programs(ss, b, torch.zeros_like(b), reps=2,
-                                           resid_tol=w["resid_tol"], k_max=w["k_max"],
-                                           refine_max=100)
-        thc = ths.cpu().numpy()
-        out["mixed_split"] = {
-            "workload": args.workload, "precision": "mixed (bf16 powers, residual and G-side "
-                                                  "from split fp16 operands, fp64 Richardson)",
-            "solves_per_s": msp["solves_per_s"], "ms_per_solve": msp["ms_per_solve"],
-            "speedup_vs_fp64": msp["solves_per_s"] / m["solves_per_s"],
-            "rel_resid": float(np.linalg.norm(sysm.b - sysm.A @ thc) / np.linalg.norm(sysm.b)),
-            "fwd_err_vs_closed_form": float(np.linalg.norm(thc - theta_star)
-                                            / np.linalg.norm(theta_star)),
-            "latency_ms_p50": msp["latency_ms_p50"], "latency_ms_p99": msp["latency_ms_p99"],
-            "gemm": msp["gemm"], **report_of(msp["last"]),
-            "programs": [{"program": t.program.name, "ms_per_solve": t.ms,
-                          "solves_per_s": 1e3 / t.ms, "ns_steps": t.ns_steps,
-                          "refine_steps": t.refine_steps, "mmm": t.mmm, "ok": t.ok}
-                         for t in sp_trials],
-            "chosen": sp_trials[0].program.name,
-        }
-        # best program per precision against each other (the float64 one from
-        # the programs leg, when it ran)
-        if "programs" in out and sp_trials[0].ok:
-            fb = out["programs"]["trials"][0]
-            out["mixed_split"]["best_vs_fp64_best"] = {
-                "fp64": {"program": fb["program"], "solves_per_s": fb["solves_per_s"]},
-                "mixed_split": {"program": sp_trials[0].program.name,
-                                "solves_per_s": 1e3 / sp_trials[0].ms},
-                "speedup": (1e3 / sp_trials[0].ms) / fb["solves_per_s"]}
-        del ss
-        torch.cuda.empty_cache()
-    if not args.no_mixed and not fixed:
-        # Each leg starts from an empty allocator cache: the serving loop's
-        # latencies should not depend on what earlier legs left allocated.
+        for label, prec, desc in (
+                ("mixed", nsr.PREC_MIXED_BF16,
+                 "mixed (bf16 powers, fp32 residual and G-side, fp64 Richardson)"),
+                ("mixed_split", nsr.PREC_MIXED_SPLIT,
+                 "split-fp16 mode (bf16 powers; residual and G-side from split fp16 "
+                 "operands, 22 significant bits; fp64 Richardson)")):
+            ms = nsr.Solver(n, precision=prec, composite=False)
+            ms.bind(A)
+            thm = torch.zeros_like(b)
+            mm = measure(torch, ms, b, thm, kwm, args.steps, args.warmup, label)
+            thc = thm.cpu().numpy()
+            leg = {
+                "precision": desc,
+                "solves_per_s": mm["solves_per_s"], "ms_per_solve": mm["ms_per_solve"],
+                "speedup_vs_fp64": mm["solves_per_s"] / m["solves_per_s"],
+                "rel_resid": float(np.linalg.norm(sysm.b - sysm.A @ thc)
+                                   / np.linalg.norm(sysm.b)),
+                "fwd_err_vs_closed_form": float(np.linalg.norm(thc - theta_star)
+                                                / np.linalg.norm(theta_star)),
+                "latency_ms_p50": mm["latency_ms_p50"], "latency_ms_p99": mm["latency_ms_p99"],
+                "gemm": mm["gemm"], **report_of(mm["last"]),
+            }
+            if label == "mixed_split" and not args.no_programs:
+                sp_trials = autotune.time_programs(ms, b, torch.zeros_like(b), reps=2,
+                                                   resid_tol=w["resid_tol"], k_max=w["k_max"],
+                                                   refine_max=100)
+                leg["programs"] = [{"program": t.program.name, "ms_per_solve": t.ms,
+                                    "solves_per_s": 1e3 / t.ms, "ns_steps": t.ns_steps,
+                                    "refine_steps": t.refine_steps, "mmm": t.mmm, "ok": t.ok}
+                                   for t in sp_trials]
+                leg["chosen"] = sp_trials[0].program.name
+            out[label] = leg
+            del ms
+            torch.cuda.empty_cache()
+    return out
+
+
+def headline_line(args, metric, value, w, config, dtype, roofline, ms_per_step):
+    return {
+        "metric": metric, "value": value, "unit": "solves/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": dtype,
+        "data": "synthetic", "config": config, "roofline": roofline,
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="spd8192_k1e6_dns8",
+                    choices=["spd8192_k1e6_dns8", "spd4096_k1e4_o8", "spd64_k1e2_o4"],
+                    help="headline workload (default: the N=8192 mixed-vs-float64 pair)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="only the headline workload (no other legs)")
+    ap.add_argument("--no-spd4096", action="store_true", help="skip the N=4096 legs")
+    ap.add_argument("--no-mixed4096", action="store_true",
+                    help="skip the mixed and split solves of the N=4096 system")
+    ap.add_argument("--no-composite", action="store_true",
+                    help="skip the factorized / split variants of the N=8192 system")
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched leg")
+    ap.add_argument("--no-serving", action="store_true", help="skip the serving leg")
+    ap.add_argument("--serving-seconds", type=float, default=3.0,
+                    help="length of the serving trace (Poisson arrivals at 2000 req/s)")
+    ap.add_argument("--no-small", action="store_true",
+                    help="skip the N=64 fixed-step leg (eager versus captured graph)")
+    ap.add_argument("--no-comparisons", action="store_true",
+                    help="skip the Newton-Schulz variant comparison and the three-frequency "
+                         "analogue")
+    ap.add_argument("--no-programs", action="store_true",
+                    help="skip timing the other evaluation programs on the N=4096 system")
+    ap.add_argument("--calibrate-copy-mib", type=int, default=0,
+                    help="also run a plain device copy of this many MiB (PMC calibration)")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU: the solver runs on a single MI355X "
+              "(DESIGN.md describes how the path would shard); --gpus must be 1.",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2008_11480_amd import nsr
+
+    assert torch.cuda.is_available(), "no GPU"
+    torch.cuda.set_device(0)
+
+    if args.calibrate_copy_mib > 0:
+        nel = args.calibrate_copy_mib * (1 << 20) // 8
+        src = torch.ones(nel, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"calibration copy of {args.calibrate_copy_mib} MiB done")
+        del src, dst
+
+    extras = not args.no_extras
+    cpu_sample = None
+    if args.workload == "spd8192_k1e6_dns8":
+        w, A8, b8, legs = run_headline_dns8(torch, nsr, args.steps, args.warmup)
+        mx, f64 = legs["mixed"], legs["fp64"]
+        lm, lf = mx["m"]["last"], f64["m"]["last"]
+        out = headline_line(
+            args, "solves/s at rel. residual <= 1e-10, mixed (bf16 powers, fp32 residual / "
+                  "G-side / merge, fp64 refinement) vs plain fp64; N=8192 double "
+                  "Newton-Schulz order 8",
+            mx["m"]["solves_per_s"], w,
+            {"workload": "spd8192_k1e6_dns8", "n": w["n"], "kappa": w["kappa"],
+             "order": 8, "form": "double Newton-Schulz (Section 5.1), inner sums "
+                                 "(I+F)(I+F^2)(I+F^4)",
+             "precision": "mixed_bf16", "stop": "||F||_F floor, then Richardson to rel. "
+                                               "residual 1e-10", "seed": w["seed"]},
+            "bf16/fp32 (fp64 refinement)",
+            roofline_of(mx["m"]["gemm"]["f32"], "f32",
+                        "gemm_f32_nn_kernel<128,128,32> (float32 MFMA 16x16x4: residual, "
+                        "G-side and merge products)", traffic_per_launch("f32")),
+            mx["m"]["ms_per_solve"])
+        out["roofline"]["note"] = PEAK_NOTE
+        out["fp64"] = {
+            "solves_per_s": f64["m"]["solves_per_s"], "ms_per_solve": f64["m"]["ms_per_solve"],
+            "steps": f64["steps"], "warmup": f64["warmup"],
+            "rel_resid": f64["rel_resid"], "fwd_err_vs_closed_form": f64["fwd_err_vs_closed_form"],
+            "alg_tflops_per_solve": f64["alg_tflops_per_solve"], "gemm": f64["m"]["gemm"],
+            **report_of(lf)}
+        out["speedup_mixed_vs_fp64"] = mx["m"]["solves_per_s"] / f64["m"]["solves_per_s"]
+        out["solve"] = {**report_of(lm), "rel_resid": mx["rel_resid"],
+                        "fwd_err_vs_closed_form": mx["fwd_err_vs_closed_form"],
+                        "alg_tflops_per_solve": mx["alg_tflops_per_solve"],
+                        "latency_ms_p50": mx["m"]["latency_ms_p50"],
+                        "latency_ms_p99": mx["m"]["latency_ms_p99"],
+                        "fnorm_hist": lm.fnorm_hist, "gemm": mx["m"]["gemm"]}
+        log(f"headline: mixed {mx['m']['solves_per_s']:.3f} solves/s, fp64 "
+            f"{f64['m']['solves_per_s']:.3f} solves/s, speedup {out['speedup_mixed_vs_fp64']:.2f}")
+        if not args.no_cpu_baseline:
+            cpu_sample = (A8.cpu().numpy(), b8.cpu().numpy(), lm.ns_steps, lm.refine_steps)
+        del A8, b8, legs
+        release(torch)
+        if extras and not args.no_spd4096:
+            s4 = run_spd4096(torch, nsr, args)
+            s4.pop("_m"), s4.pop("_sysm")
+            out["spd4096_k1e4_o8"] = s4
+            release(torch)
+    elif args.workload == "spd4096_k1e4_o8":
+        s4 = run_spd4096(torch, nsr, args)
+        m, sysm = s4.pop("_m"), s4.pop("_sysm")
+        w = inputs.WORKLOADS["spd4096_k1e4_o8"]
+        out = headline_line(
+            args, "solves/s at rel. residual <= 1e-12, plain fp64; N=4096 order-8 "
+                  "factorized Newton-Schulz", m["solves_per_s"], w,
+            {"workload": "spd4096_k1e4_o8", "n": w["n"], "kappa": w["kappa"], "order": 8,
+             "form": s4["form"], "precision": "fp64", "stop": s4["stop"], "seed": w["seed"]},
+            "f64", s4.pop("roofline"), m["ms_per_solve"])
+        out["spd4096_k1e4_o8"] = s4
+        if not args.no_cpu_baseline:
+            last = m["last"]
+            out["cpu_baseline"] = cpu_baseline(sysm, 8, last.ns_steps, last.refine_steps)
+            out["cpu_cholesky"] = cpu_cholesky(sysm)
+        extras = False
+        release(torch)
+    else:
+        out = {"small_fixed": run_small_fixed(torch, nsr)}
+        print(json.dumps(out), flush=True)
+        return
+
+    if extras:
+        if not args.no_small:
+            out["small_fixed"] = run_small_fixed(torch, nsr)
+        if not args.no_comparisons:
+            out["fig4_analogue"] = run_fig4_analogue(torch, nsr)
+        release(torch)
         if not args.no_composite:
-            out["composite"] = run_composite(torch, nsr, max(2, args.steps // 2), 1)
+            out["composite_variants"] = run_composite_variants(torch, nsr,
+                                                               max(2, args.steps // 2), 1)
             release(torch)
         if not args.no_batch:
             out["batch"] = run_batch(torch, nsr, 3)
             release(torch)
         if not args.no_serving:
-            out["serving"] = run_serving(torch, nsr)
+            out["serving"] = run_serving(torch, nsr, duration_s=args.serving_seconds)
 
-    if not args.no_cpu_baseline and not fixed:
-        log("timing the CPU oracle on a bounded sample")
-        out["cpu_baseline"] = cpu_baseline(sysm, order, last.ns_steps, last.refine_steps)
-        out["cpu_cholesky"] = cpu_cholesky(sysm)
-        # the same oracle sample on one BLAS thread
-        import threadpoolctl
-        with threadpoolctl.threadpool_limits(limits=1, user_api="blas"):
-            one = cpu_baseline(sysm, order, last.ns_steps, last.refine_steps)
-        out["cpu_baseline_1core"] = {"value": one["value"], "unit": one["unit"],
-                                     "cores": one["cores"], "kind": "oracle"}
+    if cpu_sample is not None:
+        log("timing the CPU oracle on a bounded sample of the N=8192 workload")
+        a_h, b_h, ns_steps, refine_steps = cpu_sample
+        out["cpu_baseline"] = cpu_baseline_composite(a_h, b_h, 8, ns_steps, refine_steps)
+        del cpu_sample, a_h, b_h
     print(json.dumps(out), flush=True)
 
 

@@ -108,8 +108,16 @@ typedef enum {
 typedef enum {
   NS_STOP_NONE = 0,
   NS_STOP_F_TOL = 1,        /* ||F_k||_F <= f_tol                              */
-  NS_STOP_FLOOR = 2,        /* rounding floor: an earlier ||F|| ratio was < 1/2
-                               and the current one is > 1/2                    */
+  NS_STOP_FLOOR = 2,        /* rounding floor, found by either of two tests.
+                               Error law: ||F_{k-1}|| < 1 and ||F_k|| >
+                               1e3 ||F_{k-1}||^n (eq. fk1 bounds ||F_k|| by
+                               ||F_{k-1}||^n in exact arithmetic; the double
+                               Newton-Schulz exponent grows at least n-fold
+                               per step).  Ratio: ||F_k|| > ||F_{k-1}|| / 2
+                               while ||F_k^2|| <= ||F_k|| / 4, which exact
+                               iterates cannot show (F_k = F_{k-1}^n).  Not
+                               used by the general composite and [sri] forms
+                               (ratio test only)                              */
   NS_STOP_K_MAX = 3,
   NS_STOP_DIVERGED = 4,     /* ||F_k|| > ||F_0|| or non-finite                 */
   NS_STOP_RESID_TOL = 5,    /* ||b - A theta|| / ||b|| <= resid_tol            */

@@ -25,6 +25,8 @@
 //    XCDs, so each XCD is given a contiguous run of a grouped (8 tile-rows)
 //    order, keeping the X row panels and Y column panels it reuses in its own
 //    L2.
+#include <atomic>
+
 #include "nsr_internal.h"
 
 // Tuning knobs of the large-tile configuration (chosen by measurement):
@@ -608,16 +610,20 @@ Plan plan_f64(int64_t m, int64_t n, int64_t k, bool sym, int64_t sk_cap) {
 }  // namespace
 
 int device_cus() {
-  static int cus = 0;
-  if (cus == 0) {
+  // Read and written by any host thread that plans a launch: atomic, and
+  // every writer stores the same value.
+  static std::atomic<int> cus{0};
+  int c = cus.load(std::memory_order_relaxed);
+  if (c == 0) {
     int dev = 0, v = 0;
     if (hipGetDevice(&dev) == hipSuccess &&
         hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && v > 0)
-      cus = v;
+      c = v;
     else
-      cus = 256;
+      c = 256;
+    cus.store(c, std::memory_order_relaxed);
   }
-  return cus;
+  return c;
 }
 
 int64_t gemm_f64_partials(int64_t m, int64_t n, bool sym) {

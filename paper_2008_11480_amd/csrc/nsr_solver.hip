@@ -1602,11 +1602,11 @@ size_t ns_gemm_f32_split_scratch_bytes(int64_t m, int64_t n, int64_t k) {
   return split_scratch_bytes(m, n, k);
 }
 
-int ns_gemm_f32_split(void* hip_stream, int64_t m, int64_t n, int64_t k, const float* X,
-                      int64_t ldx, const float* Y, int64_t ldy, float* D, int64_t ldd,
-                      uint16_t* Db, int64_t lddb, const float* E1, int64_t lde1, const float* E2,
-                      int64_t lde2, float diag, float scale, double* sumsq_out, void* scratch,
-                      size_t scratch_bytes) {
+// Argument checks shared by the split product's entry points.
+static int split_args_ok(int64_t m, int64_t n, int64_t k, const float* X, int64_t ldx,
+                         const float* Y, int64_t ldy, const float* D, int64_t ldd,
+                         const uint16_t* Db, int64_t lddb, const float* E1, int64_t lde1,
+                         const float* E2, int64_t lde2) {
   if (m < 0 || n < 0 || k < 0) return fail(NS_EINVAL, "negative size");
   if (m == 0 || n == 0) return NS_OK;
   if ((!D && !Db) || (k > 0 && (!X || !Y))) return fail(NS_EINVAL, "null operand");
@@ -1616,12 +1616,17 @@ int ns_gemm_f32_split(void* hip_stream, int64_t m, int64_t n, int64_t k, const f
   if ((D && ((const void*)D == X || (const void*)D == Y)) ||
       (Db && ((const void*)Db == X || (const void*)Db == Y)))
     return fail(NS_EINVAL, "outputs must not alias X or Y");
-  if (!scratch || scratch_bytes < split_scratch_bytes(m, n, k))
-    return fail(NS_ENOMEM, "scratch too small: %zu bytes needed", split_scratch_bytes(m, n, k));
-  if ((reinterpret_cast<uintptr_t>(scratch) & (kAlign - 1)) != 0)
-    return fail(NS_EINVAL, "scratch must be %zu-byte aligned", (size_t)kAlign);
-  hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
-  SplitPlanes sp = carve_split(static_cast<char*>(scratch), m, n, k);
+  return NS_OK;
+}
+
+// The split product itself: operand splits into the planes of `sp`, the
+// GEMM, and (sumsq_out non-NULL) the fixed-order reduction of the per-tile
+// partial sums held at `part`.
+static int split_gemm_run(hipStream_t st, int64_t m, int64_t n, int64_t k, const float* X,
+                          int64_t ldx, const float* Y, int64_t ldy, float* D, int64_t ldd,
+                          uint16_t* Db, int64_t lddb, const float* E1, int64_t lde1,
+                          const float* E2, int64_t lde2, float diag, float scale,
+                          const SplitPlanes& sp, double* part, double* sumsq_out) {
   GemmLpArgs a{};
   if (k > 0) {
     split_operand(X, ldx, m, k, false, sp.xh, sp.xl, sp.ldk, sp.part, sp.exps, st);
@@ -1648,13 +1653,29 @@ int ns_gemm_f32_split(void* hip_stream, int64_t m, int64_t n, int64_t k, const f
   a.K = k;
   a.diag = diag;
   a.scale = scale;
-  double* part = sumsq_out ? sumsq_out + 1 : nullptr;
-  a.partial = part;
+  a.partial = sumsq_out ? part : nullptr;
   const int64_t np = launch_gemm_f16s_nt(a, st);
   if (np < 0) return fail(NS_EHIP, "GEMM launch failed: %s", hipGetErrorString(hipGetLastError()));
   if (sumsq_out) launch_reduce(part, np, sumsq_out, 0, 0.0, st);
   if (hipGetLastError() != hipSuccess) return fail(NS_EHIP, "kernel launch failed");
   return NS_OK;
+}
+
+int ns_gemm_f32_split(void* hip_stream, int64_t m, int64_t n, int64_t k, const float* X,
+                      int64_t ldx, const float* Y, int64_t ldy, float* D, int64_t ldd,
+                      uint16_t* Db, int64_t lddb, const float* E1, int64_t lde1, const float* E2,
+                      int64_t lde2, float diag, float scale, double* sumsq_out, void* scratch,
+                      size_t scratch_bytes) {
+  const int rc = split_args_ok(m, n, k, X, ldx, Y, ldy, D, ldd, Db, lddb, E1, lde1, E2, lde2);
+  if (rc != NS_OK || m == 0 || n == 0) return rc;
+  if (!scratch || scratch_bytes < split_scratch_bytes(m, n, k))
+    return fail(NS_ENOMEM, "scratch too small: %zu bytes needed", split_scratch_bytes(m, n, k));
+  if ((reinterpret_cast<uintptr_t>(scratch) & (kAlign - 1)) != 0)
+    return fail(NS_EINVAL, "scratch must be %zu-byte aligned", (size_t)kAlign);
+  const SplitPlanes sp = carve_split(static_cast<char*>(scratch), m, n, k);
+  return split_gemm_run(reinterpret_cast<hipStream_t>(hip_stream), m, n, k, X, ldx, Y, ldy, D,
+                        ldd, Db, lddb, E1, lde1, E2, lde2, diag, scale, sp,
+                        sumsq_out ? sumsq_out + 1 : nullptr, sumsq_out);
 }
 
 // The symmetric-output bf16 kernel faulted the GPU on its first test and the

@@ -506,6 +506,48 @@ def test_split_composite_full_size_spd8192(torch):
     assert fwd <= 1.01 * w["kappa"] * rel + 50 * w["kappa"] * U64, (fwd, rel)
 
 
+def double_ns_exponent(n, k):
+    """Exponent of F_0 in the double Newton-Schulz residual after k steps,
+    eq. (ermoex1) with h = 1: k n^(k+1) + n^k."""
+    return k * n ** (k + 1) + n ** k
+
+
+def test_mixed_bf16_composite_full_size_spd8192(torch):
+    """N = 8192, kappa = 1e6, double Newton-Schulz of order 8 (Section 5.1) in
+    the mixed mode the benchmark's headline times (bf16 powers and assembly,
+    float32 residual, G-side and merge, float64 Richardson), with the same
+    solver set-up: relative residual <= 1e-10 after refinement, the forward
+    error against theta* = Q diag(1/lam) Q^T b within kappa times the
+    attained residual, and the ||F_k|| trace on the eigen closed form of
+    eq. (ermoex1), ||F_k||_F = sqrt(sum mu_i^(2 e_k)), e_k = k n^(k+1) + n^k,
+    while the iteration is above its float32 floor."""
+    w = inputs.WORKLOADS["spd8192_k1e6_dns8"]
+    A, b, lam, Q = inputs.spd_qlq_device(w["n"], w["kappa"], w["seed"])
+    s = nsr.Solver(w["n"], precision=nsr.PREC_MIXED_BF16, composite=True)
+    s.bind(A)
+    th = torch.zeros_like(b)
+    rep = s.solve(b, th, order=8, form="composite_double", k_max=64, resid_tol=1e-10,
+                  refine_max=100)
+    torch.cuda.synchronize()
+    assert rep.precision == nsr.PREC_MIXED_BF16
+    assert rep.status == nsr.NS_OK and rep.rel_resid <= 1e-10, (rep.refine_stop, rep.rel_resid)
+    rel = float(torch.linalg.norm(b - A @ th) / torch.linalg.norm(b))
+    theta_star = Q @ ((Q.T.contiguous() @ b) / lam)
+    fwd = float(torch.linalg.norm(th - theta_star) / torch.linalg.norm(theta_star))
+    assert rel <= 2e-10
+    assert fwd <= 1.01 * w["kappa"] * rel + 50 * w["kappa"] * U64, (fwd, rel)
+    mu = 1.0 - lam.cpu().numpy() / rep.alpha
+    floor = min(rep.fnorm_hist)
+    checked = 0
+    for k, fk in enumerate(rep.fnorm_hist):
+        ref = float(np.sqrt(np.sum(mu ** (2.0 * double_ns_exponent(8, k)))))
+        print(f"k={k} gpu={fk:.6e} closed_form={ref:.6e} rel={abs(fk - ref) / ref:.2e}")
+        if ref > 10 * floor:
+            assert abs(fk - ref) <= 3e-2 * ref, (k, fk, ref)
+            checked += 1
+    assert checked >= 3, (checked, rep.fnorm_hist)
+
+
 def test_mixed_accelerated_composite(torch):
     """Mixed precision with the accelerator of eq. (ttk1): reaches 1e-10 and
     agrees with the float64 oracle to the refinement's accuracy."""

@@ -266,6 +266,34 @@ def test_solve_matches_oracle(torch, n, kappa, order, form, p, w, symmetric):
     assert np.linalg.norm(th - orc.theta) <= 10 * kappa * U * np.linalg.norm(orc.theta) + 1e-300
 
 
+def test_fp64_composite_full_size_spd4096(torch):
+    """Float64 double Newton-Schulz of order 8 (Section 5.1) at N = 4096, the
+    size at which every product runs 128 x 128 tiles and the symmetric power
+    products cut their partial last round of tiles along K: the ||F_k||
+    trace, the stop step and theta against the oracle's double Newton-Schulz
+    on the same system, and the trace on the closed form of eq. (ermoex1)
+    while above the floor."""
+    w = inputs.WORKLOADS["spd4096_k1e4_o8"]
+    sysm = inputs.spd_qlq(w["n"], w["kappa"], w["seed"])
+    th, rep = gpu_solve(torch, sysm, order=8, form="composite_double", k_max=64,
+                        resid_tol=w["resid_tol"], refine_max=64)
+    orc = oracle.solve(sysm.A, sysm.b, oracle.SolveOptions(order=8, composite=True,
+                                                           resid_tol=w["resid_tol"]))
+    print("gpu", rep.ns_steps, rep.fnorm_hist)
+    print("orc", orc.ns_steps, orc.fnorm_hist)
+    assert abs(rep.ns_steps - orc.ns_steps) <= 1, (rep.ns_steps, orc.ns_steps)
+    compare_traces(rep.fnorm_hist, orc.fnorm_hist, rel=1e-9)
+    assert rep.rel_resid <= max(w["resid_tol"], 2 * orc.rel_resid)
+    kappa = w["kappa"]
+    assert np.linalg.norm(th - orc.theta) <= 10 * kappa * U * np.linalg.norm(orc.theta)
+    mu = 1.0 - sysm.lam / rep.alpha
+    for k, fk in enumerate(rep.fnorm_hist):
+        e_k = k * 8 ** (k + 1) + 8 ** k
+        ref = math.sqrt(float(np.sum(mu ** (2.0 * e_k))))
+        if ref > 1e3 * min(rep.fnorm_hist):
+            assert fk == pytest.approx(ref, rel=1e-6), (k, fk, ref)
+
+
 def test_step_level_G_matches_oracle(torch):
     """ns_step / ns_get_G / ns_get_F element-wise against the oracle's G_k, F_k."""
     n = 257

@@ -298,6 +298,35 @@ def test_stop_rule():
         chk([1.0, 0.9], 0.0, 1, 64)
 
 
+@pytest.mark.parametrize("c3,stalls", [(0.614, True), (0.52, True), (0.48, False),
+                                       (0.343, False)])
+def test_refinement_stall_rule_closed_form(c3, stalls):
+    """The refinement phase's stall stop on an input whose residual history is
+    known in closed form.  A = diag(1, x), b = e_2, order 2, one fixed
+    Newton-Schulz step.  With mu = 1 - x/alpha, theta_0 = b/alpha leaves
+    r_0 = mu e_2; the coupled update with G_1 leaves r_1 = F_1 r_0 =
+    mu^3 e_2 (eq. fk1: F_1 = F_0^2), and every refinement step multiplies
+    the residual by c = mu^2.  So the recorded history is mu, mu^3, mu^5, ...,
+    and progress over three steps is c^3: the stall stop (less than a factor
+    2 over 3 steps) fires at exactly the third refinement step when
+    c^3 > 1/2, and never otherwise (then the step budget ends the run)."""
+    c = c3 ** (1.0 / 3.0)
+    mu = math.sqrt(c)
+    d = 1.0 - mu                          # x / alpha with alpha = sqrt(1 + x^2)
+    x = d / math.sqrt(1.0 - d * d)
+    a = np.diag([1.0, x])
+    b = np.array([0.0, 1.0])
+    rep = oracle.solve(a, b, oracle.SolveOptions(order=2, k_max=1, floor_detect=False,
+                                                 resid_tol=0.0, refine_max=12))
+    assert rep.alpha == pytest.approx(math.sqrt(1.0 + x * x), rel=1e-15)
+    want = [mu ** (2 * j + 1) for j in range(len(rep.resid_hist))]
+    np.testing.assert_allclose(rep.resid_hist, want, rtol=1e-12)
+    if stalls:
+        assert rep.refine_stop == "refine_stall" and rep.refine_steps == 3
+    else:
+        assert rep.refine_stop == "refine_max" and rep.refine_steps == 12
+
+
 def test_error_law_floor_rule():
     """The error-law floor test (eq. fk1: ||F_k|| <= ||F_{k-1}||^n exactly):
     fires on a norm far above ||F_{k-1}||^n, never while ||F_{k-1}|| >= 1,
