@@ -484,6 +484,30 @@ int ns_gemm_f32_split(void* hip_stream, int64_t m, int64_t n, int64_t k,
                       float diag, float scale, double* sumsq_out,
                       void* scratch, size_t scratch_bytes);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, allocation-free serving loops, harnesses that forbid hipMalloc):
+ * ns_gemm_f32_split without the scratch argument.  The split planes, block
+ * maxima, scale exponents and per-tile partial sums live in a scratch array
+ * built into the library, one copy per GPU, of NS_SPLIT_NOALLOC_MAX_BYTES
+ * bytes, held from the library's load until the process ends; the call makes
+ * no allocation of any kind.  sumsq_out, when non-NULL, is ONE device double
+ * that receives sum(D_ij^2) (the partial sums stay in the built-in array).
+ * Shapes need ns_gemm_f32_split_scratch_bytes(m, n, k) bytes, plus
+ * 8 ns_gemm_lp_partials(m, n) rounded up to 256 with sumsq_out; larger shapes
+ * are rejected with NS_ENOMEM (square shapes up to about n = 2800 fit).
+ * Every call on a GPU shares that GPU's array and leaves its contents behind:
+ * calls that overlap in time on one GPU (different streams, or several host
+ * threads) race and must be serialised by the caller.  Nothing in the array
+ * needs to start at zero: every byte a call reads was written earlier by the
+ * same call.  Operation, arguments, results and other errors as
+ * ns_gemm_f32_split; the stream must belong to the current device. */
+#define NS_SPLIT_NOALLOC_MAX_BYTES (64u << 20)
+int ns_gemm_f32_split_noalloc(void* hip_stream, int64_t m, int64_t n, int64_t k,
+                              const float* X, int64_t ldx, const float* Y, int64_t ldy,
+                              float* D, int64_t ldd, uint16_t* Db, int64_t lddb,
+                              const float* E1, int64_t lde1, const float* E2, int64_t lde2,
+                              float diag, float scale, double* sumsq_out);
+
 const char* ns_status_string(int status);
 const char* ns_last_error(void);
 

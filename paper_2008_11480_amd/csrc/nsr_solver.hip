@@ -9,6 +9,7 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -1676,6 +1677,65 @@ int ns_gemm_f32_split(void* hip_stream, int64_t m, int64_t n, int64_t k, const f
   return split_gemm_run(reinterpret_cast<hipStream_t>(hip_stream), m, n, k, X, ldx, Y, ldy, D,
                         ldd, Db, lddb, E1, lde1, E2, lde2, diag, scale, sp,
                         sumsq_out ? sumsq_out + 1 : nullptr, sumsq_out);
+}
+
+// ---- The split product without any allocation ----------------------------
+// Scratch of ns_gemm_f32_split_noalloc: the split planes, block maxima and
+// scale exponents, then the per-tile partial sums.  One copy per GPU, held by
+// the loaded code object until the process ends.  In host code this name is
+// not a device address; the address comes from hipGetSymbolAddress.
+static __device__ __align__(256) unsigned char split_noalloc_scratch[NS_SPLIT_NOALLOC_MAX_BYTES];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_noalloc_mu;
+void* g_noalloc_ptr[kMaxDevices] = {};
+
+// Device address of split_noalloc_scratch on the current device, looked up
+// once per device (with that device current) and kept.
+int noalloc_scratch(void** out) {
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return fail(NS_EINVAL, "device %d out of range", dev);
+  std::lock_guard<std::mutex> lock(g_noalloc_mu);
+  if (!g_noalloc_ptr[dev]) {
+    void* p = nullptr;
+    HIP_TRY(hipGetSymbolAddress(&p, HIP_SYMBOL(split_noalloc_scratch)));
+    if (!p) return fail(NS_EHIP, "hipGetSymbolAddress returned NULL");
+    g_noalloc_ptr[dev] = p;
+  }
+  *out = g_noalloc_ptr[dev];
+  return NS_OK;
+}
+
+size_t noalloc_need(int64_t m, int64_t n, int64_t k, bool sumsq) {
+  return split_scratch_bytes(m, n, k) +
+         (sumsq ? align_up((size_t)gemm_lp_partials(m, n) * sizeof(double), kAlign) : 0);
+}
+}  // namespace
+
+int ns_gemm_f32_split_noalloc(void* hip_stream, int64_t m, int64_t n, int64_t k,
+                              const float* X, int64_t ldx, const float* Y, int64_t ldy,
+                              float* D, int64_t ldd, uint16_t* Db, int64_t lddb,
+                              const float* E1, int64_t lde1, const float* E2, int64_t lde2,
+                              float diag, float scale, double* sumsq_out) {
+  const int rc = split_args_ok(m, n, k, X, ldx, Y, ldy, D, ldd, Db, lddb, E1, lde1, E2, lde2);
+  if (rc != NS_OK || m == 0 || n == 0) return rc;
+  const size_t need = noalloc_need(m, n, k, sumsq_out != nullptr);
+  if (need > (size_t)NS_SPLIT_NOALLOC_MAX_BYTES)
+    return fail(NS_ENOMEM,
+                "shape %lld x %lld x %lld needs %zu bytes of scratch; the built-in "
+                "scratch holds %zu (use ns_gemm_f32_split with a workspace)",
+                (long long)m, (long long)n, (long long)k, need,
+                (size_t)NS_SPLIT_NOALLOC_MAX_BYTES);
+  void* base = nullptr;
+  const int rs = noalloc_scratch(&base);
+  if (rs != NS_OK) return rs;
+  char* p = static_cast<char*>(base);
+  const SplitPlanes sp = carve_split(p, m, n, k);
+  double* part = reinterpret_cast<double*>(p + split_scratch_bytes(m, n, k));
+  return split_gemm_run(reinterpret_cast<hipStream_t>(hip_stream), m, n, k, X, ldx, Y, ldy, D,
+                        ldd, Db, lddb, E1, lde1, E2, lde2, diag, scale, sp, part, sumsq_out);
 }
 
 // The symmetric-output bf16 kernel faulted the GPU on its first test and the

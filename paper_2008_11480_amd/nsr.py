@@ -42,6 +42,7 @@ EXPORTS = (
     "ns_gemm_f64_scratch_bytes", "ns_gemm_f64_ws",
     "ns_gemm_f32", "ns_gemm_bf16_nt", "ns_gemm_lp_partials", "ns_gemm_f32_split",
     "ns_gemm_f32_split_scratch_bytes", "ns_gemm_bf16_nt_ws", "ns_gemm_bf16_scratch_bytes",
+    "ns_gemm_f32_split_noalloc",
     "ns_batch_workspace_bytes", "ns_batch_create", "ns_batch_set_launch", "ns_batch_submit",
     "ns_batch_poll", "ns_batch_autotune", "ns_batch_timeline", "ns_batch_destroy",
     "ns_status_string", "ns_last_error", "ns_version",
@@ -134,6 +135,9 @@ def lib() -> ctypes.CDLL:
                                    i64, vp, i64, ctypes.c_float, ctypes.c_float, vp, vp,
                                    ctypes.c_size_t]),
         "ns_gemm_f32_split_scratch_bytes": (ctypes.c_size_t, [i64, i64, i64]),
+        "ns_gemm_f32_split_noalloc": (ci, [vp, i64, i64, i64, vp, i64, vp, i64, vp, i64, vp,
+                                           i64, vp, i64, vp, i64, ctypes.c_float,
+                                           ctypes.c_float, vp]),
         "ns_gemm_bf16_nt_ws": (ci, [vp, i64, i64, i64, vp, i64, vp, i64, vp, i64, vp, i64, vp,
                                     i64, vp, i64, ctypes.c_float, ctypes.c_float, ci, vp, vp,
                                     ctypes.c_size_t]),
@@ -673,6 +677,41 @@ def gemm_f32_split(X, Y, D=None, want_bf16: bool = False, E1=None, E2=None,
         E2.stride(0) if E2 is not None else 0, float(diag), float(scale), _ptr(ss),
         _ptr(scratch), scratch.numel() * scratch.element_size()))
     return D, Db, (ss[0] if ss is not None else None)
+
+
+# Size of the library's built-in scratch of ns_gemm_f32_split_noalloc (include/nsr.h).
+SPLIT_NOALLOC_MAX_BYTES = 64 << 20
+
+
+def gemm_f32_split_noalloc(X, Y, D=None, want_bf16: bool = False, E1=None, E2=None,
+                           diag: float = 0.0, scale: float = 1.0, sumsq=None, stream=None):
+    """``ns_gemm_f32_split_noalloc``: the split product of ``gemm_f32_split``
+    with the library's built-in scratch (no scratch argument).  ``sumsq``, when
+    given, is a one-element float64 CUDA tensor that receives sum(D^2).
+    Returns (D, Db or None)."""
+    import torch
+    for t, nm in ((X, "X"), (Y, "Y")):
+        if not t.is_cuda or t.dtype != torch.float32 or t.stride(-1) != 1:
+            raise TypeError(f"{nm} must be a row-major float32 CUDA tensor")
+    m, k = X.shape
+    n = Y.shape[1]
+    if Y.shape[0] != k:
+        raise ValueError("inner dimensions differ")
+    for t in (E1, E2):
+        if t is not None and (t.dtype != torch.float32 or not t.is_cuda):
+            raise TypeError("addends must be float32 CUDA tensors")
+    if sumsq is not None and (sumsq.dtype != torch.float64 or not sumsq.is_cuda
+                              or sumsq.numel() < 1):
+        raise TypeError("sumsq must be a float64 CUDA tensor with at least one element")
+    if D is None:
+        D = torch.empty(m, n, dtype=torch.float32, device=X.device)
+    Db = torch.empty(m, n, dtype=torch.bfloat16, device=X.device) if want_bf16 else None
+    check(lib().ns_gemm_f32_split_noalloc(
+        _stream_handle(stream), m, n, k, _ptr(X), X.stride(0), _ptr(Y), Y.stride(0),
+        _ptr(D), D.stride(0), _ptr(Db), Db.stride(0) if Db is not None else 0,
+        _ptr(E1), E1.stride(0) if E1 is not None else 0, _ptr(E2),
+        E2.stride(0) if E2 is not None else 0, float(diag), float(scale), _ptr(sumsq)))
+    return D, Db
 
 
 def exported_symbols() -> list[str]:
