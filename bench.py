@@ -247,15 +247,25 @@ def roofline_of(g, kind, kernel, traffic):
     }
 
 
-def run_headline_dns8(torch, nsr, steps, warmup):
+def run_headline_dns8(torch, nsr, steps, warmup, host_inputs=False):
     """N = 8192, kappa = 1e6, double Newton-Schulz of order 8: the mixed
     mode (bf16 powers, float32 residual / G-side / merge, float64
     Richardson) and the same solve in float64, each with its own warm-up
-    and timed solves."""
+    and timed solves.  host_inputs: build the system with numpy on the host
+    (same recipe and draws; Q differs only by the QR's rounding) instead of
+    torch on the GPU."""
     w = inputs.WORKLOADS["spd8192_k1e6_dns8"]
     n = w["n"]
-    log(f"generating spd8192_k1e6_dns8 on the GPU: N={n} kappa={w['kappa']:g} seed={w['seed']}")
-    A, b, lam, Q = inputs.spd_qlq_device(n, w["kappa"], w["seed"])
+    where = "host" if host_inputs else "GPU"
+    log(f"generating spd8192_k1e6_dns8 on the {where}: N={n} kappa={w['kappa']:g} "
+        f"seed={w['seed']}")
+    if host_inputs:
+        sysm = inputs.spd_qlq(n, w["kappa"], w["seed"])
+        A, b = torch.from_numpy(sysm.A).cuda(), torch.from_numpy(sysm.b).cuda()
+        lam, Q = torch.from_numpy(sysm.lam).cuda(), torch.from_numpy(sysm.Q).cuda()
+        del sysm
+    else:
+        A, b, lam, Q = inputs.spd_qlq_device(n, w["kappa"], w["seed"])
     theta_star = Q @ ((Q.T.contiguous() @ b) / lam)
     del Q
     kw = dict(order=8, form="composite_double", k_max=w["k_max"], resid_tol=w["resid_tol"],
@@ -864,6 +874,9 @@ def main():
                          "analogue")
     ap.add_argument("--no-programs", action="store_true",
                     help="skip timing the other evaluation programs on the N=4096 system")
+    ap.add_argument("--host-inputs", action="store_true",
+                    help="build the N=8192 system on the host (numpy QR) rather than on the "
+                         "GPU; for profiler runs in which torch's device QR cannot run")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="also run a plain device copy of this many MiB (PMC calibration)")
     args = ap.parse_args()
@@ -893,7 +906,8 @@ def main():
     extras = not args.no_extras
     cpu_sample = None
     if args.workload == "spd8192_k1e6_dns8":
-        w, A8, b8, legs = run_headline_dns8(torch, nsr, args.steps, args.warmup)
+        w, A8, b8, legs = run_headline_dns8(torch, nsr, args.steps, args.warmup,
+                                            args.host_inputs)
         mx, f64 = legs["mixed"], legs["fp64"]
         lm, lf = mx["m"]["last"], f64["m"]["last"]
         out = headline_line(
