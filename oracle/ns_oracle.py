@@ -36,7 +36,8 @@ __all__ = [
     "diag_preconditioner", "initial_series", "gc_init", "gc_step", "gc_exponent",
     "sri_init", "sri_step", "sri_exponent",
     "z_table", "TABLE_ORDERS", "z_form", "form_mmm", "ns_step",
-    "dns_init", "dns_step", "richardson_update", "accelerator_apply", "SolveOptions",
+    "dns_init", "dns_step", "dns_step_recursive", "accelerator_matrix",
+    "richardson_update", "accelerator_apply", "SolveOptions",
     "SolveReport", "riem6_gamma",
     "solve", "stop_check", "floor_probe_needed", "STOP", "LAW_MARGIN", "efficiency_index",
 ]
@@ -325,6 +326,38 @@ def dns_step(a, st: DNSState, order, form="squaring", p=None, w=None, ctr=None) 
     gam_n = residual(a, l_k, ctr)
     hmat = z_form(a, st.G, order, form, p, w, ctr, y=st.F)
     g_k = l_k + _mm(ctr, hmat, gam_n)
+    f_k = residual(a, g_k, ctr)
+    return DNSState(L=l_k, Gam=gam_n, G=g_k, F=f_k)
+
+
+def accelerator_matrix(a, st: DNSState, q, ctr=None):
+    """Eq. (redttk2)'s ``omega_k`` formed as a matrix, right orientation:
+    ``omega_k = L_k + G_k {sum_{j<q} F_k^j} Gamma_k^n`` (the sum by Horner's
+    scheme, eq. z1), for the state after step k."""
+    w = st.G
+    for _ in range(q - 1):
+        w = st.G + _mm(ctr, w, st.F)
+    return st.L + _mm(ctr, w, st.Gam)
+
+
+def dns_step_recursive(a, st: DNSState, omega_prev, order, form="squaring", p=None, w=None,
+                       ctr=None) -> DNSState:
+    """One double Newton-Schulz step with ``G_k`` from the recursion of
+    eq. (gkrecu1) (Section 6.2), right orientation.
+
+    Both parts start from the sum ``P(Gamma_k) = sum_{j<n} Gamma_k^j`` with
+    ``Gamma_k = Gamma_{k-1}^n``.  Part 1: the ordinary loop
+    ``H = G_{k-1} P(F_{k-1})`` and ``G_k = (omega_{k-1} - H) P(Gamma_k) + H``,
+    one product given ``omega_{k-1}`` (eq. redttk2 with q = n, of the previous
+    step, as a matrix).  Part 2: ``L_k = L_{k-1} P(Gamma_k)`` (lkk1) and
+    ``Gamma_k^n = I - A L_k`` (gamk21).  Then ``F_k = I - A G_k``.  In exact
+    arithmetic ``G_k`` equals eq. (gkgen21)'s ``L_k + H Gamma_k^n``."""
+    eye = _eye_like(a)
+    p_gam = z_form(a, eye, order, form, p, w, ctr, y=st.Gam)
+    l_k = _mm(ctr, st.L, p_gam)
+    gam_n = residual(a, l_k, ctr)
+    hmat = z_form(a, st.G, order, form, p, w, ctr, y=st.F)
+    g_k = _mm(ctr, omega_prev - hmat, p_gam) + hmat
     f_k = residual(a, g_k, ctr)
     return DNSState(L=l_k, Gam=gam_n, G=g_k, F=f_k)
 

@@ -198,6 +198,67 @@ def test_double_ns_exponent_exact(n, ks):
             np.testing.assert_array_equal(st.Gam, shift_power(m, n ** (k + 1)))
 
 
+@pytest.mark.parametrize("n,q,ks", [(2, 2, (1, 2, 3)), (3, 3, (1, 2)), (2, 1, (1, 2)),
+                                    (4, 2, (1,))])
+def test_accelerator_matrix_exact(n, q, ks):
+    """eq. (redttk2) / (riem1) mirrored: I - A omega_k = F_k^q Gamma_k^n, so on
+    the shift operand omega_k = sum_{j < q e_k + n^(k+1)} J^j exactly, and the
+    operator applied to a vector (the solver's form) equals the matrix."""
+    m = 72
+    a = np.eye(m) - inputs.shift_matrix(m)
+    st = oracle.dns_init(a, np.eye(m), n, "horner")
+    r = np.arange(1.0, m + 1.0)
+    for k in range(1, max(ks) + 1):
+        st = oracle.dns_step(a, st, n, "horner")
+        if k in ks:
+            om = oracle.accelerator_matrix(a, st, q)
+            e_k = k * n ** (k + 1) + n ** k
+            np.testing.assert_array_equal(om, band_ones(m, q * e_k + n ** (k + 1)))
+            np.testing.assert_array_equal(oracle.accelerator_apply(a, st, r, q), om @ r)
+
+
+@pytest.mark.parametrize("n,ks", [(2, (1, 2, 3)), (3, (1, 2)), (4, (1,))])
+def test_gkrecu1_recursion_exact(n, ks):
+    """eq. (gkrecu1): G_k rebuilt from omega_{k-1} (eq. redttk2, q = n) with
+    one product equals the double Newton-Schulz iterate of eq. (gkgen21):
+    exactly on the shift operand (G_k = sum_{j < e_k} J^j), and the whole
+    state (L_k, Gamma_k^n, G_k, F_k) of both steps agrees."""
+    m = 64 if n != 3 else 72
+    a = np.eye(m) - inputs.shift_matrix(m)
+    st = oracle.dns_init(a, np.eye(m), n, "horner")
+    rec = st
+    for k in range(1, max(ks) + 1):
+        om = oracle.accelerator_matrix(a, rec, n)
+        rec = oracle.dns_step_recursive(a, rec, om, n, "horner")
+        st = oracle.dns_step(a, st, n, "horner")
+        e_k = k * n ** (k + 1) + n ** k
+        if k in ks:
+            np.testing.assert_array_equal(rec.G, band_ones(m, e_k))
+            np.testing.assert_array_equal(rec.F, shift_power(m, e_k))
+        for x, y in ((rec.L, st.L), (rec.Gam, st.Gam), (rec.G, st.G), (rec.F, st.F)):
+            np.testing.assert_array_equal(x, y)
+
+
+@pytest.mark.parametrize("order,form", [(4, "squaring"), (8, "squaring"), (3, "horner")])
+def test_gkrecu1_recursion_matches_merge_on_spd(order, form):
+    """On a seeded SPD system the recursion of eq. (gkrecu1) and the merge of
+    eq. (gkgen21) give the same G_k to rounding over four steps, and
+    I - A omega_k = F_k^n Gamma_k^n (eq. riem3 mirrored) holds as matrices."""
+    s = inputs.spd_qlq(96, 1e3, seed=17)
+    g0 = np.eye(96) / oracle.alpha_frobenius(s.A)
+    st = oracle.dns_init(s.A, g0, order, form)
+    rec = st
+    for _ in range(4):
+        om = oracle.accelerator_matrix(s.A, rec, order)
+        rec = oracle.dns_step_recursive(s.A, rec, om, order, form)
+        st = oracle.dns_step(s.A, st, order, form)
+        assert np.linalg.norm(rec.G - st.G) <= 1e-12 * np.linalg.norm(st.G)
+        om = oracle.accelerator_matrix(s.A, st, order)
+        lhs = np.eye(96) - s.A @ om
+        rhs = np.linalg.matrix_power(st.F, order) @ st.Gam
+        assert np.linalg.norm(lhs - rhs) <= 1e-12 * max(1.0, np.linalg.norm(rhs))
+
+
 def test_double_ns_eigen_closed_form():
     """||F_k||_F = sqrt(sum mu^{2 e_k}), e_k = k n^{k+1} + n^k (eq. ermoex1)."""
     s = inputs.spd_qlq(64, 1e3, seed=5)
