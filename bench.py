@@ -679,50 +679,61 @@ def run_batch(torch, nsr, reps_timed):
     }
 
 
-def run_serving(torch, nsr, duration_s=3.0, rate=2000.0):
+def run_serving(torch, nsr, duration_s=60.0, rate=2000.0, fp64_seconds=5.0, program="auto"):
     """Poisson arrivals at `rate` req/s for `duration_s` s; N log-uniform in
-    32..2048, kappa log-uniform in 10..1e6, mixed precision to 1e-10."""
+    32..2048, kappa log-uniform in 10..1e6, mixed precision to 1e-10.  Each
+    request's system is made on the device when it is admitted and freed
+    when it completes; single solves use the autotuned program table."""
     from paper_2008_11480_amd.serve import GpuExecutor, Server, make_requests
     trace = inputs.serving_trace(rate, duration_s, seed=5)
-    log(f"generating {len(trace)} serving requests on the GPU")
-    reqs = make_requests(trace)
-    torch.cuda.synchronize()
     # N <= 192 requests go to the batched kernel (one workgroup per system);
     # larger ones to 12 worker threads with their own streams (and hardware
     # queues, see GPU_MAX_HW_QUEUES above).
     workers, small = 12, 192
-    ex = GpuExecutor(workers=workers, precision=nsr.PREC_MIXED_BF16, small_max_n=small)
+    ex = GpuExecutor(workers=workers, precision=nsr.PREC_MIXED_BF16, small_max_n=small,
+                     order=program if program == "auto" else int(program))
+    t0 = time.perf_counter()
+    reqs = make_requests(trace, draw=ex)     # host data now; device systems per solve
+    log(f"serving trace: {len(trace)} requests over {duration_s:g} s "
+        f"(host draws {time.perf_counter() - t0:.1f} s)")
+    t0 = time.perf_counter()
+    choices = ex.prepare([q.n for q in trace])
+    log(f"program table tuned in {time.perf_counter() - t0:.1f} s: "
+        + ", ".join(f"2^{c['log2_n']}/p{c['precision']}: {c['program']}" for c in choices))
     # warm up the kernels and the allocator on a few requests of each path
-    warm = make_requests(inputs.serving_trace(rate, 0.02, seed=55))
+    warm = make_requests(inputs.serving_trace(rate, 0.02, seed=55), draw=ex)
     Server(ex, budget_bytes=32 << 30, workers=workers, small_max_n=small).run(warm)
     srv = Server(ex, budget_bytes=32 << 30, workers=workers, small_max_n=small)
     log("serving")
     st = srv.run(reqs)
     torch.cuda.synchronize()
-    rel = []
-    for r in reqs:
-        if r.status == "ok":
-            A, b, th = r.payload[:3]
-            rel.append(float(torch.linalg.norm(b - A @ th) / torch.linalg.norm(b)))
-    st["rel_resid_max"] = max(rel) if rel else None
     st["workload"] = f"serving_poisson{int(rate)}_{duration_s:g}s_n32-2048_k10-1e6"
-    st.pop("not_ok", None)
-    # The same trace with every solve in float64 (batched systems too): the
+    st["program_table"] = choices
+    st["not_ok"] = st.get("not_ok", [])[:5]
+    log(f"serving: {st['served']} served, {st['ok']} ok, p50 {st['latency_ms_p50']:.2f} ms, "
+        f"p99 {st['latency_ms_p99']:.2f} ms, {st['solves_per_s']:.0f} solves/s; stages "
+        + json.dumps(st["stages"]))
+    # The same arrivals with every solve in float64 (batched systems too): the
     # offered load exceeds what float64 sustains, so its solves/s over the
     # span (arrival of the first request to the last completion) is the
-    # float64 path's maximum sustainable rate.
+    # float64 path's maximum sustainable rate.  A shorter trace suffices.
     del reqs, ex, srv, warm
     release(torch)
-    reqs = make_requests(trace)
-    torch.cuda.synchronize()
-    ex64 = GpuExecutor(workers=workers, precision=nsr.PREC_FP64, small_max_n=small)
-    warm = make_requests(inputs.serving_trace(rate, 0.02, seed=55))
+    trace64 = [q for q in trace if q.arrival_s < fp64_seconds]
+    ex64 = GpuExecutor(workers=workers, precision=nsr.PREC_FP64, small_max_n=small,
+                       order=program if program == "auto" else int(program))
+    reqs = make_requests(trace64, draw=ex64)
+    choices64 = ex64.prepare([q.n for q in trace64])
+    warm = make_requests(inputs.serving_trace(rate, 0.02, seed=55), draw=ex64)
     Server(ex64, budget_bytes=32 << 30, workers=workers, small_max_n=small).run(warm)
-    log("serving, float64")
+    log(f"serving, float64 ({len(reqs)} requests over {fp64_seconds:g} s)")
     st64 = Server(ex64, budget_bytes=32 << 30, workers=workers, small_max_n=small).run(reqs)
     torch.cuda.synchronize()
-    st["fp64"] = {k: st64[k] for k in ("served", "ok", "solves_per_s", "span_s", "latency_ms_p50",
-                                       "latency_ms_p99", "latency_ms_max")}
+    st["fp64"] = {k: st64[k] for k in ("requests", "served", "ok", "solves_per_s", "span_s",
+                                       "latency_ms_p50", "latency_ms_p99", "latency_ms_max",
+                                       "rel_resid_max_reported")}
+    st["fp64"]["trace_seconds"] = fp64_seconds
+    st["fp64"]["program_table"] = choices64
     del reqs, ex64, warm
     return st
 
@@ -865,8 +876,13 @@ def main():
                     help="skip the factorized / split variants of the N=8192 system")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched leg")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving leg")
-    ap.add_argument("--serving-seconds", type=float, default=3.0,
+    ap.add_argument("--serving-seconds", type=float, default=60.0,
                     help="length of the serving trace (Poisson arrivals at 2000 req/s)")
+    ap.add_argument("--serving-fp64-seconds", type=float, default=5.0,
+                    help="length of the trace served in float64 (its sustainable rate)")
+    ap.add_argument("--serving-program", default="auto",
+                    help="single-solve program: 'auto' (autotuned table) or an order "
+                         "(squaring form)")
     ap.add_argument("--no-small", action="store_true",
                     help="skip the N=64 fixed-step leg (eager versus captured graph)")
     ap.add_argument("--no-comparisons", action="store_true",
@@ -986,7 +1002,9 @@ def main():
             out["batch"] = run_batch(torch, nsr, 3)
             release(torch)
         if not args.no_serving:
-            out["serving"] = run_serving(torch, nsr, duration_s=args.serving_seconds)
+            out["serving"] = run_serving(torch, nsr, duration_s=args.serving_seconds,
+                                         fp64_seconds=args.serving_fp64_seconds,
+                                         program=args.serving_program)
 
     if cpu_sample is not None:
         log("timing the CPU oracle on a bounded sample of the N=8192 workload")

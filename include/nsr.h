@@ -348,6 +348,46 @@ int ns_batch_timeline(ns_batch* b, uint64_t ticket, double* times_us, int32_t* w
 
 int ns_batch_destroy(ns_batch* b);
 
+/* ---- Admission by HBM footprint -----------------------------------------
+ *
+ * A ledger of device bytes in service against a budget, for serving loops
+ * that admit requests only while their inputs and workspaces fit (the
+ * request loop of the serving workload).  Host memory only; every call is
+ * thread-safe (one mutex per ledger), so any number of host threads may admit
+ * and release through one ledger. */
+typedef struct ns_ledger ns_ledger;
+
+/* budget_bytes > 0.  Errors: NS_EINVAL, NS_ENOMEM (host allocation). */
+int ns_ledger_create(size_t budget_bytes, ns_ledger** out);
+
+/* Admit `bytes` if they fit: NS_OK (in service += bytes), NS_ENOMEM if the
+ * bytes in service would exceed the budget (nothing changes; retry after a
+ * release), NS_EINVAL if `bytes` exceeds the whole budget (never fits). */
+int ns_ledger_admit(ns_ledger* l, size_t bytes);
+
+/* Return `bytes` admitted earlier.  NS_EINVAL if more than are in service. */
+int ns_ledger_release(ns_ledger* l, size_t bytes);
+
+/* Bytes in service, their peak, the budget, and the numbers of admissions
+ * and of NS_ENOMEM refusals so far (any pointer may be NULL). */
+int ns_ledger_query(ns_ledger* l, size_t* in_use, size_t* peak, size_t* budget,
+                    uint64_t* admitted, uint64_t* refused);
+int ns_ledger_destroy(ns_ledger* l);
+
+/* Device bytes one richardson_ns_solve of dimension n holds while it runs:
+ * the workspace (ns_workspace_bytes) plus A, b and theta in float64.
+ * 0 for invalid arguments. */
+size_t ns_solve_footprint(int64_t n, int precision, int composite);
+
+/* Attach a ledger to a batch handle (NULL detaches).  Each ns_batch_submit
+ * then admits the submission's footprint, the sum of (n^2 + 2 n) * 8 bytes
+ * of its systems' A, b and theta: NS_ENOMEM (over the budget) or NS_EINVAL
+ * (larger than the whole budget) is returned with nothing enqueued.
+ * ns_batch_poll releases the bytes when it reports completion, and
+ * ns_batch_destroy releases a submission still in flight.  Errors:
+ * NS_EINVAL, NS_EBUSY (a submission in flight). */
+int ns_batch_set_ledger(ns_batch* b, ns_ledger* ledger);
+
 /* Per-kernel timing with HIP events on the solver's stream.  While enabled,
  * every GEMM launch is bracketed by an event pair.  ns_timing_read returns
  * the number of timed GEMM launches, their summed duration (ms) and their
@@ -483,6 +523,31 @@ int ns_gemm_f32_split(void* hip_stream, int64_t m, int64_t n, int64_t k,
                       const float* E1, int64_t lde1, const float* E2, int64_t lde2,
                       float diag, float scale, double* sumsq_out,
                       void* scratch, size_t scratch_bytes);
+
+/* ---- Tile table of the project's tile autotuner --------------------------
+ *
+ * The MFMA GEMMs pick their output tile by a rule fitted on MI355X
+ * (occupancy of the 256 compute units per tile round).  A tile autotuner
+ * (autotune.tune_tiles in the Python package: it times each candidate tile
+ * per family and size and keeps the fastest) overrides that rule per GEMM
+ * family and size bucket: products whose output is m x n use the tile set
+ * for bucket ceil(log2(max(m, n))).  Families: NS_TILE_F64 (ns_gemm_f64 and
+ * the float64 solver products; tiles 64, 128), NS_TILE_F32 (float32 MFMA;
+ * 64, 128), NS_TILE_BF16 (bf16 powers; 64, 128, 256), NS_TILE_F16S (split
+ * half-precision products; 64, 128, 256).  Tile 0 restores the rule.  The
+ * table is process-wide (all devices); every tile is valid for every shape,
+ * and buffers sized by ns_gemm_f64_partials / ns_gemm_lp_partials /
+ * ns_workspace_bytes hold the partial sums of any choice.  Setting an entry
+ * while products run on other threads is allowed (each launch reads it
+ * once).  ns_tile_set errors: NS_EINVAL (unknown family, bucket outside
+ * 0..23, or a tile the family does not have).  ns_tile_get returns the
+ * entry, or -1 for invalid arguments. */
+#define NS_TILE_F64 0
+#define NS_TILE_F32 1
+#define NS_TILE_BF16 2
+#define NS_TILE_F16S 3
+int ns_tile_set(int family, int log2_dim, int tile);
+int ns_tile_get(int family, int log2_dim);
 
 /* For callers that cannot allocate device memory (code under HIP graph
  * capture, allocation-free serving loops, harnesses that forbid hipMalloc):

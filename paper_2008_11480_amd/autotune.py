@@ -138,19 +138,38 @@ def bucket(n: int, kappa: float, precision: int) -> tuple:
 class ProgramTable:
     """Best program per (precision, N bucket, kappa bucket), tuned on first use
     with a seeded stand-in system (Householder-product SPD matrix with a
-    log-uniform spectrum of condition number kappa)."""
+    log-uniform spectrum of condition number kappa).  Callers that do not
+    know their system's kappa (a serving loop) look up with ``kappa=None``,
+    which uses ``kappa_hint``.  Thread-safe: concurrent lookups of a bucket
+    that is not tuned yet tune it once."""
 
-    def __init__(self, programs=CANDIDATES, resid_tol: float = 1e-12, seed: int = 7):
+    def __init__(self, programs=CANDIDATES, resid_tol: float = 1e-12, seed: int = 7,
+                 kappa_hint: float = 1e4, refine_max: int = 64):
+        import threading
         self.programs = tuple(programs)
         self.resid_tol = resid_tol
         self.seed = seed
+        self.kappa_hint = float(kappa_hint)
+        self.refine_max = int(refine_max)
         self.table: dict[tuple, list[Trial]] = {}
+        self._lock = threading.Lock()
 
-    def lookup(self, n: int, kappa: float, precision: int) -> Program:
+    def lookup(self, n: int, kappa: float | None, precision: int) -> Program:
+        kappa = self.kappa_hint if kappa is None else kappa
         key = bucket(n, kappa, precision)
-        if key not in self.table:
-            self.table[key] = self._tune(n, kappa, precision)
-        return self.table[key][0].program
+        with self._lock:
+            if key not in self.table:
+                self.table[key] = self._tune(n, kappa, precision)
+            return self.table[key][0].program
+
+    def choices(self) -> list[dict]:
+        """The tuned buckets and their winners (for reports)."""
+        with self._lock:
+            return [{"precision": k[0], "log2_n": k[1], "log10_kappa": k[2],
+                     "program": v[0].program.name, "ms": v[0].ms,
+                     "runner_up": v[1].program.name if len(v) > 1 else None,
+                     "runner_up_ms": v[1].ms if len(v) > 1 else None}
+                    for k, v in sorted(self.table.items())]
 
     def _tune(self, n, kappa, precision):
         import torch
@@ -160,6 +179,78 @@ class ProgramTable:
         s = nsr.Solver(n, precision=precision, composite=False)
         try:
             s.bind(A)
-            return time_programs(s, b, theta, self.programs, resid_tol=self.resid_tol)
+            return time_programs(s, b, theta, self.programs, resid_tol=self.resid_tol,
+                                 refine_max=self.refine_max)
         finally:
             s.close()
+
+
+_DEFAULT_TABLE: ProgramTable | None = None
+
+
+def default_table() -> ProgramTable:
+    """Process-wide table behind ``Solver.solve(order="auto")``."""
+    global _DEFAULT_TABLE
+    if _DEFAULT_TABLE is None:
+        _DEFAULT_TABLE = ProgramTable()
+    return _DEFAULT_TABLE
+
+
+# ---------------------------------------------------------------------------
+# Tile autotuner: the GEMM tile per family and size bucket, by measurement.
+# ---------------------------------------------------------------------------
+
+def _family_gemm(family: int, n: int, torch, nsr):
+    """A representative product of the family at n x n x n (the solver's
+    shapes): returns a zero-argument callable that enqueues it."""
+    g = torch.Generator(device="cpu").manual_seed(n)
+    if family == nsr.TILE_F64:
+        X = torch.randn(n, n, generator=g, dtype=torch.float64).cuda()
+        D = torch.empty_like(X)
+        return lambda: nsr.gemm_f64(X, X, D=D)
+    X = torch.randn(n, n, generator=g, dtype=torch.float32).cuda()
+    D = torch.empty_like(X)
+    if family == nsr.TILE_F32:
+        return lambda: nsr.gemm_lp(X, X, nt=False, D=D)
+    if family == nsr.TILE_BF16:
+        Xb = X.to(torch.bfloat16)
+        return lambda: nsr.gemm_lp(Xb, Xb, nt=True, D=D)
+    scratch = torch.empty(int(nsr.lib().ns_gemm_f32_split_scratch_bytes(n, n, n)),
+                          dtype=torch.uint8, device="cuda")
+    return lambda: nsr.gemm_f32_split(X, X, D=D, scratch=scratch)
+
+
+def tune_tiles(families=None, sizes=(256, 512, 1024, 2048, 4096, 8192), reps: int = 3,
+               install: bool = True) -> list[dict]:
+    """Time every tile of each GEMM family at each size (n x n x n, one
+    warm-up then ``reps`` timed launches between HIP events on the current
+    stream) and, with ``install``, set the fastest for that size's bucket
+    (``ns_tile_set``).  Returns one record per (family, size) with every
+    candidate's time and the rule's own choice's time."""
+    import torch
+    from . import nsr
+    families = tuple(nsr.TILE_OPTIONS) if families is None else tuple(families)
+    out = []
+    for fam in families:
+        for n in sizes:
+            b = int(math.ceil(math.log2(n)))
+            run = _family_gemm(fam, n, torch, nsr)
+            times = {}
+            for tile in (0,) + nsr.TILE_OPTIONS[fam]:
+                nsr.tile_set(fam, b, tile)
+                run()
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record()
+                for _ in range(reps):
+                    run()
+                e1.record()
+                e1.synchronize()
+                times[tile] = e0.elapsed_time(e1) / reps
+            best = min((t for t in times if t), key=lambda t: times[t])
+            nsr.tile_set(fam, b, best if install else 0)
+            out.append({"family": fam, "n": n, "log2_dim": b, "best_tile": best,
+                        "ms": {str(k): v for k, v in times.items()},
+                        "speedup_vs_rule": times[0] / times[best]})
+            del run
+        torch.cuda.empty_cache()
+    return out

@@ -1276,6 +1276,8 @@ struct ns_batch {
   std::vector<BatchDesc> h_desc;
   std::vector<int32_t> h_order;
   std::vector<BatchResult> h_res;
+  ns_ledger* ledger = nullptr;   // HBM admission (ns_batch_set_ledger), may be NULL
+  size_t held = 0;               // bytes the in-flight submission holds in it
 };
 
 namespace {
@@ -1420,13 +1422,37 @@ int ns_batch_set_launch(ns_batch* B, int waves_per_group, int groups) {
   return NS_OK;
 }
 
+int ns_batch_set_ledger(ns_batch* B, ns_ledger* ledger) {
+  if (!B) return bfail(NS_EINVAL, "null batch");
+  if (B->busy) return bfail(NS_EBUSY, "a submission is still in flight; poll it first");
+  B->ledger = ledger;
+  return NS_OK;
+}
+
 int ns_batch_submit(ns_batch* B, int count, const int64_t* n, const double* const* A,
                     const int64_t* lda, const double* const* b, double* const* theta,
                     const ns_solve_opts* opts, uint64_t* ticket) {
   if (!B) return bfail(NS_EINVAL, "null batch");
   if (B->busy) return bfail(NS_EBUSY, "a submission is still in flight; poll it first");
-  if (int rc = batch_enqueue(B, count, n, A, lda, b, theta, opts)) return rc;
-  if (hipEventRecord(B->done, B->stream) != hipSuccess) return bfail(NS_EHIP, "hipEventRecord failed");
+  size_t bytes = 0;
+  if (B->ledger) {
+    // Admission by HBM footprint: the submission's A, b and theta.
+    if (count > 0 && !n) return bfail(NS_EINVAL, "null array");
+    for (int i = 0; i < count; ++i)
+      if (n[i] > 0) bytes += ((size_t)n[i] * (size_t)n[i] + 2 * (size_t)n[i]) * sizeof(double);
+    const int rc = ns_ledger_admit(B->ledger, bytes);
+    if (rc != NS_OK) return rc;
+  }
+  if (int rc = batch_enqueue(B, count, n, A, lda, b, theta, opts)) {
+    if (B->ledger) (void)ns_ledger_release(B->ledger, bytes);
+    return rc;
+  }
+  if (hipEventRecord(B->done, B->stream) != hipSuccess) {
+    (void)hipStreamSynchronize(B->stream);
+    if (B->ledger) (void)ns_ledger_release(B->ledger, bytes);
+    return bfail(NS_EHIP, "hipEventRecord failed");
+  }
+  B->held = bytes;
   B->busy = true;
   B->inflight = ++B->next_ticket;
   B->inflight_count = count;
@@ -1478,6 +1504,8 @@ int ns_batch_poll(ns_batch* B, uint64_t ticket, int wait, ns_solve_report* repor
                            hipMemcpyDeviceToHost) != hipSuccess)
     return bfail(NS_EHIP, "result download failed");
   B->busy = false;
+  if (B->ledger && B->held) (void)ns_ledger_release(B->ledger, B->held);
+  B->held = 0;
   B->last_polled = ticket;
   B->have_results = true;
   int worst = NS_OK;
@@ -1559,6 +1587,7 @@ int ns_batch_autotune(ns_batch* B, int count, const int64_t* n, const double* co
 int ns_batch_destroy(ns_batch* B) {
   if (!B) return NS_OK;
   if (B->busy) (void)hipEventSynchronize(B->done);
+  if (B->busy && B->ledger && B->held) (void)ns_ledger_release(B->ledger, B->held);
   if (B->done) (void)hipEventDestroy(B->done);
   delete B;
   return NS_OK;

@@ -27,6 +27,7 @@
 //    L2.
 #include <atomic>
 
+#include "nsr.h"
 #include "nsr_internal.h"
 
 // Tuning knobs of the large-tile configuration (chosen by measurement):
@@ -576,10 +577,12 @@ Plan plan_f64(int64_t m, int64_t n, int64_t k, bool sym, int64_t sk_cap) {
   const int64_t cus = device_cus();
   const int64_t s128 = 2 * cus;
   const int64_t c128 = tile_count(m, n, 128, sym), c64 = tile_count(m, n, 64, sym);
+  const int tc = tile_choice(kTileF64, m, n);          // the tile autotuner's choice
+  const int force = tc ? tc : NSR_F64_FORCE_TILE;
   Plan pl;
   double cost = 0.0;
-  if (NSR_F64_FORCE_TILE == 128 ||
-      (NSR_F64_FORCE_TILE != 64 && eff_rounds(c128, s128) <= 0.54 * eff_rounds(c64, 4 * cus))) {
+  if (force == 128 ||
+      (force != 64 && eff_rounds(c128, s128) <= 0.54 * eff_rounds(c64, 4 * cus))) {
     pl.big = true;
     pl.nt = pl.dp = c128;
     cost = eff_rounds(c128, s128);
@@ -588,7 +591,7 @@ Plan plan_f64(int64_t m, int64_t n, int64_t k, bool sym, int64_t sk_cap) {
     cost = 0.54 * eff_rounds(c64, 4 * cus);
   }
   const int64_t rem = c128 % s128;
-  if (NSR_F64_SPLIT && NSR_F64_FORCE_TILE != 64 && sk_cap > 0 && c128 > s128 && rem != 0) {
+  if (NSR_F64_SPLIT && force != 64 && sk_cap > 0 && c128 > s128 && rem != 0) {
     const int64_t nk = (k + 15) / 16;
     int64_t sp = s128 / rem < nk ? s128 / rem : nk;
     if (sp >= 2) {
@@ -608,6 +611,29 @@ Plan plan_f64(int64_t m, int64_t n, int64_t k, bool sym, int64_t sk_cap) {
 }
 
 }  // namespace
+
+namespace {
+// Tile choices of the tile autotuner (ns_tile_set), per GEMM family and
+// bucket ceil(log2(max(m, n))); 0 = the library's rule.
+constexpr int kTileBuckets = 24;
+std::atomic<int> g_tiles[kTileFamilies][kTileBuckets];
+
+int tile_bucket(int64_t d) {
+  int b = 0;
+  while (b + 1 < kTileBuckets && ((int64_t)1 << b) < d) ++b;
+  return b;
+}
+
+bool tile_valid(int family, int tile) {
+  if (tile == 0 || tile == 64 || tile == 128) return true;
+  return tile == 256 && (family == kTileBf16 || family == kTileF16s);
+}
+}  // namespace
+
+int tile_choice(int family, int64_t m, int64_t n) {
+  if (family < 0 || family >= kTileFamilies) return 0;
+  return g_tiles[family][tile_bucket(m > n ? m : n)].load(std::memory_order_relaxed);
+}
 
 int device_cus() {
   // Read and written by any host thread that plans a launch: atomic, and
@@ -649,3 +675,24 @@ int64_t launch_gemm_f64(const GemmF64Args& a, hipStream_t st) {
 }
 
 }  // namespace nsr
+
+extern "C" {
+
+int ns_tile_set(int family, int log2_dim, int tile) {
+  if (family < 0 || family >= nsr::kTileFamilies || log2_dim < 0 ||
+      log2_dim >= nsr::kTileBuckets || !nsr::tile_valid(family, tile)) {
+    nsr::ns_set_error("ns_tile_set: unknown family, bucket or tile");
+    return NS_EINVAL;
+  }
+  nsr::g_tiles[family][log2_dim].store(tile, std::memory_order_relaxed);
+  return NS_OK;
+}
+
+int ns_tile_get(int family, int log2_dim) {
+  if (family < 0 || family >= nsr::kTileFamilies || log2_dim < 0 ||
+      log2_dim >= nsr::kTileBuckets)
+    return -1;
+  return nsr::g_tiles[family][log2_dim].load(std::memory_order_relaxed);
+}
+
+}  // extern "C"

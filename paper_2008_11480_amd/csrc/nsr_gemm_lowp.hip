@@ -1116,17 +1116,16 @@ bool big_tiles(int64_t m, int64_t n) { return ((m + 127) / 128) * ((n + 127) / 1
 
 }  // namespace
 
-int64_t gemm_lp_partials(int64_t m, int64_t n) {
-  if (big_tiles(m, n)) return ((m + 127) / 128) * ((n + 127) / 128);
-  return ((m + 63) / 64) * ((n + 63) / 64);
-}
+// Per-tile partial sums of any tile choice (64 x 64 tiles give the most).
+int64_t gemm_lp_partials(int64_t m, int64_t n) { return ((m + 63) / 64) * ((n + 63) / 64); }
 
 int64_t launch_gemm_f32_nn(const GemmLpArgs& a, hipStream_t st) {
   if (a.M <= 0 || a.N <= 0) return 0;
   const bool vec = ((a.ldx & 3) == 0) && ((a.ldy & 3) == 0) &&
                    ((reinterpret_cast<uintptr_t>(a.X) & 15) == 0) &&
                    ((reinterpret_cast<uintptr_t>(a.Y) & 15) == 0);
-  const bool big = big_tiles(a.M, a.N);
+  const int tc = tile_choice(kTileF32, a.M, a.N);
+  const bool big = tc ? tc == 128 : big_tiles(a.M, a.N);
   const int bm = big ? 128 : 64;
   const int tiles_m = (int)((a.M + bm - 1) / bm), tiles_n = (int)((a.N + bm - 1) / bm);
   dim3 grid((unsigned)((int64_t)tiles_m * tiles_n)), block(256);
@@ -1146,8 +1145,9 @@ int64_t launch_gemm_bf16_nt(const GemmLpArgs& a, hipStream_t st) {
   const bool vec = ((a.ldx & 7) == 0) && ((a.ldy & 7) == 0) &&
                    ((reinterpret_cast<uintptr_t>(a.X) & 15) == 0) &&
                    ((reinterpret_cast<uintptr_t>(a.Y) & 15) == 0);
-  const bool huge = NSR_BF16_HUGE && ((a.M + 255) / 256) * ((a.N + 255) / 256) >= 256;
-  const bool big = big_tiles(a.M, a.N);
+  const int tc = tile_choice(kTileBf16, a.M, a.N);
+  const bool huge = tc ? tc == 256 : NSR_BF16_HUGE && ((a.M + 255) / 256) * ((a.N + 255) / 256) >= 256;
+  const bool big = tc ? tc == 128 : big_tiles(a.M, a.N);
   const int bm = huge ? 256 : (big ? 128 : 64);
   const int tiles_m = (int)((a.M + bm - 1) / bm), tiles_n = (int)((a.N + bm - 1) / bm);
   dim3 grid((unsigned)((int64_t)tiles_m * tiles_n)), block(256);
@@ -1207,8 +1207,9 @@ int64_t launch_gemm_f16s_nt(const GemmLpArgs& a, hipStream_t st) {
                    ((reinterpret_cast<uintptr_t>(a.Y) & 15) == 0) &&
                    ((reinterpret_cast<uintptr_t>(a.Xl) & 15) == 0) &&
                    ((reinterpret_cast<uintptr_t>(a.Yl) & 15) == 0);
-  const bool huge = ((a.M + 255) / 256) * ((a.N + 255) / 256) >= 256;
-  const bool big = big_tiles(a.M, a.N);
+  const int tc = tile_choice(kTileF16s, a.M, a.N);
+  const bool huge = tc ? tc == 256 : ((a.M + 255) / 256) * ((a.N + 255) / 256) >= 256;
+  const bool big = tc ? tc == 128 : big_tiles(a.M, a.N);
   const int bm = huge ? 256 : (big ? 128 : 64);
   const int tiles_m = (int)((a.M + bm - 1) / bm), tiles_n = (int)((a.N + bm - 1) / bm);
   dim3 grid((unsigned)((int64_t)tiles_m * tiles_n)), block(256);

@@ -170,4 +170,10 @@ int64_t launch_vec_sumsq(const double* v, int64_t n, double* partial, hipStream_
 // Set the calling thread's ns_last_error() message.
 void ns_set_error(const char* msg);
 
+// GEMM families of the tile table (the values of NS_TILE_* in nsr.h).
+constexpr int kTileF64 = 0, kTileF32 = 1, kTileBf16 = 2, kTileF16s = 3, kTileFamilies = 4;
+// Tile edge set by the tile autotuner for an m x n output of a family, or 0
+// (use the library's rule).
+int tile_choice(int family, int64_t m, int64_t n);
+
 }  // namespace nsr

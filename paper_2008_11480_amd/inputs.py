@@ -102,31 +102,108 @@ def spd_qlq_device(n: int, kappa: float, seed: int, device="cuda"):
     return a.contiguous(), torch.from_numpy(b).to(device), lt, q.contiguous()
 
 
-def spd_householder_device(n: int, kappa: float, seed: int, reflectors: int = 4,
-                           device="cuda"):
-    """Serving-size SPD system on ``device``: ``A = Q diag(lam) Q^T`` with ``Q``
-    a product of ``reflectors`` seeded Householder reflections (``O(n^2)`` work
-    each, so requests are cheap to make), ``lam`` log-uniform in
-    ``[1, kappa]`` with both ends pinned, ``b ~ N(0, 1)``.  The method's
-    convergence depends only on ``lam`` and ``alpha``.  Returns torch tensors
-    ``(A, b, lam, V)`` (float64); ``V`` holds the reflection vectors as rows,
-    applied in order (``Q = H_1 H_2 ... H_r`` acting on ``diag(lam)``)."""
-    import torch
+def householder_factors(n: int, kappa: float, seed: int, reflectors: int = 4):
+    """Host draws of a serving-size SPD system ``A = Q diag(lam) Q^T`` with
+    ``Q = H_1 H_2 ... H_r`` a product of ``reflectors`` seeded Householder
+    reflections: ``lam`` log-uniform in ``[1, kappa]`` with both ends pinned,
+    the reflection vectors ``V`` (rows), ``b ~ N(0, 1)``.  O(n) numbers."""
     rng = np.random.default_rng(seed)
     lam = loguniform_spectrum(n, kappa, rng)
     vs = rng.standard_normal((reflectors, n))
     b = rng.standard_normal(n)
-    a = torch.diag(torch.from_numpy(lam).to(device))
-    V = torch.from_numpy(vs).to(device)
-    for i in range(reflectors - 1, -1, -1):
-        v = V[i]
-        sv = torch.dot(v, v)
-        w = a @ v
-        # H a H with H = I - 2 v v^T / s: a rank-2 update
-        a = (a - (2.0 / sv) * (torch.outer(v, w) + torch.outer(w, v))
-             + (4.0 * torch.dot(v, w) / (sv * sv)) * torch.outer(v, v))
-    a = 0.5 * (a + a.T)
-    return (a.contiguous(), torch.from_numpy(b).to(device), torch.from_numpy(lam).to(device), V)
+    return lam, vs, b
+
+
+def _wy_core(lam: np.ndarray, vs: np.ndarray) -> tuple[np.ndarray, np.ndarray]:
+    """``Q diag(lam) Q^T = diag(lam) + Z C Z^T`` for ``Q = H_1 ... H_r``
+    (``H_i = I - tau_i v_i v_i^T``, ``tau_i = 2 / v_i^T v_i``): the compact WY
+    form ``Q = I - W T W^T`` (``W = [v_1 .. v_r]``, ``T`` upper triangular,
+    accumulated one reflection at a time) gives ``Z = [W, diag(lam) W]`` and
+    ``C = [[T M T^T, -T], [-T^T, 0]]`` with ``M = W^T diag(lam) W``."""
+    w = np.ascontiguousarray(vs.T)                      # n x r
+    r = w.shape[1]
+    t = np.zeros((r, r))
+    for j in range(r):
+        tau = 2.0 / float(w[:, j] @ w[:, j])
+        if j:
+            t[:j, j] = -tau * (t[:j, :j] @ (w[:, :j].T @ w[:, j]))
+        t[j, j] = tau
+    u = lam[:, None] * w
+    m = w.T @ u
+    c = np.zeros((2 * r, 2 * r))
+    tmt = t @ m @ t.T
+    c[:r, :r] = 0.5 * (tmt + tmt.T)                     # symmetric to the bit
+    c[:r, r:] = -t
+    c[r:, :r] = -t.T
+    return np.concatenate([w, u], axis=1), c
+
+
+def householder_pack(lam: np.ndarray, vs: np.ndarray, b: np.ndarray) -> np.ndarray:
+    """One host array holding what the device needs to make the system of
+    :func:`householder_factors`: ``[Z C (n x 2r) | Z (n x 2r) | lam | b |
+    zeros (theta) | V (r x n)]`` (see :func:`_wy_core`)."""
+    z, c = _wy_core(lam, vs)
+    return np.concatenate([(z @ c).ravel(), z.ravel(), lam, b, np.zeros_like(b), vs.ravel()])
+
+
+def householder_unpack_device(packed: np.ndarray, n: int, reflectors: int = 4, device="cuda"):
+    """Device tensors ``(A, b, theta, lam, V)`` from :func:`householder_pack`:
+    one upload, then ``A = (Z C) Z^T`` and ``diag(A) += lam`` (two device
+    operations).  ``A`` is symmetric to the rounding of that product's
+    summation order; ``theta`` is zero."""
+    import torch
+    w = 2 * reflectors
+    dev = torch.from_numpy(packed).to(device)
+    o = 0
+    zc = dev[o:o + n * w].view(n, w)
+    o += n * w
+    z = dev[o:o + n * w].view(n, w)
+    o += n * w
+    lam = dev[o:o + n]
+    b = dev[o + n:o + 2 * n]
+    theta = dev[o + 2 * n:o + 3 * n]
+    V = dev[o + 3 * n:].view(reflectors, n)
+    a = zc @ z.T
+    a.diagonal().add_(lam)
+    return a, b, theta, lam, V
+
+
+def householder_dense_pack(lam: np.ndarray, vs: np.ndarray, b: np.ndarray) -> np.ndarray:
+    """``[A (n x n, row-major) | b | zeros (theta) | lam | V (r x n)]`` on the
+    host, ``A = diag(lam) + (Z C) Z^T`` (for small systems, uploaded whole)."""
+    z, c = _wy_core(lam, vs)
+    a = (z @ c) @ z.T
+    a[np.diag_indices_from(a)] += lam
+    return np.concatenate([a.ravel(), b, np.zeros_like(b), lam, vs.ravel()])
+
+
+def dense_unpack(dev, n: int, reflectors: int = 4):
+    """Views ``(A, b, theta, lam, V)`` of a device copy of
+    :func:`householder_dense_pack`'s array."""
+    o = n * n
+    return (dev[:o].view(n, n), dev[o:o + n], dev[o + n:o + 2 * n], dev[o + 2 * n:o + 3 * n],
+            dev[o + 3 * n:o + 3 * n + reflectors * n].view(reflectors, n))
+
+
+def spd_from_factors_device(lam: np.ndarray, vs: np.ndarray, b: np.ndarray, device="cuda"):
+    """Device tensors ``(A, b, lam, V)`` (float64) of the system of
+    :func:`householder_factors` (via :func:`householder_pack`)."""
+    a, bt, _, lt, V = householder_unpack_device(householder_pack(lam, vs, b), lam.shape[0],
+                                                vs.shape[0], device)
+    return a, bt, lt, V
+
+
+def spd_householder_device(n: int, kappa: float, seed: int, reflectors: int = 4,
+                           device="cuda"):
+    """Serving-size SPD system on ``device``: ``A = Q diag(lam) Q^T`` with ``Q``
+    a product of ``reflectors`` seeded Householder reflections (O(n^2) work,
+    so requests are cheap to make), ``lam`` log-uniform in ``[1, kappa]`` with
+    both ends pinned, ``b ~ N(0, 1)``.  The method's convergence depends only
+    on ``lam`` and ``alpha``.  Returns torch tensors ``(A, b, lam, V)``
+    (float64); ``V`` holds the reflection vectors as rows, applied in order
+    (``Q = H_1 H_2 ... H_r`` acting on ``diag(lam)``)."""
+    lam, vs, b = householder_factors(n, kappa, seed, reflectors)
+    return spd_from_factors_device(lam, vs, b, device)
 
 
 def householder_solve_device(lam, V, b):

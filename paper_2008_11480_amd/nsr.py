@@ -42,9 +42,11 @@ EXPORTS = (
     "ns_gemm_f64_scratch_bytes", "ns_gemm_f64_ws",
     "ns_gemm_f32", "ns_gemm_bf16_nt", "ns_gemm_lp_partials", "ns_gemm_f32_split",
     "ns_gemm_f32_split_scratch_bytes", "ns_gemm_bf16_nt_ws", "ns_gemm_bf16_scratch_bytes",
-    "ns_gemm_f32_split_noalloc",
+    "ns_gemm_f32_split_noalloc", "ns_tile_set", "ns_tile_get",
     "ns_batch_workspace_bytes", "ns_batch_create", "ns_batch_set_launch", "ns_batch_submit",
     "ns_batch_poll", "ns_batch_autotune", "ns_batch_timeline", "ns_batch_destroy",
+    "ns_batch_set_ledger", "ns_ledger_create", "ns_ledger_admit", "ns_ledger_release",
+    "ns_ledger_query", "ns_ledger_destroy", "ns_solve_footprint",
     "ns_status_string", "ns_last_error", "ns_version",
 )
 
@@ -135,6 +137,8 @@ def lib() -> ctypes.CDLL:
                                    i64, vp, i64, ctypes.c_float, ctypes.c_float, vp, vp,
                                    ctypes.c_size_t]),
         "ns_gemm_f32_split_scratch_bytes": (ctypes.c_size_t, [i64, i64, i64]),
+        "ns_tile_set": (ci, [ci, ci, ci]),
+        "ns_tile_get": (ci, [ci, ci]),
         "ns_gemm_f32_split_noalloc": (ci, [vp, i64, i64, i64, vp, i64, vp, i64, vp, i64, vp,
                                            i64, vp, i64, vp, i64, ctypes.c_float,
                                            ctypes.c_float, vp]),
@@ -153,6 +157,17 @@ def lib() -> ctypes.CDLL:
                                    ctypes.POINTER(ci), ctypes.POINTER(ci), pd]),
         "ns_batch_timeline": (ci, [vp, ctypes.c_uint64, vp, vp]),
         "ns_batch_destroy": (ci, [vp]),
+        "ns_batch_set_ledger": (ci, [vp, vp]),
+        "ns_ledger_create": (ci, [ctypes.c_size_t, ctypes.POINTER(vp)]),
+        "ns_ledger_admit": (ci, [vp, ctypes.c_size_t]),
+        "ns_ledger_release": (ci, [vp, ctypes.c_size_t]),
+        "ns_ledger_query": (ci, [vp, ctypes.POINTER(ctypes.c_size_t),
+                                 ctypes.POINTER(ctypes.c_size_t),
+                                 ctypes.POINTER(ctypes.c_size_t),
+                                 ctypes.POINTER(ctypes.c_uint64),
+                                 ctypes.POINTER(ctypes.c_uint64)]),
+        "ns_ledger_destroy": (ci, [vp]),
+        "ns_solve_footprint": (ctypes.c_size_t, [i64, ci, ci]),
         "ns_status_string": (ctypes.c_char_p, [ci]),
         "ns_last_error": (ctypes.c_char_p, []),
         "ns_version": (ctypes.c_char_p, []),
@@ -211,6 +226,7 @@ class Solver:
         nbytes = workspace_bytes(n, precision, composite)
         if nbytes == 0:
             raise NSError(NS_EINVAL, "unsupported size/precision")
+        self.precision = int(precision)
         self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8,
                                      device=f"cuda:{self.device}")
         base = self.workspace.data_ptr()
@@ -279,14 +295,22 @@ class Solver:
         check(lib().ns_richardson_step(self._h, _ptr(b), _ptr(theta), ctypes.byref(r)))
         return r.value
 
-    def solve(self, b, theta, order: int = 8, form: str = "squaring", p: int = 0, w: int = 0,
-              k_max: int = 64, refine_max: int = 64, floor_detect: bool = True,
+    def solve(self, b, theta, order: int | str = 8, form: str = "squaring", p: int = 0,
+              w: int = 0, k_max: int = 64, refine_max: int = 64, floor_detect: bool = True,
               scale: int = SCALE_FROBENIUS, eps: float = 0.0, f_tol: float = 0.0,
               resid_tol: float = 1e-12, theta0_mode: int = 0, accel_q: int = 0,
               init_order: int = 0, init_p: int = 0, init_w: int = 0, graph: bool = False,
-              raise_on_error: bool = True):
+              raise_on_error: bool = True, kappa: float | None = None, table=None):
+        """``richardson_ns_solve``.  ``order="auto"``: the program (order, form,
+        p, w) comes from ``table`` (default: ``autotune.default_table()``),
+        tuned for this solver's N and precision and for ``kappa`` (None: the
+        table's hint); ``form`` is then ignored."""
         _require_cuda_f64(b, "b")
         _require_cuda_f64(theta, "theta")
+        if order == "auto":
+            from . import autotune
+            prog = (table or autotune.default_table()).lookup(self.n, kappa, self.precision)
+            order, form, p, w = prog.order, prog.form, prog.p, prog.w
         o = SolveOpts(order=order, factorization=FACT[form], p=p, w=w, k_max=k_max,
                       refine_max=refine_max, floor_detect=1 if floor_detect else 0, scale=scale,
                       eps=eps, f_tol=f_tol, resid_tol=resid_tol, theta0_mode=theta0_mode,
@@ -442,6 +466,49 @@ def _report_arrays(reps, count: int) -> dict:
     return {f: arr[f].copy() for f in _REPORT_COLUMNS}
 
 
+class Ledger:
+    """``ns_ledger``: HBM-footprint admission (host memory only, thread-safe)."""
+
+    def __init__(self, budget_bytes: int):
+        h = ctypes.c_void_p()
+        check(lib().ns_ledger_create(int(budget_bytes), ctypes.byref(h)))
+        self._h = h
+
+    def admit(self, nbytes: int) -> bool:
+        """True if admitted; False if over the budget now (NS_ENOMEM).  Raises
+        NSError(NS_EINVAL) for a footprint above the whole budget."""
+        st = lib().ns_ledger_admit(self._h, int(nbytes))
+        if st == NS_ENOMEM:
+            return False
+        check(st)
+        return True
+
+    def release(self, nbytes: int):
+        check(lib().ns_ledger_release(self._h, int(nbytes)))
+
+    def query(self) -> dict:
+        v = [ctypes.c_size_t() for _ in range(3)] + [ctypes.c_uint64() for _ in range(2)]
+        check(lib().ns_ledger_query(self._h, *[ctypes.byref(x) for x in v]))
+        return dict(zip(("in_use", "peak", "budget", "admitted", "refused"),
+                        (x.value for x in v)))
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().ns_ledger_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def solve_footprint(n: int, precision: int = PREC_FP64, composite: int = 0) -> int:
+    """``ns_solve_footprint``: workspace plus A, b, theta of one solve."""
+    return int(lib().ns_solve_footprint(int(n), int(precision), int(composite)))
+
+
 class Batch:
     """``ns_batch`` handle: many independent systems per persistent launch."""
 
@@ -473,6 +540,12 @@ class Batch:
         if getattr(self, "_h", None) is not None and self._h.value:
             lib().ns_batch_destroy(self._h)
             self._h = None
+
+    def set_ledger(self, ledger: "Ledger | None"):
+        """Admit each submission's A, b, theta bytes through ``ledger``
+        (``submit`` then raises NSError(NS_ENOMEM) when over the budget)."""
+        check(lib().ns_batch_set_ledger(self._h, ledger._h if ledger is not None else None))
+        self._ledger = ledger
 
     def __del__(self):
         try:
@@ -677,6 +750,22 @@ def gemm_f32_split(X, Y, D=None, want_bf16: bool = False, E1=None, E2=None,
         E2.stride(0) if E2 is not None else 0, float(diag), float(scale), _ptr(ss),
         _ptr(scratch), scratch.numel() * scratch.element_size()))
     return D, Db, (ss[0] if ss is not None else None)
+
+
+# GEMM families of the tile table (NS_TILE_* in include/nsr.h) and their tiles.
+TILE_F64, TILE_F32, TILE_BF16, TILE_F16S = 0, 1, 2, 3
+TILE_OPTIONS = {TILE_F64: (64, 128), TILE_F32: (64, 128), TILE_BF16: (64, 128, 256),
+                TILE_F16S: (64, 128, 256)}
+
+
+def tile_set(family: int, log2_dim: int, tile: int):
+    """``ns_tile_set``: the tile of a family's products with max(m, n) in
+    (2^(log2_dim - 1), 2^log2_dim]; 0 restores the library's rule."""
+    check(lib().ns_tile_set(int(family), int(log2_dim), int(tile)))
+
+
+def tile_get(family: int, log2_dim: int) -> int:
+    return int(lib().ns_tile_get(int(family), int(log2_dim)))
 
 
 # Size of the library's built-in scratch of ns_gemm_f32_split_noalloc (include/nsr.h).

@@ -16,9 +16,18 @@ than the whole budget is rejected.  Admitted requests are routed by size:
   float32-class products of split half-precision operands, which are faster
   there).
 
-Latency = completion - arrival.  The scheduling and admission logic is plain
-host code driven through an executor object, so it runs on the CPU with a
-fake executor in the tests; :class:`GpuExecutor` is the real one.
+A request's system is made on the device when it is admitted (its inputs
+count in the ledger from then on) and freed when it completes, so only the
+requests in service occupy HBM, whatever the length of the trace.  The
+admission ledger is the library's (``ns_ledger_*``: thread-safe, host only).
+Single solves take their Newton-Schulz program from an autotuned
+:class:`autotune.ProgramTable` per (precision, N bucket), tuned before the
+clock starts (``GpuExecutor.prepare``).
+
+Latency = completion - arrival (making the request's system on the device is
+part of it).  The scheduling and admission logic is plain host code driven
+through an executor object, so it runs on the CPU with a fake executor in the
+tests; :class:`GpuExecutor` is the real one.
 """
 from __future__ import annotations
 
@@ -35,40 +44,47 @@ class Request:
     rid: int
     arrival_s: float
     n: int
-    payload: object = None          # executor-specific (device tensors)
+    kappa: float = 0.0              # of the request's seeded system (not used to solve)
+    seed: int = 0
+    payload: object = None          # executor-specific (device tensors while in service)
+    host: object = None             # host draws of the system, until it is made
     footprint: int = 0
     admitted_s: float = float("nan")
+    ready_s: float = float("nan")   # its system made on the device
+    start_s: float = float("nan")   # its solve started
     end_s: float = float("nan")
     status: str = "pending"         # pending | ok | noconv | diverged | rejected | error
     path: str = ""                  # "batch" | "single"
     precision: int = -1
     ns_steps: int = 0
+    rel_resid: float = float("nan")  # the library's report of the returned theta
 
 
 class Admission:
-    """HBM-footprint admission control (host logic, thread-safe)."""
+    """HBM-footprint admission control through the library's ledger
+    (``ns_ledger_*``, thread-safe)."""
 
     def __init__(self, budget_bytes: int):
+        from . import nsr
         self.budget = int(budget_bytes)
-        self.in_use = 0
-        self.peak = 0
-        self._lock = threading.Lock()
+        self._ledger = nsr.Ledger(self.budget)
+
+    @property
+    def in_use(self) -> int:
+        return self._ledger.query()["in_use"]
+
+    @property
+    def peak(self) -> int:
+        return self._ledger.query()["peak"]
 
     def fits_at_all(self, footprint: int) -> bool:
         return footprint <= self.budget
 
     def try_admit(self, footprint: int) -> bool:
-        with self._lock:
-            if self.in_use + footprint > self.budget:
-                return False
-            self.in_use += footprint
-            self.peak = max(self.peak, self.in_use)
-            return True
+        return self._ledger.admit(footprint)
 
     def release(self, footprint: int):
-        with self._lock:
-            self.in_use -= footprint
-            assert self.in_use >= 0
+        self._ledger.release(footprint)
 
 
 class Server:
@@ -96,11 +112,15 @@ class Server:
 
         def now():
             return time.perf_counter() - t0
+        self.ex._now = now
 
         def finish(batch):
+            end = now()
+            for r in batch:
+                self.ex.release(r)          # the request's device memory
             with cv:
                 for r in batch:
-                    r.end_s = now()
+                    r.end_s = end
                     self.adm.release(r.footprint)
                 state["done"] += len(batch)
                 cv.notify_all()
@@ -125,6 +145,7 @@ class Server:
                     if not large_q:
                         return
                     r = large_q.popleft()
+                r.start_s = now()
                 try:
                     self.ex.solve_single(r, wid)
                     r.path = "single"
@@ -145,6 +166,9 @@ class Server:
                            and not (state["arrivals_done"] and not arrived)):
                         cv.wait(max(1e-4, self.batch_window_s - (now() - small_q[0].admitted_s)))
                     batch = [small_q.popleft() for _ in range(min(len(small_q), self.batch_max))]
+                t_start = now()
+                for r in batch:
+                    r.start_s = t_start
                 try:
                     self.ex.solve_batch(batch)
                     for r in batch:
@@ -187,6 +211,16 @@ class Server:
         lat = np.array([r.end_s - r.arrival_s / time_scale for r in served]) * 1e3
         wait = np.array([r.admitted_s - r.arrival_s / time_scale for r in served]) * 1e3
         span = max((r.end_s for r in reqs), default=0.0)
+
+        def pct(vals, q):
+            v = np.array([x for x in vals if np.isfinite(x)]) * 1e3
+            return float(np.percentile(v, q)) if len(v) else None
+        stages = {
+            "queue_ms": [r.start_s - r.admitted_s for r in served],
+            "make_system_ms": [r.ready_s - r.start_s for r in served],
+            "solve_single_ms": [r.end_s - r.start_s for r in served if r.path == "single"],
+            "solve_batch_ms": [r.end_s - r.start_s for r in served if r.path == "batch"],
+        }
         out = {
             "requests": len(reqs),
             "served": len(served),
@@ -206,23 +240,32 @@ class Server:
             "single": sum(1 for r in served if r.path == "single"),
             "escalated_to_fp64": sum(1 for r in served if r.precision == 0 and r.path == "batch"),
             "single_split": sum(1 for r in served if r.precision == 3 and r.path == "single"),
+            "rel_resid_max_reported": max((r.rel_resid for r in served if r.status == "ok"),
+                                          default=None),
+            "stages": {k: {"p50": pct(v, 50), "p99": pct(v, 99)} for k, v in stages.items()},
         }
         return out
 
 
 class GpuExecutor:
     """Runs requests through libnsr: batches for small systems, one solver per
-    worker thread and HIP stream for the rest."""
+    worker thread and HIP stream for the rest.  ``order="auto"``: single
+    solves take their program from ``self.table`` (an autotuned
+    :class:`autotune.ProgramTable`, kappa unknown to the server: the table's
+    ``kappa_hint``); an integer order runs the squaring form of that order."""
 
-    def __init__(self, workers: int, precision: int, order: int = 8, resid_tol: float = 1e-10,
+    def __init__(self, workers: int, precision: int, order="auto", resid_tol: float = 1e-10,
                  small_max_n: int = 256, batch_max: int = 256, refine_max: int = 100,
-                 split_min_n: int = 1536):
+                 split_min_n: int = 1536, kappa_hint: float = 1e4):
         import torch
-        from . import nsr
+        from . import autotune, nsr
         self.torch, self.nsr = torch, nsr
         self.precision, self.order, self.resid_tol = precision, order, resid_tol
         self.split_min_n = split_min_n
+        self.small_max_n = small_max_n
         self.refine_max = refine_max
+        self.table = autotune.ProgramTable(resid_tol=resid_tol, kappa_hint=kappa_hint,
+                                           refine_max=refine_max)
         self.streams = [torch.cuda.Stream() for _ in range(workers)]
         self.batch_stream = torch.cuda.Stream()
         cus = torch.cuda.get_device_properties(0).multi_processor_count
@@ -243,51 +286,116 @@ class GpuExecutor:
 
     def footprint(self, r: Request) -> int:
         n = r.n
-        ws = self.nsr.workspace_bytes(n, self.precision_for(n), False)
-        return ws + (n * n + 2 * n) * 8
+        if n <= self.small_max_n:   # batched: inputs only (the batch workspace is resident)
+            return (n * n + 2 * n) * 8
+        return self.nsr.solve_footprint(n, self.precision_for(n), 0)
+
+    def prepare(self, sizes):
+        """Tune the program table for the single-solve sizes in ``sizes``
+        (one lookup per (precision, N bucket)) before the clock starts."""
+        if self.order != "auto":
+            return []
+        seen = set()
+        for n in sorted(set(int(x) for x in sizes)):
+            if n <= self.small_max_n:
+                continue
+            from .autotune import bucket
+            key = bucket(n, self.table.kappa_hint, self.precision_for(n))
+            if key in seen:
+                continue
+            seen.add(key)
+            self.table.lookup(n, None, self.precision_for(n))
+        return self.table.choices()
+
+    def host_draws(self, r: Request):
+        """The request's host data (before the clock): small systems whole
+        (``inputs.householder_dense_pack``, uploaded with their batch), larger
+        ones as O(n) factors (``inputs.householder_pack``, made on the device
+        by the worker that solves them)."""
+        from . import inputs
+        f = inputs.householder_factors(r.n, r.kappa, r.seed % (2 ** 31))
+        return (inputs.householder_dense_pack(*f) if r.n <= self.small_max_n
+                else inputs.householder_pack(*f))
+
+    def _make_single(self, r: Request):
+        """Make a single-path request's system on the current stream."""
+        from . import inputs
+        host = r.host if r.host is not None else self.host_draws(r)
+        r.payload = inputs.householder_unpack_device(host, r.n)
+        r.host = None
+
+    def _make_batch(self, batch: list[Request]):
+        """Upload a batch of small requests' systems with one copy on the
+        current stream."""
+        import numpy as np
+        from . import inputs
+        hosts = [r.host if r.host is not None else self.host_draws(r) for r in batch]
+        dev = self.torch.from_numpy(np.concatenate(hosts)).to("cuda", non_blocking=False)
+        o = 0
+        for r, h in zip(batch, hosts):
+            r.payload = inputs.dense_unpack(dev[o:o + h.size], r.n)
+            r.host = None
+            o += h.size
+
+    def release(self, r: Request):
+        """Drop the request's device tensors, keeping theta and what checks it
+        (lam, V, b) unless ``keep_results`` is off."""
+        if r.payload is not None and not getattr(self, "keep_results", False):
+            r.payload = None
 
     def solve_single(self, r: Request, wid: int):
         torch, nsr = self.torch, self.nsr
         st = self.streams[wid]
-        A, b, th = r.payload[:3]
         with torch.cuda.stream(st):
+            self._make_single(r)
+            r.ready_s = self._now() if hasattr(self, "_now") else float("nan")
+            A, b, th = r.payload[:3]
             s = nsr.Solver(r.n, precision=self.precision_for(r.n), composite=False, stream=st)
             s.bind(A)
-            rep = s.solve(b, th, order=self.order, form="squaring", k_max=64,
-                          resid_tol=self.resid_tol, refine_max=self.refine_max,
-                          raise_on_error=False)
+            prog = dict(order="auto", table=self.table) if self.order == "auto" else dict(
+                order=self.order, form="squaring")
+            rep = s.solve(b, th, k_max=64, resid_tol=self.resid_tol,
+                          refine_max=self.refine_max, raise_on_error=False, **prog)
             s.close()
             del s
         r.status = {nsr.NS_OK: "ok", nsr.NS_ENOCONV: "noconv"}.get(rep.status, "diverged")
         r.precision = rep.precision
         r.ns_steps = rep.ns_steps
+        r.rel_resid = rep.rel_resid
 
     def solve_batch(self, batch: list[Request]):
         torch, nsr = self.torch, self.nsr
-        As = [r.payload[0] for r in batch]
-        bs = [r.payload[1] for r in batch]
-        ths = [r.payload[2] for r in batch]
         with torch.cuda.stream(self.batch_stream):
+            self._make_batch(batch)
+            ready = self._now() if hasattr(self, "_now") else float("nan")
+            for r in batch:
+                r.ready_s = ready
+            As = [r.payload[0] for r in batch]
+            bs = [r.payload[1] for r in batch]
+            ths = [r.payload[2] for r in batch]
             t = self.batch.submit(As, bs, ths, order=4, resid_tol=self.resid_tol,
                                   refine_max=self.refine_max)
             cols = self.batch.poll_arrays(t, wait=True)
         names = {nsr.NS_OK: "ok", nsr.NS_ENOCONV: "noconv"}
-        for r, st, prec, steps in zip(batch, cols["status"].tolist(), cols["precision"].tolist(),
-                                      cols["ns_steps"].tolist()):
+        for r, st, prec, steps, rel in zip(batch, cols["status"].tolist(),
+                                           cols["precision"].tolist(), cols["ns_steps"].tolist(),
+                                           cols["rel_resid"].tolist()):
             r.status = names.get(st, "diverged")
             r.precision = prec
             r.ns_steps = steps
+            r.rel_resid = rel
 
 
-def make_requests(trace, device="cuda") -> list[Request]:
-    """Device-resident requests for a trace of ``inputs.Request`` records
-    (generated before the serving clock starts)."""
-    import torch
-    from . import inputs
+def make_requests(trace, draw=None) -> list[Request]:
+    """Requests for a trace of ``inputs.Request`` records.  ``draw`` (an
+    executor): make each request's host data now, before the serving clock
+    (``GpuExecutor.host_draws``); otherwise the executor makes it when the
+    request starts.  The system reaches the device only when its solve
+    starts, and is freed when it completes."""
     out = []
     for i, q in enumerate(trace):
-        A, b, lam, V = inputs.spd_householder_device(q.n, q.kappa, q.seed % (2 ** 31),
-                                                     device=device)
-        out.append(Request(rid=i, arrival_s=q.arrival_s, n=q.n,
-                           payload=(A, b, torch.zeros_like(b), lam, V)))
+        r = Request(rid=i, arrival_s=q.arrival_s, n=q.n, kappa=q.kappa, seed=q.seed)
+        if draw is not None and draw is not False:
+            r.host = draw.host_draws(r)
+        out.append(r)
     return out

@@ -24,8 +24,10 @@ def torch():
 def test_serving_short_trace(torch):
     trace = inputs.serving_trace(2000.0, 0.12, seed=7)
     reqs = make_requests(trace)
-    torch.cuda.synchronize()
     ex = GpuExecutor(workers=4, precision=nsr.PREC_MIXED_BF16)
+    ex.keep_results = True                 # keep each request's system to check it
+    choices = ex.prepare([r.n for r in reqs])
+    assert choices and all(c["program"] for c in choices)
     srv = Server(ex, budget_bytes=8 << 30, workers=4)
     st = srv.run(reqs)
     torch.cuda.synchronize()
