@@ -96,8 +96,9 @@ def test_batch_inf_half_scaling(torch):
 
 def test_batch_timeline(torch):
     """Per-system device timeline: every float32 attempt has begin <= end,
-    escalated systems (and only they) have a float64 attempt, and the float64
-    pass starts after every float32 attempt ended (separate kernels)."""
+    escalated systems (and only they) have a float64 attempt, and each float64
+    re-solve starts after its own float32 attempt ended (re-solves run beside
+    the float32 pass, not after it)."""
     rng = np.random.default_rng(13)
     systems = [inputs.harmonic_gram(int(m), seed=int(rng.integers(1 << 30)))
                for m in rng.integers(8, 129, size=40)]
@@ -114,7 +115,7 @@ def test_batch_timeline(torch):
     assert np.all(np.isnan(times[~esc, 2])) and np.all(wg[~esc, 1] == -1)
     if esc.any():
         assert np.all(times[esc, 3] >= times[esc, 2])
-        assert np.min(times[esc, 2]) >= np.max(times[:, 1])
+        assert np.all(times[esc, 2] >= times[esc, 1])
     with pytest.raises(nsr.NSError):
         B.timeline(t + 1)
 
@@ -316,3 +317,48 @@ def test_packed_submission_matches_lists(torch):
             for f in ("status", "precision", "ns_steps", "refine_steps", "alpha", "rel_resid",
                       "mmm"):
                 assert cols[f][i] == getattr(r, f), (f, i)
+
+
+def harmonic_members(seed, count, idx):
+    """Members idx of inputs.harmonic_batch(count, seed), made alone."""
+    ss = np.random.SeedSequence(seed)
+    ms = np.random.default_rng(ss).integers(8, 129, size=count)
+    children = ss.spawn(count)
+    return [inputs.harmonic_gram(int(ms[i]), int(children[i].generate_state(1)[0])) for i in idx]
+
+
+@pytest.mark.skip(reason="the float64 team kernel is switched off: the run that tested the fix "
+                         "of its first stall stalled again (nine team workgroups), cause not found")
+def test_batch_float64_teams(torch):
+    """Ill-conditioned harmonic Gram systems (n = 230..250, kappa 1e8..1e9,
+    from the 2048-system workload) that float32 cannot solve, in a batch with
+    many idle slots: their float64 re-solves run with their products shared
+    among the idle workgroups of the team kernel.  Every system reaches the
+    tolerance, the hard ones in float64, each matches the oracle, and the
+    step counts equal those of the same systems solved by the float64-only
+    batch (whose products run on one workgroup each) within one step."""
+    hard = [1654, 1582, 1425, 4, 526]
+    systems = harmonic_members(4, 2048, hard) + [inputs.harmonic_gram(m, seed=70 + m)
+                                                 for m in (9, 20, 33)]
+    for s in systems[:5]:
+        assert s.n >= 200
+    As, bs, ths = upload(torch, systems)
+    B = nsr.Batch(max_n=256, max_count=16, slots=64)
+    B.set_launch(8, 0)
+    t = B.submit(As, bs, ths, order=4, resid_tol=1e-10, refine_max=100)
+    reps = B.poll(t, wait=True)
+    times, wg = B.timeline(t)
+    assert all(r.status == nsr.NS_OK for r in reps), [(r.status, r.precision) for r in reps]
+    assert all(reps[i].precision == nsr.PREC_FP64 for i in range(5))
+    assert np.all(times[:5, 2] >= times[:5, 1])
+    check_against_oracle(systems, ths, reps, 4, 1e-10)
+    B64 = nsr.Batch(max_n=256, max_count=16, slots=64, precision=nsr.PREC_FP64)
+    ths64 = [torch.zeros_like(b) for b in bs]
+    reps64 = B64.poll(B64.submit(As, bs, ths64, order=4, resid_tol=1e-10, refine_max=100),
+                      wait=True)
+    for i in range(5):
+        assert abs(reps[i].ns_steps - reps64[i].ns_steps) <= 1, (i, reps[i].ns_steps,
+                                                                  reps64[i].ns_steps)
+        d = float(torch.linalg.norm(ths[i] - ths64[i]) / torch.linalg.norm(ths64[i]))
+        lam = np.linalg.eigvalsh(systems[i].A)
+        assert d <= 100 * lam.max() / lam.min() * U64, (i, d)
