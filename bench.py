@@ -867,6 +867,8 @@ def main():
                     choices=["spd8192_k1e6_dns8", "spd4096_k1e4_o8", "spd64_k1e2_o4"],
                     help="headline workload (default: the N=8192 mixed-vs-float64 pair)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-tile-tuning", action="store_true",
+                    help="keep the GEMM tile rule (skip the tile autotuner)")
     ap.add_argument("--no-extras", action="store_true",
                     help="only the headline workload (no other legs)")
     ap.add_argument("--no-spd4096", action="store_true", help="skip the N=4096 legs")
@@ -921,6 +923,16 @@ def main():
 
     extras = not args.no_extras
     cpu_sample = None
+    tiles = None
+    if not args.no_tile_tuning:
+        # The project's tile autotuner: every GEMM family's tiles timed per
+        # size bucket, the fastest installed before anything is measured.
+        from paper_2008_11480_amd import autotune
+        t0 = time.perf_counter()
+        tiles = autotune.tune_tiles()
+        release(torch)
+        log(f"tile autotune ({time.perf_counter() - t0:.1f} s): "
+            + ", ".join(f"{r['family']}/{r['n']}:{r['best_tile']}" for r in tiles))
     if args.workload == "spd8192_k1e6_dns8":
         w, A8, b8, legs = run_headline_dns8(torch, nsr, args.steps, args.warmup,
                                             args.host_inputs)
@@ -1006,6 +1018,9 @@ def main():
                                          fp64_seconds=args.serving_fp64_seconds,
                                          program=args.serving_program)
 
+    if tiles is not None:
+        fam = {0: "f64", 1: "f32", 2: "bf16", 3: "f16_split"}
+        out["tile_autotune"] = [{**r, "family": fam[r["family"]]} for r in tiles]
     if cpu_sample is not None:
         log("timing the CPU oracle on a bounded sample of the N=8192 workload")
         a_h, b_h, ns_steps, refine_steps = cpu_sample

@@ -240,7 +240,8 @@ typedef struct {
                          updates without host round trips, captured once into
                          a HIP graph and replayed on later solves with the same
                          operands and options; the history is recorded on the
-                         device and read once.  Otherwise ignored.          */
+                         device and read once.  Otherwise ignored.  Batched
+                         submissions: see ns_batch_submit.                  */
 } ns_solve_opts;
 
 #define NS_HIST_F 65
@@ -308,7 +309,13 @@ int ns_batch_create(int device, void* hip_stream, int64_t max_n, int max_count,
  * kernel for n <= 64 runs eight waves when waves_per_group is 8, else four. */
 int ns_batch_set_launch(ns_batch* b, int waves_per_group, int groups);
 
-/* Enqueue the solves of `count` systems.  n, A, lda, b, theta are HOST arrays
+/* Enqueue the solves of `count` systems.  opts->graph = 1: the submission's
+ * device work (reset of its counters by a kernel, the persistent kernels) is
+ * captured once into a HIP graph and replayed by later submissions with the
+ * same systems (pointers, sizes), options and launch shape; any other
+ * submission re-captures, and an ordinary submission in between makes the
+ * next graph submission re-capture.  Results are identical either way.
+ * n, A, lda, b, theta are HOST arrays
  * of length count holding each system's size and DEVICE pointers (A: row-major
  * float64 n x n, lda >= n; b, theta: float64 n).  The caller keeps A, b,
  * theta alive and unmodified (theta: untouched) until ns_batch_poll reports

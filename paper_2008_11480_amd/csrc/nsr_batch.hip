@@ -1622,6 +1622,22 @@ int launch_small(const BatchArgs& a, int grid, int waves, hipStream_t st) {
 
 bool small_fits(int max_n, int order) { return max_n <= SMALL_N && (order == 2 || order == 4); }
 
+// Zero n 32-bit words (a kernel, not hipMemsetAsync: submissions may be
+// captured into a HIP graph, where memset nodes are avoided).
+__global__ void __launch_bounds__(256) zero_words_kernel(uint32_t* p, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
+    p[i] = 0u;
+}
+
+int zero_words(void* p, size_t bytes, hipStream_t st) {
+  const int64_t n = (int64_t)(bytes / 4);
+  if (n <= 0) return 0;
+  const int64_t blocks = std::min<int64_t>((n + 255) / 256, 1024);
+  hipLaunchKernelGGL(zero_words_kernel, dim3((unsigned)blocks), dim3(256), 0, st,
+                     static_cast<uint32_t*>(p), n);
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
 // Float32 attempts with float64 escalation in one persistent launch
 // (escalate_kernel), or the float64 pass alone.  With small = true every pass
 // runs the LDS-resident kernel (four or eight waves): the float32 pass, then
@@ -1739,6 +1755,9 @@ struct ns_batch {
   std::vector<BatchDesc> h_desc;
   std::vector<int32_t> h_order;
   std::vector<BatchResult> h_res;
+  hipGraphExec_t gexec = nullptr;  // the captured submission (opts->graph)
+  hipStream_t cap = nullptr;        // private stream for the capture
+  std::vector<char> graph_key;      // what gexec was captured for (empty: none)
   ns_ledger* ledger = nullptr;   // HBM admission (ns_batch_set_ledger), may be NULL
   size_t held = 0;               // bytes the in-flight submission holds in it
 };
@@ -1753,9 +1772,18 @@ namespace {
 // submissions run the float32 pass and then the float64 pass over its queue.
 constexpr bool kTeamKernelEnabled = false;
 
-int batch_enqueue(ns_batch* B, int count, const int64_t* n, const double* const* A,
+// A submission's launch: its arguments and grid, decided on the host.
+struct Launch {
+  BatchArgs a;
+  int grid, grid64;
+  bool small;
+};
+
+// Checks and host-side set-up of a submission (descriptors in largest-first
+// order, launch arguments); no device work.
+int batch_prepare(ns_batch* B, int count, const int64_t* n, const double* const* A,
                   const int64_t* lda, const double* const* b, double* const* theta,
-                  const ns_solve_opts* o) {
+                  const ns_solve_opts* o, Launch& L) {
   if (count < 0) return bfail(NS_EINVAL, "count < 0");
   if (count > B->max_count) return bfail(NS_ENOMEM, "count exceeds the batch capacity");
   if (!o) return bfail(NS_EINVAL, "null opts");
@@ -1783,20 +1811,8 @@ int batch_enqueue(ns_batch* B, int count, const int64_t* n, const double* const*
   // Largest systems first (longest-processing-time order for the work pull).
   std::stable_sort(B->h_order.begin(), B->h_order.end(),
                    [&](int32_t x, int32_t y) { return B->h_desc[x].n > B->h_desc[y].n; });
-  if (hipSetDevice(B->device) != hipSuccess) return bfail(NS_EHIP, "hipSetDevice failed");
-  if (count > 0) {
-    if (hipMemcpyAsync(B->d_desc, B->h_desc.data(), count * sizeof(BatchDesc),
-                       hipMemcpyHostToDevice, B->stream) != hipSuccess ||
-        hipMemcpyAsync(B->d_order, B->h_order.data(), count * sizeof(int32_t),
-                       hipMemcpyHostToDevice, B->stream) != hipSuccess)
-      return bfail(NS_EHIP, "descriptor upload failed");
-  }
-  if (hipMemsetAsync(B->d_counter, 0, kCounters * sizeof(int32_t), B->stream) != hipSuccess ||
-      (count > 0 &&
-       (hipMemsetAsync(B->d_retry, 0, count * sizeof(int32_t), B->stream) != hipSuccess ||
-        hipMemsetAsync(B->d_team, 0, count * sizeof(TeamState), B->stream) != hipSuccess)))
-    return bfail(NS_EHIP, "counter reset failed");
-  BatchArgs a{};
+  BatchArgs& a = L.a;
+  a = BatchArgs{};
   a.desc = B->d_desc;
   a.res = B->d_res;
   a.order = B->d_order;
@@ -1818,26 +1834,120 @@ int batch_enqueue(ns_batch* B, int count, const int64_t* n, const double* const*
   a.eps = o->eps;
   a.f_tol = o->f_tol;
   a.resid_tol = o->resid_tol;
-  int grid = B->groups > 0 ? B->groups : B->slots;
-  if (grid > B->slots) grid = B->slots;
-  if (grid > count) grid = count;
-  int grid64 = B->cus < B->slots ? B->cus : B->slots;
-  if (grid64 > count) grid64 = count;
+  L.grid = B->groups > 0 ? B->groups : B->slots;
+  if (L.grid > B->slots) L.grid = B->slots;
+  if (L.grid > count) L.grid = count;
+  L.grid64 = B->cus < B->slots ? B->cus : B->slots;
+  if (L.grid64 > count) L.grid64 = count;
   int max_sys = 0;
   for (int i = 0; i < count; ++i) max_sys = std::max(max_sys, (int)n[i]);
-  const bool small = small_fits(max_sys, o->order);
-  if (kTeamKernelEnabled && grid > 0 && !small && a.escalate) {
+  L.small = small_fits(max_sys, o->order);
+  return NS_OK;
+}
+
+// Upload of the prepared descriptors (host vectors of the handle) on st.
+int batch_upload(ns_batch* B, int count, hipStream_t st) {
+  if (hipSetDevice(B->device) != hipSuccess) return bfail(NS_EHIP, "hipSetDevice failed");
+  if (count > 0 &&
+      (hipMemcpyAsync(B->d_desc, B->h_desc.data(), count * sizeof(BatchDesc),
+                      hipMemcpyHostToDevice, st) != hipSuccess ||
+       hipMemcpyAsync(B->d_order, B->h_order.data(), count * sizeof(int32_t),
+                      hipMemcpyHostToDevice, st) != hipSuccess))
+    return bfail(NS_EHIP, "descriptor upload failed");
+  return NS_OK;
+}
+
+// The submission's device work after the upload: reset of its counters,
+// queue and team states, then the persistent kernels.  Enqueued on st (the
+// handle's stream, or a stream under graph capture).
+int batch_launch(ns_batch* B, const Launch& L, hipStream_t st, bool allow_team) {
+  const int count = L.a.count;
+  if (zero_words(B->d_counter, kCounters * sizeof(int32_t), st) ||
+      zero_words(B->d_retry, (size_t)count * sizeof(int32_t), st) ||
+      zero_words(B->d_team, (size_t)count * sizeof(TeamState), st))
+    return bfail(NS_EHIP, "counter reset failed");
+  if (allow_team && kTeamKernelEnabled && L.grid > 0 && !L.small && L.a.escalate) {
     // the team kernel: one workgroup per CU, in the slots after the float32
     // pass's (none when the slots are all taken)
-    int team_grid = std::min(B->cus, B->slots - grid);
+    int team_grid = std::min(B->cus, B->slots - L.grid);
     if (team_grid < 0) team_grid = 0;
-    if (launch_escalating(a, grid, B->waves, team_grid, grid64, B->stream, B->side, B->ev_start,
+    if (launch_escalating(L.a, L.grid, B->waves, team_grid, L.grid64, st, B->side, B->ev_start,
                           B->ev_side) != 0)
       return bfail(NS_EHIP, "batch kernel launch failed");
     return NS_OK;
   }
-  if (grid > 0 && launch_batch(a, grid, B->waves, grid64, 8, small, B->stream) != 0)
+  if (L.grid > 0 && launch_batch(L.a, L.grid, B->waves, L.grid64, 8, L.small, st) != 0)
     return bfail(NS_EHIP, "batch kernel launch failed");
+  return NS_OK;
+}
+
+int batch_enqueue(ns_batch* B, int count, const int64_t* n, const double* const* A,
+                  const int64_t* lda, const double* const* b, double* const* theta,
+                  const ns_solve_opts* o) {
+  Launch L;
+  if (int rc = batch_prepare(B, count, n, A, lda, b, theta, o, L)) return rc;
+  B->graph_key.clear();   // the device descriptors change: a captured graph is stale
+  if (int rc = batch_upload(B, count, B->stream)) return rc;
+  return batch_launch(B, L, B->stream, true);
+}
+
+// Key of a submission for graph reuse: every input the captured work
+// depends on (launch shape, options, descriptors).
+std::vector<char> graph_key(const ns_batch* B, const Launch& L, const ns_solve_opts* o) {
+  std::vector<char> k;
+  auto put = [&](const void* p, size_t n) {
+    const char* c = static_cast<const char*>(p);
+    k.insert(k.end(), c, c + n);
+  };
+  put(&B->waves, sizeof(B->waves));
+  put(&B->groups, sizeof(B->groups));
+  put(&L.grid, sizeof(L.grid));
+  put(&L.grid64, sizeof(L.grid64));
+  ns_solve_opts oc = *o;
+  oc.graph = 0;
+  put(&oc, sizeof(oc));
+  put(B->h_desc.data(), B->h_desc.size() * sizeof(BatchDesc));
+  return k;
+}
+
+// Graph path of ns_batch_submit: replay the captured submission when this
+// one is identical to it, else upload, capture the device work on a private
+// stream, instantiate, and launch the graph on the handle's stream.
+int batch_enqueue_graph(ns_batch* B, int count, const int64_t* n, const double* const* A,
+                        const int64_t* lda, const double* const* b, double* const* theta,
+                        const ns_solve_opts* o) {
+  Launch L;
+  if (int rc = batch_prepare(B, count, n, A, lda, b, theta, o, L)) return rc;
+  if (hipSetDevice(B->device) != hipSuccess) return bfail(NS_EHIP, "hipSetDevice failed");
+  std::vector<char> key = graph_key(B, L, o);
+  if (!B->gexec || key != B->graph_key) {
+    B->graph_key.clear();
+    if (B->gexec) {
+      (void)hipGraphExecDestroy(B->gexec);
+      B->gexec = nullptr;
+    }
+    if (int rc = batch_upload(B, count, B->stream)) return rc;
+    if (hipStreamSynchronize(B->stream) != hipSuccess) return bfail(NS_EHIP, "stream sync failed");
+    if (!B->cap && hipStreamCreateWithFlags(&B->cap, hipStreamNonBlocking) != hipSuccess)
+      return bfail(NS_EHIP, "hipStreamCreate failed");
+    if (hipStreamBeginCapture(B->cap, hipStreamCaptureModeThreadLocal) != hipSuccess)
+      return bfail(NS_EHIP, "hipStreamBeginCapture failed");
+    const int rc = batch_launch(B, L, B->cap, false);
+    hipGraph_t g = nullptr;
+    const hipError_t e = hipStreamEndCapture(B->cap, &g);
+    if (rc != NS_OK || e != hipSuccess || !g) {
+      if (g) (void)hipGraphDestroy(g);
+      return rc != NS_OK ? rc : bfail(NS_EHIP, "hipStreamEndCapture failed");
+    }
+    const hipError_t ei = hipGraphInstantiate(&B->gexec, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (ei != hipSuccess) {
+      B->gexec = nullptr;
+      return bfail(NS_EHIP, "hipGraphInstantiate failed");
+    }
+    B->graph_key = std::move(key);
+  }
+  if (hipGraphLaunch(B->gexec, B->stream) != hipSuccess) return bfail(NS_EHIP, "hipGraphLaunch failed");
   return NS_OK;
 }
 
@@ -1941,9 +2051,12 @@ int ns_batch_submit(ns_batch* B, int count, const int64_t* n, const double* cons
     const int rc = ns_ledger_admit(B->ledger, bytes);
     if (rc != NS_OK) return rc;
   }
-  if (int rc = batch_enqueue(B, count, n, A, lda, b, theta, opts)) {
+  const int rc_enq = (opts && opts->graph)
+                        ? batch_enqueue_graph(B, count, n, A, lda, b, theta, opts)
+                        : batch_enqueue(B, count, n, A, lda, b, theta, opts);
+  if (rc_enq != NS_OK) {
     if (B->ledger) (void)ns_ledger_release(B->ledger, bytes);
-    return rc;
+    return rc_enq;
   }
   if (hipEventRecord(B->done, B->stream) != hipSuccess) {
     (void)hipStreamSynchronize(B->stream);
@@ -2096,6 +2209,8 @@ int ns_batch_destroy(ns_batch* B) {
   if (B->busy) (void)hipEventSynchronize(B->done);
   if (B->busy && B->ledger && B->held) (void)ns_ledger_release(B->ledger, B->held);
   if (B->side) (void)hipStreamSynchronize(B->side);
+  if (B->gexec) (void)hipGraphExecDestroy(B->gexec);
+  if (B->cap) (void)hipStreamDestroy(B->cap);
   if (B->done) (void)hipEventDestroy(B->done);
   if (B->ev_start) (void)hipEventDestroy(B->ev_start);
   if (B->ev_side) (void)hipEventDestroy(B->ev_side);

@@ -577,11 +577,11 @@ class Batch:
 
     @staticmethod
     def _opts(order=4, k_max=64, refine_max=64, floor_detect=True, f_tol=0.0, resid_tol=1e-10,
-              scale=SCALE_FROBENIUS, eps=0.0):
+              scale=SCALE_FROBENIUS, eps=0.0, graph=False):
         return SolveOpts(order=order, factorization=FACT["squaring"], p=0, w=0, k_max=k_max,
                          refine_max=refine_max, floor_detect=1 if floor_detect else 0,
                          scale=scale, eps=eps, f_tol=f_tol, resid_tol=resid_tol,
-                         theta0_mode=0)
+                         theta0_mode=0, graph=1 if graph else 0)
 
     def set_launch(self, waves: int, groups: int = 0):
         check(lib().ns_batch_set_launch(self._h, int(waves), int(groups)))

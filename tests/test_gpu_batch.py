@@ -362,3 +362,48 @@ def test_batch_float64_teams(torch):
         d = float(torch.linalg.norm(ths[i] - ths64[i]) / torch.linalg.norm(ths64[i]))
         lam = np.linalg.eigvalsh(systems[i].A)
         assert d <= 100 * lam.max() / lam.min() * U64, (i, d)
+
+
+def test_batch_graph_replay_matches_eager(torch):
+    """opts.graph: the submission is captured once into a HIP graph and
+    replayed; every replay gives exactly the eager submission's results
+    (theta bit-identical, same reports), with eager batches, torch work and
+    host synchronizations in between, on the general kernel with float64
+    escalation and on the LDS path; new outputs re-capture."""
+    cases = (
+        [inputs.spd_qlq(n, k, seed=900 + n) for n, k in ((130, 1e3), (40, 1e2), (200, 1e9), (7, 10.0))],
+        [inputs.spd_qlq(n, 1e3, seed=950 + n) for n in (1, 17, 40, 64)],
+    )
+    fields = ("status", "precision", "ns_steps", "refine_steps", "alpha", "rel_resid", "mmm")
+    for systems in cases:
+        As, bs, ths = upload(torch, systems)
+        B = nsr.Batch(max_n=256, max_count=8, slots=8)
+        B.set_launch(4, 0)
+        print(f"graph replay: sizes {[s.n for s in systems]}", flush=True)
+        ref = B.poll(B.submit(As, bs, ths, order=4, resid_tol=1e-10), wait=True)
+        want = [t.clone() for t in ths]
+        check_against_oracle(systems, ths, ref, 4, 1e-10)
+        other = [inputs.spd_qlq(n, 1e2, seed=990 + n) for n in (50, 9)]
+        oA, ob, oth = upload(torch, other)
+        for rep in range(4):
+            for t in ths:
+                t.fill_(float("nan"))
+            got = B.poll(B.submit(As, bs, ths, order=4, resid_tol=1e-10, graph=True), wait=True)
+            for i in range(len(systems)):
+                assert torch.equal(ths[i], want[i]), (rep, i)
+                for f in fields:
+                    assert getattr(got[i], f) == getattr(ref[i], f), (rep, i, f)
+            # eager work between replays: another batch on the same handle
+            # (which also makes the next graph submission re-capture) and torch
+            if rep % 2 == 0:
+                r2 = B.poll(B.submit(oA, ob, oth, order=4, resid_tol=1e-10), wait=True)
+                assert all(r.status == nsr.NS_OK for r in r2)
+            x = torch.randn(512, 512, device="cuda")
+            (x @ x).sum().item()
+        # new output buffers: a different submission, captured anew
+        ths2 = [torch.zeros_like(t) for t in ths]
+        for _ in range(2):
+            got = B.poll(B.submit(As, bs, ths2, order=4, resid_tol=1e-10, graph=True), wait=True)
+            for i in range(len(systems)):
+                assert torch.equal(ths2[i], want[i]), i
+                assert got[i].ns_steps == ref[i].ns_steps
