@@ -221,35 +221,52 @@ def _family_gemm(family: int, n: int, torch, nsr):
 
 
 def tune_tiles(families=None, sizes=(256, 512, 1024, 2048, 4096, 8192), reps: int = 3,
-               install: bool = True) -> list[dict]:
-    """Time every tile of each GEMM family at each size (n x n x n, one
-    warm-up then ``reps`` timed launches between HIP events on the current
-    stream) and, with ``install``, set the fastest for that size's bucket
-    (``ns_tile_set``).  Returns one record per (family, size) with every
-    candidate's time and the rule's own choice's time."""
+               trials: int = 3, min_ms: float = 4.0, install: bool = True) -> list[dict]:
+    """Time every tile of each GEMM family at each size (n x n x n) and, with
+    ``install``, set the fastest for that size's bucket (``ns_tile_set``).
+
+    Each candidate (the rule's own choice, tile 0, and every explicit tile)
+    is warmed up once; then ``trials`` rounds go over the candidates in turn,
+    each timing a run of at least ``reps`` launches and ``min_ms``
+    milliseconds between HIP events on the current stream, and a candidate's
+    time is its fastest round (interleaving the rounds keeps clock and
+    cache drift from favouring the candidates timed last).  Returns one
+    record per (family, size) with every candidate's time and the rule's."""
     import torch
     from . import nsr
     families = tuple(nsr.TILE_OPTIONS) if families is None else tuple(families)
     out = []
+
+    def timed(run, k):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(k):
+            run()
+        e1.record()
+        e1.synchronize()
+        return e0.elapsed_time(e1) / k
+
     for fam in families:
         for n in sizes:
             b = int(math.ceil(math.log2(n)))
             run = _family_gemm(fam, n, torch, nsr)
-            times = {}
-            for tile in (0,) + nsr.TILE_OPTIONS[fam]:
+            cands = (0,) + tuple(nsr.TILE_OPTIONS[fam])
+            k = max(1, int(reps))
+            for tile in cands:
                 nsr.tile_set(fam, b, tile)
                 run()
-                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-                e0.record()
-                for _ in range(reps):
-                    run()
-                e1.record()
-                e1.synchronize()
-                times[tile] = e0.elapsed_time(e1) / reps
+                est = timed(run, 1)
+                k = max(k, min(200, int(math.ceil(min_ms / max(est, 1e-3)))))
+            times = {t: float("inf") for t in cands}
+            for _ in range(max(1, int(trials))):
+                for tile in cands:
+                    nsr.tile_set(fam, b, tile)
+                    times[tile] = min(times[tile], timed(run, k))
             best = min((t for t in times if t), key=lambda t: times[t])
             nsr.tile_set(fam, b, best if install else 0)
             out.append({"family": fam, "n": n, "log2_dim": b, "best_tile": best,
-                        "ms": {str(k): v for k, v in times.items()},
+                        "launches_per_round": k,
+                        "ms": {str(t): v for t, v in times.items()},
                         "speedup_vs_rule": times[0] / times[best]})
             del run
         torch.cuda.empty_cache()
