@@ -636,6 +636,19 @@ def run_batch(torch, nsr, reps_timed):
     rel_inf = rel_resid(P)
     log(f"batch inf_half scaling: {mk_inf * 1e3:.1f} ms, ns_steps p50 "
         f"{np.median(steps_inf):.0f} (frobenius {np.median(steps):.0f})")
+    # Variant: S = diag(A) (Section 2, for diagonally dominant matrices);
+    # harmonic Gram matrices mostly violate 2S - A > 0, so most diverge.
+    opts_diag = dict(opts, scale=nsr.SCALE_DIAG)
+    mk_dg, _, rep_dg, _ = timed(P, opts_diag)
+    ok_dg = rep_dg["status"] == nsr.NS_OK
+    div_dg = rep_dg["status"] == nsr.NS_EDIVERGED
+    log(f"batch diag(A) scaling: {mk_dg * 1e3:.1f} ms, {int(ok_dg.sum())} converged, "
+        f"{int(div_dg.sum())} diverged")
+    # The same submission captured into a HIP graph and replayed.
+    mk_g, mk_g_dev, rep_g, _ = timed(P, dict(opts, graph=True))
+    same_g = bool(np.array_equal(rep_g["ns_steps"], rep["ns_steps"]) and
+                  np.array_equal(rep_g["rel_resid"], rep["rel_resid"]))
+    log(f"batch graph replay: {mk_g * 1e3:.1f} ms (reports identical: {same_g})")
     # The same batch in plain float64 (every system solved in float64 from
     # the start), with its own autotuned launch: the mixed batch's speedup.
     B64 = nsr.Batch(max_n=256, max_count=count,
@@ -660,6 +673,16 @@ def run_batch(torch, nsr, reps_timed):
             "ns_steps_p50": float(np.median(steps_inf)), "ns_steps_max": int(steps_inf.max()),
             "ns_steps_total": int(steps_inf.sum()), "ns_steps_total_frobenius": int(steps.sum()),
         },
+        "diag_variant": {
+            "makespan_ms": mk_dg * 1e3, "ok": int(ok_dg.sum()), "diverged": int(div_dg.sum()),
+            "ns_steps_p50_ok": float(np.median(rep_dg["ns_steps"][ok_dg])) if ok_dg.any() else None,
+            "ns_steps_p50_ok_frobenius": float(np.median(steps[ok_dg])) if ok_dg.any() else None,
+            "note": "S = diag(A) needs 2S - A > 0 (Section 2); harmonic Gram matrices are "
+                    "not diagonally dominant and their diagonals are nearly equal, so the "
+                    "scaling neither converges for most nor changes kappa",
+        },
+        "graph_replay": {"makespan_ms": mk_g * 1e3, "device_ms": mk_g_dev * 1e3,
+                         "reports_identical": same_g},
         "fp64_only": {
             "makespan_ms": mk64 * 1e3, "device_ms": mk64_dev * 1e3, "solves_per_s": count / mk64,
             "launch": {"waves_per_group": w64, "groups": g64}, "ok": int(ok64.sum()),

@@ -322,8 +322,10 @@ int ns_batch_set_launch(ns_batch* b, int waves_per_group, int groups);
  * completion.  One submission may be in flight per handle.  Errors:
  * NS_EBUSY (previous ticket not polled to completion), NS_ENOMEM (count >
  * max_count or a system larger than max_n: the admission check), NS_EINVAL
- * (options other than the squaring form of order 2^s, the Frobenius or
- * inf / 2 scale, theta0_mode 0). */
+ * (options other than the squaring form of order 2^s, theta0_mode 0; an
+ * unknown scale).  Scales: Frobenius, inf / 2, or S = diag(A) (Section 2;
+ * a system whose 2S - A is not positive definite diverges and is reported
+ * NS_EDIVERGED, its report's alpha = max_i A_ii). */
 int ns_batch_submit(ns_batch* b, int count, const int64_t* n, const double* const* A,
                     const int64_t* lda, const double* const* b_vec,
                     double* const* theta, const ns_solve_opts* opts, uint64_t* ticket);

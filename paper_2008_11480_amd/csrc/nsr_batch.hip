@@ -425,8 +425,8 @@ __device__ double wg_gemm(int n, const T* X, int ldx, const double* XA, int64_t 
 constexpr int EW = 8;
 
 template <typename T, int NW>
-__device__ double wg_init_resid(int n, const double* A, int64_t lda, double alpha, T* F, int ldw,
-                                double* red) {
+__device__ double wg_init_resid(int n, const double* A, int64_t lda, double alpha,
+                                const double* sd, T* F, int ldw, double* red) {
   constexpr int NTH = NW * 64;
   const int nn = n * n;
   double ss = 0.0;
@@ -442,7 +442,7 @@ __device__ double wg_init_resid(int n, const double* A, int64_t lda, double alph
       const int i = i0 + u * NTH;
       if (i < nn) {
         const int row = i / n, col = i % n;
-        double v = -a[u] / alpha;
+        double v = -a[u] / (sd ? sd[col] : alpha);   // F_0 = I - A S^-1
         if (row == col) v += 1.0;
         const T t = (T)v;
         F[row * ldw + col] = t;
@@ -455,7 +455,8 @@ __device__ double wg_init_resid(int n, const double* A, int64_t lda, double alph
 }
 
 template <typename T, int NW>
-__device__ void wg_scaled_identity_plus(int n, const T* C, double alpha, T* G, int ldw) {
+__device__ void wg_scaled_identity_plus(int n, const T* C, double alpha, const double* sd, T* G,
+                                        int ldw) {
   constexpr int NTH = NW * 64;
   const int nn = n * n;
   for (int i0 = threadIdx.x; i0 < nn; i0 += NTH * EW) {
@@ -472,7 +473,7 @@ __device__ void wg_scaled_identity_plus(int n, const T* C, double alpha, T* G, i
         const int row = i / n, col = i % n;
         double v = (double)c[u];
         if (row == col) v += 1.0;
-        G[row * ldw + col] = (T)(v / alpha);
+        G[row * ldw + col] = (T)(v / (sd ? sd[row] : alpha));   // G_1 = S^-1 (I + C)
       }
     }
   }
@@ -596,6 +597,7 @@ struct SlotMats {
   void* C[2];
   float* A32;
   double* r;
+  double* sd;  // S = diag(A) (NS_SCALE_DIAG), n values
   void* lds;   // Stage<T, NW>::BYTES of LDS for the GEMM stages
 };
 
@@ -607,11 +609,24 @@ struct Ctl {
   int ns_steps, ns_stop, refine_steps, refine_stop, n_fnorm, precision;
 };
 
-// Scalar preconditioner S = alpha I (Section 2): alpha = ||A||_F, or the
-// maximum row sum of |A| over 2 plus eps (uniform result).
+// Preconditioner S (Section 2): S = alpha I with alpha = ||A||_F, or the
+// maximum row sum of |A| over 2 plus eps; or S = diag(A), written to sd,
+// reporting alpha = max_i A_ii (-1 when a diagonal entry is not finite and
+// positive).  Uniform result.
 template <int NW>
-__device__ __forceinline__ double wg_alpha(const BatchArgs& P, const BatchDesc& d, double* red) {
+__device__ __forceinline__ double wg_alpha(const BatchArgs& P, const BatchDesc& d, double* red,
+                                           double* sd) {
   const int n = d.n;
+  if (P.scale == NS_SCALE_DIAG) {
+    double mx = 0.0;
+    for (int i = threadIdx.x; i < n; i += NW * 64) {
+      const double a = d.A[(int64_t)i * d.lda + i];
+      sd[i] = a;
+      mx = (a > 0.0 && isfinite(a)) ? fmax(mx, a) : INFINITY;
+    }
+    const double m = block_max_all<NW>(mx, red);   // its barriers publish sd
+    return isfinite(m) ? m : -1.0;
+  }
   if (P.scale == NS_SCALE_INF_HALF) {
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     double mx = 0.0;
@@ -630,13 +645,13 @@ __device__ __forceinline__ double wg_alpha(const BatchArgs& P, const BatchDesc& 
   return sqrt(block_sum_all<NW>(ssa, red));
 }
 
-// theta_0 = b / alpha; returns ||b|| (1 for b = 0), uniform.
+// theta_0 = S^-1 b; returns ||b|| (1 for b = 0), uniform.
 template <int NW>
 __device__ __forceinline__ double wg_theta0(int n, const double* b, double* theta, double alpha,
-                                            double* red) {
+                                            const double* sd, double* red) {
   double bb = 0.0;
   for (int i = threadIdx.x; i < n; i += NW * 64) {
-    theta[i] = b[i] / alpha;
+    theta[i] = b[i] / (sd ? sd[i] : alpha);
     bb += b[i] * b[i];
   }
   const double bnorm = sqrt(block_sum_all<NW>(bb, red));
@@ -881,7 +896,8 @@ __device__ bool wg_solve(const BatchArgs& P, const BatchDesc& d, const SlotMats&
   c.ns_steps = 0;
   c.refine_steps = 0;
   c.rel_resid = NAN;
-  const double alpha = wg_alpha<NW>(P, d, red);
+  const double* sd = (P.scale == NS_SCALE_DIAG) ? sm.sd : nullptr;
+  const double alpha = wg_alpha<NW>(P, d, red, sm.sd);
   c.alpha = alpha;
   if (!(alpha > 0.0) || !isfinite(alpha)) {
     c.ns_stop = NS_STOP_DIVERGED;
@@ -891,9 +907,9 @@ __device__ bool wg_solve(const BatchArgs& P, const BatchDesc& d, const SlotMats&
   if (is32) wg_copy_A<float, NW>(n, d.A, d.lda, sm.A32, ldw);  // for the residual products
   const T* AX = is32 ? (const T*)sm.A32 : nullptr;
   const double* AXd = is32 ? nullptr : d.A;
-  // F_0 = I - A / alpha, theta_0 = b / alpha, ||b||
-  const double f0 = sqrt(wg_init_resid<T, NW>(n, d.A, d.lda, alpha, F, ldw, red));
-  const double bnorm = wg_theta0<NW>(n, d.b, d.theta, alpha, red);
+  // F_0 = I - A S^-1, theta_0 = S^-1 b, ||b||
+  const double f0 = sqrt(wg_init_resid<T, NW>(n, d.A, d.lda, alpha, sd, F, ldw, red));
+  const double bnorm = wg_theta0<NW>(n, d.b, d.theta, alpha, sd, red);
   if (threadIdx.x == 0) hist[0] = f0;
   c.n_fnorm = 1;
   int sexp = 0;
@@ -927,7 +943,7 @@ __device__ bool wg_solve(const BatchArgs& P, const BatchDesc& d, const SlotMats&
     }
     T* Gn = G[gc ^ 1];
     if (implicit) {
-      wg_scaled_identity_plus<T, NW>(n, cc, alpha, Gn, ldw);
+      wg_scaled_identity_plus<T, NW>(n, cc, alpha, sd, Gn, ldw);
     } else {
       wg_mm<T, NW, TEAM>(tc, n, G[gc], ldw, nullptr, 0, cc, ldw, Gn, ldw, G[gc], nullptr, ldw, T(0), T(1),
                      false, red, sm.lds);
@@ -1156,7 +1172,7 @@ __device__ bool small_refine(const BatchArgs& P, int n, const double* A, int lda
 
 // One complete solve of a small system in LDS (same steps, stop rule and
 // escalation as wg_solve; orders 2 and 4).  lds: the four matrices (two G
-// buffers, F, C; SMALL_N x SmallLd elements each).  vec: 3 x SMALL_N float64
+// buffers, F, C; SMALL_N x SmallLd elements each).  vec: 4 x SMALL_N float64
 // of LDS for theta, b and the residual; theta goes to global memory at the
 // end.  A in float64: a64 (float32 solves; copied once, leading dimension
 // SMALL_N) or, in float64 solves, C's buffer, refilled every step once C is
@@ -1174,6 +1190,8 @@ __device__ bool wg_solve_small(const BatchArgs& P, const BatchDesc& d, T* lds, d
   double* th = vec;
   double* bv = vec + SMALL_N;
   double* rv = vec + 2 * SMALL_N;
+  double* sv = vec + 3 * SMALL_N;   // S = diag(A) (NS_SCALE_DIAG)
+  const double* sd = (P.scale == NS_SCALE_DIAG) ? sv : nullptr;
   // float64 A: C's buffer (float64 solves) or a64
   double* A64 = dbl ? reinterpret_cast<double*>(lds) + oC : a64;
   constexpr int ALD = dbl ? LD : SMALL_N;
@@ -1186,7 +1204,7 @@ __device__ bool wg_solve_small(const BatchArgs& P, const BatchDesc& d, T* lds, d
   for (int i = threadIdx.x; i < 4 * MS; i += NW * 64) lds[i] = T(0);
   for (int i = threadIdx.x; i < n; i += NW * 64) bv[i] = d.b[i];
   __syncthreads();
-  const double alpha = wg_alpha<NW>(P, d, red);
+  const double alpha = wg_alpha<NW>(P, d, red, sv);
   c.alpha = alpha;
   if (!(alpha > 0.0) || !isfinite(alpha)) {
     c.ns_stop = NS_STOP_DIVERGED;
@@ -1194,8 +1212,8 @@ __device__ bool wg_solve_small(const BatchArgs& P, const BatchDesc& d, T* lds, d
     return false;
   }
   wg_copy_A<double, NW>(n, d.A, d.lda, A64, ALD);
-  const double f0 = sqrt(wg_init_resid<T, NW>(n, A64, ALD, alpha, lds + oF, LD, red));
-  const double bnorm = wg_theta0<NW>(n, bv, th, alpha, red);
+  const double f0 = sqrt(wg_init_resid<T, NW>(n, A64, ALD, alpha, sd, lds + oF, LD, red));
+  const double bnorm = wg_theta0<NW>(n, bv, th, alpha, sd, red);
   if (threadIdx.x == 0) hist[0] = f0;
   c.n_fnorm = 1;
   const bool order4 = P.ns_order == 4;
@@ -1220,7 +1238,7 @@ __device__ bool wg_solve_small(const BatchArgs& P, const BatchDesc& d, T* lds, d
       occ = oC;
     }
     if (implicit) {
-      wg_scaled_identity_plus<T, NW>(n, lds + occ, alpha, lds + oGn, LD);
+      wg_scaled_identity_plus<T, NW>(n, lds + occ, alpha, sd, lds + oGn, LD);
     } else {
       lds_gemm<T, NW>(lds, np, n, oG[gc], occ, oGn, oG[gc], -1, T(0), T(1), false, red);
       c.mmm += 1;
@@ -1358,13 +1376,14 @@ __device__ __forceinline__ SlotMats slot_mats(const BatchArgs& P, char* slot, vo
     sm.C[1] = d + 6 * nn;
   }
   sm.r = d + 7 * nn;
+  sm.sd = d + 7 * nn + P.ldw;
   sm.lds = lds;
   return sm;
 }
 
 __device__ __forceinline__ double* slot_part(const BatchArgs& P, char* slot) {
   const int64_t nn = (int64_t)P.ldw * P.ldw;
-  return reinterpret_cast<double*>(slot + 8 * nn * sizeof(float)) + 7 * nn + P.ldw;
+  return reinterpret_cast<double*>(slot + 8 * nn * sizeof(float)) + 7 * nn + 2 * P.ldw;
 }
 
 template <typename T, int NW>
@@ -1564,7 +1583,7 @@ __global__ void __launch_bounds__(NW * 64) small_kernel(BatchArgs P) {
   constexpr int LD = SmallLd<T>::value;
   __shared__ double red[NW];
   __shared__ double hist[NS_HIST_F];
-  __shared__ double vec[3 * SMALL_N];
+  __shared__ double vec[4 * SMALL_N];
   __shared__ double part[NW * SMALL_N];
   __shared__ double a64[dbl ? 1 : SMALL_N * SMALL_N];
   __shared__ int s_idx;
@@ -1594,7 +1613,7 @@ __global__ void __launch_bounds__(NW * 64) small_kernel(BatchArgs P) {
 size_t batch_slot_bytes(int ldw) {
   const size_t nn = (size_t)ldw * ldw;
   const size_t blocks = ((size_t)ldw / 32) * ((size_t)ldw / 32);   // team products' blocks
-  size_t b = 8 * nn * sizeof(float) + 7 * nn * sizeof(double) + (size_t)ldw * sizeof(double) +
+  size_t b = 8 * nn * sizeof(float) + 7 * nn * sizeof(double) + 2 * (size_t)ldw * sizeof(double) +
              blocks * sizeof(double);
   return (b + 255) / 256 * 256;
 }
@@ -1793,7 +1812,8 @@ int batch_prepare(ns_batch* B, int count, const int64_t* n, const double* const*
     return bfail(NS_EINVAL, "order must be 2^s >= 2");
   if (o->k_max < 1 || o->k_max > NS_HIST_F - 1) return bfail(NS_EINVAL, "k_max must be in 1..64");
   if (o->refine_max < 0) return bfail(NS_EINVAL, "refine_max < 0");
-  if (o->scale != NS_SCALE_FROBENIUS && o->scale != NS_SCALE_INF_HALF)
+  if (o->scale != NS_SCALE_FROBENIUS && o->scale != NS_SCALE_INF_HALF &&
+      o->scale != NS_SCALE_DIAG)
     return bfail(NS_EINVAL, "unknown scale");
   if (o->scale == NS_SCALE_INF_HALF && !(o->eps >= 0.0)) return bfail(NS_EINVAL, "eps < 0");
   if (o->theta0_mode != 0) return bfail(NS_EINVAL, "batched solves start from theta_0 = b/alpha");

@@ -407,3 +407,63 @@ def test_batch_graph_replay_matches_eager(torch):
             for i in range(len(systems)):
                 assert torch.equal(ths2[i], want[i]), i
                 assert got[i].ns_steps == ref[i].ns_steps
+
+
+@pytest.mark.parametrize("precision", [nsr.PREC_FP32, nsr.PREC_FP64])
+@pytest.mark.parametrize("sizes", [(16, 40, 100, 181, 250), (8, 33, 64)])
+def test_batch_diag_preconditioner(torch, precision, sizes):
+    """S = diag(A) (Section 2) in the batched kernels, general and LDS paths:
+    on diagonally scaled SDD systems (diagonal over three decades) every
+    solve matches the oracle's solve with the same S (alpha = max A_ii,
+    ||F_0|| = ||I - A S^-1||_F, theta within the kappa bound, NS steps within
+    one), and takes fewer steps than with alpha = ||A||_F."""
+    systems = [inputs.spd_jacobi(n, seed=1300 + n) for n in sizes]
+    As, bs, ths = upload(torch, systems)
+    B = nsr.Batch(max_n=256, max_count=8, slots=8, precision=precision)
+    B.set_launch(4, 0)
+    print(f"diag batch: precision {precision} sizes {sizes}", flush=True)
+    reps = B.poll(B.submit(As, bs, ths, order=4, resid_tol=1e-10, scale=nsr.SCALE_DIAG), wait=True)
+    fro = [torch.zeros_like(t) for t in ths]
+    reps_f = B.poll(B.submit(As, bs, fro, order=4, resid_tol=1e-10), wait=True)
+    for i, s in enumerate(systems):
+        rep = reps[i]
+        assert rep.status == nsr.NS_OK, (i, rep)
+        sd = np.diag(s.A)
+        assert rep.alpha == sd.max()
+        f0 = np.linalg.norm(np.eye(s.n) - s.A / sd[None, :])
+        assert rep.fnorm_hist[0] == pytest.approx(f0, rel=1e-5 if rep.precision == 1 else 1e-12)
+        orc = oracle.solve(s.A, s.b, oracle.SolveOptions(order=4, resid_tol=1e-13, scale="diag"))
+        th = ths[i].cpu().numpy()
+        lam = np.linalg.eigvalsh(s.A)
+        kappa = lam.max() / lam.min()
+        assert np.linalg.norm(s.b - s.A @ th) / np.linalg.norm(s.b) <= 1.01e-10
+        fwd = np.linalg.norm(th - orc.theta) / np.linalg.norm(orc.theta)
+        assert fwd <= max(50 * kappa * U64, 10 * 1e-10 * kappa), (i, fwd, kappa)
+        if precision == nsr.PREC_FP64:
+            assert abs(rep.ns_steps - orc.ns_steps) <= 1, (i, rep.ns_steps, orc.ns_steps)
+        else:   # float32 reaches its (higher) floor no later
+            assert rep.ns_steps <= orc.ns_steps + 1, (i, rep.ns_steps, orc.ns_steps)
+        assert rep.ns_steps < reps_f[i].ns_steps, (i, rep.ns_steps, reps_f[i].ns_steps)
+
+
+def test_batch_diag_preconditioner_outside_its_condition(torch):
+    """Harmonic Gram systems are not diagonally dominant: S = diag(A)
+    converges exactly when lambda_max(S^-1 A) < 2 (2S - A positive definite,
+    Section 2); the others are reported diverged, in float32 and after the
+    float64 retry alike."""
+    rng = np.random.default_rng(31)
+    systems = [inputs.harmonic_gram(int(m), seed=int(rng.integers(1 << 30)))
+               for m in rng.integers(8, 65, size=24)]
+    As, bs, ths = upload(torch, systems)
+    B = nsr.Batch(max_n=128, max_count=32, slots=16)
+    reps = B.poll(B.submit(As, bs, ths, order=4, resid_tol=1e-10, scale=nsr.SCALE_DIAG), wait=True)
+    n_conv = 0
+    for i, s in enumerate(systems):
+        d = np.sqrt(np.diag(s.A))
+        lmax = np.linalg.eigvalsh(s.A / d[:, None] / d[None, :]).max()
+        if lmax < 1.99:
+            assert reps[i].status == nsr.NS_OK, (i, lmax, reps[i])
+            n_conv += 1
+        elif lmax > 2.01:
+            assert reps[i].status == nsr.NS_EDIVERGED, (i, lmax, reps[i])
+    assert 0 < n_conv < len(systems)
