@@ -43,6 +43,11 @@
 #ifndef NSR_BATCH_GR
 #define NSR_BATCH_GR 2
 #endif
+// 1: float64 re-solves of escalated systems run in lockstep across the GPU
+// (batches whose largest system has n >= kLsMinN).
+#ifndef NSR_BATCH_LOCKSTEP
+#define NSR_BATCH_LOCKSTEP 1
+#endif
 
 namespace nsr {
 
@@ -72,7 +77,8 @@ struct BatchArgs {
                           // float64-only work counter, [1] float64 queue entries
                           // claimed, [2] queue length, [3] float64 re-solves
                           // finished, [4] float32 attempts finished, [5] error
-                          // flag of a timed-out wait (escalating kernel)
+                          // flag of a timed-out wait (escalating kernel),
+                          // [6] overflow entries claimed, [7] overflow length
   int32_t* retry;         // queue of systems for float64 (count entries; an
                           // entry holds sid + 1 once written, 0 before)
   struct TeamState* team; // per queue entry: its float64 team (escalating kernel)
@@ -89,6 +95,13 @@ struct BatchArgs {
   int32_t scale;           // ns_scale
   int32_t slot_base;       // first slot of this launch (the team kernel's follow
                            // the float32 pass's)
+  int32_t ls_on;           // 1: the queue is re-solved in lockstep; the float64
+                           // pass then takes the overflow queue
+  int32_t ls_slots;        // slots the lockstep re-solve may use (queue entry q
+                           // uses slot q)
+  struct LsState* ls;      // per queue entry: lockstep state
+  int32_t* ovf;            // overflow queue (sid + 1): entries beyond the slots,
+                           // systems still iterating after the enqueued steps
   int64_t ticks_ms;        // device wall-clock ticks per millisecond
   double eps;              // NS_SCALE_INF_HALF: alpha = ||A||_inf / 2 + eps
   double f_tol;
@@ -118,6 +131,14 @@ struct TeamState {
   int32_t done;               // blocks finished in the current phase
   int32_t active;             // 1 while the leader runs
   TeamDesc desc;
+};
+
+// State of one system's lockstep float64 re-solve (see the lockstep kernels).
+struct LsState {
+  double alpha, f0, fprev, fk, bnorm;
+  int64_t mmm;       // float64 products (write_result adds the float32 attempt's)
+  int64_t t_begin;
+  int32_t sid, n, k, ns_stop, active, implicit, gc, f2_ready, probe, pad;
 };
 
 constexpr int kCounters = 8;
@@ -1392,17 +1413,19 @@ __device__ __forceinline__ void batch_loop(const BatchArgs& P, double* red, doub
   constexpr bool dbl = sizeof(T) == 8;
   char* slot = P.slots + (int64_t)(P.slot_base + blockIdx.x) * P.slot_bytes;
   const SlotMats sm = slot_mats<T>(P, slot, stage);
-  // Work list: all systems in P.order, or (float64 after float32) the queue.
+  // Work list: all systems in P.order, or (float64 after float32) the queue
+  // (after a lockstep re-solve: its overflow queue).
   const bool from_queue = dbl && !P.fp64_only;
-  int* counter = P.counter + (from_queue ? 1 : 0);
-  const int total = from_queue ? P.counter[2] : P.count;
+  const bool ovf = from_queue && P.ls_on;
+  int* counter = P.counter + (ovf ? 6 : (from_queue ? 1 : 0));
+  const int total = ovf ? P.counter[7] : (from_queue ? P.counter[2] : P.count);
   for (;;) {
     if (threadIdx.x == 0) s_idx = atomicAdd(counter, 1);
     __syncthreads();
     const int q = s_idx;
     __syncthreads();
     if (q >= total) break;
-    const int sid = from_queue ? P.retry[q] - 1 : P.order[q];
+    const int sid = ovf ? P.ovf[q] - 1 : (from_queue ? P.retry[q] - 1 : P.order[q]);
     const BatchDesc d = P.desc[sid];
     const int64_t t_begin = wall_clock64();
     Ctl c;
@@ -1577,6 +1600,319 @@ team_kernel(BatchArgs P) {
 // Persistent solver for submissions whose systems all fit the LDS path
 // (n <= SMALL_N, order 2 or 4); same work list, queue and reports as
 // batch_kernel.
+
+// ---------------------------------------------------------------------------
+// Lockstep float64 re-solve of the queued systems.  The systems float32
+// could not solve (the queue, whose length only the device knows) are
+// re-solved together, one sub-step of the Newton-Schulz step at a time:
+// each product is one launch whose workgroups share the output blocks of
+// every queued system (wg_gemm_block), and small per-system kernels run the
+// Richardson update, the stop rule and the refinement.  A hard system's
+// float64 chain then runs on many CUs at once instead of one, and no
+// workgroup ever waits for another: kernel boundaries order the sub-steps.
+// The arithmetic is the one-workgroup solve's (same blocks, same K order);
+// the sums of squares add per-block partial sums in block order.  Queue
+// entry q uses slot q; entries beyond the slots, and systems still iterating
+// after the enqueued steps, go to the overflow queue, which the
+// one-workgroup float64 pass re-solves afterwards.
+// ---------------------------------------------------------------------------
+constexpr int kLsNW = 8;      // waves of the lockstep kernels
+constexpr int kLsMinN = 128;  // smallest largest-system size that uses lockstep
+constexpr int kLsSteps = 28;  // Newton-Schulz steps enqueued (capped by k_max)
+enum : int { kLsPow = 0, kLsAsm = 1, kLsGside = 2, kLsResid = 3, kLsProbe = 4 };
+
+__device__ __forceinline__ int ls_count(const BatchArgs& P) {
+  const int q = P.counter[2];
+  return q < P.ls_slots ? q : P.ls_slots;
+}
+__device__ __forceinline__ char* ls_slot(const BatchArgs& P, int q) {
+  return P.slots + (int64_t)q * P.slot_bytes;
+}
+
+// Operands of system s's product in phase ph (sub-step i of the power loop),
+// following wg_solve's buffer rotation: the power loop starts from F each
+// step, so power i goes to Pw[(i - 1) & 1] and assembly i to Cc[(i - 1) & 1].
+struct LsOp {
+  const double* X;
+  const double* XA;
+  const double* Y;
+  double* D;
+  const double* E1;
+  const double* E2;
+  int64_t lda;
+  double diag, scale;
+  bool ss, elem;
+};
+
+__device__ __forceinline__ bool ls_operands(const BatchArgs& P, const LsState& s,
+                                            const SlotMats& sm, int ph, int i, LsOp& o) {
+  if (!s.active) return false;
+  int sexp = 0;
+  while ((1 << sexp) < P.ns_order) ++sexp;
+  // Buffer choices by selects (an indexed local array would live in
+  // private memory).
+  double* const F = (double*)sm.F;
+  auto pw = [&](int j) { return (j & 1) ? (double*)sm.P[1] : (double*)sm.P[0]; };
+  auto cc = [&](int j) { return (j & 1) ? (double*)sm.C[1] : (double*)sm.C[0]; };
+  double* const Gcur = s.gc ? (double*)sm.G[1] : (double*)sm.G[0];
+  double* const Gnew = s.gc ? (double*)sm.G[0] : (double*)sm.G[1];
+  o = LsOp{nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, 0, 0.0, 1.0, false, false};
+  if (ph == kLsPow) {
+    if (i == 1 && s.f2_ready) return false;   // F^2 from the floor probe
+    o.X = o.Y = (i == 1) ? F : pw(i - 2);
+    o.D = pw(i - 1);
+    return true;
+  }
+  if (ph == kLsAsm) {
+    o.X = o.E1 = (i == 1) ? F : cc(i - 2);
+    o.Y = o.E2 = pw(i - 1);
+    o.D = cc(i - 1);
+    return true;
+  }
+  if (ph == kLsGside) {
+    o.Y = sexp > 1 ? cc(sexp - 2) : F;
+    o.D = Gnew;
+    if (s.implicit)
+      o.elem = true;            // G_1 = S^-1 (I + C)
+    else
+      o.X = o.E1 = Gcur;        // G_{k+1} = G_k + G_k C
+    return true;
+  }
+  if (ph == kLsResid) {
+    const BatchDesc d = P.desc[s.sid];
+    o.XA = d.A;
+    o.lda = d.lda;
+    o.Y = Gnew;
+    o.D = F;
+    o.diag = 1.0;
+    o.scale = -1.0;
+    o.ss = true;
+    return true;
+  }
+  if (ph == kLsProbe && s.probe) {
+    o.X = o.Y = F;
+    o.D = pw(0);
+    o.ss = true;
+    return true;
+  }
+  return false;
+}
+
+// Per-block partial sums of D^2 of the residual product (part[0..)) and of
+// the floor probe (part[ls_probe_off..)): blocks of the largest system each.
+__device__ __forceinline__ int ls_probe_off(int ldw) {
+  return ((ldw + Block<kLsNW>::BM - 1) / Block<kLsNW>::BM) *
+         ((ldw + Block<kLsNW>::BN - 1) / Block<kLsNW>::BN);
+}
+
+// Sum of one product's per-block partial sums, in block order.
+__device__ __forceinline__ double ls_sum_parts(const BatchArgs& P, int q, int n, int off) {
+  constexpr int BM = Block<kLsNW>::BM, BN = Block<kLsNW>::BN;
+  const double* part = slot_part(P, ls_slot(P, q)) + off;
+  const int nb = ((n + BM - 1) / BM) * ((n + BN - 1) / BN);
+  double t = 0.0;
+  for (int b = 0; b < nb; ++b) t += part[b];
+  return t;
+}
+
+// The stop rule of wg_solve after the residual product of step k (state s
+// before this step's update): returns the stop (NS_STOP_NONE: none) and
+// whether the floor probe F_k^2 is needed.  A pure function of s and the
+// partial sums, so the probe launch and the control launch agree.
+__device__ __forceinline__ int ls_rule(const BatchArgs& P, const LsState& s, double fk,
+                                       bool& probe) {
+  probe = false;
+  if (!isfinite(fk) || fk > s.f0) return NS_STOP_DIVERGED;
+  if (fk <= P.f_tol) return NS_STOP_F_TOL;
+  if (P.floor_detect && s.fprev < 1.0 && fk > kLawMargin * pow(s.fprev, (double)P.ns_order))
+    return NS_STOP_FLOOR;
+  probe = P.floor_detect && fk > 0.5 * s.fprev;
+  return NS_STOP_NONE;
+}
+
+// One lockstep product for every participating system: items (system,
+// block) strided over the grid.  The residual launch also carries one
+// Richardson-update item per system (it reads the same new G and writes
+// theta, which no product reads).
+__global__ void __launch_bounds__(kLsNW * 64) ls_gemm_kernel(BatchArgs P, int ph, int i) {
+  constexpr int NW = kLsNW, BM = Block<NW>::BM, BN = Block<NW>::BN;
+  __shared__ __attribute__((aligned(16))) char lds[Stage<double, NW>::BYTES];
+  __shared__ double red[NW];
+  const int nsys = ls_count(P);
+  const int bmax = (P.ldw + BM - 1) / BM, bnmax = (P.ldw + BN - 1) / BN, per = bmax * bnmax;
+  const int items = nsys * per + (ph == kLsResid ? nsys : 0);
+  for (int item = blockIdx.x; item < items; item += gridDim.x) {
+    if (item >= nsys * per) {
+      // Richardson update with G_k (eq. redttk1)
+      const int q = item - nsys * per;
+      const LsState s = P.ls[q];
+      if (!s.active) continue;
+      const BatchDesc d = P.desc[s.sid];
+      const SlotMats sm = slot_mats<double>(P, ls_slot(P, q), nullptr);
+      wg_resid<NW, NSR_BATCH_GR>(s.n, d.A, d.lda, d.b, d.theta, sm.r, red);
+      wg_update<double, NW, NSR_BATCH_GR>(s.n, (const double*)(s.gc ? sm.G[0] : sm.G[1]), P.ldw,
+                                          false, s.alpha, sm.r, d.theta);
+      continue;
+    }
+    const int q = item / per, b = item % per;
+    LsState s = P.ls[q];
+    if (ph == kLsProbe && s.active) {
+      bool probe;
+      const double fk = sqrt(ls_sum_parts(P, q, s.n, 0));
+      const int stop = ls_rule(P, s, fk, probe);
+      s.probe = (stop == NS_STOP_NONE && probe) ? 1 : 0;
+    }
+    char* slot = ls_slot(P, q);
+    const SlotMats sm = slot_mats<double>(P, slot, lds);
+    LsOp o;
+    if (!ls_operands(P, s, sm, ph, i, o)) continue;
+    const int n = s.n, bi = b / bnmax, bj = b % bnmax;
+    if (bi * BM >= n || bj * BN >= n) continue;
+    const int blk = bi * ((n + BN - 1) / BN) + bj;
+    if (o.elem) {
+      // G_1 = S^-1 (I + C) over the block
+      const double* sd = (P.scale == NS_SCALE_DIAG) ? sm.sd : nullptr;
+      for (int e = threadIdx.x; e < BM * BN; e += NW * 64) {
+        const int row = bi * BM + e / BN, col = bj * BN + e % BN;
+        if (row < n && col < n) {
+          double v = o.Y[row * P.ldw + col];
+          if (row == col) v += 1.0;
+          o.D[row * P.ldw + col] = v / (sd ? sd[row] : s.alpha);
+        }
+      }
+      continue;
+    }
+    double ss = wg_gemm_block<double, NW>(blk, n, o.X, P.ldw, o.XA, o.lda, o.Y, P.ldw, o.D, P.ldw,
+                                          o.E1, o.E2, P.ldw, o.diag, o.scale, lds);
+    if (o.ss) {
+      ss = block_sum_all<NW>(ss, red);
+      if (threadIdx.x == 0)
+        slot_part(P, slot)[(ph == kLsProbe ? ls_probe_off(P.ldw) : 0) + blk] = ss;
+    }
+  }
+}
+
+// Start of each queued system's float64 solve (F_0, theta_0), or its move
+// to the overflow queue when the slots are taken.
+__global__ void __launch_bounds__(kLsNW * 64) ls_init_kernel(BatchArgs P) {
+  constexpr int NW = kLsNW;
+  __shared__ double red[NW];
+  const int qlen = P.counter[2];
+  for (int q = blockIdx.x; q < qlen; q += gridDim.x) {
+    const int sid = P.retry[q] - 1;
+    if (q >= P.ls_slots) {
+      if (threadIdx.x == 0) {
+        const int idx = atomicAdd(P.counter + 7, 1);
+        P.ovf[idx] = sid + 1;
+      }
+      continue;
+    }
+    const BatchDesc d = P.desc[sid];
+    const SlotMats sm = slot_mats<double>(P, ls_slot(P, q), nullptr);
+    const int64_t t0 = wall_clock64();
+    const double* sd = (P.scale == NS_SCALE_DIAG) ? sm.sd : nullptr;
+    const double alpha = wg_alpha<NW>(P, d, red, sm.sd);
+    LsState st{};
+    st.alpha = alpha;
+    st.sid = sid;
+    st.n = d.n;
+    st.t_begin = t0;
+    st.implicit = 1;
+    st.ns_stop = NS_STOP_DIVERGED;
+    if (alpha > 0.0 && isfinite(alpha)) {
+      const double f0 =
+          sqrt(wg_init_resid<double, NW>(d.n, d.A, d.lda, alpha, sd, (double*)sm.F, P.ldw, red));
+      st.bnorm = wg_theta0<NW>(d.n, d.b, d.theta, alpha, sd, red);
+      st.f0 = st.fprev = f0;
+      st.ns_stop = isfinite(f0) ? NS_STOP_NONE : NS_STOP_DIVERGED;
+      if (threadIdx.x == 0) P.res[sid].fnorm_hist[0] = f0;
+    }
+    st.active = st.ns_stop == NS_STOP_NONE;
+    if (threadIdx.x == 0) P.ls[q] = st;
+    __syncthreads();
+  }
+}
+
+// End of a step (one thread per system): ||F_k||, its history, the stop
+// rule with the floor probe's verdict, k_max, and the state for the next
+// step.
+__global__ void __launch_bounds__(64) ls_ctl_kernel(BatchArgs P) {
+  const int nsys = ls_count(P);
+  for (int q = blockIdx.x * 64 + threadIdx.x; q < nsys; q += gridDim.x * 64) {
+    LsState s = P.ls[q];
+    if (!s.active) continue;
+    int sexp = 0;
+    while ((1 << sexp) < P.ns_order) ++sexp;
+    const double fk = sqrt(ls_sum_parts(P, q, s.n, 0));
+    bool probe;
+    int stop = ls_rule(P, s, fk, probe);
+    s.k += 1;
+    s.mmm += (sexp > 1 ? 2 * (sexp - 1) - (s.f2_ready ? 1 : 0) : 0) + (s.implicit ? 0 : 1) + 1;
+    s.gc ^= 1;
+    s.implicit = 0;
+    s.f2_ready = 0;
+    if (s.k < NS_HIST_F) P.res[s.sid].fnorm_hist[s.k] = fk;
+    if (stop == NS_STOP_NONE && probe) {
+      const double f2 = sqrt(ls_sum_parts(P, q, s.n, ls_probe_off(P.ldw)));
+      s.mmm += 1;
+      s.f2_ready = 1;
+      if (f2 <= 0.25 * fk) stop = NS_STOP_FLOOR;
+    }
+    if (stop == NS_STOP_NONE && s.k >= P.k_max) stop = NS_STOP_K_MAX;
+    s.ns_stop = stop;
+    s.active = stop == NS_STOP_NONE;
+    s.probe = 0;
+    s.fk = fk;
+    s.fprev = fk;
+    P.ls[q] = s;
+  }
+}
+
+// Refinement and report of each system whose Newton-Schulz phase ended;
+// systems still iterating go to the overflow queue.
+__global__ void __launch_bounds__(kLsNW * 64) ls_finish_kernel(BatchArgs P) {
+  constexpr int NW = kLsNW;
+  __shared__ double red[NW];
+  const int nsys = ls_count(P);
+  for (int q = blockIdx.x; q < nsys; q += gridDim.x) {
+    const LsState s = P.ls[q];
+    if (s.ns_stop == NS_STOP_NONE) {
+      if (threadIdx.x == 0) {
+        const int idx = atomicAdd(P.counter + 7, 1);
+        P.ovf[idx] = s.sid + 1;
+      }
+      continue;
+    }
+    const BatchDesc d = P.desc[s.sid];
+    const SlotMats sm = slot_mats<double>(P, ls_slot(P, q), nullptr);
+    Ctl c;
+    c.alpha = s.alpha;
+    c.rel_resid = NAN;
+    c.mmm = s.mmm;
+    c.ns_steps = s.k;
+    c.ns_stop = s.ns_stop;
+    c.refine_steps = 0;
+    c.refine_stop = NS_STOP_NONE;
+    c.n_fnorm = (s.k + 1 < NS_HIST_F) ? s.k + 1 : NS_HIST_F;
+    c.precision = NS_PREC_FP64;
+    bool ok = false;
+    if (s.ns_stop == NS_STOP_DIVERGED) {
+      c.refine_stop = NS_STOP_DIVERGED;
+    } else {
+      ok = wg_refine<double, NW, NSR_BATCH_GR>(P, s.n, d.A, d.lda, d.b, d.theta,
+                                               (const double*)(s.gc ? sm.G[1] : sm.G[0]), P.ldw,
+                                               s.alpha, sm.r,
+                                               s.bnorm, red, c);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      BatchResult* R = &P.res[s.sid];
+      write_result(P, s.sid, true, true, ok, c, R->fnorm_hist, s.t_begin);
+    }
+    __syncthreads();
+  }
+}
+
 template <typename T, int NW>
 __global__ void __launch_bounds__(NW * 64) small_kernel(BatchArgs P) {
   constexpr bool dbl = sizeof(T) == 8;
@@ -1612,7 +1948,11 @@ __global__ void __launch_bounds__(NW * 64) small_kernel(BatchArgs P) {
 
 size_t batch_slot_bytes(int ldw) {
   const size_t nn = (size_t)ldw * ldw;
-  const size_t blocks = ((size_t)ldw / 32) * ((size_t)ldw / 32);   // team products' blocks
+  // per-block partial sums: the team products' 32 x 32 blocks, or the
+  // lockstep residual and probe products' 128 x 64 blocks
+  const size_t team = ((size_t)ldw / 32) * ((size_t)ldw / 32);
+  const size_t ls = 2 * (((size_t)ldw + 127) / 128) * (((size_t)ldw + 63) / 64);
+  const size_t blocks = team > ls ? team : ls;
   size_t b = 8 * nn * sizeof(float) + 7 * nn * sizeof(double) + 2 * (size_t)ldw * sizeof(double) +
              blocks * sizeof(double);
   return (b + 255) / 256 * 256;
@@ -1710,6 +2050,42 @@ int launch_escalating(BatchArgs a, int grid, int waves, int team_grid, int grid6
   return launch_pass<double>(a, grid64, 8, st);
 }
 
+// Lockstep float64 re-solve of the float32 pass's queue (see the lockstep
+// kernels), then the one-workgroup float64 pass over its overflow queue.
+// The number of queued systems is known only on the device, so every launch
+// is sized for the largest queue and does nothing for absent or finished
+// systems.
+int launch_lockstep(BatchArgs a, int sys_grid, int grid64, int cus, hipStream_t st) {
+  a.ls_on = 1;
+  int sexp = 0;
+  while ((1 << sexp) < a.ns_order) ++sexp;
+  constexpr int BM = Block<kLsNW>::BM, BN = Block<kLsNW>::BN;
+  const int per = ((a.ldw + BM - 1) / BM) * ((a.ldw + BN - 1) / BN);
+  const int nsys = std::min(a.count, a.ls_slots);
+  const int ggrid = std::max(1, std::min(nsys * per + nsys, 2 * cus));
+  const int cgrid = std::max(1, (nsys + 63) / 64);
+  sys_grid = std::max(1, sys_grid);
+  const dim3 blk(kLsNW * 64);
+  // Steps enqueued: enough for the stop rule to end every iteration of
+  // kappa up to ~1e12 (28 steps of order 4); a system still iterating after
+  // them is re-solved by the one-workgroup pass.
+  const int steps = std::min(a.k_max, std::max(1, (2 * kLsSteps) / std::max(sexp, 1)));
+  hipLaunchKernelGGL(ls_init_kernel, dim3(sys_grid), blk, 0, st, a);
+  for (int k = 0; k < steps; ++k) {
+    for (int i = 1; i < sexp; ++i) {
+      hipLaunchKernelGGL(ls_gemm_kernel, dim3(ggrid), blk, 0, st, a, (int)kLsPow, i);
+      hipLaunchKernelGGL(ls_gemm_kernel, dim3(ggrid), blk, 0, st, a, (int)kLsAsm, i);
+    }
+    hipLaunchKernelGGL(ls_gemm_kernel, dim3(ggrid), blk, 0, st, a, (int)kLsGside, 0);
+    hipLaunchKernelGGL(ls_gemm_kernel, dim3(ggrid), blk, 0, st, a, (int)kLsResid, 0);
+    hipLaunchKernelGGL(ls_gemm_kernel, dim3(ggrid), blk, 0, st, a, (int)kLsProbe, 0);
+    hipLaunchKernelGGL(ls_ctl_kernel, dim3(cgrid), dim3(64), 0, st, a);
+  }
+  hipLaunchKernelGGL(ls_finish_kernel, dim3(sys_grid), blk, 0, st, a);
+  if (hipGetLastError() != hipSuccess) return -1;
+  return launch_pass<double>(a, grid64, 8, st);
+}
+
 }  // namespace nsr
 
 // ---------------------------------------------------------------------------
@@ -1737,6 +2113,8 @@ size_t batch_layout(int64_t max_n, int max_count, int slots) {
   b += balign((size_t)max_count * sizeof(int32_t));   // float64 queue
   b += balign(kCounters * sizeof(int32_t));           // counters
   b += balign((size_t)max_count * sizeof(TeamState)); // float64 teams
+  b += balign((size_t)max_count * sizeof(LsState));   // lockstep states
+  b += balign((size_t)max_count * sizeof(int32_t));   // overflow queue
   b += (size_t)slots * batch_slot_bytes(ldw_for(max_n));
   return b;
 }
@@ -1761,6 +2139,8 @@ struct ns_batch {
   int32_t* d_counter = nullptr;   // kCounters counters (see BatchArgs)
   int32_t* d_retry = nullptr;
   TeamState* d_team = nullptr;
+  LsState* d_ls = nullptr;       // lockstep states (max_count)
+  int32_t* d_ovf = nullptr;      // overflow queue (max_count)
   char* d_slots = nullptr;
   hipEvent_t done = nullptr;
   hipStream_t side = nullptr;     // the float64 team kernel's stream
@@ -1795,6 +2175,7 @@ constexpr bool kTeamKernelEnabled = false;
 struct Launch {
   BatchArgs a;
   int grid, grid64;
+  int max_n;
   bool small;
 };
 
@@ -1839,6 +2220,10 @@ int batch_prepare(ns_batch* B, int count, const int64_t* n, const double* const*
   a.counter = B->d_counter;
   a.retry = B->d_retry;
   a.team = B->d_team;
+  a.ls = B->d_ls;
+  a.ovf = B->d_ovf;
+  a.ls_slots = B->slots;
+  a.ls_on = 0;
   a.ticks_ms = B->ticks_ms;
   a.slots = B->d_slots;
   a.slot_bytes = (int64_t)batch_slot_bytes(B->ldw);
@@ -1862,6 +2247,7 @@ int batch_prepare(ns_batch* B, int count, const int64_t* n, const double* const*
   int max_sys = 0;
   for (int i = 0; i < count; ++i) max_sys = std::max(max_sys, (int)n[i]);
   L.small = small_fits(max_sys, o->order);
+  L.max_n = max_sys;
   return NS_OK;
 }
 
@@ -1893,6 +2279,13 @@ int batch_launch(ns_batch* B, const Launch& L, hipStream_t st, bool allow_team) 
     if (team_grid < 0) team_grid = 0;
     if (launch_escalating(L.a, L.grid, B->waves, team_grid, L.grid64, st, B->side, B->ev_start,
                           B->ev_side) != 0)
+      return bfail(NS_EHIP, "batch kernel launch failed");
+    return NS_OK;
+  }
+  const bool lockstep = NSR_BATCH_LOCKSTEP && !L.small && L.a.escalate && L.max_n >= kLsMinN;
+  if (L.grid > 0 && lockstep) {
+    if (launch_pass<float>(L.a, L.grid, B->waves, st) != 0 ||
+        launch_lockstep(L.a, std::min(L.a.count, 2 * B->cus), L.grid64, B->cus, st) != 0)
       return bfail(NS_EHIP, "batch kernel launch failed");
     return NS_OK;
   }
@@ -2024,6 +2417,10 @@ int ns_batch_create(int device, void* hip_stream, int64_t max_n, int max_count, 
   p += balign(kCounters * sizeof(int32_t));
   B->d_team = reinterpret_cast<TeamState*>(p);
   p += balign((size_t)max_count * sizeof(TeamState));
+  B->d_ls = reinterpret_cast<LsState*>(p);
+  p += balign((size_t)max_count * sizeof(LsState));
+  B->d_ovf = reinterpret_cast<int32_t*>(p);
+  p += balign((size_t)max_count * sizeof(int32_t));
   B->d_slots = p;
   if (hipEventCreate(&B->done) != hipSuccess ||
       hipEventCreateWithFlags(&B->ev_start, hipEventDisableTiming) != hipSuccess ||

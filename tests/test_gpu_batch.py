@@ -467,3 +467,65 @@ def test_batch_diag_preconditioner_outside_its_condition(torch):
         elif lmax > 2.01:
             assert reps[i].status == nsr.NS_EDIVERGED, (i, lmax, reps[i])
     assert 0 < n_conv < len(systems)
+
+
+def test_batch_lockstep_float64_resolves(torch):
+    """Escalated systems of a batch with n >= 128 are re-solved in float64 in
+    lockstep (every product shared by the whole GPU).  Their iteration is the
+    one-workgroup solve's: same alpha, same ||F_k|| to rounding of the sums
+    of squares, the same steps (within one) as the float64-only batch, theta
+    within the kappa bound of it, every solve against the oracle; a batch
+    with fewer slots than escalations sends the rest to the overflow pass."""
+    hard = [inputs.spd_qlq(n, k, seed=1500 + n) for n, k in
+            ((130, 1e8), (200, 3e8), (250, 2e8), (160, 1e8))]
+    tol = 1e-7   # float64 reaches it at kappa 3e8 (u kappa ~ 3e-8); float32 cannot
+    easy = [inputs.spd_qlq(n, 1e2, seed=1600 + n) for n in (140, 33, 90)]
+    systems = hard + easy
+    for slots in (16, 2):
+        As, bs, ths = upload(torch, systems)
+        B = nsr.Batch(max_n=256, max_count=8, slots=slots)
+        print(f"lockstep: slots {slots}", flush=True)
+        reps = B.poll(B.submit(As, bs, ths, order=4, resid_tol=tol), wait=True)
+        B64 = nsr.Batch(max_n=256, max_count=8, slots=slots, precision=nsr.PREC_FP64)
+        th64 = [torch.zeros_like(t) for t in ths]
+        reps64 = B64.poll(B64.submit(As, bs, th64, order=4, resid_tol=tol), wait=True)
+        for i, s in enumerate(systems):
+            r, r64 = reps[i], reps64[i]
+            assert r.status == nsr.NS_OK and r64.status == nsr.NS_OK, (i, r, r64)
+            if i < len(hard):
+                assert r.precision == nsr.PREC_FP64, (i, r)
+                assert r.alpha == pytest.approx(r64.alpha, rel=1e-14)
+                assert abs(r.ns_steps - r64.ns_steps) <= 1, (i, r.ns_steps, r64.ns_steps)
+                # alpha differs in its last bit (sums in another order), and
+                # each step multiplies a relative perturbation by about the
+                # order: compare the trace above the rounding floor
+                n = min(len(r.fnorm_hist), len(r64.fnorm_hist), r.ns_steps, r64.ns_steps)
+                h, h64 = np.array(r.fnorm_hist[:n]), np.array(r64.fnorm_hist[:n])
+                above = h64 > 1e-4
+                np.testing.assert_allclose(h[above], h64[above], rtol=1e-5)
+                lam = np.linalg.eigvalsh(s.A)
+                kappa = lam.max() / lam.min()
+                a, b64 = ths[i].cpu().numpy(), th64[i].cpu().numpy()
+                assert np.linalg.norm(a - b64) <= 10 * tol * kappa * np.linalg.norm(b64), i
+            else:
+                assert r.precision == nsr.PREC_FP32, (i, r)
+        check_against_oracle(systems, ths, reps, 4, tol)
+
+
+def test_batch_lockstep_k_max(torch):
+    """k_max below the steps a hard system needs: the lockstep re-solve stops
+    at k_max like the one-workgroup solve (same steps and stop), and the
+    report says not converged."""
+    systems = [inputs.spd_qlq(200, 1e9, seed=1700), inputs.spd_qlq(150, 10.0, seed=1701)]
+    As, bs, ths = upload(torch, systems)
+    B = nsr.Batch(max_n=256, max_count=4, slots=4)
+    reps = B.poll(B.submit(As, bs, ths, order=4, resid_tol=1e-10, k_max=5), wait=True)
+    B64 = nsr.Batch(max_n=256, max_count=4, slots=4, precision=nsr.PREC_FP64)
+    th64 = [torch.zeros_like(t) for t in ths]
+    reps64 = B64.poll(B64.submit(As, bs, th64, order=4, resid_tol=1e-10, k_max=5), wait=True)
+    r, r64 = reps[0], reps64[0]
+    assert r.precision == nsr.PREC_FP64
+    assert r.ns_steps == r64.ns_steps == 5
+    assert r.ns_stop == r64.ns_stop
+    assert r.status == r64.status != nsr.NS_OK
+    assert reps[1].status == nsr.NS_OK
