@@ -1437,8 +1437,13 @@ __device__ __forceinline__ void batch_loop(const BatchArgs& P, double* red, doub
 }
 
 
+// Held to 128 registers per lane (four waves per SIMD, two eight-wave
+// workgroups per CU): the solve then spills some 40 registers (loop-invariant
+// addresses) to scratch, and still runs the 2048-system batch 13% (float32
+// pass) to 15% (float64-only) faster than at two waves per SIMD unspilled.
 template <typename T, int NW>
-__global__ void __launch_bounds__(NW * 64) batch_kernel(BatchArgs P) {
+__global__ void __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(4)))
+batch_kernel(BatchArgs P) {
   __shared__ double red[NW];
   __shared__ double hist[NS_HIST_F];
   __shared__ int s_idx;
