@@ -43,6 +43,10 @@
 #ifndef NSR_BATCH_GR
 #define NSR_BATCH_GR 2
 #endif
+// 1: float32 in-workgroup products stage their K slabs by LDS DMA.
+#ifndef NSR_BATCH_F32_DMA
+#define NSR_BATCH_F32_DMA 1
+#endif
 // 1: float64 re-solves of escalated systems run in lockstep across the GPU
 // (batches whose largest system has n >= kLsMinN).
 #ifndef NSR_BATCH_LOCKSTEP
@@ -422,6 +426,191 @@ __device__ double wg_gemm_block(int blk, int n, const T* X, int ldx, const doubl
   return ss;
 }
 
+// ---------------------------------------------------------------------------
+// Float32 products fed by LDS DMA.  Operands are slot matrices (leading
+// dimension ldw, a multiple of 32) whose rows and columns n .. ceil32(n) - 1
+// are zero (wg_zero_pads), so K runs in whole 32-deep slabs.  Each slab goes
+// from global memory straight into a ring of three LDS stages, two slabs
+// ahead of the MFMAs; one barrier per slab.  Rows of X past n (and columns
+// of Y past ldw) read row n - 1 (column ldw - 4) instead: they only feed
+// outputs that are not stored.
+//
+// LDS: X rows of 32 floats (8 chunks of 16 bytes, chunk c stored at c ^
+// ((row >> 1) & 7)), then 32 Y rows of BN floats (chunk c at c ^ ysw(k)).
+// An operand read of the 16 x 16 x 4 MFMA (16 rows or columns, 4 k) then
+// touches 64 different banks.
+// ---------------------------------------------------------------------------
+template <int NW> struct DmaF32 {
+  static constexpr int BM = Block<NW>::BM, BN = Block<NW>::BN, KB = 32, NST = 3;
+  static constexpr int XBYTES = BM * KB * 4, YBYTES = KB * BN * 4;
+  static constexpr int SBYTES = XBYTES + YBYTES, BYTES = NST * SBYTES;
+  static constexpr int YCH = BN / 4;            // 16-byte chunks per Y row
+  static constexpr int YR = 64 / YCH;           // Y rows per DMA instruction
+  static constexpr int XI = (BM / 8) / NW;      // DMA instructions per wave and slab
+  static constexpr int YI = (KB / YR) / NW;
+  static constexpr int PER = XI + YI;
+  static_assert(XI * NW * 8 == BM && YI * NW * YR == KB, "DMA split");
+};
+// Y chunk permutation for k row kr: rows of one 256-byte bank window are
+// separated by their 128-byte half, rows of the four k of an MFMA step by
+// the chunk group.
+template <int YCH>
+__device__ __forceinline__ int dma_ysw(int kr) {
+  return YCH >= 16 ? 4 * (kr & 3) : 4 * ((kr >> 1) & 1);
+}
+
+// LDS bytes of a workgroup's GEMM stages.
+template <typename T, int NW> struct StageBytes {
+  static constexpr int value =
+      (sizeof(T) == 4 && NSR_BATCH_F32_DMA) ? DmaF32<NW>::BYTES : Stage<T, NW>::BYTES;
+};
+
+// Zero rows and columns n .. ceil32(n) - 1 (within the first ceil32(n) rows
+// and columns) of the eight float32 slot matrices starting at m0 (ldw^2
+// floats apart).
+template <int NW>
+__device__ void wg_zero_pads(int n, float* m0, int ldw) {
+  const int kp = (n + 31) & ~31;
+  const int w = kp - n;   // pad width
+  if (w == 0) return;
+  const int per = 2 * n * w + w * w;   // [0,n) x [n,kp), [n,kp) x [0,kp)
+  for (int mtx = 0; mtx < 8; ++mtx) {
+    float* M = m0 + (int64_t)mtx * ldw * ldw;
+    for (int e = threadIdx.x; e < per; e += NW * 64) {
+      int row, col;
+      if (e < n * w) {
+        row = e / w;
+        col = n + e % w;
+      } else {
+        const int f = e - n * w;
+        row = n + f / kp;
+        col = f % kp;
+      }
+      M[row * ldw + col] = 0.0f;
+    }
+  }
+  __syncthreads();
+}
+
+template <int NW>
+__device__ double wg_gemm_block_dma(int blk, int n, const float* X, const float* Y, float* D,
+                                    int ldw, const float* E1, const float* E2, float diag,
+                                    float scale, void* lds) {
+  typedef DmaF32<NW> S;
+  constexpr int BM = S::BM, BN = S::BN, KB = S::KB, NST = S::NST, YCH = S::YCH;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int nbn = (n + BN - 1) / BN;
+  const int r0 = (blk / nbn) * BM, c0 = (blk % nbn) * BN;
+  const int nk = (n + KB - 1) / KB;
+  unsigned char* ring = static_cast<unsigned char*>(lds);
+  const uint32_t ring_lds = lds_addr(ring);
+  // DMA sources (k offset added per slab)
+  const float* xs[S::XI];
+  const float* ys[S::YI];
+#pragma unroll
+  for (int u = 0; u < S::XI; ++u) {
+    const int r = (u * NW + wave) * 8 + (lane >> 3);
+    const int c = (lane & 7) ^ ((r >> 1) & 7);
+    const int gr = r0 + r < n ? r0 + r : n - 1;
+    xs[u] = X + (int64_t)gr * ldw + 4 * c;
+  }
+#pragma unroll
+  for (int u = 0; u < S::YI; ++u) {
+    const int kr = (u * NW + wave) * S::YR + lane / YCH;
+    const int c = (lane % YCH) ^ dma_ysw<YCH>(kr);
+    int col = c0 + 4 * c;
+    if (col > ldw - 4) col = ldw - 4;
+    ys[u] = Y + (int64_t)kr * ldw + col;
+  }
+  auto issue = [&](int kt) {
+    const uint32_t st = ring_lds + (uint32_t)((kt % NST) * S::SBYTES);
+    const int64_t k0 = (int64_t)kt * KB;
+#pragma unroll
+    for (int u = 0; u < S::XI; ++u)
+      lds_dma16(xs[u] + k0, st + (uint32_t)((u * NW + wave) * 8 * KB * 4));
+#pragma unroll
+    for (int u = 0; u < S::YI; ++u)
+      lds_dma16(ys[u] + k0 * ldw, st + (uint32_t)(S::XBYTES + (u * NW + wave) * 1024));
+  };
+  const int lr = lane & 15, lk = lane >> 4;
+  const int sr = (wave / (BN / 32)) * 32, sc = (wave % (BN / 32)) * 32;
+  const bool active = (r0 + sr < n) && (c0 + sc < n);   // wave-uniform
+  const int xsw = (lr >> 1) & 7;                        // row swizzle of this lane's rows
+  const int ysw = dma_ysw<YCH>(lk);                     // k row swizzle (k = ks + lk, ks % 4 == 0)
+  const int offa = (sr + lr) * KB * 4 + 4 * lk;
+  int offb[2];
+#pragma unroll
+  for (int j = 0; j < 2; ++j)
+    offb[j] = S::XBYTES + lk * BN * 4 + 16 * (((sc + 16 * j + lr) >> 2) ^ ysw) + 4 * (lr & 3);
+  f32x4 acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0, 0, 0, 0};
+  issue(0);
+  if (nk > 1) issue(1);
+  for (int kt = 0; kt < nk; ++kt) {
+    const int later = nk - 1 - kt;
+    if (later >= 1)
+      dma_wait_barrier<S::PER>();
+    else
+      dma_wait_barrier<0>();
+    if (kt + 2 < nk) issue(kt + 2);
+    if (active) {
+      const unsigned char* st = ring + (kt % NST) * S::SBYTES;
+#pragma unroll
+      for (int ks = 0; ks < KB; ks += 4) {
+        const int ca = 16 * ((ks >> 2) ^ xsw);
+        const float a0 = *reinterpret_cast<const float*>(st + offa + ca);
+        const float a1 = *reinterpret_cast<const float*>(st + offa + 16 * KB * 4 + ca);
+        const float b0 = *reinterpret_cast<const float*>(st + offb[0] + ks * BN * 4);
+        const float b1 = *reinterpret_cast<const float*>(st + offb[1] + ks * BN * 4);
+        acc[0][0] = mfma(a0, b0, acc[0][0]);
+        acc[0][1] = mfma(a0, b1, acc[0][1]);
+        acc[1][0] = mfma(a1, b0, acc[1][0]);
+        acc[1][1] = mfma(a1, b1, acc[1][1]);
+      }
+    }
+  }
+  double ss = 0.0;
+  if (active) {
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      float e1[2][4], e2[2][4];
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        const int col = c0 + sc + 16 * j + lr;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int row = r0 + sr + 16 * i + acc_row(0.0f, lk, r);
+          const bool in = row < n && col < n;
+          e1[j][r] = (E1 && in) ? E1[row * ldw + col] : 0.0f;
+          e2[j][r] = (E2 && in) ? E2[row * ldw + col] : 0.0f;
+        }
+      }
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        const int col = c0 + sc + 16 * j + lr;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int row = r0 + sr + 16 * i + acc_row(0.0f, lk, r);
+          if (row < n && col < n) {
+            float v = scale * acc[i][j][r];
+            if (row == col) v += diag;
+            if (E1) v += e1[j][r];
+            if (E2) v += e2[j][r];
+            D[row * ldw + col] = v;
+            ss += (double)v * (double)v;
+          }
+        }
+      }
+    }
+  }
+  __syncthreads();  // the ring is free for the next block, D complete
+  return ss;
+}
+
 // D = diag I + scale X Y + E1 + E2 (n x n); returns sum D^2 over the
 // workgroup when want_ss (uniform).  XA: X is the float64 input A (read
 // through lda), otherwise X is T with leading dimension ldx (multiple of 4).
@@ -432,9 +621,18 @@ __device__ double wg_gemm(int n, const T* X, int ldx, const double* XA, int64_t 
                           T scale, bool want_ss, double* red, void* lds) {
   double ss = 0.0;
   const int nb = wg_gemm_blocks<T, NW>(n);
-  for (int blk = 0; blk < nb; ++blk)
-    ss += wg_gemm_block<T, NW>(blk, n, X, ldx, XA, lda, Y, ldy, D, ldd, E1, E2, lde, diag, scale,
-                               lds);
+  if constexpr (sizeof(T) == 4 && NSR_BATCH_F32_DMA) {
+    // float32 operands are always slot matrices (leading dimension ldx ==
+    // ldy == ldd == lde, zero pads), never the float64 input
+    for (int blk = 0; blk < nb; ++blk)
+      ss += wg_gemm_block_dma<NW>(blk, n, (const float*)X, (const float*)Y, (float*)D, ldd,
+                                  (const float*)E1, (const float*)E2, (float)diag, (float)scale,
+                                  lds);
+  } else {
+    for (int blk = 0; blk < nb; ++blk)
+      ss += wg_gemm_block<T, NW>(blk, n, X, ldx, XA, lda, Y, ldy, D, ldd, E1, E2, lde, diag,
+                                 scale, lds);
+  }
   if (!want_ss) return 0.0;
   return block_sum_all<NW>(ss, red);
 }
@@ -926,6 +1124,7 @@ __device__ bool wg_solve(const BatchArgs& P, const BatchDesc& d, const SlotMats&
     return false;
   }
   if (is32) wg_copy_A<float, NW>(n, d.A, d.lda, sm.A32, ldw);  // for the residual products
+  if (is32 && NSR_BATCH_F32_DMA) wg_zero_pads<NW>(n, sm.A32, ldw);  // K runs in whole slabs
   const T* AX = is32 ? (const T*)sm.A32 : nullptr;
   const double* AXd = is32 ? nullptr : d.A;
   // F_0 = I - A S^-1, theta_0 = S^-1 b, ||b||
@@ -1447,7 +1646,7 @@ batch_kernel(BatchArgs P) {
   __shared__ double red[NW];
   __shared__ double hist[NS_HIST_F];
   __shared__ int s_idx;
-  __shared__ __attribute__((aligned(16))) char stage[Stage<T, NW>::BYTES];
+  __shared__ __attribute__((aligned(1024))) char stage[StageBytes<T, NW>::value];
   batch_loop<T, NW>(P, red, hist, s_idx, stage);
 }
 
@@ -1461,7 +1660,7 @@ f32_pass_kernel(BatchArgs P) {
   __shared__ double red[NW];
   __shared__ double hist[NS_HIST_F];
   __shared__ int s_idx;
-  __shared__ __attribute__((aligned(16))) char stage[Stage<float, NW>::BYTES];
+  __shared__ __attribute__((aligned(1024))) char stage[StageBytes<float, NW>::value];
   batch_loop<float, NW>(P, red, hist, s_idx, stage);
 }
 

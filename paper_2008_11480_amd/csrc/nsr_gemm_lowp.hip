@@ -483,25 +483,6 @@ constexpr int kDmaRowBytes = kDmaBK * 2;
 
 __device__ __forceinline__ int dma_swz(int row) { return (row >> 3) & 3; }
 
-// One LDS DMA instruction: 16 bytes per lane from src to LDS byte address
-// lds + 16 * lane (lds wave-uniform).  Written as inline assembly so that
-// the compiler, which does not see these LDS writes, adds no wait of its own
-// before the operand reads: the kernel orders them itself (vmcnt + barrier).
-// m0 is set right before the load (one wait state between the two).
-__device__ __forceinline__ void lds_dma16(const void* src, uint32_t lds) {
-  asm volatile("s_mov_b32 m0, %1\n\ts_nop 0\n\tglobal_load_lds_dwordx4 %0, off"
-               :
-               : "v"(src), "s"(lds)
-               : "memory");
-}
-
-// Wait until at most CNT of this wave's DMA instructions are outstanding and
-// its LDS reads are complete, then the workgroup barrier.
-template <int CNT>
-__device__ __forceinline__ void dma_wait_barrier() {
-  asm volatile("s_waitcnt vmcnt(%0) lgkmcnt(0)\n\ts_barrier" : : "n"(CNT) : "memory");
-}
-
 // 256 x BN tile (BN = 256: eight waves, one workgroup per CU; BN = 128: four
 // waves, two workgroups per CU), waves of 128 x 64, NST stages of 32-deep
 // slabs in LDS.  The library launches <256, 4>: <128, 3> (two workgroups per

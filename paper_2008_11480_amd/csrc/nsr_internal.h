@@ -176,4 +176,35 @@ constexpr int kTileF64 = 0, kTileF32 = 1, kTileBf16 = 2, kTileF16s = 3, kTileFam
 // (use the library's rule).
 int tile_choice(int family, int64_t m, int64_t n);
 
+
+// ---------------------------------------------------------------------------
+// LDS DMA (device code of the GEMMs that stage operands with
+// global_load_lds_dwordx4).
+// ---------------------------------------------------------------------------
+// One LDS DMA instruction: 16 bytes per lane from src to LDS byte address
+// lds + 16 * lane (lds wave-uniform).  Written as inline assembly so that
+// the compiler, which does not see these LDS writes, adds no wait of its own
+// before the operand reads: the kernels order them themselves (vmcnt +
+// barrier).  m0 is set right before the load (one wait state between the
+// two); no other code of these kernels uses m0.
+__device__ __forceinline__ void lds_dma16(const void* src, uint32_t lds) {
+  asm volatile("s_mov_b32 m0, %1\n\ts_nop 0\n\tglobal_load_lds_dwordx4 %0, off"
+               :
+               : "v"(src), "s"(lds)
+               : "memory");
+}
+
+// Wait until at most CNT of this wave's DMA instructions are outstanding and
+// its LDS reads are complete, then the workgroup barrier.
+template <int CNT>
+__device__ __forceinline__ void dma_wait_barrier() {
+  asm volatile("s_waitcnt vmcnt(%0) lgkmcnt(0)\n\ts_barrier" : : "n"(CNT) : "memory");
+}
+
+// LDS byte address of a shared-memory object (the low 32 bits of its
+// generic address).
+__device__ __forceinline__ uint32_t lds_addr(const void* p) {
+  return (uint32_t)reinterpret_cast<uintptr_t>(p);
+}
+
 }  // namespace nsr
