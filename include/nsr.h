@@ -309,6 +309,13 @@ int ns_batch_create(int device, void* hip_stream, int64_t max_n, int max_count,
  * kernel for n <= 64 runs eight waves when waves_per_group is 8, else four. */
 int ns_batch_set_launch(ns_batch* b, int waves_per_group, int groups);
 
+/* Float64 re-solve of the systems float32 could not solve: in submissions
+ * of at least min_count systems whose largest has n >= 128, the re-solves run
+ * in lockstep across the GPU (each product shared by all CUs; a fixed
+ * schedule of about 170 launches per submission), otherwise one workgroup
+ * per system.  Default 512; 0 turns lockstep off.  Errors: NS_EINVAL. */
+int ns_batch_set_lockstep(ns_batch* b, int min_count);
+
 /* Enqueue the solves of `count` systems.  opts->graph = 1: the submission's
  * device work (reset of its counters by a kernel, the persistent kernels) is
  * captured once into a HIP graph and replayed by later submissions with the

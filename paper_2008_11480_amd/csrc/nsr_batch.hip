@@ -48,7 +48,7 @@
 #define NSR_BATCH_F32_DMA 1
 #endif
 // 1: float64 re-solves of escalated systems run in lockstep across the GPU
-// (batches whose largest system has n >= kLsMinN).
+// (batches of at least kLsMinCount systems whose largest has n >= kLsMinN).
 #ifndef NSR_BATCH_LOCKSTEP
 #define NSR_BATCH_LOCKSTEP 1
 #endif
@@ -1820,8 +1820,17 @@ team_kernel(BatchArgs P) {
 // after the enqueued steps, go to the overflow queue, which the
 // one-workgroup float64 pass re-solves afterwards.
 // ---------------------------------------------------------------------------
-constexpr int kLsNW = 8;      // waves of the lockstep kernels
-constexpr int kLsMinN = 128;  // smallest largest-system size that uses lockstep
+constexpr int kLsNW = 8;      // waves of the lockstep per-system kernels
+#ifndef NSR_LS_GEMM_NW
+#define NSR_LS_GEMM_NW 8
+#endif
+constexpr int kLsGemmNW = NSR_LS_GEMM_NW;   // waves of the lockstep product kernel
+constexpr int kLsMinN = 128;    // smallest largest-system size that uses lockstep
+constexpr int kLsMinCount = 512;  // smallest batch that uses lockstep: the fixed
+                                  // schedule (170 launches) costs ~2 ms of host
+                                  // enqueue and ~0.5 ms of device time, which a
+                                  // serving-sized batch (<= 256 systems) pays
+                                  // in latency even when nothing escalates
 constexpr int kLsSteps = 28;  // Newton-Schulz steps enqueued (capped by k_max)
 enum : int { kLsPow = 0, kLsAsm = 1, kLsGside = 2, kLsResid = 3, kLsProbe = 4 };
 
@@ -1905,13 +1914,13 @@ __device__ __forceinline__ bool ls_operands(const BatchArgs& P, const LsState& s
 // Per-block partial sums of D^2 of the residual product (part[0..)) and of
 // the floor probe (part[ls_probe_off..)): blocks of the largest system each.
 __device__ __forceinline__ int ls_probe_off(int ldw) {
-  return ((ldw + Block<kLsNW>::BM - 1) / Block<kLsNW>::BM) *
-         ((ldw + Block<kLsNW>::BN - 1) / Block<kLsNW>::BN);
+  return ((ldw + Block<kLsGemmNW>::BM - 1) / Block<kLsGemmNW>::BM) *
+         ((ldw + Block<kLsGemmNW>::BN - 1) / Block<kLsGemmNW>::BN);
 }
 
 // Sum of one product's per-block partial sums, in block order.
 __device__ __forceinline__ double ls_sum_parts(const BatchArgs& P, int q, int n, int off) {
-  constexpr int BM = Block<kLsNW>::BM, BN = Block<kLsNW>::BN;
+  constexpr int BM = Block<kLsGemmNW>::BM, BN = Block<kLsGemmNW>::BN;
   const double* part = slot_part(P, ls_slot(P, q)) + off;
   const int nb = ((n + BM - 1) / BM) * ((n + BN - 1) / BN);
   double t = 0.0;
@@ -1938,8 +1947,8 @@ __device__ __forceinline__ int ls_rule(const BatchArgs& P, const LsState& s, dou
 // block) strided over the grid.  The residual launch also carries one
 // Richardson-update item per system (it reads the same new G and writes
 // theta, which no product reads).
-__global__ void __launch_bounds__(kLsNW * 64) ls_gemm_kernel(BatchArgs P, int ph, int i) {
-  constexpr int NW = kLsNW, BM = Block<NW>::BM, BN = Block<NW>::BN;
+__global__ void __launch_bounds__(kLsGemmNW * 64) ls_gemm_kernel(BatchArgs P, int ph, int i) {
+  constexpr int NW = kLsGemmNW, BM = Block<NW>::BM, BN = Block<NW>::BN;
   __shared__ __attribute__((aligned(16))) char lds[Stage<double, NW>::BYTES];
   __shared__ double red[NW];
   const int nsys = ls_count(P);
@@ -2155,7 +2164,8 @@ size_t batch_slot_bytes(int ldw) {
   // per-block partial sums: the team products' 32 x 32 blocks, or the
   // lockstep residual and probe products' 128 x 64 blocks
   const size_t team = ((size_t)ldw / 32) * ((size_t)ldw / 32);
-  const size_t ls = 2 * (((size_t)ldw + 127) / 128) * (((size_t)ldw + 63) / 64);
+  const size_t ls = 2 * (((size_t)ldw + Block<kLsGemmNW>::BM - 1) / Block<kLsGemmNW>::BM) *
+                   (((size_t)ldw + Block<kLsGemmNW>::BN - 1) / Block<kLsGemmNW>::BN);
   const size_t blocks = team > ls ? team : ls;
   size_t b = 8 * nn * sizeof(float) + 7 * nn * sizeof(double) + 2 * (size_t)ldw * sizeof(double) +
              blocks * sizeof(double);
@@ -2263,10 +2273,11 @@ int launch_lockstep(BatchArgs a, int sys_grid, int grid64, int cus, hipStream_t 
   a.ls_on = 1;
   int sexp = 0;
   while ((1 << sexp) < a.ns_order) ++sexp;
-  constexpr int BM = Block<kLsNW>::BM, BN = Block<kLsNW>::BN;
+  constexpr int BM = Block<kLsGemmNW>::BM, BN = Block<kLsGemmNW>::BN;
   const int per = ((a.ldw + BM - 1) / BM) * ((a.ldw + BN - 1) / BN);
   const int nsys = std::min(a.count, a.ls_slots);
-  const int ggrid = std::max(1, std::min(nsys * per + nsys, 2 * cus));
+  const int ggrid = std::max(1, std::min(nsys * per + nsys, (16 / kLsGemmNW) * cus));
+  const dim3 gblk(kLsGemmNW * 64);
   const int cgrid = std::max(1, (nsys + 63) / 64);
   sys_grid = std::max(1, sys_grid);
   const dim3 blk(kLsNW * 64);
@@ -2277,12 +2288,12 @@ int launch_lockstep(BatchArgs a, int sys_grid, int grid64, int cus, hipStream_t 
   hipLaunchKernelGGL(ls_init_kernel, dim3(sys_grid), blk, 0, st, a);
   for (int k = 0; k < steps; ++k) {
     for (int i = 1; i < sexp; ++i) {
-      hipLaunchKernelGGL(ls_gemm_kernel, dim3(ggrid), blk, 0, st, a, (int)kLsPow, i);
-      hipLaunchKernelGGL(ls_gemm_kernel, dim3(ggrid), blk, 0, st, a, (int)kLsAsm, i);
+      hipLaunchKernelGGL(ls_gemm_kernel, dim3(ggrid), gblk, 0, st, a, (int)kLsPow, i);
+      hipLaunchKernelGGL(ls_gemm_kernel, dim3(ggrid), gblk, 0, st, a, (int)kLsAsm, i);
     }
-    hipLaunchKernelGGL(ls_gemm_kernel, dim3(ggrid), blk, 0, st, a, (int)kLsGside, 0);
-    hipLaunchKernelGGL(ls_gemm_kernel, dim3(ggrid), blk, 0, st, a, (int)kLsResid, 0);
-    hipLaunchKernelGGL(ls_gemm_kernel, dim3(ggrid), blk, 0, st, a, (int)kLsProbe, 0);
+    hipLaunchKernelGGL(ls_gemm_kernel, dim3(ggrid), gblk, 0, st, a, (int)kLsGside, 0);
+    hipLaunchKernelGGL(ls_gemm_kernel, dim3(ggrid), gblk, 0, st, a, (int)kLsResid, 0);
+    hipLaunchKernelGGL(ls_gemm_kernel, dim3(ggrid), gblk, 0, st, a, (int)kLsProbe, 0);
     hipLaunchKernelGGL(ls_ctl_kernel, dim3(cgrid), dim3(64), 0, st, a);
   }
   hipLaunchKernelGGL(ls_finish_kernel, dim3(sys_grid), blk, 0, st, a);
@@ -2334,6 +2345,7 @@ struct ns_batch {
   int ldw = 0;
   int precision = NS_PREC_FP32;
   int waves = 4;
+  int ls_min_count = kLsMinCount;   // lockstep float64 re-solve from this many systems (0: off)
   int groups = 0;  // launch size (<= slots); 0: all slots
   int cus = 256;   // compute units of the device
   int64_t ticks_ms = 100000;   // device wall-clock ticks per millisecond
@@ -2486,7 +2498,8 @@ int batch_launch(ns_batch* B, const Launch& L, hipStream_t st, bool allow_team) 
       return bfail(NS_EHIP, "batch kernel launch failed");
     return NS_OK;
   }
-  const bool lockstep = NSR_BATCH_LOCKSTEP && !L.small && L.a.escalate && L.max_n >= kLsMinN;
+  const bool lockstep = NSR_BATCH_LOCKSTEP && !L.small && L.a.escalate && L.max_n >= kLsMinN &&
+                        B->ls_min_count > 0 && L.a.count >= B->ls_min_count;
   if (L.grid > 0 && lockstep) {
     if (launch_pass<float>(L.a, L.grid, B->waves, st) != 0 ||
         launch_lockstep(L.a, std::min(L.a.count, 2 * B->cus), L.grid64, B->cus, st) != 0)
@@ -2637,6 +2650,14 @@ int ns_batch_create(int device, void* hip_stream, int64_t max_n, int max_count, 
     return bfail(NS_EHIP, "hipEventCreate / hipStreamCreate failed");
   }
   *out = B;
+  return NS_OK;
+}
+
+int ns_batch_set_lockstep(ns_batch* B, int min_count) {
+  if (!B) return bfail(NS_EINVAL, "null batch");
+  if (min_count < 0) return bfail(NS_EINVAL, "min_count < 0");
+  B->ls_min_count = min_count;
+  B->graph_key.clear();
   return NS_OK;
 }
 

@@ -43,7 +43,8 @@ EXPORTS = (
     "ns_gemm_f32", "ns_gemm_bf16_nt", "ns_gemm_lp_partials", "ns_gemm_f32_split",
     "ns_gemm_f32_split_scratch_bytes", "ns_gemm_bf16_nt_ws", "ns_gemm_bf16_scratch_bytes",
     "ns_gemm_f32_split_noalloc", "ns_tile_set", "ns_tile_get",
-    "ns_batch_workspace_bytes", "ns_batch_create", "ns_batch_set_launch", "ns_batch_submit",
+    "ns_batch_workspace_bytes", "ns_batch_create", "ns_batch_set_launch", "ns_batch_set_lockstep",
+    "ns_batch_submit",
     "ns_batch_poll", "ns_batch_autotune", "ns_batch_timeline", "ns_batch_destroy",
     "ns_batch_set_ledger", "ns_ledger_create", "ns_ledger_admit", "ns_ledger_release",
     "ns_ledger_query", "ns_ledger_destroy", "ns_solve_footprint",
@@ -150,6 +151,7 @@ def lib() -> ctypes.CDLL:
         "ns_batch_create": (ci, [ci, vp, i64, ci, ci, ci, vp, ctypes.c_size_t,
                                  ctypes.POINTER(vp)]),
         "ns_batch_set_launch": (ci, [vp, ci, ci]),
+        "ns_batch_set_lockstep": (ci, [vp, ci]),
         "ns_batch_submit": (ci, [vp, ci, vp, vp, vp, vp, vp, ctypes.POINTER(SolveOpts),
                                  ctypes.POINTER(ctypes.c_uint64)]),
         "ns_batch_poll": (ci, [vp, ctypes.c_uint64, ci, vp]),
@@ -585,6 +587,11 @@ class Batch:
 
     def set_launch(self, waves: int, groups: int = 0):
         check(lib().ns_batch_set_launch(self._h, int(waves), int(groups)))
+
+    def set_lockstep(self, min_count: int):
+        """``ns_batch_set_lockstep``: lockstep float64 re-solves in
+        submissions of at least ``min_count`` systems (0: off)."""
+        check(lib().ns_batch_set_lockstep(self._h, int(min_count)))
 
     def submit(self, As, bs, thetas, **opts) -> int:
         count, n, pa, lda, pb, pt = self._arrays(As, bs, thetas)

@@ -375,11 +375,12 @@ def test_batch_graph_replay_matches_eager(torch):
         [inputs.spd_qlq(n, 1e3, seed=950 + n) for n in (1, 17, 40, 64)],
     )
     fields = ("status", "precision", "ns_steps", "refine_steps", "alpha", "rel_resid", "mmm")
-    for systems in cases:
+    for systems, lockstep in ((cases[0], 0), (cases[0], 1), (cases[1], 0)):
         As, bs, ths = upload(torch, systems)
         B = nsr.Batch(max_n=256, max_count=8, slots=8)
         B.set_launch(4, 0)
-        print(f"graph replay: sizes {[s.n for s in systems]}", flush=True)
+        B.set_lockstep(lockstep)   # 1: the escalation runs the lockstep schedule
+        print(f"graph replay: sizes {[s.n for s in systems]} lockstep {lockstep}", flush=True)
         ref = B.poll(B.submit(As, bs, ths, order=4, resid_tol=1e-10), wait=True)
         want = [t.clone() for t in ths]
         check_against_oracle(systems, ths, ref, 4, 1e-10)
@@ -484,6 +485,7 @@ def test_batch_lockstep_float64_resolves(torch):
     for slots in (16, 2):
         As, bs, ths = upload(torch, systems)
         B = nsr.Batch(max_n=256, max_count=8, slots=slots)
+        B.set_lockstep(1)
         print(f"lockstep: slots {slots}", flush=True)
         reps = B.poll(B.submit(As, bs, ths, order=4, resid_tol=tol), wait=True)
         B64 = nsr.Batch(max_n=256, max_count=8, slots=slots, precision=nsr.PREC_FP64)
@@ -519,6 +521,7 @@ def test_batch_lockstep_k_max(torch):
     systems = [inputs.spd_qlq(200, 1e9, seed=1700), inputs.spd_qlq(150, 10.0, seed=1701)]
     As, bs, ths = upload(torch, systems)
     B = nsr.Batch(max_n=256, max_count=4, slots=4)
+    B.set_lockstep(1)
     reps = B.poll(B.submit(As, bs, ths, order=4, resid_tol=1e-10, k_max=5), wait=True)
     B64 = nsr.Batch(max_n=256, max_count=4, slots=4, precision=nsr.PREC_FP64)
     th64 = [torch.zeros_like(t) for t in ths]
