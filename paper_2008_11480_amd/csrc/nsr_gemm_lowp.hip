@@ -131,8 +131,12 @@ gemm_f32_nn_kernel(GemmLpArgs p, int tiles_m, int tiles_n) {
   constexpr int NT = 256;
   constexpr int WTM = BM / 2, WTN = BN / 2;
   constexpr int FM = WTM / 16, FN = WTN / 16;
-  constexpr int XS = BK + 4;    // floats
-  constexpr int YS = BN + 4;
+  // Row strides (floats).  An MFMA operand read has 16 lanes along one
+  // dimension and 4 along K: X rows 36 floats apart put the 16 rows x 4 k in
+  // 64 different banks; Y rows (k) must be 16 banks apart for the same
+  // (BN + 4 put consecutive k rows 4 banks apart: 40% conflict cycles).
+  constexpr int XS = BK + 4;
+  constexpr int YS = BN + 16;
   constexpr int XV = (BM * BK / 4) / NT;  // float4 per thread
   constexpr int YV = (BK * BN / 4) / NT;
   static_assert(XV >= 1 && YV >= 1, "tile too small");
