@@ -549,8 +549,10 @@ int ns_gemm_f32_split(void* hip_stream, int64_t m, int64_t n, int64_t k,
  * family and size bucket: products whose output is m x n use the tile set
  * for bucket ceil(log2(max(m, n))).  Families: NS_TILE_F64 (ns_gemm_f64 and
  * the float64 solver products; tiles 64, 128), NS_TILE_F32 (float32 MFMA;
- * 64, 128), NS_TILE_BF16 (bf16 powers; 64, 128, 256), NS_TILE_F16S (split
- * half-precision products; 64, 128, 256).  Tile 0 restores the rule.  The
+ * 64, 128, 256: the 256 tile needs K a multiple of 32, N a multiple of 4 and
+ * 16-byte aligned rows, and falls back to 128 otherwise), NS_TILE_BF16 (bf16
+ * powers; 64, 128, 256), NS_TILE_F16S (split half-precision products; 64,
+ * 128, 256).  Tile 0 restores the rule.  The
  * table is process-wide (all devices); every tile is valid for every shape,
  * and buffers sized by ns_gemm_f64_partials / ns_gemm_lp_partials /
  * ns_workspace_bytes hold the partial sums of any choice.  Setting an entry

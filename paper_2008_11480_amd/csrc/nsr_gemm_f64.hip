@@ -626,7 +626,7 @@ int tile_bucket(int64_t d) {
 
 bool tile_valid(int family, int tile) {
   if (tile == 0 || tile == 64 || tile == 128) return true;
-  return tile == 256 && (family == kTileBf16 || family == kTileF16s);
+  return tile == 256 && (family == kTileF32 || family == kTileBf16 || family == kTileF16s);
 }
 }  // namespace
 

@@ -44,6 +44,10 @@
 #ifndef NSR_BF16_HUGE_BK
 #define NSR_BF16_HUGE_BK 64
 #endif
+// 1: 256 x 256 float32 tiles (LDS-DMA kernel) where its requirements hold.
+#ifndef NSR_F32_DMA
+#define NSR_F32_DMA 1
+#endif
 // 1: 256 x 256 bf16 tiles use the LDS-DMA kernel where its requirements hold.
 #ifndef NSR_BF16_DMA
 #define NSR_BF16_DMA 1
@@ -56,6 +60,15 @@ typedef float f32x16 __attribute__((ext_vector_type(16)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
 namespace {
+
+// fn(std::integral_constant<int, I>) for I = B .. E - 1, unrolled at compile time.
+template <int B, int E, typename Fn>
+__device__ __forceinline__ void static_for(Fn&& fn) {
+  if constexpr (B < E) {
+    fn(std::integral_constant<int, B>{});
+    static_for<B + 1, E>(fn);
+  }
+}
 
 __device__ __forceinline__ void map_tile_lp(int bid, int tiles_m, int tiles_n, int& tm, int& tn) {
   const int ntiles = tiles_m * tiles_n;
@@ -286,6 +299,190 @@ gemm_f32_nn_kernel(GemmLpArgs p, int tiles_m, int tiles_n) {
     }
   }
   write_partial(p, ss, red, tm, tn, tiles_n);
+}
+
+// ---------------------------------------------------------------------------
+// float32, NN, 256 x 256 tiles fed by LDS DMA
+// ---------------------------------------------------------------------------
+// Eight waves of 64 x 128 (one workgroup per CU, two waves per SIMD: one
+// wave's waits hide behind the other's MFMAs).  K runs in 32-deep slabs
+// that global_load_lds_dwordx4 writes into two LDS stages: a slab lands while
+// the previous one is multiplied (eight k-steps of 32 MFMAs per wave), and one
+// barrier per slab orders the stages.  An X row keeps K contiguous (128 B per
+// row and slab), a Y row N (1 KB per k).  One 16-byte read gives a lane the A
+// operands of four MFMA steps: in k-group g (16 k) lane (r, q) = (lane % 16,
+// lane / 16) holds X[row][16 g + 4 q + j] for step j, so its B operand in
+// step j is Y[16 g + 4 q + j][col].  The 16-byte chunks of every LDS row are
+// permuted so that both operand reads spread over all 64 banks: chunk c of X
+// row R sits at c ^ f32_xsw(R) (R mod 16 decides which bank half and window a
+// lane of a 16-lane read group hits), chunk c of Y row k at c ^ f32_ysw(k)
+// (the four k rows of one B read, 4 apart, land in different 16-bank
+// windows).  Requires K a multiple of 32, N a multiple of 4, row strides
+// multiples of 4 floats and 16-byte aligned operands; rows past M and columns
+// past N of edge tiles read row M - 1 and the last four columns instead and
+// feed only outputs that are not stored.
+constexpr int kF32DmaBK = 32;
+
+__device__ __forceinline__ int f32_xsw(int row) { return (row & 2) | ((row >> 1) & 4); }
+__device__ __forceinline__ int f32_ysw(int k) { return ((k >> 2) & 3) << 2; }
+
+__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2)))
+gemm_f32_nn_dma_kernel(GemmLpArgs p, int tiles_m, int tiles_n) {
+  constexpr int BM = 256, BN = 256, BK = kF32DmaBK, NW = 8, NST = 2;
+  constexpr int WTM = 64, WTN = 128, FM = WTM / 16, FN = WTN / 16;
+  constexpr int XBYTES = BM * BK * 4;           // 256 rows of 128 B
+  constexpr int SBYTES = XBYTES + BK * BN * 4;  // + 32 rows of 1 KB
+  constexpr int XI = BM / 8 / NW;               // DMA instructions per wave and slab: X, 8 rows each
+  constexpr int YI = BK / NW;                   // Y, one row each
+  static_assert(XI * NW * 8 == BM && YI * NW == BK && BN == 256, "DMA split");
+  __shared__ __attribute__((aligned(1024))) unsigned char ring[NST * SBYTES];
+  __shared__ double red[NW];
+
+  const float* X = static_cast<const float*>(p.X);
+  const float* Y = static_cast<const float*>(p.Y);
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int wm = wave >> 1, wn = wave & 1;
+  int tm, tn;
+  map_tile_lp(blockIdx.x, tiles_m, tiles_n, tm, tn);
+  const int64_t m0 = (int64_t)tm * BM, n0 = (int64_t)tn * BN;
+  const int64_t M = p.M, N = p.N, K = p.K;
+  const uint32_t ring_lds = lds_addr(&ring[0]);
+
+  // DMA sources, as byte offsets from the slab's wave-uniform base: X
+  // instruction u of this wave covers tile rows (u NW + wave) 8 .. + 7, Y
+  // instruction u slab row k = u NW + wave.
+  uint32_t xoff[XI], yoff[YI];
+#pragma unroll
+  for (int u = 0; u < XI; ++u) {
+    const int row = (u * NW + wave) * 8 + (lane >> 3);
+    const int c = (lane & 7) ^ f32_xsw(row);
+    const int64_t g = (m0 + row < M ? m0 + row : M - 1) - m0;
+    xoff[u] = (uint32_t)((g * p.ldx + 4 * c) * 4);
+  }
+#pragma unroll
+  for (int u = 0; u < YI; ++u) {
+    const int k = u * NW + wave;
+    const int64_t col = n0 + 4 * (lane ^ f32_ysw(k));
+    yoff[u] = (uint32_t)(((int64_t)k * p.ldy + (col < N ? col : N - 4) - n0) * 4);
+  }
+  const float* xbase = X + m0 * p.ldx;
+  const float* ybase = Y + n0;
+  auto issue = [&](int kt) {
+    const uint32_t st = ring_lds + (uint32_t)((kt % NST) * SBYTES);
+    const float* xb = xbase + (int64_t)kt * BK;
+    const float* yb = ybase + (int64_t)kt * BK * p.ldy;
+#pragma unroll
+    for (int u = 0; u < XI; ++u) lds_dma16s(xb, xoff[u], st + (uint32_t)((u * NW + wave) * 1024));
+#pragma unroll
+    for (int u = 0; u < YI; ++u)
+      lds_dma16s(yb, yoff[u], st + (uint32_t)(XBYTES + (u * NW + wave) * 1024));
+  };
+
+  // Operand byte offsets within a stage.  A, k-group g, fragment i (+ 2048 i):
+  // row wm 64 + r, chunk 4 g + q.  B, fragment j, step s of group g
+  // (+ 256 (j / 4) + 1024 (16 g + s)): row 4 q, column chunk wn 32 + r / 4 + 4 j
+  // at position (wn 32 + r / 4) | 4 (j ^ q).
+  const int r = lane & 15, q = lane >> 4;
+  int offa[2], offb[4];
+#pragma unroll
+  for (int g = 0; g < 2; ++g) offa[g] = (wm * WTM + r) * 128 + (((4 * g + q) ^ f32_xsw(r)) * 16);
+#pragma unroll
+  for (int jl = 0; jl < 4; ++jl)
+    offb[jl] = XBYTES + q * 4096 + (wn * 32 + (r >> 2)) * 16 + ((jl ^ q) * 64) + (r & 3) * 4;
+
+  auto read_a = [&](int kt, int g, f32x4 (&a)[FM]) {
+    const unsigned char* stage = ring + (kt % NST) * SBYTES;
+#pragma unroll
+    for (int i = 0; i < FM; ++i)
+      a[i] = *reinterpret_cast<const f32x4*>(stage + offa[g] + i * 2048);
+  };
+  auto read_b = [&](int kt, int t, float (&b)[FN]) {   // step t = 4 g + s of the slab
+    const unsigned char* stage = ring + (kt % NST) * SBYTES + (16 * (t >> 2) + (t & 3)) * 1024;
+#pragma unroll
+    for (int j = 0; j < FN; ++j)
+      b[j] = *reinterpret_cast<const float*>(stage + offb[j & 3] + (j >> 2) * 256);
+  };
+
+  f32x4 acc[FM][FN];
+#pragma unroll
+  for (int i = 0; i < FM; ++i)
+#pragma unroll
+    for (int j = 0; j < FN; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+  // A is read a k-group (four steps) ahead, B a step ahead.  Slab kt + 1
+  // lands during the MFMAs of slab kt; the barrier before slab kt's last step
+  // (every wave then holds all its operands of slab kt) makes it visible and
+  // frees slab kt's stage for slab kt + 2.
+  const int nk = (int)(K / BK);
+  f32x4 fa[2][FM];
+  float fb[2][FN];
+  if (nk > 0) {
+    issue(0);
+    if (nk > 1) {
+      issue(1);
+      dma_wait_barrier<XI + YI>();
+    } else {
+      dma_wait_barrier<0>();
+    }
+    read_a(0, 0, fa[0]);
+    read_b(0, 0, fb[0]);
+  }
+  for (int kt = 0; kt < nk; ++kt) {
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+      if (t == 0) read_a(kt, 1, fa[1]);
+      if (t < 7) {
+        read_b(kt, t + 1, fb[(t + 1) & 1]);
+      } else if (kt + 1 < nk) {
+        dma_wait_barrier<0>();
+        if (kt + 2 < nk) issue(kt + 2);
+        read_a(kt + 1, 0, fa[0]);
+        read_b(kt + 1, 0, fb[0]);
+      }
+      const int g = t >> 2, sidx = t & 3;
+#pragma unroll
+      for (int i = 0; i < FM; ++i)
+#pragma unroll
+        for (int j = 0; j < FN; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(fa[g][i][sidx], fb[t & 1][j], acc[i][j],
+                                                           0, 0, 0);
+      // Each step's region: the next step's LDS reads first, then its
+      // MFMAs (the default schedule sinks the reads to the end of the step,
+      // where their latency shows).
+      __builtin_amdgcn_sched_group_barrier(0x100, 8, 0);
+      __builtin_amdgcn_sched_group_barrier(0x008, FM * FN, 0);
+      __builtin_amdgcn_sched_barrier(0);
+    }
+  }
+
+  // The next fragment's addends are loaded before the current one's stores;
+  // fragments by compile-time index (a run-time index would put acc in
+  // scratch).
+  double ss = 0.0;
+  float e1[2][4], e2[2][4];
+  auto frag_col = [&](int f) { return n0 + wn * WTN + (f % FN) * 16 + r; };
+  auto frag_r0 = [&](int f) { return m0 + wm * WTM + (f / FN) * 16 + 4 * q; };
+  {
+    const int64_t r00 = frag_r0(0);
+    load_addends<4>(p, frag_col(0), [r00](int e) { return r00 + e; }, e1[0], e2[0]);
+  }
+  static_for<0, FM * FN>([&](auto fc) {
+    constexpr int f = decltype(fc)::value;
+    if constexpr (f + 1 < FM * FN) {
+      const int64_t rn = frag_r0(f + 1);
+      load_addends<4>(p, frag_col(f + 1), [rn](int e) { return rn + e; }, e1[(f + 1) & 1],
+                      e2[(f + 1) & 1]);
+    }
+    const int64_t col = frag_col(f), r0 = frag_r0(f);
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int64_t row = r0 + e;
+      if (row < M && col < N)
+        put(p, row, col, acc[f / FN][f % FN][e], e1[f & 1][e], e2[f & 1][e], ss);
+    }
+  });
+  write_partial<NW>(p, ss, red, tm, tn, tiles_n);
 }
 
 // ---------------------------------------------------------------------------
@@ -1346,11 +1543,17 @@ int64_t launch_gemm_f32_nn(const GemmLpArgs& a, hipStream_t st) {
                    ((reinterpret_cast<uintptr_t>(a.X) & 15) == 0) &&
                    ((reinterpret_cast<uintptr_t>(a.Y) & 15) == 0);
   const int tc = tile_choice(kTileF32, a.M, a.N);
-  const bool big = tc ? tc == 128 : big_tiles(a.M, a.N);
-  const int bm = big ? 128 : 64;
+  // 256 x 256 tiles (LDS DMA) by the rule once they fill the CUs.
+  const bool dma = NSR_F32_DMA && vec && (a.K % kF32DmaBK) == 0 && (a.N % 4) == 0 &&
+                   (a.ldx % 4) == 0 && (a.ldy % 4) == 0;
+  const bool huge = dma && (tc ? tc == 256 : ((a.M + 255) / 256) * ((a.N + 255) / 256) >= device_cus());
+  const bool big = !huge && (tc ? tc == 128 || tc == 256 : big_tiles(a.M, a.N));
+  const int bm = huge ? 256 : (big ? 128 : 64);
   const int tiles_m = (int)((a.M + bm - 1) / bm), tiles_n = (int)((a.N + bm - 1) / bm);
   dim3 grid((unsigned)((int64_t)tiles_m * tiles_n)), block(256);
-  if (big) {
+  if (huge) {
+    hipLaunchKernelGGL(gemm_f32_nn_dma_kernel, grid, dim3(512), 0, st, a, tiles_m, tiles_n);
+  } else if (big) {
     if (vec) hipLaunchKernelGGL((gemm_f32_nn_kernel<128, 128, 32, true>), grid, block, 0, st, a, tiles_m, tiles_n);
     else hipLaunchKernelGGL((gemm_f32_nn_kernel<128, 128, 32, false>), grid, block, 0, st, a, tiles_m, tiles_n);
   } else {

@@ -194,6 +194,15 @@ __device__ __forceinline__ void lds_dma16(const void* src, uint32_t lds) {
                : "memory");
 }
 
+// The same with a wave-uniform base address and a 32-bit per-lane byte offset
+// (one VGPR per instruction instead of a pair).
+__device__ __forceinline__ void lds_dma16s(const void* base, uint32_t off, uint32_t lds) {
+  asm volatile("s_mov_b32 m0, %2\n\ts_nop 0\n\tglobal_load_lds_dwordx4 %0, %1"
+               :
+               : "v"(off), "s"(base), "s"(lds)
+               : "memory");
+}
+
 // Wait until at most CNT of this wave's DMA instructions are outstanding and
 // its LDS reads are complete, then the workgroup barrier.
 template <int CNT>

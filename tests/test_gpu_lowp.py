@@ -332,6 +332,41 @@ def test_gemm_bf16_full_size_sampled(torch):
         assert abs(Dc[i, j] - ref) <= bound, (i, j)
 
 
+@pytest.mark.parametrize("addends", [0, 2])
+@pytest.mark.parametrize("m,n,k", [(300, 520, 32), (513, 260, 64), (1000, 700, 96),
+                                   (2100, 1900, 1024), (4100, 4000, 224)])
+def test_gemm_f32_dma_tiles(torch, m, n, k, addends):
+    """The 256 x 256 float32 tiles fed by LDS DMA (K a multiple of 32, N of
+    4): one to many slabs (the two-stage ring's start, wrap and drain),
+    ragged edge tiles, every epilogue form, within the element-wise bound."""
+    b = int(np.ceil(np.log2(max(m, n))))
+    nsr.tile_set(nsr.TILE_F32, b, 256)
+    try:
+        g = torch.Generator(device="cpu").manual_seed(m * 5 + n * 11 + k)
+        X = torch.randn(m, k, generator=g, dtype=torch.float32)
+        Y = torch.randn(k, n, generator=g, dtype=torch.float32)
+        E = [torch.randn(m, n, generator=g, dtype=torch.float32) for _ in range(addends)]
+        diag, scale = 0.75, -1.25
+        print(f"f32 dma tiles {m}x{n}x{k} addends {addends}", flush=True)
+        D, Db, ss = nsr.gemm_lp(X.cuda(), Y.cuda(), nt=False, want_bf16=True,
+                                E1=E[0].cuda() if addends > 0 else None,
+                                E2=E[1].cuda() if addends > 1 else None,
+                                diag=diag, scale=scale, want_sumsq=True)
+        torch.cuda.synchronize()
+    finally:
+        nsr.tile_set(nsr.TILE_F32, b, 0)
+    Xd, Yd = X.double().numpy(), Y.double().numpy()
+    Ed = [e.double().numpy() for e in E]
+    ref = scale * (Xd @ Yd) + diag * np.eye(m, n) + sum(Ed, np.zeros((m, n)))
+    bound = g32(k + 4) * (abs(scale) * (np.abs(Xd) @ np.abs(Yd)) + diag * np.eye(m, n)
+                          + sum((np.abs(e) for e in Ed), np.zeros((m, n))))
+    got = D.double().cpu().numpy()
+    assert np.all(np.abs(got - ref) <= 2 * bound), float(np.max(np.abs(got - ref) / bound))
+    assert torch.equal(Db.cpu(), D.cpu().to(torch.bfloat16))
+    ssr = float(np.sum(got * got))
+    assert abs(float(ss.cpu()) - ssr) <= 1e-12 * ssr
+
+
 def test_gemm_f32_full_size_sampled(torch):
     n = 8192
     g = torch.Generator(device="cuda").manual_seed(8)
