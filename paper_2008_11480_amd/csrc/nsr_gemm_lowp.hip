@@ -368,15 +368,13 @@ gemm_f32_nn_dma_kernel(GemmLpArgs p, int tiles_m, int tiles_n) {
   }
   const float* xbase = X + m0 * p.ldx;
   const float* ybase = Y + n0;
-  auto issue = [&](int kt) {
+  // Part h (0 .. 3) of slab kt's DMA: X instruction h and Y instruction h.
+  static_assert(XI == 4 && YI == 4, "DMA parts");
+  auto issue_part = [&](int kt, int h) {
     const uint32_t st = ring_lds + (uint32_t)((kt % NST) * SBYTES);
-    const float* xb = xbase + (int64_t)kt * BK;
-    const float* yb = ybase + (int64_t)kt * BK * p.ldy;
-#pragma unroll
-    for (int u = 0; u < XI; ++u) lds_dma16s(xb, xoff[u], st + (uint32_t)((u * NW + wave) * 1024));
-#pragma unroll
-    for (int u = 0; u < YI; ++u)
-      lds_dma16s(yb, yoff[u], st + (uint32_t)(XBYTES + (u * NW + wave) * 1024));
+    lds_dma16s(xbase + (int64_t)kt * BK, xoff[h], st + (uint32_t)((h * NW + wave) * 1024));
+    lds_dma16s(ybase + (int64_t)kt * BK * p.ldy, yoff[h],
+               st + (uint32_t)(XBYTES + (h * NW + wave) * 1024));
   };
 
   // Operand byte offsets within a stage.  A, k-group g, fragment i (+ 2048 i):
@@ -410,21 +408,19 @@ gemm_f32_nn_dma_kernel(GemmLpArgs p, int tiles_m, int tiles_n) {
 #pragma unroll
     for (int j = 0; j < FN; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
 
-  // A is read a k-group (four steps) ahead, B a step ahead.  Slab kt + 1
-  // lands during the MFMAs of slab kt; the barrier before slab kt's last step
-  // (every wave then holds all its operands of slab kt) makes it visible and
-  // frees slab kt's stage for slab kt + 2.
+  // A is read a k-group (four steps) ahead, B a step ahead.  Slab kt + 1's
+  // DMA is issued in four parts over slab kt's first four steps (all at once
+  // it queues 64 instructions on the CU's address unit behind the barrier) into
+  // the stage slab kt - 1 used; the barrier before slab kt's last step (every
+  // wave then holds all its operands of slab kt) makes it visible and frees
+  // slab kt's stage.
   const int nk = (int)(K / BK);
   f32x4 fa[2][FM];
   float fb[2][FN];
   if (nk > 0) {
-    issue(0);
-    if (nk > 1) {
-      issue(1);
-      dma_wait_barrier<XI + YI>();
-    } else {
-      dma_wait_barrier<0>();
-    }
+#pragma unroll
+    for (int h = 0; h < 4; ++h) issue_part(0, h);
+    dma_wait_barrier<0>();
     read_a(0, 0, fa[0]);
     read_b(0, 0, fb[0]);
   }
@@ -434,12 +430,15 @@ gemm_f32_nn_dma_kernel(GemmLpArgs p, int tiles_m, int tiles_n) {
       if (t == 0) read_a(kt, 1, fa[1]);
       if (t < 7) {
         read_b(kt, t + 1, fb[(t + 1) & 1]);
-      } else if (kt + 1 < nk) {
+      } else {
+        // Also after the last slab (the reads are then unused): with the
+        // reads on every path the compiler's LDS wait before this step's
+        // MFMAs does not count them.
         dma_wait_barrier<0>();
-        if (kt + 2 < nk) issue(kt + 2);
         read_a(kt + 1, 0, fa[0]);
         read_b(kt + 1, 0, fb[0]);
       }
+      if (t < 4 && kt + 1 < nk) issue_part(kt + 1, t);
       const int g = t >> 2, sidx = t & 3;
 #pragma unroll
       for (int i = 0; i < FM; ++i)
