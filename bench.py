@@ -973,8 +973,9 @@ def main():
                                                "residual 1e-10", "seed": w["seed"]},
             "bf16/fp32 (fp64 refinement)",
             roofline_of(mx["m"]["gemm"]["f32"], "f32",
-                        "gemm_f32_nn_kernel<128,128,32> (float32 MFMA 16x16x4: residual, "
-                        "G-side and merge products)", traffic_per_launch("f32")),
+                        "gemm_f32_nn_dma_kernel (256x256 tiles, LDS DMA, float32 MFMA "
+                        "16x16x4: residual, G-side and merge products)",
+                        traffic_per_launch("f32")),
             mx["m"]["ms_per_solve"])
         out["roofline"]["note"] = PEAK_NOTE
         out["fp64"] = {

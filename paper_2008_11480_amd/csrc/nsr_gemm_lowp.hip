@@ -820,12 +820,19 @@ gemm_bf16_nt_dma_kernel(GemmLpArgs p, int tiles_m, int tiles_n) {
     for (int t = 0; t < T; ++t) {
       if (t + 1 < T) {
         read_frags(kt, t + 1, fa[(t + 1) & 1], fb[(t + 1) & 1]);
-      } else if (kt + 1 < nk) {
+      } else {
+        // Also after the last slab (the reads are then unused): with the
+        // reads on every path the compiler's LDS wait before this step's
+        // MFMAs does not count them.
         wait_slab(kt + 1);
         if (kt + NST < nk) issue(kt + NST);
         read_frags(kt + 1, 0, fa[0], fb[0]);
       }
       mfmas(fa[t & 1], fb[t & 1]);
+      // Each step's region: the next step's LDS reads first, then its MFMAs.
+      __builtin_amdgcn_sched_group_barrier(0x100, FM + FN, 0);
+      __builtin_amdgcn_sched_group_barrier(0x008, FM * FN, 0);
+      __builtin_amdgcn_sched_barrier(0);
     }
   }
   if (NSR_LP_SETPRIO) __builtin_amdgcn_s_setprio(0);
