@@ -334,11 +334,14 @@ def test_gemm_bf16_full_size_sampled(torch):
 
 @pytest.mark.parametrize("addends", [0, 2])
 @pytest.mark.parametrize("m,n,k", [(300, 520, 32), (513, 260, 64), (1000, 700, 96),
-                                   (2100, 1900, 1024), (4100, 4000, 224)])
+                                   (2100, 1900, 1024), (4100, 4000, 224),
+                                   (257, 259, 64), (300, 256, 100)])
 def test_gemm_f32_dma_tiles(torch, m, n, k, addends):
     """The 256 x 256 float32 tiles fed by LDS DMA (K a multiple of 32, N of
     4): one to many slabs (the two-stage ring's start, wrap and drain),
-    ragged edge tiles, every epilogue form, within the element-wise bound."""
+    ragged edge tiles, every epilogue form, within the element-wise bound.
+    The last two shapes miss the DMA requirements (N = 259, K = 100): the
+    256 tile then falls back to the 128 x 128 kernel."""
     b = int(np.ceil(np.log2(max(m, n))))
     nsr.tile_set(nsr.TILE_F32, b, 256)
     try:
