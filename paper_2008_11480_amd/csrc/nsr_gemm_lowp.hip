@@ -48,6 +48,11 @@
 #ifndef NSR_F32_DMA
 #define NSR_F32_DMA 1
 #endif
+// 1: 256 x 256 split half-precision tiles use the LDS-DMA kernel where its
+// requirements hold.
+#ifndef NSR_F16S_DMA
+#define NSR_F16S_DMA 1
+#endif
 // 1: 256 x 256 bf16 tiles use the LDS-DMA kernel where its requirements hold.
 #ifndef NSR_BF16_DMA
 #define NSR_BF16_DMA 1
@@ -1256,6 +1261,171 @@ gemm_f16s_nt_kernel(GemmLpArgs p, int tiles_m, int tiles_n) {
   write_partial<WGM * WGN>(p, ss, red, tm, tn, tiles_n);
 }
 
+// Split half-precision NT product, 256 x 256 tiles fed by LDS DMA: the
+// bf16 DMA kernel's layout with four operand planes (X hi, X lo, Y hi, Y lo;
+// rows of 64 bytes, 32 K per slab, chunks permuted by dma_swz<4>) and three
+// MFMA products per 16-k step.  Two 64 KB stages; the DMA sources are a
+// wave-uniform plane base plus 32-bit per-lane offsets.  Requires K a
+// multiple of 32, row strides multiples of 8 halves and 16-byte aligned
+// planes.
+constexpr int kF16sDmaBK = 32;
+
+__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2)))
+gemm_f16s_nt_dma_kernel(GemmLpArgs p, int tiles_m, int tiles_n) {
+  constexpr int BK = kF16sDmaBK, NST = 2, NW = 8, WGN = 4;
+  constexpr int WTM = 128, WTN = 64, FM = 4, FN = 2;
+  constexpr int RB = BK * 2, CH = BK / 8, RPI = 64 / CH, T = BK / 16;
+  constexpr int PB = 256 * RB;                  // bytes of one plane's slab
+  constexpr int SBYTES = 4 * PB;                // X hi, X lo, Y hi, Y lo
+  constexpr int PI = (256 / RPI) / NW;          // DMA instructions per wave, plane and slab
+  static_assert(PI * NW * RPI == 256 && T == 2, "DMA split");
+  __shared__ __attribute__((aligned(1024))) unsigned char ring[NST * SBYTES];
+  __shared__ double red[NW];
+
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int wm = wave / WGN, wn = wave % WGN;
+  int tm, tn;
+  map_tile_lp(blockIdx.x, tiles_m, tiles_n, tm, tn);
+  const int64_t m0 = (int64_t)tm * 256, n0 = (int64_t)tn * 256;
+  const int64_t M = p.M, N = p.N, K = p.K;
+  const uint32_t ring_lds = lds_addr(&ring[0]);
+
+  // Plane bases at the tile's first row (wave-uniform) and per-lane byte
+  // offsets: instruction u of this wave covers tile rows (u NW + wave) RPI
+  // .. + RPI - 1 of each plane.
+  const uint16_t* base[4] = {
+      static_cast<const uint16_t*>(p.X) + m0 * p.ldx, static_cast<const uint16_t*>(p.Xl) + m0 * p.ldx,
+      static_cast<const uint16_t*>(p.Y) + n0 * p.ldy, static_cast<const uint16_t*>(p.Yl) + n0 * p.ldy};
+  uint32_t xoff[PI], yoff[PI];
+#pragma unroll
+  for (int u = 0; u < PI; ++u) {
+    const int row = (u * NW + wave) * RPI + lane / CH;
+    const int c = (lane % CH) ^ dma_swz<CH>(row);
+    const int64_t gx = (m0 + row < M ? m0 + row : M - 1) - m0;
+    const int64_t gy = (n0 + row < N ? n0 + row : N - 1) - n0;
+    xoff[u] = (uint32_t)((gx * p.ldx + 8 * c) * 2);
+    yoff[u] = (uint32_t)((gy * p.ldy + 8 * c) * 2);
+  }
+  auto issue = [&](int kt) {
+    const uint32_t st = ring_lds + (uint32_t)((kt % NST) * SBYTES);
+    const int64_t k0 = (int64_t)kt * BK;
+#pragma unroll
+    for (int h = 0; h < 4; ++h)
+#pragma unroll
+      for (int u = 0; u < PI; ++u)
+        lds_dma16s(base[h] + k0, h < 2 ? xoff[u] : yoff[u],
+                   st + (uint32_t)(h * PB + (u * NW + wave) * 1024));
+  };
+
+  f32x16 acc[FM][FN];
+#pragma unroll
+  for (int i = 0; i < FM; ++i)
+#pragma unroll
+    for (int j = 0; j < FN; ++j) acc[i][j] = f32x16{};
+
+  const int lr = lane & 31, lk = lane >> 5;
+  const int sw = dma_swz<CH>(lr);
+  int offa[T], offb[T];
+#pragma unroll
+  for (int t = 0; t < T; ++t) {
+    const int chunk = ((2 * t + lk) ^ sw) * 16;
+    offa[t] = (wm * WTM + lr) * RB + chunk;
+    offb[t] = 2 * PB + (wn * WTN + lr) * RB + chunk;
+  }
+  struct Ops {
+    f16x8 ah[FM], al[FM], bh[FN], bl[FN];
+  };
+  auto read_ops = [&](int s, int t, Ops& o) {
+    const unsigned char* stage = ring + (s % NST) * SBYTES;
+#pragma unroll
+    for (int i = 0; i < FM; ++i) {
+      o.ah[i] = *reinterpret_cast<const f16x8*>(stage + offa[t] + i * 32 * RB);
+      o.al[i] = *reinterpret_cast<const f16x8*>(stage + PB + offa[t] + i * 32 * RB);
+    }
+#pragma unroll
+    for (int j = 0; j < FN; ++j) {
+      o.bh[j] = *reinterpret_cast<const f16x8*>(stage + offb[t] + j * 32 * RB);
+      o.bl[j] = *reinterpret_cast<const f16x8*>(stage + PB + offb[t] + j * 32 * RB);
+    }
+  };
+  auto mfmas = [&](const Ops& o) {
+    // Small terms first; each accumulator gets FM x FN independent products
+    // between its updates.
+#pragma unroll
+    for (int i = 0; i < FM; ++i)
+#pragma unroll
+      for (int j = 0; j < FN; ++j)
+        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_f16(o.al[i], o.bh[j], acc[i][j], 0, 0, 0);
+#pragma unroll
+    for (int i = 0; i < FM; ++i)
+#pragma unroll
+      for (int j = 0; j < FN; ++j)
+        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_f16(o.ah[i], o.bl[j], acc[i][j], 0, 0, 0);
+#pragma unroll
+    for (int i = 0; i < FM; ++i)
+#pragma unroll
+      for (int j = 0; j < FN; ++j)
+        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_f16(o.ah[i], o.bh[j], acc[i][j], 0, 0, 0);
+  };
+
+  // Slab kt + 1's DMA is issued right after the barrier that confirms slab
+  // kt (every wave then holds its operands of slab kt - 1, whose stage it
+  // overwrites); each step's operands are read before the previous step's
+  // MFMAs, across the slab boundary too, and the boundary reads are issued
+  // on every path (see the bf16 kernel).
+  const int nk = (int)(K / BK);
+  Ops o[2];
+  if (nk > 0) {
+    issue(0);
+    dma_wait_barrier<0>();
+    if (nk > 1) issue(1);
+    read_ops(0, 0, o[0]);
+  }
+  if (NSR_LP_SETPRIO) __builtin_amdgcn_s_setprio(1);
+  for (int kt = 0; kt < nk; ++kt) {
+#pragma unroll
+    for (int t = 0; t < T; ++t) {
+      if (t + 1 < T) {
+        read_ops(kt, t + 1, o[(t + 1) & 1]);
+      } else {
+        dma_wait_barrier<0>();
+        if (kt + 2 < nk) issue(kt + 2);
+        read_ops(kt + 1, 0, o[0]);
+      }
+      mfmas(o[t & 1]);
+      __builtin_amdgcn_sched_group_barrier(0x100, 2 * (FM + FN), 0);
+      __builtin_amdgcn_sched_group_barrier(0x008, 3 * FM * FN, 0);
+      __builtin_amdgcn_sched_barrier(0);
+    }
+  }
+  if (NSR_LP_SETPRIO) __builtin_amdgcn_s_setprio(0);
+
+  // Undo the operand scales (powers of two: exact unless the result
+  // underflows), then the shared epilogue.
+  const float fx = p.xexp ? ldexpf(1.0f, -(int)p.xexp[0]) : 1.0f;
+  const float fy = p.yexp ? ldexpf(1.0f, -(int)p.yexp[0]) : 1.0f;
+  double ss = 0.0;
+#pragma unroll
+  for (int f = 0; f < FM * FN; ++f) {
+    const int64_t col = n0 + wn * WTN + (f % FN) * 32 + lr;
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int64_t r0 = m0 + wm * WTM + (f / FN) * 32 + 16 * h + 4 * lk;
+      const auto row_of = [r0](int r) { return r0 + 8 * (r >> 2) + (r & 3); };
+      float e1[8], e2[8];
+      load_addends<8>(p, col, row_of, e1, e2);
+#pragma unroll
+      for (int r = 0; r < 8; ++r) {
+        const int64_t row = row_of(r);
+        if (row < M && col < N)
+          put(p, row, col, acc[f / FN][f % FN][8 * h + r] * fx * fy, e1[r], e2[r], ss);
+      }
+    }
+  }
+  write_partial<NW>(p, ss, red, tm, tn, tiles_n);
+}
+
 // ---------------------------------------------------------------------------
 // bf16, NT, symmetric output
 // ---------------------------------------------------------------------------
@@ -1653,7 +1823,10 @@ int64_t launch_gemm_f16s_nt(const GemmLpArgs& a, hipStream_t st) {
   dim3 grid((unsigned)((int64_t)tiles_m * tiles_n)), block(256);
   if (huge) {
     dim3 block8(512);
-    if (vec) hipLaunchKernelGGL((gemm_f16s_nt_kernel<256, 256, 32, true, 2, 4>), grid, block8, 0, st, a, tiles_m, tiles_n);
+    const bool dma = NSR_F16S_DMA && vec && (a.K % kF16sDmaBK) == 0 && (a.ldx % 8) == 0 &&
+                     (a.ldy % 8) == 0;
+    if (dma) hipLaunchKernelGGL(gemm_f16s_nt_dma_kernel, grid, block8, 0, st, a, tiles_m, tiles_n);
+    else if (vec) hipLaunchKernelGGL((gemm_f16s_nt_kernel<256, 256, 32, true, 2, 4>), grid, block8, 0, st, a, tiles_m, tiles_n);
     else hipLaunchKernelGGL((gemm_f16s_nt_kernel<256, 256, 32, false, 2, 4>), grid, block8, 0, st, a, tiles_m, tiles_n);
   } else if (big) {
     if (vec) hipLaunchKernelGGL((gemm_f16s_nt_kernel<128, 128, 32, true>), grid, block, 0, st, a, tiles_m, tiles_n);

@@ -105,6 +105,42 @@ def test_gemm_f32_split_elementwise(torch, m, n, k, addends):
     assert abs(float(ss.cpu()) - ssr) <= 1e-12 * ssr
 
 
+@pytest.mark.parametrize("addends", [0, 2])
+@pytest.mark.parametrize("m,n,k", [(300, 520, 32), (1000, 700, 96), (2100, 1900, 1024),
+                                   (4100, 4000, 224), (300, 256, 100)])
+def test_gemm_f32_split_dma_tiles(torch, m, n, k, addends):
+    """The 256 x 256 split tiles fed by LDS DMA (K a multiple of 32): one to
+    many slabs, ragged edge tiles, every epilogue form; the last shape
+    (K = 100) falls back to the register-staged kernel."""
+    b = int(np.ceil(np.log2(max(m, n))))
+    nsr.tile_set(nsr.TILE_F16S, b, 256)
+    try:
+        g = torch.Generator(device="cpu").manual_seed(m * 3 + n * 17 + k)
+        X = torch.randn(m, k, generator=g, dtype=torch.float32)
+        Y = torch.randn(k, n, generator=g, dtype=torch.float32)
+        E = [torch.randn(m, n, generator=g, dtype=torch.float32) for _ in range(addends)]
+        diag, scale = 0.75, -1.25
+        print(f"split dma tiles {m}x{n}x{k} addends {addends}", flush=True)
+        D, Db, ss = nsr.gemm_f32_split(X.cuda(), Y.cuda(), want_bf16=True,
+                                       E1=E[0].cuda() if addends > 0 else None,
+                                       E2=E[1].cuda() if addends > 1 else None,
+                                       diag=diag, scale=scale, want_sumsq=True)
+        torch.cuda.synchronize()
+    finally:
+        nsr.tile_set(nsr.TILE_F16S, b, 0)
+    Xd, Yd = X.double().numpy(), Y.double().numpy()
+    Ed = [e.double().numpy() for e in E]
+    ref = scale * (Xd @ Yd) + diag * np.eye(m, n) + sum(Ed, np.zeros((m, n)))
+    bound = split_bound(Xd, Yd, scale, k) + g32(k + 4) * (
+        abs(diag) * np.eye(m, n) + sum((np.abs(e) for e in Ed), np.zeros((m, n))))
+    bound = bound + g32(4) * np.abs(ref)
+    got = D.double().cpu().numpy()
+    assert np.all(np.abs(got - ref) <= 2 * bound), float(np.max(np.abs(got - ref) / bound))
+    assert torch.equal(Db.cpu(), D.cpu().to(torch.bfloat16))
+    ssr = float(np.sum(got * got))
+    assert abs(float(ss.cpu()) - ssr) <= 1e-12 * ssr
+
+
 @pytest.mark.parametrize("sx,sy", [(1e-8, 1e6), (3e12, 2e-15), (1.0, 1e-30)])
 def test_gemm_f32_split_operand_scales(torch, sx, sy):
     """Operands far outside the half-precision range are scaled into it (the
