@@ -29,9 +29,12 @@
 // D[8 (r/4) + 4 (l/32) + r % 4][l % 32], and the bf16 operand element e of
 // lane l is K index 8 (l/32) + e.
 //
-// Tiling as in the float64 GEMM: 128 x 128 workgroup tile, 4 waves of 64 x 64,
-// K slabs staged global -> registers (one slab ahead) -> two LDS buffers,
-// XCD-aware grouped tile order, two workgroups per CU.
+// Tiling: large outputs take 256 x 256 workgroup tiles of eight waves whose
+// K slabs go from global memory straight into a ring of LDS stages
+// (global_load_lds_dwordx4), one workgroup per CU; smaller outputs take the
+// float64 GEMM's scheme (128 x 128 or 64 x 64 tiles, 4 waves, K slabs staged
+// global -> registers (one slab ahead) -> two LDS buffers, two workgroups per
+// CU).  Every kernel walks its tiles in an XCD-aware grouped order.
 #include "nsr_internal.h"
 
 #ifndef NSR_BF16_HUGE
@@ -1752,8 +1755,8 @@ int64_t launch_gemm_bf16_nt(const GemmLpArgs& a, hipStream_t st) {
   const int tiles_m = (int)((a.M + bm - 1) / bm), tiles_n = (int)((a.N + bm - 1) / bm);
   dim3 grid((unsigned)((int64_t)tiles_m * tiles_n)), block(256);
   if (huge) {
-    // 256 x 256 tiles, eight waves of 128 x 64: a quarter of the L2 -> LDS
-    // bytes per flop of the 128 x 128 tile, which saturates the L2.
+    // 256 x 256 tiles, eight waves of 128 x 64: half the L2 -> LDS bytes per
+    // flop of the 128 x 128 tile, which saturates the L2.
     dim3 block8(512);
     const bool dma = NSR_BF16_DMA && vec && (a.K % kDmaBK) == 0 && (a.ldx % 8) == 0 &&
                      (a.ldy % 8) == 0;
