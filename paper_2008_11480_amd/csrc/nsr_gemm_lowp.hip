@@ -1723,8 +1723,10 @@ int64_t launch_gemm_f32_nn(const GemmLpArgs& a, hipStream_t st) {
                    ((reinterpret_cast<uintptr_t>(a.Y) & 15) == 0);
   const int tc = tile_choice(kTileF32, a.M, a.N);
   // 256 x 256 tiles (LDS DMA) by the rule once they fill the CUs.
+  // (The DMA sources are 32-bit byte offsets within 256 rows of X and 32 of Y.)
   const bool dma = NSR_F32_DMA && vec && (a.K % kF32DmaBK) == 0 && (a.N % 4) == 0 &&
-                   (a.ldx % 4) == 0 && (a.ldy % 4) == 0;
+                   (a.ldx % 4) == 0 && (a.ldy % 4) == 0 && a.ldx < (1 << 22) &&
+                   a.ldy < (1 << 24);
   const bool huge = dma && (tc ? tc == 256 : ((a.M + 255) / 256) * ((a.N + 255) / 256) >= device_cus());
   const bool big = !huge && (tc ? tc == 128 || tc == 256 : big_tiles(a.M, a.N));
   const int bm = huge ? 256 : (big ? 128 : 64);
@@ -1826,8 +1828,9 @@ int64_t launch_gemm_f16s_nt(const GemmLpArgs& a, hipStream_t st) {
   dim3 grid((unsigned)((int64_t)tiles_m * tiles_n)), block(256);
   if (huge) {
     dim3 block8(512);
+    // (The DMA sources are 32-bit byte offsets within 256 rows of a plane.)
     const bool dma = NSR_F16S_DMA && vec && (a.K % kF16sDmaBK) == 0 && (a.ldx % 8) == 0 &&
-                     (a.ldy % 8) == 0;
+                     (a.ldy % 8) == 0 && a.ldx < (1 << 23) && a.ldy < (1 << 23);
     if (dma) hipLaunchKernelGGL(gemm_f16s_nt_dma_kernel, grid, block8, 0, st, a, tiles_m, tiles_n);
     else if (vec) hipLaunchKernelGGL((gemm_f16s_nt_kernel<256, 256, 32, true, 2, 4>), grid, block8, 0, st, a, tiles_m, tiles_n);
     else hipLaunchKernelGGL((gemm_f16s_nt_kernel<256, 256, 32, false, 2, 4>), grid, block8, 0, st, a, tiles_m, tiles_n);
