@@ -56,6 +56,10 @@
 #ifndef NSR_F16S_DMA
 #define NSR_F16S_DMA 1
 #endif
+// Chunks of addends the bf16 LDS-DMA kernel's epilogue loads ahead.
+#ifndef NSR_BF16_EPI_PD
+#define NSR_BF16_EPI_PD 2
+#endif
 // 1: 256 x 256 bf16 tiles use the LDS-DMA kernel where its requirements hold.
 #ifndef NSR_BF16_DMA
 #define NSR_BF16_DMA 1
@@ -859,23 +863,37 @@ gemm_bf16_nt_dma_kernel(GemmLpArgs p, int tiles_m, int tiles_n) {
         }
       }
   } else {
-#pragma unroll
-    for (int f = 0; f < FM * FN; ++f) {
-      const int64_t col = n0 + wn * WTN + (f % FN) * 32 + lr;
-#pragma unroll
-      for (int h = 0; h < 2; ++h) {
-        const int64_t r0 = m0 + wm * WTM + (f / FN) * 32 + 16 * h + 4 * lk;
-        const auto row_of = [r0](int r) { return r0 + 8 * (r >> 2) + (r & 3); };
-        float e1[8], e2[8];
-        load_addends<8>(p, col, row_of, e1, e2);
-#pragma unroll
-        for (int r = 0; r < 8; ++r) {
-          const int64_t row = row_of(r);
-          if (row < M && col < N)
-            put(p, row, col, acc[f / FN][f % FN][8 * h + r], e1[r], e2[r], ss);
-        }
+    // Chunks of four rows of one fragment column; the addends of chunk c + PD
+    // are loaded before chunk c's stores (loads and stores complete in issue
+    // order, so a load issued after a store waits for it), and the chunks go
+    // by compile-time index (a run-time one puts acc in scratch).
+    constexpr int NC = FM * FN * 4, PD = NSR_BF16_EPI_PD;
+    auto chunk_col = [&](int c) { return n0 + wn * WTN + ((c >> 2) % FN) * 32 + lr; };
+    auto chunk_r0 = [&](int c) {
+      return m0 + wm * WTM + ((c >> 2) / FN) * 32 + 8 * (c & 3) + 4 * lk;
+    };
+    float e1[PD + 1][4], e2[PD + 1][4];
+    static_for<0, PD>([&](auto cc) {
+      constexpr int c = decltype(cc)::value;
+      const int64_t q0 = chunk_r0(c);
+      load_addends<4>(p, chunk_col(c), [q0](int r) { return q0 + r; }, e1[c], e2[c]);
+    });
+    static_for<0, NC>([&](auto cc) {
+      constexpr int c = decltype(cc)::value;
+      if constexpr (c + PD < NC) {
+        const int64_t qn = chunk_r0(c + PD);
+        load_addends<4>(p, chunk_col(c + PD), [qn](int r) { return qn + r; },
+                        e1[(c + PD) % (PD + 1)], e2[(c + PD) % (PD + 1)]);
       }
-    }
+      const int64_t col = chunk_col(c), q = chunk_r0(c);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t row = q + r;
+        if (row < M && col < N)
+          put(p, row, col, acc[(c >> 2) / FN][(c >> 2) % FN][4 * (c & 3) + r],
+              e1[c % (PD + 1)][r], e2[c % (PD + 1)][r], ss);
+      }
+    });
   }
   write_partial<NW>(p, ss, red, tm, tn, tiles_n);
 }
