@@ -56,6 +56,10 @@
 #ifndef NSR_F16S_DMA
 #define NSR_F16S_DMA 1
 #endif
+// Fragments of addends the float32 LDS-DMA kernel's epilogue loads ahead.
+#ifndef NSR_F32_EPI_PD
+#define NSR_F32_EPI_PD 4
+#endif
 // Chunks of addends the bf16 LDS-DMA kernel's epilogue loads ahead.
 #ifndef NSR_BF16_EPI_PD
 #define NSR_BF16_EPI_PD 2
@@ -467,30 +471,33 @@ gemm_f32_nn_dma_kernel(GemmLpArgs p, int tiles_m, int tiles_n) {
     }
   }
 
-  // The next fragment's addends are loaded before the current one's stores;
-  // fragments by compile-time index (a run-time index would put acc in
-  // scratch).
+  // The addends of fragment f + PD are loaded before fragment f's stores
+  // (loads and stores complete in issue order, so a load issued after a
+  // store waits for it); fragments by compile-time index (a run-time index
+  // would put acc in scratch).
+  constexpr int PD = NSR_F32_EPI_PD;
   double ss = 0.0;
-  float e1[2][4], e2[2][4];
+  float e1[PD + 1][4], e2[PD + 1][4];
   auto frag_col = [&](int f) { return n0 + wn * WTN + (f % FN) * 16 + r; };
   auto frag_r0 = [&](int f) { return m0 + wm * WTM + (f / FN) * 16 + 4 * q; };
-  {
-    const int64_t r00 = frag_r0(0);
-    load_addends<4>(p, frag_col(0), [r00](int e) { return r00 + e; }, e1[0], e2[0]);
-  }
+  static_for<0, PD>([&](auto fc) {
+    constexpr int f = decltype(fc)::value;
+    const int64_t r0 = frag_r0(f);
+    load_addends<4>(p, frag_col(f), [r0](int e) { return r0 + e; }, e1[f], e2[f]);
+  });
   static_for<0, FM * FN>([&](auto fc) {
     constexpr int f = decltype(fc)::value;
-    if constexpr (f + 1 < FM * FN) {
-      const int64_t rn = frag_r0(f + 1);
-      load_addends<4>(p, frag_col(f + 1), [rn](int e) { return rn + e; }, e1[(f + 1) & 1],
-                      e2[(f + 1) & 1]);
+    if constexpr (f + PD < FM * FN) {
+      const int64_t rn = frag_r0(f + PD);
+      load_addends<4>(p, frag_col(f + PD), [rn](int e) { return rn + e; },
+                      e1[(f + PD) % (PD + 1)], e2[(f + PD) % (PD + 1)]);
     }
     const int64_t col = frag_col(f), r0 = frag_r0(f);
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
       const int64_t row = r0 + e;
       if (row < M && col < N)
-        put(p, row, col, acc[f / FN][f % FN][e], e1[f & 1][e], e2[f & 1][e], ss);
+        put(p, row, col, acc[f / FN][f % FN][e], e1[f % (PD + 1)][e], e2[f % (PD + 1)][e], ss);
     }
   });
   write_partial<NW>(p, ss, red, tm, tn, tiles_n);
