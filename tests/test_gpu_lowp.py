@@ -406,6 +406,42 @@ def test_gemm_f32_dma_tiles(torch, m, n, k, addends):
     assert abs(float(ss.cpu()) - ssr) <= 1e-12 * ssr
 
 
+@pytest.mark.parametrize("nt", [False, True])
+@pytest.mark.parametrize("shift", [0, 1])
+def test_gemm_dma_strided_operands(torch, nt, shift):
+    """256-tile products on strided views: row strides larger than the
+    operand (the DMA sources step by the stride, not the width); with shift
+    = 1 the views start one element in, so the rows are not 16-byte aligned
+    and the products take the register-staged kernels instead."""
+    m, n, k = 700, 520, 96
+    fam = nsr.TILE_BF16 if nt else nsr.TILE_F32
+    b = int(np.ceil(np.log2(max(m, n))))
+    nsr.tile_set(fam, b, 256)
+    try:
+        g = torch.Generator(device="cpu").manual_seed(91 + shift + 2 * nt)
+        dt = torch.bfloat16 if nt else torch.float32
+        bigx = torch.randn(m, k + 40, generator=g).to(dt)
+        bigy = torch.randn(n, k + 24, generator=g).to(dt) if nt else \
+            torch.randn(k, n + 24, generator=g).to(dt)
+        X = bigx.cuda()[:, shift:shift + k]
+        Y = bigy.cuda()[:, shift:shift + k] if nt else bigy.cuda()[:, shift:shift + n]
+        E = torch.randn(m, n, generator=g, dtype=torch.float32)
+        print(f"dma strided nt={nt} shift={shift}", flush=True)
+        D, _, _ = nsr.gemm_lp(X, Y, nt=nt, E1=E.cuda(), diag=1.0, scale=-0.5)
+        torch.cuda.synchronize()
+    finally:
+        nsr.tile_set(fam, b, 0)
+    Xd = X.cpu().double().numpy()
+    Yd = Y.cpu().double().numpy()
+    P = Xd @ (Yd.T if nt else Yd)
+    Pa = np.abs(Xd) @ (np.abs(Yd).T if nt else np.abs(Yd))
+    Ed = E.double().numpy()
+    ref = -0.5 * P + np.eye(m, n) + Ed
+    bound = g32(k + 4) * (0.5 * Pa + np.eye(m, n) + np.abs(Ed))
+    got = D.double().cpu().numpy()
+    assert np.all(np.abs(got - ref) <= 2 * bound), float(np.max(np.abs(got - ref) / bound))
+
+
 def test_gemm_f32_full_size_sampled(torch):
     n = 8192
     g = torch.Generator(device="cuda").manual_seed(8)
