@@ -328,19 +328,21 @@ gemm_f32_nn_kernel(GemmLpArgs p, int tiles_m, int tiles_n) {
 // row and slab), a Y row N (1 KB per k).  One 16-byte read gives a lane the A
 // operands of four MFMA steps: in k-group g (16 k) lane (r, q) = (lane % 16,
 // lane / 16) holds X[row][16 g + 4 q + j] for step j, so its B operand in
-// step j is Y[16 g + 4 q + j][col].  The 16-byte chunks of every LDS row are
-// permuted so that both operand reads spread over all 64 banks: chunk c of X
-// row R sits at c ^ f32_xsw(R) (R mod 16 decides which bank half and window a
-// lane of a 16-lane read group hits), chunk c of Y row k at c ^ f32_ysw(k)
-// (the four k rows of one B read, 4 apart, land in different 16-bank
-// windows).  Requires K a multiple of 32, N a multiple of 4, row strides
-// multiples of 4 floats and 16-byte aligned operands; rows past M and columns
-// past N of edge tiles read row M - 1 and the last four columns instead and
-// feed only outputs that are not stored.
+// step j is Y[16 g + 4 q + j][col].  One 16-byte read of a Y row gives the B
+// operands of four fragments: fragment j of a wave's 64-column half takes the
+// columns 4 r + j, so lane (r, q) reads columns 4 r .. 4 r + 3 of the half,
+// and after the K loop it holds four adjacent columns of each output row it
+// owns (stored with one 16-byte access where the output allows).  The 16-byte
+// chunks of an X row are permuted, chunk c of row R at c ^ f32_xsw(R) (R mod
+// 16 decides which bank half and window a lane of a 16-lane read group hits),
+// so that the A reads spread over all 64 banks; the B reads do unpermuted
+// (a group's lanes read 16 different chunks).  Requires K a multiple of 32,
+// N a multiple of 4, row strides multiples of 4 floats and 16-byte aligned
+// operands; rows past M and columns past N of edge tiles read row M - 1 and
+// the last four columns instead and feed only outputs that are not stored.
 constexpr int kF32DmaBK = 32;
 
 __device__ __forceinline__ int f32_xsw(int row) { return (row & 2) | ((row >> 1) & 4); }
-__device__ __forceinline__ int f32_ysw(int k) { return ((k >> 2) & 3) << 2; }
 
 __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2)))
 gemm_f32_nn_dma_kernel(GemmLpArgs p, int tiles_m, int tiles_n) {
@@ -379,7 +381,7 @@ gemm_f32_nn_dma_kernel(GemmLpArgs p, int tiles_m, int tiles_n) {
 #pragma unroll
   for (int u = 0; u < YI; ++u) {
     const int k = u * NW + wave;
-    const int64_t col = n0 + 4 * (lane ^ f32_ysw(k));
+    const int64_t col = n0 + 4 * lane;
     yoff[u] = (uint32_t)(((int64_t)k * p.ldy + (col < N ? col : N - 4) - n0) * 4);
   }
   const float* xbase = X + m0 * p.ldx;
@@ -394,16 +396,13 @@ gemm_f32_nn_dma_kernel(GemmLpArgs p, int tiles_m, int tiles_n) {
   };
 
   // Operand byte offsets within a stage.  A, k-group g, fragment i (+ 2048 i):
-  // row wm 64 + r, chunk 4 g + q.  B, fragment j, step s of group g
-  // (+ 256 (j / 4) + 1024 (16 g + s)): row 4 q, column chunk wn 32 + r / 4 + 4 j
-  // at position (wn 32 + r / 4) | 4 (j ^ q).
+  // row wm 64 + r, chunk 4 g + q.  B, half h of the wave's columns, step s of
+  // group g (+ 256 h + 1024 (16 g + s)): row 4 q, columns wn 128 + 4 r .. + 3.
   const int r = lane & 15, q = lane >> 4;
-  int offa[2], offb[4];
+  int offa[2];
 #pragma unroll
   for (int g = 0; g < 2; ++g) offa[g] = (wm * WTM + r) * 128 + (((4 * g + q) ^ f32_xsw(r)) * 16);
-#pragma unroll
-  for (int jl = 0; jl < 4; ++jl)
-    offb[jl] = XBYTES + q * 4096 + (wn * 32 + (r >> 2)) * 16 + ((jl ^ q) * 64) + (r & 3) * 4;
+  const int offb = XBYTES + q * 4096 + wn * 512 + 16 * r;
 
   auto read_a = [&](int kt, int g, f32x4 (&a)[FM]) {
     const unsigned char* stage = ring + (kt % NST) * SBYTES;
@@ -414,8 +413,11 @@ gemm_f32_nn_dma_kernel(GemmLpArgs p, int tiles_m, int tiles_n) {
   auto read_b = [&](int kt, int t, float (&b)[FN]) {   // step t = 4 g + s of the slab
     const unsigned char* stage = ring + (kt % NST) * SBYTES + (16 * (t >> 2) + (t & 3)) * 1024;
 #pragma unroll
-    for (int j = 0; j < FN; ++j)
-      b[j] = *reinterpret_cast<const float*>(stage + offb[j & 3] + (j >> 2) * 256);
+    for (int h = 0; h < FN / 4; ++h) {
+      const f32x4 v = *reinterpret_cast<const f32x4*>(stage + offb + h * 256);
+#pragma unroll
+      for (int jj = 0; jj < 4; ++jj) b[4 * h + jj] = v[jj];
+    }
   };
 
   f32x4 acc[FM][FN];
@@ -471,33 +473,80 @@ gemm_f32_nn_dma_kernel(GemmLpArgs p, int tiles_m, int tiles_n) {
     }
   }
 
-  // The addends of fragment f + PD are loaded before fragment f's stores
-  // (loads and stores complete in issue order, so a load issued after a
-  // store waits for it); fragments by compile-time index (a run-time index
-  // would put acc in scratch).
-  constexpr int PD = NSR_F32_EPI_PD;
+  // Output unit u = (fragment row i, column half h, element e): the lane's
+  // row wm 64 + 16 i + 4 q + e and columns wn 128 + 64 h + 4 r .. + 3, the
+  // values acc[i][4 h + jj][e].  Where every output and addend allows it the
+  // four columns go as one 16-byte access (the bf16 copy as one 8-byte one);
+  // the addends of unit u + PD are loaded before unit u's stores (loads and
+  // stores complete in issue order, so a load issued after a store waits for
+  // it); units by compile-time index (a run-time index would put acc in
+  // scratch).
+  constexpr int PD = NSR_F32_EPI_PD, NU = FM * (FN / 4) * 4;
+  const bool vec = (!p.D || (((uintptr_t)p.D & 15) == 0 && (p.ldd & 3) == 0)) &&
+                   (!p.Db || (((uintptr_t)p.Db & 7) == 0 && (p.lddb & 3) == 0)) &&
+                   (!p.E1 || (((uintptr_t)p.E1 & 15) == 0 && (p.lde1 & 3) == 0)) &&
+                   (!p.E2 || (((uintptr_t)p.E2 & 15) == 0 && (p.lde2 & 3) == 0));
   double ss = 0.0;
-  float e1[PD + 1][4], e2[PD + 1][4];
-  auto frag_col = [&](int f) { return n0 + wn * WTN + (f % FN) * 16 + r; };
-  auto frag_r0 = [&](int f) { return m0 + wm * WTM + (f / FN) * 16 + 4 * q; };
-  static_for<0, PD>([&](auto fc) {
-    constexpr int f = decltype(fc)::value;
-    const int64_t r0 = frag_r0(f);
-    load_addends<4>(p, frag_col(f), [r0](int e) { return r0 + e; }, e1[f], e2[f]);
-  });
-  static_for<0, FM * FN>([&](auto fc) {
-    constexpr int f = decltype(fc)::value;
-    if constexpr (f + PD < FM * FN) {
-      const int64_t rn = frag_r0(f + PD);
-      load_addends<4>(p, frag_col(f + PD), [rn](int e) { return rn + e; },
-                      e1[(f + PD) % (PD + 1)], e2[(f + PD) % (PD + 1)]);
+  f32x4 e1[PD + 1], e2[PD + 1];
+  auto unit_row = [&](int u) { return m0 + wm * WTM + 16 * (u >> 3) + 4 * q + (u & 3); };
+  auto unit_col = [&](int u) { return n0 + wn * WTN + 64 * ((u >> 2) & 1) + 4 * r; };
+  auto load4 = [&](int u, f32x4& a1, f32x4& a2) {
+    const int64_t row = unit_row(u), col = unit_col(u);
+    a1 = f32x4{0.f, 0.f, 0.f, 0.f};
+    a2 = a1;
+    if (row >= M) return;
+    if (vec && col + 3 < N) {
+      if (p.E1) a1 = *reinterpret_cast<const f32x4*>(p.E1 + row * p.lde1 + col);
+      if (p.E2) a2 = *reinterpret_cast<const f32x4*>(p.E2 + row * p.lde2 + col);
+      return;
     }
-    const int64_t col = frag_col(f), r0 = frag_r0(f);
 #pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      const int64_t row = r0 + e;
-      if (row < M && col < N)
-        put(p, row, col, acc[f / FN][f % FN][e], e1[f % (PD + 1)][e], e2[f % (PD + 1)][e], ss);
+    for (int jj = 0; jj < 4; ++jj)
+      if (col + jj < N) {
+        if (p.E1) a1[jj] = p.E1[row * p.lde1 + col + jj];
+        if (p.E2) a2[jj] = p.E2[row * p.lde2 + col + jj];
+      }
+  };
+  static_for<0, PD>([&](auto uc) {
+    constexpr int u = decltype(uc)::value;
+    load4(u, e1[u], e2[u]);
+  });
+  static_for<0, NU>([&](auto uc) {
+    constexpr int u = decltype(uc)::value;
+    if constexpr (u + PD < NU) load4(u + PD, e1[(u + PD) % (PD + 1)], e2[(u + PD) % (PD + 1)]);
+    constexpr int i = u >> 3, h = (u >> 2) & 1, e = u & 3, b = u % (PD + 1);
+    const int64_t row = unit_row(u), col = unit_col(u);
+    if (row < M) {
+      f32x4 v;
+#pragma unroll
+      for (int jj = 0; jj < 4; ++jj) {
+        float x = p.scale * acc[i][4 * h + jj][e];
+        if (row == col + jj) x += p.diag;
+        if (p.E1) x += e1[b][jj];
+        if (p.E2) x += e2[b][jj];
+        v[jj] = x;
+      }
+      if (vec && col + 3 < N) {
+        if (p.D) *reinterpret_cast<f32x4*>(p.D + row * p.ldd + col) = v;
+        if (p.Db) {
+          uint2 w;
+          w.x = (uint32_t)__builtin_bit_cast(uint16_t, (__bf16)v[0]) |
+                ((uint32_t)__builtin_bit_cast(uint16_t, (__bf16)v[1]) << 16);
+          w.y = (uint32_t)__builtin_bit_cast(uint16_t, (__bf16)v[2]) |
+                ((uint32_t)__builtin_bit_cast(uint16_t, (__bf16)v[3]) << 16);
+          *reinterpret_cast<uint2*>(p.Db + row * p.lddb + col) = w;
+        }
+#pragma unroll
+        for (int jj = 0; jj < 4; ++jj) ss += (double)v[jj] * (double)v[jj];
+      } else {
+#pragma unroll
+        for (int jj = 0; jj < 4; ++jj)
+          if (col + jj < N) {
+            if (p.D) p.D[row * p.ldd + col + jj] = v[jj];
+            if (p.Db) p.Db[row * p.lddb + col + jj] = __builtin_bit_cast(uint16_t, (__bf16)v[jj]);
+            ss += (double)v[jj] * (double)v[jj];
+          }
+      }
     }
   });
   write_partial<NW>(p, ss, red, tm, tn, tiles_n);
