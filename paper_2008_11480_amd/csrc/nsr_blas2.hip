@@ -74,7 +74,7 @@ reduce_kernel(const double* __restrict__ partial, int64_t count, double* __restr
   sh[threadIdx.x] = v;
   __syncthreads();
   for (int w = kThreads / 2; w > 0; w >>= 1) {
-    if (threadIdx.x < w) {
+    if ((int)threadIdx.x < w) {
       const double a = sh[threadIdx.x], b = sh[threadIdx.x + w];
       sh[threadIdx.x] = is_max ? fmax(a, b) : a + b;
     }
