@@ -924,9 +924,8 @@ def main():
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py measures one GPU: the solver runs on a single MI355X "
-              "(DESIGN.md describes how the path would shard); --gpus must be 1.",
-              file=sys.stderr)
+        print("bench.py measures one GPU: the solver runs on a single MI355X; "
+              "--gpus must be 1.", file=sys.stderr)
         sys.exit(2)
 
     import torch

@@ -1,6 +1,6 @@
 """GPU parity: the HIP path (through the C ABI) against the CPU oracle.
 
-Tolerances (derived in DESIGN.md, "Parity tolerances"):
+Tolerances (each derived from the arithmetic it bounds):
 * GEMM: |D - D_ref|_ij <= gamma_{k+4} (|s| |X||Y| + |diag| I + |E1| + |E2|)_ij,
   gamma_m = m u / (1 - m u), for both the kernel and the reference dot product.
 * ||F_k||_F traces: |d| <= 1e-10 ||F_k|| + 10 * floor, floor = the smallest
