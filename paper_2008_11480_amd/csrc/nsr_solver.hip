@@ -1759,7 +1759,7 @@ int ns_gemm_bf16_nt_ws(void* hip_stream, int64_t m, int64_t n, int64_t k, const 
                          E2, lde2, diag, scale, sumsq_out);
   if (flags & ~NS_GEMM_SYMMETRIC) return fail(NS_EINVAL, "unknown flags %d", flags);
   if (!kBf16SymEnabled)
-    return fail(NS_EINVAL, "the symmetric-output bf16 kernel is disabled in this build");
+    return fail(NS_EINVAL, "the symmetric-output bf16 kernel is disabled");
   if (m != n) return fail(NS_EINVAL, "a symmetric output needs m == n");
   if (m < 0 || k < 0) return fail(NS_EINVAL, "negative size");
   if (m == 0) return NS_OK;
