@@ -46,6 +46,10 @@
 #ifndef NSR_F64_SETPRIO
 #define NSR_F64_SETPRIO 1
 #endif
+// 1: full products of large outputs use the 256 x 128 LDS-DMA kernel.
+#ifndef NSR_F64_DMA
+#define NSR_F64_DMA 1
+#endif
 // Row padding (doubles) of the X and Y slabs in LDS.
 #ifndef NSR_F64_XPAD
 #define NSR_F64_XPAD 2
@@ -493,6 +497,224 @@ gemm_f64_split_fixup(GemmF64Args p, int tiles_m, int tiles_n, int dp, int splits
   }
 }
 
+// Full (not symmetric-output) products of large outputs: 256 x 128 tiles fed
+// by LDS DMA, eight waves of 64 x 64 (one workgroup per CU, two waves per
+// SIMD), K in 16-deep slabs that global_load_lds_dwordx4 writes into two
+// LDS stages (an X slab: 256 rows of 128 B; a Y slab: 16 rows of 1 KB).
+// One 16-byte read gives a lane the A operands of two MFMA steps: in
+// k-group g (8 k) lane (r, q) = (lane % 16, lane / 16) holds
+// X[row][8 g + 2 q + j] for step j, so its B operand in that step is
+// Y[8 g + 2 q + j][col]; one 16-byte read of a Y row gives the B operands of
+// two fragments (fragment jj of a wave's 32-column half takes the columns
+// 2 r + jj), so after the K loop a lane holds two adjacent columns of each
+// output row it owns and the epilogue moves them as one 16-byte access where
+// the output allows.  X rows put chunk c at c ^ f64_xsw(R) (R mod 16 decides
+// which bank half and window a lane of a 16-lane read group hits); the B
+// reads need no permutation.  Requires K a multiple of 16, N even, even row
+// strides and 16-byte aligned operands; rows past M and columns past N of
+// edge tiles read row M - 1 and the last two columns instead and feed only
+// outputs that are not stored.
+constexpr int kF64DmaBK = 16;
+
+__device__ __forceinline__ int f64_xsw(int row) { return (row & 2) | ((row >> 1) & 4); }
+
+typedef double f64x2 __attribute__((ext_vector_type(2)));
+
+__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2)))
+gemm_f64_nn_dma_kernel(GemmF64Args p, int tiles_m, int tiles_n) {
+  constexpr int BM = 256, BN = 128, BK = kF64DmaBK, NW = 8, NST = 2;
+  constexpr int WTM = 64, WTN = 64, FM = WTM / 16, FN = WTN / 16;
+  constexpr int XBYTES = BM * BK * 8;            // 256 rows of 128 B
+  constexpr int SBYTES = XBYTES + BK * BN * 8;   // + 16 rows of 1 KB
+  constexpr int XI = BM / 8 / NW, YI = BK / NW;  // DMA instructions per wave and slab
+  static_assert(XI == 4 && YI == 2 && BN == 128, "DMA split");
+  __shared__ __attribute__((aligned(1024))) unsigned char ring[NST * SBYTES];
+  __shared__ double red[NW];
+
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int wm = wave >> 1, wn = wave & 1;
+  int tm, tn;
+  group_tile(xcd_perm(blockIdx.x, tiles_m * tiles_n), tiles_m, tiles_n, tm, tn);
+  const int64_t m0 = (int64_t)tm * BM, n0 = (int64_t)tn * BN;
+  const int64_t M = p.M, N = p.N, K = p.K;
+  const uint32_t ring_lds = lds_addr(&ring[0]);
+
+  // DMA sources, as byte offsets from the slab's wave-uniform base: X
+  // instruction u of this wave covers tile rows (u NW + wave) 8 .. + 7, Y
+  // instruction u slab row k = u NW + wave.
+  uint32_t xoff[XI], yoff[YI];
+#pragma unroll
+  for (int u = 0; u < XI; ++u) {
+    const int row = (u * NW + wave) * 8 + (lane >> 3);
+    const int c = (lane & 7) ^ f64_xsw(row);
+    const int64_t g = (m0 + row < M ? m0 + row : M - 1) - m0;
+    xoff[u] = (uint32_t)((g * p.ldx + 2 * c) * 8);
+  }
+#pragma unroll
+  for (int u = 0; u < YI; ++u) {
+    const int k = u * NW + wave;
+    const int64_t col = n0 + 2 * lane;
+    yoff[u] = (uint32_t)(((int64_t)k * p.ldy + (col < N ? col : N - 2) - n0) * 8);
+  }
+  const double* xbase = p.X + m0 * p.ldx;
+  const double* ybase = p.Y + n0;
+  // Part h of slab kt's DMA: X instructions 2 h, 2 h + 1 and Y instruction h.
+  auto issue_part = [&](int kt, int h) {
+    const uint32_t st = ring_lds + (uint32_t)((kt % NST) * SBYTES);
+    const double* xb = xbase + (int64_t)kt * BK;
+#pragma unroll
+    for (int v = 0; v < 2; ++v)
+      lds_dma16s(xb, xoff[2 * h + v], st + (uint32_t)(((2 * h + v) * NW + wave) * 1024));
+    lds_dma16s(ybase + (int64_t)kt * BK * p.ldy, yoff[h],
+               st + (uint32_t)(XBYTES + (h * NW + wave) * 1024));
+  };
+
+  // Operand byte offsets within a stage.  A, k-group g, fragment i (+ 2048 i):
+  // row wm 64 + r, chunk 4 g + q.  B, half h of the wave's columns, step j of
+  // group g (+ 256 h + 1024 (8 g + j)): row 2 q, columns wn 64 + 2 r, + 1.
+  const int r = lane & 15, q = lane >> 4;
+  int offa[2];
+#pragma unroll
+  for (int g = 0; g < 2; ++g) offa[g] = (wm * WTM + r) * 128 + (((4 * g + q) ^ f64_xsw(r)) * 16);
+  const int offb = XBYTES + q * 2048 + wn * 512 + 16 * r;
+  auto read_a = [&](int kt, int g, f64x2 (&a)[FM]) {
+    const unsigned char* stage = ring + (kt % NST) * SBYTES;
+#pragma unroll
+    for (int i = 0; i < FM; ++i) a[i] = *reinterpret_cast<const f64x2*>(stage + offa[g] + i * 2048);
+  };
+  auto read_b = [&](int kt, int t, double (&b)[FN]) {   // step t = 2 g + j of the slab
+    const unsigned char* stage = ring + (kt % NST) * SBYTES + (8 * (t >> 1) + (t & 1)) * 1024;
+#pragma unroll
+    for (int h = 0; h < FN / 2; ++h) {
+      const f64x2 v = *reinterpret_cast<const f64x2*>(stage + offb + h * 256);
+      b[2 * h] = v[0];
+      b[2 * h + 1] = v[1];
+    }
+  };
+
+  f64x4 acc[FM][FN];
+#pragma unroll
+  for (int i = 0; i < FM; ++i)
+#pragma unroll
+    for (int j = 0; j < FN; ++j) acc[i][j] = f64x4{0.0, 0.0, 0.0, 0.0};
+
+  // A is read a k-group (two steps) ahead, B a step ahead.  Slab kt + 1's DMA
+  // is issued in two parts over slab kt's first two steps into the stage slab
+  // kt - 1 used; the barrier before slab kt's last step (every wave then
+  // holds all its operands of slab kt) makes it visible and frees slab kt's
+  // stage.
+  const int nk = (int)(K / BK);
+  f64x2 fa[2][FM];
+  double fb[2][FN];
+  if (nk > 0) {
+    issue_part(0, 0);
+    issue_part(0, 1);
+    dma_wait_barrier<0>();
+    read_a(0, 0, fa[0]);
+    read_b(0, 0, fb[0]);
+  }
+  for (int kt = 0; kt < nk; ++kt) {
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      if (t == 0) read_a(kt, 1, fa[1]);
+      if (t < 3) {
+        read_b(kt, t + 1, fb[(t + 1) & 1]);
+      } else {
+        // Also after the last slab (the reads are then unused): with the
+        // reads on every path the compiler's LDS wait before this step's
+        // MFMAs does not count them.
+        dma_wait_barrier<0>();
+        read_a(kt + 1, 0, fa[0]);
+        read_b(kt + 1, 0, fb[0]);
+      }
+      if (t < 2 && kt + 1 < nk) issue_part(kt + 1, t);
+      const int g = t >> 1, jstep = t & 1;
+#pragma unroll
+      for (int i = 0; i < FM; ++i)
+#pragma unroll
+        for (int j = 0; j < FN; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[g][i][jstep], fb[t & 1][j], acc[i][j],
+                                                           0, 0, 0);
+      // Each step's region: the next step's LDS reads first, then its MFMAs.
+      __builtin_amdgcn_sched_group_barrier(0x100, 8, 0);
+      __builtin_amdgcn_sched_group_barrier(0x008, FM * FN, 0);
+      __builtin_amdgcn_sched_barrier(0);
+    }
+  }
+
+  // Output unit u = (fragment row i, column half h, element e): the lane's
+  // row wm 64 + 16 i + q + 4 e and columns wn 64 + 32 h + 2 r, + 1, the values
+  // acc[i][2 h + jj][e].  Where every output and addend allows it the two
+  // columns go as one 16-byte access; the addends of unit u + PD are loaded
+  // before unit u's stores (loads and stores complete in issue order); units
+  // by compile-time index (a run-time index would put acc in scratch).
+  constexpr int PD = 4, NU = FM * (FN / 2) * 4;
+  const bool vec = ((uintptr_t)p.D & 15) == 0 && (p.ldd & 1) == 0 &&
+                   (!p.E1 || (((uintptr_t)p.E1 & 15) == 0 && (p.lde1 & 1) == 0)) &&
+                   (!p.E2 || (((uintptr_t)p.E2 & 15) == 0 && (p.lde2 & 1) == 0));
+  double ss = 0.0;
+  f64x2 e1[PD + 1], e2[PD + 1];
+  auto unit_row = [&](int u) { return m0 + wm * WTM + 16 * (u >> 3) + q + 4 * (u & 3); };
+  auto unit_col = [&](int u) { return n0 + wn * WTN + 32 * ((u >> 2) & 1) + 2 * r; };
+  auto load2 = [&](int u, f64x2& a1, f64x2& a2) {
+    const int64_t row = unit_row(u), col = unit_col(u);
+    a1 = f64x2{0.0, 0.0};
+    a2 = a1;
+    if (row >= M) return;
+    if (vec && col + 1 < N) {
+      if (p.E1) a1 = *reinterpret_cast<const f64x2*>(p.E1 + row * p.lde1 + col);
+      if (p.E2) a2 = *reinterpret_cast<const f64x2*>(p.E2 + row * p.lde2 + col);
+      return;
+    }
+#pragma unroll
+    for (int jj = 0; jj < 2; ++jj)
+      if (col + jj < N) {
+        if (p.E1) a1[jj] = p.E1[row * p.lde1 + col + jj];
+        if (p.E2) a2[jj] = p.E2[row * p.lde2 + col + jj];
+      }
+  };
+  static_for<0, PD>([&](auto uc) {
+    constexpr int u = decltype(uc)::value;
+    load2(u, e1[u], e2[u]);
+  });
+  static_for<0, NU>([&](auto uc) {
+    constexpr int u = decltype(uc)::value;
+    if constexpr (u + PD < NU) load2(u + PD, e1[(u + PD) % (PD + 1)], e2[(u + PD) % (PD + 1)]);
+    constexpr int i = u >> 3, h = (u >> 2) & 1, e = u & 3, b = u % (PD + 1);
+    const int64_t row = unit_row(u), col = unit_col(u);
+    if (row < M) {
+      f64x2 v;
+#pragma unroll
+      for (int jj = 0; jj < 2; ++jj)
+        v[jj] = epi_value(p, row, col + jj, acc[i][2 * h + jj][e], e1[b][jj], e2[b][jj]);
+      if (vec && col + 1 < N) {
+        *reinterpret_cast<f64x2*>(p.D + row * p.ldd + col) = v;
+        ss += v[0] * v[0] + v[1] * v[1];
+      } else {
+#pragma unroll
+        for (int jj = 0; jj < 2; ++jj)
+          if (col + jj < N) {
+            p.D[row * p.ldd + col + jj] = v[jj];
+            ss += v[jj] * v[jj];
+          }
+      }
+    }
+  });
+  if (p.partial) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) ss += __shfl_xor(ss, off, 64);
+    if (lane == 0) red[wave] = ss;
+    __syncthreads();
+    if (tid == 0) {
+      double t = 0.0;
+#pragma unroll
+      for (int w = 0; w < NW; ++w) t += red[w];
+      p.partial[(int64_t)tm * tiles_n + tn] = t;
+    }
+  }
+}
+
 // How one product is cut into workgroups.
 struct Plan {
   bool big = false;    // 128 x 128 tiles (else 64 x 64)
@@ -626,7 +848,7 @@ int tile_bucket(int64_t d) {
 
 bool tile_valid(int family, int tile) {
   if (tile == 0 || tile == 64 || tile == 128) return true;
-  return tile == 256 && (family == kTileF32 || family == kTileBf16 || family == kTileF16s);
+  return tile == 256;   // every family: float64 full products 256 x 128
 }
 }  // namespace
 
@@ -669,6 +891,22 @@ size_t gemm_f64_split_bytes(int64_t m, int64_t n, int64_t k, bool sym) {
 int64_t launch_gemm_f64(const GemmF64Args& a, hipStream_t st) {
   if (a.M <= 0 || a.N <= 0) return 0;
   if (a.sym && a.M != a.N) return -1;
+  // Full products of outputs that fill the CUs with 256 x 128 tiles take the
+  // LDS-DMA kernel where its requirements hold (the DMA sources are 32-bit
+  // byte offsets within 256 rows of X and 16 of Y).
+  const int tc = tile_choice(kTileF64, a.M, a.N);
+  const bool dma = NSR_F64_DMA && !a.sym && (a.K % kF64DmaBK) == 0 && (a.N % 2) == 0 &&
+                   (a.ldx % 2) == 0 && (a.ldy % 2) == 0 &&
+                   (reinterpret_cast<uintptr_t>(a.X) & 15) == 0 &&
+                   (reinterpret_cast<uintptr_t>(a.Y) & 15) == 0 && a.ldx < (1 << 21) &&
+                   a.ldy < (1 << 24);
+  const int tiles_m = (int)((a.M + 255) / 256), tiles_n = (int)((a.N + 127) / 128);
+  if (dma && (tc ? tc == 256 : (int64_t)tiles_m * tiles_n >= device_cus())) {
+    hipLaunchKernelGGL(gemm_f64_nn_dma_kernel, dim3((unsigned)(tiles_m * tiles_n)), dim3(512), 0,
+                       st, a, tiles_m, tiles_n);
+    if (hipGetLastError() != hipSuccess) return -1;
+    return a.partial ? (int64_t)tiles_m * tiles_n : 0;
+  }
   const Plan pl = plan_f64(a.M, a.N, a.K, a.sym != 0, a.sk ? a.sk_cap : 0);
   if (pl.big) return launch_cfg<128, 128, NSR_F64_BIG_BK, NSR_F64_BIG_NBUF>(a, pl, st);
   return launch_cfg<64, 64, 16, 2>(a, pl, st);

@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 namespace nsr {
 
 // D = diag * I + scale * (X Y) + E1 + E2 for row-major float64 operands.
@@ -208,6 +210,17 @@ __device__ __forceinline__ void lds_dma16s(const void* base, uint32_t off, uint3
 template <int CNT>
 __device__ __forceinline__ void dma_wait_barrier() {
   asm volatile("s_waitcnt vmcnt(%0) lgkmcnt(0)\n\ts_barrier" : : "n"(CNT) : "memory");
+}
+
+// fn(std::integral_constant<int, I>) for I = B .. E - 1, unrolled at compile
+// time (a loop the compiler only partly unrolls would index register arrays
+// at run time, which puts them in scratch).
+template <int B, int E, typename Fn>
+__device__ __forceinline__ void static_for(Fn&& fn) {
+  if constexpr (B < E) {
+    fn(std::integral_constant<int, B>{});
+    static_for<B + 1, E>(fn);
+  }
 }
 
 // LDS byte address of a shared-memory object (the low 32 bits of its

@@ -761,7 +761,7 @@ def gemm_f32_split(X, Y, D=None, want_bf16: bool = False, E1=None, E2=None,
 
 # GEMM families of the tile table (NS_TILE_* in include/nsr.h) and their tiles.
 TILE_F64, TILE_F32, TILE_BF16, TILE_F16S = 0, 1, 2, 3
-TILE_OPTIONS = {TILE_F64: (64, 128), TILE_F32: (64, 128, 256), TILE_BF16: (64, 128, 256),
+TILE_OPTIONS = {TILE_F64: (64, 128, 256), TILE_F32: (64, 128, 256), TILE_BF16: (64, 128, 256),
                 TILE_F16S: (64, 128, 256)}
 
 

@@ -72,6 +72,46 @@ def test_gemm_f64_elementwise(torch, m, n, k, odd_ld):
     assert abs(float(ss.cpu()) - ss_ref) <= 1e-13 * ss_ref
 
 
+@pytest.mark.parametrize("addends", [0, 2])
+@pytest.mark.parametrize("m,n,k,shift", [(300, 520, 32, 0), (513, 260, 64, 0),
+                                         (1000, 700, 96, 0), (2100, 1900, 1024, 0),
+                                         (4100, 4000, 224, 0), (700, 520, 96, 1),
+                                         (301, 259, 64, 0), (300, 256, 100, 0)])
+def test_gemm_f64_dma_tiles(torch, m, n, k, shift, addends):
+    """The 256 x 128 float64 tiles fed by LDS DMA (full products, K a
+    multiple of 16, N even): one to many slabs (the two-stage ring's start,
+    wrap and drain), ragged edge tiles, row strides above the width, every
+    epilogue form.  shift = 1 starts the operand views one element in (rows
+    not 16-byte aligned), N = 259 is odd and K = 100 not a multiple of 16:
+    those products take the register-staged kernel instead."""
+    b = int(np.ceil(np.log2(max(m, n))))
+    nsr.tile_set(nsr.TILE_F64, b, 256)
+    try:
+        rng = np.random.default_rng(m * 3 + n * 5 + k + addends)
+        Xb = rng.standard_normal((m, k + 8))
+        Yb = rng.standard_normal((k, n + 6))
+        E = [rng.standard_normal((m, n)) for _ in range(addends)]
+        X, Y = Xb[:, shift:shift + k], Yb[:, shift:shift + n]
+        diag, scale = 0.7, -1.3
+        print(f"f64 dma tiles {m}x{n}x{k} shift {shift} addends {addends}", flush=True)
+        D, ss = nsr.gemm_f64(to_dev(torch, Xb)[:, shift:shift + k],
+                             to_dev(torch, Yb)[:, shift:shift + n],
+                             E1=to_dev(torch, E[0]) if addends > 0 else None,
+                             E2=to_dev(torch, E[1]) if addends > 1 else None,
+                             diag=diag, scale=scale, want_sumsq=True)
+        torch.cuda.synchronize()
+    finally:
+        nsr.tile_set(nsr.TILE_F64, b, 0)
+    got = D.cpu().numpy()
+    ref = scale * (X @ Y) + diag * np.eye(m, n) + sum(E, np.zeros((m, n)))
+    bound = gamma(k + 4) * (abs(scale) * (np.abs(X) @ np.abs(Y)) + abs(diag) * np.eye(m, n)
+                            + sum((np.abs(e) for e in E), np.zeros((m, n))))
+    err = np.abs(got - ref)
+    assert np.all(err <= 2 * bound + 1e-300), float(np.max(err / (bound + 1e-300)))
+    ss_ref = float(np.sum(got * got))
+    assert abs(float(ss.cpu()) - ss_ref) <= 1e-13 * ss_ref
+
+
 @pytest.mark.parametrize("n", [1, 5, 64, 100, 257, 1000, 2900, 4096])
 def test_gemm_f64_symmetric_output(torch, n):
     """Symmetric output: the upper triangle obeys the element-wise bound, the

@@ -84,7 +84,7 @@ def test_every_tile_matches_reference(torch, family, m, n, k):
 
 
 def test_tile_set_rejects_unknown(torch):
-    for bad in ((4, 10, 64), (0, 24, 64), (nsr.TILE_F64, 10, 256), (nsr.TILE_F32, 10, 32)):
+    for bad in ((4, 10, 64), (0, 24, 64), (nsr.TILE_F64, 10, 512), (nsr.TILE_F32, 10, 32)):
         with pytest.raises(nsr.NSError):
             nsr.tile_set(*bad)
     assert nsr.tile_get(9, 0) == -1
