@@ -548,7 +548,10 @@ int ns_gemm_f32_split(void* hip_stream, int64_t m, int64_t n, int64_t k,
  * per family and size and keeps the fastest) overrides that rule per GEMM
  * family and size bucket: products whose output is m x n use the tile set
  * for bucket ceil(log2(max(m, n))).  Families: NS_TILE_F64 (ns_gemm_f64 and
- * the float64 solver products; tiles 64, 128), NS_TILE_F32 (float32 MFMA;
+ * the float64 solver products; tiles 64, 128, 256: the 256 x 128 tile serves
+ * full-output products with K a multiple of 16, N even, even leading
+ * dimensions and 16-byte aligned X and Y; symmetric-output products and
+ * other shapes then take the rule's choice of 64 or 128), NS_TILE_F32 (float32 MFMA;
  * 64, 128, 256: the 256 tile needs K a multiple of 32, N a multiple of 4 and
  * 16-byte aligned rows, and falls back to 128 otherwise), NS_TILE_BF16 (bf16
  * powers; 64, 128, 256), NS_TILE_F16S (split half-precision products; 64,

@@ -846,9 +846,10 @@ int tile_bucket(int64_t d) {
   return b;
 }
 
-bool tile_valid(int family, int tile) {
-  if (tile == 0 || tile == 64 || tile == 128) return true;
-  return tile == 256;   // every family: float64 full products 256 x 128
+// Every family has the tiles 64, 128 and 256 (float64: 256 x 128 for full
+// products); 0 selects the fitted rule.
+bool tile_valid(int /*family*/, int tile) {
+  return tile == 0 || tile == 64 || tile == 128 || tile == 256;
 }
 }  // namespace
 
