@@ -50,6 +50,11 @@
 #ifndef NSR_F64_DMA
 #define NSR_F64_DMA 1
 #endif
+// 1: the 128 x 128 tiles take their K slabs by LDS DMA where the operands
+// allow it.
+#ifndef NSR_F64_DMA128
+#define NSR_F64_DMA128 1
+#endif
 // Row padding (doubles) of the X and Y slabs in LDS.
 #ifndef NSR_F64_XPAD
 #define NSR_F64_XPAD 2
@@ -136,12 +141,31 @@ __device__ __forceinline__ void load_addends(const GemmF64Args& p, int64_t row0,
   }
 }
 
+// Row permutation of the 16-byte chunks of a 128-byte X slab row in the DMA
+// form of gemm_f64_kernel: rows R and R + 1 sit in opposite bank halves, and
+// (R >> 1) & 7 spreads the 16 rows of an MFMA operand read over the chunks,
+// so a read of one double per lane (16 rows x 4 k) touches every bank once
+// per 32 lanes.
+__device__ __forceinline__ int f64_rsw(int row) { return (row >> 1) & 7; }
+
 // Grid: the first dp workgroups own whole tiles (positions 0..dp-1 of the
 // tile order).  When splits > 0, the remaining tiles (the last, partial round)
 // are cut along K into `splits` slices of `slabs` K-slabs; workgroup dp + q
 // computes slice q % splits of tail tile q / splits and stores its raw
 // accumulators in p.sk (gemm_f64_split_fixup finishes those tiles).
-template <int BM, int BN, int BK, int NBUF, bool VEC, bool SYM>
+//
+// DMA (128 x 128 tiles, BK = 16, two stages; K a multiple of 16, N even, even
+// row strides, 16-byte aligned X and Y): the K slabs go from global memory
+// straight into LDS with global_load_lds_dwordx4, slab kt + 1 issued in two
+// parts during slab kt's first two MFMA steps, one barrier per slab.  X rows
+// (128 B) keep chunk c at c ^ f64_rsw(row); Y rows (1 KB) put chunk c at
+// c ^ 8 in odd k rows, so the two k rows a 32-lane read group touches use
+// opposite bank halves.  The MFMA sequence and the accumulator layout are
+// those of the register-staged loop (the results are the same bits), so the
+// epilogue, the mirror and the split tail are shared.  Rows past M and
+// columns past N of edge tiles read row M - 1 and the last two columns and
+// feed only outputs that are not stored.
+template <int BM, int BN, int BK, int NBUF, bool VEC, bool SYM, bool DMA = false>
 __global__ void __launch_bounds__(256)
 __attribute__((amdgpu_waves_per_eu(NSR_F64_WAVES_PER_EU)))
 gemm_f64_kernel(GemmF64Args p, int tiles_m, int tiles_n, int dp, int splits, int slabs) {
@@ -163,7 +187,10 @@ gemm_f64_kernel(GemmF64Args p, int tiles_m, int tiles_n, int dp, int splits, int
   constexpr int MS = BM + 1;                 // stride of the transposed staging
   constexpr int MIRROR = SYM ? WTN * MS : 0;
   constexpr int ARENA = MAIN > MIRROR ? MAIN : MIRROR;
-  __shared__ __attribute__((aligned(16))) double smem[ARENA];
+  static_assert(!DMA || (BM == 128 && BN == 128 && BK == 16 && NBUF == 2 && VEC),
+                "DMA form: 128 x 128 tiles, 16-deep slabs, two stages");
+  static_assert(!DMA || MAIN * 8 >= 2 * (BM * BK + BK * BN) * 8, "DMA ring fits the arena");
+  __shared__ __attribute__((aligned(1024))) double smem[ARENA];
   __shared__ double red[4];
   double (*Xs)[BM * XS] = reinterpret_cast<double (*)[BM * XS]>(smem);
   double (*Ys)[BK * YS] = reinterpret_cast<double (*)[BK * YS]>(smem + NBUF * BM * XS);
@@ -286,8 +313,101 @@ gemm_f64_kernel(GemmF64Args p, int tiles_m, int tiles_n, int dp, int splits, int
   }
   const int lr = lane & 15;
   const int lk = lane >> 4;
-  if (kt0 < kt1) load((int64_t)kt0 * BK);
-  for (int kt = kt0; kt < kt1; ++kt) {
+  if constexpr (DMA) {
+    constexpr int XB = BM * BK * 8;          // 128 rows of 128 B
+    constexpr int SB = XB + BK * BN * 8;     // + 16 rows of 1 KB
+    const uint32_t ring_lds = lds_addr(smem);
+    const unsigned char* ring = reinterpret_cast<const unsigned char*>(smem);
+    const int wv = __builtin_amdgcn_readfirstlane(wave);
+    // DMA sources as byte offsets from the slab's wave-uniform base: X
+    // instruction u of this wave covers tile rows (4 u + wave) 8 .. + 7, Y
+    // instruction u the slab row k = 4 u + wave.
+    uint32_t xoff[4], yoff[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int row = (4 * u + wv) * 8 + (lane >> 3);
+      const int c = (lane & 7) ^ f64_rsw(row);
+      const int64_t g = (m0 + row < M ? m0 + row : M - 1) - m0;
+      xoff[u] = (uint32_t)((g * p.ldx + 2 * c) * 8);
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int k = 4 * u + wv;
+      const int64_t col = n0 + 2 * (lane ^ ((k & 1) << 3));
+      yoff[u] = (uint32_t)(((int64_t)k * p.ldy + (col < N ? col : N - 2) - n0) * 8);
+    }
+    const double* xbase = p.X + m0 * p.ldx;
+    const double* ybase = p.Y + n0;
+    // Part h of slab kt: X and Y instructions 2 h and 2 h + 1.
+    auto issue_part = [&](int kt, int h) {
+      const uint32_t st = ring_lds + (uint32_t)((kt & 1) * SB);
+      const double* xb = xbase + (int64_t)kt * BK;
+      const double* yb = ybase + (int64_t)kt * BK * p.ldy;
+#pragma unroll
+      for (int v = 0; v < 2; ++v) {
+        const int u = 2 * h + v;
+        lds_dma16s(xb, xoff[u], st + (uint32_t)((4 * u + wv) * 1024));
+        lds_dma16s(yb, yoff[u], st + (uint32_t)(XB + (4 * u + wv) * 1024));
+      }
+    };
+    // Operand byte offsets within a stage for MFMA step t (k = 4 t + lk):
+    // A X[wm 64 + 16 i + lr][k] at offa[t] + 2048 i, B Y[k][wn 64 + 16 j + lr]
+    // at offb[j] + 4096 t.
+    const int sw = f64_rsw(lr);   // = f64_rsw of every row this lane reads
+    int offa[4], offb[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+      offa[t] = (wm * WTM + lr) * 128 + (((2 * t + (lk >> 1)) ^ sw) * 16) + (lk & 1) * 8;
+#pragma unroll
+    for (int j = 0; j < FN; ++j)
+      offb[j] = XB + lk * 1024 +
+                (((wn * WTN + 16 * j + lr) >> 1) ^ ((lk & 1) << 3)) * 16 + (lr & 1) * 8;
+    auto read_ops = [&](int kt, int t, double (&a)[FM], double (&b)[FN]) {
+      const unsigned char* stage = ring + (kt & 1) * SB;
+#pragma unroll
+      for (int i = 0; i < FM; ++i) a[i] = *reinterpret_cast<const double*>(stage + offa[t] + 2048 * i);
+#pragma unroll
+      for (int j = 0; j < FN; ++j)
+        b[j] = *reinterpret_cast<const double*>(stage + offb[j] + 4096 * t);
+    };
+    double fa[2][FM], fb[2][FN];
+    if (kt0 < kt1) {
+      issue_part(kt0, 0);
+      issue_part(kt0, 1);
+      dma_wait_barrier<0>();
+      read_ops(kt0, 0, fa[0], fb[0]);
+    }
+    if (NSR_F64_SETPRIO) __builtin_amdgcn_s_setprio(1);
+    for (int kt = kt0; kt < kt1; ++kt) {
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        if (t < 3) {
+          read_ops(kt, t + 1, fa[(t + 1) & 1], fb[(t + 1) & 1]);
+        } else {
+          // Slab kt + 1 has landed and every wave holds its slab-kt operands;
+          // the reads follow on every path (after the last slab they read a
+          // stage and go unused) so the compiler's LDS wait before this
+          // step's MFMAs does not count them.
+          dma_wait_barrier<0>();
+          read_ops(kt + 1, 0, fa[0], fb[0]);
+        }
+        if (t < 2 && kt + 1 < kt1) issue_part(kt + 1, t);
+#pragma unroll
+        for (int i = 0; i < FM; ++i)
+#pragma unroll
+          for (int j = 0; j < FN; ++j)
+            acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[t & 1][i], fb[t & 1][j], acc[i][j],
+                                                             0, 0, 0);
+        // Each step's region: the next step's LDS reads first, then its MFMAs.
+        __builtin_amdgcn_sched_group_barrier(0x100, FM + FN, 0);
+        __builtin_amdgcn_sched_group_barrier(0x008, FM * FN, 0);
+        __builtin_amdgcn_sched_barrier(0);
+      }
+    }
+    if (NSR_F64_SETPRIO) __builtin_amdgcn_s_setprio(0);
+  }
+  if (!DMA && kt0 < kt1) load((int64_t)kt0 * BK);
+  for (int kt = kt0; kt < kt1 && !DMA; ++kt) {
     const int buf = (NBUF == 2) ? (kt & 1) : 0;
     if (NBUF == 1 && kt > kt0) __syncthreads();   // everyone done reading the slab
     store(buf);
@@ -734,7 +854,23 @@ int64_t launch_cfg(const GemmF64Args& a, const Plan& pl, hipStream_t st) {
   const int64_t tail = pl.splits > 0 ? pl.nt - pl.dp : 0;
   dim3 grid((unsigned)(pl.dp + tail * pl.splits)), block(256);
   const int dp = (int)pl.dp, splits = pl.splits, slabs = pl.slabs;
-  if (a.sym) {
+  // LDS-DMA K loop where its requirements hold (the DMA sources are 32-bit
+  // byte offsets within 128 rows of X and 16 of Y).
+  bool launched = false;
+  if constexpr (BM == 128 && BN == 128 && BK == 16 && NBUF == 2) {
+    if (NSR_F64_DMA128 && vec && (a.K % 16) == 0 && (a.N % 2) == 0 && a.ldx < (1 << 21) &&
+        a.ldy < (1 << 24)) {
+      if (a.sym)
+        hipLaunchKernelGGL((gemm_f64_kernel<BM, BN, BK, NBUF, true, true, true>), grid, block, 0,
+                           st, a, tiles_m, tiles_n, dp, splits, slabs);
+      else
+        hipLaunchKernelGGL((gemm_f64_kernel<BM, BN, BK, NBUF, true, false, true>), grid, block, 0,
+                           st, a, tiles_m, tiles_n, dp, splits, slabs);
+      launched = true;
+    }
+  }
+  if (launched) {
+  } else if (a.sym) {
     if (vec)
       hipLaunchKernelGGL((gemm_f64_kernel<BM, BN, BK, NBUF, true, true>), grid, block, 0, st, a,
                          tiles_m, tiles_n, dp, splits, slabs);
