@@ -793,8 +793,8 @@ def run_spd4096(torch, nsr, args):
         "solves_per_s": m["solves_per_s"], "ms_per_solve": m["ms_per_solve"],
         "roofline": roofline_of(m["gemm"]["f64"], "f64", (
             "gemm_f64_nn_dma_kernel (full products: 256x128 tiles fed by LDS DMA) and "
-            "gemm_f64_kernel (symmetric-output power products: 128x128 tiles, the last, "
-            "partial round cut along K and finished by gemm_f64_split_fixup)"),
+            "gemm_f64_kernel (symmetric-output power products: 128x128 tiles fed by LDS "
+            "DMA, the last, partial round cut along K and finished by gemm_f64_split_fixup)"),
             traffic_per_launch("f64")),
         "solve": {
             **report_of(last), "rel_resid": rel, "fwd_err_vs_closed_form": fwd,
