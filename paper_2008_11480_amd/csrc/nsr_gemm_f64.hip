@@ -905,10 +905,12 @@ int64_t launch_cfg(const GemmF64Args& a, const Plan& pl, hipStream_t st) {
 
 // Tile shape: 128 x 128 (two workgroups per CU) or 64 x 64 (four per CU).
 // Time ~ rounds of resident workgroups x time of one tile; a partial last
-// round costs about half a round (its tiles run with less contention), and a
-// 64 x 64 tile takes 0.54 of a 128 x 128 one at the same K.  Fitted to the
-// measured full / symmetric GEMMs at N = 2048, 4096, 8192; the rule picks the
-// faster shape in all six.  A third choice, given scratch: 128 x 128 tiles
+// round that fills at most half the slots (one workgroup per CU) costs about
+// half a round (its tiles run with less contention), a fuller one a round,
+// and a 64 x 64 tile takes 0.54 of a 128 x 128 one at the same K.  Fitted to
+// the measured full / symmetric GEMMs at N = 2048, 4096, 8192 (N = 2048 full
+// products with the DMA K loop: 0.270 ms on 256 tiles of 128, one per CU,
+// against 0.301 ms on 64 x 64 tiles).  A third choice, given scratch: 128 x 128 tiles
 // whose last, partial round is cut along K into as many slices as fill the
 // resident slots (a tail of r tiles in S slots takes ~ S / r times less than
 // a round), finished by a small reduction kernel.  NSR_F64_FORCE_TILE (128
@@ -923,7 +925,7 @@ constexpr int64_t kBigTile = 128 * 128;
 
 double eff_rounds(int64_t tiles, int64_t slots) {
   const int64_t full = tiles / slots, rem = tiles % slots;
-  return (double)full + (rem == 0 ? 0.0 : (2 * rem >= slots ? 1.0 : 0.5));
+  return (double)full + (rem == 0 ? 0.0 : (2 * rem > slots ? 1.0 : 0.5));
 }
 
 int64_t tile_count(int64_t m, int64_t n, int64_t b, bool sym) {
