@@ -112,6 +112,56 @@ def test_gemm_f64_dma_tiles(torch, m, n, k, shift, addends):
     assert abs(float(ss.cpu()) - ss_ref) <= 1e-13 * ss_ref
 
 
+@pytest.mark.parametrize("addends", [0, 2])
+@pytest.mark.parametrize("m,n,k,sym", [(300, 520, 32, False), (1000, 700, 96, False),
+                                       (2100, 1900, 1024, False), (130, 130, 16, True),
+                                       (2064, 2064, 2064, True), (700, 522, 96, False)])
+def test_gemm_f64_dma128_tiles(torch, m, n, k, sym, addends):
+    """128 x 128 float64 tiles with K slabs fed by LDS DMA (K a multiple of
+    16, N even, even strides, 16-byte aligned operands), forced for full and
+    symmetric-output products: one to many slabs, ragged edge tiles (rows
+    past M and columns past N read clamped copies that feed no stored
+    output), row strides above the width, every epilogue form."""
+    b = int(np.ceil(np.log2(max(m, n))))
+    nsr.tile_set(nsr.TILE_F64, b, 128)
+    try:
+        rng = np.random.default_rng(m * 3 + n * 5 + k + addends + 11 * sym)
+        if sym:
+            B = rng.standard_normal((m, k))
+            X = 0.5 * (B + B.T) if m == k else B
+            Xb = np.concatenate([X, rng.standard_normal((m, 8))], axis=1)
+            Yb = np.concatenate([X.T, rng.standard_normal((k, 6))], axis=1)
+            E = [rng.standard_normal((m, n)) for _ in range(addends)]
+            E = [0.5 * (e + e.T) for e in E]
+        else:
+            Xb = rng.standard_normal((m, k + 8))
+            Yb = rng.standard_normal((k, n + 6))
+            E = [rng.standard_normal((m, n)) for _ in range(addends)]
+        X, Y = Xb[:, :k], Yb[:, :n]
+        diag, scale = 0.7, -1.3
+        print(f"f64 dma128 tiles {m}x{n}x{k} sym {sym} addends {addends}", flush=True)
+        D, ss = nsr.gemm_f64(to_dev(torch, Xb)[:, :k], to_dev(torch, Yb)[:, :n],
+                             E1=to_dev(torch, E[0]) if addends > 0 else None,
+                             E2=to_dev(torch, E[1]) if addends > 1 else None,
+                             diag=diag, scale=scale, want_sumsq=True, symmetric=sym)
+        torch.cuda.synchronize()
+    finally:
+        nsr.tile_set(nsr.TILE_F64, b, 0)
+    got = D.cpu().numpy()
+    if sym:
+        assert np.array_equal(got, got.T)
+    ref = scale * (X @ Y) + diag * np.eye(m, n) + sum(E, np.zeros((m, n)))
+    bound = gamma(k + 4) * (abs(scale) * (np.abs(X) @ np.abs(Y)) + abs(diag) * np.eye(m, n)
+                            + sum((np.abs(e) for e in E), np.zeros((m, n))))
+    err = np.abs(got - ref)
+    if sym:
+        iu = np.triu_indices(m)
+        err, bound = err[iu], bound[iu]
+    assert np.all(err <= 2 * bound + 1e-300), float(np.max(err / (bound + 1e-300)))
+    ss_ref = float(np.sum(got * got))
+    assert abs(float(ss.cpu()) - ss_ref) <= 1e-13 * ss_ref
+
+
 @pytest.mark.parametrize("n", [1, 5, 64, 100, 257, 1000, 2900, 4096])
 def test_gemm_f64_symmetric_output(torch, n):
     """Symmetric output: the upper triangle obeys the element-wise bound, the
@@ -135,7 +185,8 @@ def test_gemm_f64_symmetric_output(torch, n):
 
 
 SPLIT_SHAPES = [(2944, 2944, 2944, False), (3000, 3100, 1000, False), (2944, 2944, 33, False),
-                (4096, 4096, 4096, True), (4100, 4100, 4100, True), (4096, 4096, 100, True)]
+                (4096, 4096, 4096, True), (4100, 4100, 4100, True), (4096, 4096, 100, True),
+                (4112, 4112, 4112, True)]
 
 
 @pytest.mark.parametrize("m,n,k,sym", SPLIT_SHAPES)
