@@ -51,6 +51,11 @@
 #ifndef NSR_F32_DMA
 #define NSR_F32_DMA 1
 #endif
+// 1: the 128 x 128 float32 tiles take their K slabs by LDS DMA where the
+// operands allow it.
+#ifndef NSR_F32_DMA128
+#define NSR_F32_DMA128 1
+#endif
 // 1: 256 x 256 split half-precision tiles use the LDS-DMA kernel where its
 // requirements hold.
 #ifndef NSR_F16S_DMA
@@ -145,7 +150,18 @@ __device__ __forceinline__ void write_partial(const GemmLpArgs& p, double ss, do
 // ---------------------------------------------------------------------------
 // float32, NN
 // ---------------------------------------------------------------------------
-template <int BM, int BN, int BK, bool VEC>
+// DMA form (128 x 128 tiles, BK = 32, two 32 KB stages; K a multiple of 32,
+// N a multiple of 4, row strides multiples of 4 floats, 16-byte aligned X
+// and Y): the K slabs go from global memory straight into LDS with
+// global_load_lds_dwordx4, slab kt + 1 issued in two parts during slab kt's
+// first two MFMA steps, one barrier per slab.  X rows (128 B) keep chunk c at
+// c ^ ((row >> 1) & 7); Y rows (512 B) keep chunk c at c ^ 4 (k & 3), so the
+// one-float-per-lane operand reads (16 rows or columns x 4 k) touch 64
+// different banks.  The MFMA sequence and the accumulator layout are those of
+// the register-staged loop (the results are the same bits) and the epilogue
+// is shared.  Rows past M and columns past N of edge tiles read row M - 1
+// and the last four columns and feed only outputs that are not stored.
+template <int BM, int BN, int BK, bool VEC, bool DMA = false>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
 gemm_f32_nn_kernel(GemmLpArgs p, int tiles_m, int tiles_n) {
   constexpr int NT = 256;
@@ -160,9 +176,16 @@ gemm_f32_nn_kernel(GemmLpArgs p, int tiles_m, int tiles_n) {
   constexpr int XV = (BM * BK / 4) / NT;  // float4 per thread
   constexpr int YV = (BK * BN / 4) / NT;
   static_assert(XV >= 1 && YV >= 1, "tile too small");
-  __shared__ __attribute__((aligned(16))) float Xs[2][BM * XS];
-  __shared__ __attribute__((aligned(16))) float Ys[2][BK * YS];
+  static_assert(!DMA || (BM == 128 && BN == 128 && BK == 32 && VEC),
+                "DMA form: 128 x 128 tiles, 32-deep slabs");
+  // One LDS arena: the two register-staged slab buffers of X and Y, or the
+  // DMA ring (two stages of BM x BK and BK x BN floats).
+  constexpr int ARENA = 2 * BM * XS + 2 * BK * YS;
+  static_assert(!DMA || ARENA >= 2 * (BM * BK + BK * BN), "DMA ring fits the arena");
+  __shared__ __attribute__((aligned(1024))) float arena[ARENA];
   __shared__ double red[4];
+  float (*Xs)[BM * XS] = reinterpret_cast<float (*)[BM * XS]>(arena);
+  float (*Ys)[BK * YS] = reinterpret_cast<float (*)[BK * YS]>(arena + 2 * BM * XS);
 
   const float* X = static_cast<const float*>(p.X);
   const float* Y = static_cast<const float*>(p.Y);
@@ -255,8 +278,97 @@ gemm_f32_nn_kernel(GemmLpArgs p, int tiles_m, int tiles_n) {
 
   const int nk = (int)((K + BK - 1) / BK);
   const int lr = lane & 15, lk = lane >> 4;
-  if (nk > 0) load(0);
-  for (int kt = 0; kt < nk; ++kt) {
+  if constexpr (DMA) {
+    constexpr int XB = BM * BK * 4, SB = XB + BK * BN * 4;   // 16 KB of X, 16 KB of Y
+    unsigned char* ring = reinterpret_cast<unsigned char*>(arena);
+    const uint32_t ring_lds = lds_addr(ring);
+    const int wv = __builtin_amdgcn_readfirstlane(wave);
+    // DMA sources as byte offsets from the slab's wave-uniform base: X
+    // instruction u of this wave covers tile rows (4 u + wave) 8 .. + 7, Y
+    // instruction u the slab rows k = (4 u + wave) 2, + 1.
+    uint32_t xoff[4], yoff[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int row = (4 * u + wv) * 8 + (lane >> 3);
+      const int c = (lane & 7) ^ ((row >> 1) & 7);
+      const int64_t g = (m0 + row < M ? m0 + row : M - 1) - m0;
+      xoff[u] = (uint32_t)((g * p.ldx + 4 * c) * 4);
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int k = (4 * u + wv) * 2 + (lane >> 5);
+      const int64_t col = n0 + 4 * ((lane & 31) ^ ((k & 3) << 2));
+      yoff[u] = (uint32_t)(((int64_t)k * p.ldy + (col < N ? col : N - 4) - n0) * 4);
+    }
+    const float* xbase = X + m0 * p.ldx;
+    const float* ybase = Y + n0;
+    auto issue_part = [&](int kt, int h) {   // X and Y instructions 2 h, 2 h + 1
+      const uint32_t st = ring_lds + (uint32_t)((kt & 1) * SB);
+      const float* xb = xbase + (int64_t)kt * BK;
+      const float* yb = ybase + (int64_t)kt * BK * p.ldy;
+#pragma unroll
+      for (int v = 0; v < 2; ++v) {
+        const int u = 2 * h + v;
+        lds_dma16s(xb, xoff[u], st + (uint32_t)((4 * u + wv) * 1024));
+        lds_dma16s(yb, yoff[u], st + (uint32_t)(XB + (4 * u + wv) * 1024));
+      }
+    };
+    // Operand byte offsets within a stage for MFMA step t (k = 4 t + lk): A
+    // X[wm 64 + 16 i + lr][k] at offa[t] + 2048 i, B Y[k][wn 64 + 16 j + lr]
+    // at offb[j] + 2048 t.
+    const int sw = (lr >> 1) & 7;   // row permutation of every row this lane reads
+    int offa[8], offb[FN];
+#pragma unroll
+    for (int t = 0; t < 8; ++t) offa[t] = (wm * WTM + lr) * 128 + ((t ^ sw) * 16) + 4 * lk;
+#pragma unroll
+    for (int j = 0; j < FN; ++j)
+      offb[j] = XB + lk * 512 + ((((wn * WTN + 16 * j + lr) >> 2) ^ (lk << 2)) * 16) + 4 * (lr & 3);
+    auto read_ops = [&](int kt, int t, float (&a)[FM], float (&b)[FN]) {
+      const unsigned char* stage = ring + (kt & 1) * SB;
+#pragma unroll
+      for (int i = 0; i < FM; ++i) a[i] = *reinterpret_cast<const float*>(stage + offa[t] + 2048 * i);
+#pragma unroll
+      for (int j = 0; j < FN; ++j)
+        b[j] = *reinterpret_cast<const float*>(stage + offb[j] + 2048 * t);
+    };
+    float fa[2][FM], fb[2][FN];
+    if (nk > 0) {
+      issue_part(0, 0);
+      issue_part(0, 1);
+      dma_wait_barrier<0>();
+      read_ops(0, 0, fa[0], fb[0]);
+    }
+    if (NSR_LP_SETPRIO) __builtin_amdgcn_s_setprio(1);
+    for (int kt = 0; kt < nk; ++kt) {
+#pragma unroll
+      for (int t = 0; t < 8; ++t) {
+        if (t < 7) {
+          read_ops(kt, t + 1, fa[(t + 1) & 1], fb[(t + 1) & 1]);
+        } else {
+          // Slab kt + 1 has landed and every wave holds its slab-kt operands;
+          // the reads follow on every path (after the last slab they read a
+          // stage and go unused) so the compiler's LDS wait before this
+          // step's MFMAs does not count them.
+          dma_wait_barrier<0>();
+          read_ops(kt + 1, 0, fa[0], fb[0]);
+        }
+        if (t < 2 && kt + 1 < nk) issue_part(kt + 1, t);
+#pragma unroll
+        for (int i = 0; i < FM; ++i)
+#pragma unroll
+          for (int j = 0; j < FN; ++j)
+            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(fa[t & 1][i], fb[t & 1][j], acc[i][j],
+                                                             0, 0, 0);
+        // Each step's region: the next step's LDS reads first, then its MFMAs.
+        __builtin_amdgcn_sched_group_barrier(0x100, FM + FN, 0);
+        __builtin_amdgcn_sched_group_barrier(0x008, FM * FN, 0);
+        __builtin_amdgcn_sched_barrier(0);
+      }
+    }
+    if (NSR_LP_SETPRIO) __builtin_amdgcn_s_setprio(0);
+  }
+  if (nk > 0 && !DMA) load(0);
+  for (int kt = 0; kt < nk && !DMA; ++kt) {
     const int buf = kt & 1;
     store(buf);
     __syncthreads();
@@ -1800,7 +1912,13 @@ int64_t launch_gemm_f32_nn(const GemmLpArgs& a, hipStream_t st) {
   if (huge) {
     hipLaunchKernelGGL(gemm_f32_nn_dma_kernel, grid, dim3(512), 0, st, a, tiles_m, tiles_n);
   } else if (big) {
-    if (vec) hipLaunchKernelGGL((gemm_f32_nn_kernel<128, 128, 32, true>), grid, block, 0, st, a, tiles_m, tiles_n);
+    // LDS-DMA K loop where its requirements hold (the DMA sources are 32-bit
+    // byte offsets within 128 rows of X and 32 of Y).
+    if (NSR_F32_DMA128 && vec && (a.K % 32) == 0 && (a.N % 4) == 0 && (a.ldx % 4) == 0 &&
+        (a.ldy % 4) == 0 && a.ldx < (1 << 22) && a.ldy < (1 << 24))
+      hipLaunchKernelGGL((gemm_f32_nn_kernel<128, 128, 32, true, true>), grid, block, 0, st, a,
+                         tiles_m, tiles_n);
+    else if (vec) hipLaunchKernelGGL((gemm_f32_nn_kernel<128, 128, 32, true>), grid, block, 0, st, a, tiles_m, tiles_n);
     else hipLaunchKernelGGL((gemm_f32_nn_kernel<128, 128, 32, false>), grid, block, 0, st, a, tiles_m, tiles_n);
   } else {
     if (vec) hipLaunchKernelGGL((gemm_f32_nn_kernel<64, 64, 32, true>), grid, block, 0, st, a, tiles_m, tiles_n);
