@@ -368,25 +368,26 @@ def test_gemm_bf16_full_size_sampled(torch):
         assert abs(Dc[i, j] - ref) <= bound, (i, j)
 
 
+@pytest.mark.parametrize("tile", [256, 128])
 @pytest.mark.parametrize("addends", [0, 2])
 @pytest.mark.parametrize("m,n,k", [(300, 520, 32), (513, 260, 64), (1000, 700, 96),
                                    (2100, 1900, 1024), (4100, 4000, 224),
                                    (257, 259, 64), (300, 256, 100)])
-def test_gemm_f32_dma_tiles(torch, m, n, k, addends):
-    """The 256 x 256 float32 tiles fed by LDS DMA (K a multiple of 32, N of
-    4): one to many slabs (the two-stage ring's start, wrap and drain),
-    ragged edge tiles, every epilogue form, within the element-wise bound.
-    The last two shapes miss the DMA requirements (N = 259, K = 100): the
-    256 tile then falls back to the 128 x 128 kernel."""
+def test_gemm_f32_dma_tiles(torch, m, n, k, addends, tile):
+    """The 256 x 256 and 128 x 128 float32 tiles fed by LDS DMA (K a
+    multiple of 32, N of 4): one to many slabs (the two-stage ring's start,
+    wrap and drain), ragged edge tiles, every epilogue form, within the
+    element-wise bound.  The last two shapes miss the DMA requirements
+    (N = 259, K = 100) and take the register-staged 128 x 128 kernel."""
     b = int(np.ceil(np.log2(max(m, n))))
-    nsr.tile_set(nsr.TILE_F32, b, 256)
+    nsr.tile_set(nsr.TILE_F32, b, tile)
     try:
         g = torch.Generator(device="cpu").manual_seed(m * 5 + n * 11 + k)
         X = torch.randn(m, k, generator=g, dtype=torch.float32)
         Y = torch.randn(k, n, generator=g, dtype=torch.float32)
         E = [torch.randn(m, n, generator=g, dtype=torch.float32) for _ in range(addends)]
         diag, scale = 0.75, -1.25
-        print(f"f32 dma tiles {m}x{n}x{k} addends {addends}", flush=True)
+        print(f"f32 dma tiles {tile}: {m}x{n}x{k} addends {addends}", flush=True)
         D, Db, ss = nsr.gemm_lp(X.cuda(), Y.cuda(), nt=False, want_bf16=True,
                                 E1=E[0].cuda() if addends > 0 else None,
                                 E2=E[1].cuda() if addends > 1 else None,
