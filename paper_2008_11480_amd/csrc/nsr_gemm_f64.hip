@@ -17,9 +17,11 @@
 //  * A workgroup of 4 waves owns a BM x BN output tile; each wave owns a
 //    (BM/2) x (BN/2) quadrant = (BM/32) x (BN/32) MFMA blocks kept in
 //    registers for the whole K loop.
-//  * K is walked in slabs of BK.  Each slab of X (BM x BK) and Y (BK x BN) is
-//    loaded from global memory into registers one slab ahead (16-byte loads,
-//    coalesced along rows), stored into one of two LDS buffers and read back
+//  * K is walked in slabs of BK.  Each slab of X (BM x BK) and Y (BK x BN)
+//    goes from global memory into one of two LDS stages, either straight by
+//    LDS DMA (global_load_lds_dwordx4; the 128 x 128 tiles and the 256 x 128
+//    full-product kernel, where the operands allow it) or through registers
+//    one slab ahead (16-byte loads, coalesced along rows), and is read back
 //    as MFMA fragments; one barrier per slab.
 //  * Tile order is XCD-aware: consecutive workgroup ids land on different
 //    XCDs, so each XCD is given a contiguous run of a grouped (8 tile-rows)

@@ -34,7 +34,9 @@
 // (global_load_lds_dwordx4), one workgroup per CU; smaller outputs take the
 // float64 GEMM's scheme (128 x 128 or 64 x 64 tiles, 4 waves, K slabs staged
 // global -> registers (one slab ahead) -> two LDS buffers, two workgroups per
-// CU).  Every kernel walks its tiles in an XCD-aware grouped order.
+// CU; the float32 128 x 128 tiles take their slabs by LDS DMA too where the
+// operands allow it).  Every kernel walks its tiles in an XCD-aware grouped
+// order.
 #include "nsr_internal.h"
 
 #ifndef NSR_BF16_HUGE
