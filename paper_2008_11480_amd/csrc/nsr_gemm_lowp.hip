@@ -53,10 +53,13 @@
 #ifndef NSR_F32_DMA
 #define NSR_F32_DMA 1
 #endif
-// 1: the 128 x 128 float32 tiles take their K slabs by LDS DMA where the
-// operands allow it.
+// 1: the 128 x 128 float32 and bf16 tiles take their K slabs by LDS DMA
+// where the operands allow it.
 #ifndef NSR_F32_DMA128
 #define NSR_F32_DMA128 1
+#endif
+#ifndef NSR_BF16_DMA128
+#define NSR_BF16_DMA128 1
 #endif
 // 1: 256 x 256 split half-precision tiles use the LDS-DMA kernel where its
 // requirements hold.
@@ -862,26 +865,29 @@ __device__ __forceinline__ int dma_swz(int row) {
   return CH == 4 ? (row >> 3) & 3 : ((row >> 1) & 1) | ((row >> 2) & 6);
 }
 
-// 256 x BN tile (BN = 256: eight waves, one workgroup per CU; BN = 128: four
-// waves, two workgroups per CU), waves of 128 x 64, NST stages of BK-deep
-// slabs in LDS.  The library launches <256, 2, 64> when K is a multiple of
-// 64 (half the barriers of <256, 4, 32>, one slab of prefetch: 2-4% faster
-// at N = 4096 and 8192), else <256, 4, 32>.  <128, 3, 32> (two workgroups
-// per CU, 72 KB each) measured 15% slower.
-template <int BN, int NST, int BK>
+// BM x BN tile, waves of (BM / 2) x 64, NST stages of BK-deep slabs in LDS.
+// BM = 256: BN = 256 is eight waves, one workgroup per CU; BN = 128 four
+// waves, two workgroups per CU.  BM = BN = 128: four waves of 64 x 64, two
+// workgroups per CU (64 KB of LDS each), for outputs too small to fill the
+// CUs with 256-row tiles.  The library launches <256, 2, 64> when K is a
+// multiple of 64 (half the barriers of <256, 4, 32>, one slab of prefetch:
+// 2-4% faster at N = 4096 and 8192), else <256, 4, 32> (the same pair with
+// BM = 128 for 128 x 128 tiles).  <128, 3, 32> with 256 rows (two workgroups
+// per CU, 72 KB each) measured 15% slower than <256, 2, 64>.
+template <int BN, int NST, int BK, int BM = 256>
 __global__ void __launch_bounds__(64 * 2 * (BN / 64)) __attribute__((amdgpu_waves_per_eu(2)))
 gemm_bf16_nt_dma_kernel(GemmLpArgs p, int tiles_m, int tiles_n) {
   constexpr int WGN = BN / 64, NW = 2 * WGN;
-  constexpr int WTM = 128, WTN = 64, FM = 4, FN = 2;
+  constexpr int WTM = BM / 2, WTN = 64, FM = WTM / 32, FN = 2;
   constexpr int RB = BK * 2;                 // row bytes
   constexpr int CH = BK / 8;                 // 16-byte chunks per row
   constexpr int RPI = 64 / CH;               // rows per DMA instruction
   constexpr int T = BK / 16;                 // MFMA k-steps per slab
-  constexpr int XBYTES = 256 * RB;
+  constexpr int XBYTES = BM * RB;
   constexpr int SBYTES = XBYTES + BN * RB;
-  constexpr int XI = (256 / RPI) / NW, YI = (BN / RPI) / NW;   // DMA instructions per wave and slab
+  constexpr int XI = (BM / RPI) / NW, YI = (BN / RPI) / NW;   // DMA instructions per wave and slab
   constexpr int PER = XI + YI;
-  static_assert(XI * NW * RPI == 256 && YI * NW * RPI == BN, "DMA split");
+  static_assert(XI * NW * RPI == BM && YI * NW * RPI == BN, "DMA split");
   static_assert(T % 2 == 0, "operand buffers alternate by step parity");
   __shared__ __attribute__((aligned(1024))) unsigned char ring[NST * SBYTES];
   __shared__ double red[NW];
@@ -893,7 +899,7 @@ gemm_bf16_nt_dma_kernel(GemmLpArgs p, int tiles_m, int tiles_n) {
   const int wm = wave / WGN, wn = wave % WGN;
   int tm, tn;
   map_tile_lp(blockIdx.x, tiles_m, tiles_n, tm, tn);
-  const int64_t m0 = (int64_t)tm * 256, n0 = (int64_t)tn * BN;
+  const int64_t m0 = (int64_t)tm * BM, n0 = (int64_t)tn * BN;
   const int64_t M = p.M, N = p.N, K = p.K;
   const uint32_t ring_lds = lds_addr(&ring[0]);
 
@@ -1960,7 +1966,15 @@ int64_t launch_gemm_bf16_nt(const GemmLpArgs& a, hipStream_t st) {
       hipLaunchKernelGGL((gemm_bf16_nt_kernel<256, 256, NSR_BF16_HUGE_BK, false, 2, 4>), grid,
                          block8, 0, st, a, tiles_m, tiles_n);
   } else if (big) {
-    if (vec) hipLaunchKernelGGL((gemm_bf16_nt_kernel<128, 128, 64, true>), grid, block, 0, st, a, tiles_m, tiles_n);
+    const bool dma = NSR_BF16_DMA128 && vec && (a.K % kDmaBK) == 0 && (a.ldx % 8) == 0 &&
+                     (a.ldy % 8) == 0;
+    if (dma && (a.K % 64) == 0)
+      hipLaunchKernelGGL((gemm_bf16_nt_dma_kernel<128, 2, 64, 128>), grid, block, 0, st, a,
+                         tiles_m, tiles_n);
+    else if (dma)
+      hipLaunchKernelGGL((gemm_bf16_nt_dma_kernel<128, 4, 32, 128>), grid, block, 0, st, a,
+                         tiles_m, tiles_n);
+    else if (vec) hipLaunchKernelGGL((gemm_bf16_nt_kernel<128, 128, 64, true>), grid, block, 0, st, a, tiles_m, tiles_n);
     else hipLaunchKernelGGL((gemm_bf16_nt_kernel<128, 128, 64, false>), grid, block, 0, st, a, tiles_m, tiles_n);
   } else {
     if (vec) hipLaunchKernelGGL((gemm_bf16_nt_kernel<64, 64, 64, true>), grid, block, 0, st, a, tiles_m, tiles_n);
