@@ -672,22 +672,24 @@ def test_mixed_accelerated_composite(torch):
     assert fwd <= 1e4 * 2e-10, fwd
 
 
+@pytest.mark.parametrize("tile", [256, 128])
 @pytest.mark.parametrize("addends", [0, 2])
 @pytest.mark.parametrize("m,n,k", [(300, 520, 32), (513, 260, 64), (1000, 700, 96),
                                    (2100, 1900, 1024), (4100, 4000, 224)])
-def test_gemm_bf16_dma_tiles(torch, m, n, k, addends):
-    """The 256 x 256 bf16 tiles fed by LDS DMA (K a multiple of 32): one to
-    many slabs (the four-stage ring's start, wrap and drain), ragged edge
-    tiles, every epilogue form, within the element-wise bound."""
+def test_gemm_bf16_dma_tiles(torch, m, n, k, addends, tile):
+    """The 256 x 256 and 128 x 128 bf16 tiles fed by LDS DMA (K a multiple
+    of 32): one to many slabs (the ring's start, wrap and drain; two stages
+    of 64-deep slabs when K is a multiple of 64, else four of 32), ragged
+    edge tiles, every epilogue form, within the element-wise bound."""
     b = int(np.ceil(np.log2(max(m, n))))
-    nsr.tile_set(nsr.TILE_BF16, b, 256)
+    nsr.tile_set(nsr.TILE_BF16, b, tile)
     try:
         g = torch.Generator(device="cpu").manual_seed(m * 7 + n * 3 + k)
         X = torch.randn(m, k, generator=g).to(torch.bfloat16)
         Y = torch.randn(n, k, generator=g).to(torch.bfloat16)
         E = [torch.randn(m, n, generator=g, dtype=torch.float32) for _ in range(addends)]
         diag, scale = 1.0, -0.5
-        print(f"bf16 dma tiles {m}x{n}x{k} addends {addends}", flush=True)
+        print(f"bf16 dma tiles {tile}: {m}x{n}x{k} addends {addends}", flush=True)
         D, Db, ss = nsr.gemm_lp(X.cuda(), Y.cuda(), nt=True, want_bf16=True,
                                 E1=E[0].cuda() if addends > 0 else None,
                                 E2=E[1].cuda() if addends > 1 else None,
