@@ -1449,24 +1449,26 @@ gemm_f16s_nt_kernel(GemmLpArgs p, int tiles_m, int tiles_n) {
   write_partial<WGM * WGN>(p, ss, red, tm, tn, tiles_n);
 }
 
-// Split half-precision NT product, 256 x 256 tiles fed by LDS DMA: the
-// bf16 DMA kernel's layout with four operand planes (X hi, X lo, Y hi, Y lo;
-// rows of 64 bytes, 32 K per slab, chunks permuted by dma_swz<4>) and three
-// MFMA products per 16-k step.  Two 64 KB stages; the DMA sources are a
-// wave-uniform plane base plus 32-bit per-lane offsets.  Requires K a
-// multiple of 32, row strides multiples of 8 halves and 16-byte aligned
-// planes.
+// Split half-precision NT product, BM x BM tiles fed by LDS DMA: the bf16
+// DMA kernel's layout with four operand planes (X hi, X lo, Y hi, Y lo; rows
+// of 64 bytes, 32 K per slab, chunks permuted by dma_swz<4>) and three MFMA
+// products per 16-k step.  BM = 256: eight waves of 128 x 64, two 64 KB
+// stages, one workgroup per CU; BM = 128: four waves of 64 x 64, two 32 KB
+// stages, two workgroups per CU.  The DMA sources are a wave-uniform plane
+// base plus 32-bit per-lane offsets.  Requires K a multiple of 32, row
+// strides multiples of 8 halves and 16-byte aligned planes.
 constexpr int kF16sDmaBK = 32;
 
-__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2)))
+template <int BM>
+__global__ void __launch_bounds__(BM == 256 ? 512 : 256) __attribute__((amdgpu_waves_per_eu(2)))
 gemm_f16s_nt_dma_kernel(GemmLpArgs p, int tiles_m, int tiles_n) {
-  constexpr int BK = kF16sDmaBK, NST = 2, NW = 8, WGN = 4;
-  constexpr int WTM = 128, WTN = 64, FM = 4, FN = 2;
+  constexpr int BK = kF16sDmaBK, NST = 2, NW = BM == 256 ? 8 : 4, WGN = BM / 64;
+  constexpr int WTM = BM / 2, WTN = 64, FM = WTM / 32, FN = 2;
   constexpr int RB = BK * 2, CH = BK / 8, RPI = 64 / CH, T = BK / 16;
-  constexpr int PB = 256 * RB;                  // bytes of one plane's slab
+  constexpr int PB = BM * RB;                   // bytes of one plane's slab
   constexpr int SBYTES = 4 * PB;                // X hi, X lo, Y hi, Y lo
-  constexpr int PI = (256 / RPI) / NW;          // DMA instructions per wave, plane and slab
-  static_assert(PI * NW * RPI == 256 && T == 2, "DMA split");
+  constexpr int PI = (BM / RPI) / NW;           // DMA instructions per wave, plane and slab
+  static_assert(NW == 2 * WGN && PI * NW * RPI == BM && T == 2, "DMA split");
   __shared__ __attribute__((aligned(1024))) unsigned char ring[NST * SBYTES];
   __shared__ double red[NW];
 
@@ -1475,7 +1477,7 @@ gemm_f16s_nt_dma_kernel(GemmLpArgs p, int tiles_m, int tiles_n) {
   const int wm = wave / WGN, wn = wave % WGN;
   int tm, tn;
   map_tile_lp(blockIdx.x, tiles_m, tiles_n, tm, tn);
-  const int64_t m0 = (int64_t)tm * 256, n0 = (int64_t)tn * 256;
+  const int64_t m0 = (int64_t)tm * BM, n0 = (int64_t)tn * BM;
   const int64_t M = p.M, N = p.N, K = p.K;
   const uint32_t ring_lds = lds_addr(&ring[0]);
 
@@ -2030,11 +2032,14 @@ int64_t launch_gemm_f16s_nt(const GemmLpArgs& a, hipStream_t st) {
     // (The DMA sources are 32-bit byte offsets within 256 rows of a plane.)
     const bool dma = NSR_F16S_DMA && vec && (a.K % kF16sDmaBK) == 0 && (a.ldx % 8) == 0 &&
                      (a.ldy % 8) == 0 && a.ldx < (1 << 23) && a.ldy < (1 << 23);
-    if (dma) hipLaunchKernelGGL(gemm_f16s_nt_dma_kernel, grid, block8, 0, st, a, tiles_m, tiles_n);
+    if (dma) hipLaunchKernelGGL(gemm_f16s_nt_dma_kernel<256>, grid, block8, 0, st, a, tiles_m, tiles_n);
     else if (vec) hipLaunchKernelGGL((gemm_f16s_nt_kernel<256, 256, 32, true, 2, 4>), grid, block8, 0, st, a, tiles_m, tiles_n);
     else hipLaunchKernelGGL((gemm_f16s_nt_kernel<256, 256, 32, false, 2, 4>), grid, block8, 0, st, a, tiles_m, tiles_n);
   } else if (big) {
-    if (vec) hipLaunchKernelGGL((gemm_f16s_nt_kernel<128, 128, 32, true>), grid, block, 0, st, a, tiles_m, tiles_n);
+    const bool dma = NSR_F16S_DMA && vec && (a.K % kF16sDmaBK) == 0 && (a.ldx % 8) == 0 &&
+                     (a.ldy % 8) == 0 && a.ldx < (1 << 23) && a.ldy < (1 << 23);
+    if (dma) hipLaunchKernelGGL(gemm_f16s_nt_dma_kernel<128>, grid, block, 0, st, a, tiles_m, tiles_n);
+    else if (vec) hipLaunchKernelGGL((gemm_f16s_nt_kernel<128, 128, 32, true>), grid, block, 0, st, a, tiles_m, tiles_n);
     else hipLaunchKernelGGL((gemm_f16s_nt_kernel<128, 128, 32, false>), grid, block, 0, st, a, tiles_m, tiles_n);
   } else {
     if (vec) hipLaunchKernelGGL((gemm_f16s_nt_kernel<64, 64, 32, true>), grid, block, 0, st, a, tiles_m, tiles_n);
