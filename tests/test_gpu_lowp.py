@@ -105,15 +105,16 @@ def test_gemm_f32_split_elementwise(torch, m, n, k, addends):
     assert abs(float(ss.cpu()) - ssr) <= 1e-12 * ssr
 
 
+@pytest.mark.parametrize("tile", [256, 128])
 @pytest.mark.parametrize("addends", [0, 2])
 @pytest.mark.parametrize("m,n,k", [(300, 520, 32), (1000, 700, 96), (2100, 1900, 1024),
                                    (4100, 4000, 224), (300, 256, 100)])
-def test_gemm_f32_split_dma_tiles(torch, m, n, k, addends):
-    """The 256 x 256 split tiles fed by LDS DMA (K a multiple of 32): one to
-    many slabs, ragged edge tiles, every epilogue form; the last shape
-    (K = 100) falls back to the register-staged kernel."""
+def test_gemm_f32_split_dma_tiles(torch, m, n, k, addends, tile):
+    """The 256 x 256 and 128 x 128 split tiles fed by LDS DMA (K a multiple
+    of 32): one to many slabs, ragged edge tiles, every epilogue form; the
+    last shape (K = 100) falls back to the register-staged kernel."""
     b = int(np.ceil(np.log2(max(m, n))))
-    nsr.tile_set(nsr.TILE_F16S, b, 256)
+    nsr.tile_set(nsr.TILE_F16S, b, tile)
     try:
         g = torch.Generator(device="cpu").manual_seed(m * 3 + n * 17 + k)
         X = torch.randn(m, k, generator=g, dtype=torch.float32)
