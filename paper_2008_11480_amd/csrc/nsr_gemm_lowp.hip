@@ -34,9 +34,9 @@
 // (global_load_lds_dwordx4), one workgroup per CU; smaller outputs take the
 // float64 GEMM's scheme (128 x 128 or 64 x 64 tiles, 4 waves, K slabs staged
 // global -> registers (one slab ahead) -> two LDS buffers, two workgroups per
-// CU; the float32 128 x 128 tiles take their slabs by LDS DMA too where the
-// operands allow it).  Every kernel walks its tiles in an XCD-aware grouped
-// order.
+// CU; the 128 x 128 tiles of every family take their slabs by LDS DMA too
+// where the operands allow it).  Every kernel walks its tiles in an
+// XCD-aware grouped order.
 #include "nsr_internal.h"
 
 #ifndef NSR_BF16_HUGE
@@ -54,7 +54,7 @@
 #define NSR_F32_DMA 1
 #endif
 // 1: the 128 x 128 float32 and bf16 tiles take their K slabs by LDS DMA
-// where the operands allow it.
+// where the operands allow it (the split tiles follow NSR_F16S_DMA).
 #ifndef NSR_F32_DMA128
 #define NSR_F32_DMA128 1
 #endif
