@@ -573,6 +573,34 @@ def test_split_mode_timing_kind(torch):
     assert cnt[0] == cnt[3] + cnt[4], cnt
 
 
+@pytest.mark.parametrize("prec", [nsr.PREC_FP64, nsr.PREC_MIXED_BF16])
+def test_ragged_tiles_solve_n2112(torch, prec):
+    """N = 2112 = 16.5 x 128 (K a multiple of 64, ragged last tile row and
+    column): every product of the solve takes a 128 x 128 tile fed by LDS DMA
+    (float64 full and symmetric, float32, bf16), with clamped edge reads.
+    Order 8 to the floor, kappa = 1e4: the ||F_k|| trace follows the eigen
+    closed form of eq. (fk1) above the precision's floor, and theta matches
+    theta* = Q diag(1/lam) Q^T b within kappa times the attained residual."""
+    n, kappa = 2112, 1e4
+    sysm = inputs.spd_qlq(n, kappa, seed=21)
+    print(f"ragged tiles solve n={n} precision {prec}", flush=True)
+    s, th, rep = run(torch, sysm, prec, order=8, form="squaring", k_max=64, resid_tol=1e-12,
+                     refine_max=100)
+    assert rep.status == nsr.NS_OK and rep.rel_resid <= 1e-12
+    mu = 1.0 - sysm.lam / rep.alpha
+    floor = min(rep.fnorm_hist)
+    tol = 1e-8 if prec == nsr.PREC_FP64 else 3e-2
+    for k, fk in enumerate(rep.fnorm_hist):
+        ref = float(np.sqrt(np.sum(mu ** (2 * 8 ** k))))
+        if ref > 1e3 * floor:
+            assert abs(fk - ref) <= tol * ref, (k, fk, ref)
+    theta_star = sysm.Q @ ((sysm.Q.T @ sysm.b) / sysm.lam)
+    rel_cpu = np.linalg.norm(sysm.b - sysm.A @ th) / np.linalg.norm(sysm.b)
+    fwd = np.linalg.norm(th - theta_star) / np.linalg.norm(theta_star)
+    assert rel_cpu <= 2e-12
+    assert fwd <= 1.01 * kappa * rel_cpu + 50 * kappa * U64, (fwd, rel_cpu)
+
+
 @pytest.mark.parametrize("prec", [nsr.PREC_MIXED_BF16, nsr.PREC_MIXED_SPLIT])
 def test_mixed_full_size_spd4096(torch, prec):
     """N = 4096, kappa = 1e4, order 8 (the mixed legs the benchmark times, in
