@@ -29,6 +29,7 @@ sample of the same workload.
 from __future__ import annotations
 
 import argparse
+import dataclasses
 import gc
 import hashlib
 import json
@@ -736,11 +737,29 @@ def run_serving(torch, nsr, duration_s=60.0, rate=2000.0, fp64_seconds=5.0, prog
     log(f"serving: {st['served']} served, {st['ok']} ok, p50 {st['latency_ms_p50']:.2f} ms, "
         f"p99 {st['latency_ms_p99']:.2f} ms, {st['solves_per_s']:.0f} solves/s; stages "
         + json.dumps(st["stages"]))
+    # Capacity of the mixed path: the first fp64_seconds of the same arrivals
+    # offered cap_speedup times faster, beyond what it sustains, so its
+    # solves/s over the span (arrival of the first request to the last
+    # completion) is its maximum sustainable rate, measured as the float64
+    # one below.
+    del reqs, srv
+    cap_speedup = 4.0
+    trace_cap = [dataclasses.replace(q, arrival_s=q.arrival_s / cap_speedup)
+                 for q in trace if q.arrival_s < fp64_seconds]
+    reqs = make_requests(trace_cap, draw=ex)
+    log(f"serving capacity, mixed ({len(reqs)} requests over {fp64_seconds / cap_speedup:g} s)")
+    stc = Server(ex, budget_bytes=32 << 30, workers=workers, small_max_n=small).run(reqs)
+    torch.cuda.synchronize()
+    st["capacity"] = {k: stc[k] for k in ("requests", "served", "ok", "solves_per_s", "span_s",
+                                          "latency_ms_p50", "latency_ms_p99",
+                                          "rel_resid_max_reported")}
+    st["capacity"]["offered_per_s"] = rate * cap_speedup
+    log(f"serving capacity, mixed: {stc['solves_per_s']:.0f} solves/s over {stc['span_s']:.2f} s")
     # The same arrivals with every solve in float64 (batched systems too): the
     # offered load exceeds what float64 sustains, so its solves/s over the
-    # span (arrival of the first request to the last completion) is the
-    # float64 path's maximum sustainable rate.  A shorter trace suffices.
-    del reqs, ex, srv, warm
+    # span is the float64 path's maximum sustainable rate.  A shorter trace
+    # suffices.
+    del reqs, ex, warm
     release(torch)
     trace64 = [q for q in trace if q.arrival_s < fp64_seconds]
     ex64 = GpuExecutor(workers=workers, precision=nsr.PREC_FP64, small_max_n=small,
